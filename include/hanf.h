@@ -1,0 +1,174 @@
+/*
+ * hanf.h — C ABI of the MI355X (gfx950) HyperANF library.
+ *
+ * HyperANF (Boldi, Rosa, Vigna, arXiv:1011.5599) approximates the neighbourhood
+ * function N_G(t), the number of node pairs (x, y) with y reachable from x in at most
+ * t arcs, by keeping one HyperLogLog counter per node (Section 3.1, Algorithm 1) and
+ * replacing, at every iteration, each counter by the register-wise maximum of itself
+ * and its successors' counters (Section 3.2, Algorithm 2), until no counter changes.
+ * The statistics of Sections 4-5 (distance cdf, effective diameter, average distance,
+ * spid) follow from the sequence N_hat(0..T).
+ *
+ * Conventions for every function:
+ *   - Return value: HANF_OK (0), HANF_DONE (1, only hanf_iterate) or a negative error
+ *     code. No exception or abort crosses the ABI. After an error the context stays
+ *     valid for hanf_last_error and hanf_destroy; its run state may need a new
+ *     hanf_init_counters.
+ *   - The caller owns every buffer it passes in or receives into; the library owns the
+ *     device memory it allocates and the context handle.
+ *   - Work is ordered on the context's HIP stream. Calls that hand results to the
+ *     host (hanf_iterate, hanf_read_*, hanf_stats, hanf_load_csr) synchronise that
+ *     stream before returning.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Device pointers are HIP device addresses on the context's device (for instance
+ *     torch.Tensor.data_ptr() of a tensor on that device).
+ */
+#ifndef HANF_H
+#define HANF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes */
+#define HANF_OK 0
+#define HANF_DONE 1      /* hanf_iterate: the fixpoint was reached */
+#define HANF_EINVAL -1   /* invalid argument or malformed graph */
+#define HANF_ENOMEM -2   /* device or host allocation failed */
+#define HANF_EDEVICE -3  /* HIP runtime error */
+#define HANF_ESTATE -4   /* call out of order (e.g. iterate before init) */
+#define HANF_ERANGE -5   /* output capacity too small */
+#define HANF_EMAXITER -6 /* the pass cap was reached before the fixpoint */
+
+/* ---- flags for buffers handed to the library */
+#define HANF_HOST_PTRS 0u   /* host memory: copied */
+#define HANF_DEVICE_PTRS 1u /* device memory: borrowed (load_csr) or copied (registers) */
+
+/* ---- options (hanf_set_option) */
+#define HANF_OPT_FRONTIER 1     /* 1 (default): skip successors whose counter did not change
+                                   in the previous pass (Section 3.3, tracking modified
+                                   counters); 0: every pass maximises with every successor */
+#define HANF_OPT_MAX_PASSES 2   /* cap on passes before HANF_EMAXITER; default n + 1 */
+#define HANF_OPT_LIGHT_MAX 3    /* nodes with at most this many arcs are handled by one lane
+                                   group; default depends on m (0 = default) */
+#define HANF_OPT_CHUNK_ARCS 4   /* arcs per wavefront chunk for the other nodes (0 = default) */
+#define HANF_OPT_TIMING 5       /* 1: time every kernel with HIP events (hanf_read_pass_log) */
+#define HANF_OPT_BATCH 6        /* passes enqueued between host checks of the fixpoint (default 4) */
+#define HANF_OPT_TILE_NODES 7   /* nodes per light tile (multiple of the slots per wave; 0 = auto) */
+
+typedef struct hanf_ctx hanf_ctx;
+
+/* Statistics of Sections 4-5 of the paper, from N_hat(0..T). */
+typedef struct {
+  double ed;       /* effective diameter at alpha: smallest t with H(t) >= alpha (Section 4) */
+  double ied;      /* interpolated effective diameter: the alpha crossing of the linear
+                      interpolation of (t, H(t)) (Section 4) */
+  double avg_dist; /* E = sum_t t h(t), h(t) = H(t) - H(t-1) (Section 4, moments) */
+  double var;      /* sum_t t^2 h(t) - E^2 (Section 4, moments) */
+  double spid;     /* var / avg_dist, the shortest-paths index of dispersion (Section 5);
+                      NaN when avg_dist = 0 */
+  double n_max;    /* max_t N_hat(t), the normaliser of H */
+  double d_lo;     /* Algorithm 3 with error eps: largest t with N_hat(t)/M <= alpha(1-2eps); -1 if none */
+  double d_hi;     /* Algorithm 3: smallest t with N_hat(t)/M >= alpha(1+2eps); -1 if none */
+  int32_t T;       /* the fixpoint iteration: N_hat has T+1 values */
+  int32_t distinct;/* 1 if computed on pairs at distance >= 1 only (self-pairs dropped) */
+} hanf_stats_t;
+
+/* One record per executed pass (pass t turns c_t into c_{t+1}). */
+typedef struct {
+  int64_t changed;       /* counters that changed in the pass */
+  int64_t arcs_scanned;  /* arcs whose successor was examined */
+  int64_t arcs_gathered; /* arcs whose successor counter was maximised in (A_t) */
+  int64_t rows_written;  /* counters written to the next buffer */
+  float union_ms;        /* union kernel time (HANF_OPT_TIMING), else 0 */
+  float finalize_ms;     /* multi-chunk combine kernel time, else 0 */
+  float reduce_ms;       /* estimate reduction kernels time, else 0 */
+  float pad_;
+} hanf_pass_t;
+
+/* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work
+ * on, or NULL for a stream owned by the library. */
+int hanf_create(int device, void *hip_stream, hanf_ctx **out);
+
+/* Releases every device allocation of the context. Safe on NULL and after errors. */
+void hanf_destroy(hanf_ctx *ctx);
+
+/* Sets one HANF_OPT_* option. Schedule options take effect at the next hanf_load_csr. */
+int hanf_set_option(hanf_ctx *ctx, int option, int64_t value);
+
+/* Graph ingest (the graph G of Section 3.2, as successor lists). CSR: the successors of
+ * v are col_idx[row_ptr[v] .. row_ptr[v+1]), 0 <= v < n. Requirements, checked on the
+ * device: n >= 1, 0 <= arcs < 2^31, row_ptr[0] = 0, row_ptr nondecreasing,
+ * row_ptr[n] = arcs, 0 <= col_idx[a] < n (HANF_EINVAL otherwise). Duplicate arcs and
+ * self-loops are allowed and change nothing. With HANF_HOST_PTRS the arrays are copied;
+ * with HANF_DEVICE_PTRS they are borrowed and must stay alive and unchanged until the
+ * context is destroyed or another graph is loaded. Builds the degree-aware work
+ * schedule on the device. Discards any previous run state. */
+int hanf_load_csr(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr,
+                  const int32_t *col_idx, uint32_t flags);
+
+/* Counter initialisation (Algorithm 2: add v to c[v]; Algorithm 1 add). m = 2^log2m
+ * registers per counter, 4 <= log2m <= 8. The item v is hashed with splitmix64:
+ * h = output number v+1 of the generator started from state `seed`; register index =
+ * the leftmost log2m bits of h; value = rho+ of the remaining bits (leading zeroes plus
+ * one), saturated at 31. Computes N_hat(0) = sum_v size(c[v]) (Algorithm 1 size with the
+ * HyperLogLog small-range rule). Asynchronous (no host synchronisation). */
+int hanf_init_counters(hanf_ctx *ctx, int32_t log2m, uint64_t seed);
+
+/* Runs up to max_steps passes of Algorithm 2's main loop (max_steps <= 0: until the
+ * fixpoint). Each pass computes c_{t+1}[v] = register-wise max(c_t[v], c_t[w] for
+ * v -> w) for every v, reading only c_t (synchronous update, as through the paper's
+ * update file), then N_hat(t+1). Returns HANF_DONE when a pass left every counter
+ * unchanged (the only sound stop, Section 3.2): T is then the last t, and N_hat has T+1
+ * values. *steps_done (may be NULL) receives the passes run by this call, including
+ * the final unchanged one; *changed_last (may be NULL) the changed count of the last
+ * pass. HANF_EMAXITER if the pass cap is reached first. */
+int hanf_iterate(hanf_ctx *ctx, int32_t max_steps, int32_t *steps_done, int64_t *changed_last);
+
+/* Copies N_hat(0..t) to host `out` (FP64). *len receives t+1; HANF_ERANGE if cap < t+1. */
+int hanf_read_nt(hanf_ctx *ctx, double *out, int32_t cap, int32_t *len);
+
+/* Copies the current counters c_t (n*m bytes, node-major, m bytes per node, register j
+ * of node v at v*m + j) to `out` (host or device per flags). `bytes` must be n*m. */
+int hanf_read_registers(hanf_ctx *ctx, uint8_t *out, int64_t bytes, uint32_t flags);
+
+/* Resumes from a checkpoint: counters `in` (n*m bytes, layout of hanf_read_registers,
+ * values <= 31) taken at iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
+ * Every counter is treated as modified for the next pass, so the continuation is
+ * identical to an uninterrupted run. Requires a prior hanf_init_counters (fixes m). */
+int hanf_write_registers(hanf_ctx *ctx, const uint8_t *in, int64_t bytes, int32_t t,
+                         const double *nt_prefix, int32_t len, uint32_t flags);
+
+/* Statistics of Sections 4-5 and Algorithm 3, computed on the device from the context's
+ * N_hat(0..t): H(t) = N_hat(t)/max N_hat, h(t) = H(t) - H(t-1) (H(-1) = 0), ed, ied,
+ * average distance, variance, spid, and Algorithm 3's interval with error eps. alpha in
+ * (0, 1] (0.9 is the paper's default). distinct = 1 drops the self-pairs: H'(t) =
+ * (N_hat(t) - N_hat(0)) / (max N_hat - N_hat(0)). */
+int hanf_stats(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);
+
+/* Per-pass records of the current run (one per executed pass). *len = passes so far. */
+int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *len);
+
+/* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers
+ * (graph copy included when copy_graph = 1): two register arrays (the counters and the
+ * update buffer, Section 3.2), the CSR, flags and estimate sums. Pure host function;
+ * the memory figure of Section 3.4 (O(n m) register bytes) is its dominant term. */
+int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
+
+/* Last error message of the context, or of the calling thread when ctx is NULL. */
+const char *hanf_last_error(const hanf_ctx *ctx);
+
+/* Register-wise maximum of `count` 32-bit words, each holding four registers (values
+ * <= 127): out[i] = bytewise max(x[i], y[i]), on device `device`. Device pointers. Exposes
+ * the union kernel's packed maximum (Algorithm 2 union; Section 3.3's broadword idea) for
+ * exhaustive testing. Synchronous. */
+int hanf_bytemax_words(int device, const uint32_t *x, const uint32_t *y, uint32_t *out,
+                       int64_t count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HANF_H */

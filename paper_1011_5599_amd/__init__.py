@@ -1,0 +1,303 @@
+"""MI355X HyperANF: Python binding of libhanf.so (the C ABI declared in include/hanf.h).
+
+HyperANF (Boldi, Rosa, Vigna, arXiv:1011.5599) approximates the neighbourhood function
+N(t) of a graph with one HyperLogLog counter per node; every pass replaces each counter
+by the register-wise max of itself and its successors' counters, until no counter
+changes. The functions below marshal arguments to the library of the same names; every
+step of the computation runs in its HIP kernels. Host arrays are numpy arrays; device
+arrays are torch tensors on the context's device (torch serves as allocator and stream
+provider only). There is no fallback: if libhanf.so is missing, importing the functions'
+library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhanf.so")
+
+HANF_OK = 0
+HANF_DONE = 1
+HANF_EINVAL = -1
+HANF_ENOMEM = -2
+HANF_EDEVICE = -3
+HANF_ESTATE = -4
+HANF_ERANGE = -5
+HANF_EMAXITER = -6
+
+HANF_HOST_PTRS = 0
+HANF_DEVICE_PTRS = 1
+
+HANF_OPT_FRONTIER = 1
+HANF_OPT_MAX_PASSES = 2
+HANF_OPT_LIGHT_MAX = 3
+HANF_OPT_CHUNK_ARCS = 4
+HANF_OPT_TIMING = 5
+HANF_OPT_BATCH = 6
+HANF_OPT_TILE_NODES = 7
+HANF_OPT_UNROLL = 100
+
+ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
+               HANF_ESTATE: "ESTATE", HANF_ERANGE: "ERANGE", HANF_EMAXITER: "EMAXITER"}
+
+
+class hanf_stats_t(ctypes.Structure):
+    _fields_ = [("ed", ctypes.c_double), ("ied", ctypes.c_double), ("avg_dist", ctypes.c_double),
+                ("var", ctypes.c_double), ("spid", ctypes.c_double), ("n_max", ctypes.c_double),
+                ("d_lo", ctypes.c_double), ("d_hi", ctypes.c_double), ("T", ctypes.c_int32),
+                ("distinct", ctypes.c_int32)]
+
+
+class hanf_pass_t(ctypes.Structure):
+    _fields_ = [("changed", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
+                ("arcs_gathered", ctypes.c_int64), ("rows_written", ctypes.c_int64),
+                ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
+                ("reduce_ms", ctypes.c_float), ("pad_", ctypes.c_float)]
+
+
+class HanfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhanf.so. Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(or python -m paper_1011_5599_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        i32, i64, u32, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+        sig = {
+            "hanf_create": ([ctypes.c_int, vp, ctypes.POINTER(vp)], ctypes.c_int),
+            "hanf_destroy": ([vp], None),
+            "hanf_set_option": ([vp, ctypes.c_int, i64], ctypes.c_int),
+            "hanf_load_csr": ([vp, i32, i64, vp, vp, u32], ctypes.c_int),
+            "hanf_init_counters": ([vp, i32, u64], ctypes.c_int),
+            "hanf_iterate": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
+            "hanf_read_nt": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
+            "hanf_read_registers": ([vp, vp, i64, u32], ctypes.c_int),
+            "hanf_write_registers": ([vp, vp, i64, i32, vp, i32, u32], ctypes.c_int),
+            "hanf_stats": ([vp, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
+            "hanf_read_pass_log": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
+            "hanf_footprint": ([i32, i64, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
+            "hanf_last_error": ([vp], ctypes.c_char_p),
+            "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def hanf_last_error(ctx=None) -> str:
+    msg = lib().hanf_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def _check(rc: int, ctx=None, ok=(HANF_OK,)) -> int:
+    if rc not in ok:
+        raise HanfError(rc, hanf_last_error(ctx))
+    return rc
+
+
+def _is_tensor(x) -> bool:
+    return hasattr(x, "data_ptr") and hasattr(x, "is_cuda")
+
+
+def _ptr(x, dtype):
+    """(pointer, flags, keepalive) for a numpy array (host) or a torch tensor (device)."""
+    if _is_tensor(x):
+        if not x.is_cuda:
+            x = x.numpy()
+        else:
+            if not x.is_contiguous():
+                raise ValueError("device tensor must be contiguous")
+            return x.data_ptr(), HANF_DEVICE_PTRS, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, HANF_HOST_PTRS, a
+
+
+# ------------------------------------------------------------------ the C ABI, by name
+
+def hanf_create(device: int = 0, stream=None):
+    """Context on HIP device `device`; `stream` is a hipStream_t handle (int), e.g.
+    torch.cuda.current_stream().cuda_stream, or None for a library-owned stream."""
+    out = ctypes.c_void_p()
+    _check(lib().hanf_create(device, stream, ctypes.byref(out)))
+    return out
+
+
+def hanf_destroy(ctx) -> None:
+    lib().hanf_destroy(ctx)
+
+
+def hanf_set_option(ctx, option: int, value: int) -> None:
+    _check(lib().hanf_set_option(ctx, option, int(value)), ctx)
+
+
+def hanf_load_csr(ctx, row_ptr, col_idx):
+    """CSR int32 graph: numpy arrays (copied) or torch tensors on the device (borrowed:
+    keep them alive). Returns the objects to keep alive."""
+    p_rp, f1, k1 = _ptr(row_ptr, np.int32)
+    p_ci, f2, k2 = _ptr(col_idx, np.int32)
+    if f1 != f2:
+        raise ValueError("row_ptr and col_idx must both be host or both be device arrays")
+    n = (k1.numel() if _is_tensor(k1) else k1.size) - 1
+    arcs = k2.numel() if _is_tensor(k2) else k2.size
+    _check(lib().hanf_load_csr(ctx, n, arcs, p_rp, p_ci if arcs > 0 else None, f1), ctx)
+    return (k1, k2)
+
+
+def hanf_init_counters(ctx, log2m: int, seed: int) -> None:
+    _check(lib().hanf_init_counters(ctx, log2m, seed & 0xFFFFFFFFFFFFFFFF), ctx)
+
+
+def hanf_iterate(ctx, max_steps: int = 0):
+    """Returns (status, steps_done, changed_last); status HANF_OK or HANF_DONE."""
+    steps = ctypes.c_int32()
+    changed = ctypes.c_int64()
+    rc = lib().hanf_iterate(ctx, max_steps, ctypes.byref(steps), ctypes.byref(changed))
+    _check(rc, ctx, ok=(HANF_OK, HANF_DONE))
+    return rc, steps.value, changed.value
+
+
+def hanf_read_nt(ctx) -> np.ndarray:
+    n = ctypes.c_int32()
+    rc = lib().hanf_read_nt(ctx, None, 0, ctypes.byref(n))
+    _check(rc, ctx, ok=(HANF_OK, HANF_ERANGE))
+    out = np.zeros(max(n.value, 1), np.float64)
+    _check(lib().hanf_read_nt(ctx, out.ctypes.data, out.size, ctypes.byref(n)), ctx)
+    return out[: n.value]
+
+
+def hanf_read_registers(ctx, n: int, log2m: int, out=None):
+    """Current counters as an (n, m) uint8 array (numpy), or into `out` (numpy or device
+    tensor of n*m bytes)."""
+    nbytes = n << log2m
+    if out is None:
+        out = np.empty((n, 1 << log2m), np.uint8)
+    if _is_tensor(out) and out.is_cuda:
+        _check(lib().hanf_read_registers(ctx, out.data_ptr(), nbytes, HANF_DEVICE_PTRS), ctx)
+    else:
+        if not out.flags["C_CONTIGUOUS"] or out.dtype != np.uint8 or out.size != nbytes:
+            raise ValueError("out must be a contiguous uint8 array of n*m bytes")
+        _check(lib().hanf_read_registers(ctx, out.ctypes.data, nbytes, HANF_HOST_PTRS), ctx)
+    return out
+
+
+def hanf_write_registers(ctx, regs, t: int, nt_prefix) -> None:
+    p, flags, keep = _ptr(regs, np.uint8)
+    nbytes = keep.numel() if _is_tensor(keep) else keep.size
+    pre = np.ascontiguousarray(nt_prefix, dtype=np.float64)
+    _check(lib().hanf_write_registers(ctx, p, nbytes, t, pre.ctypes.data, pre.size, flags), ctx)
+
+
+def hanf_stats(ctx, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
+    s = hanf_stats_t()
+    _check(lib().hanf_stats(ctx, alpha, eps, int(distinct), ctypes.byref(s)), ctx)
+    return {f: getattr(s, f) for f, _ in hanf_stats_t._fields_}
+
+
+def hanf_read_pass_log(ctx) -> list[dict]:
+    n = ctypes.c_int32()
+    rc = lib().hanf_read_pass_log(ctx, None, 0, ctypes.byref(n))
+    _check(rc, ctx, ok=(HANF_OK, HANF_ERANGE))
+    arr = (hanf_pass_t * max(n.value, 1))()
+    _check(lib().hanf_read_pass_log(ctx, ctypes.cast(arr, ctypes.c_void_p), n.value, ctypes.byref(n)), ctx)
+    return [{f: getattr(arr[i], f) for f, _ in hanf_pass_t._fields_ if f != "pad_"}
+            for i in range(n.value)]
+
+
+def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True) -> int:
+    out = ctypes.c_int64()
+    _check(lib().hanf_footprint(n, arcs, log2m, int(copy_graph), ctypes.byref(out)))
+    return out.value
+
+
+def hanf_bytemax_words(device: int, x, y, out) -> None:
+    """Device tensors of int32/uint32 words; out[i] = register-wise max of x[i], y[i]."""
+    _check(lib().hanf_bytemax_words(device, x.data_ptr(), y.data_ptr(), out.data_ptr(), x.numel()))
+
+
+# ------------------------------------------------------------------ convenience wrapper
+
+class HyperANF:
+    """One graph and one run on one device: load, init, iterate to the fixpoint, read."""
+
+    def __init__(self, device: int = 0, stream=None, **options):
+        self.ctx = hanf_create(device, stream)
+        self.n = 0
+        self.log2m = 0
+        self._keep = None
+        names = {"frontier": HANF_OPT_FRONTIER, "max_passes": HANF_OPT_MAX_PASSES,
+                 "light_max": HANF_OPT_LIGHT_MAX, "chunk_arcs": HANF_OPT_CHUNK_ARCS,
+                 "timing": HANF_OPT_TIMING, "batch": HANF_OPT_BATCH,
+                 "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL}
+        for k, v in options.items():
+            hanf_set_option(self.ctx, names[k], int(v))
+
+    def close(self):
+        if self.ctx is not None:
+            hanf_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, row_ptr, col_idx):
+        self._keep = hanf_load_csr(self.ctx, row_ptr, col_idx)
+        k = self._keep[0]
+        self.n = (k.numel() if _is_tensor(k) else k.size) - 1
+        return self
+
+    def init(self, log2m: int, seed: int):
+        hanf_init_counters(self.ctx, log2m, seed)
+        self.log2m = log2m
+        return self
+
+    def step(self, k: int = 1):
+        return hanf_iterate(self.ctx, k)
+
+    def run(self):
+        """Iterates to the fixpoint; returns N_hat(0..T)."""
+        hanf_iterate(self.ctx, 0)
+        return hanf_read_nt(self.ctx)
+
+    def nt(self):
+        return hanf_read_nt(self.ctx)
+
+    def registers(self, out=None):
+        return hanf_read_registers(self.ctx, self.n, self.log2m, out)
+
+    def stats(self, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
+        return hanf_stats(self.ctx, alpha, eps, distinct)
+
+    def pass_log(self):
+        return hanf_read_pass_log(self.ctx)
+
+
+def rsd(log2m: int, beta: float = 1.06) -> float:
+    """Relative standard deviation bound beta/sqrt(m) of Section 3.1."""
+    return beta / math.sqrt(1 << log2m)

@@ -1,0 +1,708 @@
+// C ABI of the HyperANF library (declared in include/hanf.h): context management, graph
+// ingest and schedule construction, the host side of the iteration loop, checkpoints and
+// statistics. Every computation on graph data runs in the HIP kernels of hanf_kernels.hip;
+// this layer validates arguments, owns device memory and orders launches on the stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hanf.h"
+#include "hanf_internal.h"
+
+using namespace hanf;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+// Published HyperLogLog bias constants (the paper defers alpha_m to the HyperLogLog paper).
+double alpha_for(int m) {
+  if (m == 16) return 0.673;
+  if (m == 32) return 0.697;
+  if (m == 64) return 0.709;
+  return 0.7213 / (1.0 + 1.079 / m);
+}
+
+struct Schedule {
+  int G = 0;  // lanes per counter the schedule was built for
+  int32_t light_max = 0, chunk_arcs = 0, tile_nodes = 0;
+  int32_t n_tiles = 0, n_chunks = 0, n_heavy = 0;
+  int32_t n_chunk_wgs = 0, n_light_wgs = 0, n_fin_wgs = 0;
+  int32_t *light = nullptr;
+  Chunk *chunks = nullptr;
+  Heavy *heavy = nullptr;
+  uint8_t *partial = nullptr;
+  uint8_t *partial_any = nullptr;
+  int64_t *wgstat = nullptr;
+};
+
+}  // namespace
+
+struct hanf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  int fail_alloc_at = 0;  // test hook (HANF_TEST_FAIL_ALLOC): make that allocation fail
+  int alloc_count = 0;
+  std::vector<void *> allocs;
+
+  // options
+  int frontier = 1;
+  int64_t max_passes_opt = 0;
+  int32_t light_max_opt = 0, chunk_opt = 0, tile_opt = 0;
+  int timing = 0;
+  int batch = 4;
+  int unroll = 4;
+
+  // graph
+  int32_t n = 0;
+  int64_t arcs = 0;
+  const int32_t *rp = nullptr, *ci = nullptr;
+  int32_t *rp_own = nullptr, *ci_own = nullptr;
+  bool graph_ok = false;
+
+  Schedule sch;
+
+  // run state
+  int log2m = 0;
+  bool inited = false;
+  uint8_t *regs[2] = {nullptr, nullptr};
+  uint32_t *bits[2] = {nullptr, nullptr};
+  double *est = nullptr, *blocksum = nullptr, *wgsum = nullptr, *lc = nullptr, *nt = nullptr;
+  double *stats_out = nullptr;
+  int64_t *wgcnt = nullptr;
+  PassLog *log = nullptr;
+  DevState *st = nullptr;
+  DevState *st_host = nullptr;  // pinned
+  int32_t nt_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
+  std::vector<double> lc_host;
+  std::vector<hanf_pass_t> host_log;
+  PassArgs args{};
+};
+
+namespace {
+
+int fail(hanf_ctx *c, int code, const std::string &msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_thread_error = msg;
+  return code;
+}
+
+int hip_fail(hanf_ctx *c, hipError_t e, const char *what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? HANF_ENOMEM : HANF_EDEVICE, msg);
+}
+
+#define HIP_TRY(ctx, expr, what)           \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+template <typename T>
+int dev_alloc(hanf_ctx *c, T **p, size_t count, const char *what) {
+  *p = nullptr;
+  c->alloc_count++;
+  if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at)
+    return fail(c, HANF_ENOMEM, std::string("forced allocation failure: ") + what);
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, HANF_ENOMEM, std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
+  }
+  *p = static_cast<T *>(q);
+  return HANF_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_schedule(hanf_ctx *c) {
+  Schedule &s = c->sch;
+  dev_free(s.light);
+  dev_free(s.chunks);
+  dev_free(s.heavy);
+  dev_free(s.partial);
+  dev_free(s.partial_any);
+  dev_free(s.wgstat);
+  s = Schedule();
+}
+
+void free_run(hanf_ctx *c) {
+  for (int i = 0; i < 2; ++i) {
+    dev_free(c->regs[i]);
+    dev_free(c->bits[i]);
+  }
+  dev_free(c->est);
+  dev_free(c->blocksum);
+  dev_free(c->wgsum);
+  dev_free(c->wgcnt);
+  dev_free(c->lc);
+  dev_free(c->nt);
+  dev_free(c->log);
+  dev_free(c->stats_out);
+  c->inited = false;
+  c->log2m = 0;
+}
+
+void free_graph(hanf_ctx *c) {
+  dev_free(c->rp_own);
+  dev_free(c->ci_own);
+  c->rp = c->ci = nullptr;
+  c->graph_ok = false;
+  c->n = 0;
+  c->arcs = 0;
+}
+
+int sync(hanf_ctx *c, const char *what) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return HANF_OK;
+}
+
+int read_state(hanf_ctx *c) {
+  HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
+          "state read");
+  return sync(c, "state read");
+}
+
+// Default schedule parameters for G lanes per counter (W = 64/G slots per wavefront).
+void choose_schedule(hanf_ctx *c, int G, Schedule &s) {
+  const int W = kWave / G;
+  s.G = G;
+  s.light_max = c->light_max_opt > 0 ? c->light_max_opt : 64;
+  s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, W * c->unroll * 8);
+  int32_t tile = c->tile_opt;
+  if (tile <= 0) {
+    // enough wavefronts to fill the chip on small graphs, 256 nodes per tile on large ones
+    int64_t rounds = (int64_t)c->n / ((int64_t)W * 2048);
+    rounds = std::max<int64_t>(1, std::min<int64_t>(rounds, kMaxTile / W));
+    tile = (int32_t)(rounds * W);
+  }
+  tile = std::max(W, std::min(kMaxTile, (tile / W) * W));
+  s.tile_nodes = tile;
+}
+
+int build_schedule(hanf_ctx *c, int G) {
+  free_schedule(c);
+  Schedule &s = c->sch;
+  choose_schedule(c, G, s);
+  const int32_t n = c->n;
+  s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
+  int rc;
+  if ((rc = dev_alloc(c, &s.light, (size_t)s.n_tiles * s.tile_nodes, "light tiles"))) return rc;
+  HIP_TRY(c, launch_build_tiles(c->rp, n, s.light_max, s.tile_nodes, s.n_tiles, s.light, c->stream),
+          "build tiles");
+  // chunk counts, prefix sums, chunk and heavy lists
+  uint64_t *keys = nullptr, *tmp = nullptr;
+  if ((rc = dev_alloc(c, &keys, (size_t)n + 1, "schedule keys"))) return rc;
+  if ((rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
+    dev_free(keys);
+    return rc;
+  }
+  hipError_t e = launch_classify(c->rp, n, s.light_max, s.chunk_arcs, keys, c->stream);
+  if (e == hipSuccess) e = launch_exclusive_scan_u64(keys, (int64_t)n + 1, tmp, c->stream);
+  uint64_t total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, keys + n, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    dev_free(keys);
+    dev_free(tmp);
+    return hip_fail(c, e, "schedule scan");
+  }
+  s.n_chunks = (int32_t)(total >> 32);
+  s.n_heavy = (int32_t)(total & 0xffffffffull);
+  const int m = 16 * G;
+  if ((rc = dev_alloc(c, &s.chunks, (size_t)s.n_chunks, "chunks")) ||
+      (rc = dev_alloc(c, &s.heavy, (size_t)s.n_heavy, "heavy nodes")) ||
+      (rc = dev_alloc(c, &s.partial, (size_t)s.n_chunks * m, "chunk partials")) ||
+      (rc = dev_alloc(c, &s.partial_any, (size_t)s.n_chunks, "chunk flags"))) {
+    dev_free(keys);
+    dev_free(tmp);
+    return rc;
+  }
+  e = launch_fill_chunks(c->rp, n, keys, s.chunk_arcs, s.chunks, s.heavy, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(keys);
+  dev_free(tmp);
+  if (e != hipSuccess) return hip_fail(c, e, "fill chunks");
+  s.n_chunk_wgs = (s.n_chunks + 3) / 4;
+  s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
+  s.n_light_wgs = (s.n_tiles + 3) / 4;
+  s.n_fin_wgs = (s.n_heavy + 3) / 4;
+  if ((rc = dev_alloc(c, &s.wgstat, ((size_t)s.n_chunk_wgs + s.n_light_wgs + s.n_fin_wgs) * 4, "workgroup counters")))
+    return rc;
+  return HANF_OK;
+}
+
+void fill_args(hanf_ctx *c) {
+  PassArgs &a = c->args;
+  a.row_ptr = c->rp;
+  a.col_idx = c->ci;
+  a.regs0 = c->regs[0];
+  a.regs1 = c->regs[1];
+  a.bits0 = c->bits[0];
+  a.bits1 = c->bits[1];
+  a.est = c->est;
+  a.blocksum = c->blocksum;
+  a.wgsum = c->wgsum;
+  a.wgcnt = c->wgcnt;
+  a.wgstat = c->sch.wgstat;
+  a.light = c->sch.light;
+  a.chunks = c->sch.chunks;
+  a.heavy = c->sch.heavy;
+  a.partial = c->sch.partial;
+  a.partial_any = c->sch.partial_any;
+  a.st = c->st;
+  a.nt = c->nt;
+  a.log = c->log;
+  a.lc = c->lc;
+  const int m = 1 << c->log2m;
+  a.K = alpha_for(m) * m * m * 2147483648.0;
+  a.n = c->n;
+  a.log2m = c->log2m;
+  a.n_blocks = c->n_blocks;
+  a.n_chunks = c->sch.n_chunks;
+  a.n_chunk_wgs = c->sch.n_chunk_wgs;
+  a.n_light_wgs = c->sch.n_light_wgs;
+  a.n_tiles = c->sch.n_tiles;
+  a.tile_nodes = c->sch.tile_nodes;
+  a.n_heavy = c->sch.n_heavy;
+  a.n_fin_wgs = c->sch.n_fin_wgs;
+  a.n_reduce_wgs = c->n_reduce_wgs;
+  a.nt_cap = c->nt_cap;
+}
+
+int alloc_run(hanf_ctx *c, int log2m) {
+  free_run(c);
+  const int m = 1 << log2m;
+  const size_t bytes = (size_t)c->n * m;
+  c->n_blocks = (int32_t)(((int64_t)c->n + kNodesPerBlock - 1) / kNodesPerBlock);
+  c->n_reduce_wgs = (c->n_blocks + 3) / 4;
+  c->max_passes = c->max_passes_opt > 0 ? (int32_t)std::min<int64_t>(c->max_passes_opt, INT32_MAX - 8)
+                                        : (int32_t)std::min<int64_t>((int64_t)c->n + 1, INT32_MAX - 8);
+  c->nt_cap = c->max_passes + 2;
+  int rc;
+  if ((rc = dev_alloc(c, &c->regs[0], bytes, "counters")) || (rc = dev_alloc(c, &c->regs[1], bytes, "counters")) ||
+      (rc = dev_alloc(c, &c->bits[0], (size_t)2 * c->n_blocks, "flags")) ||
+      (rc = dev_alloc(c, &c->bits[1], (size_t)2 * c->n_blocks, "flags")) ||
+      (rc = dev_alloc(c, &c->est, (size_t)c->n, "estimates")) ||
+      (rc = dev_alloc(c, &c->blocksum, (size_t)c->n_blocks, "block sums")) ||
+      (rc = dev_alloc(c, &c->wgsum, (size_t)c->n_reduce_wgs, "partial sums")) ||
+      (rc = dev_alloc(c, &c->wgcnt, (size_t)c->n_reduce_wgs, "partial counts")) ||
+      (rc = dev_alloc(c, &c->lc, (size_t)m + 1, "linear-counting table")) ||
+      (rc = dev_alloc(c, &c->nt, (size_t)c->nt_cap, "N history")) ||
+      (rc = dev_alloc(c, &c->log, (size_t)c->nt_cap, "pass log")) ||
+      (rc = dev_alloc(c, &c->stats_out, 16, "statistics"))) {
+    free_run(c);
+    return rc;
+  }
+  // linear counting m ln(m/V), V = 1..m (entry 0 unused)
+  c->lc_host.assign((size_t)m + 1, 0.0);
+  for (int V = 1; V <= m; ++V) c->lc_host[V] = m * std::log((double)m / V);
+  HIP_TRY(c, hipMemcpyAsync(c->lc, c->lc_host.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, c->stream),
+          "table upload");
+  c->log2m = log2m;
+  return HANF_OK;
+}
+
+int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
+  hipStream_t s = c->stream;
+  if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
+  HIP_TRY(c, launch_union(c->args, c->unroll, s), "union kernel");
+  if (ev) HIP_TRY(c, hipEventRecord(ev[1], s), "event");
+  HIP_TRY(c, launch_finalize(c->args, s), "finalize kernel");
+  if (ev) HIP_TRY(c, hipEventRecord(ev[2], s), "event");
+  HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s), "reduce kernels");
+  if (ev) HIP_TRY(c, hipEventRecord(ev[3], s), "event");
+  return HANF_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
+  if (!out) return fail(nullptr, HANF_EINVAL, "hanf_create: out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(nullptr, HANF_EDEVICE, "hanf_create: no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(nullptr, HANF_EINVAL, "hanf_create: bad device index");
+  hanf_ctx *c = new (std::nothrow) hanf_ctx();
+  if (!c) return fail(nullptr, HANF_ENOMEM, "hanf_create: out of host memory");
+  c->device = device;
+  if (const char *f = std::getenv("HANF_TEST_FAIL_ALLOC")) c->fail_alloc_at = std::atoi(f);
+  e = hipSetDevice(device);
+  if (e == hipSuccess) {
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      c->own_stream = e == hipSuccess;
+    }
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    std::string msg = std::string("hanf_create: ") + hipGetErrorString(e);
+    hanf_destroy(c);
+    return fail(nullptr, HANF_EDEVICE, msg);
+  }
+  int rc = dev_alloc(c, &c->st, 1, "state");
+  if (rc) {
+    std::string msg = c->err;
+    hanf_destroy(c);
+    return fail(nullptr, rc, msg);
+  }
+  *out = c;
+  return HANF_OK;
+}
+
+void hanf_destroy(hanf_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_run(c);
+  free_schedule(c);
+  free_graph(c);
+  dev_free(c->st);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_set_option: NULL context");
+  switch (option) {
+    case HANF_OPT_FRONTIER:
+      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "frontier must be 0 or 1");
+      c->frontier = (int)value;
+      break;
+    case HANF_OPT_MAX_PASSES:
+      if (value < 0) return fail(c, HANF_EINVAL, "max passes must be >= 0");
+      c->max_passes_opt = value;
+      break;
+    case HANF_OPT_LIGHT_MAX:
+      if (value < 0 || value > (1 << 20)) return fail(c, HANF_EINVAL, "light max out of range");
+      c->light_max_opt = (int32_t)value;
+      break;
+    case HANF_OPT_CHUNK_ARCS:
+      if (value < 0 || value > (1 << 24)) return fail(c, HANF_EINVAL, "chunk arcs out of range");
+      c->chunk_opt = (int32_t)value;
+      break;
+    case HANF_OPT_TIMING:
+      c->timing = value ? 1 : 0;
+      break;
+    case HANF_OPT_BATCH:
+      if (value < 1 || value > 1024) return fail(c, HANF_EINVAL, "batch must be in 1..1024");
+      c->batch = (int)value;
+      break;
+    case HANF_OPT_TILE_NODES:
+      if (value < 0 || value > kMaxTile) return fail(c, HANF_EINVAL, "tile nodes must be in 0..256");
+      c->tile_opt = (int32_t)value;
+      break;
+    case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
+      if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
+      c->unroll = (int)value;
+      break;
+    default:
+      return fail(c, HANF_EINVAL, "unknown option");
+  }
+  return HANF_OK;
+}
+
+int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, const int32_t *col_idx,
+                  uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_csr: NULL context");
+  if (n < 1) return fail(c, HANF_EINVAL, "n must be >= 1");
+  if (arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
+  if (!row_ptr || (arcs > 0 && !col_idx)) return fail(c, HANF_EINVAL, "NULL CSR array");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_run(c);
+  free_schedule(c);
+  free_graph(c);
+  int rc;
+  if (flags == HANF_DEVICE_PTRS) {
+    for (const void *p : {(const void *)row_ptr, (const void *)col_idx}) {
+      if (!p) continue;
+      hipPointerAttribute_t attr;
+      hipError_t e = hipPointerGetAttributes(&attr, p);
+      if (e != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != c->device) {
+        (void)hipGetLastError();
+        return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: pointer is not device memory of this device");
+      }
+    }
+    c->rp = row_ptr;
+    c->ci = arcs > 0 ? col_idx : nullptr;
+  } else {
+    if ((rc = dev_alloc(c, &c->rp_own, (size_t)n + 1, "row_ptr")) ||
+        (rc = dev_alloc(c, &c->ci_own, (size_t)arcs, "col_idx"))) {
+      free_graph(c);
+      return rc;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->rp_own, row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, c->stream),
+            "row_ptr upload");
+    if (arcs > 0)
+      HIP_TRY(c, hipMemcpyAsync(c->ci_own, col_idx, sizeof(int32_t) * (size_t)arcs, hipMemcpyHostToDevice, c->stream),
+              "col_idx upload");
+    c->rp = c->rp_own;
+    c->ci = c->ci_own;
+  }
+  c->n = n;
+  c->arcs = arcs;
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, c->stream), "state reset");
+  HIP_TRY(c, launch_validate(c->rp, c->ci, n, arcs, c->st, c->stream), "validate");
+  if ((rc = read_state(c))) return rc;
+  if (c->st_host->err) {
+    const int e = c->st_host->err;
+    std::string msg = "malformed CSR:";
+    if (e & 1) msg += " row_ptr[0] != 0;";
+    if (e & 2) msg += " row_ptr decreases;";
+    if (e & 4) msg += " row_ptr[n] != arcs;";
+    if (e & 8) msg += " col_idx out of [0, n);";
+    free_graph(c);
+    return fail(c, HANF_EINVAL, msg);
+  }
+  c->graph_ok = true;
+  return HANF_OK;
+}
+
+int hanf_init_counters(hanf_ctx *c, int32_t log2m, uint64_t seed) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_init_counters: NULL context");
+  if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
+  if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  const int G = 1 << (log2m - 4);
+  int rc;
+  Schedule want;
+  choose_schedule(c, G, want);
+  if (c->sch.G != G || !c->sch.light || want.light_max != c->sch.light_max ||
+      want.chunk_arcs != c->sch.chunk_arcs || want.tile_nodes != c->sch.tile_nodes) {
+    if ((rc = build_schedule(c, G))) return rc;
+  }
+  const int64_t want_cap = (c->max_passes_opt > 0 ? c->max_passes_opt : (int64_t)c->n + 1) + 2;
+  if (c->log2m != log2m || !c->regs[0] || want_cap != c->nt_cap) {
+    if ((rc = alloc_run(c, log2m))) return rc;
+  }
+  c->inited = false;
+  fill_args(c);
+  c->host_log.clear();
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, c->stream), "state reset");
+  HIP_TRY(c, launch_init(c->args, seed, c->stream), "init kernel");
+  HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
+  c->inited = true;
+  return HANF_OK;
+}
+
+int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *changed_last) {
+  if (steps_done) *steps_done = 0;
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_iterate: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  int32_t steps = 0;
+  std::vector<hipEvent_t> ev;
+  for (;;) {
+    DevState s0 = *c->st_host;
+    if (changed_last) *changed_last = s0.changed_last;
+    if (s0.done) {
+      if (steps_done) *steps_done = steps;
+      return HANF_DONE;
+    }
+    if (s0.capped) {
+      if (steps_done) *steps_done = steps;
+      return fail(c, HANF_EMAXITER, "pass cap reached before the fixpoint");
+    }
+    if (max_steps > 0 && steps >= max_steps) break;
+    int B = c->batch;
+    if (max_steps > 0) B = std::min(B, max_steps - steps);
+    if (c->timing) {
+      ev.resize((size_t)B * 4);
+      for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) return fail(c, HANF_EDEVICE, "event create");
+    }
+    for (int i = 0; i < B; ++i) {
+      rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * 4] : nullptr);
+      if (rc) return rc;
+    }
+    if ((rc = read_state(c))) return rc;
+    const int32_t ran = c->st_host->passes - s0.passes;
+    if (ran > 0) {
+      std::vector<PassLog> recs((size_t)ran);
+      HIP_TRY(c, hipMemcpyAsync(recs.data(), c->log + s0.passes, sizeof(PassLog) * ran, hipMemcpyDeviceToHost,
+                                c->stream),
+              "pass log read");
+      if ((rc = sync(c, "pass log read"))) return rc;
+      for (int32_t i = 0; i < ran; ++i) {
+        hanf_pass_t r{};
+        r.changed = recs[i].changed;
+        r.arcs_scanned = recs[i].scanned;
+        r.arcs_gathered = recs[i].gathered;
+        r.rows_written = recs[i].written;
+        if (c->timing) {
+          hipEvent_t *e = &ev[(size_t)i * 4];
+          (void)hipEventElapsedTime(&r.union_ms, e[0], e[1]);
+          (void)hipEventElapsedTime(&r.finalize_ms, e[1], e[2]);
+          (void)hipEventElapsedTime(&r.reduce_ms, e[2], e[3]);
+        }
+        c->host_log.push_back(r);
+      }
+    }
+    if (c->timing) {
+      for (auto &x : ev) (void)hipEventDestroy(x);
+      ev.clear();
+    }
+    steps += ran;
+    if (ran == 0 && !c->st_host->done && !c->st_host->capped)
+      return fail(c, HANF_EDEVICE, "no pass completed (device state did not advance)");
+  }
+  if (steps_done) *steps_done = steps;
+  return HANF_OK;
+}
+
+int hanf_read_nt(hanf_ctx *c, double *out, int32_t cap, int32_t *len) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_nt: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (!len) return fail(c, HANF_EINVAL, "len is NULL");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  const int32_t have = c->st_host->t + 1;
+  *len = have;
+  if (cap < have) return fail(c, HANF_ERANGE, "output capacity below t+1");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  HIP_TRY(c, hipMemcpyAsync(out, c->nt, sizeof(double) * have, hipMemcpyDeviceToHost, c->stream), "history read");
+  return sync(c, "history read");
+}
+
+int hanf_read_registers(hanf_ctx *c, uint8_t *out, int64_t bytes, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_registers: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (bytes != (int64_t)c->n << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n * m");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  const uint8_t *src = c->regs[c->st_host->t & 1];
+  HIP_TRY(c, hipMemcpyAsync(out, src, (size_t)bytes,
+                            flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+          "register read");
+  return sync(c, "register read");
+}
+
+int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t t, const double *nt_prefix,
+                         int32_t len, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_write_registers: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised (m unknown)");
+  if (!in || !nt_prefix) return fail(c, HANF_EINVAL, "NULL input");
+  if (bytes != (int64_t)c->n << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n * m");
+  if (t < 0 || len != t + 1) return fail(c, HANF_EINVAL, "len must be t + 1");
+  if (t + 2 > c->nt_cap) return fail(c, HANF_ERANGE, "t beyond the pass cap");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  c->inited = false;
+  HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, c->stream), "state reset");
+  HIP_TRY(c, hipMemcpyAsync(c->regs[t & 1], in, (size_t)bytes, kind, c->stream), "register upload");
+  HIP_TRY(c, launch_check_registers(c->regs[t & 1], bytes, c->st, c->stream), "register check");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  if (c->st_host->err) return fail(c, HANF_EINVAL, "register value above 31");
+  HIP_TRY(c, hipMemcpyAsync(c->regs[(t + 1) & 1], c->regs[t & 1], (size_t)bytes, hipMemcpyDeviceToDevice, c->stream),
+          "register copy");
+  fill_args(c);
+  c->host_log.clear();
+  HIP_TRY(c, launch_estimate_all(c->args, c->regs[t & 1], c->stream), "estimate kernel");
+  HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
+  HIP_TRY(c, hipMemcpyAsync(c->nt, nt_prefix, sizeof(double) * len, hipMemcpyHostToDevice, c->stream),
+          "history upload");
+  if ((rc = sync(c, "resume"))) return rc;
+  c->inited = true;
+  return HANF_OK;
+}
+
+int hanf_stats(hanf_ctx *c, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_stats: NULL context");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(c, HANF_EINVAL, "alpha must be in (0, 1]");
+  if (!(eps >= 0.0)) return fail(c, HANF_EINVAL, "eps must be >= 0");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  double buf[9];
+  HIP_TRY(c, launch_stats(c->nt, c->st, alpha, eps, distinct ? 1 : 0, c->stats_out, c->stream), "stats kernel");
+  HIP_TRY(c, hipMemcpyAsync(buf, c->stats_out, sizeof(buf), hipMemcpyDeviceToHost, c->stream), "stats read");
+  int rc;
+  if ((rc = sync(c, "stats"))) return rc;
+  out->ed = buf[0];
+  out->ied = buf[1];
+  out->avg_dist = buf[2];
+  out->var = buf[3];
+  out->spid = buf[4];
+  out->n_max = buf[5];
+  out->d_lo = buf[6];
+  out->d_hi = buf[7];
+  out->T = (int32_t)buf[8];
+  out->distinct = distinct ? 1 : 0;
+  return HANF_OK;
+}
+
+int hanf_read_pass_log(hanf_ctx *c, hanf_pass_t *out, int32_t cap, int32_t *len) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_pass_log: NULL context");
+  if (!len) return fail(c, HANF_EINVAL, "len is NULL");
+  const int32_t have = (int32_t)c->host_log.size();
+  *len = have;
+  if (cap < have) return fail(c, HANF_ERANGE, "output capacity below the pass count");
+  if (have > 0 && !out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (have > 0) std::memcpy(out, c->host_log.data(), sizeof(hanf_pass_t) * have);
+  return HANF_OK;
+}
+
+int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes) {
+  if (!bytes) return fail(nullptr, HANF_EINVAL, "bytes is NULL");
+  if (n < 1 || arcs < 0 || arcs >= (int64_t)INT32_MAX || log2m < 4 || log2m > 8)
+    return fail(nullptr, HANF_EINVAL, "hanf_footprint: argument out of range");
+  const int64_t m = 1LL << log2m;
+  const int64_t blocks = ((int64_t)n + kNodesPerBlock - 1) / kNodesPerBlock;
+  int64_t b = 2 * (int64_t)n * m;                        // counters + update buffer
+  b += 2 * 2 * blocks * 4;                               // modified flags
+  b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
+  b += (int64_t)n * 4 + 4096;                            // light tiles
+  b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)
+  if (copy_graph) b += ((int64_t)n + 1) * 4 + arcs * 4;
+  *bytes = b;
+  return HANF_OK;
+}
+
+const char *hanf_last_error(const hanf_ctx *c) { return c ? c->err.c_str() : g_thread_error.c_str(); }
+
+int hanf_bytemax_words(int device, const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
+  if (!x || !y || !out || count < 0) return fail(nullptr, HANF_EINVAL, "hanf_bytemax_words: bad argument");
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess && count > 0) e = launch_bytemax_words(x, y, out, count, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hanf_bytemax_words");
+  return HANF_OK;
+}
+
+}  // extern "C"

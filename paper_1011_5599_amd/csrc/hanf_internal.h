@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP kernels (hanf_kernels.hip) and the C-ABI host
+// layer (hanf_api.hip). Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hanf {
+
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kBlockThreads = 256; // 4 wavefronts per workgroup
+constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 consecutive nodes
+constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
+constexpr int kXcds = 8;           // MI355X accelerator complex dies
+
+// Run state kept in device memory, so consecutive passes can be enqueued without a host
+// round trip: kernels read the iteration t and stop early once the run has halted.
+struct DevState {
+  int32_t t;          // the counters in regs[t & 1] are c_t
+  int32_t halted;     // 1 once a pass changed nothing (done) or the pass cap was reached
+  int32_t done;       // 1 once a pass changed nothing
+  int32_t capped;     // 1 if the pass cap stopped the run
+  int32_t first_pass; // 1 after init/resume: both register buffers hold c_t, every
+                      // successor is maximised in, and no copy is needed
+  int32_t frontier;   // 1 = skip successors unchanged in the previous pass
+  int32_t max_passes;
+  int32_t passes;     // passes executed so far
+  int32_t err;        // validation error bits
+  int32_t pad_;
+  int64_t changed_last;
+};
+
+struct PassLog {  // per executed pass, filled on the device
+  int64_t changed, scanned, gathered, written;
+};
+
+struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
+  int32_t v, a0, a1, part;  // part: partial-result slot for nodes split in several chunks, else -1
+};
+
+struct Heavy {   // a node split in several chunks, combined by the finalize kernel
+  int32_t v, first, count, pad_;
+};
+
+enum ReduceMode : int32_t { kReduceInit = 0, kReducePass = 1 };
+
+// Kernel arguments of one pass (passed by value).
+struct PassArgs {
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  uint8_t *regs0, *regs1;    // regs[t & 1] = c_t, regs[(t+1) & 1] = c_{t+1}
+  uint32_t *bits0, *bits1;   // changed flags: bits[t & 1] written by pass t-1, bits[(t+1) & 1] by pass t
+  double *est;               // per-node estimate of the current counter
+  double *blocksum;          // per 64 nodes
+  double *wgsum;             // per reduce workgroup
+  int64_t *wgcnt;            // per reduce workgroup: changed counters
+  int64_t *wgstat;           // per union/finalize workgroup: scanned, gathered, written, pad
+  const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
+  const Chunk *chunks;
+  const Heavy *heavy;
+  uint8_t *partial;          // m bytes per chunk of a multi-chunk node
+  uint8_t *partial_any;      // 1 if the chunk maximised at least one successor
+  DevState *st;
+  double *nt;                // N_hat history
+  PassLog *log;
+  const double *lc;          // linear-counting table m ln(m/V), V = 0..m
+  double K;                  // alpha_m m^2 2^31
+  int32_t n;
+  int32_t log2m;
+  int32_t n_blocks;          // ceil(n / 64)
+  int32_t n_chunks;
+  int32_t n_chunk_wgs;       // union workgroups given to chunks (multiple of 8)
+  int32_t n_light_wgs;
+  int32_t n_tiles;
+  int32_t tile_nodes;
+  int32_t n_heavy;
+  int32_t n_fin_wgs;
+  int32_t n_reduce_wgs;
+  int32_t nt_cap;
+};
+
+// ---- launchers (hanf_kernels.hip); all asynchronous on `s`
+hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t arcs,
+                           DevState *st, hipStream_t s);
+hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
+                              hipStream_t s);
+hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
+                           uint64_t *keys, hipStream_t s);
+// exclusive scan of n uint64 values in place; `tmp` needs scan_tmp_elems(n) elements
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_exclusive_scan_u64(uint64_t *data, int64_t n, uint64_t *tmp, hipStream_t s);
+hipError_t launch_fill_chunks(const int32_t *row_ptr, int32_t n, const uint64_t *offs,
+                              int32_t chunk_arcs, Chunk *chunks, Heavy *heavy, hipStream_t s);
+hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t tile_nodes,
+                              int32_t n_tiles, int32_t *light, hipStream_t s);
+hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s);
+hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s);
+hipError_t launch_union(const PassArgs &a, int u, hipStream_t s);
+hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
+hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
+hipError_t launch_stats(const double *nt, const DevState *st, double alpha, double eps,
+                        int32_t distinct, double *out, hipStream_t s);
+hipError_t launch_check_registers(const uint8_t *regs, int64_t bytes, DevState *st, hipStream_t s);
+hipError_t launch_set_history(double *nt, const double *prefix, int32_t len, DevState *st,
+                              int32_t t, hipStream_t s);
+hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
+                                hipStream_t s);
+
+}  // namespace hanf

@@ -1,0 +1,888 @@
+// HIP kernels for gfx950 (CDNA4): HyperANF's iteration (Boldi, Rosa, Vigna, Algorithm 2)
+// over HyperLogLog counters (Algorithm 1).
+//
+// Data layout in HBM:
+//   regs[2]   uint8 [n][m]     counters c_t and c_{t+1}, node-major, m = 2^log2m bytes each
+//   bits[2]   uint32 [2 * ceil(n/64)]  modified-counter flags of the previous / current pass
+//   est       double [n]       estimate of each current counter
+//   blocksum  double [ceil(n/64)]  cached estimate sums per 64 consecutive nodes
+//
+// One pass (c_t -> c_{t+1}) is one launch of k_union (+ k_finalize when a node's arcs are
+// split over several wavefronts) and two reduction launches. The union is bound by HBM
+// bandwidth: random gathers of m-byte successor counters. Lanes load counters 16 bytes at a
+// time; a counter is handled by G = m/16 lanes (a "slot"); a wavefront holds W = 64/G slots.
+//   - light nodes (few arcs): one slot per node, nodes of a tile sorted by degree so the
+//     slots of a wavefront finish together; tiles are assigned to XCDs in contiguous runs
+//     so neighbouring ids (and their shared successors) meet in the same L2;
+//   - other nodes: one wavefront per chunk of arcs, its W slots striding over the chunk;
+//     nodes with several chunks leave per-chunk partial maxima combined by k_finalize.
+#include "hanf_internal.h"
+
+namespace hanf {
+namespace {
+
+// ------------------------------------------------------------------ packed register max
+
+// Register-wise max of four registers packed in a 32-bit word. Registers hold values <= 31
+// (at most 127 is required), so the top bit of every byte is free: (x | 0x80808080) - y
+// never borrows across bytes and leaves each byte's top bit set exactly where x_b >= y_b.
+// That bit becomes a 0x7f byte mask selecting x, and bit-field insert takes y elsewhere.
+// (The same idea as the paper's broadword maximisation, specialised to 8-bit blocks with a
+// spare high bit.)
+__device__ __forceinline__ uint32_t bytemax(uint32_t x, uint32_t y) {
+  const uint32_t d = (x | 0x80808080u) - y;
+  const uint32_t hi = d & 0x80808080u;
+  const uint32_t keep_x = hi - (hi >> 7);
+  return (x & keep_x) | (y & ~keep_x);
+}
+
+__device__ __forceinline__ uint4 bytemax4(uint4 a, uint4 b) {
+  return make_uint4(bytemax(a.x, b.x), bytemax(a.y, b.y), bytemax(a.z, b.z), bytemax(a.w, b.w));
+}
+
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+__device__ __forceinline__ uint4 ldrow(const uint8_t *regs, int32_t v, int m, int sub) {
+  return *reinterpret_cast<const uint4 *>(regs + (size_t)v * (size_t)m + (size_t)sub * 16);
+}
+
+__device__ __forceinline__ void strow(uint8_t *regs, int32_t v, int m, int sub, uint4 x) {
+  *reinterpret_cast<uint4 *>(regs + (size_t)v * (size_t)m + (size_t)sub * 16) = x;
+}
+
+__device__ __forceinline__ bool testbit(const uint32_t *bits, int32_t v) {
+  return (bits[v >> 5] >> (v & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint4 shfl_xor4(uint4 a, int off) {
+  return make_uint4(__shfl_xor(a.x, off), __shfl_xor(a.y, off), __shfl_xor(a.z, off),
+                    __shfl_xor(a.w, off));
+}
+
+// ------------------------------------------------------------------ hash (Algorithm 1 add)
+
+// Output number k (k >= 1) of the splitmix64 generator whose state starts at `seed`: the
+// state advances by the golden-ratio increment before each output, then is mixed.
+__device__ __forceinline__ uint64_t splitmix64_output(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// ------------------------------------------------------------------ estimator (Algorithm 1 size)
+
+// size() of the counter held by the G lanes of a slot (16 registers per lane), with the
+// HyperLogLog small-range rule. S = sum_j 2^(31 - M[j]) is an exact integer (<= 2^39), so
+// raw = alpha m^2 / sum_j 2^-M[j] = K / S with K = alpha m^2 2^31 takes one IEEE division.
+// All G lanes of the slot must be active; every lane returns the estimate.
+template <int G>
+__device__ __forceinline__ double slot_estimate(uint4 acc, const double *lc, double K) {
+  const uint32_t w[4] = {acc.x, acc.y, acc.z, acc.w};
+  uint64_t S = 0;
+  uint32_t V = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t r = (w[i] >> (8 * k)) & 0xffu;
+      S += (uint64_t)(1u << (31u - r));
+      V += (r == 0u);
+    }
+  }
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)S, off);
+    const uint32_t hi = __shfl_xor((uint32_t)(S >> 32), off);
+    S += ((uint64_t)hi << 32) | lo;
+    V += __shfl_xor(V, off);
+  }
+  const double m = 16.0 * G;
+  const double raw = K / (double)S;
+  return (raw <= 2.5 * m && V > 0u) ? lc[V] : raw;
+}
+
+// ------------------------------------------------------------------ pass helpers
+
+struct Flags {
+  const uint8_t *cur;
+  uint8_t *nxt;
+  const uint32_t *prev_bits;  // counters modified by the previous pass
+  uint32_t *cur_bits;         // counters modified by this pass
+  bool gather_all;            // maximise with every successor (first pass, or frontier off)
+  bool copy_check;            // next[v] may hold c_{t-1}[v] != c_t[v]: copy when v was modified
+};
+
+__device__ __forceinline__ Flags make_flags(const PassArgs &a, int32_t t, int32_t first,
+                                            int32_t frontier) {
+  Flags f;
+  const bool odd = t & 1;
+  f.cur = odd ? a.regs1 : a.regs0;
+  f.nxt = odd ? a.regs0 : a.regs1;
+  f.prev_bits = odd ? a.bits1 : a.bits0;
+  f.cur_bits = odd ? a.bits0 : a.bits1;
+  f.gather_all = first || !frontier;
+  f.copy_check = !first;
+  return f;
+}
+
+struct Counters {
+  int32_t scanned = 0, gathered = 0, written = 0;
+};
+
+// Writes c_{t+1}[v] for the node of a slot, given `acc`, the max over the successors
+// maximised in (and over c_t[v] when own_loaded). Called with all 64 lanes active; idle
+// slots pass v < 0. Keeps the two register buffers consistent without copying unchanged
+// counters: next[v] already equals c_t[v] unless v was modified by the previous pass.
+template <int G>
+__device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f, int32_t v, int lane,
+                                              uint4 acc, bool any, bool own_loaded, uint4 own,
+                                              Counters &cnt) {
+  constexpr int m = 16 * G;
+  const int sub = lane % G;
+  const bool pv = (v >= 0 && f.copy_check) ? testbit(f.prev_bits, v) : false;
+  const bool work = v >= 0 && (any || pv);
+  if (work && !own_loaded) own = ldrow(f.cur, v, m, sub);
+  if (work) acc = bytemax4(acc, own);
+  const bool diff = work && (acc.x != own.x || acc.y != own.y || acc.z != own.z || acc.w != own.w);
+  const uint64_t bal = __ballot(diff);
+  const int first_lane = lane & ~(G - 1);
+  const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  const bool changed = ((bal >> first_lane) & gmask) != 0ull;
+  if (work && (changed || pv)) {
+    strow(f.nxt, v, m, sub, acc);
+    if (sub == 0) cnt.written++;
+  }
+  if (changed) {
+    const double E = slot_estimate<G>(acc, a.lc, a.K);
+    if (sub == 0) {
+      a.est[v] = E;
+      atomicOr(&f.cur_bits[v >> 5], 1u << (v & 31));
+    }
+  }
+}
+
+// One round of a light tile: each slot handles one node (all its arcs, U at a time).
+template <int G, int U>
+__device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
+                                            Counters &cnt) {
+  constexpr int m = 16 * G;
+  const int sub = lane % G;
+  int32_t beg = 0, end = 0;
+  if (v >= 0) {
+    beg = a.row_ptr[v];
+    end = a.row_ptr[v + 1];
+  }
+  uint4 own = zero4(), acc = zero4();
+  bool own_loaded = false;
+  if (f.gather_all && end > beg) {
+    own = ldrow(f.cur, v, m, sub);
+    acc = own;
+    own_loaded = true;
+  }
+  bool any = false;
+  for (int32_t p = beg; p < end; p += U) {
+    int32_t w[U];
+    bool ok[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      ok[k] = p + k < end;
+      w[k] = ok[k] ? a.col_idx[p + k] : 0;
+    }
+    if (!f.gather_all) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
+    }
+    uint4 x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) x[k] = ok[k] ? ldrow(f.cur, w[k], m, sub) : zero4();
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      acc = bytemax4(acc, x[k]);
+      any = any || ok[k];
+      if (sub == 0) cnt.gathered += ok[k] ? 1 : 0;
+    }
+    if (sub == 0) cnt.scanned += min(U, end - p);
+  }
+  finalize_slot<G>(a, f, v, lane, acc, any, own_loaded, own, cnt);
+}
+
+// Max across the W slots of a wavefront (all lanes active).
+template <int G>
+__device__ __forceinline__ void combine_slots(uint4 &acc, bool &any) {
+  int anyi = any ? 1 : 0;
+#pragma unroll
+  for (int off = G; off < kWave; off <<= 1) {
+    acc = bytemax4(acc, shfl_xor4(acc, off));
+    anyi |= __shfl_xor(anyi, off);
+  }
+  any = anyi != 0;
+}
+
+// A chunk of one node's arcs handled by a whole wavefront.
+template <int G, int U>
+__device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, int32_t c, int lane,
+                                           Counters &cnt) {
+  constexpr int W = kWave / G;
+  constexpr int m = 16 * G;
+  const int slot = lane / G, sub = lane % G;
+  const Chunk ch = a.chunks[c];
+  uint4 acc = zero4();
+  bool any = false;
+  for (int32_t base = ch.a0; base < ch.a1; base += W * U) {
+    int32_t w[U];
+    bool ok[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int32_t p = base + k * W + slot;
+      ok[k] = p < ch.a1;
+      w[k] = ok[k] ? a.col_idx[p] : 0;
+    }
+    if (!f.gather_all) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
+    }
+    uint4 x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) x[k] = ok[k] ? ldrow(f.cur, w[k], m, sub) : zero4();
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      acc = bytemax4(acc, x[k]);
+      any = any || ok[k];
+      if (sub == 0) cnt.gathered += ok[k] ? 1 : 0;
+    }
+  }
+  if (lane == 0) cnt.scanned += ch.a1 - ch.a0;
+  combine_slots<G>(acc, any);
+  if (ch.part < 0) {
+    finalize_slot<G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, zero4(), cnt);
+  } else if (slot == 0) {
+    strow(a.partial, ch.part, m, sub, acc);
+    if (sub == 0) a.partial_any[ch.part] = any ? 1 : 0;
+  }
+}
+
+// Logical index of light workgroup j when workgroups are dealt to the 8 XCDs round-robin:
+// each XCD receives a contiguous run of tiles.
+__device__ __forceinline__ int32_t xcd_remap(int32_t j, int32_t total) {
+  const int32_t x = j % kXcds, pos = j / kXcds;
+  const int32_t base = total / kXcds, extra = total % kXcds;
+  return x * base + min(x, extra) + pos;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  return x;
+}
+
+__device__ __forceinline__ void store_block_counters(const Counters &c, int64_t *out) {
+  __shared__ int32_t red[3][kBlockThreads / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written);
+  if (lane == 0) {
+    red[0][wave] = s0;
+    red[1][wave] = s1;
+    red[2][wave] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t0 = 0, t1 = 0, t2 = 0;
+    for (int i = 0; i < kBlockThreads / kWave; ++i) {
+      t0 += red[0][i];
+      t1 += red[1][i];
+      t2 += red[2][i];
+    }
+    out[0] = t0;
+    out[1] = t1;
+    out[2] = t2;
+    out[3] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ kernels: one pass
+
+template <int G, int U>
+__global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st->t, st->first_pass, st->frontier);
+  Counters cnt;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
+    const int32_t c = (int32_t)blockIdx.x * 4 + wave;
+    if (c < a.n_chunks) chunk_wave<G, U>(a, f, c, lane, cnt);
+  } else {
+    constexpr int W = kWave / G;
+    const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
+    const int32_t tile = L * 4 + wave;
+    if (tile < a.n_tiles) {
+      const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
+      const int rounds = a.tile_nodes / W;
+      const int slot = lane / G;
+      for (int r = 0; r < rounds; ++r) {
+        const int32_t v = tl[r * W + slot];
+        if (!__any(v >= 0)) break;  // empty entries sort last
+        light_round<G, U>(a, f, v, lane, cnt);
+      }
+    }
+  }
+  store_block_counters(cnt, a.wgstat + (size_t)blockIdx.x * 4);
+}
+
+// Combines the partial maxima of nodes split over several chunks (one wavefront per node).
+template <int G>
+__global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st->t, st->first_pass, st->frontier);
+  Counters cnt;
+  constexpr int W = kWave / G;
+  constexpr int m = 16 * G;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = lane / G, sub = lane % G;
+  const int32_t h = (int32_t)blockIdx.x * 4 + wave;
+  if (h < a.n_heavy) {
+    const Heavy hv = a.heavy[h];
+    uint4 acc = zero4();
+    bool any = false;
+    for (int32_t j = slot; j < hv.count; j += W) {
+      acc = bytemax4(acc, ldrow(a.partial, hv.first + j, m, sub));
+      any = any || a.partial_any[hv.first + j] != 0;
+    }
+    combine_slots<G>(acc, any);
+    finalize_slot<G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, zero4(), cnt);
+  }
+  store_block_counters(cnt, a.wgstat + ((size_t)a.n_chunk_wgs + a.n_light_wgs + blockIdx.x) * 4);
+}
+
+// Per 64-node block: re-sum the estimates where a counter changed (else reuse the cached
+// sum, Section 3.3), count changed counters, clear the flags of the previous pass.
+__global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int32_t force) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  __shared__ double s_sum[kBlockThreads / kWave];
+  __shared__ int32_t s_cnt[kBlockThreads / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t t = st->t;
+  const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
+  uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
+  const int32_t b = (int32_t)blockIdx.x * 4 + wave;
+  double bs = 0.0;
+  int32_t cnt = 0;
+  if (b < a.n_blocks) {
+    uint32_t w0 = 0, w1 = 0;
+    if (!force) {
+      w0 = cb[2 * b];
+      w1 = cb[2 * b + 1];
+    }
+    if (force || (w0 | w1)) {
+      const int32_t v = b * kNodesPerBlock + lane;
+      bs = wave_sum(v < a.n ? a.est[v] : 0.0);
+      if (lane == 0) a.blocksum[b] = bs;
+    } else {
+      bs = a.blocksum[b];
+    }
+    cnt = __popc(w0) + __popc(w1);
+    if (!force && lane == 0) {
+      pb[2 * b] = 0u;
+      pb[2 * b + 1] = 0u;
+    }
+  }
+  if (lane == 0) {
+    s_sum[wave] = bs;
+    s_cnt[wave] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.wgsum[blockIdx.x] = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
+    a.wgcnt[blockIdx.x] = (int64_t)s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+  }
+}
+
+// Totals of a pass (one workgroup, fixed summation order): N_hat(t+1), changed count and
+// work counters; advances t or marks the fixpoint.
+constexpr int kTopThreads = 1024;
+
+__global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t mode) {
+  DevState *st = a.st;
+  if (st->halted) return;
+  __shared__ double s_sum[kTopThreads];
+  __shared__ int64_t s_i[4][kTopThreads];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  int64_t c = 0, sc = 0, ga = 0, wr = 0;
+  for (int32_t i = tid; i < a.n_reduce_wgs; i += kTopThreads) {
+    s += a.wgsum[i];
+    c += a.wgcnt[i];
+  }
+  if (mode == kReducePass) {
+    const int32_t nw = a.n_chunk_wgs + a.n_light_wgs + a.n_fin_wgs;
+    for (int32_t i = tid; i < nw; i += kTopThreads) {
+      sc += a.wgstat[(size_t)i * 4 + 0];
+      ga += a.wgstat[(size_t)i * 4 + 1];
+      wr += a.wgstat[(size_t)i * 4 + 2];
+    }
+  }
+  s_sum[tid] = s;
+  s_i[0][tid] = c;
+  s_i[1][tid] = sc;
+  s_i[2][tid] = ga;
+  s_i[3][tid] = wr;
+  __syncthreads();
+  for (int off = kTopThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_sum[tid] += s_sum[tid + off];
+      for (int k = 0; k < 4; ++k) s_i[k][tid] += s_i[k][tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double total = s_sum[0];
+    const int32_t t = st->t;
+    if (mode == kReduceInit) {
+      if (t < a.nt_cap) a.nt[t] = total;
+    } else {
+      const int32_t p = st->passes;
+      PassLog rec;
+      rec.changed = s_i[0][0];
+      rec.scanned = s_i[1][0];
+      rec.gathered = s_i[2][0];
+      rec.written = s_i[3][0];
+      if (p < a.nt_cap) a.log[p] = rec;
+      st->passes = p + 1;
+      st->changed_last = rec.changed;
+      st->first_pass = 0;
+      if (rec.changed == 0) {
+        st->done = 1;
+        st->halted = 1;
+      } else {
+        st->t = t + 1;
+        if (t + 1 < a.nt_cap) a.nt[t + 1] = total;
+        if (p + 1 >= st->max_passes) {
+          st->capped = 1;
+          st->halted = 1;
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels: init
+
+// Algorithm 2's initialisation (add v to c[v]) into both register buffers, its estimate,
+// and cleared modified-counter flags. G lanes per node, 16 registers each.
+template <int G>
+__global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed) {
+  constexpr int m = 16 * G;
+  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (gid < 2 * (int64_t)a.n_blocks) {
+    a.bits0[gid] = 0u;
+    a.bits1[gid] = 0u;
+  }
+  const int64_t v64 = gid / G;
+  const int sub = (int)(gid % G);
+  if (v64 >= a.n) return;  // whole slots leave together (n * G lanes, G | 256)
+  const int32_t v = (int32_t)v64;
+  const uint64_t h = splitmix64_output(seed, (uint64_t)v + 1);
+  const int b = a.log2m;
+  const uint32_t idx = (uint32_t)(h >> (64 - b));
+  const uint64_t rest = h << b;
+  int r = rest ? __clzll((long long)rest) + 1 : 64 - b + 1;
+  r = r > 31 ? 31 : r;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if ((int)(idx >> 4) == sub) {
+    const uint32_t byte = idx & 15u;
+    w[byte >> 2] = (uint32_t)r << (8 * (byte & 3u));
+  }
+  const uint4 c = make_uint4(w[0], w[1], w[2], w[3]);
+  strow(a.regs0, v, m, sub, c);
+  strow(a.regs1, v, m, sub, c);
+  const double E = slot_estimate<G>(c, a.lc, a.K);
+  if (sub == 0) a.est[v] = E;
+}
+
+// Estimates of every counter of `regs` (resume from a checkpoint) and cleared flags.
+template <int G>
+__global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, const uint8_t *regs) {
+  constexpr int m = 16 * G;
+  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (gid < 2 * (int64_t)a.n_blocks) {
+    a.bits0[gid] = 0u;
+    a.bits1[gid] = 0u;
+  }
+  const int64_t v64 = gid / G;
+  const int sub = (int)(gid % G);
+  if (v64 >= a.n) return;
+  const int32_t v = (int32_t)v64;
+  const double E = slot_estimate<G>(ldrow(regs, v, m, sub), a.lc, a.K);
+  if (sub == 0) a.est[v] = E;
+}
+
+// ------------------------------------------------------------------ kernels: graph ingest
+
+__global__ void k_validate(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs,
+                           DevState *st) {
+  int32_t err = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t top = arcs > (int64_t)n + 1 ? arcs : (int64_t)n + 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
+    if (i == 0 && rp[0] != 0) err |= 1;
+    if (i < n && rp[i] > rp[i + 1]) err |= 2;
+    if (i == n && (int64_t)rp[n] != arcs) err |= 4;
+    if (i < arcs) {
+      const int32_t w = ci[i];
+      if (w < 0 || w >= n) err |= 8;
+    }
+  }
+  if (err) atomicOr(&st->err, err);
+}
+
+__global__ void k_check_registers(const uint32_t *words, int64_t nwords, DevState *st) {
+  int32_t err = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
+    if (words[i] & 0xe0e0e0e0u) err = 16;  // a register above 31
+  if (err) atomicOr(&st->err, err);
+}
+
+__global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes) {
+  st->t = t;
+  st->halted = 0;
+  st->done = 0;
+  st->capped = 0;
+  st->first_pass = 1;
+  st->frontier = frontier;
+  st->max_passes = max_passes;
+  st->passes = 0;
+  st->err = 0;
+  st->changed_last = -1;
+}
+
+// keys[v] = (chunks of v) << 32 | (v needs a combine step); keys[n] = 0.
+__global__ void k_classify(const int32_t *rp, int32_t n, int32_t light_max, int32_t chunk_arcs,
+                           uint64_t *keys) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  if (v == n) {
+    keys[n] = 0;
+    return;
+  }
+  const int32_t deg = rp[v + 1] - rp[v];
+  uint64_t nch = 0;
+  if (deg > light_max) nch = ((uint64_t)deg + chunk_arcs - 1) / chunk_arcs;
+  keys[v] = (nch << 32) | (nch > 1 ? 1ull : 0ull);
+}
+
+__global__ void k_fill_chunks(const int32_t *rp, int32_t n, const uint64_t *offs, int32_t chunk_arcs,
+                              Chunk *chunks, Heavy *heavy) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t o0 = offs[v], o1 = offs[v + 1];
+  const int32_t c0 = (int32_t)(o0 >> 32), nch = (int32_t)((o1 >> 32) - (o0 >> 32));
+  if (nch == 0) return;
+  const bool multi = nch > 1;
+  const int32_t beg = rp[v], end = rp[v + 1];
+  for (int32_t j = 0; j < nch; ++j) {
+    Chunk c;
+    c.v = (int32_t)v;
+    const int64_t a0 = (int64_t)beg + (int64_t)j * chunk_arcs;
+    c.a0 = (int32_t)a0;
+    c.a1 = (int32_t)min((int64_t)end, a0 + chunk_arcs);
+    c.part = multi ? c0 + j : -1;
+    chunks[c0 + j] = c;
+  }
+  if (multi) {
+    Heavy h;
+    h.v = (int32_t)v;
+    h.first = c0;
+    h.count = nch;
+    h.pad_ = 0;
+    heavy[(int32_t)(o0 & 0xffffffffull)] = h;
+  }
+}
+
+// One workgroup per tile of consecutive ids: light nodes sorted by decreasing degree (ties
+// by id), the rest of the tile filled with -1.
+__global__ __launch_bounds__(kMaxTile) void k_build_tiles(const int32_t *rp, int32_t n, int32_t light_max,
+                                                          int32_t tile_nodes, int32_t *light) {
+  __shared__ uint64_t keys[kMaxTile];
+  const int i = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * tile_nodes;
+  const int64_t v = base + i;
+  uint64_t key = ~0ull;
+  if (i < tile_nodes && v < n) {
+    const int32_t deg = rp[v + 1] - rp[v];
+    if (deg <= light_max) key = ((uint64_t)(0x7fffffff - deg) << 32) | (uint32_t)i;
+  }
+  keys[i] = key;
+  __syncthreads();
+  for (int k = 2; k <= kMaxTile; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int p = i ^ j;
+      if (p > i) {
+        const uint64_t x = keys[i], y = keys[p];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+          keys[i] = y;
+          keys[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (i < tile_nodes) {
+    const uint64_t s = keys[i];
+    light[base + i] = (s == ~0ull) ? -1 : (int32_t)(base + (int64_t)(s & 0xffffffffull));
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan (uint64)
+
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = kScanThreads * kScanPer;
+
+__device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t *total) {
+  __shared__ uint64_t buf[kScanThreads];
+  const int i = threadIdx.x;
+  buf[i] = x;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint64_t y = i >= off ? buf[i - off] : 0;
+    __syncthreads();
+    buf[i] += y;
+    __syncthreads();
+  }
+  const uint64_t incl = buf[i];
+  *total = buf[kScanThreads - 1];
+  __syncthreads();
+  return incl - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const uint64_t *d, int64_t n, uint64_t *sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  uint64_t s = 0;
+  for (int k = 0; k < kScanPer; ++k)
+    if (base + k < n) s += d[base + k];
+  uint64_t total;
+  block_exclusive_scan(s, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(uint64_t *sums, int64_t nb) {
+  const int64_t per = (nb + kScanThreads - 1) / kScanThreads;
+  const int64_t lo = (int64_t)threadIdx.x * per, hi = min(nb, lo + per);
+  uint64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += sums[i];
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, &total);
+  for (int64_t i = lo; i < hi; ++i) {
+    const uint64_t x = sums[i];
+    sums[i] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint64_t *d, int64_t n, const uint64_t *sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  uint64_t v[kScanPer];
+  uint64_t s = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = base + k < n ? d[base + k] : 0;
+    s += v[k];
+  }
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(s, &total) + sums[blockIdx.x];
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) d[base + k] = run;
+    run += v[k];
+  }
+}
+
+// ------------------------------------------------------------------ statistics (Sections 4-5)
+
+// out: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi, T. One thread: O(T) work.
+__global__ void k_stats(const double *nt, const DevState *st, double alpha, double eps,
+                        int32_t distinct, double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int32_t T = st->t;
+  double M = nt[0];
+  for (int32_t t = 1; t <= T; ++t) M = nt[t] > M ? nt[t] : M;
+  const double base = distinct ? nt[0] : 0.0;
+  const double den = M - base;
+  const double nan = __builtin_nan("");
+  double ed = nan, ied = nan, mean = 0.0, second = 0.0;
+  double Hprev = 0.0;
+  bool found = false;
+  for (int32_t t = 0; t <= T; ++t) {
+    const double H = den > 0.0 ? (nt[t] - base) / den : nan;
+    const double h = H - Hprev;
+    mean += (double)t * h;
+    second += (double)t * (double)t * h;
+    if (!found && H >= alpha) {
+      found = true;
+      ed = (double)t;
+      ied = t == 0 ? 0.0 : (double)(t - 1) + (alpha - Hprev) / (H - Hprev);
+    }
+    Hprev = H;
+  }
+  const double var = second - mean * mean;
+  double d_lo = -1.0, d_hi = -1.0;
+  for (int32_t t = 0; t <= T; ++t) {
+    const double r = nt[t] / M;
+    if (r <= alpha * (1.0 - 2.0 * eps)) d_lo = (double)t;
+    if (d_hi < 0.0 && r >= alpha * (1.0 + 2.0 * eps)) d_hi = (double)t;
+  }
+  out[0] = ed;
+  out[1] = ied;
+  out[2] = mean;
+  out[3] = var;
+  out[4] = mean != 0.0 ? var / mean : nan;
+  out[5] = M;
+  out[6] = d_lo;
+  out[7] = d_hi;
+  out[8] = (double)T;
+}
+
+__global__ void k_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    out[i] = bytemax(x[i], y[i]);
+}
+
+int grid_for(int64_t items, int threads, int64_t cap = 1 << 20) {
+  int64_t g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t arcs,
+                           DevState *st, hipStream_t s) {
+  const int64_t top = arcs > (int64_t)n + 1 ? arcs : (int64_t)n + 1;
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(top, 256, 8192)), dim3(256), 0, s, row_ptr, col_idx, n,
+                     arcs, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st, t, frontier, max_passes);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
+                           uint64_t *keys, hipStream_t s) {
+  hipLaunchKernelGGL(k_classify, dim3(grid_for((int64_t)n + 1, 256, 1 << 30)), dim3(256), 0, s, row_ptr,
+                     n, light_max, chunk_arcs, keys);
+  return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t launch_exclusive_scan_u64(uint64_t *data, int64_t n, uint64_t *tmp, hipStream_t s) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_chunks(const int32_t *row_ptr, int32_t n, const uint64_t *offs,
+                              int32_t chunk_arcs, Chunk *chunks, Heavy *heavy, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_chunks, dim3(grid_for(n, 256, 1 << 30)), dim3(256), 0, s, row_ptr, n, offs,
+                     chunk_arcs, chunks, heavy);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t tile_nodes,
+                              int32_t n_tiles, int32_t *light, hipStream_t s) {
+  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)n_tiles), dim3(kMaxTile), 0, s, row_ptr, n, light_max,
+                     tile_nodes, light);
+  return hipGetLastError();
+}
+
+#define HANF_DISPATCH_G(G_, EXPR) \
+  switch (G_) {                   \
+    case 1: { constexpr int G = 1; EXPR; } break;   \
+    case 2: { constexpr int G = 2; EXPR; } break;   \
+    case 4: { constexpr int G = 4; EXPR; } break;   \
+    case 8: { constexpr int G = 8; EXPR; } break;   \
+    case 16: { constexpr int G = 16; EXPR; } break; \
+    default: return hipErrorInvalidValue;           \
+  }
+
+hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s) {
+  const int G = 1 << (a.log2m - 4);
+  const int64_t lanes = (int64_t)a.n * G > 2 * (int64_t)a.n_blocks ? (int64_t)a.n * G : 2 * (int64_t)a.n_blocks;
+  const int grid = grid_for(lanes, kBlockThreads, 1 << 30);
+  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_init<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, seed));
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s) {
+  const int G = 1 << (a.log2m - 4);
+  const int64_t lanes = (int64_t)a.n * G > 2 * (int64_t)a.n_blocks ? (int64_t)a.n * G : 2 * (int64_t)a.n_blocks;
+  const int grid = grid_for(lanes, kBlockThreads, 1 << 30);
+  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_estimate_all<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, regs));
+  return hipGetLastError();
+}
+
+hipError_t launch_union(const PassArgs &a, int u, hipStream_t s) {
+  const int G = 1 << (a.log2m - 4);
+  const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs)), block(kBlockThreads);
+  if (grid.x == 0) return hipSuccess;
+  switch (u) {
+    case 2:
+      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 2>), grid, block, 0, s, a));
+      break;
+    case 8:
+      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 8>), grid, block, 0, s, a));
+      break;
+    default:
+      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 4>), grid, block, 0, s, a));
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
+  if (a.n_fin_wgs == 0) return hipSuccess;
+  const int G = 1 << (a.log2m - 4);
+  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
+                                        s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_blocks, dim3((unsigned)a.n_reduce_wgs), dim3(kBlockThreads), 0, s, a, force);
+  hipLaunchKernelGGL(k_reduce_top, dim3(1), dim3(kTopThreads), 0, s, a, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats(const double *nt, const DevState *st, double alpha, double eps,
+                        int32_t distinct, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, nt, st, alpha, eps, distinct, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_registers(const uint8_t *regs, int64_t bytes, DevState *st, hipStream_t s) {
+  const int64_t nw = bytes / 4;
+  hipLaunchKernelGGL(k_check_registers, dim3(grid_for(nw, 256, 8192)), dim3(256), 0, s,
+                     reinterpret_cast<const uint32_t *>(regs), nw, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_bytemax_words, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, x, y, out, count);
+  return hipGetLastError();
+}
+
+}  // namespace hanf

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Registers must be byte-identical at every iteration checked, N_hat(t) within 1e-12
+relative (FP64 sums in a different order), the fixpoint iteration T equal, and the
+per-pass work counters (counters changed, successor unions) exactly the oracle's.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import stats as ostats
+
+pytestmark = pytest.mark.gpu
+
+hanf = pytest.importorskip("paper_1011_5599_amd")
+
+RTOL = 1e-12
+
+
+def _flush(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def step_parity(rp, ci, b, seed, check_every=1, **opts):
+    """Runs GPU and oracle side by side one pass at a time; checks everything."""
+    n = len(rp) - 1
+    _flush(f"[parity] n={n} arcs={len(ci)} b={b} seed={seed} opts={opts}")
+    ref = oracle.run_steps(rp, ci, b, seed, skip_unmodified=True)
+    mod = np.ones(n, np.uint8)
+    with hanf.HyperANF(0, **opts) as h:
+        h.load(rp, ci).init(b, seed)
+        nts = []
+        T = None
+        for t, c, s in ref:
+            nts.append(s)
+            if t % check_every == 0:
+                got = h.registers()
+                assert np.array_equal(got, c), f"registers differ at t={t}"
+            # the oracle's next pass, for the exact work counters
+            _, mod_out, changed, maxed = oracle.step(rp, ci, b, c, mod)
+            st, steps, ch_last = h.step(1)
+            assert steps == 1
+            log = h.pass_log()[-1]
+            assert log["changed"] == changed, (t, log, changed)
+            if opts.get("frontier", 1):
+                assert log["arcs_gathered"] == maxed, (t, log, maxed)
+            assert ch_last == changed
+            mod = mod_out
+            T = t
+            if changed == 0:
+                assert st == hanf.HANF_DONE
+            else:
+                assert st == hanf.HANF_OK
+        got_nt = h.nt()
+        want = np.array(nts)
+        assert len(got_nt) == len(want) == T + 1
+        np.testing.assert_allclose(got_nt, want, rtol=RTOL, atol=0)
+        return h.stats(), want
+
+
+def test_bytemax_exhaustive():
+    """The packed register max equals np.maximum for every pair of byte values < 128 in
+    every byte position."""
+    import torch
+    vals = np.arange(128, dtype=np.uint32)
+    X, Y = np.meshgrid(vals, vals, indexing="ij")
+    X = X.ravel()
+    Y = Y.ravel()
+    rng = np.random.default_rng(0)
+    for pos in range(4):
+        ox = rng.integers(0, 128, (X.size, 4)).astype(np.uint32)
+        oy = rng.integers(0, 128, (X.size, 4)).astype(np.uint32)
+        ox[:, pos] = X
+        oy[:, pos] = Y
+        wx = (ox[:, 0] | (ox[:, 1] << 8) | (ox[:, 2] << 16) | (ox[:, 3] << 24)).astype(np.uint32)
+        wy = (oy[:, 0] | (oy[:, 1] << 8) | (oy[:, 2] << 16) | (oy[:, 3] << 24)).astype(np.uint32)
+        want = np.maximum(ox, oy)
+        want_w = (want[:, 0] | (want[:, 1] << 8) | (want[:, 2] << 16) | (want[:, 3] << 24)).astype(np.uint32)
+        tx = torch.from_numpy(wx.view(np.int32)).cuda()
+        ty = torch.from_numpy(wy.view(np.int32)).cuda()
+        to = torch.empty_like(tx)
+        hanf.hanf_bytemax_words(0, tx, ty, to)
+        assert np.array_equal(to.cpu().numpy().view(np.uint32), want_w)
+
+
+def test_rmat14_every_iteration():
+    """Directed R-MAT scale 14, 262,144 arcs, 16 registers, hash seed 1: registers at every
+    t, N_hat, T, work counters; statistics against the oracle's."""
+    rp, ci = graphgen.rmat(14, 262_144, seed=14)
+    s, want = step_parity(rp, ci, 4, 1)
+    ref = ostats.stats(list(want))
+    for k in ("ed", "ied", "avg_dist", "var", "spid", "n_max"):
+        assert s[k] == pytest.approx(ref[k], rel=1e-10), k
+    assert s["T"] == ref["T"]
+
+
+@pytest.mark.parametrize("b", [4, 5, 6, 7, 8])
+def test_register_counts_with_heavy_rows(b):
+    """Every m, on a graph whose high-degree rows are split over several wavefront chunks."""
+    rp, ci = graphgen.rmat(12, 60_000, seed=40 + b)
+    deg = np.diff(rp)
+    assert deg.max() > 1000
+    step_parity(rp, ci, b, 1000 + b)
+
+
+def test_frontier_off_identical():
+    """Dense passes (no modified-counter skipping) give identical counters at every t."""
+    rp, ci = graphgen.rmat(11, 20_000, seed=5)
+    step_parity(rp, ci, 6, 3, frontier=0)
+
+
+@pytest.mark.parametrize("opts", [dict(light_max=4, chunk_arcs=16), dict(light_max=1000, chunk_arcs=4096),
+                                  dict(tile_nodes=16, unroll=2), dict(unroll=8, tile_nodes=256),
+                                  dict(batch=1)])
+def test_schedules_identical(opts):
+    """Any work schedule gives the same counters (max is order-free)."""
+    rp, ci = graphgen.rmat(12, 40_000, seed=6)
+    step_parity(rp, ci, 6, 17, **opts)
+
+
+@pytest.mark.parametrize("name", ["single", "empty100", "star_out", "star_in", "cycle", "path",
+                                  "complete", "cpc", "loops_dups"])
+def test_edge_graphs(name):
+    if name == "single":
+        g = graphgen.empty(1)
+    elif name == "empty100":
+        g = graphgen.empty(100)
+    elif name == "star_out":
+        g = graphgen.star_out(100_001)
+    elif name == "star_in":
+        g = graphgen.star_in(30_000)
+    elif name == "cycle":
+        g = graphgen.directed_cycle(300)
+    elif name == "path":
+        g = graphgen.directed_path(700)
+    elif name == "complete":
+        g = graphgen.complete(120)
+    elif name == "cpc":
+        g = graphgen.clique_path_clique(40, 7)
+    else:
+        rp, ci = graphgen.erdos_renyi(3000, 20_000, seed=8)
+        n = len(rp) - 1
+        arcs = [(u, int(w)) for u in range(n) for w in ci[rp[u]:rp[u + 1]]]
+        arcs += arcs[::7] + [(u, u) for u in range(0, n, 5)]
+        g = graphgen.from_arcs(n, arcs)
+    for b in (4, 7):
+        step_parity(*g, b, 99)
+
+
+def test_device_pointers_match_host():
+    import torch
+    rp, ci = graphgen.rmat(13, 100_000, seed=9)
+    trp = torch.from_numpy(rp).cuda()
+    tci = torch.from_numpy(ci).cuda()
+    with hanf.HyperANF(0) as a, hanf.HyperANF(0) as d:
+        a.load(rp, ci).init(6, 5)
+        d.load(trp, tci).init(6, 5)
+        na = a.run()
+        nd = d.run()
+        assert np.array_equal(na, nd)
+        assert np.array_equal(a.registers(), d.registers())
+        out = torch.empty(d.n * 64, dtype=torch.uint8, device="cuda")
+        d.registers(out)
+        assert np.array_equal(out.cpu().numpy().reshape(d.n, 64), a.registers())
+
+
+def test_checkpoint_resume_identical():
+    rp, ci = graphgen.rmat(12, 50_000, seed=12)
+    with hanf.HyperANF(0) as h:
+        h.load(rp, ci).init(5, 77)
+        full = h.run()
+        final = h.registers()
+    with hanf.HyperANF(0) as h:
+        h.load(rp, ci).init(5, 77)
+        h.step(3)
+        regs = h.registers()
+        prefix = h.nt()
+    with hanf.HyperANF(0) as h2:
+        h2.load(rp, ci).init(5, 1)  # fixes m; counters are replaced
+        hanf.hanf_write_registers(h2.ctx, regs, 3, prefix)
+        nt = h2.run()
+        assert np.array_equal(h2.registers(), final)
+        np.testing.assert_allclose(nt, full, rtol=RTOL, atol=0)
+        assert len(nt) == len(full)
+
+
+def test_errors():
+    rp, ci = graphgen.rmat(8, 1000, seed=1)
+    with hanf.HyperANF(0) as h:
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_iterate(h.ctx)
+        assert e.value.code == hanf.HANF_ESTATE
+        bad = rp.copy()
+        bad[0] = 1
+        with pytest.raises(hanf.HanfError) as e:
+            h.load(bad, ci)
+        assert e.value.code == hanf.HANF_EINVAL
+        bad = rp.copy()
+        bad[5], bad[6] = bad[6], bad[5] + 3
+        with pytest.raises(hanf.HanfError):
+            h.load(bad, ci)
+        badc = ci.copy()
+        badc[10] = len(rp) - 1
+        with pytest.raises(hanf.HanfError):
+            h.load(rp, badc)
+        badc[10] = -1
+        with pytest.raises(hanf.HanfError):
+            h.load(rp, badc)
+        h.load(rp, ci)
+        for b in (3, 9):
+            with pytest.raises(hanf.HanfError) as e:
+                h.init(b, 1)
+            assert e.value.code == hanf.HANF_EINVAL
+        h.init(6, 1)
+        bad_regs = np.full((len(rp) - 1, 64), 32, np.uint8)
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_write_registers(h.ctx, bad_regs, 0, [1.0])
+        assert e.value.code == hanf.HANF_EINVAL
+    # pass cap
+    rp, ci = graphgen.directed_path(200)
+    with hanf.HyperANF(0, max_passes=5) as h:
+        h.load(rp, ci).init(6, 1)
+        with pytest.raises(hanf.HanfError) as e:
+            h.run()
+        assert e.value.code == hanf.HANF_EMAXITER
+        assert len(h.nt()) == 6
+
+
+def test_forced_allocation_failure():
+    rp, ci = graphgen.rmat(8, 1000, seed=1)
+    for k in (2, 5, 9):
+        os.environ["HANF_TEST_FAIL_ALLOC"] = str(k)
+        try:
+            h = hanf.HyperANF(0)
+        finally:
+            del os.environ["HANF_TEST_FAIL_ALLOC"]
+        with pytest.raises(hanf.HanfError) as e:
+            h.load(rp, ci).init(6, 1)
+        assert e.value.code == hanf.HANF_ENOMEM
+        h.close()
