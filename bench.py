@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""HyperANF benchmark on one MI355X.
+
+One step is a whole HyperANF run on a graph already resident in HBM: graph ingest
+(device-side validation and work schedule), counter initialisation, passes until no
+counter changes, and the statistics (distance distribution, effective diameter, spid).
+The default workload is the symmetric R-MAT graph of scale 22 (2^22 nodes, 2^26 arcs,
+a=.57 b=.19 c=.19 d=.05) with 64 registers per counter and hash seed 7.
+
+Prints one JSON line. `value` = edge-register updates per second over the whole step:
+m * (successor counters actually maximised in, summed over the passes) / step time.
+`roofline` is for the union kernel (the dominant kernel), timed with HIP events on the
+library's stream; `cpu_baseline` times the CPU oracle on the whole run of the same graph,
+multi-threaded over node segments.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(rec, n, m):
+    """Bytes a union pass must move: row_ptr (4 B/node), col_idx of every arc scanned
+    (4 B), m bytes per successor counter maximised in, per own counter read and per new
+    counter written, and one flag bit per node read and written."""
+    return (4 * (n + 1) + 4 * rec["arcs_scanned"]
+            + m * (rec["arcs_gathered"] + rec["rows_read"] + rec["rows_written"]) + n // 4)
+
+
+def run_cpu_baseline(rp, ci, b, seed, passes, threads):
+    """The oracle on the same job: initialisation, N_hat(t) every iteration, passes (with
+    modified-counter skipping, multi-threaded over node segments) until no counter changes,
+    or `passes` passes when passes > 0."""
+    import numpy as np
+
+    import oracle
+    n = len(rp) - 1
+    t0 = time.perf_counter()
+    c = oracle.init(n, b, seed)
+    mod = np.ones(n, np.uint8)
+    maxed_total = 0
+    done = 0
+    while True:
+        oracle.sum_sizes(c, b)
+        if passes > 0 and done >= passes:
+            break
+        nxt, mod, changed, maxed = oracle.step(rp, ci, b, c, mod, nthreads=threads)
+        maxed_total += maxed
+        done += 1
+        if changed == 0:
+            break
+        c = nxt
+    el = time.perf_counter() - t0
+    what = "the whole run to the fixpoint" if passes <= 0 else f"initialisation and the first {done} passes"
+    return dict(value=(1 << b) * maxed_total / el, unit="edge-register updates/s", cores=threads,
+                kind="oracle",
+                sample=f"{what} of the same graph ({done} passes, {maxed_total} successor unions, "
+                       f"N_hat every iteration) in {el:.2f} s, {threads} threads over contiguous "
+                       f"node segments")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat22sym")
+    ap.add_argument("--cpu-passes", type=int, default=0, help="0 = whole run to the fixpoint")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--opt", action="append", default=[], help="library option name=value")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              f"(asked for {max(args.gpus, world)}).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1011_5599_amd as hanf
+
+    spec = graphgen.WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    rp, ci = graphgen.workload_graph(spec)
+    gen_s = time.perf_counter() - t0
+    n, arcs = len(rp) - 1, len(ci)
+    b, seed = spec["log2m"], spec["seed"]
+    m = 1 << b
+    print(f"[bench] workload={args.workload} n={n} arcs={arcs} m={m} gen={gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    trp = torch.from_numpy(rp).to(dev)
+    tci = torch.from_numpy(ci).to(dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    opts = dict(timing=0 if args.no_timing else 1)
+    for kv in args.opt:
+        k, v = kv.split("=")
+        opts[k] = int(v)
+    h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
+
+    def step():
+        h.load(trp, tci)
+        h.init(b, seed)
+        nt = h.run()
+        return nt, h.stats(), h.pass_log()
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    logs = []
+    for i in range(args.steps):
+        nt, st, log = step()
+        logs.append(log)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    print(f"[bench] {args.steps} steps in {elapsed:.3f}s, T={st['T']}", file=sys.stderr, flush=True)
+
+    log = logs[-1]
+    updates = m * sum(r["arcs_gathered"] for r in log)
+    value = updates / (ms_per_step / 1000.0)
+
+    roofline = None
+    full_pass = None
+    if not args.no_timing:
+        all_recs = [r for lg in logs for r in lg]
+        union_ms = sum(r["union_ms"] for r in all_recs)
+        byts = sum(algorithmic_bytes(r, n, m) for r in all_recs)
+        launches = len(all_recs)
+        achieved = byts / (union_ms / 1000.0) / 1e9
+        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                        kernel="k_union", launches=launches,
+                        avg_launch_us=round(1000.0 * union_ms / launches, 2),
+                        avg_algorithmic_bytes=int(byts / launches))
+        p0 = [lg[0] for lg in logs]
+        ms0 = sum(r["union_ms"] for r in p0) / len(p0)
+        b0 = algorithmic_bytes(p0[0], n, m)
+        full_pass = dict(union_ms=round(ms0, 4), algorithmic_gb=round(b0 / 1e9, 4),
+                         gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
+                         updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0),
+                         frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4))
+        other = dict(finalize_ms=round(sum(r["finalize_ms"] for r in log), 4),
+                     reduce_ms=round(sum(r["reduce_ms"] for r in log), 4),
+                     union_ms=round(sum(r["union_ms"] for r in log), 4))
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        cpu = run_cpu_baseline(rp, ci, b, seed, args.cpu_passes, threads)
+
+    out = {
+        "metric": "edge-register updates/s",
+        "value": value,
+        "unit": "edge-register updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": spec_name(args.workload), "n": n, "arcs": arcs, "log2m": b,
+                   "hash_seed": seed, "T": st["T"], "passes": len(log)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "full_pass": full_pass,
+        "per_step_kernel_ms": other if not args.no_timing else None,
+        "dense_equivalent_updates_per_s": m * arcs * (st["T"] + 1) / (ms_per_step / 1000.0),
+        "graphs_per_s": 1000.0 / ms_per_step,
+        "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
+    }
+    h.close()
+    print(json.dumps(out))
+
+
+def spec_name(name):
+    return {
+        "rmat22sym": "symmetric R-MAT scale 22 (a=.57,b=.19,c=.19), 2^26 arcs, 64 registers, hash seed 7",
+        "rmat14": "directed R-MAT scale 14, 262144 arcs, 16 registers, hash seed 1",
+        "web24": "web-like 2^24 nodes, lognormal hosts (mean 1000), out-degree mean 20, 80% local arcs, "
+                 "power-law in-degree 2.1, 128 registers, hash seed 1",
+    }.get(name, name)
+
+
+if __name__ == "__main__":
+    main()

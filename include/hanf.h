@@ -82,6 +82,7 @@ typedef struct {
   int64_t arcs_scanned;  /* arcs whose successor was examined */
   int64_t arcs_gathered; /* arcs whose successor counter was maximised in (A_t) */
   int64_t rows_written;  /* counters written to the next buffer */
+  int64_t rows_read;     /* own counters read to build a new counter */
   float union_ms;        /* union kernel time (HANF_OPT_TIMING), else 0 */
   float finalize_ms;     /* multi-chunk combine kernel time, else 0 */
   float reduce_ms;       /* estimate reduction kernels time, else 0 */

@@ -55,6 +55,7 @@ class hanf_stats_t(ctypes.Structure):
 class hanf_pass_t(ctypes.Structure):
     _fields_ = [("changed", ctypes.c_int64), ("arcs_scanned", ctypes.c_int64),
                 ("arcs_gathered", ctypes.c_int64), ("rows_written", ctypes.c_int64),
+                ("rows_read", ctypes.c_int64),
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
                 ("reduce_ms", ctypes.c_float), ("pad_", ctypes.c_float)]
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -52,7 +53,8 @@ struct hanf_ctx {
   std::string err;
   int fail_alloc_at = 0;  // test hook (HANF_TEST_FAIL_ALLOC): make that allocation fail
   int alloc_count = 0;
-  std::vector<void *> allocs;
+  std::multimap<size_t, void *> pool;  // released device buffers, reused by exact size
+  std::map<void *, size_t> sizes;      // byte size of every live or pooled buffer
 
   // options
   int frontier = 1;
@@ -109,20 +111,54 @@ int hip_fail(hanf_ctx *c, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
   } while (0)
 
+// Device allocations go through a per-context pool: a released buffer is kept and handed
+// out again for a request of the same byte size, so repeated runs on graphs of one size
+// allocate nothing after the first. Everything is returned to HIP at hanf_destroy.
 template <typename T>
 int dev_alloc(hanf_ctx *c, T **p, size_t count, const char *what) {
   *p = nullptr;
   c->alloc_count++;
   if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at)
     return fail(c, HANF_ENOMEM, std::string("forced allocation failure: ") + what);
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  auto it = c->pool.find(bytes);
+  if (it != c->pool.end()) {
+    *p = static_cast<T *>(it->second);
+    c->pool.erase(it);
+    return HANF_OK;
+  }
   void *q = nullptr;
-  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    // release pooled buffers and retry once
+    for (auto &kv : c->pool) {
+      c->sizes.erase(kv.second);
+      (void)hipFree(kv.second);
+    }
+    c->pool.clear();
+    e = hipMalloc(&q, bytes);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, HANF_ENOMEM, std::string("hipMalloc failed for ") + what + ": " + hipGetErrorString(e));
   }
+  c->sizes[q] = bytes;
   *p = static_cast<T *>(q);
   return HANF_OK;
+}
+
+// Returns a buffer to the context's pool (the pointer is cleared).
+template <typename T>
+void dev_release(hanf_ctx *c, T *&p) {
+  if (p) {
+    auto it = c->sizes.find((void *)p);
+    if (it != c->sizes.end())
+      c->pool.emplace(it->second, (void *)p);
+    else
+      (void)hipFree(p);
+  }
+  p = nullptr;
 }
 
 template <typename T>
@@ -133,35 +169,35 @@ void dev_free(T *&p) {
 
 void free_schedule(hanf_ctx *c) {
   Schedule &s = c->sch;
-  dev_free(s.light);
-  dev_free(s.chunks);
-  dev_free(s.heavy);
-  dev_free(s.partial);
-  dev_free(s.partial_any);
-  dev_free(s.wgstat);
+  dev_release(c, s.light);
+  dev_release(c, s.chunks);
+  dev_release(c, s.heavy);
+  dev_release(c, s.partial);
+  dev_release(c, s.partial_any);
+  dev_release(c, s.wgstat);
   s = Schedule();
 }
 
 void free_run(hanf_ctx *c) {
   for (int i = 0; i < 2; ++i) {
-    dev_free(c->regs[i]);
-    dev_free(c->bits[i]);
+    dev_release(c, c->regs[i]);
+    dev_release(c, c->bits[i]);
   }
-  dev_free(c->est);
-  dev_free(c->blocksum);
-  dev_free(c->wgsum);
-  dev_free(c->wgcnt);
-  dev_free(c->lc);
-  dev_free(c->nt);
-  dev_free(c->log);
-  dev_free(c->stats_out);
+  dev_release(c, c->est);
+  dev_release(c, c->blocksum);
+  dev_release(c, c->wgsum);
+  dev_release(c, c->wgcnt);
+  dev_release(c, c->lc);
+  dev_release(c, c->nt);
+  dev_release(c, c->log);
+  dev_release(c, c->stats_out);
   c->inited = false;
   c->log2m = 0;
 }
 
 void free_graph(hanf_ctx *c) {
-  dev_free(c->rp_own);
-  dev_free(c->ci_own);
+  dev_release(c, c->rp_own);
+  dev_release(c, c->ci_own);
   c->rp = c->ci = nullptr;
   c->graph_ok = false;
   c->n = 0;
@@ -211,7 +247,7 @@ int build_schedule(hanf_ctx *c, int G) {
   uint64_t *keys = nullptr, *tmp = nullptr;
   if ((rc = dev_alloc(c, &keys, (size_t)n + 1, "schedule keys"))) return rc;
   if ((rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
-    dev_free(keys);
+    dev_release(c, keys);
     return rc;
   }
   hipError_t e = launch_classify(c->rp, n, s.light_max, s.chunk_arcs, keys, c->stream);
@@ -220,8 +256,8 @@ int build_schedule(hanf_ctx *c, int G) {
   if (e == hipSuccess) e = hipMemcpyAsync(&total, keys + n, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
-    dev_free(keys);
-    dev_free(tmp);
+    dev_release(c, keys);
+    dev_release(c, tmp);
     return hip_fail(c, e, "schedule scan");
   }
   s.n_chunks = (int32_t)(total >> 32);
@@ -231,14 +267,14 @@ int build_schedule(hanf_ctx *c, int G) {
       (rc = dev_alloc(c, &s.heavy, (size_t)s.n_heavy, "heavy nodes")) ||
       (rc = dev_alloc(c, &s.partial, (size_t)s.n_chunks * m, "chunk partials")) ||
       (rc = dev_alloc(c, &s.partial_any, (size_t)s.n_chunks, "chunk flags"))) {
-    dev_free(keys);
-    dev_free(tmp);
+    dev_release(c, keys);
+    dev_release(c, tmp);
     return rc;
   }
   e = launch_fill_chunks(c->rp, n, keys, s.chunk_arcs, s.chunks, s.heavy, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  dev_free(keys);
-  dev_free(tmp);
+  dev_release(c, keys);
+  dev_release(c, tmp);
   if (e != hipSuccess) return hip_fail(c, e, "fill chunks");
   s.n_chunk_wgs = (s.n_chunks + 3) / 4;
   s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
@@ -384,7 +420,10 @@ void hanf_destroy(hanf_ctx *c) {
   free_run(c);
   free_schedule(c);
   free_graph(c);
-  dev_free(c->st);
+  dev_release(c, c->st);
+  for (auto &kv : c->sizes) (void)hipFree(kv.first);
+  c->sizes.clear();
+  c->pool.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -561,6 +600,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.arcs_scanned = recs[i].scanned;
         r.arcs_gathered = recs[i].gathered;
         r.rows_written = recs[i].written;
+        r.rows_read = recs[i].read;
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * 4];
           (void)hipEventElapsedTime(&r.union_ms, e[0], e[1]);

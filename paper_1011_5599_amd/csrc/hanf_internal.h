@@ -31,7 +31,7 @@ struct DevState {
 };
 
 struct PassLog {  // per executed pass, filled on the device
-  int64_t changed, scanned, gathered, written;
+  int64_t changed, scanned, gathered, written, read;
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
@@ -54,7 +54,7 @@ struct PassArgs {
   double *blocksum;          // per 64 nodes
   double *wgsum;             // per reduce workgroup
   int64_t *wgcnt;            // per reduce workgroup: changed counters
-  int64_t *wgstat;           // per union/finalize workgroup: scanned, gathered, written, pad
+  int64_t *wgstat;           // per union/finalize workgroup: scanned, gathered, written, read
   const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
   const Chunk *chunks;
   const Heavy *heavy;

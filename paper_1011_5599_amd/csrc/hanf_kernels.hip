@@ -127,7 +127,7 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, int32_t t, int32_
 }
 
 struct Counters {
-  int32_t scanned = 0, gathered = 0, written = 0;
+  int32_t scanned = 0, gathered = 0, written = 0, read = 0;
 };
 
 // Writes c_{t+1}[v] for the node of a slot, given `acc`, the max over the successors
@@ -143,7 +143,10 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
   const bool pv = (v >= 0 && f.copy_check) ? testbit(f.prev_bits, v) : false;
   const bool work = v >= 0 && (any || pv);
   if (work && !own_loaded) own = ldrow(f.cur, v, m, sub);
-  if (work) acc = bytemax4(acc, own);
+  if (work) {
+    acc = bytemax4(acc, own);
+    if (sub == 0) cnt.read++;
+  }
   const bool diff = work && (acc.x != own.x || acc.y != own.y || acc.z != own.z || acc.w != own.w);
   const uint64_t bal = __ballot(diff);
   const int first_lane = lane & ~(G - 1);
@@ -278,26 +281,22 @@ __device__ __forceinline__ T wave_sum(T x) {
 }
 
 __device__ __forceinline__ void store_block_counters(const Counters &c, int64_t *out) {
-  __shared__ int32_t red[3][kBlockThreads / kWave];
+  __shared__ int32_t red[4][kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written);
+  const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written),
+                s3 = wave_sum(c.read);
   if (lane == 0) {
     red[0][wave] = s0;
     red[1][wave] = s1;
     red[2][wave] = s2;
+    red[3][wave] = s3;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t t0 = 0, t1 = 0, t2 = 0;
-    for (int i = 0; i < kBlockThreads / kWave; ++i) {
-      t0 += red[0][i];
-      t1 += red[1][i];
-      t2 += red[2][i];
-    }
-    out[0] = t0;
-    out[1] = t1;
-    out[2] = t2;
-    out[3] = 0;
+    int64_t tot[4] = {0, 0, 0, 0};
+    for (int i = 0; i < kBlockThreads / kWave; ++i)
+      for (int k = 0; k < 4; ++k) tot[k] += red[k][i];
+    for (int k = 0; k < 4; ++k) out[k] = tot[k];
   }
 }
 
@@ -409,10 +408,10 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kTopThreads];
-  __shared__ int64_t s_i[4][kTopThreads];
+  __shared__ int64_t s_i[5][kTopThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
-  int64_t c = 0, sc = 0, ga = 0, wr = 0;
+  int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0;
   for (int32_t i = tid; i < a.n_reduce_wgs; i += kTopThreads) {
     s += a.wgsum[i];
     c += a.wgcnt[i];
@@ -423,6 +422,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       sc += a.wgstat[(size_t)i * 4 + 0];
       ga += a.wgstat[(size_t)i * 4 + 1];
       wr += a.wgstat[(size_t)i * 4 + 2];
+      rd += a.wgstat[(size_t)i * 4 + 3];
     }
   }
   s_sum[tid] = s;
@@ -430,11 +430,12 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   s_i[1][tid] = sc;
   s_i[2][tid] = ga;
   s_i[3][tid] = wr;
+  s_i[4][tid] = rd;
   __syncthreads();
   for (int off = kTopThreads / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_sum[tid] += s_sum[tid + off];
-      for (int k = 0; k < 4; ++k) s_i[k][tid] += s_i[k][tid + off];
+      for (int k = 0; k < 5; ++k) s_i[k][tid] += s_i[k][tid + off];
     }
     __syncthreads();
   }
@@ -450,6 +451,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       rec.scanned = s_i[1][0];
       rec.gathered = s_i[2][0];
       rec.written = s_i[3][0];
+      rec.read = s_i[4][0];
       if (p < a.nt_cap) a.log[p] = rec;
       st->passes = p + 1;
       st->changed_last = rec.changed;

@@ -105,8 +105,9 @@ def test_register_counts_with_heavy_rows(b):
     """Every m, on a graph whose high-degree rows are split over several wavefront chunks."""
     rp, ci = graphgen.rmat(12, 60_000, seed=40 + b)
     deg = np.diff(rp)
-    assert deg.max() > 1000
-    step_parity(rp, ci, b, 1000 + b)
+    assert deg.max() > 4 * 150
+    step_parity(rp, ci, b, 1000 + b, chunk_arcs=150)
+    step_parity(rp, ci, b, 2000 + b)
 
 
 def test_frontier_off_identical():
@@ -202,9 +203,15 @@ def test_errors():
             h.load(bad, ci)
         assert e.value.code == hanf.HANF_EINVAL
         bad = rp.copy()
-        bad[5], bad[6] = bad[6], bad[5] + 3
-        with pytest.raises(hanf.HanfError):
+        bad[5] = bad[6] + 5  # row_ptr decreases from 5 to 6
+        with pytest.raises(hanf.HanfError) as e:
             h.load(bad, ci)
+        assert e.value.code == hanf.HANF_EINVAL
+        bad = rp.copy()
+        bad[-1] += 1  # row_ptr[n] != arcs
+        with pytest.raises(hanf.HanfError) as e:
+            h.load(bad, ci)
+        assert e.value.code == hanf.HANF_EINVAL
         badc = ci.copy()
         badc[10] = len(rp) - 1
         with pytest.raises(hanf.HanfError):
