@@ -57,6 +57,10 @@ extern "C" {
 #define HANF_OPT_TIMING 5       /* 1: time every kernel with HIP events (hanf_read_pass_log) */
 #define HANF_OPT_BATCH 6        /* passes enqueued between host checks of the fixpoint (default 4) */
 #define HANF_OPT_TILE_NODES 7   /* nodes per light tile (multiple of the slots per wave; 0 = auto) */
+#define HANF_OPT_DENSE_SWITCH 8 /* d: after a pass that changed >= n/d counters, the next pass
+                                   maximises with every successor instead of testing each one's
+                                   modified flag (same result; cheaper when most changed).
+                                   Default 4; 0 = never */
 
 typedef struct hanf_ctx hanf_ctx;
 
@@ -86,7 +90,7 @@ typedef struct {
   float union_ms;        /* union kernel time (HANF_OPT_TIMING), else 0 */
   float finalize_ms;     /* multi-chunk combine kernel time, else 0 */
   float reduce_ms;       /* estimate reduction kernels time, else 0 */
-  float pad_;
+  int32_t gather_all;    /* 1 if the pass maximised with every successor */
 } hanf_pass_t;
 
 /* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work

@@ -39,6 +39,7 @@ HANF_OPT_CHUNK_ARCS = 4
 HANF_OPT_TIMING = 5
 HANF_OPT_BATCH = 6
 HANF_OPT_TILE_NODES = 7
+HANF_OPT_DENSE_SWITCH = 8
 HANF_OPT_UNROLL = 100
 
 ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
@@ -57,7 +58,7 @@ class hanf_pass_t(ctypes.Structure):
                 ("arcs_gathered", ctypes.c_int64), ("rows_written", ctypes.c_int64),
                 ("rows_read", ctypes.c_int64),
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
-                ("reduce_ms", ctypes.c_float), ("pad_", ctypes.c_float)]
+                ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32)]
 
 
 class HanfError(RuntimeError):
@@ -218,7 +219,7 @@ def hanf_read_pass_log(ctx) -> list[dict]:
     _check(rc, ctx, ok=(HANF_OK, HANF_ERANGE))
     arr = (hanf_pass_t * max(n.value, 1))()
     _check(lib().hanf_read_pass_log(ctx, ctypes.cast(arr, ctypes.c_void_p), n.value, ctypes.byref(n)), ctx)
-    return [{f: getattr(arr[i], f) for f, _ in hanf_pass_t._fields_ if f != "pad_"}
+    return [{f: getattr(arr[i], f) for f, _ in hanf_pass_t._fields_}
             for i in range(n.value)]
 
 
@@ -246,7 +247,8 @@ class HyperANF:
         names = {"frontier": HANF_OPT_FRONTIER, "max_passes": HANF_OPT_MAX_PASSES,
                  "light_max": HANF_OPT_LIGHT_MAX, "chunk_arcs": HANF_OPT_CHUNK_ARCS,
                  "timing": HANF_OPT_TIMING, "batch": HANF_OPT_BATCH,
-                 "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL}
+                 "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
+                 "dense_switch": HANF_OPT_DENSE_SWITCH}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))
 

@@ -61,6 +61,7 @@ struct hanf_ctx {
   int64_t max_passes_opt = 0;
   int32_t light_max_opt = 0, chunk_opt = 0, tile_opt = 0;
   int timing = 0;
+  int dense_div = 4;  // a pass after one that changed >= n/dense_div counters maximises with all successors
   int batch = 4;
   int unroll = 4;
 
@@ -356,6 +357,11 @@ int alloc_run(hanf_ctx *c, int log2m) {
   return HANF_OK;
 }
 
+int64_t dense_threshold(const hanf_ctx *c) {
+  if (c->dense_div <= 0) return 0;
+  return std::max<int64_t>(1, (int64_t)c->n / c->dense_div);
+}
+
 int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   hipStream_t s = c->stream;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
@@ -459,6 +465,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < 0 || value > kMaxTile) return fail(c, HANF_EINVAL, "tile nodes must be in 0..256");
       c->tile_opt = (int32_t)value;
       break;
+    case HANF_OPT_DENSE_SWITCH:
+      if (value < 0 || value > (1 << 30)) return fail(c, HANF_EINVAL, "dense switch out of range");
+      c->dense_div = (int)value;
+      break;
     case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
       if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
       c->unroll = (int)value;
@@ -510,7 +520,7 @@ int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, 
   }
   c->n = n;
   c->arcs = arcs;
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, c->stream), "state reset");
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream), "state reset");
   HIP_TRY(c, launch_validate(c->rp, c->ci, n, arcs, c->st, c->stream), "validate");
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) {
@@ -547,7 +557,8 @@ int hanf_init_counters(hanf_ctx *c, int32_t log2m, uint64_t seed) {
   c->inited = false;
   fill_args(c);
   c->host_log.clear();
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, c->stream), "state reset");
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, dense_threshold(c), c->stream),
+          "state reset");
   HIP_TRY(c, launch_init(c->args, seed, c->stream), "init kernel");
   HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
   c->inited = true;
@@ -601,6 +612,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.arcs_gathered = recs[i].gathered;
         r.rows_written = recs[i].written;
         r.rows_read = recs[i].read;
+        r.gather_all = (int32_t)recs[i].gather_all;
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * 4];
           (void)hipEventElapsedTime(&r.union_ms, e[0], e[1]);
@@ -663,7 +675,8 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   c->inited = false;
-  HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, c->stream), "state reset");
+  HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), c->stream),
+          "state reset");
   HIP_TRY(c, hipMemcpyAsync(c->regs[t & 1], in, (size_t)bytes, kind, c->stream), "register upload");
   HIP_TRY(c, launch_check_registers(c->regs[t & 1], bytes, c->st, c->stream), "register check");
   int rc;

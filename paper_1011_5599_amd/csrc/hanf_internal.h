@@ -26,12 +26,14 @@ struct DevState {
   int32_t max_passes;
   int32_t passes;     // passes executed so far
   int32_t err;        // validation error bits
-  int32_t pad_;
+  int32_t dense_next; // 1: the next pass maximises with every successor (the previous pass
+                      // changed at least dense_threshold counters)
   int64_t changed_last;
+  int64_t dense_threshold;  // 0 = never
 };
 
 struct PassLog {  // per executed pass, filled on the device
-  int64_t changed, scanned, gathered, written, read;
+  int64_t changed, scanned, gathered, written, read, gather_all;
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
@@ -83,7 +85,7 @@ struct PassArgs {
 hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t arcs,
                            DevState *st, hipStream_t s);
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
-                              hipStream_t s);
+                              int64_t dense_threshold, hipStream_t s);
 hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
                            uint64_t *keys, hipStream_t s);
 // exclusive scan of n uint64 values in place; `tmp` needs scan_tmp_elems(n) elements

@@ -113,15 +113,15 @@ struct Flags {
   bool copy_check;            // next[v] may hold c_{t-1}[v] != c_t[v]: copy when v was modified
 };
 
-__device__ __forceinline__ Flags make_flags(const PassArgs &a, int32_t t, int32_t first,
-                                            int32_t frontier) {
+__device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *st) {
+  const int32_t t = st->t, first = st->first_pass;
   Flags f;
   const bool odd = t & 1;
   f.cur = odd ? a.regs1 : a.regs0;
   f.nxt = odd ? a.regs0 : a.regs1;
   f.prev_bits = odd ? a.bits1 : a.bits0;
   f.cur_bits = odd ? a.bits0 : a.bits1;
-  f.gather_all = first || !frontier;
+  f.gather_all = first || !st->frontier || st->dense_next;
   f.copy_check = !first;
   return f;
 }
@@ -165,12 +165,19 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
   }
 }
 
-// One round of a light tile: each slot handles one node (all its arcs, U at a time).
+// One round of a light tile: each slot handles one node. Per step the slot's G lanes load
+// G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
+// in (all of them, or those modified by the previous pass), compact the kept ids into the
+// slot's queue in LDS and gather the queued counters U at a time.
 template <int G, int U>
 __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
-                                            Counters &cnt) {
+                                            int32_t *queue, Counters &cnt) {
   constexpr int m = 16 * G;
   const int sub = lane % G;
+  const int first = lane & ~(G - 1);
+  const uint64_t smask = ((G == 64) ? ~0ull : ((1ull << G) - 1ull)) << first;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t *q = queue + first * U;  // G*U entries per slot
   int32_t beg = 0, end = 0;
   if (v >= 0) {
     beg = a.row_ptr[v];
@@ -183,31 +190,43 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     acc = own;
     own_loaded = true;
   }
-  bool any = false;
-  for (int32_t p = beg; p < end; p += U) {
+  int32_t gathered = 0;
+  for (int32_t p = beg; p < end; p += G * U) {
     int32_t w[U];
     bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      ok[k] = p + k < end;
-      w[k] = ok[k] ? a.col_idx[p + k] : 0;
+      const int32_t idx = p + k * G + sub;
+      ok[k] = idx < end;
+      w[k] = ok[k] ? a.col_idx[idx] : 0;
     }
     if (!f.gather_all) {
 #pragma unroll
       for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
     }
-    uint4 x[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) x[k] = ok[k] ? ldrow(f.cur, w[k], m, sub) : zero4();
+    int32_t total = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      acc = bytemax4(acc, x[k]);
-      any = any || ok[k];
-      if (sub == 0) cnt.gathered += ok[k] ? 1 : 0;
+      const uint64_t bk = __ballot(ok[k]) & smask;
+      if (ok[k]) q[total + __popcll(bk & below)] = w[k];
+      total += __popcll(bk);
     }
-    if (sub == 0) cnt.scanned += min(U, end - p);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t j = 0; j < total; j += U) {
+      uint4 x[U];
+#pragma unroll
+      for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? ldrow(f.cur, q[j + i], m, sub) : zero4();
+#pragma unroll
+      for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
+    }
+    gathered += total;
+    if (sub == 0) cnt.scanned += min(G * U, end - p);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  finalize_slot<G>(a, f, v, lane, acc, any, own_loaded, own, cnt);
+  if (sub == 0) cnt.gathered += gathered;
+  finalize_slot<G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
 }
 
 // Max across the W slots of a wavefront (all lanes active).
@@ -306,7 +325,7 @@ template <int G, int U>
 __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
   const DevState *st = a.st;
   if (st->halted) return;
-  const Flags f = make_flags(a, st->t, st->first_pass, st->frontier);
+  const Flags f = make_flags(a, st);
   Counters cnt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
@@ -316,6 +335,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
     constexpr int W = kWave / G;
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
+    __shared__ int32_t queue[kBlockThreads * U];
     if (tile < a.n_tiles) {
       const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
       const int rounds = a.tile_nodes / W;
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
       for (int r = 0; r < rounds; ++r) {
         const int32_t v = tl[r * W + slot];
         if (!__any(v >= 0)) break;  // empty entries sort last
-        light_round<G, U>(a, f, v, lane, cnt);
+        light_round<G, U>(a, f, v, lane, queue + wave * kWave * U, cnt);
       }
     }
   }
@@ -335,7 +355,7 @@ template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
   const DevState *st = a.st;
   if (st->halted) return;
-  const Flags f = make_flags(a, st->t, st->first_pass, st->frontier);
+  const Flags f = make_flags(a, st);
   Counters cnt;
   constexpr int W = kWave / G;
   constexpr int m = 16 * G;
@@ -447,6 +467,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
     } else {
       const int32_t p = st->passes;
       PassLog rec;
+      rec.gather_all = (st->first_pass || !st->frontier || st->dense_next) ? 1 : 0;
       rec.changed = s_i[0][0];
       rec.scanned = s_i[1][0];
       rec.gathered = s_i[2][0];
@@ -456,6 +477,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       st->passes = p + 1;
       st->changed_last = rec.changed;
       st->first_pass = 0;
+      st->dense_next = (st->dense_threshold > 0 && rec.changed >= st->dense_threshold) ? 1 : 0;
       if (rec.changed == 0) {
         st->done = 1;
         st->halted = 1;
@@ -549,7 +571,8 @@ __global__ void k_check_registers(const uint32_t *words, int64_t nwords, DevStat
   if (err) atomicOr(&st->err, err);
 }
 
-__global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes) {
+__global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
+                              int64_t dense_threshold) {
   st->t = t;
   st->halted = 0;
   st->done = 0;
@@ -560,6 +583,8 @@ __global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t
   st->passes = 0;
   st->err = 0;
   st->changed_last = -1;
+  st->dense_next = 0;
+  st->dense_threshold = dense_threshold;
 }
 
 // keys[v] = (chunks of v) << 32 | (v needs a combine step); keys[n] = 0.
@@ -616,7 +641,8 @@ __global__ __launch_bounds__(kMaxTile) void k_build_tiles(const int32_t *rp, int
   uint64_t key = ~0ull;
   if (i < tile_nodes && v < n) {
     const int32_t deg = rp[v + 1] - rp[v];
-    if (deg <= light_max) key = ((uint64_t)(0x7fffffff - deg) << 32) | (uint32_t)i;
+    // nodes without successors never change: their counter stays c_0 in both buffers
+    if (deg > 0 && deg <= light_max) key = ((uint64_t)(0x7fffffff - deg) << 32) | (uint32_t)i;
   }
   keys[i] = key;
   __syncthreads();
@@ -774,8 +800,8 @@ hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32
 }
 
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st, t, frontier, max_passes);
+                              int64_t dense_threshold, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st, t, frontier, max_passes, dense_threshold);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ def step_parity(rp, ci, b, seed, check_every=1, **opts):
     _flush(f"[parity] n={n} arcs={len(ci)} b={b} seed={seed} opts={opts}")
     ref = oracle.run_steps(rp, ci, b, seed, skip_unmodified=True)
     mod = np.ones(n, np.uint8)
+    prev_changed = 0
     with hanf.HyperANF(0, **opts) as h:
         h.load(rp, ci).init(b, seed)
         nts = []
@@ -48,8 +49,14 @@ def step_parity(rp, ci, b, seed, check_every=1, **opts):
             assert steps == 1
             log = h.pass_log()[-1]
             assert log["changed"] == changed, (t, log, changed)
-            if opts.get("frontier", 1):
+            if log["gather_all"]:
+                assert log["arcs_gathered"] == log["arcs_scanned"], (t, log)
+            else:
                 assert log["arcs_gathered"] == maxed, (t, log, maxed)
+            assert log["gather_all"] == (t == 0 or not opts.get("frontier", 1)
+                                         or (opts.get("dense_switch", 4) > 0
+                                             and prev_changed >= max(1, n // opts.get("dense_switch", 4))))
+            prev_changed = changed
             assert ch_last == changed
             mod = mod_out
             T = t
@@ -118,7 +125,7 @@ def test_frontier_off_identical():
 
 @pytest.mark.parametrize("opts", [dict(light_max=4, chunk_arcs=16), dict(light_max=1000, chunk_arcs=4096),
                                   dict(tile_nodes=16, unroll=2), dict(unroll=8, tile_nodes=256),
-                                  dict(batch=1)])
+                                  dict(batch=1), dict(dense_switch=0), dict(dense_switch=1000000)])
 def test_schedules_identical(opts):
     """Any work schedule gives the same counters (max is order-free)."""
     rp, ci = graphgen.rmat(12, 40_000, seed=6)
