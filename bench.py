@@ -35,6 +35,20 @@ def algorithmic_bytes(rec, n, m):
             + m * (rec["arcs_gathered"] + rec["rows_read"] + rec["rows_written"]) + n // 4)
 
 
+def measured_traffic(workload):
+    """HBM bytes per union launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded
+    under profiles/, or None when the kernel source changed since they were taken."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", f"k_union_{workload}_traffic.json")
+    src = os.path.join(ROOT, "paper_1011_5599_amd", "csrc", "hanf_kernels.hip")
+    try:
+        rec = json.load(open(rec_path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return rec["traffic_bytes_per_launch"] if rec.get("kernel_source_sha256") == sha else None
+
+
 def run_cpu_baseline(rp, ci, b, seed, passes, threads):
     """The oracle on the same job: initialisation, N_hat(t) every iteration, passes (with
     modified-counter skipping, multi-threaded over node segments) until no counter changes,
@@ -77,7 +91,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--opt", action="append", default=[], help="library option name=value")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times): the reference for "
+                         "scaling HBM byte counters of a profiler")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4}))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -145,7 +171,7 @@ def main():
         launches = len(all_recs)
         achieved = byts / (union_ms / 1000.0) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args.workload),
                         kernel="k_union", launches=launches,
                         avg_launch_us=round(1000.0 * union_ms / launches, 2),
                         avg_algorithmic_bytes=int(byts / launches))
@@ -186,6 +212,8 @@ def main():
         "dense_equivalent_updates_per_s": m * arcs * (st["T"] + 1) / (ms_per_step / 1000.0),
         "graphs_per_s": 1000.0 / ms_per_step,
         "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
+        "pass_algorithmic_bytes": [algorithmic_bytes(r, n, m) for r in log],
+        "pass_union_ms": [round(r["union_ms"], 4) for r in log] if not args.no_timing else None,
     }
     h.close()
     print(json.dumps(out))

@@ -71,7 +71,7 @@ def _load():
                                ctypes.POINTER(ctypes.c_int64)]
         L.orc_pass.restype = ctypes.c_int64
         L.orc_run.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int, ctypes.c_uint64,
-                              ctypes.c_int32, ctypes.c_int, ctypes.c_int, f64p, ctypes.c_int32,
+                              ctypes.c_int32, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
         L.orc_run.restype = ctypes.c_int
         L.orc_ball_counter.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int, ctypes.c_uint64,
@@ -170,8 +170,9 @@ def step(row_ptr, col_idx, b: int, cur: np.ndarray, modified=None, nthreads: int
 
 
 def run(row_ptr, col_idx, b: int, seed: int, max_passes: int | None = None,
-        skip_unmodified: bool = True, nthreads: int = 1, want_regs: bool = False):
-    """Algorithm 2 to stabilisation. Returns (nt[0..T], T, final counters or None)."""
+        skip_unmodified: bool = True, nthreads: int = 1, want_regs: bool = False,
+        want_nt: bool = True):
+    """Algorithm 2 to stabilisation. Returns (nt[0..T] or None, T, final counters or None)."""
     rp, ci = _csr(row_ptr, col_idx)
     n = rp.size - 1
     if max_passes is None:
@@ -180,11 +181,12 @@ def run(row_ptr, col_idx, b: int, seed: int, max_passes: int | None = None,
     nt = np.zeros(cap, np.float64)
     T = ctypes.c_int32()
     regs = np.zeros((n, 1 << b), np.uint8) if want_regs else None
-    rc = _load().orc_run(n, rp, ci, b, seed, max_passes, int(skip_unmodified), nthreads, nt, cap,
+    rc = _load().orc_run(n, rp, ci, b, seed, max_passes, int(skip_unmodified), nthreads,
+                         nt.ctypes.data if want_nt else None, cap,
                          ctypes.byref(T), regs.ctypes.data if want_regs else None)
     if rc != 0:
         raise RuntimeError(f"oracle run failed with code {rc}")
-    return nt[: T.value + 1].copy(), T.value, regs
+    return (nt[: T.value + 1].copy() if want_nt else None), T.value, regs
 
 
 def run_steps(row_ptr, col_idx, b: int, seed: int, max_passes: int | None = None,

@@ -230,9 +230,10 @@ int64_t orc_pass(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int 
 
 /* The whole of Algorithm 2: initialise, then repeat { N_hat(t) = sum of sizes; one pass;
  * t <- t+1 } until no counter changes. nt receives N_hat(0..T) (T+1 values, T = the
- * first t whose pass leaves every counter unchanged). Returns 0, -5 if nt_cap is too
- * small, -6 if max_passes passes did not stabilise, -2 on allocation failure.
- * If final_regs is non-NULL it receives the stable counters (n*m bytes). */
+ * first t whose pass leaves every counter unchanged); with nt NULL the sums are skipped.
+ * Returns 0, -5 if nt_cap is too small, -6 if max_passes passes did not stabilise, -2 on
+ * allocation failure. If final_regs is non-NULL it receives the stable counters (n*m
+ * bytes). */
 int orc_run(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int b, uint64_t seed,
             int32_t max_passes, int skip_unmodified, int nthreads, double *nt, int32_t nt_cap,
             int32_t *T_out, uint8_t *final_regs) {
@@ -251,8 +252,10 @@ int orc_run(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int b, ui
   if (mod) memset(mod, 1, (size_t)n);
   int32_t t = 0;
   for (;;) {
-    if (t >= nt_cap) { rc = -5; break; }
-    nt[t] = orc_sum_sizes(n, b, cur);
+    if (nt) {
+      if (t >= nt_cap) { rc = -5; break; }
+      nt[t] = orc_sum_sizes(n, b, cur);
+    }
     if (t >= max_passes) { rc = -6; break; }
     int64_t changed = orc_pass(n, row_ptr, col_idx, b, cur, next, mod, mod_out, nthreads, NULL);
     if (changed == 0) break;

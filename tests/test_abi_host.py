@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every function
+declared in include/hanf.h, and its pure host functions and argument checks behave."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+hanf = pytest.importorskip("paper_1011_5599_amd")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "hanf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hanf_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(hanf.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding exposes each under the same name
+    for name in names:
+        assert callable(getattr(hanf, name)), name
+
+
+def test_footprint_matches_memory_model():
+    """Two register arrays of n*m bytes dominate (the O(n m) register memory of Section 3.4)."""
+    n, arcs = 1 << 22, 1 << 26
+    for b in range(4, 9):
+        fb = hanf.hanf_footprint(n, arcs, b, copy_graph=False)
+        assert 2 * n * (1 << b) <= fb <= 2 * n * (1 << b) + 40 * n + 65536
+        fg = hanf.hanf_footprint(n, arcs, b, copy_graph=True)
+        assert fg - fb == 4 * (n + 1) + 4 * arcs
+
+
+@pytest.mark.parametrize("args", [(0, 10, 6, 1), (10, -1, 6, 1), (10, 1 << 31, 6, 1), (10, 10, 3, 1),
+                                  (10, 10, 9, 1)])
+def test_footprint_rejects_bad_arguments(args):
+    with pytest.raises(hanf.HanfError) as e:
+        hanf.hanf_footprint(*args)
+    assert e.value.code == hanf.HANF_EINVAL
+    assert "out of range" in hanf.hanf_last_error(None)
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = hanf.lib()
+    i32 = ctypes.c_int32()
+    i64 = ctypes.c_int64()
+    assert lib.hanf_set_option(None, hanf.HANF_OPT_FRONTIER, 1) == hanf.HANF_EINVAL
+    assert lib.hanf_load_csr(None, 1, 0, None, None, 0) == hanf.HANF_EINVAL
+    assert lib.hanf_init_counters(None, 6, 1) == hanf.HANF_EINVAL
+    assert lib.hanf_iterate(None, 0, ctypes.byref(i32), ctypes.byref(i64)) == hanf.HANF_EINVAL
+    assert lib.hanf_read_nt(None, None, 0, ctypes.byref(i32)) == hanf.HANF_EINVAL
+    assert lib.hanf_read_registers(None, None, 0, 0) == hanf.HANF_EINVAL
+    assert lib.hanf_stats(None, 0.9, 0.0, 0, None) == hanf.HANF_EINVAL
+    lib.hanf_destroy(None)  # safe on NULL
+    assert "NULL" in hanf.hanf_last_error(None)
+
+
+def test_create_without_device_reports_error():
+    """In a process with no GPU, hanf_create fails with HANF_EDEVICE (never aborts)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(hanf.HanfError) as e:
+        hanf.hanf_create(0)
+    assert e.value.code in (hanf.HANF_EDEVICE, hanf.HANF_EINVAL)
+
+
+def test_missing_library_raises(monkeypatch, tmp_path):
+    monkeypatch.setattr(hanf, "_lib", None)
+    monkeypatch.setattr(hanf, "LIB_PATH", str(tmp_path / "absent.so"))
+    with pytest.raises(ImportError):
+        hanf.lib()
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
