@@ -41,7 +41,7 @@ struct Schedule {
   Heavy *heavy = nullptr;
   uint8_t *partial = nullptr;
   uint8_t *partial_any = nullptr;
-  int64_t *wgstat = nullptr;
+  int64_t *stat_slots = nullptr;  // kStatSlots x 4 work counters
 };
 
 }  // namespace
@@ -175,7 +175,7 @@ void free_schedule(hanf_ctx *c) {
   dev_release(c, s.heavy);
   dev_release(c, s.partial);
   dev_release(c, s.partial_any);
-  dev_release(c, s.wgstat);
+  dev_release(c, s.stat_slots);
   s = Schedule();
 }
 
@@ -281,8 +281,7 @@ int build_schedule(hanf_ctx *c, int G) {
   s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
   s.n_light_wgs = (s.n_tiles + 3) / 4;
   s.n_fin_wgs = (s.n_heavy + 3) / 4;
-  if ((rc = dev_alloc(c, &s.wgstat, ((size_t)s.n_chunk_wgs + s.n_light_wgs + s.n_fin_wgs) * 4, "workgroup counters")))
-    return rc;
+  if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * 4, "work counters"))) return rc;
   return HANF_OK;
 }
 
@@ -298,7 +297,7 @@ void fill_args(hanf_ctx *c) {
   a.blocksum = c->blocksum;
   a.wgsum = c->wgsum;
   a.wgcnt = c->wgcnt;
-  a.wgstat = c->sch.wgstat;
+  a.stat_slots = c->sch.stat_slots;
   a.light = c->sch.light;
   a.chunks = c->sch.chunks;
   a.heavy = c->sch.heavy;
@@ -329,7 +328,7 @@ int alloc_run(hanf_ctx *c, int log2m) {
   const int m = 1 << log2m;
   const size_t bytes = (size_t)c->n * m;
   c->n_blocks = (int32_t)(((int64_t)c->n + kNodesPerBlock - 1) / kNodesPerBlock);
-  c->n_reduce_wgs = (c->n_blocks + 3) / 4;
+  c->n_reduce_wgs = (c->n_blocks + kReduceBlocks - 1) / kReduceBlocks;
   c->max_passes = c->max_passes_opt > 0 ? (int32_t)std::min<int64_t>(c->max_passes_opt, INT32_MAX - 8)
                                         : (int32_t)std::min<int64_t>((int64_t)c->n + 1, INT32_MAX - 8);
   c->nt_cap = c->max_passes + 2;

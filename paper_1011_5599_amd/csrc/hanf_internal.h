@@ -12,6 +12,8 @@ constexpr int kBlockThreads = 256; // 4 wavefronts per workgroup
 constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 consecutive nodes
 constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
+constexpr int kReduceBlocks = 16;  // 64-node blocks per reduction workgroup
+constexpr int kStatSlots = 64;     // rows of work counters, spread over workgroups
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
@@ -56,7 +58,7 @@ struct PassArgs {
   double *blocksum;          // per 64 nodes
   double *wgsum;             // per reduce workgroup
   int64_t *wgcnt;            // per reduce workgroup: changed counters
-  int64_t *wgstat;           // per union/finalize workgroup: scanned, gathered, written, read
+  int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read}
   const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
   const Chunk *chunks;
   const Heavy *heavy;

@@ -169,7 +169,7 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
 // G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
 // in (all of them, or those modified by the previous pass), compact the kept ids into the
 // slot's queue in LDS and gather the queued counters U at a time.
-template <int G, int U>
+template <int G, int U, bool CountScan>
 __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
                                             int32_t *queue, Counters &cnt) {
   constexpr int m = 16 * G;
@@ -221,7 +221,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
       for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
     }
     gathered += total;
-    if (sub == 0) cnt.scanned += min(G * U, end - p);
+    if (CountScan && sub == 0) cnt.scanned += min(G * U, end - p);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -241,22 +241,64 @@ __device__ __forceinline__ void combine_slots(uint4 &acc, bool &any) {
   any = anyi != 0;
 }
 
-// A chunk of one node's arcs handled by a whole wavefront.
+// First phase of a frontier pass over a light tile: one lane per node scans the node's
+// successor ids until it meets one whose counter was modified by the previous pass. Nodes
+// that must produce a new counter (such a successor, or a counter of their own modified by
+// the previous pass, whose update-buffer row is stale) are compacted into `act`.
+// Returns their number (wavefront-uniform).
+template <int U>
+__device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f, const int32_t *tl,
+                                               int32_t nodes, int lane, int32_t *act, Counters &cnt) {
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t n_act = 0;
+  for (int32_t i = 0; i < nodes; i += kWave) {
+    const int32_t v = i + lane < nodes ? tl[i + lane] : -1;
+    if (!__any(v >= 0)) break;  // empty entries sort last
+    bool active = false;
+    if (v >= 0) {
+      active = testbit(f.prev_bits, v);
+      const int32_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+      cnt.scanned += end - beg;
+      for (int32_t p = beg; p < end && !active; p += U) {
+        int32_t w[U];
+        bool ok[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          ok[k] = p + k < end;
+          w[k] = ok[k] ? a.col_idx[p + k] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) active = active || (ok[k] && testbit(f.prev_bits, w[k]));
+      }
+    }
+    const uint64_t bal = __ballot(active);
+    if (active) act[n_act + __popcll(bal & below)] = v;
+    n_act += __popcll(bal);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return n_act;
+}
+
+// A chunk of one node's arcs handled by a whole wavefront: every lane examines its own
+// successor id (64 per load), the ids to maximise in are compacted into the wavefront's
+// queue in LDS, and the W slots gather the queued counters.
 template <int G, int U>
 __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, int32_t c, int lane,
-                                           Counters &cnt) {
+                                           int32_t *q, Counters &cnt) {
   constexpr int W = kWave / G;
   constexpr int m = 16 * G;
   const int slot = lane / G, sub = lane % G;
+  const uint64_t below = (1ull << lane) - 1ull;
   const Chunk ch = a.chunks[c];
   uint4 acc = zero4();
-  bool any = false;
-  for (int32_t base = ch.a0; base < ch.a1; base += W * U) {
+  int32_t gathered = 0;
+  for (int32_t base = ch.a0; base < ch.a1; base += kWave * U) {
     int32_t w[U];
     bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int32_t p = base + k * W + slot;
+      const int32_t p = base + k * kWave + lane;
       ok[k] = p < ch.a1;
       w[k] = ok[k] ? a.col_idx[p] : 0;
     }
@@ -264,17 +306,34 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
 #pragma unroll
       for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
     }
-    uint4 x[U];
-#pragma unroll
-    for (int k = 0; k < U; ++k) x[k] = ok[k] ? ldrow(f.cur, w[k], m, sub) : zero4();
+    int32_t total = 0;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      acc = bytemax4(acc, x[k]);
-      any = any || ok[k];
-      if (sub == 0) cnt.gathered += ok[k] ? 1 : 0;
+      const uint64_t bk = __ballot(ok[k]);
+      if (ok[k]) q[total + __popcll(bk & below)] = w[k];
+      total += __popcll(bk);
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t j = slot; j < total; j += W * U) {
+      uint4 x[U];
+#pragma unroll
+      for (int i = 0; i < U; ++i) {
+        const int32_t e = j + i * W;
+        x[i] = e < total ? ldrow(f.cur, q[e], m, sub) : zero4();
+      }
+#pragma unroll
+      for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
+    }
+    gathered += total;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  if (lane == 0) cnt.scanned += ch.a1 - ch.a0;
+  if (lane == 0) {
+    cnt.scanned += ch.a1 - ch.a0;
+    cnt.gathered += gathered;
+  }
+  bool any = gathered > 0;
   combine_slots<G>(acc, any);
   if (ch.part < 0) {
     finalize_slot<G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, zero4(), cnt);
@@ -299,7 +358,9 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-__device__ __forceinline__ void store_block_counters(const Counters &c, int64_t *out) {
+// Adds the workgroup's work counters to one of kStatSlots slot rows (spread to avoid
+// contention); k_reduce_top sums and clears the slots.
+__device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *slots) {
   __shared__ int32_t red[4][kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written),
@@ -311,11 +372,11 @@ __device__ __forceinline__ void store_block_counters(const Counters &c, int64_t 
     red[3][wave] = s3;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t tot[4] = {0, 0, 0, 0};
-    for (int i = 0; i < kBlockThreads / kWave; ++i)
-      for (int k = 0; k < 4; ++k) tot[k] += red[k][i];
-    for (int k = 0; k < 4; ++k) out[k] = tot[k];
+  if (threadIdx.x < 4) {
+    int64_t tot = 0;
+    for (int i = 0; i < kBlockThreads / kWave; ++i) tot += red[threadIdx.x][i];
+    if (tot) atomicAdd(reinterpret_cast<unsigned long long *>(slots + (blockIdx.x % kStatSlots) * 4 + threadIdx.x),
+                       (unsigned long long)tot);
   }
 }
 
@@ -327,27 +388,38 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
   if (st->halted) return;
   const Flags f = make_flags(a, st);
   Counters cnt;
+  __shared__ int32_t queue[kBlockThreads * U];
+  __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
     const int32_t c = (int32_t)blockIdx.x * 4 + wave;
-    if (c < a.n_chunks) chunk_wave<G, U>(a, f, c, lane, cnt);
+    if (c < a.n_chunks) chunk_wave<G, U>(a, f, c, lane, qw, cnt);
   } else {
     constexpr int W = kWave / G;
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
-    __shared__ int32_t queue[kBlockThreads * U];
     if (tile < a.n_tiles) {
       const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
-      const int rounds = a.tile_nodes / W;
       const int slot = lane / G;
-      for (int r = 0; r < rounds; ++r) {
-        const int32_t v = tl[r * W + slot];
-        if (!__any(v >= 0)) break;  // empty entries sort last
-        light_round<G, U>(a, f, v, lane, queue + wave * kWave * U, cnt);
+      if (f.gather_all) {
+        const int rounds = a.tile_nodes / W;
+        for (int r = 0; r < rounds; ++r) {
+          const int32_t v = tl[r * W + slot];
+          if (!__any(v >= 0)) break;  // empty entries sort last
+          light_round<G, U, true>(a, f, v, lane, qw, cnt);
+        }
+      } else {
+        int32_t *act = act_buf + wave * kMaxTile;
+        const int32_t n_act = find_active<U>(a, f, tl, a.tile_nodes, lane, act, cnt);
+        for (int32_t r = 0; r < n_act; r += W) {
+          const int32_t v = r + slot < n_act ? act[r + slot] : -1;
+          light_round<G, U, false>(a, f, v, lane, qw, cnt);
+        }
       }
     }
   }
-  store_block_counters(cnt, a.wgstat + (size_t)blockIdx.x * 4);
+  add_block_counters(cnt, a.stat_slots);
 }
 
 // Combines the partial maxima of nodes split over several chunks (one wavefront per node).
@@ -373,11 +445,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     combine_slots<G>(acc, any);
     finalize_slot<G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, zero4(), cnt);
   }
-  store_block_counters(cnt, a.wgstat + ((size_t)a.n_chunk_wgs + a.n_light_wgs + blockIdx.x) * 4);
+  add_block_counters(cnt, a.stat_slots);
 }
 
 // Per 64-node block: re-sum the estimates where a counter changed (else reuse the cached
-// sum, Section 3.3), count changed counters, clear the flags of the previous pass.
+// sum, Section 3.3), count changed counters, clear the flags of the previous pass. Each
+// workgroup covers kReduceBlocks consecutive blocks (4 per wavefront), summed in order.
 __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int32_t force) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -387,15 +460,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   const int32_t t = st->t;
   const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
   uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
-  const int32_t b = (int32_t)blockIdx.x * 4 + wave;
-  double bs = 0.0;
+  double wsum = 0.0;
   int32_t cnt = 0;
-  if (b < a.n_blocks) {
+  for (int j = 0; j < kReduceBlocks / 4; ++j) {
+    const int32_t b = (int32_t)blockIdx.x * kReduceBlocks + wave * (kReduceBlocks / 4) + j;
+    if (b >= a.n_blocks) break;
     uint32_t w0 = 0, w1 = 0;
     if (!force) {
       w0 = cb[2 * b];
       w1 = cb[2 * b + 1];
     }
+    double bs;
     if (force || (w0 | w1)) {
       const int32_t v = b * kNodesPerBlock + lane;
       bs = wave_sum(v < a.n ? a.est[v] : 0.0);
@@ -403,14 +478,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     } else {
       bs = a.blocksum[b];
     }
-    cnt = __popc(w0) + __popc(w1);
+    wsum += bs;
+    cnt += __popc(w0) + __popc(w1);
     if (!force && lane == 0) {
       pb[2 * b] = 0u;
       pb[2 * b + 1] = 0u;
     }
   }
   if (lane == 0) {
-    s_sum[wave] = bs;
+    s_sum[wave] = wsum;
     s_cnt[wave] = cnt;
   }
   __syncthreads();
@@ -436,14 +512,15 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
     s += a.wgsum[i];
     c += a.wgcnt[i];
   }
-  if (mode == kReducePass) {
-    const int32_t nw = a.n_chunk_wgs + a.n_light_wgs + a.n_fin_wgs;
-    for (int32_t i = tid; i < nw; i += kTopThreads) {
-      sc += a.wgstat[(size_t)i * 4 + 0];
-      ga += a.wgstat[(size_t)i * 4 + 1];
-      wr += a.wgstat[(size_t)i * 4 + 2];
-      rd += a.wgstat[(size_t)i * 4 + 3];
+  if (tid < kStatSlots) {
+    int64_t *sl = a.stat_slots + tid * 4;
+    if (mode == kReducePass) {
+      sc = sl[0];
+      ga = sl[1];
+      wr = sl[2];
+      rd = sl[3];
     }
+    sl[0] = sl[1] = sl[2] = sl[3] = 0;
   }
   s_sum[tid] = s;
   s_i[0][tid] = c;
