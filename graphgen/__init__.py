@@ -11,6 +11,7 @@ sorted ascending.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -42,7 +43,7 @@ def _load():
         out = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                ctypes.POINTER(i32p), ctypes.POINTER(i32p)]
         lib.gg_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                                ctypes.c_double, ctypes.c_int, ctypes.c_uint64] + out
+                                ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64] + out
         lib.gg_er.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64] + out
         lib.gg_web.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 7 + [ctypes.c_uint64] + out
         for f in (lib.gg_rmat, lib.gg_er, lib.gg_web):
@@ -71,10 +72,11 @@ def _call(fn, *args):
     return row_ptr, col_idx
 
 
-def rmat(scale: int, target: int, a=0.57, b=0.19, c=0.19, symmetric=False, seed=1):
-    """R-MAT on 2^scale ids: `target` distinct arcs (directed) or edges (symmetric, 2x arcs)."""
+def rmat(scale: int, target: int, a=0.57, b=0.19, c=0.19, symmetric=False, seed=1, n=0):
+    """R-MAT on 2^scale ids: `target` distinct arcs (directed) or edges (symmetric, 2x arcs).
+    With n > 0 the graph has n nodes: samples with an endpoint >= n are rejected."""
     lib = _load()
-    return _call(lib.gg_rmat, scale, target, a, b, c, int(symmetric), seed)
+    return _call(lib.gg_rmat, scale, target, a, b, c, int(symmetric), seed, n)
 
 
 def erdos_renyi(n: int, target: int, seed=1):
@@ -159,6 +161,51 @@ WORKLOADS = {
     # web-like, 2^24 nodes; log2m 7, hash seed 1
     "web24": dict(kind="web", n=1 << 24, graph_seed=24, log2m=7, seed=1),
 }
+
+
+def batch_sizes(count: int = 512, seed: int = 4, lo: int = 1 << 8, hi: int = 1 << 16,
+                median: float = 4096.0, sigma: float = 1.0):
+    """Node counts round(exp(X)), X ~ Normal(ln median, sigma), redrawn outside [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        x = int(round(math.exp(rng.normal(math.log(median), sigma))))
+        if lo <= x <= hi:
+            out.append(x)
+    return out
+
+
+def batch_graphs(count: int = 512, seed: int = 4):
+    """The many-graph workload: `count` graphs with lognormal node counts in [2^8, 2^16]
+    (median 2^12); the first half directed Erdos-Renyi with 8 n distinct arcs, the second
+    half directed R-MAT (a=.57, b=.19, c=.19) on the next power of two, endpoints >= n
+    rejected, 16 n distinct arcs. Graph i uses graph seed 1000 + i."""
+    sizes = batch_sizes(count, seed)
+    graphs = []
+    for i, n in enumerate(sizes):
+        if i < count // 2:
+            graphs.append(erdos_renyi(n, 8 * n, seed=1000 + i))
+        else:
+            scale = max(1, (n - 1).bit_length())
+            graphs.append(rmat(scale, 16 * n, seed=1000 + i, n=n))
+    return graphs
+
+
+def disjoint_union(graphs):
+    """(graph_off[G+1], row_ptr[N+1], col_idx[E]) of graphs laid side by side (global ids)."""
+    offs = [0]
+    for rp, _ in graphs:
+        offs.append(offs[-1] + len(rp) - 1)
+    rps = []
+    cis = []
+    arc_base = 0
+    for (rp, ci), o in zip(graphs, offs[:-1]):
+        rps.append(rp[:-1].astype(np.int64) + arc_base)
+        cis.append(ci.astype(np.int64) + o)
+        arc_base += len(ci)
+    row_ptr = np.concatenate(rps + [np.array([arc_base], np.int64)]).astype(np.int32)
+    col_idx = np.concatenate(cis).astype(np.int32) if cis else np.zeros(0, np.int32)
+    return np.array(offs, np.int32), row_ptr, col_idx
 
 
 def workload_graph(spec: dict):

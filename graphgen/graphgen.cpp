@@ -174,14 +174,17 @@ const int64_t kChunk = 1 << 16;  // samples per RNG stream
 
 extern "C" {
 
-// Directed or symmetric R-MAT on n = 2^scale ids.
+// Directed or symmetric R-MAT on 2^scale ids (or on the first n_nodes of them, by rejection).
 // Directed: distinct non-loop ordered pairs are taken in sample order until `target` arcs.
 // Symmetric: distinct unordered non-loop pairs until `target` edges, each emitted in both
 // directions (2*target arcs). Ids are relabelled by a seeded uniform permutation.
 int gg_rmat(int scale, int64_t target, double a, double b, double c, int symmetric,
-            uint64_t seed, int32_t *n_out, int64_t *arcs_out, int32_t **row_ptr, int32_t **col_idx) {
+            uint64_t seed, int64_t n_nodes, int32_t *n_out, int64_t *arcs_out, int32_t **row_ptr,
+            int32_t **col_idx) {
   if (scale < 1 || scale > 30 || target < 0) return -1;
-  const int64_t n = 1LL << scale;
+  // n_nodes > 0: R-MAT on 2^scale ids, samples with an endpoint >= n_nodes rejected
+  const int64_t n = n_nodes > 0 ? n_nodes : (1LL << scale);
+  if (n > (1LL << scale)) return -1;
   const double max_pairs = symmetric ? (double)n * (double)(n - 1) / 2.0 : (double)n * (double)(n - 1);
   if ((double)target > 0.5 * max_pairs) return -1;
   RmatQ q(a, b, c);
@@ -203,7 +206,7 @@ int gg_rmat(int scale, int64_t target, double a, double b, double c, int symmetr
         uint64_t u, v;
         q.sample(r, scale, u, v);
         if (symmetric && u > v) std::swap(u, v);
-        buf[(size_t)(k * kChunk + i)] = (u == v) ? 0 : ((u << 32) | v) + 1;
+        buf[(size_t)(k * kChunk + i)] = (u == v || (int64_t)u >= n || (int64_t)v >= n) ? 0 : ((u << 32) | v) + 1;
       }
     }
     chunk_id += nchunks;

@@ -162,6 +162,41 @@ int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *le
  * the memory figure of Section 3.4 (O(n m) register bytes) is its dominant term. */
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
 
+/* ---- Batched runs: many independent HyperANF runs in the same passes.
+ * Each input graph g is run with n_seeds hash seeds; component c = g * n_seeds + s is an
+ * independent run of Algorithm 2 on graph g with seed seeds[c]. The components are laid
+ * side by side as one graph (disjoint union, each starting on a 64-node boundary), so a
+ * pass of Algorithm 2 over it is a pass of every component; a component's counters and
+ * N_hat(t) are exactly those of its own run, and its fixpoint T is the first pass that left
+ * it unchanged. hanf_iterate runs the passes until every component has stopped. This serves
+ * the paper's protocol of many low-precision runs per graph (Section 4, moments; Section 6). */
+
+/* Loads the graphs: graph_off[n_graphs+1] node offsets (graph g has nodes graph_off[g] ..
+ * graph_off[g+1]-1, at least one), row_ptr[graph_off[n_graphs]+1] and col_idx[arcs] one CSR
+ * over all of them with global ids; no arc may leave its graph (HANF_EINVAL). Host memory,
+ * copied. Replaces any graph or batch the context held. */
+int hanf_load_batch(hanf_ctx *ctx, int32_t n_graphs, const int32_t *graph_off, int64_t arcs,
+                    const int32_t *row_ptr, const int32_t *col_idx, int32_t n_seeds);
+
+/* Initialises every component (Algorithm 2's initialisation with the graph-local node id as
+ * the item and seeds[c] as the hash seed; seeds has n_graphs * n_seeds entries, host). Passes
+ * allowed default to 1024 (HANF_OPT_MAX_PASSES changes it). */
+int hanf_init_batch(hanf_ctx *ctx, int32_t log2m, const uint64_t *seeds);
+
+/* Number of components and, if T is non-NULL (n_components entries, host), each one's
+ * fixpoint iteration, or -1 while it still changes. */
+int hanf_batch_info(hanf_ctx *ctx, int32_t *n_components, int32_t *T);
+
+/* N_hat(0..T) of component `comp` (or up to the current iteration while it still changes). */
+int hanf_batch_read_nt(hanf_ctx *ctx, int32_t comp, double *out, int32_t cap, int32_t *len);
+
+/* Current counters of component `comp`: n_g * m bytes, node-major (graph-local ids). */
+int hanf_batch_read_registers(hanf_ctx *ctx, int32_t comp, uint8_t *out, int64_t bytes, uint32_t flags);
+
+/* hanf_stats of component `comp`. */
+int hanf_batch_stats(hanf_ctx *ctx, int32_t comp, double alpha, double eps, int32_t distinct,
+                     hanf_stats_t *out);
+
 /* Last error message of the context, or of the calling thread when ctx is NULL. */
 const char *hanf_last_error(const hanf_ctx *ctx);
 

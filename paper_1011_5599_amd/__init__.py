@@ -95,6 +95,12 @@ def lib():
             "hanf_footprint": ([i32, i64, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
+            "hanf_load_batch": ([vp, i32, vp, i64, vp, vp, i32], ctypes.c_int),
+            "hanf_init_batch": ([vp, i32, vp], ctypes.c_int),
+            "hanf_batch_info": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
+            "hanf_batch_read_nt": ([vp, i32, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
+            "hanf_batch_read_registers": ([vp, i32, vp, i64, u32], ctypes.c_int),
+            "hanf_batch_stats": ([vp, i32, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -234,6 +240,52 @@ def hanf_bytemax_words(device: int, x, y, out) -> None:
     _check(lib().hanf_bytemax_words(device, x.data_ptr(), y.data_ptr(), out.data_ptr(), x.numel()))
 
 
+def hanf_load_batch(ctx, graph_off, row_ptr, col_idx, n_seeds: int) -> None:
+    """Host arrays: graph_off[G+1] node offsets, one CSR over all graphs (global ids)."""
+    go = np.ascontiguousarray(graph_off, dtype=np.int32)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    _check(lib().hanf_load_batch(ctx, go.size - 1, go.ctypes.data, ci.size, rp.ctypes.data,
+                                 ci.ctypes.data if ci.size else None, n_seeds), ctx)
+
+
+def hanf_init_batch(ctx, log2m: int, seeds) -> None:
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    _check(lib().hanf_init_batch(ctx, log2m, sd.ctypes.data), ctx)
+
+
+def hanf_batch_info(ctx, with_T: bool = True):
+    """(number of components, fixpoint T per component or None); T = -1 while changing."""
+    n = ctypes.c_int32()
+    _check(lib().hanf_batch_info(ctx, ctypes.byref(n), None), ctx)
+    if not with_T:
+        return n.value, None
+    T = np.zeros(n.value, np.int32)
+    _check(lib().hanf_batch_info(ctx, ctypes.byref(n), T.ctypes.data), ctx)
+    return n.value, T
+
+
+def hanf_batch_read_nt(ctx, comp: int) -> np.ndarray:
+    n = ctypes.c_int32()
+    rc = lib().hanf_batch_read_nt(ctx, comp, None, 0, ctypes.byref(n))
+    _check(rc, ctx, ok=(HANF_OK, HANF_ERANGE))
+    out = np.zeros(max(n.value, 1), np.float64)
+    _check(lib().hanf_batch_read_nt(ctx, comp, out.ctypes.data, out.size, ctypes.byref(n)), ctx)
+    return out[: n.value]
+
+
+def hanf_batch_read_registers(ctx, comp: int, n: int, log2m: int) -> np.ndarray:
+    out = np.empty((n, 1 << log2m), np.uint8)
+    _check(lib().hanf_batch_read_registers(ctx, comp, out.ctypes.data, out.size, HANF_HOST_PTRS), ctx)
+    return out
+
+
+def hanf_batch_stats(ctx, comp: int, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
+    s = hanf_stats_t()
+    _check(lib().hanf_batch_stats(ctx, comp, alpha, eps, int(distinct), ctypes.byref(s)), ctx)
+    return {f: getattr(s, f) for f, _ in hanf_stats_t._fields_}
+
+
 # ------------------------------------------------------------------ convenience wrapper
 
 class HyperANF:
@@ -299,6 +351,44 @@ class HyperANF:
 
     def pass_log(self):
         return hanf_read_pass_log(self.ctx)
+
+
+class Batch(HyperANF):
+    """Many independent runs in the same passes: every graph of `graphs` (a list of
+    (row_ptr, col_idx)) with each of its seeds; component g * n_seeds + s."""
+
+    def load_graphs(self, graphs, n_seeds: int):
+        sizes = [len(rp) - 1 for rp, _ in graphs]
+        offs = np.zeros(len(graphs) + 1, np.int64)
+        offs[1:] = np.cumsum(sizes)
+        rps, cis, base = [], [], 0
+        for (rp, ci), o in zip(graphs, offs[:-1]):
+            rps.append(np.asarray(rp[:-1], np.int64) + base)
+            cis.append(np.asarray(ci, np.int64) + o)
+            base += len(ci)
+        row_ptr = np.concatenate(rps + [np.array([base], np.int64)])
+        col_idx = np.concatenate(cis) if cis else np.zeros(0, np.int64)
+        hanf_load_batch(self.ctx, offs, row_ptr, col_idx, n_seeds)
+        self.sizes = sizes
+        self.n_seeds = n_seeds
+        return self
+
+    def init(self, log2m: int, seeds):
+        hanf_init_batch(self.ctx, log2m, seeds)
+        self.log2m = log2m
+        return self
+
+    def fixpoints(self):
+        return hanf_batch_info(self.ctx)[1]
+
+    def nt(self, comp: int):
+        return hanf_batch_read_nt(self.ctx, comp)
+
+    def registers(self, comp: int):
+        return hanf_batch_read_registers(self.ctx, comp, self.sizes[comp // self.n_seeds], self.log2m)
+
+    def stats(self, comp: int, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
+        return hanf_batch_stats(self.ctx, comp, alpha, eps, distinct)
 
 
 def rsd(log2m: int, beta: float = 1.06) -> float:

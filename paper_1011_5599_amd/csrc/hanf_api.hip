@@ -62,7 +62,7 @@ struct hanf_ctx {
   int32_t light_max_opt = 0, chunk_opt = 0, tile_opt = 0;
   int timing = 0;
   int dense_div = 4;  // a pass after one that changed >= n/dense_div counters maximises with all successors
-  int batch = 4;
+  int passes_per_check = 4;
   int unroll = 4;
 
   // graph
@@ -73,6 +73,16 @@ struct hanf_ctx {
   bool graph_ok = false;
 
   Schedule sch;
+
+  // batched graph: components (graph, seed) laid side by side, 64-node aligned
+  bool batch = false;
+  int32_t n_graphs = 0, n_seeds = 0, n_comp = 0;
+  std::vector<int32_t> comp_node_off_h, comp_n_h;
+  int32_t *blk_comp = nullptr, *comp_node_off = nullptr, *comp_n = nullptr;
+  // batched run state
+  uint64_t *comp_seed = nullptr;
+  int32_t *blkcnt = nullptr, *comp_T = nullptr;
+  double *comp_nt = nullptr;
 
   // run state
   int log2m = 0;
@@ -192,6 +202,10 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->nt);
   dev_release(c, c->log);
   dev_release(c, c->stats_out);
+  dev_release(c, c->comp_seed);
+  dev_release(c, c->blkcnt);
+  dev_release(c, c->comp_T);
+  dev_release(c, c->comp_nt);
   c->inited = false;
   c->log2m = 0;
 }
@@ -199,6 +213,13 @@ void free_run(hanf_ctx *c) {
 void free_graph(hanf_ctx *c) {
   dev_release(c, c->rp_own);
   dev_release(c, c->ci_own);
+  dev_release(c, c->blk_comp);
+  dev_release(c, c->comp_node_off);
+  dev_release(c, c->comp_n);
+  c->batch = false;
+  c->n_graphs = c->n_seeds = c->n_comp = 0;
+  c->comp_node_off_h.clear();
+  c->comp_n_h.clear();
   c->rp = c->ci = nullptr;
   c->graph_ok = false;
   c->n = 0;
@@ -321,6 +342,22 @@ void fill_args(hanf_ctx *c) {
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;
   a.nt_cap = c->nt_cap;
+  a.batch.active = c->batch ? 1 : 0;
+  a.batch.n_comp = c->n_comp;
+  a.batch.blk_comp = c->blk_comp;
+  a.batch.comp_node_off = c->comp_node_off;
+  a.batch.comp_n = c->comp_n;
+  a.batch.comp_seed = c->comp_seed;
+  a.batch.blkcnt = c->blkcnt;
+  a.batch.comp_T = c->comp_T;
+  a.batch.comp_nt = c->comp_nt;
+}
+
+// Passes allowed before HANF_EMAXITER: the option, else n + 1 for one graph (T is below the
+// number of nodes), else 1024 for batches (their per-component histories are kept).
+int64_t default_max_passes(const hanf_ctx *c) {
+  if (c->max_passes_opt > 0) return c->max_passes_opt;
+  return c->batch ? std::min<int64_t>(1024, (int64_t)c->n + 1) : (int64_t)c->n + 1;
 }
 
 int alloc_run(hanf_ctx *c, int log2m) {
@@ -329,8 +366,7 @@ int alloc_run(hanf_ctx *c, int log2m) {
   const size_t bytes = (size_t)c->n * m;
   c->n_blocks = (int32_t)(((int64_t)c->n + kNodesPerBlock - 1) / kNodesPerBlock);
   c->n_reduce_wgs = (c->n_blocks + kReduceBlocks - 1) / kReduceBlocks;
-  c->max_passes = c->max_passes_opt > 0 ? (int32_t)std::min<int64_t>(c->max_passes_opt, INT32_MAX - 8)
-                                        : (int32_t)std::min<int64_t>((int64_t)c->n + 1, INT32_MAX - 8);
+  c->max_passes = (int32_t)std::min<int64_t>(default_max_passes(c), INT32_MAX - 8);
   c->nt_cap = c->max_passes + 2;
   int rc;
   if ((rc = dev_alloc(c, &c->regs[0], bytes, "counters")) || (rc = dev_alloc(c, &c->regs[1], bytes, "counters")) ||
@@ -346,6 +382,15 @@ int alloc_run(hanf_ctx *c, int log2m) {
       (rc = dev_alloc(c, &c->stats_out, 16, "statistics"))) {
     free_run(c);
     return rc;
+  }
+  if (c->batch) {
+    if ((rc = dev_alloc(c, &c->comp_seed, (size_t)c->n_comp, "component seeds")) ||
+        (rc = dev_alloc(c, &c->blkcnt, (size_t)c->n_blocks, "block change counts")) ||
+        (rc = dev_alloc(c, &c->comp_T, (size_t)c->n_comp, "component fixpoints")) ||
+        (rc = dev_alloc(c, &c->comp_nt, (size_t)c->n_comp * c->nt_cap, "component histories"))) {
+      free_run(c);
+      return rc;
+    }
   }
   // linear counting m ln(m/V), V = 1..m (entry 0 unused)
   c->lc_host.assign((size_t)m + 1, 0.0);
@@ -458,7 +503,7 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       break;
     case HANF_OPT_BATCH:
       if (value < 1 || value > 1024) return fail(c, HANF_EINVAL, "batch must be in 1..1024");
-      c->batch = (int)value;
+      c->passes_per_check = (int)value;
       break;
     case HANF_OPT_TILE_NODES:
       if (value < 0 || value > kMaxTile) return fail(c, HANF_EINVAL, "tile nodes must be in 0..256");
@@ -536,8 +581,11 @@ int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, 
   return HANF_OK;
 }
 
-int hanf_init_counters(hanf_ctx *c, int32_t log2m, uint64_t seed) {
-  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_init_counters: NULL context");
+}  // extern "C"
+
+namespace {
+
+int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds) {
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
   if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
@@ -549,19 +597,40 @@ int hanf_init_counters(hanf_ctx *c, int32_t log2m, uint64_t seed) {
       want.chunk_arcs != c->sch.chunk_arcs || want.tile_nodes != c->sch.tile_nodes) {
     if ((rc = build_schedule(c, G))) return rc;
   }
-  const int64_t want_cap = (c->max_passes_opt > 0 ? c->max_passes_opt : (int64_t)c->n + 1) + 2;
+  const int64_t want_cap = default_max_passes(c) + 2;
   if (c->log2m != log2m || !c->regs[0] || want_cap != c->nt_cap) {
     if ((rc = alloc_run(c, log2m))) return rc;
   }
   c->inited = false;
   fill_args(c);
   c->host_log.clear();
+  if (seeds)
+    HIP_TRY(c, hipMemcpyAsync(c->comp_seed, seeds, sizeof(uint64_t) * c->n_comp, hipMemcpyHostToDevice, c->stream),
+            "seed upload");
   HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, dense_threshold(c), c->stream),
           "state reset");
   HIP_TRY(c, launch_init(c->args, seed, c->stream), "init kernel");
   HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
+  if (seeds && (rc = sync(c, "batch init"))) return rc;  // the seed array is the caller's
   c->inited = true;
   return HANF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hanf_init_counters(hanf_ctx *c, int32_t log2m, uint64_t seed) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_init_counters: NULL context");
+  if (c->batch) return fail(c, HANF_EINVAL, "batched graph: use hanf_init_batch");
+  return init_common(c, log2m, seed, nullptr);
+}
+
+int hanf_init_batch(hanf_ctx *c, int32_t log2m, const uint64_t *seeds) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_init_batch: NULL context");
+  if (!c->batch) return fail(c, HANF_ESTATE, "no batch loaded (hanf_load_batch)");
+  if (!seeds) return fail(c, HANF_EINVAL, "seeds is NULL");
+  return init_common(c, log2m, 0, seeds);
 }
 
 int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *changed_last) {
@@ -585,7 +654,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
       return fail(c, HANF_EMAXITER, "pass cap reached before the fixpoint");
     }
     if (max_steps > 0 && steps >= max_steps) break;
-    int B = c->batch;
+    int B = c->passes_per_check;
     if (max_steps > 0) B = std::min(B, max_steps - steps);
     if (c->timing) {
       ev.resize((size_t)B * 4);
@@ -667,6 +736,7 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
                          int32_t len, uint32_t flags) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_write_registers: NULL context");
   if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised (m unknown)");
+  if (c->batch) return fail(c, HANF_EINVAL, "checkpoint resume is for single graphs");
   if (!in || !nt_prefix) return fail(c, HANF_EINVAL, "NULL input");
   if (bytes != (int64_t)c->n << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n * m");
   if (t < 0 || len != t + 1) return fail(c, HANF_EINVAL, "len must be t + 1");
@@ -702,7 +772,8 @@ int hanf_stats(hanf_ctx *c, double alpha, double eps, int32_t distinct, hanf_sta
   if (!(eps >= 0.0)) return fail(c, HANF_EINVAL, "eps must be >= 0");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   double buf[9];
-  HIP_TRY(c, launch_stats(c->nt, c->st, alpha, eps, distinct ? 1 : 0, c->stats_out, c->stream), "stats kernel");
+  HIP_TRY(c, launch_stats(c->nt, nullptr, c->st, alpha, eps, distinct ? 1 : 0, c->stats_out, c->stream),
+          "stats kernel");
   HIP_TRY(c, hipMemcpyAsync(buf, c->stats_out, sizeof(buf), hipMemcpyDeviceToHost, c->stream), "stats read");
   int rc;
   if ((rc = sync(c, "stats"))) return rc;
@@ -743,6 +814,189 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)
   if (copy_graph) b += ((int64_t)n + 1) * 4 + arcs * 4;
   *bytes = b;
+  return HANF_OK;
+}
+
+int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int64_t arcs, const int32_t *row_ptr,
+                    const int32_t *col_idx, int32_t n_seeds) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_batch: NULL context");
+  if (n_graphs < 1 || n_seeds < 1 || !graph_off || !row_ptr || (arcs > 0 && !col_idx))
+    return fail(c, HANF_EINVAL, "bad batch arguments");
+  if (arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
+  if ((int64_t)n_graphs * n_seeds >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "too many components");
+  if (graph_off[0] != 0) return fail(c, HANF_EINVAL, "graph_off[0] must be 0");
+  for (int32_t g = 0; g < n_graphs; ++g)
+    if (graph_off[g + 1] <= graph_off[g]) return fail(c, HANF_EINVAL, "every graph needs at least one node");
+  const int32_t N = graph_off[n_graphs];
+  if (row_ptr[0] != 0 || (int64_t)row_ptr[N] != arcs) return fail(c, HANF_EINVAL, "row_ptr does not span the arcs");
+  for (int32_t g = 0; g <= n_graphs; ++g)
+    if (row_ptr[graph_off[g]] < 0 || row_ptr[graph_off[g]] > arcs) return fail(c, HANF_EINVAL, "row_ptr out of range");
+  // component layout
+  const int32_t C = n_graphs * n_seeds;
+  std::vector<int32_t> node_off((size_t)C + 1), arc_off((size_t)C + 1), ncomp((size_t)C);
+  int64_t nacc = 0, aacc = 0;
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    const int64_t ng = graph_off[g + 1] - graph_off[g];
+    const int64_t ag = (int64_t)row_ptr[graph_off[g + 1]] - row_ptr[graph_off[g]];
+    if (ag < 0) return fail(c, HANF_EINVAL, "row_ptr decreases across graphs");
+    for (int32_t sd = 0; sd < n_seeds; ++sd) {
+      const int32_t k = g * n_seeds + sd;
+      node_off[k] = (int32_t)nacc;
+      arc_off[k] = (int32_t)aacc;
+      ncomp[k] = (int32_t)ng;
+      nacc += (ng + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
+      aacc += ag;
+      if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
+        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
+    }
+  }
+  node_off[C] = (int32_t)nacc;
+  arc_off[C] = (int32_t)aacc;
+  const int64_t n_exp = nacc, e_exp = aacc;
+  std::vector<int32_t> blk((size_t)(n_exp / kNodesPerBlock));
+  for (int32_t k = 0; k < C; ++k)
+    for (int64_t b = node_off[k] / kNodesPerBlock; b < node_off[k + 1] / kNodesPerBlock; ++b) blk[(size_t)b] = k;
+
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_run(c);
+  free_schedule(c);
+  free_graph(c);
+  int rc;
+  int32_t *d_goff = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_aoff = nullptr;
+  auto cleanup = [&]() {
+    dev_release(c, d_goff);
+    dev_release(c, d_rp);
+    dev_release(c, d_ci);
+    dev_release(c, d_aoff);
+  };
+  if ((rc = dev_alloc(c, &d_goff, (size_t)n_graphs + 1, "batch graph offsets")) ||
+      (rc = dev_alloc(c, &d_rp, (size_t)N + 1, "batch row_ptr")) ||
+      (rc = dev_alloc(c, &d_ci, (size_t)arcs, "batch col_idx")) ||
+      (rc = dev_alloc(c, &d_aoff, (size_t)C + 1, "component arc offsets")) ||
+      (rc = dev_alloc(c, &c->blk_comp, blk.size(), "block components")) ||
+      (rc = dev_alloc(c, &c->comp_node_off, (size_t)C + 1, "component offsets")) ||
+      (rc = dev_alloc(c, &c->comp_n, (size_t)C, "component sizes")) ||
+      (rc = dev_alloc(c, &c->rp_own, (size_t)n_exp + 1, "row_ptr")) ||
+      (rc = dev_alloc(c, &c->ci_own, (size_t)e_exp, "col_idx"))) {
+    cleanup();
+    free_graph(c);
+    return rc;
+  }
+  hipError_t e = hipMemcpyAsync(d_goff, graph_off, sizeof(int32_t) * (n_graphs + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_rp, row_ptr, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && arcs > 0)
+    e = hipMemcpyAsync(d_ci, col_idx, sizeof(int32_t) * (size_t)arcs, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_aoff, arc_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->blk_comp, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream);
+  if (e == hipSuccess) e = launch_validate(d_rp, d_ci, N, arcs, c->st, c->stream);
+  c->batch = true;
+  c->n_graphs = n_graphs;
+  c->n_seeds = n_seeds;
+  c->n_comp = C;
+  c->n = (int32_t)n_exp;
+  c->arcs = e_exp;
+  fill_args(c);
+  if (e == hipSuccess)
+    e = launch_expand(d_goff, d_rp, d_ci, n_seeds, c->args, d_aoff, c->rp_own, c->ci_own, n_exp, e_exp, c->st, c->stream);
+  if (e != hipSuccess) {
+    cleanup();
+    free_graph(c);
+    return hip_fail(c, e, "batch ingest");
+  }
+  rc = read_state(c);
+  cleanup();
+  if (rc) {
+    free_graph(c);
+    return rc;
+  }
+  if (c->st_host->err) {
+    const int er = c->st_host->err;
+    free_graph(c);
+    return fail(c, HANF_EINVAL, (er & 32) ? "an arc leaves its graph" : "malformed CSR");
+  }
+  c->rp = c->rp_own;
+  c->ci = c->ci_own;
+  c->comp_node_off_h = node_off;
+  c->comp_n_h = ncomp;
+  c->graph_ok = true;
+  return HANF_OK;
+}
+
+int hanf_batch_info(hanf_ctx *c, int32_t *n_components, int32_t *T) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_info: NULL context");
+  if (!c->batch) return fail(c, HANF_ESTATE, "no batch loaded");
+  if (n_components) *n_components = c->n_comp;
+  if (T) {
+    if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+    HIP_TRY(c, hipMemcpyAsync(T, c->comp_T, sizeof(int32_t) * c->n_comp, hipMemcpyDeviceToHost, c->stream),
+            "fixpoint read");
+    return sync(c, "fixpoint read");
+  }
+  return HANF_OK;
+}
+
+int hanf_batch_read_nt(hanf_ctx *c, int32_t comp, double *out, int32_t cap, int32_t *len) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_nt: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (comp < 0 || comp >= c->n_comp || !len) return fail(c, HANF_EINVAL, "bad component or len");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int32_t Tc = -1;
+  HIP_TRY(c, hipMemcpyAsync(&Tc, c->comp_T + comp, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "fixpoint read");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  const int32_t have = (Tc >= 0 ? Tc : c->st_host->t) + 1;
+  *len = have;
+  if (cap < have) return fail(c, HANF_ERANGE, "output capacity below the history length");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  HIP_TRY(c, hipMemcpyAsync(out, c->comp_nt + (size_t)comp * c->nt_cap, sizeof(double) * have, hipMemcpyDeviceToHost,
+                            c->stream),
+          "history read");
+  return sync(c, "history read");
+}
+
+int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t bytes, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_registers: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
+  if (bytes != (int64_t)c->comp_n_h[comp] << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n_graph * m");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int rc;
+  if ((rc = read_state(c))) return rc;
+  const uint8_t *src = c->regs[c->st_host->t & 1] + ((size_t)c->comp_node_off_h[comp] << c->log2m);
+  HIP_TRY(c, hipMemcpyAsync(out, src, (size_t)bytes,
+                            flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+          "register read");
+  return sync(c, "register read");
+}
+
+int hanf_batch_stats(hanf_ctx *c, int32_t comp, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_stats: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
+  if (!(alpha > 0.0 && alpha <= 1.0) || !(eps >= 0.0)) return fail(c, HANF_EINVAL, "alpha or eps out of range");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  double buf[9];
+  HIP_TRY(c, launch_stats(c->comp_nt + (size_t)comp * c->nt_cap, c->comp_T + comp, c->st, alpha, eps,
+                          distinct ? 1 : 0, c->stats_out, c->stream),
+          "stats kernel");
+  HIP_TRY(c, hipMemcpyAsync(buf, c->stats_out, sizeof(buf), hipMemcpyDeviceToHost, c->stream), "stats read");
+  int rc;
+  if ((rc = sync(c, "stats"))) return rc;
+  out->ed = buf[0];
+  out->ied = buf[1];
+  out->avg_dist = buf[2];
+  out->var = buf[3];
+  out->spid = buf[4];
+  out->n_max = buf[5];
+  out->d_lo = buf[6];
+  out->d_hi = buf[7];
+  out->T = (int32_t)buf[8];
+  out->distinct = distinct ? 1 : 0;
   return HANF_OK;
 }
 

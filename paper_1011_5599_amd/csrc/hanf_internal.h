@@ -48,6 +48,20 @@ struct Heavy {   // a node split in several chunks, combined by the finalize ker
 
 enum ReduceMode : int32_t { kReduceInit = 0, kReducePass = 1 };
 
+// Layout of a batched run: independent components (graph, hash seed) laid side by side as
+// one graph, each starting on a 64-node boundary so that no estimate block straddles two.
+struct BatchArgs {
+  const int32_t *blk_comp;       // component of every 64-node block
+  const int32_t *comp_node_off;  // first node of every component, n_comp + 1 entries
+  const int32_t *comp_n;         // real nodes of every component (the rest are empty padding)
+  const uint64_t *comp_seed;     // hash seed of every component
+  int32_t *blkcnt;               // counters changed per block in the last pass
+  int32_t *comp_T;               // fixpoint iteration of every component, -1 while it changes
+  double *comp_nt;               // N_hat history: comp_nt[c * nt_cap + t]
+  int32_t n_comp;
+  int32_t active;                // 1 for a batched run
+};
+
 // Kernel arguments of one pass (passed by value).
 struct PassArgs {
   const int32_t *row_ptr;
@@ -81,6 +95,7 @@ struct PassArgs {
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;
   int32_t nt_cap;
+  BatchArgs batch;
 };
 
 // ---- launchers (hanf_kernels.hip); all asynchronous on `s`
@@ -102,8 +117,12 @@ hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream
 hipError_t launch_union(const PassArgs &a, int u, hipStream_t s);
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
-hipError_t launch_stats(const double *nt, const DevState *st, double alpha, double eps,
-                        int32_t distinct, double *out, hipStream_t s);
+hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
+                        double eps, int32_t distinct, double *out, hipStream_t s);
+hipError_t launch_reduce_components(const PassArgs &a, int32_t mode, hipStream_t s);
+hipError_t launch_expand(const int32_t *graph_off, const int32_t *rp_in, const int32_t *ci_in,
+                         int32_t n_seeds, const PassArgs &a, const int32_t *comp_arc_off, int32_t *rp_exp,
+                         int32_t *ci_exp, int64_t n_exp, int64_t e_exp, DevState *st, hipStream_t s);
 hipError_t launch_check_registers(const uint8_t *regs, int64_t bytes, DevState *st, hipStream_t s);
 hipError_t launch_set_history(double *nt, const double *prefix, int32_t len, DevState *st,
                               int32_t t, hipStream_t s);

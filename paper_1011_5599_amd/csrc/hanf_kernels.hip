@@ -479,7 +479,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
       bs = a.blocksum[b];
     }
     wsum += bs;
-    cnt += __popc(w0) + __popc(w1);
+    const int32_t bc = __popc(w0) + __popc(w1);
+    cnt += bc;
+    if (a.batch.active && lane == 0) a.batch.blkcnt[b] = bc;
     if (!force && lane == 0) {
       pb[2 * b] = 0u;
       pb[2 * b + 1] = 0u;
@@ -494,6 +496,87 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     a.wgsum[blockIdx.x] = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
     a.wgcnt[blockIdx.x] = (int64_t)s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
   }
+}
+
+// Batched runs: N_hat and changed count of every component (one workgroup per component,
+// fixed summation order over its blocks). Marks a component's fixpoint T the first time a
+// pass leaves it unchanged; until then appends N_hat(t+1) to its history.
+__global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a, int32_t mode) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  __shared__ double s_sum[kBlockThreads];
+  __shared__ int64_t s_cnt[kBlockThreads];
+  const int32_t c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int32_t b0 = a.batch.comp_node_off[c] / kNodesPerBlock, b1 = a.batch.comp_node_off[c + 1] / kNodesPerBlock;
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (int32_t b = b0 + tid; b < b1; b += kBlockThreads) {
+    sum += a.blocksum[b];
+    if (mode == kReducePass) cnt += a.batch.blkcnt[b];
+  }
+  s_sum[tid] = sum;
+  s_cnt[tid] = cnt;
+  __syncthreads();
+  for (int off = kBlockThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_sum[tid] += s_sum[tid + off];
+      s_cnt[tid] += s_cnt[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int32_t t = st->t;
+    double *hist = a.batch.comp_nt + (size_t)c * a.nt_cap;
+    if (mode == kReduceInit) {
+      a.batch.comp_T[c] = -1;
+      if (t < a.nt_cap) hist[t] = s_sum[0];
+    } else if (a.batch.comp_T[c] < 0) {
+      if (s_cnt[0] == 0)
+        a.batch.comp_T[c] = t;
+      else if (t + 1 < a.nt_cap)
+        hist[t + 1] = s_sum[0];
+    }
+  }
+}
+
+// Batched ingest: component c = g * n_seeds + s is a copy of input graph g placed at node
+// comp_node_off[c] (rows past the graph's own nodes are empty padding) and arc
+// comp_arc_off[c]. Arcs leaving their graph set error bit 32.
+__global__ void k_expand(const int32_t *graph_off, const int32_t *rp_in, const int32_t *ci_in,
+                         int32_t n_seeds, PassArgs a, const int32_t *comp_arc_off, int32_t *rp_exp,
+                         int32_t *ci_exp, int64_t n_exp, int64_t e_exp, DevState *st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = gid; i <= n_exp; i += stride) {
+    if (i == n_exp) {
+      rp_exp[i] = (int32_t)e_exp;
+      continue;
+    }
+    const int32_t c = a.batch.blk_comp[i / kNodesPerBlock];
+    const int32_t g = c / n_seeds;
+    const int32_t local = (int32_t)(i - a.batch.comp_node_off[c]);
+    const int32_t ng = graph_off[g + 1] - graph_off[g];
+    const int32_t row = graph_off[g] + (local < ng ? local : ng);
+    rp_exp[i] = comp_arc_off[c] + (rp_in[row] - rp_in[graph_off[g]]);
+  }
+  int32_t err = 0;
+  for (int64_t j = gid; j < e_exp; j += stride) {
+    int32_t lo = 0, hi = a.batch.n_comp;  // component with comp_arc_off[c] <= j < comp_arc_off[c+1]
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (comp_arc_off[mid] <= j) lo = mid; else hi = mid;
+    }
+    const int32_t c = lo, g = c / n_seeds;
+    const int32_t w = ci_in[rp_in[graph_off[g]] + (int32_t)(j - comp_arc_off[c])];
+    if (w < graph_off[g] || w >= graph_off[g + 1]) {
+      err |= 32;
+      ci_exp[j] = a.batch.comp_node_off[c];
+    } else {
+      ci_exp[j] = a.batch.comp_node_off[c] + (w - graph_off[g]);
+    }
+  }
+  if (err) atomicOr(&st->err, err);
 }
 
 // Totals of a pass (one workgroup, fixed summation order): N_hat(t+1), changed count and
@@ -586,14 +669,24 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
   const int sub = (int)(gid % G);
   if (v64 >= a.n) return;  // whole slots leave together (n * G lanes, G | 256)
   const int32_t v = (int32_t)v64;
-  const uint64_t h = splitmix64_output(seed, (uint64_t)v + 1);
+  // the item hashed is the node's id in its own graph; batched runs have a seed per component
+  uint64_t key = (uint64_t)v, sd = seed;
+  bool real = true;
+  if (a.batch.active) {
+    const int32_t c = a.batch.blk_comp[v / kNodesPerBlock];
+    const int32_t local = v - a.batch.comp_node_off[c];
+    real = local < a.batch.comp_n[c];
+    key = (uint64_t)local;
+    sd = a.batch.comp_seed[c];
+  }
+  const uint64_t h = splitmix64_output(sd, key + 1);
   const int b = a.log2m;
   const uint32_t idx = (uint32_t)(h >> (64 - b));
   const uint64_t rest = h << b;
   int r = rest ? __clzll((long long)rest) + 1 : 64 - b + 1;
   r = r > 31 ? 31 : r;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
-  if ((int)(idx >> 4) == sub) {
+  if (real && (int)(idx >> 4) == sub) {
     const uint32_t byte = idx & 15u;
     w[byte >> 2] = (uint32_t)r << (8 * (byte & 3u));
   }
@@ -809,10 +902,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint64_t *d, int64_
 // ------------------------------------------------------------------ statistics (Sections 4-5)
 
 // out: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi, T. One thread: O(T) work.
-__global__ void k_stats(const double *nt, const DevState *st, double alpha, double eps,
-                        int32_t distinct, double *out) {
+__global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
+                        double eps, int32_t distinct, double *out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int32_t T = st->t;
+  const int32_t T = (T_or_null && *T_or_null >= 0) ? *T_or_null : st->t;
   double M = nt[0];
   for (int32_t t = 1; t <= T; ++t) M = nt[t] > M ? nt[t] : M;
   const double base = distinct ? nt[0] : 0.0;
@@ -967,13 +1060,30 @@ hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
 
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_blocks, dim3((unsigned)a.n_reduce_wgs), dim3(kBlockThreads), 0, s, a, force);
+  if (a.batch.active && a.batch.n_comp > 0)
+    hipLaunchKernelGGL(k_reduce_components, dim3((unsigned)a.batch.n_comp), dim3(kBlockThreads), 0, s, a, mode);
   hipLaunchKernelGGL(k_reduce_top, dim3(1), dim3(kTopThreads), 0, s, a, mode);
   return hipGetLastError();
 }
 
-hipError_t launch_stats(const double *nt, const DevState *st, double alpha, double eps,
-                        int32_t distinct, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, nt, st, alpha, eps, distinct, out);
+hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
+                        double eps, int32_t distinct, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, nt, T_or_null, st, alpha, eps, distinct, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_components(const PassArgs &a, int32_t mode, hipStream_t s) {
+  if (!a.batch.active || a.batch.n_comp == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_components, dim3((unsigned)a.batch.n_comp), dim3(kBlockThreads), 0, s, a, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand(const int32_t *graph_off, const int32_t *rp_in, const int32_t *ci_in,
+                         int32_t n_seeds, const PassArgs &a, const int32_t *comp_arc_off, int32_t *rp_exp,
+                         int32_t *ci_exp, int64_t n_exp, int64_t e_exp, DevState *st, hipStream_t s) {
+  const int64_t top = e_exp > n_exp + 1 ? e_exp : n_exp + 1;
+  hipLaunchKernelGGL(k_expand, dim3(grid_for(top, 256, 16384)), dim3(256), 0, s, graph_off, rp_in, ci_in, n_seeds,
+                     a, comp_arc_off, rp_exp, ci_exp, n_exp, e_exp, st);
   return hipGetLastError();
 }
 

@@ -1,0 +1,127 @@
+"""Batched runs: every component (graph, seed) of a batch must equal its own run, register
+for register, with N_hat within 1e-12 and the same fixpoint T."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+hanf = pytest.importorskip("paper_1011_5599_amd")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_graphs():
+    gs = [graphgen.erdos_renyi(200 + 37 * i, 5 * (200 + 37 * i), seed=60 + i) for i in range(6)]
+    gs += [graphgen.rmat(9 + (i % 3), 3000 + 500 * i, seed=70 + i) for i in range(6)]
+    gs += [graphgen.empty(1), graphgen.empty(70), graphgen.directed_path(150), graphgen.star_out(3000),
+           graphgen.directed_cycle(65), graphgen.clique_path_clique(9, 5), graphgen.complete(40)]
+    return gs
+
+
+@pytest.mark.parametrize("b,S", [(4, 3), (6, 2), (8, 1)])
+def test_batch_components_equal_their_runs(b, S):
+    gs = _mixed_graphs()
+    seeds = [1000 * g + 17 * s + 1 for g in range(len(gs)) for s in range(S)]
+    _say(f"[batch] {len(gs)} graphs x {S} seeds, b={b}")
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, S).init(b, seeds)
+        bt.run()
+        T = bt.fixpoints()
+        assert (T >= 0).all()
+        for g, (rp, ci) in enumerate(gs):
+            for s in range(S):
+                c = g * S + s
+                nt_ref, T_ref, regs_ref = oracle.run(rp, ci, b, seeds[c], want_regs=True)
+                assert T[c] == T_ref, (g, s)
+                np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=1e-12, atol=0)
+                assert np.array_equal(bt.registers(c), regs_ref), (g, s)
+                st = bt.stats(c)
+                with hanf.HyperANF(0) as h:
+                    h.load(rp, ci).init(b, seeds[c])
+                    nt_plain = h.run()
+                    sp = h.stats()
+                np.testing.assert_allclose(nt_plain, bt.nt(c), rtol=1e-12, atol=0)
+                for k in ("ed", "ied", "avg_dist", "spid"):
+                    if np.isnan(sp[k]):
+                        assert np.isnan(st[k])
+                    else:
+                        assert st[k] == pytest.approx(sp[k], rel=1e-9, abs=1e-12), k
+
+
+def test_batch_step_by_step_registers():
+    """Registers of every component at every t, while other components still change."""
+    gs = [graphgen.directed_path(40), graphgen.rmat(10, 6000, seed=3), graphgen.erdos_renyi(500, 1500, seed=4)]
+    seeds = [11, 12, 13]
+    refs = [[c.copy() for _, c, _ in oracle.run_steps(rp, ci, 6, sd)] for (rp, ci), sd in zip(gs, seeds)]
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, 1).init(6, seeds)
+        for t in range(max(len(r) for r in refs) + 1):
+            for g in range(3):
+                want = refs[g][min(t, len(refs[g]) - 1)]
+                assert np.array_equal(bt.registers(g), want), (t, g)
+            st, _, _ = bt.step(1)
+            if st == hanf.HANF_DONE:
+                break
+        assert list(bt.fixpoints()) == [len(r) - 1 for r in refs]
+
+
+def test_batch_errors():
+    rp, ci = graphgen.erdos_renyi(100, 300, seed=1)
+    with hanf.HyperANF(0) as h:
+        offs = np.array([0, 50, 100], np.int32)  # arcs cross the cut at 50
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_load_batch(h.ctx, offs, rp, ci, 2)
+        assert e.value.code == hanf.HANF_EINVAL
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_load_batch(h.ctx, np.array([0, 0, 100], np.int32), rp, ci, 1)
+        assert e.value.code == hanf.HANF_EINVAL
+        hanf.hanf_load_batch(h.ctx, np.array([0, 100], np.int32), rp, ci, 2)
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_init_counters(h.ctx, 6, 1)
+        assert e.value.code == hanf.HANF_EINVAL
+        hanf.hanf_init_batch(h.ctx, 6, [1, 2])
+        with pytest.raises(hanf.HanfError):
+            hanf.hanf_batch_read_nt(h.ctx, 2)
+
+
+@pytest.mark.timeout(900)
+def test_batch_512_graphs_8_seeds():
+    """The many-graph workload at full size: 512 graphs (lognormal 2^8..2^16 nodes, half
+    Erdos-Renyi with 8n arcs, half R-MAT with 16n arcs) x 8 seeds, 64 registers. Every
+    component's T and N_hat against its plain run; registers and N_hat of 48 sampled
+    components against the oracle."""
+    gs = graphgen.batch_graphs()
+    S, b = 8, 6
+    seeds = [(g << 8) + s + 1 for g in range(len(gs)) for s in range(S)]
+    _say(f"[batch512] nodes={sum(len(r) - 1 for r, _ in gs)} arcs={sum(len(c) for _, c in gs)}")
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, S).init(b, seeds)
+        bt.run()
+        T = bt.fixpoints()
+        assert (T >= 0).all()
+        rng = np.random.default_rng(5)
+        sample = set(rng.choice(len(gs) * S, 48, replace=False).tolist())
+        with hanf.HyperANF(0) as h:
+            for g, (rp, ci) in enumerate(gs):
+                h.load(rp, ci)
+                for s in range(S):
+                    c = g * S + s
+                    h.init(b, seeds[c])
+                    nt_plain = h.run()
+                    assert len(nt_plain) == T[c] + 1, c
+                    np.testing.assert_allclose(bt.nt(c), nt_plain, rtol=1e-12, atol=0)
+                    if c in sample:
+                        nt_ref, T_ref, regs_ref = oracle.run(rp, ci, b, seeds[c], want_regs=True)
+                        assert T_ref == T[c]
+                        np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=1e-12, atol=0)
+                        assert np.array_equal(bt.registers(c), regs_ref)
+                if g % 64 == 0:
+                    _say(f"[batch512] graph {g} ok")
