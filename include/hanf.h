@@ -172,11 +172,13 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
  * the paper's protocol of many low-precision runs per graph (Section 4, moments; Section 6). */
 
 /* Loads the graphs: graph_off[n_graphs+1] node offsets (graph g has nodes graph_off[g] ..
- * graph_off[g+1]-1, at least one), row_ptr[graph_off[n_graphs]+1] and col_idx[arcs] one CSR
- * over all of them with global ids; no arc may leave its graph (HANF_EINVAL). Host memory,
- * copied. Replaces any graph or batch the context held. */
-int hanf_load_batch(hanf_ctx *ctx, int32_t n_graphs, const int32_t *graph_off, int64_t arcs,
-                    const int32_t *row_ptr, const int32_t *col_idx, int32_t n_seeds);
+ * graph_off[g+1]-1, at least one) and arc_off[n_graphs+1] arc offsets (host memory), and
+ * row_ptr[graph_off[n_graphs]+1], col_idx[arc_off[n_graphs]]: one CSR over all graphs with
+ * global ids (host memory, copied, or device memory with HANF_DEVICE_PTRS, read only during
+ * this call). row_ptr[graph_off[g]] must equal arc_off[g] and no arc may leave its graph
+ * (HANF_EINVAL). Replaces any graph or batch the context held. */
+int hanf_load_batch(hanf_ctx *ctx, int32_t n_graphs, const int32_t *graph_off, const int32_t *arc_off,
+                    const int32_t *row_ptr, const int32_t *col_idx, int32_t n_seeds, uint32_t flags);
 
 /* Initialises every component (Algorithm 2's initialisation with the graph-local node id as
  * the item and seeds[c] as the hash seed; seeds has n_graphs * n_seeds entries, host). Passes
@@ -196,6 +198,9 @@ int hanf_batch_read_registers(hanf_ctx *ctx, int32_t comp, uint8_t *out, int64_t
 /* hanf_stats of component `comp`. */
 int hanf_batch_stats(hanf_ctx *ctx, int32_t comp, double alpha, double eps, int32_t distinct,
                      hanf_stats_t *out);
+
+/* hanf_stats of every component in one launch; out has n_components entries (host). */
+int hanf_batch_stats_all(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);
 
 /* Last error message of the context, or of the calling thread when ctx is NULL. */
 const char *hanf_last_error(const hanf_ctx *ctx);

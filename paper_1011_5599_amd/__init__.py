@@ -70,14 +70,36 @@ class HanfError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln})
+    except OSError:
+        return []
+
+
 def lib():
-    """The loaded libhanf.so. Raises if it has not been built."""
+    """The loaded libhanf.so. Raises if it has not been built.
+
+    PyTorch ships its own copy of the HIP runtime, which its libraries load under the name
+    libamdhip64.so. libhanf.so needs libamdhip64.so.7, the soname of both copies. Importing
+    torch first makes libhanf.so bind to the runtime torch already loaded, so the process
+    has one HIP runtime and torch's tensors and streams can be handed to the library. Two
+    runtimes in one process are refused."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "(or python -m paper_1011_5599_amd.build)")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
+        rts = _hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError(f"two HIP runtimes loaded in one process: {rts}")
         vp = ctypes.c_void_p
         i32, i64, u32, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
         sig = {
@@ -95,12 +117,13 @@ def lib():
             "hanf_footprint": ([i32, i64, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
-            "hanf_load_batch": ([vp, i32, vp, i64, vp, vp, i32], ctypes.c_int),
+            "hanf_load_batch": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
             "hanf_init_batch": ([vp, i32, vp], ctypes.c_int),
             "hanf_batch_info": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
             "hanf_batch_read_nt": ([vp, i32, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
             "hanf_batch_read_registers": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_batch_stats": ([vp, i32, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
+            "hanf_batch_stats_all": ([vp, dbl, dbl, i32, vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -240,13 +263,17 @@ def hanf_bytemax_words(device: int, x, y, out) -> None:
     _check(lib().hanf_bytemax_words(device, x.data_ptr(), y.data_ptr(), out.data_ptr(), x.numel()))
 
 
-def hanf_load_batch(ctx, graph_off, row_ptr, col_idx, n_seeds: int) -> None:
-    """Host arrays: graph_off[G+1] node offsets, one CSR over all graphs (global ids)."""
+def hanf_load_batch(ctx, graph_off, arc_off, row_ptr, col_idx, n_seeds: int) -> None:
+    """graph_off[G+1], arc_off[G+1] (host); one CSR over all graphs with global ids: numpy
+    arrays (copied) or device tensors (read during the call)."""
     go = np.ascontiguousarray(graph_off, dtype=np.int32)
-    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
-    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
-    _check(lib().hanf_load_batch(ctx, go.size - 1, go.ctypes.data, ci.size, rp.ctypes.data,
-                                 ci.ctypes.data if ci.size else None, n_seeds), ctx)
+    ao = np.ascontiguousarray(arc_off, dtype=np.int32)
+    p_rp, f1, k1 = _ptr(row_ptr, np.int32)
+    p_ci, f2, k2 = _ptr(col_idx, np.int32)
+    if f1 != f2:
+        raise ValueError("row_ptr and col_idx must both be host or both be device arrays")
+    _check(lib().hanf_load_batch(ctx, go.size - 1, go.ctypes.data, ao.ctypes.data, p_rp,
+                                 p_ci if int(ao[-1]) > 0 else None, n_seeds, f1), ctx)
 
 
 def hanf_init_batch(ctx, log2m: int, seeds) -> None:
@@ -284,6 +311,15 @@ def hanf_batch_stats(ctx, comp: int, alpha: float = 0.9, eps: float = 0.0, disti
     s = hanf_stats_t()
     _check(lib().hanf_batch_stats(ctx, comp, alpha, eps, int(distinct), ctypes.byref(s)), ctx)
     return {f: getattr(s, f) for f, _ in hanf_stats_t._fields_}
+
+
+def hanf_batch_stats_all(ctx, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
+    """Statistics of every component: dict of numpy arrays (ed, ied, avg_dist, var, spid,
+    n_max, d_lo, d_hi, T)."""
+    n, _ = hanf_batch_info(ctx, with_T=False)
+    arr = (hanf_stats_t * max(n, 1))()
+    _check(lib().hanf_batch_stats_all(ctx, alpha, eps, int(distinct), ctypes.cast(arr, ctypes.c_void_p)), ctx)
+    return {f: np.array([getattr(arr[i], f) for i in range(n)]) for f, _ in hanf_stats_t._fields_}
 
 
 # ------------------------------------------------------------------ convenience wrapper
@@ -357,21 +393,32 @@ class Batch(HyperANF):
     """Many independent runs in the same passes: every graph of `graphs` (a list of
     (row_ptr, col_idx)) with each of its seeds; component g * n_seeds + s."""
 
-    def load_graphs(self, graphs, n_seeds: int):
+    @staticmethod
+    def union(graphs):
+        """(graph_off, arc_off, row_ptr, col_idx) of graphs laid side by side (global ids)."""
         sizes = [len(rp) - 1 for rp, _ in graphs]
-        offs = np.zeros(len(graphs) + 1, np.int64)
-        offs[1:] = np.cumsum(sizes)
-        rps, cis, base = [], [], 0
-        for (rp, ci), o in zip(graphs, offs[:-1]):
-            rps.append(np.asarray(rp[:-1], np.int64) + base)
-            cis.append(np.asarray(ci, np.int64) + o)
-            base += len(ci)
-        row_ptr = np.concatenate(rps + [np.array([base], np.int64)])
-        col_idx = np.concatenate(cis) if cis else np.zeros(0, np.int64)
-        hanf_load_batch(self.ctx, offs, row_ptr, col_idx, n_seeds)
-        self.sizes = sizes
+        arcs = [len(ci) for _, ci in graphs]
+        goff = np.zeros(len(graphs) + 1, np.int64)
+        goff[1:] = np.cumsum(sizes)
+        aoff = np.zeros(len(graphs) + 1, np.int64)
+        aoff[1:] = np.cumsum(arcs)
+        row_ptr = np.concatenate([np.asarray(rp[:-1], np.int64) + a for (rp, _), a in zip(graphs, aoff[:-1])]
+                                 + [aoff[-1:]])
+        col_idx = (np.concatenate([np.asarray(ci, np.int64) + o for (_, ci), o in zip(graphs, goff[:-1])])
+                   if aoff[-1] else np.zeros(0, np.int64))
+        return goff, aoff, row_ptr.astype(np.int32), col_idx.astype(np.int32)
+
+    def load_union(self, graph_off, arc_off, row_ptr, col_idx, n_seeds: int):
+        """Loads graphs already laid side by side (see union); row_ptr / col_idx may be device
+        tensors."""
+        hanf_load_batch(self.ctx, graph_off, arc_off, row_ptr, col_idx, n_seeds)
+        go = np.asarray(graph_off)
+        self.sizes = list(np.diff(go))
         self.n_seeds = n_seeds
         return self
+
+    def load_graphs(self, graphs, n_seeds: int):
+        return self.load_union(*self.union(graphs), n_seeds)
 
     def init(self, log2m: int, seeds):
         hanf_init_batch(self.ctx, log2m, seeds)
@@ -389,6 +436,22 @@ class Batch(HyperANF):
 
     def stats(self, comp: int, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
         return hanf_batch_stats(self.ctx, comp, alpha, eps, distinct)
+
+    def stats_all(self, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
+        return hanf_batch_stats_all(self.ctx, alpha, eps, distinct)
+
+    def seed_summary(self, alpha: float = 0.9):
+        """A-posteriori statistics over the seeds of each graph (the paper's many low-precision
+        runs, Section 6): mean and empirical standard deviation of ed, ied, average distance
+        and spid, per graph."""
+        st = self.stats_all(alpha)
+        S = self.n_seeds
+        out = {}
+        for k in ("ed", "ied", "avg_dist", "spid"):
+            v = st[k].reshape(-1, S)
+            out[k + "_mean"] = v.mean(axis=1)
+            out[k + "_std"] = v.std(axis=1, ddof=1) if S > 1 else np.zeros(v.shape[0])
+        return out
 
 
 def rsd(log2m: int, beta: float = 1.06) -> float:

@@ -817,32 +817,33 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   return HANF_OK;
 }
 
-int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int64_t arcs, const int32_t *row_ptr,
-                    const int32_t *col_idx, int32_t n_seeds) {
+int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, const int32_t *arc_off, const int32_t *row_ptr,
+                    const int32_t *col_idx, int32_t n_seeds, uint32_t flags) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_batch: NULL context");
-  if (n_graphs < 1 || n_seeds < 1 || !graph_off || !row_ptr || (arcs > 0 && !col_idx))
+  if (n_graphs < 1 || n_seeds < 1 || !graph_off || !arc_off || !row_ptr)
     return fail(c, HANF_EINVAL, "bad batch arguments");
-  if (arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  const int64_t arcs = arc_off[n_graphs];
+  if (arcs > 0 && !col_idx) return fail(c, HANF_EINVAL, "col_idx is NULL");
+  if (arc_off[0] != 0 || arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
   if ((int64_t)n_graphs * n_seeds >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "too many components");
   if (graph_off[0] != 0) return fail(c, HANF_EINVAL, "graph_off[0] must be 0");
-  for (int32_t g = 0; g < n_graphs; ++g)
+  for (int32_t g = 0; g < n_graphs; ++g) {
     if (graph_off[g + 1] <= graph_off[g]) return fail(c, HANF_EINVAL, "every graph needs at least one node");
+    if (arc_off[g + 1] < arc_off[g]) return fail(c, HANF_EINVAL, "arc_off decreases");
+  }
   const int32_t N = graph_off[n_graphs];
-  if (row_ptr[0] != 0 || (int64_t)row_ptr[N] != arcs) return fail(c, HANF_EINVAL, "row_ptr does not span the arcs");
-  for (int32_t g = 0; g <= n_graphs; ++g)
-    if (row_ptr[graph_off[g]] < 0 || row_ptr[graph_off[g]] > arcs) return fail(c, HANF_EINVAL, "row_ptr out of range");
   // component layout
   const int32_t C = n_graphs * n_seeds;
-  std::vector<int32_t> node_off((size_t)C + 1), arc_off((size_t)C + 1), ncomp((size_t)C);
+  std::vector<int32_t> node_off((size_t)C + 1), comp_aoff((size_t)C + 1), ncomp((size_t)C);
   int64_t nacc = 0, aacc = 0;
   for (int32_t g = 0; g < n_graphs; ++g) {
     const int64_t ng = graph_off[g + 1] - graph_off[g];
-    const int64_t ag = (int64_t)row_ptr[graph_off[g + 1]] - row_ptr[graph_off[g]];
-    if (ag < 0) return fail(c, HANF_EINVAL, "row_ptr decreases across graphs");
+    const int64_t ag = (int64_t)arc_off[g + 1] - arc_off[g];
     for (int32_t sd = 0; sd < n_seeds; ++sd) {
       const int32_t k = g * n_seeds + sd;
       node_off[k] = (int32_t)nacc;
-      arc_off[k] = (int32_t)aacc;
+      comp_aoff[k] = (int32_t)aacc;
       ncomp[k] = (int32_t)ng;
       nacc += (ng + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
       aacc += ag;
@@ -851,7 +852,7 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int
     }
   }
   node_off[C] = (int32_t)nacc;
-  arc_off[C] = (int32_t)aacc;
+  comp_aoff[C] = (int32_t)aacc;
   const int64_t n_exp = nacc, e_exp = aacc;
   std::vector<int32_t> blk((size_t)(n_exp / kNodesPerBlock));
   for (int32_t k = 0; k < C; ++k)
@@ -863,16 +864,25 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int
   free_schedule(c);
   free_graph(c);
   int rc;
-  int32_t *d_goff = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_aoff = nullptr;
+  const bool dev_in = flags == HANF_DEVICE_PTRS;
+  int32_t *d_goff = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_aoff = nullptr, *d_gaoff = nullptr;
   auto cleanup = [&]() {
     dev_release(c, d_goff);
-    dev_release(c, d_rp);
-    dev_release(c, d_ci);
+    dev_release(c, d_gaoff);
+    if (!dev_in) {
+      dev_release(c, d_rp);
+      dev_release(c, d_ci);
+    }
     dev_release(c, d_aoff);
   };
+  if (dev_in) {
+    d_rp = const_cast<int32_t *>(row_ptr);
+    d_ci = const_cast<int32_t *>(col_idx);
+  }
   if ((rc = dev_alloc(c, &d_goff, (size_t)n_graphs + 1, "batch graph offsets")) ||
-      (rc = dev_alloc(c, &d_rp, (size_t)N + 1, "batch row_ptr")) ||
-      (rc = dev_alloc(c, &d_ci, (size_t)arcs, "batch col_idx")) ||
+      (rc = dev_alloc(c, &d_gaoff, (size_t)n_graphs + 1, "batch arc offsets")) ||
+      (!dev_in && (rc = dev_alloc(c, &d_rp, (size_t)N + 1, "batch row_ptr"))) ||
+      (!dev_in && (rc = dev_alloc(c, &d_ci, (size_t)arcs, "batch col_idx"))) ||
       (rc = dev_alloc(c, &d_aoff, (size_t)C + 1, "component arc offsets")) ||
       (rc = dev_alloc(c, &c->blk_comp, blk.size(), "block components")) ||
       (rc = dev_alloc(c, &c->comp_node_off, (size_t)C + 1, "component offsets")) ||
@@ -884,16 +894,20 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int
     return rc;
   }
   hipError_t e = hipMemcpyAsync(d_goff, graph_off, sizeof(int32_t) * (n_graphs + 1), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_rp, row_ptr, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess && arcs > 0)
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_gaoff, arc_off, sizeof(int32_t) * (n_graphs + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && !dev_in)
+    e = hipMemcpyAsync(d_rp, row_ptr, sizeof(int32_t) * ((size_t)N + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && arcs > 0 && !dev_in)
     e = hipMemcpyAsync(d_ci, col_idx, sizeof(int32_t) * (size_t)arcs, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(d_aoff, arc_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_aoff, comp_aoff.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->blk_comp, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream);
   if (e == hipSuccess) e = launch_validate(d_rp, d_ci, N, arcs, c->st, c->stream);
+  if (e == hipSuccess) e = launch_check_offsets(d_rp, d_goff, d_gaoff, n_graphs, c->st, c->stream);
   c->batch = true;
   c->n_graphs = n_graphs;
   c->n_seeds = n_seeds;
@@ -917,7 +931,8 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, int
   if (c->st_host->err) {
     const int er = c->st_host->err;
     free_graph(c);
-    return fail(c, HANF_EINVAL, (er & 32) ? "an arc leaves its graph" : "malformed CSR");
+    return fail(c, HANF_EINVAL, (er & 32) ? "an arc leaves its graph"
+                                : (er & 64) ? "arc_off disagrees with row_ptr" : "malformed CSR");
   }
   c->rp = c->rp_own;
   c->ci = c->ci_own;
@@ -997,6 +1012,38 @@ int hanf_batch_stats(hanf_ctx *c, int32_t comp, double alpha, double eps, int32_
   out->d_hi = buf[7];
   out->T = (int32_t)buf[8];
   out->distinct = distinct ? 1 : 0;
+  return HANF_OK;
+}
+
+int hanf_batch_stats_all(hanf_ctx *c, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_stats_all: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (!(alpha > 0.0 && alpha <= 1.0) || !(eps >= 0.0)) return fail(c, HANF_EINVAL, "alpha or eps out of range");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  double *dbuf = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &dbuf, (size_t)c->n_comp * 9, "statistics"))) return rc;
+  std::vector<double> buf((size_t)c->n_comp * 9);
+  hipError_t e = launch_stats_all(c->args, alpha, eps, distinct ? 1 : 0, dbuf, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(buf.data(), dbuf, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_release(c, dbuf);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics");
+  for (int32_t k = 0; k < c->n_comp; ++k) {
+    const double *b = &buf[(size_t)k * 9];
+    out[k].ed = b[0];
+    out[k].ied = b[1];
+    out[k].avg_dist = b[2];
+    out[k].var = b[3];
+    out[k].spid = b[4];
+    out[k].n_max = b[5];
+    out[k].d_lo = b[6];
+    out[k].d_hi = b[7];
+    out[k].T = (int32_t)b[8];
+    out[k].distinct = distinct ? 1 : 0;
+  }
   return HANF_OK;
 }
 

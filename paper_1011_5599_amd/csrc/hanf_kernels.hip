@@ -579,6 +579,13 @@ __global__ void k_expand(const int32_t *graph_off, const int32_t *rp_in, const i
   if (err) atomicOr(&st->err, err);
 }
 
+// row_ptr at every graph boundary must equal the graph's arc offset (error bit 64).
+__global__ void k_check_offsets(const int32_t *rp, const int32_t *goff, const int32_t *aoff, int32_t n_graphs,
+                                DevState *st) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g <= n_graphs && rp[goff[g]] != aoff[g]) atomicOr(&st->err, 64);
+}
+
 // Totals of a pass (one workgroup, fixed summation order): N_hat(t+1), changed count and
 // work counters; advances t or marks the fixpoint.
 constexpr int kTopThreads = 1024;
@@ -901,11 +908,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint64_t *d, int64_
 
 // ------------------------------------------------------------------ statistics (Sections 4-5)
 
-// out: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi, T. One thread: O(T) work.
-__global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
-                        double eps, int32_t distinct, double *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int32_t T = (T_or_null && *T_or_null >= 0) ? *T_or_null : st->t;
+// Statistics of N_hat(0..T) into out[0..8]: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi,
+// T. Sequential O(T) work.
+__device__ void stats_of(const double *nt, int32_t T, double alpha, double eps, int32_t distinct,
+                         double *out) {
   double M = nt[0];
   for (int32_t t = 1; t <= T; ++t) M = nt[t] > M ? nt[t] : M;
   const double base = distinct ? nt[0] : 0.0;
@@ -942,6 +948,21 @@ __global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevSta
   out[6] = d_lo;
   out[7] = d_hi;
   out[8] = (double)T;
+}
+
+__global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
+                        double eps, int32_t distinct, double *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int32_t T = (T_or_null && *T_or_null >= 0) ? *T_or_null : st->t;
+  stats_of(nt, T, alpha, eps, distinct, out);
+}
+
+// Statistics of every component of a batch, one thread each: out[c * 9 + k].
+__global__ void k_stats_all(PassArgs a, double alpha, double eps, int32_t distinct, double *out) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.batch.n_comp) return;
+  const int32_t Tc = a.batch.comp_T[c];
+  stats_of(a.batch.comp_nt + (size_t)c * a.nt_cap, Tc >= 0 ? Tc : a.st->t, alpha, eps, distinct, out + (size_t)c * 9);
 }
 
 __global__ void k_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
@@ -1069,6 +1090,20 @@ hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStre
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, nt, T_or_null, st, alpha, eps, distinct, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, double *out,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_stats_all, dim3(grid_for(a.batch.n_comp, 64, 1 << 30)), dim3(64), 0, s, a, alpha, eps, distinct,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_offsets(const int32_t *rp, const int32_t *goff, const int32_t *aoff, int32_t n_graphs,
+                                DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n_graphs + 1, 256, 1 << 30)), dim3(256), 0, s, rp, goff,
+                     aoff, n_graphs, st);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ def declared_functions():
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
     assert len(names) >= 14
-    lib = ctypes.CDLL(hanf.LIB_PATH)
+    lib = hanf.lib()
     for name in names:
         assert hasattr(lib, name), name
     # and the binding exposes each under the same name
@@ -86,3 +86,13 @@ def test_bench_refuses_several_gpus():
                        capture_output=True, text=True)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_single_hip_runtime_in_process():
+    """Loading the library and torch leaves exactly one HIP runtime mapped in the process."""
+    import subprocess
+    import sys
+    code = ("import paper_1011_5599_amd as h; h.lib(); import torch; "
+            "rts = h._hip_runtimes(); assert len(rts) == 1, rts; print('ok')")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stderr

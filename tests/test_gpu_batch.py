@@ -73,17 +73,39 @@ def test_batch_step_by_step_registers():
         assert list(bt.fixpoints()) == [len(r) - 1 for r in refs]
 
 
+def test_batch_device_pointers():
+    import torch
+    gs = [graphgen.rmat(9, 2000, seed=5 + i) for i in range(5)]
+    go, ao, rp, ci = hanf.Batch.union(gs)
+    seeds = list(range(1, 11))
+    with hanf.Batch(0) as a, hanf.Batch(0) as d:
+        a.load_union(go, ao, rp, ci, 2).init(6, seeds)
+        d.load_union(go, ao, torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(), 2).init(6, seeds)
+        a.run()
+        d.run()
+        assert np.array_equal(a.fixpoints(), d.fixpoints())
+        for c in range(10):
+            assert np.array_equal(a.registers(c), d.registers(c))
+            assert np.array_equal(a.nt(c), d.nt(c))
+
+
 def test_batch_errors():
     rp, ci = graphgen.erdos_renyi(100, 300, seed=1)
     with hanf.HyperANF(0) as h:
         offs = np.array([0, 50, 100], np.int32)  # arcs cross the cut at 50
+        aoff = np.array([0, rp[50], rp[100]], np.int32)
         with pytest.raises(hanf.HanfError) as e:
-            hanf.hanf_load_batch(h.ctx, offs, rp, ci, 2)
+            hanf.hanf_load_batch(h.ctx, offs, aoff, rp, ci, 2)
         assert e.value.code == hanf.HANF_EINVAL
         with pytest.raises(hanf.HanfError) as e:
-            hanf.hanf_load_batch(h.ctx, np.array([0, 0, 100], np.int32), rp, ci, 1)
+            hanf.hanf_load_batch(h.ctx, np.array([0, 0, 100], np.int32), np.array([0, 0, rp[100]], np.int32),
+                                 rp, ci, 1)
         assert e.value.code == hanf.HANF_EINVAL
-        hanf.hanf_load_batch(h.ctx, np.array([0, 100], np.int32), rp, ci, 2)
+        with pytest.raises(hanf.HanfError) as e:  # arc offsets disagree with row_ptr
+            hanf.hanf_load_batch(h.ctx, np.array([0, 100], np.int32), np.array([0, rp[100] - 1], np.int32),
+                                 rp, ci, 1)
+        assert e.value.code == hanf.HANF_EINVAL
+        hanf.hanf_load_batch(h.ctx, np.array([0, 100], np.int32), np.array([0, rp[100]], np.int32), rp, ci, 2)
         with pytest.raises(hanf.HanfError) as e:
             hanf.hanf_init_counters(h.ctx, 6, 1)
         assert e.value.code == hanf.HANF_EINVAL
