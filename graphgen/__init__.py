@@ -191,6 +191,28 @@ def batch_graphs(count: int = 512, seed: int = 4):
     return graphs
 
 
+def serve_requests(count: int = 96, trace_seed: int = 5, lo: int = 1 << 10, hi: int = 1 << 22,
+                   median: float = 1 << 16, sigma: float = 1.5):
+    """The request stream of the serving workload: node counts round(exp(X)),
+    X ~ Normal(ln median, sigma), clipped to [lo, hi]; generator R-MAT (16 n distinct arcs on
+    the next power of two, endpoints >= n rejected) or web-like (out-degree mean 20), with
+    probability 1/2 each; log2m uniform over {4, 6, 8}; hash seed = request id. Returns a list
+    of dicts (rid, kind, n, log2m, seed, graph)."""
+    rng = np.random.default_rng(trace_seed)
+    out = []
+    for rid in range(count):
+        n = int(min(hi, max(lo, round(math.exp(rng.normal(math.log(median), sigma))))))
+        kind = "rmat" if rng.random() < 0.5 else "web"
+        log2m = int(rng.choice([4, 6, 8]))
+        gseed = 50_000 + rid
+        if kind == "rmat":
+            g = rmat(max(1, (n - 1).bit_length()), 16 * n, seed=gseed, n=n)
+        else:
+            g = web(n, seed=gseed)
+        out.append(dict(rid=rid, kind=kind, n=n, log2m=log2m, seed=rid + 1, graph=g))
+    return out
+
+
 def disjoint_union(graphs):
     """(graph_off[G+1], row_ptr[N+1], col_idx[E]) of graphs laid side by side (global ids)."""
     offs = [0]

@@ -34,7 +34,8 @@ extern "C" {
 
 /* ---- status codes */
 #define HANF_OK 0
-#define HANF_DONE 1      /* hanf_iterate: the fixpoint was reached */
+#define HANF_DONE 1      /* hanf_iterate / hanf_poll: the fixpoint was reached */
+#define HANF_BUSY 2      /* hanf_poll: enqueued passes are still running */
 #define HANF_EINVAL -1   /* invalid argument or malformed graph */
 #define HANF_ENOMEM -2   /* device or host allocation failed */
 #define HANF_EDEVICE -3  /* HIP runtime error */
@@ -132,6 +133,16 @@ int hanf_init_counters(hanf_ctx *ctx, int32_t log2m, uint64_t seed);
  * pass. HANF_EMAXITER if the pass cap is reached first. */
 int hanf_iterate(hanf_ctx *ctx, int32_t max_steps, int32_t *steps_done, int64_t *changed_last);
 
+/* Non-blocking form of hanf_iterate, for callers that keep several runs in flight on
+ * different streams: enqueues `passes` passes and a copy of the run state, and returns at
+ * once. Passes enqueued past the fixpoint do nothing. The pass log is not kept. */
+int hanf_enqueue(hanf_ctx *ctx, int32_t passes);
+
+/* Does not wait: HANF_BUSY while the work of the last hanf_enqueue runs; then HANF_DONE if
+ * the fixpoint was reached, HANF_OK if more passes are needed, HANF_EMAXITER at the pass cap.
+ * *t (may be NULL) receives the iteration reached. HANF_ESTATE if nothing was enqueued. */
+int hanf_poll(hanf_ctx *ctx, int32_t *t);
+
 /* Copies N_hat(0..t) to host `out` (FP64). *len receives t+1; HANF_ERANGE if cap < t+1. */
 int hanf_read_nt(hanf_ctx *ctx, double *out, int32_t cap, int32_t *len);
 
@@ -179,6 +190,15 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
  * (HANF_EINVAL). Replaces any graph or batch the context held. */
 int hanf_load_batch(hanf_ctx *ctx, int32_t n_graphs, const int32_t *graph_off, const int32_t *arc_off,
                     const int32_t *row_ptr, const int32_t *col_idx, int32_t n_seeds, uint32_t flags);
+
+/* The same, with the graphs given separately, each as its own CSR with its own node ids
+ * 0..n_nodes[g]-1: row_ptrs[g] (n_nodes[g]+1 entries) and col_idxs[g] (n_arcs[g] entries),
+ * all host memory (copied) or all device memory (HANF_DEVICE_PTRS, read during the call).
+ * The arrays of pointers and sizes are host memory. Each graph's CSR is checked as in
+ * hanf_load_csr. */
+int hanf_load_batch_list(hanf_ctx *ctx, int32_t n_graphs, const int32_t *const *row_ptrs,
+                         const int32_t *const *col_idxs, const int32_t *n_nodes, const int64_t *n_arcs,
+                         int32_t n_seeds, uint32_t flags);
 
 /* Initialises every component (Algorithm 2's initialisation with the graph-local node id as
  * the item and seeds[c] as the hash seed; seeds has n_graphs * n_seeds entries, host). Passes

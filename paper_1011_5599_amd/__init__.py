@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libhanf.so")
 
 HANF_OK = 0
 HANF_DONE = 1
+HANF_BUSY = 2
 HANF_EINVAL = -1
 HANF_ENOMEM = -2
 HANF_EDEVICE = -3
@@ -118,6 +119,9 @@ def lib():
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
             "hanf_load_batch": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
+            "hanf_load_batch_list": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
+            "hanf_enqueue": ([vp, i32], ctypes.c_int),
+            "hanf_poll": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
             "hanf_init_batch": ([vp, i32, vp], ctypes.c_int),
             "hanf_batch_info": ([vp, ctypes.POINTER(i32), vp], ctypes.c_int),
             "hanf_batch_read_nt": ([vp, i32, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
@@ -205,6 +209,18 @@ def hanf_iterate(ctx, max_steps: int = 0):
     return rc, steps.value, changed.value
 
 
+def hanf_enqueue(ctx, passes: int) -> None:
+    _check(lib().hanf_enqueue(ctx, passes), ctx)
+
+
+def hanf_poll(ctx):
+    """(status, t): status HANF_BUSY, HANF_OK (more passes needed) or HANF_DONE."""
+    t = ctypes.c_int32()
+    rc = lib().hanf_poll(ctx, ctypes.byref(t))
+    _check(rc, ctx, ok=(HANF_OK, HANF_DONE, HANF_BUSY))
+    return rc, t.value
+
+
 def hanf_read_nt(ctx) -> np.ndarray:
     n = ctypes.c_int32()
     rc = lib().hanf_read_nt(ctx, None, 0, ctypes.byref(n))
@@ -274,6 +290,24 @@ def hanf_load_batch(ctx, graph_off, arc_off, row_ptr, col_idx, n_seeds: int) -> 
         raise ValueError("row_ptr and col_idx must both be host or both be device arrays")
     _check(lib().hanf_load_batch(ctx, go.size - 1, go.ctypes.data, ao.ctypes.data, p_rp,
                                  p_ci if int(ao[-1]) > 0 else None, n_seeds, f1), ctx)
+
+
+def hanf_load_batch_list(ctx, graphs, n_seeds: int):
+    """graphs: list of (row_ptr, col_idx) with their own node ids, all numpy (copied) or all
+    device tensors (read during the call). Returns the objects to keep alive until then."""
+    ptrs = [(_ptr(rp, np.int32), _ptr(ci, np.int32)) for rp, ci in graphs]
+    flags = {p[0][1] for p in ptrs} | {p[1][1] for p in ptrs}
+    if len(flags) != 1:
+        raise ValueError("all arrays must be host arrays or all device tensors")
+    G = len(graphs)
+    rps = (ctypes.c_void_p * G)(*[p[0][0] for p in ptrs])
+    cis = (ctypes.c_void_p * G)(*[p[1][0] for p in ptrs])
+    sizes = lambda k: (k.numel() if _is_tensor(k) else k.size)  # noqa: E731
+    nn = np.array([sizes(p[0][2]) - 1 for p in ptrs], np.int32)
+    na = np.array([sizes(p[1][2]) for p in ptrs], np.int64)
+    _check(lib().hanf_load_batch_list(ctx, G, ctypes.cast(rps, ctypes.c_void_p), ctypes.cast(cis, ctypes.c_void_p),
+                                      nn.ctypes.data, na.ctypes.data, n_seeds, flags.pop()), ctx)
+    return ptrs
 
 
 def hanf_init_batch(ctx, log2m: int, seeds) -> None:
@@ -418,7 +452,12 @@ class Batch(HyperANF):
         return self
 
     def load_graphs(self, graphs, n_seeds: int):
-        return self.load_union(*self.union(graphs), n_seeds)
+        """Loads a list of (row_ptr, col_idx), each with its own node ids (numpy or device
+        tensors), with no concatenation on the host."""
+        hanf_load_batch_list(self.ctx, graphs, n_seeds)
+        self.sizes = [len(rp) - 1 for rp, _ in graphs]
+        self.n_seeds = n_seeds
+        return self
 
     def init(self, log2m: int, seeds):
         hanf_init_batch(self.ctx, log2m, seeds)

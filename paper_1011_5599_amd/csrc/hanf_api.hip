@@ -95,6 +95,9 @@ struct hanf_ctx {
   PassLog *log = nullptr;
   DevState *st = nullptr;
   DevState *st_host = nullptr;  // pinned
+  DevState *st_poll = nullptr;  // pinned, written by the copy hanf_enqueue leaves on the stream
+  hipEvent_t poll_ev = nullptr;
+  bool poll_pending = false;
   int32_t nt_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
   std::vector<double> lc_host;
   std::vector<hanf_pass_t> host_log;
@@ -122,16 +125,27 @@ int hip_fail(hanf_ctx *c, hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
   } while (0)
 
+// Allocation sizes above 64 KiB are rounded up to size classes 2^k and 1.5 * 2^k, so that
+// runs on graphs of different sizes can reuse each other's buffers (at most a third wasted).
+size_t size_class(size_t bytes) {
+  if (bytes <= (64u << 10)) return (bytes + 255) / 256 * 256;
+  size_t p = 1;
+  while (p < bytes) p <<= 1;
+  const size_t mid = p / 2 + p / 4;
+  return bytes <= mid ? mid : p;
+}
+
 // Device allocations go through a per-context pool: a released buffer is kept and handed
-// out again for a request of the same byte size, so repeated runs on graphs of one size
-// allocate nothing after the first. Everything is returned to HIP at hanf_destroy.
+// out again for a request of the same size class, so repeated runs allocate nothing after
+// the first (hipFree also waits for the whole device, which would stall other streams).
+// Everything is returned to HIP at hanf_destroy.
 template <typename T>
 int dev_alloc(hanf_ctx *c, T **p, size_t count, const char *what) {
   *p = nullptr;
   c->alloc_count++;
   if (c->fail_alloc_at > 0 && c->alloc_count == c->fail_alloc_at)
     return fail(c, HANF_ENOMEM, std::string("forced allocation failure: ") + what);
-  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  const size_t bytes = size_class(std::max<size_t>(count, 1) * sizeof(T));
   auto it = c->pool.find(bytes);
   if (it != c->pool.end()) {
     *p = static_cast<T *>(it->second);
@@ -448,6 +462,8 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
     }
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_poll, sizeof(DevState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     std::string msg = std::string("hanf_create: ") + hipGetErrorString(e);
     hanf_destroy(c);
@@ -475,6 +491,8 @@ void hanf_destroy(hanf_ctx *c) {
   c->sizes.clear();
   c->pool.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
+  if (c->st_poll) (void)hipHostFree(c->st_poll);
+  if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -699,6 +717,39 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
       return fail(c, HANF_EDEVICE, "no pass completed (device state did not advance)");
   }
   if (steps_done) *steps_done = steps;
+  return HANF_OK;
+}
+
+int hanf_enqueue(hanf_ctx *c, int32_t passes) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_enqueue: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (passes < 1) return fail(c, HANF_EINVAL, "passes must be >= 1");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  int rc;
+  for (int32_t i = 0; i < passes; ++i)
+    if ((rc = enqueue_pass(c, nullptr))) return rc;
+  HIP_TRY(c, hipMemcpyAsync(c->st_poll, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), "state copy");
+  HIP_TRY(c, hipEventRecord(c->poll_ev, c->stream), "event");
+  c->poll_pending = true;
+  return HANF_OK;
+}
+
+int hanf_poll(hanf_ctx *c, int32_t *t) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_poll: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (!c->poll_pending) return fail(c, HANF_ESTATE, "nothing enqueued");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  const hipError_t e = hipEventQuery(c->poll_ev);
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();
+    return HANF_BUSY;
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "poll");
+  c->poll_pending = false;
+  const DevState s0 = *c->st_poll;
+  if (t) *t = s0.t;
+  if (s0.done) return HANF_DONE;
+  if (s0.capped) return fail(c, HANF_EMAXITER, "pass cap reached before the fixpoint");
   return HANF_OK;
 }
 
@@ -933,6 +984,124 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
     free_graph(c);
     return fail(c, HANF_EINVAL, (er & 32) ? "an arc leaves its graph"
                                 : (er & 64) ? "arc_off disagrees with row_ptr" : "malformed CSR");
+  }
+  c->rp = c->rp_own;
+  c->ci = c->ci_own;
+  c->comp_node_off_h = node_off;
+  c->comp_n_h = ncomp;
+  c->graph_ok = true;
+  return HANF_OK;
+}
+
+int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *row_ptrs,
+                         const int32_t *const *col_idxs, const int32_t *n_nodes, const int64_t *n_arcs,
+                         int32_t n_seeds, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_batch_list: NULL context");
+  if (n_graphs < 1 || n_seeds < 1 || !row_ptrs || !col_idxs || !n_nodes || !n_arcs)
+    return fail(c, HANF_EINVAL, "bad batch arguments");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  if ((int64_t)n_graphs * n_seeds >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "too many components");
+  std::vector<int32_t> goff((size_t)n_graphs + 1), aoff((size_t)n_graphs + 1);
+  int64_t nacc = 0, aacc = 0;
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    if (n_nodes[g] < 1 || n_arcs[g] < 0 || !row_ptrs[g] || (n_arcs[g] > 0 && !col_idxs[g]))
+      return fail(c, HANF_EINVAL, "every graph needs at least one node and its arrays");
+    goff[g] = (int32_t)nacc;
+    aoff[g] = (int32_t)aacc;
+    nacc += n_nodes[g];
+    aacc += n_arcs[g];
+    if (nacc + n_graphs >= (int64_t)INT32_MAX || aacc >= (int64_t)INT32_MAX)
+      return fail(c, HANF_EINVAL, "batch too large for 32-bit indices");
+  }
+  goff[n_graphs] = (int32_t)nacc;
+  aoff[n_graphs] = (int32_t)aacc;
+  const int32_t C = n_graphs * n_seeds;
+  std::vector<int32_t> node_off((size_t)C + 1), comp_aoff((size_t)C + 1), ncomp((size_t)C);
+  int64_t en = 0, ea = 0;
+  for (int32_t g = 0; g < n_graphs; ++g)
+    for (int32_t sd = 0; sd < n_seeds; ++sd) {
+      const int32_t k = g * n_seeds + sd;
+      node_off[k] = (int32_t)en;
+      comp_aoff[k] = (int32_t)ea;
+      ncomp[k] = n_nodes[g];
+      en += ((int64_t)n_nodes[g] + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
+      ea += n_arcs[g];
+      if (en >= (int64_t)INT32_MAX - kNodesPerBlock || ea >= (int64_t)INT32_MAX)
+        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
+    }
+  node_off[C] = (int32_t)en;
+  comp_aoff[C] = (int32_t)ea;
+  std::vector<int32_t> blk((size_t)(en / kNodesPerBlock));
+  for (int32_t k = 0; k < C; ++k)
+    for (int64_t b = node_off[k] / kNodesPerBlock; b < node_off[k + 1] / kNodesPerBlock; ++b) blk[(size_t)b] = k;
+
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_run(c);
+  free_schedule(c);
+  free_graph(c);
+  int rc;
+  int32_t *d_goff = nullptr, *d_gaoff = nullptr, *d_rp = nullptr, *d_ci = nullptr, *d_aoff = nullptr;
+  auto cleanup = [&]() {
+    dev_release(c, d_goff);
+    dev_release(c, d_gaoff);
+    dev_release(c, d_rp);
+    dev_release(c, d_ci);
+    dev_release(c, d_aoff);
+  };
+  if ((rc = dev_alloc(c, &d_goff, (size_t)n_graphs + 1, "batch graph offsets")) ||
+      (rc = dev_alloc(c, &d_gaoff, (size_t)n_graphs + 1, "batch arc offsets")) ||
+      (rc = dev_alloc(c, &d_rp, (size_t)nacc + n_graphs, "batch row_ptr")) ||
+      (rc = dev_alloc(c, &d_ci, (size_t)aacc, "batch col_idx")) ||
+      (rc = dev_alloc(c, &d_aoff, (size_t)C + 1, "component arc offsets")) ||
+      (rc = dev_alloc(c, &c->blk_comp, blk.size(), "block components")) ||
+      (rc = dev_alloc(c, &c->comp_node_off, (size_t)C + 1, "component offsets")) ||
+      (rc = dev_alloc(c, &c->comp_n, (size_t)C, "component sizes")) ||
+      (rc = dev_alloc(c, &c->rp_own, (size_t)en + 1, "row_ptr")) ||
+      (rc = dev_alloc(c, &c->ci_own, (size_t)ea, "col_idx"))) {
+    cleanup();
+    free_graph(c);
+    return rc;
+  }
+  const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  hipError_t e = hipSuccess;
+  for (int32_t g = 0; g < n_graphs && e == hipSuccess; ++g) {
+    e = hipMemcpyAsync(d_rp + goff[g] + g, row_ptrs[g], sizeof(int32_t) * ((size_t)n_nodes[g] + 1), kind, c->stream);
+    if (e == hipSuccess && n_arcs[g] > 0)
+      e = hipMemcpyAsync(d_ci + aoff[g], col_idxs[g], sizeof(int32_t) * (size_t)n_arcs[g], kind, c->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(d_goff, goff.data(), sizeof(int32_t) * (n_graphs + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_gaoff, aoff.data(), sizeof(int32_t) * (n_graphs + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_aoff, comp_aoff.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->blk_comp, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream);
+  c->batch = true;
+  c->n_graphs = n_graphs;
+  c->n_seeds = n_seeds;
+  c->n_comp = C;
+  c->n = (int32_t)en;
+  c->arcs = ea;
+  fill_args(c);
+  if (e == hipSuccess)
+    e = launch_expand_local(d_goff, d_gaoff, d_rp, d_ci, n_graphs, n_seeds, c->args, d_aoff, c->rp_own, c->ci_own, en,
+                            ea, c->st, c->stream);
+  if (e != hipSuccess) {
+    cleanup();
+    free_graph(c);
+    return hip_fail(c, e, "batch ingest");
+  }
+  rc = read_state(c);
+  cleanup();
+  if (rc) {
+    free_graph(c);
+    return rc;
+  }
+  if (c->st_host->err) {
+    free_graph(c);
+    return fail(c, HANF_EINVAL, "malformed CSR in the batch");
   }
   c->rp = c->rp_own;
   c->ci = c->ci_own;

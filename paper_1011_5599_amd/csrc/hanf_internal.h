@@ -120,6 +120,10 @@ hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStre
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out, hipStream_t s);
 hipError_t launch_reduce_components(const PassArgs &a, int32_t mode, hipStream_t s);
+hipError_t launch_expand_local(const int32_t *graph_off, const int32_t *arc_off, const int32_t *rp_in,
+                               const int32_t *ci_in, int32_t n_graphs, int32_t n_seeds, const PassArgs &a,
+                               const int32_t *comp_arc_off, int32_t *rp_exp, int32_t *ci_exp, int64_t n_exp,
+                               int64_t e_exp, DevState *st, hipStream_t s);
 hipError_t launch_check_offsets(const int32_t *rp, const int32_t *goff, const int32_t *aoff, int32_t n_graphs,
                                 DevState *st, hipStream_t s);
 hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, double *out,

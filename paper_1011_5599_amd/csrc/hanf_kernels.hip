@@ -579,6 +579,55 @@ __global__ void k_expand(const int32_t *graph_off, const int32_t *rp_in, const i
   if (err) atomicOr(&st->err, err);
 }
 
+// Batched ingest from graphs given separately with their own ids: graph g's row_ptr
+// (n_g + 1 entries, from 0) is at rp_in[graph_off[g] + g], its col_idx (ids 0..n_g-1) at
+// ci_in[arc_off[g]]. Builds the expanded CSR as k_expand does and checks every graph's CSR
+// (error bits: 1 row_ptr[0] != 0, 2 decreasing, 4 row_ptr[n] != arcs, 8 id out of range).
+__global__ void k_expand_local(const int32_t *graph_off, const int32_t *arc_off, const int32_t *rp_in,
+                               const int32_t *ci_in, int32_t n_graphs, int32_t n_seeds, PassArgs a,
+                               const int32_t *comp_arc_off, int32_t *rp_exp, int32_t *ci_exp, int64_t n_exp,
+                               int64_t e_exp, DevState *st) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t err = 0;
+  for (int64_t i = gid; i <= n_exp; i += stride) {
+    if (i == n_exp) {
+      rp_exp[i] = (int32_t)e_exp;
+      continue;
+    }
+    const int32_t c = a.batch.blk_comp[i / kNodesPerBlock];
+    const int32_t g = c / n_seeds;
+    const int32_t local = (int32_t)(i - a.batch.comp_node_off[c]);
+    const int32_t ng = graph_off[g + 1] - graph_off[g];
+    const int32_t *rp = rp_in + graph_off[g] + g;
+    const int32_t row = local < ng ? local : ng;
+    const int32_t r0 = rp[row];
+    rp_exp[i] = comp_arc_off[c] + r0;
+    if (c % n_seeds == 0 && local < ng) {  // checks, once per graph
+      if (local == 0 && r0 != 0) err |= 1;
+      if (rp[local + 1] < r0) err |= 2;
+      if (local == ng - 1 && rp[ng] != arc_off[g + 1] - arc_off[g]) err |= 4;
+    }
+  }
+  for (int64_t j = gid; j < e_exp; j += stride) {
+    int32_t lo = 0, hi = a.batch.n_comp;
+    while (hi - lo > 1) {
+      const int32_t mid = (lo + hi) >> 1;
+      if (comp_arc_off[mid] <= j) lo = mid; else hi = mid;
+    }
+    const int32_t c = lo, g = c / n_seeds;
+    const int32_t w = ci_in[arc_off[g] + (int32_t)(j - comp_arc_off[c])];
+    const int32_t ng = graph_off[g + 1] - graph_off[g];
+    if (w < 0 || w >= ng) {
+      err |= 8;
+      ci_exp[j] = a.batch.comp_node_off[c];
+    } else {
+      ci_exp[j] = a.batch.comp_node_off[c] + w;
+    }
+  }
+  if (err) atomicOr(&st->err, err);
+}
+
 // row_ptr at every graph boundary must equal the graph's arc offset (error bit 64).
 __global__ void k_check_offsets(const int32_t *rp, const int32_t *goff, const int32_t *aoff, int32_t n_graphs,
                                 DevState *st) {
@@ -1097,6 +1146,16 @@ hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t
                             hipStream_t s) {
   hipLaunchKernelGGL(k_stats_all, dim3(grid_for(a.batch.n_comp, 64, 1 << 30)), dim3(64), 0, s, a, alpha, eps, distinct,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_local(const int32_t *graph_off, const int32_t *arc_off, const int32_t *rp_in,
+                               const int32_t *ci_in, int32_t n_graphs, int32_t n_seeds, const PassArgs &a,
+                               const int32_t *comp_arc_off, int32_t *rp_exp, int32_t *ci_exp, int64_t n_exp,
+                               int64_t e_exp, DevState *st, hipStream_t s) {
+  const int64_t top = e_exp > n_exp + 1 ? e_exp : n_exp + 1;
+  hipLaunchKernelGGL(k_expand_local, dim3(grid_for(top, 256, 16384)), dim3(256), 0, s, graph_off, arc_off, rp_in, ci_in,
+                     n_graphs, n_seeds, a, comp_arc_off, rp_exp, ci_exp, n_exp, e_exp, st);
   return hipGetLastError();
 }
 

@@ -112,6 +112,16 @@ def test_batch_errors():
         hanf.hanf_init_batch(h.ctx, 6, [1, 2])
         with pytest.raises(hanf.HanfError):
             hanf.hanf_batch_read_nt(h.ctx, 2)
+        bad = ci.copy()
+        bad[7] = 100  # out of its graph's ids
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_load_batch_list(h.ctx, [(rp, ci), (rp, bad)], 1)
+        assert e.value.code == hanf.HANF_EINVAL
+        badr = rp.copy()
+        badr[3] = badr[4] + 1
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_load_batch_list(h.ctx, [(badr, ci)], 1)
+        assert e.value.code == hanf.HANF_EINVAL
 
 
 @pytest.mark.timeout(900)
