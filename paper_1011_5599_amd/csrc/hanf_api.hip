@@ -260,9 +260,10 @@ void choose_schedule(hanf_ctx *c, int G, Schedule &s) {
   s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, W * c->unroll * 8);
   int32_t tile = c->tile_opt;
   if (tile <= 0) {
-    // enough wavefronts to fill the chip on small graphs, 256 nodes per tile on large ones
+    // about 8 rounds of W nodes per wavefront on large graphs (measured best on MI355X for
+    // m = 64 and 128), fewer on small graphs so that the chip still gets many wavefronts
     int64_t rounds = (int64_t)c->n / ((int64_t)W * 2048);
-    rounds = std::max<int64_t>(1, std::min<int64_t>(rounds, kMaxTile / W));
+    rounds = std::max<int64_t>(1, std::min<int64_t>({rounds, (int64_t)8, (int64_t)(kMaxTile / W)}));
     tile = (int32_t)(rounds * W);
   }
   tile = std::max(W, std::min(kMaxTile, (tile / W) * W));
@@ -352,6 +353,7 @@ void fill_args(hanf_ctx *c) {
   a.n_light_wgs = c->sch.n_light_wgs;
   a.n_tiles = c->sch.n_tiles;
   a.tile_nodes = c->sch.tile_nodes;
+  a.light_max = c->sch.light_max;
   a.n_heavy = c->sch.n_heavy;
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;

@@ -13,7 +13,7 @@ constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 co
 constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 16;  // 64-node blocks per reduction workgroup
-constexpr int kStatSlots = 64;     // rows of work counters, spread over workgroups
+constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
@@ -91,6 +91,7 @@ struct PassArgs {
   int32_t n_light_wgs;
   int32_t n_tiles;
   int32_t tile_nodes;
+  int32_t light_max;         // nodes with more arcs are handled by chunks
   int32_t n_heavy;
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;

@@ -241,38 +241,106 @@ __device__ __forceinline__ void combine_slots(uint4 &acc, bool &any) {
   any = anyi != 0;
 }
 
-// First phase of a frontier pass over a light tile: one lane per node scans the node's
-// successor ids until it meets one whose counter was modified by the previous pass. Nodes
-// that must produce a new counter (such a successor, or a counter of their own modified by
-// the previous pass, whose update-buffer row is stale) are compacted into `act`.
-// Returns their number (wavefront-uniform).
+// First phase of a frontier pass over a light tile: find the nodes that must produce a new
+// counter (a successor modified by the previous pass, or their own counter modified by it,
+// which leaves their update-buffer row stale). The tile covers consecutive ids, so the arcs
+// of each 64-node sub-round form one contiguous CSR range: the wavefront streams it 64 ids
+// per load (skipping the arcs of nodes with more than light_max arcs, which chunks handle),
+// tests each successor's modified flag, and only a lane that hits one looks up its source
+// node (binary search over the sub-round's 65 row pointers in LDS). The active nodes are
+// then compacted into `act` in the tile's degree order. Returns their number
+// (wavefront-uniform). `rps` holds 65 ints of LDS per wavefront.
 template <int U>
-__device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f, const int32_t *tl,
-                                               int32_t nodes, int lane, int32_t *act, Counters &cnt) {
+__device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f, const int32_t *tl, int32_t tile,
+                                               int32_t light_max, int lane, int32_t *rps, int32_t *act,
+                                               Counters &cnt) {
   const uint64_t below = (1ull << lane) - 1ull;
-  int32_t n_act = 0;
-  for (int32_t i = 0; i < nodes; i += kWave) {
-    const int32_t v = i + lane < nodes ? tl[i + lane] : -1;
-    if (!__any(v >= 0)) break;  // empty entries sort last
-    bool active = false;
-    if (v >= 0) {
-      active = testbit(f.prev_bits, v);
-      const int32_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
-      cnt.scanned += end - beg;
-      for (int32_t p = beg; p < end && !active; p += U) {
-        int32_t w[U];
-        bool ok[U];
+  const int32_t lo = tile * a.tile_nodes;
+  const int32_t hi = min(a.n, lo + a.tile_nodes);
+  uint64_t marks[kMaxTile / kWave];
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-          ok[k] = p + k < end;
-          w[k] = ok[k] ? a.col_idx[p + k] : 0;
+  for (int k = 0; k < kMaxTile / kWave; ++k) marks[k] = 0ull;
+  for (int32_t s0 = lo; s0 < hi; s0 += kWave) {
+    const int32_t cnt_nodes = min(kWave, hi - s0);
+    const int32_t v = s0 + lane;
+    const bool valid = lane < cnt_nodes;
+    const int32_t r0 = valid ? a.row_ptr[v] : 0;
+    const int32_t r1 = valid ? a.row_ptr[v + 1] : 0;
+    if (valid) rps[lane] = r0;
+    if (lane == cnt_nodes - 1) rps[cnt_nodes] = r1;
+    const int32_t deg = r1 - r0;
+    const bool heavy = valid && deg > light_max;
+    bool act = valid && deg > 0 && !heavy && testbit(f.prev_bits, v);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t hmask = __ballot(heavy);
+    uint64_t hit = 0ull;  // nodes (lanes) with a modified successor; the same value in every lane
+    int32_t j0 = 0;
+    while (j0 < cnt_nodes) {
+      const uint64_t rest = hmask >> j0;
+      const int32_t j1 = rest ? j0 + __ffsll((long long)rest) - 1 : cnt_nodes;  // light run [j0, j1)
+      if (j1 > j0) {
+        const int32_t A = rps[j0], B = rps[j1];
+        if (lane == 0) cnt.scanned += B - A;
+        for (int32_t base = A; base < B; base += kWave * U) {
+          int32_t w[U];
+          bool ok[U];
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            const int32_t p = base + k * kWave + lane;
+            ok[k] = p < B;
+            w[k] = ok[k] ? a.col_idx[p] : 0;
+          }
+#pragma unroll
+          for (int k = 0; k < U; ++k) {
+            const bool h = ok[k] && testbit(f.prev_bits, w[k]);
+            if (__any(h)) {
+              int32_t src = -1;
+              if (h) {  // source node: the last j in [j0, j1) with rps[j] <= arc
+                const int32_t arc = base + k * kWave + lane;
+                int32_t l = j0, r = j1;
+                while (r - l > 1) {
+                  const int32_t mid = (l + r) >> 1;
+                  if (rps[mid] <= arc) l = mid; else r = mid;
+                }
+                src = l;
+              }
+              // OR the source lanes into `hit`, one distinct source per step
+              uint64_t pending = __ballot(src >= 0);
+              while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const int32_t sv = __shfl(src, leader);
+                hit |= 1ull << sv;
+                pending &= ~__ballot(src == sv);
+              }
+            }
+          }
         }
-#pragma unroll
-        for (int k = 0; k < U; ++k) active = active || (ok[k] && testbit(f.prev_bits, w[k]));
       }
+      j0 = j1 + 1;
     }
-    const uint64_t bal = __ballot(active);
-    if (active) act[n_act + __popcll(bal & below)] = v;
+    act = act || (valid && ((hit >> lane) & 1ull));
+    const uint64_t am = __ballot(act);
+#pragma unroll
+    for (int k = 0; k < kMaxTile / kWave; ++k)
+      if ((s0 - lo) / kWave == k) marks[k] = am;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  // compact the active nodes in the tile's (degree) order
+  int32_t n_act = 0;
+  for (int32_t i = 0; i < a.tile_nodes; i += kWave) {
+    const int32_t v = i + lane < a.tile_nodes ? tl[i + lane] : -1;
+    if (!__any(v >= 0)) break;  // empty entries sort last
+    bool keep = false;
+    if (v >= 0) {
+      const int32_t lv = v - lo;
+#pragma unroll
+      for (int k = 0; k < kMaxTile / kWave; ++k)
+        if ((lv >> 6) == k) keep = (marks[k] >> (lv & 63)) & 1ull;
+    }
+    const uint64_t bal = __ballot(keep);
+    if (keep) act[n_act + __popcll(bal & below)] = v;
     n_act += __popcll(bal);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -333,12 +401,12 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     cnt.scanned += ch.a1 - ch.a0;
     cnt.gathered += gathered;
   }
-  bool any = gathered > 0;
-  combine_slots<G>(acc, any);
+  bool any = gathered > 0;  // wavefront-uniform
+  if (any) combine_slots<G>(acc, any);
   if (ch.part < 0) {
     finalize_slot<G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, zero4(), cnt);
   } else if (slot == 0) {
-    strow(a.partial, ch.part, m, sub, acc);
+    if (any) strow(a.partial, ch.part, m, sub, acc);  // rows of empty chunks are never read
     if (sub == 0) a.partial_any[ch.part] = any ? 1 : 0;
   }
 }
@@ -390,6 +458,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
   __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
+  __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
@@ -411,7 +480,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
         }
       } else {
         int32_t *act = act_buf + wave * kMaxTile;
-        const int32_t n_act = find_active<U>(a, f, tl, a.tile_nodes, lane, act, cnt);
+        const int32_t n_act =
+            find_active<U>(a, f, tl, tile, a.light_max, lane, rp_buf + wave * (kWave + 1), act, cnt);
         for (int32_t r = 0; r < n_act; r += W) {
           const int32_t v = r + slot < n_act ? act[r + slot] : -1;
           light_round<G, U, false>(a, f, v, lane, qw, cnt);
@@ -439,8 +509,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     uint4 acc = zero4();
     bool any = false;
     for (int32_t j = slot; j < hv.count; j += W) {
-      acc = bytemax4(acc, ldrow(a.partial, hv.first + j, m, sub));
-      any = any || a.partial_any[hv.first + j] != 0;
+      if (a.partial_any[hv.first + j]) {
+        acc = bytemax4(acc, ldrow(a.partial, hv.first + j, m, sub));
+        any = true;
+      }
     }
     combine_slots<G>(acc, any);
     finalize_slot<G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, zero4(), cnt);
