@@ -62,6 +62,16 @@ extern "C" {
                                    maximises with every successor instead of testing each one's
                                    modified flag (same result; cheaper when most changed).
                                    Default 4; 0 = never */
+#define HANF_OPT_SYSTOLIC 9     /* s: after a pass that changed < n/s counters, the next pass is
+                                   systolic (Section 3.3, systolic computation): the modified
+                                   counters signal their predecessors through the transposed
+                                   graph and only signalled nodes are recomputed (same result).
+                                   Needs a transposed graph (hanf_load_transpose or
+                                   hanf_build_transpose); default 4 as in the paper; 0 = never */
+
+/* ---- hanf_footprint flags */
+#define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */
+#define HANF_FP_TRANSPOSE 2     /* include the transposed graph and the systolic signal buffers */
 
 typedef struct hanf_ctx hanf_ctx;
 
@@ -92,6 +102,9 @@ typedef struct {
   float finalize_ms;     /* multi-chunk combine kernel time, else 0 */
   float reduce_ms;       /* estimate reduction kernels time, else 0 */
   int32_t gather_all;    /* 1 if the pass maximised with every successor */
+  int32_t systolic;      /* 1 if only nodes signalled by a modified successor were recomputed */
+  int64_t arcs_signalled;/* systolic pass: predecessor arcs of the modified counters followed */
+  float signal_ms;       /* systolic signal kernels time (HANF_OPT_TIMING), else 0 */
 } hanf_pass_t;
 
 /* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work
@@ -114,6 +127,24 @@ int hanf_set_option(hanf_ctx *ctx, int option, int64_t value);
  * schedule on the device. Discards any previous run state. */
 int hanf_load_csr(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr,
                   const int32_t *col_idx, uint32_t flags);
+
+/* Transposed graph for systolic passes (Section 3.3, systolic computation: a modified
+ * counter signals the predecessors of its node). The predecessor lists of the loaded graph
+ * as CSR: row_ptr_t[n + 1], col_idx_t[arcs], where n and arcs must be the graph's
+ * (HANF_EINVAL otherwise); the order inside a list is free. With HANF_DEVICE_PTRS the
+ * arrays are borrowed and must outlive the context's use of this graph; for a symmetric
+ * graph the graph's own arrays may be passed. The CSR shape is checked on the device
+ * (HANF_EINVAL); that it is the transpose is the caller's guarantee (otherwise the results
+ * are undefined). Single graphs only. Call after hanf_load_csr and before
+ * hanf_init_counters (a run in progress must be initialised again). Replaced by the next
+ * graph ingest. */
+int hanf_load_transpose(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr_t,
+                        const int32_t *col_idx_t, uint32_t flags);
+
+/* Builds the transposed graph of the loaded graph (or batch) on the device: in-degree
+ * counts, their prefix sums, then the predecessor lists (4 (n + 1) + 4 arcs bytes, kept
+ * until the next graph ingest). Same call order as hanf_load_transpose. */
+int hanf_build_transpose(hanf_ctx *ctx);
 
 /* Counter initialisation (Algorithm 2: add v to c[v]; Algorithm 1 add). m = 2^log2m
  * registers per counter, 4 <= log2m <= 8. The item v is hashed with splitmix64:
@@ -167,10 +198,11 @@ int hanf_stats(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_s
 /* Per-pass records of the current run (one per executed pass). *len = passes so far. */
 int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *len);
 
-/* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers
- * (graph copy included when copy_graph = 1): two register arrays (the counters and the
- * update buffer, Section 3.2), the CSR, flags and estimate sums. Pure host function;
- * the memory figure of Section 3.4 (O(n m) register bytes) is its dominant term. */
+/* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers:
+ * two register arrays (the counters and the update buffer, Section 3.2), flags and estimate
+ * sums, plus the graph copy (HANF_FP_COPY_GRAPH in `copy_graph`) and the transposed graph
+ * with the systolic signal buffers (HANF_FP_TRANSPOSE). Pure host function; the memory
+ * figure of Section 3.4 (O(n m) register bytes) is its dominant term. */
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
 
 /* ---- Batched runs: many independent HyperANF runs in the same passes.

@@ -41,7 +41,11 @@ HANF_OPT_TIMING = 5
 HANF_OPT_BATCH = 6
 HANF_OPT_TILE_NODES = 7
 HANF_OPT_DENSE_SWITCH = 8
+HANF_OPT_SYSTOLIC = 9
+HANF_FP_COPY_GRAPH = 1
+HANF_FP_TRANSPOSE = 2
 HANF_OPT_UNROLL = 100
+HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
 
 ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
                HANF_ESTATE: "ESTATE", HANF_ERANGE: "ERANGE", HANF_EMAXITER: "EMAXITER"}
@@ -59,7 +63,9 @@ class hanf_pass_t(ctypes.Structure):
                 ("arcs_gathered", ctypes.c_int64), ("rows_written", ctypes.c_int64),
                 ("rows_read", ctypes.c_int64),
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
-                ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32)]
+                ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32),
+                ("systolic", ctypes.c_int32), ("arcs_signalled", ctypes.c_int64),
+                ("signal_ms", ctypes.c_float)]
 
 
 class HanfError(RuntimeError):
@@ -108,6 +114,8 @@ def lib():
             "hanf_destroy": ([vp], None),
             "hanf_set_option": ([vp, ctypes.c_int, i64], ctypes.c_int),
             "hanf_load_csr": ([vp, i32, i64, vp, vp, u32], ctypes.c_int),
+            "hanf_load_transpose": ([vp, i32, i64, vp, vp, u32], ctypes.c_int),
+            "hanf_build_transpose": ([vp], ctypes.c_int),
             "hanf_init_counters": ([vp, i32, u64], ctypes.c_int),
             "hanf_iterate": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_read_nt": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
@@ -196,6 +204,23 @@ def hanf_load_csr(ctx, row_ptr, col_idx):
     return (k1, k2)
 
 
+def hanf_load_transpose(ctx, row_ptr_t, col_idx_t):
+    """Predecessor lists of the loaded graph (CSR int32, numpy or device tensors; device
+    tensors are borrowed). Returns the objects to keep alive."""
+    p_rp, f1, k1 = _ptr(row_ptr_t, np.int32)
+    p_ci, f2, k2 = _ptr(col_idx_t, np.int32)
+    if f1 != f2:
+        raise ValueError("row_ptr_t and col_idx_t must both be host or both be device arrays")
+    n = (k1.numel() if _is_tensor(k1) else k1.size) - 1
+    arcs = k2.numel() if _is_tensor(k2) else k2.size
+    _check(lib().hanf_load_transpose(ctx, n, arcs, p_rp, p_ci if arcs > 0 else None, f1), ctx)
+    return (k1, k2)
+
+
+def hanf_build_transpose(ctx) -> None:
+    _check(lib().hanf_build_transpose(ctx), ctx)
+
+
 def hanf_init_counters(ctx, log2m: int, seed: int) -> None:
     _check(lib().hanf_init_counters(ctx, log2m, seed & 0xFFFFFFFFFFFFFFFF), ctx)
 
@@ -268,9 +293,10 @@ def hanf_read_pass_log(ctx) -> list[dict]:
             for i in range(n.value)]
 
 
-def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True) -> int:
+def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True, transpose: bool = False) -> int:
     out = ctypes.c_int64()
-    _check(lib().hanf_footprint(n, arcs, log2m, int(copy_graph), ctypes.byref(out)))
+    flags = (HANF_FP_COPY_GRAPH if copy_graph else 0) | (HANF_FP_TRANSPOSE if transpose else 0)
+    _check(lib().hanf_footprint(n, arcs, log2m, flags, ctypes.byref(out)))
     return out.value
 
 
@@ -370,7 +396,8 @@ class HyperANF:
                  "light_max": HANF_OPT_LIGHT_MAX, "chunk_arcs": HANF_OPT_CHUNK_ARCS,
                  "timing": HANF_OPT_TIMING, "batch": HANF_OPT_BATCH,
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
-                 "dense_switch": HANF_OPT_DENSE_SWITCH}
+                 "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
+                 "union_policy": HANF_OPT_UNION_POLICY}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))
 
@@ -395,6 +422,17 @@ class HyperANF:
         self._keep = hanf_load_csr(self.ctx, row_ptr, col_idx)
         k = self._keep[0]
         self.n = (k.numel() if _is_tensor(k) else k.size) - 1
+        return self
+
+    def load_transpose(self, row_ptr_t, col_idx_t):
+        """The graph's predecessor lists, for systolic passes; for a symmetric graph loaded
+        from device tensors, pass the same tensors."""
+        self._keep_t = hanf_load_transpose(self.ctx, row_ptr_t, col_idx_t)
+        return self
+
+    def build_transpose(self):
+        """Builds the predecessor lists on the device, for systolic passes."""
+        hanf_build_transpose(self.ctx)
         return self
 
     def init(self, log2m: int, seed: int):

@@ -41,6 +41,8 @@ struct Schedule {
   Heavy *heavy = nullptr;
   uint8_t *partial = nullptr;
   uint8_t *partial_any = nullptr;
+  uint8_t *tile_todo = nullptr;   // systolic flags of the light tiles
+  int32_t *unit_list = nullptr;   // systolic work units
   int64_t *stat_slots = nullptr;  // kStatSlots x 4 work counters
 };
 
@@ -64,6 +66,9 @@ struct hanf_ctx {
   int dense_div = 4;  // a pass after one that changed >= n/dense_div counters maximises with all successors
   int passes_per_check = 4;
   int unroll = 4;
+  int sys_div = 4;    // a pass after one that changed < n/sys_div counters is systolic (0 = never)
+  int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
+  bool sys_seen = false; // the last state read showed a systolic next pass
 
   // graph
   int32_t n = 0;
@@ -71,6 +76,9 @@ struct hanf_ctx {
   const int32_t *rp = nullptr, *ci = nullptr;
   int32_t *rp_own = nullptr, *ci_own = nullptr;
   bool graph_ok = false;
+  // transposed graph (systolic passes): owned, or the caller's device arrays
+  const int32_t *trp = nullptr, *tci = nullptr;
+  int32_t *trp_own = nullptr, *tci_own = nullptr;
 
   Schedule sch;
 
@@ -89,6 +97,8 @@ struct hanf_ctx {
   bool inited = false;
   uint8_t *regs[2] = {nullptr, nullptr};
   uint32_t *bits[2] = {nullptr, nullptr};
+  uint8_t *todo = nullptr;                             // systolic signals, one byte per node
+  int32_t *sys_node = nullptr, *sys_pos = nullptr;     // systolic signal list
   double *est = nullptr, *blocksum = nullptr, *wgsum = nullptr, *lc = nullptr, *nt = nullptr;
   double *stats_out = nullptr;
   int64_t *wgcnt = nullptr;
@@ -199,6 +209,8 @@ void free_schedule(hanf_ctx *c) {
   dev_release(c, s.heavy);
   dev_release(c, s.partial);
   dev_release(c, s.partial_any);
+  dev_release(c, s.tile_todo);
+  dev_release(c, s.unit_list);
   dev_release(c, s.stat_slots);
   s = Schedule();
 }
@@ -220,11 +232,21 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->blkcnt);
   dev_release(c, c->comp_T);
   dev_release(c, c->comp_nt);
+  dev_release(c, c->todo);
+  dev_release(c, c->sys_node);
+  dev_release(c, c->sys_pos);
   c->inited = false;
   c->log2m = 0;
 }
 
+void free_transpose(hanf_ctx *c) {
+  dev_release(c, c->trp_own);
+  dev_release(c, c->tci_own);
+  c->trp = c->tci = nullptr;
+}
+
 void free_graph(hanf_ctx *c) {
+  free_transpose(c);
   dev_release(c, c->rp_own);
   dev_release(c, c->ci_own);
   dev_release(c, c->blk_comp);
@@ -317,7 +339,10 @@ int build_schedule(hanf_ctx *c, int G) {
   s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
   s.n_light_wgs = (s.n_tiles + 3) / 4;
   s.n_fin_wgs = (s.n_heavy + 3) / 4;
-  if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * 4, "work counters"))) return rc;
+  if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * 4, "work counters")) ||
+      (rc = dev_alloc(c, &s.tile_todo, ((size_t)s.n_tiles + 3) / 4 * 4, "tile flags")) ||
+      (rc = dev_alloc(c, &s.unit_list, (size_t)s.n_chunks + s.n_tiles, "work unit list")))
+    return rc;
   return HANF_OK;
 }
 
@@ -339,6 +364,14 @@ void fill_args(hanf_ctx *c) {
   a.heavy = c->sch.heavy;
   a.partial = c->sch.partial;
   a.partial_any = c->sch.partial_any;
+  a.tile_todo = c->sch.tile_todo;
+  a.unit_list = c->sch.unit_list;
+  const bool sys = c->trp && c->todo;
+  a.trow_ptr = sys ? c->trp : nullptr;
+  a.tcol_idx = sys ? c->tci : nullptr;
+  a.todo = c->todo;
+  a.sys_node = c->sys_node;
+  a.sys_pos = c->sys_pos;
   a.st = c->st;
   a.nt = c->nt;
   a.log = c->log;
@@ -358,6 +391,7 @@ void fill_args(hanf_ctx *c) {
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;
   a.nt_cap = c->nt_cap;
+  a.arcs = c->arcs;
   a.batch.active = c->batch ? 1 : 0;
   a.batch.n_comp = c->n_comp;
   a.batch.blk_comp = c->blk_comp;
@@ -422,15 +456,28 @@ int64_t dense_threshold(const hanf_ctx *c) {
   return std::max<int64_t>(1, (int64_t)c->n / c->dense_div);
 }
 
+// Systolic passes need the transposed graph and the signal buffers of the run.
+int32_t systolic_div(const hanf_ctx *c) { return (c->args.trow_ptr && c->frontier) ? c->sys_div : 0; }
+
+constexpr int kPassEvents = 5;
+
 int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   hipStream_t s = c->stream;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
-  HIP_TRY(c, launch_union(c->args, c->unroll, s), "union kernel");
+  HIP_TRY(c, launch_signal(c->args, c->arcs, s), "signal kernels");
   if (ev) HIP_TRY(c, hipEventRecord(ev[1], s), "event");
-  HIP_TRY(c, launch_finalize(c->args, s), "finalize kernel");
+  // The per-unit kernel is skipped once the last state read showed systolic passes (the
+  // persistent kernel then runs every pass, whatever its kind); otherwise both are launched
+  // and each leaves the passes that are not its own.
+  const bool has_sys = c->args.trow_ptr != nullptr;
+  const int list = c->union_policy == 2 || (c->union_policy == 0 && has_sys);
+  const int full = c->union_policy == 1 || (c->union_policy == 0 && !(has_sys && c->sys_seen));
+  HIP_TRY(c, launch_union(c->args, c->unroll, full, list, s), "union kernel");
   if (ev) HIP_TRY(c, hipEventRecord(ev[2], s), "event");
-  HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s), "reduce kernels");
+  HIP_TRY(c, launch_finalize(c->args, s), "finalize kernel");
   if (ev) HIP_TRY(c, hipEventRecord(ev[3], s), "event");
+  HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s), "reduce kernels");
+  if (ev) HIP_TRY(c, hipEventRecord(ev[4], s), "event");
   return HANF_OK;
 }
 
@@ -533,6 +580,14 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < 0 || value > (1 << 30)) return fail(c, HANF_EINVAL, "dense switch out of range");
       c->dense_div = (int)value;
       break;
+    case HANF_OPT_SYSTOLIC:
+      if (value < 0 || value > (1 << 30)) return fail(c, HANF_EINVAL, "systolic switch out of range");
+      c->sys_div = (int)value;
+      break;
+    case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
+      if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
+      c->union_policy = (int)value;
+      break;
     case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
       if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
       c->unroll = (int)value;
@@ -584,7 +639,7 @@ int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, 
   }
   c->n = n;
   c->arcs = arcs;
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream), "state reset");
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream), "state reset");
   HIP_TRY(c, launch_validate(c->rp, c->ci, n, arcs, c->st, c->stream), "validate");
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) {
@@ -598,6 +653,96 @@ int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, 
     return fail(c, HANF_EINVAL, msg);
   }
   c->graph_ok = true;
+  return HANF_OK;
+}
+
+int hanf_load_transpose(hanf_ctx *c, int32_t n_t, int64_t arcs_t, const int32_t *row_ptr_t, const int32_t *col_idx_t,
+                        uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_transpose: NULL context");
+  if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
+  if (c->batch) return fail(c, HANF_EINVAL, "batched graph: use hanf_build_transpose");
+  if (n_t != c->n || arcs_t != c->arcs)
+    return fail(c, HANF_EINVAL, "the transposed graph must have the graph's n and arcs");
+  if (!row_ptr_t || (c->arcs > 0 && !col_idx_t)) return fail(c, HANF_EINVAL, "NULL CSR array");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_transpose(c);
+  c->inited = false;  // the signal buffers are sized at the next initialisation
+  const int32_t n = c->n;
+  const int64_t arcs = c->arcs;
+  int rc;
+  if (flags == HANF_DEVICE_PTRS) {
+    for (const void *p : {(const void *)row_ptr_t, (const void *)col_idx_t}) {
+      if (!p) continue;
+      hipPointerAttribute_t attr;
+      hipError_t e = hipPointerGetAttributes(&attr, p);
+      if (e != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != c->device) {
+        (void)hipGetLastError();
+        return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: pointer is not device memory of this device");
+      }
+    }
+    c->trp = row_ptr_t;
+    c->tci = arcs > 0 ? col_idx_t : nullptr;
+  } else {
+    if ((rc = dev_alloc(c, &c->trp_own, (size_t)n + 1, "transposed row_ptr")) ||
+        (rc = dev_alloc(c, &c->tci_own, (size_t)arcs, "transposed col_idx"))) {
+      free_transpose(c);
+      return rc;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->trp_own, row_ptr_t, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice,
+                              c->stream),
+            "transposed row_ptr upload");
+    if (arcs > 0)
+      HIP_TRY(c, hipMemcpyAsync(c->tci_own, col_idx_t, sizeof(int32_t) * (size_t)arcs, hipMemcpyHostToDevice,
+                                c->stream),
+              "transposed col_idx upload");
+    c->trp = c->trp_own;
+    c->tci = c->tci_own;
+  }
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream), "state reset");
+  HIP_TRY(c, launch_validate(c->trp, c->tci, n, arcs, c->st, c->stream), "validate");
+  if ((rc = read_state(c))) return rc;
+  if (c->st_host->err) {
+    free_transpose(c);
+    return fail(c, HANF_EINVAL, "malformed transposed CSR (it must have the graph's n and arcs)");
+  }
+  return HANF_OK;
+}
+
+int hanf_build_transpose(hanf_ctx *c) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_build_transpose: NULL context");
+  if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_transpose(c);
+  c->inited = false;
+  const int32_t n = c->n;
+  const int64_t arcs = c->arcs;
+  uint64_t *keys = nullptr, *tmp = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &c->trp_own, (size_t)n + 1, "transposed row_ptr")) ||
+      (rc = dev_alloc(c, &c->tci_own, (size_t)arcs, "transposed col_idx")) ||
+      (rc = dev_alloc(c, &keys, (size_t)n + 1, "in-degrees")) ||
+      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
+    dev_release(c, keys);
+    dev_release(c, tmp);
+    free_transpose(c);
+    return rc;
+  }
+  hipError_t e = launch_fill_u64(keys, (int64_t)n + 1, 0ull, c->stream);
+  if (e == hipSuccess) e = launch_transpose_count(c->ci, arcs, keys, c->stream);
+  if (e == hipSuccess) e = launch_exclusive_scan_u64(keys, (int64_t)n + 1, tmp, c->stream);
+  if (e == hipSuccess) e = launch_transpose_fill(c->rp, c->ci, n, keys, c->trp_own, c->tci_own, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_release(c, keys);
+  dev_release(c, tmp);
+  if (e != hipSuccess) {
+    free_transpose(c);
+    return hip_fail(c, e, "transpose");
+  }
+  c->trp = c->trp_own;
+  c->tci = c->tci_own;
   return HANF_OK;
 }
 
@@ -621,13 +766,23 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (c->log2m != log2m || !c->regs[0] || want_cap != c->nt_cap) {
     if ((rc = alloc_run(c, log2m))) return rc;
   }
+  if (c->trp && !c->todo) {  // signal buffers for systolic passes
+    if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals")) ||
+        (rc = dev_alloc(c, &c->sys_node, (size_t)c->n, "systolic list")) ||
+        (rc = dev_alloc(c, &c->sys_pos, (size_t)c->n, "systolic list"))) {
+      free_run(c);
+      return rc;
+    }
+  }
   c->inited = false;
+  c->sys_seen = false;
   fill_args(c);
   c->host_log.clear();
   if (seeds)
     HIP_TRY(c, hipMemcpyAsync(c->comp_seed, seeds, sizeof(uint64_t) * c->n_comp, hipMemcpyHostToDevice, c->stream),
             "seed upload");
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, dense_threshold(c), c->stream),
+  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
+                                c->stream),
           "state reset");
   HIP_TRY(c, launch_init(c->args, seed, c->stream), "init kernel");
   HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
@@ -664,6 +819,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
   std::vector<hipEvent_t> ev;
   for (;;) {
     DevState s0 = *c->st_host;
+    c->sys_seen = s0.systolic != 0;
     if (changed_last) *changed_last = s0.changed_last;
     if (s0.done) {
       if (steps_done) *steps_done = steps;
@@ -677,12 +833,12 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
     int B = c->passes_per_check;
     if (max_steps > 0) B = std::min(B, max_steps - steps);
     if (c->timing) {
-      ev.resize((size_t)B * 4);
+      ev.resize((size_t)B * kPassEvents);
       for (auto &x : ev)
         if (hipEventCreate(&x) != hipSuccess) return fail(c, HANF_EDEVICE, "event create");
     }
     for (int i = 0; i < B; ++i) {
-      rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * 4] : nullptr);
+      rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * kPassEvents] : nullptr);
       if (rc) return rc;
     }
     if ((rc = read_state(c))) return rc;
@@ -701,11 +857,14 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.rows_written = recs[i].written;
         r.rows_read = recs[i].read;
         r.gather_all = (int32_t)recs[i].gather_all;
+        r.systolic = (int32_t)recs[i].systolic;
+        r.arcs_signalled = recs[i].signalled;
         if (c->timing) {
-          hipEvent_t *e = &ev[(size_t)i * 4];
-          (void)hipEventElapsedTime(&r.union_ms, e[0], e[1]);
-          (void)hipEventElapsedTime(&r.finalize_ms, e[1], e[2]);
-          (void)hipEventElapsedTime(&r.reduce_ms, e[2], e[3]);
+          hipEvent_t *e = &ev[(size_t)i * kPassEvents];
+          (void)hipEventElapsedTime(&r.signal_ms, e[0], e[1]);
+          (void)hipEventElapsedTime(&r.union_ms, e[1], e[2]);
+          (void)hipEventElapsedTime(&r.finalize_ms, e[2], e[3]);
+          (void)hipEventElapsedTime(&r.reduce_ms, e[3], e[4]);
         }
         c->host_log.push_back(r);
       }
@@ -749,6 +908,7 @@ int hanf_poll(hanf_ctx *c, int32_t *t) {
   if (e != hipSuccess) return hip_fail(c, e, "poll");
   c->poll_pending = false;
   const DevState s0 = *c->st_poll;
+  c->sys_seen = s0.systolic != 0;
   if (t) *t = s0.t;
   if (s0.done) return HANF_DONE;
   if (s0.capped) return fail(c, HANF_EMAXITER, "pass cap reached before the fixpoint");
@@ -797,7 +957,9 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   c->inited = false;
-  HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), c->stream),
+  c->sys_seen = false;
+  HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
+                                c->stream),
           "state reset");
   HIP_TRY(c, hipMemcpyAsync(c->regs[t & 1], in, (size_t)bytes, kind, c->stream), "register upload");
   HIP_TRY(c, launch_check_registers(c->regs[t & 1], bytes, c->st, c->stream), "register check");
@@ -865,7 +1027,11 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
   b += (int64_t)n * 4 + 4096;                            // light tiles
   b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)
-  if (copy_graph) b += ((int64_t)n + 1) * 4 + arcs * 4;
+  if (copy_graph & HANF_FP_COPY_GRAPH) b += ((int64_t)n + 1) * 4 + arcs * 4;
+  if (copy_graph & HANF_FP_TRANSPOSE) {
+    b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
+    b += blocks * kNodesPerBlock + (int64_t)n * 8;  // signals and signal list
+  }
   *bytes = b;
   return HANF_OK;
 }
@@ -958,7 +1124,7 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream);
+  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
   if (e == hipSuccess) e = launch_validate(d_rp, d_ci, N, arcs, c->st, c->stream);
   if (e == hipSuccess) e = launch_check_offsets(d_rp, d_goff, d_gaoff, n_graphs, c->st, c->stream);
   c->batch = true;
@@ -1079,7 +1245,7 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, c->stream);
+  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
   c->batch = true;
   c->n_graphs = n_graphs;
   c->n_seeds = n_seeds;

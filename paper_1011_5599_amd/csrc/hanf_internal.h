@@ -12,7 +12,7 @@ constexpr int kBlockThreads = 256; // 4 wavefronts per workgroup
 constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 consecutive nodes
 constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
-constexpr int kReduceBlocks = 16;  // 64-node blocks per reduction workgroup
+constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
@@ -30,12 +30,18 @@ struct DevState {
   int32_t err;        // validation error bits
   int32_t dense_next; // 1: the next pass maximises with every successor (the previous pass
                       // changed at least dense_threshold counters)
+  int32_t systolic;   // 1: this pass only recomputes nodes signalled through the transposed
+                      // graph (the previous pass changed fewer than n / sys_div counters)
+  int32_t sys_div;    // 0 = never systolic
   int64_t changed_last;
   int64_t dense_threshold;  // 0 = never
+  uint64_t sys_acc;   // systolic pass: (signalling nodes << 32) | their predecessor arcs
+  int32_t sys_units;  // systolic pass: work units listed for the union kernel
+  int32_t pad_;
 };
 
 struct PassLog {  // per executed pass, filled on the device
-  int64_t changed, scanned, gathered, written, read, gather_all;
+  int64_t changed, scanned, gathered, written, read, gather_all, systolic, signalled;
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
@@ -78,6 +84,14 @@ struct PassArgs {
   const Heavy *heavy;
   uint8_t *partial;          // m bytes per chunk of a multi-chunk node
   uint8_t *partial_any;      // 1 if the chunk maximised at least one successor
+  const int32_t *trow_ptr;   // transposed graph (predecessor lists), systolic passes only
+  const int32_t *tcol_idx;
+  uint8_t *todo;             // systolic pass: 1 for nodes with a successor modified by the previous
+                             //   pass (one byte per node, 64 per block: set with plain stores)
+  uint8_t *tile_todo;        // systolic pass: 1 for light tiles holding such a node
+  int32_t *unit_list;        // systolic pass: work units with something to do (chunks, then tiles)
+  int32_t *sys_node;         // systolic pass: modified nodes with predecessors ...
+  int32_t *sys_pos;          //   ... and the offset of their predecessor arcs in the signal list
   DevState *st;
   double *nt;                // N_hat history
   PassLog *log;
@@ -96,6 +110,7 @@ struct PassArgs {
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;
   int32_t nt_cap;
+  int64_t arcs;
   BatchArgs batch;
 };
 
@@ -103,7 +118,7 @@ struct PassArgs {
 hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int64_t arcs,
                            DevState *st, hipStream_t s);
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
-                              int64_t dense_threshold, hipStream_t s);
+                              int64_t dense_threshold, int32_t sys_div, hipStream_t s);
 hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
                            uint64_t *keys, hipStream_t s);
 // exclusive scan of n uint64 values in place; `tmp` needs scan_tmp_elems(n) elements
@@ -115,7 +130,16 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
                               int32_t n_tiles, int32_t *light, hipStream_t s);
 hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s);
-hipError_t launch_union(const PassArgs &a, int u, hipStream_t s);
+hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s);
+// full: the kernel with one wavefront per work unit; list: the persistent kernel, which
+// runs the systolic passes when both are launched and every pass when it runs alone
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s);
+// transposed graph: in-degree counts into keys (n + 1 zeroed uint64), then, after their
+// exclusive scan, the predecessor lists (keys are consumed as fill cursors)
+hipError_t launch_transpose_count(const int32_t *col_idx, int64_t arcs, uint64_t *keys, hipStream_t s);
+hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, uint64_t *keys,
+                                 int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,

@@ -111,6 +111,8 @@ struct Flags {
   uint32_t *cur_bits;         // counters modified by this pass
   bool gather_all;            // maximise with every successor (first pass, or frontier off)
   bool copy_check;            // next[v] may hold c_{t-1}[v] != c_t[v]: copy when v was modified
+  bool systolic;              // only nodes in `todo` (signalled by a modified successor) may change
+  const uint8_t *todo;
 };
 
 __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *st) {
@@ -123,6 +125,8 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *s
   f.cur_bits = odd ? a.bits0 : a.bits1;
   f.gather_all = first || !st->frontier || st->dense_next;
   f.copy_check = !first;
+  f.systolic = !f.gather_all && st->systolic;
+  f.todo = a.todo;
   return f;
 }
 
@@ -169,9 +173,9 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
 // G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
 // in (all of them, or those modified by the previous pass), compact the kept ids into the
 // slot's queue in LDS and gather the queued counters U at a time.
-template <int G, int U, bool CountScan>
+template <int G, int U>
 __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
-                                            int32_t *queue, Counters &cnt) {
+                                            int32_t *queue, Counters &cnt, bool count_scan) {
   constexpr int m = 16 * G;
   const int sub = lane % G;
   const int first = lane & ~(G - 1);
@@ -221,7 +225,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
       for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
     }
     gathered += total;
-    if (CountScan && sub == 0) cnt.scanned += min(G * U, end - p);
+    if (count_scan && sub == 0) cnt.scanned += min(G * U, end - p);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -249,7 +253,8 @@ __device__ __forceinline__ void combine_slots(uint4 &acc, bool &any) {
 // tests each successor's modified flag, and only a lane that hits one looks up its source
 // node (binary search over the sub-round's 65 row pointers in LDS). The active nodes are
 // then compacted into `act` in the tile's degree order. Returns their number
-// (wavefront-uniform). `rps` holds 65 ints of LDS per wavefront.
+// (wavefront-uniform). `rps` holds 65 ints of LDS per wavefront. In a systolic pass the
+// nodes with a modified successor are already marked in `todo`, and no arc is read here.
 template <int U>
 __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f, const int32_t *tl, int32_t tile,
                                                int32_t light_max, int lane, int32_t *rps, int32_t *act,
@@ -270,12 +275,13 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
     if (lane == cnt_nodes - 1) rps[cnt_nodes] = r1;
     const int32_t deg = r1 - r0;
     const bool heavy = valid && deg > light_max;
-    bool act = valid && deg > 0 && !heavy && testbit(f.prev_bits, v);
+    bool act = valid && deg > 0 && !heavy &&
+               (testbit(f.prev_bits, v) || (f.systolic && f.todo[v] != 0));
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const uint64_t hmask = __ballot(heavy);
     uint64_t hit = 0ull;  // nodes (lanes) with a modified successor; the same value in every lane
-    int32_t j0 = 0;
+    int32_t j0 = f.systolic ? cnt_nodes : 0;  // systolic: `todo` already names them
     while (j0 < cnt_nodes) {
       const uint64_t rest = hmask >> j0;
       const int32_t j1 = rest ? j0 + __ffsll((long long)rest) - 1 : cnt_nodes;  // light run [j0, j1)
@@ -359,15 +365,18 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   const int slot = lane / G, sub = lane % G;
   const uint64_t below = (1ull << lane) - 1ull;
   const Chunk ch = a.chunks[c];
+  // systolic pass: a node no modified successor signalled keeps its counter (its arcs are
+  // not read; the copy rule below still applies)
+  const int32_t a1 = (f.systolic && f.todo[ch.v] == 0) ? ch.a0 : ch.a1;
   uint4 acc = zero4();
   int32_t gathered = 0;
-  for (int32_t base = ch.a0; base < ch.a1; base += kWave * U) {
+  for (int32_t base = ch.a0; base < a1; base += kWave * U) {
     int32_t w[U];
     bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const int32_t p = base + k * kWave + lane;
-      ok[k] = p < ch.a1;
+      ok[k] = p < a1;
       w[k] = ok[k] ? a.col_idx[p] : 0;
     }
     if (!f.gather_all) {
@@ -398,7 +407,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     __builtin_amdgcn_wave_barrier();
   }
   if (lane == 0) {
-    cnt.scanned += ch.a1 - ch.a0;
+    cnt.scanned += a1 - ch.a0;
     cnt.gathered += gathered;
   }
   bool any = gathered > 0;  // wavefront-uniform
@@ -450,11 +459,38 @@ __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *s
 
 // ------------------------------------------------------------------ kernels: one pass
 
+// One light tile handled by one wavefront: every node when the pass maximises with all
+// successors, else the active nodes found by find_active, W nodes per round.
 template <int G, int U>
-__global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
+__device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int lane, int32_t *qw,
+                                             int32_t *act, int32_t *rps, Counters &cnt) {
+  constexpr int W = kWave / G;
+  const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
+  const int slot = lane / G;
+  const int32_t *list = tl;
+  int32_t count = a.tile_nodes;
+  if (!f.gather_all) {
+    count = find_active<U>(a, f, tl, tile, a.light_max, lane, rps, act, cnt);
+    list = act;
+  }
+  // arcs read here are counted unless find_active already scanned them
+  const bool count_scan = f.gather_all || f.systolic;
+  for (int32_t r = 0; r < count; r += W) {
+    const int32_t v = r + slot < count ? list[r + slot] : -1;
+    if (!__any(v >= 0)) break;  // empty tile entries sort last
+    light_round<G, U>(a, f, v, lane, qw, cnt, count_scan);
+  }
+}
+
+// The union step of one pass (Algorithm 2), one work unit per wavefront: workgroups below
+// n_chunk_wgs take 4 chunks each, the others 4 light tiles (XCD-aware order). With
+// `list_too` set, k_union_list runs the systolic passes and this kernel leaves at once.
+template <int G, int U>
+__global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t list_too) {
   const DevState *st = a.st;
   if (st->halted) return;
   const Flags f = make_flags(a, st);
+  if (list_too && f.systolic) return;
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
   __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
@@ -465,29 +501,40 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a) {
     const int32_t c = (int32_t)blockIdx.x * 4 + wave;
     if (c < a.n_chunks) chunk_wave<G, U>(a, f, c, lane, qw, cnt);
   } else {
-    constexpr int W = kWave / G;
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
-    if (tile < a.n_tiles) {
-      const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
-      const int slot = lane / G;
-      if (f.gather_all) {
-        const int rounds = a.tile_nodes / W;
-        for (int r = 0; r < rounds; ++r) {
-          const int32_t v = tl[r * W + slot];
-          if (!__any(v >= 0)) break;  // empty entries sort last
-          light_round<G, U, true>(a, f, v, lane, qw, cnt);
-        }
-      } else {
-        int32_t *act = act_buf + wave * kMaxTile;
-        const int32_t n_act =
-            find_active<U>(a, f, tl, tile, a.light_max, lane, rp_buf + wave * (kWave + 1), act, cnt);
-        for (int32_t r = 0; r < n_act; r += W) {
-          const int32_t v = r + slot < n_act ? act[r + slot] : -1;
-          light_round<G, U, false>(a, f, v, lane, qw, cnt);
-        }
-      }
-    }
+    if (tile < a.n_tiles)
+      process_tile<G, U>(a, f, tile, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1), cnt);
+  }
+  add_block_counters(cnt, a.stat_slots);
+}
+
+// The union step from a persistent grid (kListWgs workgroups): in a systolic pass over the
+// work units k_sys_units listed, else over every unit (chunks, then light tiles), one unit
+// per wavefront at a time. With `full_too` set, k_union runs the other passes and this
+// kernel leaves at once. Its grid is far smaller than one wavefront per unit, so a pass in
+// which few nodes are active costs few launches.
+template <int G, int U>
+__global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_t full_too) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st);
+  if (full_too && !f.systolic) return;
+  Counters cnt;
+  __shared__ int32_t queue[kBlockThreads * U];
+  __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
+  __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int32_t *qw = queue + wave * kWave * U;
+  const int64_t total = f.systolic ? (int64_t)st->sys_units : (int64_t)a.n_chunks + a.n_tiles;
+  const int64_t stride = (int64_t)gridDim.x * (kBlockThreads / kWave);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave; i < total; i += stride) {
+    const int32_t u = f.systolic ? a.unit_list[i] : (int32_t)i;
+    if (u < a.n_chunks)
+      chunk_wave<G, U>(a, f, u, lane, qw, cnt);
+    else
+      process_tile<G, U>(a, f, u - a.n_chunks, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1),
+                         cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
@@ -508,7 +555,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     const Heavy hv = a.heavy[h];
     uint4 acc = zero4();
     bool any = false;
-    for (int32_t j = slot; j < hv.count; j += W) {
+    // systolic pass: the chunks of an unsignalled node gathered nothing (they may have been
+    // skipped without clearing their flags)
+    const int32_t count = (f.systolic && f.todo[hv.v] == 0) ? 0 : hv.count;
+    for (int32_t j = slot; j < count; j += W) {
       if (a.partial_any[hv.first + j]) {
         acc = bytemax4(acc, ldrow(a.partial, hv.first + j, m, sub));
         any = true;
@@ -520,9 +570,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
   add_block_counters(cnt, a.stat_slots);
 }
 
-// Per 64-node block: re-sum the estimates where a counter changed (else reuse the cached
-// sum, Section 3.3), count changed counters, clear the flags of the previous pass. Each
-// workgroup covers kReduceBlocks consecutive blocks (4 per wavefront), summed in order.
+// Per 64-node block, one lane each: re-sum the estimates where a counter changed (else
+// reuse the cached sum, Section 3.3), count changed counters, clear the flags of the
+// previous pass (and the signals of a systolic pass). A workgroup covers kReduceBlocks
+// consecutive blocks, a quarter per wavefront; sums are taken in a fixed order.
 __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int32_t force) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -532,36 +583,54 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   const int32_t t = st->t;
   const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
   uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
-  double wsum = 0.0;
-  int32_t cnt = 0;
-  for (int j = 0; j < kReduceBlocks / 4; ++j) {
-    const int32_t b = (int32_t)blockIdx.x * kReduceBlocks + wave * (kReduceBlocks / 4) + j;
-    if (b >= a.n_blocks) break;
-    uint32_t w0 = 0, w1 = 0;
-    if (!force) {
-      w0 = cb[2 * b];
-      w1 = cb[2 * b + 1];
+  const bool sys = st->systolic != 0;  // this pass's signals are cleared with its flags
+  constexpr int kPerWave = kReduceBlocks / (kBlockThreads / kWave);  // blocks per wavefront
+  const int64_t b0 = (int64_t)blockIdx.x * kReduceBlocks + wave * kPerWave;  // the wavefront's first block
+  const int64_t b = b0 + lane;
+  const bool valid = lane < kPerWave && b < a.n_blocks;
+  uint2 w = make_uint2(0u, 0u);
+  if (valid && !force) w = reinterpret_cast<const uint2 *>(cb)[b];
+  const bool dirty = valid && (force || (w.x | w.y));
+  double bs = (valid && !dirty) ? a.blocksum[b] : 0.0;
+  // the dirty blocks of the wavefront, 4 at a time: 64 estimates each, summed across lanes
+  uint64_t pend = __ballot(dirty);
+  while (pend) {
+    int32_t jb[4];
+    double e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      jb[k] = pend ? __ffsll((long long)pend) - 1 : -1;
+      if (pend) pend &= pend - 1;
     }
-    double bs;
-    if (force || (w0 | w1)) {
-      const int32_t v = b * kNodesPerBlock + lane;
-      bs = wave_sum(v < a.n ? a.est[v] : 0.0);
-      if (lane == 0) a.blocksum[b] = bs;
-    } else {
-      bs = a.blocksum[b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t v = (b0 + jb[k]) * kNodesPerBlock + lane;
+      e[k] = (jb[k] >= 0 && v < a.n) ? a.est[v] : 0.0;
     }
-    wsum += bs;
-    const int32_t bc = __popc(w0) + __popc(w1);
-    cnt += bc;
-    if (a.batch.active && lane == 0) a.batch.blkcnt[b] = bc;
-    if (!force && lane == 0) {
-      pb[2 * b] = 0u;
-      pb[2 * b + 1] = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (jb[k] >= 0) {  // wavefront-uniform
+        const double sum = wave_sum(e[k]);
+        if (lane == jb[k]) {
+          bs = sum;
+          a.blocksum[b] = sum;
+        }
+      }
     }
   }
+  const int32_t bc = __popc(w.x) + __popc(w.y);
+  if (valid && a.batch.active) a.batch.blkcnt[b] = bc;
+  if (valid && !force) reinterpret_cast<uint2 *>(pb)[b] = make_uint2(0u, 0u);
+  if (valid && sys) {
+    uint4 *tq = reinterpret_cast<uint4 *>(a.todo + b * kNodesPerBlock);
+#pragma unroll
+    for (int k = 0; k < kNodesPerBlock / 16; ++k) tq[k] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  const double ws = wave_sum(bs);
+  const int32_t wc = wave_sum(bc);
   if (lane == 0) {
-    s_sum[wave] = wsum;
-    s_cnt[wave] = cnt;
+    s_sum[wave] = ws;
+    s_cnt[wave] = wc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -761,11 +830,19 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       rec.gathered = s_i[2][0];
       rec.written = s_i[3][0];
       rec.read = s_i[4][0];
+      rec.systolic = st->systolic;
+      rec.signalled = rec.systolic ? (int64_t)(st->sys_acc & 0xffffffffull) : 0;
       if (p < a.nt_cap) a.log[p] = rec;
       st->passes = p + 1;
       st->changed_last = rec.changed;
       st->first_pass = 0;
       st->dense_next = (st->dense_threshold > 0 && rec.changed >= st->dense_threshold) ? 1 : 0;
+      // Section 3.3, systolic computation: once fewer than n / sys_div counters changed, the
+      // next pass recomputes only the nodes their changes signal
+      st->systolic = (!st->dense_next && st->frontier && st->sys_div > 0 &&
+                      rec.changed * (int64_t)st->sys_div < (int64_t)a.n) ? 1 : 0;
+      st->sys_acc = 0ull;
+      st->sys_units = 0;
       if (rec.changed == 0) {
         st->done = 1;
         st->halted = 1;
@@ -781,6 +858,265 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   }
 }
 
+// ------------------------------------------------------------------ kernels: systolic signals
+
+// Section 3.3, systolic computation. A counter modified by pass t-1 signals its predecessors
+// (its arcs in the transposed graph) that they may change in pass t; pass t then recomputes
+// only signalled nodes. Three kernels run before the union step of a systolic pass:
+// k_sys_list lists the modified nodes that have predecessors, each with the offset of its
+// predecessor arcs in one virtual array of all of them (each workgroup reserves its list
+// entries and arc offsets together with one 64-bit atomic, so offsets increase along the
+// list); k_sys_mark walks that virtual array in fixed tiles of kMarkTile arcs, whatever the
+// in-degrees, and marks every predecessor; k_sys_units lists the work units (chunks, light
+// tiles) that hold a marked or modified node.
+constexpr int kMarkTile = 1024;
+constexpr int kListWgs = 2048;  // persistent union grid: 8 workgroups per compute unit
+constexpr int kSigRounds = 4;   // items per thread in the signal compaction kernels
+constexpr int kSysArcDiv = 16;  // a systolic pass that would signal more than arcs/16 arcs falls
+                                // back to testing every arc's flag (cheaper at that density)
+
+// Inclusive scan across the wavefront of a 64-bit value (two 32-bit shuffles per step).
+__device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long x, int lane) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint32_t lo = __shfl_up((uint32_t)(x & 0xffffffffull), off);
+    const uint32_t hi = __shfl_up((uint32_t)(x >> 32), off);
+    if (lane >= off) x += ((unsigned long long)hi << 32) | lo;
+  }
+  return x;
+}
+
+// Each workgroup takes kSigRounds * 256 consecutive items, one per thread and round, and
+// reserves room for all its results with one atomic (positions in the list follow the
+// item order inside the workgroup).
+__global__ __launch_bounds__(kBlockThreads) void k_sys_list(PassArgs a) {
+  DevState *st = a.st;
+  if (st->halted || !st->systolic) return;
+  const int32_t t = st->t;
+  const uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;  // counters modified by pass t-1
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kBlockThreads / kWave;
+  __shared__ unsigned long long s_tot[kSigRounds * NW];
+  __shared__ unsigned long long s_base;
+  const int64_t nwords = 2 * (int64_t)a.n_blocks;
+  const int64_t base = (int64_t)blockIdx.x * (kBlockThreads * kSigRounds);
+  uint32_t word[kSigRounds];
+  unsigned long long own[kSigRounds], incl[kSigRounds];
+#pragma unroll
+  for (int r = 0; r < kSigRounds; ++r) {
+    const int64_t wi = base + r * kBlockThreads + threadIdx.x;  // one flag word per thread and round
+    word[r] = wi < nwords ? pb[wi] : 0u;
+    uint32_t cnt = 0, deg = 0;
+    for (uint32_t x = word[r]; x; x &= x - 1) {
+      const int64_t v = wi * 32 + __ffs(x) - 1;
+      const int32_t d = v < a.n ? a.trow_ptr[v + 1] - a.trow_ptr[v] : 0;
+      if (d > 0) {
+        cnt++;
+        deg += (uint32_t)d;
+      }
+    }
+    own[r] = ((unsigned long long)cnt << 32) | deg;  // arcs < 2^31: the low half never carries
+    incl[r] = wave_scan_u64(own[r], lane);
+    if (lane == kWave - 1) s_tot[r * NW + wave] = incl[r];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long acc = 0ull;
+    for (int i = 0; i < kSigRounds * NW; ++i) {
+      const unsigned long long x = s_tot[i];
+      s_tot[i] = acc;
+      acc += x;
+    }
+    s_base = acc ? atomicAdd(reinterpret_cast<unsigned long long *>(&st->sys_acc), acc) : 0ull;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSigRounds; ++r) {
+    const int64_t wi = base + r * kBlockThreads + threadIdx.x;
+    const unsigned long long off = s_base + s_tot[r * NW + wave] + incl[r] - own[r];
+    int32_t idx = (int32_t)(off >> 32);
+    int32_t pos = (int32_t)(off & 0xffffffffull);
+    for (uint32_t x = word[r]; x; x &= x - 1) {
+      const int64_t v = wi * 32 + __ffs(x) - 1;
+      const int32_t d = v < a.n ? a.trow_ptr[v + 1] - a.trow_ptr[v] : 0;
+      if (d > 0) {
+        a.sys_node[idx] = (int32_t)v;
+        a.sys_pos[idx] = pos;
+        idx++;
+        pos += d;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
+  DevState *st = a.st;
+  if (st->halted || !st->systolic) return;
+  const uint64_t acc = st->sys_acc;
+  const int32_t K = (int32_t)(acc >> 32);             // listed nodes
+  const int64_t P = (int64_t)(acc & 0xffffffffull);   // their predecessor arcs
+  if (P * kSysArcDiv > a.arcs) {  // every workgroup sees the same P and leaves
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->systolic = 0;
+    return;
+  }
+  __shared__ int32_t s_pos[kMarkTile], s_base[kMarkTile];
+  __shared__ int32_t s_red[kBlockThreads / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t t0 = (int64_t)blockIdx.x * kMarkTile; t0 < P; t0 += (int64_t)gridDim.x * kMarkTile) {
+    // first list entry of the tile: the last with sys_pos <= t0, by a 256-way search
+    // (offsets strictly increase along the list, and entry 0 starts at 0)
+    int32_t lo = 0, hi = K;
+    while (hi - lo > 1) {
+      const int32_t step = (hi - lo + kBlockThreads - 1) / kBlockThreads;
+      const int64_t j = (int64_t)lo + (int64_t)threadIdx.x * step;
+      const bool ok = j < hi && a.sys_pos[j] <= t0;  // true on a prefix of the threads
+      const int c = __popcll(__ballot(ok));
+      if (lane == 0) s_red[wave] = c;
+      __syncthreads();
+      const int total = s_red[0] + s_red[1] + s_red[2] + s_red[3];  // >= 1: thread 0 holds lo
+      __syncthreads();
+      lo += (total - 1) * step;
+      hi = min(hi, lo + step);
+    }
+    // the entries that can own arcs of this tile (at most one per arc), to LDS
+    const int32_t cnt = min(kMarkTile, K - lo);
+    for (int j = threadIdx.x; j < kMarkTile; j += kBlockThreads) {
+      if (j < cnt) {
+        const int32_t p = a.sys_pos[lo + j];
+        s_pos[j] = p;
+        s_base[j] = a.trow_ptr[a.sys_node[lo + j]] - p;
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kMarkTile; j += kBlockThreads) {
+      const int64_t i = t0 + j;
+      if (i < P) {
+        int32_t l = 0, r = cnt;  // last entry with s_pos <= i
+        while (r - l > 1) {
+          const int32_t mid = (l + r) >> 1;
+          if (s_pos[mid] <= i) l = mid; else r = mid;
+        }
+        const int32_t u = a.tcol_idx[s_base[l] + (int32_t)i];
+        a.todo[u] = 1;  // same value from every writer: no atomic needed at byte granularity
+        a.tile_todo[u / a.tile_nodes] = 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Third signal kernel: the work units of the systolic pass (appended per workgroup, as in
+// k_sys_list): a chunk whose node was signalled or modified by the previous pass (the copy
+// rule), a light tile whose flag k_sys_mark set (the flag is consumed here) or that holds a
+// modified node.
+__global__ __launch_bounds__(kBlockThreads) void k_sys_units(PassArgs a) {
+  DevState *st = a.st;
+  if (st->halted || !st->systolic) return;
+  const int32_t t = st->t;
+  const uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = kBlockThreads / kWave;
+  __shared__ int32_t s_tot[kSigRounds * NW];
+  __shared__ int32_t s_base;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t units = (int64_t)a.n_chunks + a.n_tiles;
+  const int64_t base = (int64_t)blockIdx.x * (kBlockThreads * kSigRounds);
+  uint64_t bal[kSigRounds];
+#pragma unroll
+  for (int r = 0; r < kSigRounds; ++r) {
+    const int64_t u = base + r * kBlockThreads + threadIdx.x;
+    bool need = false;
+    if (u < a.n_chunks) {
+      const int32_t v = a.chunks[u].v;
+      need = a.todo[v] != 0 || ((pb[v >> 5] >> (v & 31)) & 1u);
+    } else if (u < units) {
+      const int32_t tile = (int32_t)(u - a.n_chunks);
+      need = a.tile_todo[tile] != 0;
+      if (need) {
+        a.tile_todo[tile] = 0;  // consumed
+      } else {
+        const int32_t lo = tile * a.tile_nodes;
+        const int32_t hi = min(a.n, lo + a.tile_nodes);
+        for (int32_t w = lo >> 5; w <= (hi - 1) >> 5 && !need; ++w) need = pb[w] != 0u;
+      }
+    }
+    bal[r] = __ballot(need);
+    if (lane == 0) s_tot[r * NW + wave] = __popcll(bal[r]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < kSigRounds * NW; ++i) {
+      const int32_t x = s_tot[i];
+      s_tot[i] = acc;
+      acc += x;
+    }
+    s_base = acc ? atomicAdd(&st->sys_units, acc) : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSigRounds; ++r) {
+    if ((bal[r] >> lane) & 1ull) {
+      const int64_t u = base + r * kBlockThreads + threadIdx.x;
+      a.unit_list[s_base + s_tot[r * NW + wave] + __popcll(bal[r] & below)] = (int32_t)u;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ kernels: transposed graph
+
+__global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t value) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+__global__ void k_transpose_count(const int32_t *ci, int64_t arcs, uint64_t *keys) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < arcs; e += stride)
+    atomicAdd(reinterpret_cast<unsigned long long *>(keys + ci[e]), 1ull);
+}
+
+__global__ void k_transpose_rows(const uint64_t *keys, int32_t n, int32_t *trp) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v <= n) trp[v] = (int32_t)keys[v];
+}
+
+// One wavefront per 64 consecutive nodes: their arcs form one CSR range, read 64 at a time;
+// each lane finds its arc's source by binary search over the 65 row pointers (LDS) and
+// appends the source to its target's predecessor list. The order inside a list is
+// arbitrary (it only feeds the signal marks, a set).
+__global__ __launch_bounds__(kBlockThreads) void k_transpose_fill(const int32_t *rp, const int32_t *ci, int32_t n,
+                                                                  uint64_t *cursor, int32_t *tci) {
+  __shared__ int32_t rps[kBlockThreads / kWave][kWave + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  const int64_t stride = (int64_t)gridDim.x * (kBlockThreads / kWave);
+  for (int64_t g = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave; g < groups; g += stride) {
+    const int32_t v0 = (int32_t)(g * kWave);
+    const int32_t cn = min(kWave, n - v0);
+    if (lane < cn) rps[wave][lane] = rp[v0 + lane];
+    if (lane == cn - 1) rps[wave][cn] = rp[v0 + cn];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int64_t A = rps[wave][0], B = rps[wave][cn];
+    for (int64_t base = A; base < B; base += kWave) {
+      const int32_t p = (int32_t)min(base + lane, B);
+      if (p < B) {
+        int32_t l = 0, r = cn;  // last node j with rps[j] <= p: the arc's source
+        while (r - l > 1) {
+          const int32_t mid = (l + r) >> 1;
+          if (rps[wave][mid] <= p) l = mid; else r = mid;
+        }
+        const int32_t w = ci[p];
+        const uint64_t at = atomicAdd(reinterpret_cast<unsigned long long *>(cursor + w), 1ull);
+        tci[at] = v0 + l;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // ------------------------------------------------------------------ kernels: init
 
 // Algorithm 2's initialisation (add v to c[v]) into both register buffers, its estimate,
@@ -793,6 +1129,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
     a.bits0[gid] = 0u;
     a.bits1[gid] = 0u;
   }
+  if (a.todo && gid < (int64_t)(kNodesPerBlock / 4) * a.n_blocks) reinterpret_cast<uint32_t *>(a.todo)[gid] = 0u;
+  if (gid < ((int64_t)a.n_tiles + 3) / 4) reinterpret_cast<uint32_t *>(a.tile_todo)[gid] = 0u;
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
   if (v64 >= a.n) return;  // whole slots leave together (n * G lanes, G | 256)
@@ -834,6 +1172,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, cons
     a.bits0[gid] = 0u;
     a.bits1[gid] = 0u;
   }
+  if (a.todo && gid < (int64_t)(kNodesPerBlock / 4) * a.n_blocks) reinterpret_cast<uint32_t *>(a.todo)[gid] = 0u;
+  if (gid < ((int64_t)a.n_tiles + 3) / 4) reinterpret_cast<uint32_t *>(a.tile_todo)[gid] = 0u;
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
   if (v64 >= a.n) return;
@@ -870,7 +1210,7 @@ __global__ void k_check_registers(const uint32_t *words, int64_t nwords, DevStat
 }
 
 __global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
-                              int64_t dense_threshold) {
+                              int64_t dense_threshold, int32_t sys_div) {
   st->t = t;
   st->halted = 0;
   st->done = 0;
@@ -883,6 +1223,10 @@ __global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t
   st->changed_last = -1;
   st->dense_next = 0;
   st->dense_threshold = dense_threshold;
+  st->systolic = 0;
+  st->sys_div = sys_div;
+  st->sys_acc = 0ull;
+  st->sys_units = 0;
 }
 
 // keys[v] = (chunks of v) << 32 | (v needs a combine step); keys[n] = 0.
@@ -1112,8 +1456,9 @@ hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32
 }
 
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
-                              int64_t dense_threshold, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st, t, frontier, max_passes, dense_threshold);
+                              int64_t dense_threshold, int32_t sys_div, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st, t, frontier, max_passes, dense_threshold,
+                     sys_div);
   return hipGetLastError();
 }
 
@@ -1174,20 +1519,71 @@ hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_union(const PassArgs &a, int u, hipStream_t s) {
+hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s) {
+  if (!a.trow_ptr) return hipSuccess;
+  hipLaunchKernelGGL(k_sys_list, dim3(grid_for(2 * (int64_t)a.n_blocks, kBlockThreads * kSigRounds, 1 << 30)),
+                     dim3(kBlockThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sys_mark, dim3(grid_for(arcs, kMarkTile, 2048)), dim3(kBlockThreads), 0, s, a);
+  hipLaunchKernelGGL(k_sys_units, dim3(grid_for((int64_t)a.n_chunks + a.n_tiles, kBlockThreads * kSigRounds, 1 << 30)),
+                     dim3(kBlockThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_count(const int32_t *col_idx, int64_t arcs, uint64_t *keys, hipStream_t s) {
+  if (arcs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_count, dim3(grid_for(arcs, 256, 16384)), dim3(256), 0, s, col_idx, arcs, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, uint64_t *keys,
+                                 int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_transpose_rows, dim3(grid_for((int64_t)n + 1, 256, 1 << 30)), dim3(256), 0, s, keys, n,
+                     trow_ptr);
+  const int64_t groups = ((int64_t)n + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_transpose_fill, dim3(grid_for(groups, kBlockThreads / kWave, 1 << 16)), dim3(kBlockThreads), 0,
+                     s, row_ptr, col_idx, n, keys, tcol_idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s) {
   const int G = 1 << (a.log2m - 4);
-  const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs)), block(kBlockThreads);
-  if (grid.x == 0) return hipSuccess;
-  switch (u) {
-    case 2:
-      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 2>), grid, block, 0, s, a));
-      break;
-    case 8:
-      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 8>), grid, block, 0, s, a));
-      break;
-    default:
-      HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 4>), grid, block, 0, s, a));
-      break;
+  const dim3 block(kBlockThreads);
+  if (a.n_chunk_wgs + a.n_light_wgs == 0) return hipSuccess;
+  if (full) {
+    const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
+    const int32_t list_too = list ? 1 : 0;
+    switch (u) {
+      case 2:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 2>), grid, block, 0, s, a, list_too));
+        break;
+      case 8:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 8>), grid, block, 0, s, a, list_too));
+        break;
+      default:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 4>), grid, block, 0, s, a, list_too));
+        break;
+    }
+  }
+  if (list) {
+    const int64_t units = (int64_t)a.n_chunks + a.n_tiles;
+    const dim3 grid((unsigned)grid_for(units, kBlockThreads / kWave, kListWgs));
+    const int32_t full_too = full ? 1 : 0;
+    switch (u) {
+      case 2:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 2>), grid, block, 0, s, a, full_too));
+        break;
+      case 8:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 8>), grid, block, 0, s, a, full_too));
+        break;
+      default:
+        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 4>), grid, block, 0, s, a, full_too));
+        break;
+    }
   }
   return hipGetLastError();
 }

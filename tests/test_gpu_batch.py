@@ -56,6 +56,26 @@ def test_batch_components_equal_their_runs(b, S):
                         assert st[k] == pytest.approx(sp[k], rel=1e-9, abs=1e-12), k
 
 
+@pytest.mark.parametrize("sys_div", [1, 4])
+def test_batch_systolic_components_equal_their_runs(sys_div):
+    """Systolic passes over a batch (transposed union built on the device)."""
+    gs = _mixed_graphs()
+    S, b = 2, 6
+    seeds = [500 + 3 * c for c in range(len(gs) * S)]
+    with hanf.Batch(0, systolic=sys_div) as bt:
+        bt.load_graphs(gs, S).build_transpose().init(b, seeds)
+        bt.run()
+        assert any(r["systolic"] for r in bt.pass_log())
+        T = bt.fixpoints()
+        for g, (rp, ci) in enumerate(gs):
+            for s in range(S):
+                c = g * S + s
+                nt_ref, T_ref, regs_ref = oracle.run(rp, ci, b, seeds[c], want_regs=True)
+                assert T[c] == T_ref, (g, s)
+                np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=1e-12, atol=0)
+                assert np.array_equal(bt.registers(c), regs_ref), (g, s)
+
+
 def test_batch_step_by_step_registers():
     """Registers of every component at every t, while other components still change."""
     gs = [graphgen.directed_path(40), graphgen.rmat(10, 6000, seed=3), graphgen.erdos_renyi(500, 1500, seed=4)]

@@ -3,7 +3,8 @@
 * symmetric R-MAT scale 22 (2^26 arcs), 64 registers, hash seed 7: registers byte-equal to
   the oracle's at every iteration, N_hat(t) within 1e-12, same T;
 * web-like graph of 2^24 nodes (3.4e8 arcs), 128 registers, hash seed 1: N_hat(0) against
-  its closed form, the final counters and T against a full (multi-threaded) oracle run,
+  its closed form, the final counters and T against a full (multi-threaded) oracle run
+  (with and without systolic passes, the transposed graph built on the device),
   N_hat(T) against the oracle's sum on its own final counters, and, for sampled nodes,
   c_t[v] against the counter of the ball B(v, t) built by BFS (the identity of Section
   3.2) at t = 1, 2, 3.
@@ -32,13 +33,22 @@ def _say(msg):
 
 
 @pytest.mark.timeout(600)
-def test_rmat22sym_every_iteration():
+@pytest.mark.parametrize("systolic", [False, True])
+def test_rmat22sym_every_iteration(systolic):
+    """With systolic=True in the benchmark's configuration: the symmetric graph's own
+    device arrays serve as its transpose."""
+    import torch
     spec = graphgen.WORKLOADS["rmat22sym"]
     rp, ci = graphgen.workload_graph(spec)
     b, seed = spec["log2m"], spec["seed"]
-    _say(f"[fullsize] rmat22sym n={len(rp) - 1} arcs={len(ci)} b={b} seed={seed}")
+    _say(f"[fullsize] rmat22sym n={len(rp) - 1} arcs={len(ci)} b={b} seed={seed} systolic={systolic}")
     with hanf.HyperANF(0) as h:
-        h.load(rp, ci).init(b, seed)
+        if systolic:
+            drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+            h.load(drp, dci).load_transpose(drp, dci)
+        else:
+            h.load(rp, ci)
+        h.init(b, seed)
         want = []
         T = None
         for t, c, s in oracle.run_steps(rp, ci, b, seed, nthreads=THREADS):
@@ -52,6 +62,7 @@ def test_rmat22sym_every_iteration():
         nt = h.nt()
         assert len(nt) == T + 1
         np.testing.assert_allclose(nt, np.array(want), rtol=1e-12, atol=0)
+        assert any(r["systolic"] for r in h.pass_log()) == systolic
 
 
 @pytest.mark.timeout(900)
@@ -75,6 +86,14 @@ def test_web24_final_counters_and_samples():
         h.run()
         nt = h.nt()
         final = h.registers()
+    with hanf.HyperANF(0) as h:  # systolic passes, transposed graph built on the device
+        h.load(rp, ci).build_transpose().init(b, seed)
+        nt_sys = h.run()
+        assert any(r["systolic"] for r in h.pass_log())
+        final_sys = h.registers()
+    assert np.array_equal(final_sys, final)
+    del final_sys
+    np.testing.assert_allclose(nt_sys, nt, rtol=1e-12, atol=0)
     assert nt[0] == pytest.approx(n * m * math.log(m / (m - 1)), rel=1e-12)
     for t in (1, 2, 3):
         for i, v in enumerate(sample[:8]):

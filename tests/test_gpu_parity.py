@@ -27,15 +27,42 @@ def _flush(msg):
     sys.stdout.flush()
 
 
-def step_parity(rp, ci, b, seed, check_every=1, **opts):
+def transpose_csr(rp, ci):
+    """Predecessor lists (CSR) of a CSR graph, by a stable sort on the target."""
+    n = len(rp) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    order = np.argsort(ci, kind="stable")
+    trp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(ci, minlength=n), out=trp[1:])
+    return trp.astype(np.int32), src[order].astype(np.int32)
+
+
+def _load(h, rp, ci, transpose):
+    """Loads the graph and, for systolic passes, its transpose: 'build' on the device,
+    'host' from numpy, 'self' (symmetric graph: its own device arrays)."""
+    if transpose == "self":
+        import torch
+        drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+        h.load(drp, dci).load_transpose(drp, dci)
+    else:
+        h.load(rp, ci)
+        if transpose == "build":
+            h.build_transpose()
+        elif transpose == "host":
+            h.load_transpose(*transpose_csr(rp, ci))
+    return h
+
+
+def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
     """Runs GPU and oracle side by side one pass at a time; checks everything."""
     n = len(rp) - 1
-    _flush(f"[parity] n={n} arcs={len(ci)} b={b} seed={seed} opts={opts}")
+    _flush(f"[parity] n={n} arcs={len(ci)} b={b} seed={seed} transpose={transpose} opts={opts}")
     ref = oracle.run_steps(rp, ci, b, seed, skip_unmodified=True)
     mod = np.ones(n, np.uint8)
     prev_changed = 0
+    sys_div = opts.get("systolic", 4) if transpose else 0
     with hanf.HyperANF(0, **opts) as h:
-        h.load(rp, ci).init(b, seed)
+        _load(h, rp, ci, transpose).init(b, seed)
         nts = []
         T = None
         for t, c, s in ref:
@@ -56,6 +83,15 @@ def step_parity(rp, ci, b, seed, check_every=1, **opts):
             assert log["gather_all"] == (t == 0 or not opts.get("frontier", 1)
                                          or (opts.get("dense_switch", 4) > 0
                                              and prev_changed >= max(1, n // opts.get("dense_switch", 4))))
+            # systolic after a pass that changed < n / sys_div counters, unless it would signal
+            # more than arcs / 16 arcs
+            want_sys = (not log["gather_all"] and opts.get("frontier", 1) and sys_div > 0
+                        and prev_changed * sys_div < n and maxed * 16 <= len(ci))
+            assert log["systolic"] == int(bool(want_sys)), (t, log)
+            if log["systolic"]:
+                # every arc into a counter modified by the previous pass is signalled once:
+                # the same arcs the frontier gathers, counted from the other end
+                assert log["arcs_signalled"] == maxed, (t, log, maxed)
             prev_changed = changed
             assert ch_last == changed
             mod = mod_out
@@ -132,6 +168,76 @@ def test_schedules_identical(opts):
     step_parity(rp, ci, 6, 17, **opts)
 
 
+@pytest.mark.parametrize("transpose", ["build", "host"])
+def test_systolic_rmat14_every_iteration(transpose):
+    """Systolic passes (Section 3.3): same registers, N_hat and work counters at every t;
+    the arcs signalled in a systolic pass are exactly the arcs into modified counters."""
+    rp, ci = graphgen.rmat(14, 262_144, seed=14)
+    step_parity(rp, ci, 4, 1, transpose=transpose)
+
+
+@pytest.mark.parametrize("opts", [dict(systolic=1), dict(systolic=1, dense_switch=0),
+                                  dict(systolic=2, chunk_arcs=150, light_max=8), dict(systolic=1000000),
+                                  dict(systolic=0), dict(systolic=1, unroll=8, tile_nodes=256),
+                                  dict(systolic=1, frontier=0), dict(systolic=1, batch=1),
+                                  dict(systolic=1, union_policy=1), dict(systolic=1, union_policy=2),
+                                  dict(systolic=0, union_policy=2), dict(frontier=0, union_policy=2),
+                                  dict(systolic=1, union_policy=2, chunk_arcs=150, light_max=8, unroll=2),
+                                  dict(systolic=1, union_policy=2, dense_switch=0, tile_nodes=16)])
+def test_systolic_schedules_identical(opts):
+    """Every schedule and either union kernel (one wavefront per work unit, or the
+    persistent kernel that skips idle units) in every kind of pass."""
+    rp, ci = graphgen.rmat(12, 40_000, seed=6)
+    step_parity(rp, ci, 6, 17, transpose="build", **opts)
+
+
+@pytest.mark.parametrize("b", [4, 6, 8])
+def test_systolic_symmetric_self_transpose(b):
+    """A symmetric graph is its own transpose: its device arrays serve both roles."""
+    rp, ci = graphgen.rmat(13, 60_000, symmetric=True, seed=30 + b)
+    step_parity(rp, ci, b, 7, transpose="self")
+    step_parity(rp, ci, b, 8, transpose="self", dense_switch=0, systolic=1)
+
+
+def test_transpose_errors():
+    rp, ci = graphgen.erdos_renyi(100, 300, seed=1)
+    trp, tci = transpose_csr(rp, ci)
+    with hanf.HyperANF(0) as h:
+        with pytest.raises(hanf.HanfError) as e:
+            h.build_transpose()
+        assert e.value.code == hanf.HANF_ESTATE
+        h.load(rp, ci)
+        with pytest.raises(hanf.HanfError) as e:  # not the graph's arc count
+            h.load_transpose(trp, tci[:-1])
+        assert e.value.code == hanf.HANF_EINVAL
+        bad = tci.copy()
+        bad[3] = 100
+        with pytest.raises(hanf.HanfError) as e:
+            h.load_transpose(trp, bad)
+        assert e.value.code == hanf.HANF_EINVAL
+        badr = trp.copy()
+        badr[5] = badr[6] + 1
+        with pytest.raises(hanf.HanfError) as e:
+            h.load_transpose(badr, tci)
+        assert e.value.code == hanf.HANF_EINVAL
+        # loading a transpose discards the run in progress
+        h.init(6, 1)
+        h.load_transpose(trp, tci)
+        with pytest.raises(hanf.HanfError) as e:
+            h.step(1)
+        assert e.value.code == hanf.HANF_ESTATE
+        h.init(6, 1)
+        nt = h.run()
+        assert any(r["systolic"] for r in h.pass_log())
+    want, _, _ = oracle.run(rp, ci, 6, 1)
+    np.testing.assert_allclose(nt, want, rtol=RTOL, atol=0)
+    with hanf.Batch(0) as bt:
+        bt.load_graphs([(rp, ci)], 2)
+        with pytest.raises(hanf.HanfError) as e:
+            bt.load_transpose(trp, tci)
+        assert e.value.code == hanf.HANF_EINVAL
+
+
 @pytest.mark.parametrize("name", ["single", "empty100", "star_out", "star_in", "cycle", "path",
                                   "complete", "cpc", "loops_dups"])
 def test_edge_graphs(name):
@@ -159,6 +265,8 @@ def test_edge_graphs(name):
         g = graphgen.from_arcs(n, arcs)
     for b in (4, 7):
         step_parity(*g, b, 99)
+        step_parity(*g, b, 98, transpose="build", systolic=1)
+        step_parity(*g, b, 97, transpose="build", systolic=1, union_policy=2, chunk_arcs=256)
 
 
 def test_device_pointers_match_host():
