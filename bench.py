@@ -5,7 +5,10 @@ One step is a whole HyperANF run on a graph already resident in HBM: graph inges
 (device-side validation and work schedule), counter initialisation, passes until no
 counter changes, and the statistics (distance distribution, effective diameter, spid).
 The default workload is the symmetric R-MAT graph of scale 22 (2^22 nodes, 2^26 arcs,
-a=.57 b=.19 c=.19 d=.05) with 64 registers per counter and hash seed 7.
+a=.57 b=.19 c=.19 d=.05) with 64 registers per counter and hash seed 7. Late passes are
+systolic (Section 3.3): a symmetric graph is its own transpose, so its device arrays are
+given as the transposed graph too (--transpose self); for a directed workload the
+transpose is built on the device inside the step (--transpose build) or not used (none).
 
 Prints one JSON line. `value` = edge-register updates per second over the whole step:
 m * (successor counters actually maximised in, summed over the passes) / step time.
@@ -28,11 +31,15 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def algorithmic_bytes(rec, n, m):
-    """Bytes a union pass must move: row_ptr (4 B/node), col_idx of every arc scanned
-    (4 B), m bytes per successor counter maximised in, per own counter read and per new
-    counter written, and one flag bit per node read and written."""
-    return (4 * (n + 1) + 4 * rec["arcs_scanned"]
-            + m * (rec["arcs_gathered"] + rec["rows_read"] + rec["rows_written"]) + n // 4)
+    """Bytes a union pass must move: col_idx of every arc scanned (4 B), m bytes per
+    successor counter maximised in, per own counter read and per new counter written; plus,
+    in a pass over every node, row_ptr (4 B/node) and one flag bit per node read and
+    written, or, in a systolic pass (only signalled nodes visited), two row_ptr entries per
+    node whose counter was read."""
+    rows = m * (rec["arcs_gathered"] + rec["rows_read"] + rec["rows_written"])
+    if rec.get("systolic"):
+        return 8 * rec["rows_read"] + 4 * rec["arcs_scanned"] + rows
+    return 4 * (n + 1) + 4 * rec["arcs_scanned"] + rows + n // 4
 
 
 def measured_traffic(workload):
@@ -295,6 +302,9 @@ def main():
                          "serve: Poisson request stream")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
     ap.add_argument("--max-batches", type=int, default=8, help="serve mode: batches in flight")
+    ap.add_argument("--transpose", choices=["auto", "self", "build", "none"], default="auto",
+                    help="transposed graph for systolic passes: auto = self for symmetric workloads, "
+                         "none otherwise")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for "
                          "scaling HBM byte counters of a profiler")
@@ -348,9 +358,19 @@ def main():
         k, v = kv.split("=")
         opts[k] = int(v)
     h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
+    tmode = args.transpose
+    if tmode == "auto":
+        tmode = "self" if spec.get("symmetric") else "none"
+    if tmode == "self" and not spec.get("symmetric"):
+        print("bench.py: --transpose self needs a symmetric workload", file=sys.stderr)
+        sys.exit(2)
 
     def step():
         h.load(trp, tci)
+        if tmode == "self":
+            h.load_transpose(trp, tci)
+        elif tmode == "build":
+            h.build_transpose()
         h.init(b, seed)
         nt = h.run()
         return nt, h.stats(), h.pass_log()
@@ -383,7 +403,7 @@ def main():
         achieved = byts / (union_ms / 1000.0) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args.workload),
-                        kernel="k_union", launches=launches,
+                        kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
                         avg_launch_us=round(1000.0 * union_ms / launches, 2),
                         avg_algorithmic_bytes=int(byts / launches))
         p0 = [lg[0] for lg in logs]
@@ -393,7 +413,8 @@ def main():
                          gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
                          updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0),
                          frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4))
-        other = dict(finalize_ms=round(sum(r["finalize_ms"] for r in log), 4),
+        other = dict(signal_ms=round(sum(r["signal_ms"] for r in log), 4),
+                     finalize_ms=round(sum(r["finalize_ms"] for r in log), 4),
                      reduce_ms=round(sum(r["reduce_ms"] for r in log), 4),
                      union_ms=round(sum(r["union_ms"] for r in log), 4))
     cpu = None
@@ -415,7 +436,9 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": spec_name(args.workload), "n": n, "arcs": arcs, "log2m": b,
-                   "hash_seed": seed, "T": st["T"], "passes": len(log)},
+                   "hash_seed": seed, "T": st["T"], "passes": len(log), "transpose": tmode,
+                   "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
+                                         for r in log)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "full_pass": full_pass,

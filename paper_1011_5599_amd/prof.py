@@ -1,0 +1,178 @@
+"""Summaries of rocprofv3 runs of bench.py, written under profiles/.
+
+* the kernel-time table of a `rocprofv3 --kernel-trace --stats` run, with the union step's
+  average time per pass beside bench.py's own HIP-event figure from the same run;
+* the HBM bytes of the union step per pass, from two `rocprofv3 --pmc` runs (FETCH_SIZE,
+  then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a
+  plain device copy of known size (`bench.py --copy-calibration MIB`).
+
+The union step of a pass is every k_union / k_union_list dispatch between two k_reduce_top
+dispatches (in a systolic pass both may be launched, one of them leaving at once); passes
+enqueued after the fixpoint (they return at once) are left out.
+
+    python -m paper_1011_5599_amd.prof --workload rmat22sym --trace DIR --trace-json FILE \\
+        --fetch DIR --write DIR --pmc-json FILE --copy-fetch DIR --copy-write DIR \\
+        --copy-mib 1024 --commands FILE --out-md profiles/k_union_rmat22sym.md \\
+        --out-json profiles/k_union_rmat22sym_traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SRC = os.path.join(ROOT, "paper_1011_5599_amd", "csrc", "hanf_kernels.hip")
+
+
+def _short(name: str) -> str:
+    """Kernel name without namespaces and argument lists."""
+    base = name.replace("hanf::(anonymous namespace)::", "").replace("void ", "")
+    return base.split("(")[0]
+
+
+def _is_union(name: str) -> bool:
+    s = _short(name)
+    return s.startswith("k_union<") or s.startswith("k_union_list<")
+
+
+def kernel_table(trace_dir: str):
+    with open(os.path.join(trace_dir, "run_kernel_stats.csv")) as f:
+        rows = list(csv.DictReader(f))
+    return [dict(name=_short(r["Name"]), calls=int(r["Calls"]), avg_us=float(r["AverageNs"]) / 1e3,
+                 total_ms=float(r["TotalDurationNs"]) / 1e6, pct=float(r["Percentage"])) for r in rows]
+
+
+def _dispatches(path: str):
+    """(dispatch id, kernel name, value) in dispatch order; value = duration ns (trace) or the
+    counter value (counter collection)."""
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if "Counter_Value" in r:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+            else:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                            float(r["End_Timestamp"]) - float(r["Start_Timestamp"])))
+    out.sort()
+    return out
+
+
+def union_per_pass(dispatches, passes_per_run):
+    """Sums of the union-step values of every executed pass: a run starts at k_init, its
+    first k_reduce_top is the initial estimate, and each later k_reduce_top closes a pass.
+    Only the first `passes_per_run` passes of a run count: passes enqueued after the fixpoint
+    return at once."""
+    out, run, cur = [], None, None
+    for _, name, val in dispatches:
+        s = _short(name)
+        if s.startswith("k_init"):
+            if run:
+                out += run[:passes_per_run]
+            run, cur = [], None
+        elif run is None:
+            continue
+        elif s.startswith("k_reduce_top"):
+            if cur is not None:
+                run.append(cur)
+            cur = 0.0
+        elif _is_union(name) and cur is not None:
+            cur += val
+    if run:
+        out += run[:passes_per_run]
+    return out
+
+
+def copy_scale(copy_dir: str, copy_bytes: int) -> float:
+    rows = [(n, v) for _, n, v in _dispatches(os.path.join(copy_dir, "run_counter_collection.csv"))
+            if "copyBuffer" in n or "copy" in _short(n).lower()]
+    if not rows:
+        raise SystemExit(f"no copy kernel in {copy_dir}")
+    kib = sum(v for _, v in rows) / len(rows)
+    return copy_bytes / (kib * 1024.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--trace", required=True, help="rocprofv3 --kernel-trace --stats output dir")
+    ap.add_argument("--trace-json", required=True, help="bench.py JSON line of the trace run")
+    ap.add_argument("--fetch", help="rocprofv3 --pmc FETCH_SIZE output dir")
+    ap.add_argument("--write", help="rocprofv3 --pmc WRITE_SIZE output dir")
+    ap.add_argument("--pmc-json", help="bench.py JSON line of the counter runs")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--commands", required=True, help="text file with the commands that were run")
+    ap.add_argument("--out-md", required=True)
+    ap.add_argument("--out-json")
+    args = ap.parse_args()
+
+    bench = json.loads(open(args.trace_json).read().strip().splitlines()[-1])
+    table = kernel_table(args.trace)
+    trace = _dispatches(os.path.join(args.trace, "run_kernel_trace.csv"))
+    per_pass_ns = union_per_pass(trace, bench["config"]["passes"])
+    step_avg_us = sum(per_pass_ns) / len(per_pass_ns) / 1e3 if per_pass_ns else float("nan")
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+    L = [f"# Union step on {args.workload}" + (f" ({args.title})" if args.title else ""), ""]
+    L += ["Run from the repository root on one MI355X (gfx950), ROCm 7.2, after "
+          "`python -c 'import __graft_entry__ as g; g.build()'`. Commands:", "", "```"]
+    L += [ln.rstrip() for ln in open(args.commands) if ln.strip()]
+    L += ["```", "", "## Kernel trace", ""]
+    runs = bench["steps"] + bench["warmup"]
+    L += [f"{runs} HyperANF runs ({bench['warmup']} warm-up + {bench['steps']} timed), "
+          f"{bench['config']['passes']} passes each (T = {bench['config']['T']}, pass kinds "
+          f"{bench['config'].get('pass_kinds', '?')}: D all successors, F modified-flag frontier, "
+          f"S systolic).", ""]
+    L += ["| kernel | calls | avg µs | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in table:
+        L.append(f"| {r['name']} | {r['calls']} | {r['avg_us']:.1f} | {r['total_ms']:.3f} | {r['pct']:.2f} |")
+    rl = bench.get("roofline") or {}
+    L += ["", f"Union step (k_union and k_union_list dispatches of a pass): rocprofv3 average over "
+              f"{len(per_pass_ns)} passes {step_avg_us:.2f} µs; bench.py's HIP events in the same run "
+              f"(timed runs, {rl.get('launches')} passes) {rl.get('avg_launch_us')} µs.", ""]
+
+    rec = None
+    if args.fetch and args.write and args.pmc_json and args.copy_fetch and args.copy_write:
+        pmc = json.loads(open(args.pmc_json).read().strip().splitlines()[-1])
+        alg = pmc["pass_algorithmic_bytes"]
+        pr = pmc["config"]["passes"]
+        fetch = union_per_pass(_dispatches(os.path.join(args.fetch, "run_counter_collection.csv")), pr)
+        write = union_per_pass(_dispatches(os.path.join(args.write, "run_counter_collection.csv")), pr)
+        copy_bytes = args.copy_mib << 20
+        fs = copy_scale(args.copy_fetch, copy_bytes)
+        ws = copy_scale(args.copy_write, copy_bytes)
+        n = min(len(fetch), len(write), len(alg))
+        L += ["## HBM byte counters", ""]
+        L += [f"Calibration: a plain {args.copy_mib} MiB device copy reads FETCH_SIZE and WRITE_SIZE such "
+              f"that FETCH_SIZE is scaled by {fs:.3f} and WRITE_SIZE by {ws:.3f} to bytes.", ""]
+        L += ["| pass t | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM GB | algorithmic GB | ratio |",
+              "|---:|---:|---:|---:|---:|---:|"]
+        tot_hbm = tot_alg = 0.0
+        for t in range(n):
+            hbm = fetch[t] * 1024 * fs + write[t] * 1024 * ws
+            tot_hbm += hbm
+            tot_alg += alg[t]
+            L.append(f"| {t} | {fetch[t]:.0f} | {write[t]:.0f} | {hbm / 1e9:.3f} | {alg[t] / 1e9:.3f} | "
+                     f"{hbm / alg[t]:.2f} |")
+        L += ["", f"Per pass (average of {n}): {tot_hbm / n / 1e9:.3f} GB moved beyond L2 vs "
+                  f"{tot_alg / n / 1e9:.3f} GB algorithmic (ratio {tot_hbm / tot_alg:.2f}).", ""]
+        rec = dict(kernel="union step (k_union, k_union_list)", workload=args.workload,
+                   kernel_source_sha256=sha, traffic_bytes_per_launch=int(tot_hbm / n),
+                   algorithmic_bytes_per_launch=int(tot_alg / n), fetch_scale=fs, write_scale=ws,
+                   launches=n)
+    L += [f"Kernel source at measurement: `paper_1011_5599_amd/csrc/hanf_kernels.hip` sha256 `{sha[:16]}…` "
+          "(bench.py reports `traffic` only while the source is unchanged)."]
+    with open(args.out_md, "w") as f:
+        f.write("\n".join(L) + "\n")
+    if rec and args.out_json:
+        with open(args.out_json, "w") as f:
+            json.dump(rec, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
