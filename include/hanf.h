@@ -69,6 +69,11 @@ extern "C" {
                                    Needs a transposed graph (hanf_load_transpose or
                                    hanf_build_transpose); default 4 as in the paper; 0 = never */
 
+#define HANF_OPT_SEEDS_PER_ROW 10 /* batched runs: counters of one graph's seeds side by side in a
+                                   node's row (one successor scan and one gather serve them
+                                   all). 0 (default): as many as fit, up to 32 and 1024 bytes
+                                   per row; else a power of two up to 32. Results do not change */
+
 /* ---- hanf_footprint flags */
 #define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */
 #define HANF_FP_TRANSPOSE 2     /* include the transposed graph and the systolic signal buffers */

@@ -42,6 +42,7 @@ HANF_OPT_BATCH = 6
 HANF_OPT_TILE_NODES = 7
 HANF_OPT_DENSE_SWITCH = 8
 HANF_OPT_SYSTOLIC = 9
+HANF_OPT_SEEDS_PER_ROW = 10
 HANF_FP_COPY_GRAPH = 1
 HANF_FP_TRANSPOSE = 2
 HANF_OPT_UNROLL = 100
@@ -397,6 +398,7 @@ class HyperANF:
                  "timing": HANF_OPT_TIMING, "batch": HANF_OPT_BATCH,
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
+                 "seeds_per_row": HANF_OPT_SEEDS_PER_ROW,
                  "union_policy": HANF_OPT_UNION_POLICY}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))

@@ -82,18 +82,29 @@ struct hanf_ctx {
 
   Schedule sch;
 
-  // batched graph: components (graph, seed) laid side by side, 64-node aligned
+  // batched graph. Base (from ingest): every graph once, side by side, 64-node aligned.
+  // Layout (chosen at initialisation, once m is known): rows of S = 2^sl counters, and
+  // `copies` copies of every graph when its seeds need more than one row.
   bool batch = false;
-  int32_t n_graphs = 0, n_seeds = 0, n_comp = 0;
-  std::vector<int32_t> comp_node_off_h, comp_n_h;
-  int32_t *blk_comp = nullptr, *comp_node_off = nullptr, *comp_n = nullptr;
+  int32_t n_graphs = 0, n_seeds = 0, n_comp = 0, n_lay = 0;
+  int32_t base_n = 0;
+  int64_t base_arcs = 0;
+  std::vector<int32_t> g_node_off_h, g_n_h, g_aoff_h;      // per graph in the base
+  int32_t *blk_comp = nullptr, *comp_node_off = nullptr, *comp_n = nullptr;  // base tables
+  int32_t copies = 1;
+  bool layout_ok = false;
+  std::vector<int32_t> lay_node_off_h, lay_n_h, comp_row_h;
+  int32_t *lay_blk = nullptr, *lay_node_off = nullptr, *lay_n = nullptr;  // tables of an expanded layout
+  int32_t *rp_lay = nullptr, *ci_lay = nullptr, *trp_lay = nullptr, *tci_lay = nullptr;
+  int seeds_row_opt = 0;  // 0: as many counters per row as fit (<= 32, S * m <= 1024 bytes)
   // batched run state
   uint64_t *comp_seed = nullptr;
-  int32_t *blkcnt = nullptr, *comp_T = nullptr;
+  int32_t *blkcnt = nullptr, *comp_T = nullptr, *slot_comp = nullptr, *comp_row = nullptr;
   double *comp_nt = nullptr;
 
   // run state
   int log2m = 0;
+  int sl = 0;  // log2 of the counters per node row
   bool inited = false;
   uint8_t *regs[2] = {nullptr, nullptr};
   uint32_t *bits[2] = {nullptr, nullptr};
@@ -232,6 +243,8 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->blkcnt);
   dev_release(c, c->comp_T);
   dev_release(c, c->comp_nt);
+  dev_release(c, c->slot_comp);
+  dev_release(c, c->comp_row);
   dev_release(c, c->todo);
   dev_release(c, c->sys_node);
   dev_release(c, c->sys_pos);
@@ -239,27 +252,67 @@ void free_run(hanf_ctx *c) {
   c->log2m = 0;
 }
 
+// Drops an expanded batch layout (the base remains).
+void free_layout(hanf_ctx *c) {
+  dev_release(c, c->lay_blk);
+  dev_release(c, c->lay_node_off);
+  dev_release(c, c->lay_n);
+  dev_release(c, c->rp_lay);
+  dev_release(c, c->ci_lay);
+  dev_release(c, c->trp_lay);
+  dev_release(c, c->tci_lay);
+  c->layout_ok = false;
+  c->copies = 1;
+}
+
 void free_transpose(hanf_ctx *c) {
   dev_release(c, c->trp_own);
   dev_release(c, c->tci_own);
+  dev_release(c, c->trp_lay);
+  dev_release(c, c->tci_lay);
   c->trp = c->tci = nullptr;
 }
 
 void free_graph(hanf_ctx *c) {
   free_transpose(c);
+  free_layout(c);
   dev_release(c, c->rp_own);
   dev_release(c, c->ci_own);
   dev_release(c, c->blk_comp);
   dev_release(c, c->comp_node_off);
   dev_release(c, c->comp_n);
   c->batch = false;
-  c->n_graphs = c->n_seeds = c->n_comp = 0;
-  c->comp_node_off_h.clear();
-  c->comp_n_h.clear();
+  c->n_graphs = c->n_seeds = c->n_comp = c->n_lay = 0;
+  c->base_n = 0;
+  c->base_arcs = 0;
+  c->g_node_off_h.clear();
+  c->g_n_h.clear();
+  c->g_aoff_h.clear();
+  c->lay_node_off_h.clear();
+  c->lay_n_h.clear();
+  c->comp_row_h.clear();
   c->rp = c->ci = nullptr;
   c->graph_ok = false;
   c->n = 0;
   c->arcs = 0;
+}
+
+// After batched ingest: the base (every graph once) is the graph until initialisation
+// chooses the row layout.
+void set_base(hanf_ctx *c, const std::vector<int32_t> &node_off, const std::vector<int32_t> &n,
+              const std::vector<int32_t> &arc_off) {
+  c->rp = c->rp_own;
+  c->ci = c->ci_own;
+  c->g_node_off_h = node_off;
+  c->g_n_h = n;
+  c->g_aoff_h = arc_off;
+  c->base_n = c->n;
+  c->base_arcs = c->arcs;
+  c->lay_node_off_h = node_off;
+  c->lay_n_h = n;
+  c->copies = 1;
+  c->layout_ok = true;
+  c->graph_ok = true;
 }
 
 int sync(hanf_ctx *c, const char *what) {
@@ -367,8 +420,9 @@ void fill_args(hanf_ctx *c) {
   a.tile_todo = c->sch.tile_todo;
   a.unit_list = c->sch.unit_list;
   const bool sys = c->trp && c->todo;
-  a.trow_ptr = sys ? c->trp : nullptr;
-  a.tcol_idx = sys ? c->tci : nullptr;
+  const bool lay_t = c->batch && c->copies > 1;  // the transposed graph of the expanded layout
+  a.trow_ptr = sys ? (lay_t ? c->trp_lay : c->trp) : nullptr;
+  a.tcol_idx = sys ? (lay_t ? c->tci_lay : c->tci) : nullptr;
   a.todo = c->todo;
   a.sys_node = c->sys_node;
   a.sys_pos = c->sys_pos;
@@ -380,6 +434,8 @@ void fill_args(hanf_ctx *c) {
   a.K = alpha_for(m) * m * m * 2147483648.0;
   a.n = c->n;
   a.log2m = c->log2m;
+  a.seed_log2 = c->sl;
+  a.gs = c->log2m >= 4 ? 1 << (c->log2m - 4) : 1;
   a.n_blocks = c->n_blocks;
   a.n_chunks = c->sch.n_chunks;
   a.n_chunk_wgs = c->sch.n_chunk_wgs;
@@ -394,9 +450,13 @@ void fill_args(hanf_ctx *c) {
   a.arcs = c->arcs;
   a.batch.active = c->batch ? 1 : 0;
   a.batch.n_comp = c->n_comp;
-  a.batch.blk_comp = c->blk_comp;
-  a.batch.comp_node_off = c->comp_node_off;
-  a.batch.comp_n = c->comp_n;
+  a.batch.n_lay = c->n_lay;
+  const bool lay = c->batch && c->copies > 1;
+  a.batch.blk_comp = lay ? c->lay_blk : c->blk_comp;
+  a.batch.comp_node_off = lay ? c->lay_node_off : c->comp_node_off;
+  a.batch.comp_n = lay ? c->lay_n : c->comp_n;
+  a.batch.slot_comp = c->slot_comp;
+  a.batch.comp_row = c->comp_row;
   a.batch.comp_seed = c->comp_seed;
   a.batch.blkcnt = c->blkcnt;
   a.batch.comp_T = c->comp_T;
@@ -410,20 +470,21 @@ int64_t default_max_passes(const hanf_ctx *c) {
   return c->batch ? std::min<int64_t>(1024, (int64_t)c->n + 1) : (int64_t)c->n + 1;
 }
 
-int alloc_run(hanf_ctx *c, int log2m) {
+int alloc_run(hanf_ctx *c, int log2m, int sl) {
   free_run(c);
   const int m = 1 << log2m;
-  const size_t bytes = (size_t)c->n * m;
+  const size_t S = (size_t)1 << sl;  // counters per node row
+  const size_t bytes = (size_t)c->n * m * S;
   c->n_blocks = (int32_t)(((int64_t)c->n + kNodesPerBlock - 1) / kNodesPerBlock);
   c->n_reduce_wgs = (c->n_blocks + kReduceBlocks - 1) / kReduceBlocks;
   c->max_passes = (int32_t)std::min<int64_t>(default_max_passes(c), INT32_MAX - 8);
   c->nt_cap = c->max_passes + 2;
   int rc;
   if ((rc = dev_alloc(c, &c->regs[0], bytes, "counters")) || (rc = dev_alloc(c, &c->regs[1], bytes, "counters")) ||
-      (rc = dev_alloc(c, &c->bits[0], (size_t)2 * c->n_blocks, "flags")) ||
-      (rc = dev_alloc(c, &c->bits[1], (size_t)2 * c->n_blocks, "flags")) ||
-      (rc = dev_alloc(c, &c->est, (size_t)c->n, "estimates")) ||
-      (rc = dev_alloc(c, &c->blocksum, (size_t)c->n_blocks, "block sums")) ||
+      (rc = dev_alloc(c, &c->bits[0], (size_t)2 * c->n_blocks * S, "flags")) ||
+      (rc = dev_alloc(c, &c->bits[1], (size_t)2 * c->n_blocks * S, "flags")) ||
+      (rc = dev_alloc(c, &c->est, (size_t)c->n * S, "estimates")) ||
+      (rc = dev_alloc(c, &c->blocksum, (size_t)c->n_blocks * S, "block sums")) ||
       (rc = dev_alloc(c, &c->wgsum, (size_t)c->n_reduce_wgs, "partial sums")) ||
       (rc = dev_alloc(c, &c->wgcnt, (size_t)c->n_reduce_wgs, "partial counts")) ||
       (rc = dev_alloc(c, &c->lc, (size_t)m + 1, "linear-counting table")) ||
@@ -435,9 +496,11 @@ int alloc_run(hanf_ctx *c, int log2m) {
   }
   if (c->batch) {
     if ((rc = dev_alloc(c, &c->comp_seed, (size_t)c->n_comp, "component seeds")) ||
-        (rc = dev_alloc(c, &c->blkcnt, (size_t)c->n_blocks, "block change counts")) ||
+        (rc = dev_alloc(c, &c->blkcnt, (size_t)c->n_blocks * S, "block change counts")) ||
         (rc = dev_alloc(c, &c->comp_T, (size_t)c->n_comp, "component fixpoints")) ||
-        (rc = dev_alloc(c, &c->comp_nt, (size_t)c->n_comp * c->nt_cap, "component histories"))) {
+        (rc = dev_alloc(c, &c->comp_nt, (size_t)c->n_comp * c->nt_cap, "component histories")) ||
+        (rc = dev_alloc(c, &c->slot_comp, (size_t)c->n_lay * S, "row seed components")) ||
+        (rc = dev_alloc(c, &c->comp_row, (size_t)c->n_comp, "component rows"))) {
       free_run(c);
       return rc;
     }
@@ -448,12 +511,104 @@ int alloc_run(hanf_ctx *c, int log2m) {
   HIP_TRY(c, hipMemcpyAsync(c->lc, c->lc_host.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, c->stream),
           "table upload");
   c->log2m = log2m;
+  c->sl = sl;
   return HANF_OK;
 }
 
+// Batched runs: lays out `copies` copies of every graph of the base (copy q of graph g is
+// layout component L = g * copies + q, with the graph's 64-node aligned size), expanded on
+// the device from the base, and so its transposed graph if there is one. One copy is the
+// base itself.
+int set_layout(hanf_ctx *c, int32_t copies) {
+  if (c->layout_ok && copies == c->copies) return HANF_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_run(c);
+  free_schedule(c);
+  free_layout(c);
+  const int32_t G = c->n_graphs;
+  if (copies == 1) {
+    c->rp = c->rp_own;
+    c->ci = c->ci_own;
+    c->n = c->base_n;
+    c->arcs = c->base_arcs;
+    c->n_lay = G;
+    c->lay_node_off_h = c->g_node_off_h;
+    c->lay_n_h = c->g_n_h;
+    c->layout_ok = true;
+    return HANF_OK;
+  }
+  const int32_t L = G * copies;
+  std::vector<int32_t> off((size_t)L + 1), n((size_t)L), aoff((size_t)L + 1);
+  int64_t nacc = 0, aacc = 0;
+  for (int32_t g = 0; g < G; ++g)
+    for (int32_t q = 0; q < copies; ++q) {
+      const int32_t k = g * copies + q;
+      off[k] = (int32_t)nacc;
+      aoff[k] = (int32_t)aacc;
+      n[k] = c->g_n_h[g];
+      nacc += c->g_node_off_h[g + 1] - c->g_node_off_h[g];
+      aacc += c->g_aoff_h[g + 1] - c->g_aoff_h[g];
+      if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
+        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices in its row layout");
+    }
+  off[L] = (int32_t)nacc;
+  aoff[L] = (int32_t)aacc;
+  std::vector<int32_t> blk((size_t)(nacc / kNodesPerBlock));
+  for (int32_t k = 0; k < L; ++k)
+    for (int64_t b = off[k] / kNodesPerBlock; b < off[k + 1] / kNodesPerBlock; ++b) blk[(size_t)b] = k;
+  int32_t *d_aoff = nullptr;
+  const bool with_t = c->trp != nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &c->lay_blk, blk.size(), "layout blocks")) ||
+      (rc = dev_alloc(c, &c->lay_node_off, (size_t)L + 1, "layout offsets")) ||
+      (rc = dev_alloc(c, &c->lay_n, (size_t)L, "layout sizes")) ||
+      (rc = dev_alloc(c, &d_aoff, (size_t)L + 1, "layout arc offsets")) ||
+      (rc = dev_alloc(c, &c->rp_lay, (size_t)nacc + 1, "layout row_ptr")) ||
+      (rc = dev_alloc(c, &c->ci_lay, (size_t)aacc, "layout col_idx")) ||
+      (with_t && (rc = dev_alloc(c, &c->trp_lay, (size_t)nacc + 1, "layout transposed row_ptr"))) ||
+      (with_t && (rc = dev_alloc(c, &c->tci_lay, (size_t)aacc, "layout transposed col_idx")))) {
+    dev_release(c, d_aoff);
+    free_layout(c);
+    return rc;
+  }
+  int32_t *d_goff = c->comp_node_off;  // base offsets of the graphs (device)
+  hipError_t e = hipMemcpyAsync(c->lay_blk, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->lay_node_off, off.data(), sizeof(int32_t) * (L + 1), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->lay_n, n.data(), sizeof(int32_t) * L, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_aoff, aoff.data(), sizeof(int32_t) * (L + 1), hipMemcpyHostToDevice, c->stream);
+  PassArgs la{};
+  la.batch.blk_comp = c->lay_blk;
+  la.batch.comp_node_off = c->lay_node_off;
+  la.batch.n_lay = L;
+  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
+  if (e == hipSuccess)
+    e = launch_expand(d_goff, c->rp_own, c->ci_own, copies, la, d_aoff, c->rp_lay, c->ci_lay, nacc, aacc, c->st,
+                      c->stream);
+  if (e == hipSuccess && with_t)
+    e = launch_expand(d_goff, c->trp, c->tci, copies, la, d_aoff, c->trp_lay, c->tci_lay, nacc, aacc, c->st, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_release(c, d_aoff);
+  if (e != hipSuccess) {
+    free_layout(c);
+    return hip_fail(c, e, "batch row layout");
+  }
+  c->rp = c->rp_lay;
+  c->ci = c->ci_lay;
+  c->n = (int32_t)nacc;
+  c->arcs = aacc;
+  c->n_lay = L;
+  c->lay_node_off_h = off;
+  c->lay_n_h = n;
+  c->copies = copies;
+  c->layout_ok = true;
+  return HANF_OK;
+}
+
+// The switches compare changed counters with the number of counters, n S.
 int64_t dense_threshold(const hanf_ctx *c) {
   if (c->dense_div <= 0) return 0;
-  return std::max<int64_t>(1, (int64_t)c->n / c->dense_div);
+  return std::max<int64_t>(1, ((int64_t)c->n << c->sl) / c->dense_div);
 }
 
 // Systolic passes need the transposed graph and the signal buffers of the run.
@@ -583,6 +738,11 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
     case HANF_OPT_SYSTOLIC:
       if (value < 0 || value > (1 << 30)) return fail(c, HANF_EINVAL, "systolic switch out of range");
       c->sys_div = (int)value;
+      break;
+    case HANF_OPT_SEEDS_PER_ROW:
+      if (value < 0 || value > 32 || (value & (value - 1)) != 0)
+        return fail(c, HANF_EINVAL, "seeds per row must be 0 or a power of two up to 32");
+      c->seeds_row_opt = (int)value;
       break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
@@ -717,10 +877,12 @@ int hanf_build_transpose(hanf_ctx *c) {
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   free_transpose(c);
   c->inited = false;
+  int rc;
+  // a batch's transpose is built on its base; the next initialisation lays it out with the graph
+  if (c->batch && (rc = set_layout(c, 1))) return rc;
   const int32_t n = c->n;
   const int64_t arcs = c->arcs;
   uint64_t *keys = nullptr, *tmp = nullptr;
-  int rc;
   if ((rc = dev_alloc(c, &c->trp_own, (size_t)n + 1, "transposed row_ptr")) ||
       (rc = dev_alloc(c, &c->tci_own, (size_t)arcs, "transposed col_idx")) ||
       (rc = dev_alloc(c, &keys, (size_t)n + 1, "in-degrees")) ||
@@ -754,8 +916,17 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
   if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  const int G = 1 << (log2m - 4);
   int rc;
+  int sl = 0;
+  if (c->batch) {
+    // counters per row: as many seeds as fit, a power of two, at most 32, rows <= 1024 bytes
+    const int m = 1 << log2m;
+    int S = 1;
+    while (S < c->n_seeds && S < 32 && 2 * S * m <= 1024 && (c->seeds_row_opt == 0 || S < c->seeds_row_opt)) S *= 2;
+    while ((1 << sl) < S) ++sl;
+    if ((rc = set_layout(c, (c->n_seeds + S - 1) / S))) return rc;
+  }
+  const int G = (1 << (log2m - 4)) << sl;  // lanes per node row
   Schedule want;
   choose_schedule(c, G, want);
   if (c->sch.G != G || !c->sch.light || want.light_max != c->sch.light_max ||
@@ -763,8 +934,26 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
     if ((rc = build_schedule(c, G))) return rc;
   }
   const int64_t want_cap = default_max_passes(c) + 2;
-  if (c->log2m != log2m || !c->regs[0] || want_cap != c->nt_cap) {
-    if ((rc = alloc_run(c, log2m))) return rc;
+  if (c->log2m != log2m || c->sl != sl || !c->regs[0] || want_cap != c->nt_cap) {
+    if ((rc = alloc_run(c, log2m, sl))) return rc;
+  }
+  if (c->batch) {  // which result component every row seed of every layout component runs
+    const int32_t S = 1 << sl;
+    std::vector<int32_t> slot((size_t)c->n_lay * S, -1);
+    c->comp_row_h.assign((size_t)c->n_comp, 0);
+    for (int32_t g = 0; g < c->n_graphs; ++g)
+      for (int32_t sd = 0; sd < c->n_seeds; ++sd) {
+        const int32_t row = (g * c->copies + sd / S) * S + sd % S;
+        slot[(size_t)row] = g * c->n_seeds + sd;
+        c->comp_row_h[(size_t)g * c->n_seeds + sd] = row;
+      }
+    HIP_TRY(c, hipMemcpyAsync(c->slot_comp, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice,
+                              c->stream),
+            "row seed upload");
+    HIP_TRY(c, hipMemcpyAsync(c->comp_row, c->comp_row_h.data(), sizeof(int32_t) * c->n_comp, hipMemcpyHostToDevice,
+                              c->stream),
+            "component row upload");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "row tables");  // the host vectors are reused
   }
   if (c->trp && !c->todo) {  // signal buffers for systolic passes
     if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals")) ||
@@ -1052,23 +1241,20 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
     if (arc_off[g + 1] < arc_off[g]) return fail(c, HANF_EINVAL, "arc_off decreases");
   }
   const int32_t N = graph_off[n_graphs];
-  // component layout
-  const int32_t C = n_graphs * n_seeds;
+  // the base: every graph once, each starting on a 64-node boundary
+  const int32_t C = n_graphs;
   std::vector<int32_t> node_off((size_t)C + 1), comp_aoff((size_t)C + 1), ncomp((size_t)C);
   int64_t nacc = 0, aacc = 0;
   for (int32_t g = 0; g < n_graphs; ++g) {
     const int64_t ng = graph_off[g + 1] - graph_off[g];
     const int64_t ag = (int64_t)arc_off[g + 1] - arc_off[g];
-    for (int32_t sd = 0; sd < n_seeds; ++sd) {
-      const int32_t k = g * n_seeds + sd;
-      node_off[k] = (int32_t)nacc;
-      comp_aoff[k] = (int32_t)aacc;
-      ncomp[k] = (int32_t)ng;
-      nacc += (ng + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
-      aacc += ag;
-      if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
-        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
-    }
+    node_off[g] = (int32_t)nacc;
+    comp_aoff[g] = (int32_t)aacc;
+    ncomp[g] = (int32_t)ng;
+    nacc += (ng + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
+    aacc += ag;
+    if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
+      return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
   }
   node_off[C] = (int32_t)nacc;
   comp_aoff[C] = (int32_t)aacc;
@@ -1130,12 +1316,13 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
   c->batch = true;
   c->n_graphs = n_graphs;
   c->n_seeds = n_seeds;
-  c->n_comp = C;
+  c->n_comp = n_graphs * n_seeds;
+  c->n_lay = C;
   c->n = (int32_t)n_exp;
   c->arcs = e_exp;
   fill_args(c);
   if (e == hipSuccess)
-    e = launch_expand(d_goff, d_rp, d_ci, n_seeds, c->args, d_aoff, c->rp_own, c->ci_own, n_exp, e_exp, c->st, c->stream);
+    e = launch_expand(d_goff, d_rp, d_ci, 1, c->args, d_aoff, c->rp_own, c->ci_own, n_exp, e_exp, c->st, c->stream);
   if (e != hipSuccess) {
     cleanup();
     free_graph(c);
@@ -1153,11 +1340,7 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
     return fail(c, HANF_EINVAL, (er & 32) ? "an arc leaves its graph"
                                 : (er & 64) ? "arc_off disagrees with row_ptr" : "malformed CSR");
   }
-  c->rp = c->rp_own;
-  c->ci = c->ci_own;
-  c->comp_node_off_h = node_off;
-  c->comp_n_h = ncomp;
-  c->graph_ok = true;
+  set_base(c, node_off, ncomp, comp_aoff);
   return HANF_OK;
 }
 
@@ -1183,20 +1366,18 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
   }
   goff[n_graphs] = (int32_t)nacc;
   aoff[n_graphs] = (int32_t)aacc;
-  const int32_t C = n_graphs * n_seeds;
+  const int32_t C = n_graphs;  // the base: every graph once, 64-node aligned
   std::vector<int32_t> node_off((size_t)C + 1), comp_aoff((size_t)C + 1), ncomp((size_t)C);
   int64_t en = 0, ea = 0;
-  for (int32_t g = 0; g < n_graphs; ++g)
-    for (int32_t sd = 0; sd < n_seeds; ++sd) {
-      const int32_t k = g * n_seeds + sd;
-      node_off[k] = (int32_t)en;
-      comp_aoff[k] = (int32_t)ea;
-      ncomp[k] = n_nodes[g];
-      en += ((int64_t)n_nodes[g] + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
-      ea += n_arcs[g];
-      if (en >= (int64_t)INT32_MAX - kNodesPerBlock || ea >= (int64_t)INT32_MAX)
-        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
-    }
+  for (int32_t g = 0; g < n_graphs; ++g) {
+    node_off[g] = (int32_t)en;
+    comp_aoff[g] = (int32_t)ea;
+    ncomp[g] = n_nodes[g];
+    en += ((int64_t)n_nodes[g] + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
+    ea += n_arcs[g];
+    if (en >= (int64_t)INT32_MAX - kNodesPerBlock || ea >= (int64_t)INT32_MAX)
+      return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
+  }
   node_off[C] = (int32_t)en;
   comp_aoff[C] = (int32_t)ea;
   std::vector<int32_t> blk((size_t)(en / kNodesPerBlock));
@@ -1249,13 +1430,14 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
   c->batch = true;
   c->n_graphs = n_graphs;
   c->n_seeds = n_seeds;
-  c->n_comp = C;
+  c->n_comp = n_graphs * n_seeds;
+  c->n_lay = C;
   c->n = (int32_t)en;
   c->arcs = ea;
   fill_args(c);
   if (e == hipSuccess)
-    e = launch_expand_local(d_goff, d_gaoff, d_rp, d_ci, n_graphs, n_seeds, c->args, d_aoff, c->rp_own, c->ci_own, en,
-                            ea, c->st, c->stream);
+    e = launch_expand_local(d_goff, d_gaoff, d_rp, d_ci, n_graphs, 1, c->args, d_aoff, c->rp_own, c->ci_own, en, ea,
+                            c->st, c->stream);
   if (e != hipSuccess) {
     cleanup();
     free_graph(c);
@@ -1271,11 +1453,7 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
     free_graph(c);
     return fail(c, HANF_EINVAL, "malformed CSR in the batch");
   }
-  c->rp = c->rp_own;
-  c->ci = c->ci_own;
-  c->comp_node_off_h = node_off;
-  c->comp_n_h = ncomp;
-  c->graph_ok = true;
+  set_base(c, node_off, ncomp, comp_aoff);
   return HANF_OK;
 }
 
@@ -1315,13 +1493,18 @@ int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t b
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_registers: NULL context");
   if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
   if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
-  if (bytes != (int64_t)c->comp_n_h[comp] << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n_graph * m");
+  const int32_t row = c->comp_row_h[comp];
+  const int32_t L = row >> c->sl, j = row & ((1 << c->sl) - 1);
+  const size_t m = (size_t)1 << c->log2m, R = m << c->sl;
+  const int32_t ng = c->lay_n_h[L];
+  if (bytes != (int64_t)ng * (int64_t)m) return fail(c, HANF_EINVAL, "bytes must be n_graph * m");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   if ((rc = read_state(c))) return rc;
-  const uint8_t *src = c->regs[c->st_host->t & 1] + ((size_t)c->comp_node_off_h[comp] << c->log2m);
-  HIP_TRY(c, hipMemcpyAsync(out, src, (size_t)bytes,
-                            flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+  // counter j of every row of the component's nodes: a strided copy
+  const uint8_t *src = c->regs[c->st_host->t & 1] + (size_t)c->lay_node_off_h[L] * R + (size_t)j * m;
+  HIP_TRY(c, hipMemcpy2DAsync(out, m, src, R, m, (size_t)ng,
+                              flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
           "register read");
   return sync(c, "register read");
 }

@@ -54,17 +54,25 @@ struct Heavy {   // a node split in several chunks, combined by the finalize ker
 
 enum ReduceMode : int32_t { kReduceInit = 0, kReducePass = 1 };
 
-// Layout of a batched run: independent components (graph, hash seed) laid side by side as
-// one graph, each starting on a 64-node boundary so that no estimate block straddles two.
+// Layout of a batched run. Its results are components c = (graph g, seed s), independent
+// runs. Every node row holds S = 2^seed_log2 counters ("row seeds" j = 0..S-1), so the
+// graphs are laid side by side as one graph in copies ("layout components" L), each
+// starting on a 64-node boundary so that no estimate block straddles two; copy L of graph g
+// carries seeds q*S .. q*S+S-1 of g in its rows (q = L mod copies). Row seeds beyond the
+// graph's seeds hold empty counters that never change.
 struct BatchArgs {
-  const int32_t *blk_comp;       // component of every 64-node block
-  const int32_t *comp_node_off;  // first node of every component, n_comp + 1 entries
-  const int32_t *comp_n;         // real nodes of every component (the rest are empty padding)
-  const uint64_t *comp_seed;     // hash seed of every component
-  int32_t *blkcnt;               // counters changed per block in the last pass
-  int32_t *comp_T;               // fixpoint iteration of every component, -1 while it changes
+  const int32_t *blk_comp;       // layout component of every 64-node block
+  const int32_t *comp_node_off;  // first node of every layout component, n_lay + 1 entries
+  const int32_t *comp_n;         // real nodes of every layout component (the rest are padding)
+  const int32_t *slot_comp;      // result component of row seed j of layout component L at
+                                 //   [L * S + j], or -1 for an empty row seed
+  const int32_t *comp_row;       // L * S + j of every result component
+  const uint64_t *comp_seed;     // hash seed of every result component
+  int32_t *blkcnt;               // counters changed per (block, row seed) in the last pass
+  int32_t *comp_T;               // fixpoint iteration of every result component, -1 while it changes
   double *comp_nt;               // N_hat history: comp_nt[c * nt_cap + t]
-  int32_t n_comp;
+  int32_t n_comp;                // result components
+  int32_t n_lay;                 // layout components
   int32_t active;                // 1 for a batched run
 };
 
@@ -72,10 +80,12 @@ struct BatchArgs {
 struct PassArgs {
   const int32_t *row_ptr;
   const int32_t *col_idx;
-  uint8_t *regs0, *regs1;    // regs[t & 1] = c_t, regs[(t+1) & 1] = c_{t+1}
-  uint32_t *bits0, *bits1;   // changed flags: bits[t & 1] written by pass t-1, bits[(t+1) & 1] by pass t
-  double *est;               // per-node estimate of the current counter
-  double *blocksum;          // per 64 nodes
+  uint8_t *regs0, *regs1;    // regs[t & 1] = c_t, regs[(t+1) & 1] = c_{t+1}; a row of S counters
+                             //   of m bytes per node (row seed j at byte j * m)
+  uint32_t *bits0, *bits1;   // changed flags, S bits per node (bit v * S + j): bits[t & 1] written
+                             //   by pass t-1, bits[(t+1) & 1] by pass t
+  double *est;               // estimate of every current counter, [v * S + j]
+  double *blocksum;          // per 64 nodes and row seed, [b * S + j]
   double *wgsum;             // per reduce workgroup
   int64_t *wgcnt;            // per reduce workgroup: changed counters
   int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read}
@@ -98,7 +108,9 @@ struct PassArgs {
   const double *lc;          // linear-counting table m ln(m/V), V = 0..m
   double K;                  // alpha_m m^2 2^31
   int32_t n;
-  int32_t log2m;
+  int32_t log2m;             // m = 2^log2m registers per counter
+  int32_t seed_log2;         // S = 2^seed_log2 counters per node row (1 for a single run)
+  int32_t gs;                // lanes per counter, m / 16 (a row has S * gs lanes)
   int32_t n_blocks;          // ceil(n / 64)
   int32_t n_chunks;
   int32_t n_chunk_wgs;       // union workgroups given to chunks (multiple of 8)

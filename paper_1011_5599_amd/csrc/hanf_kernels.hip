@@ -1,16 +1,20 @@
 // HIP kernels for gfx950 (CDNA4): HyperANF's iteration (Boldi, Rosa, Vigna, Algorithm 2)
 // over HyperLogLog counters (Algorithm 1).
 //
-// Data layout in HBM:
-//   regs[2]   uint8 [n][m]     counters c_t and c_{t+1}, node-major, m = 2^log2m bytes each
-//   bits[2]   uint32 [2 * ceil(n/64)]  modified-counter flags of the previous / current pass
-//   est       double [n]       estimate of each current counter
-//   blocksum  double [ceil(n/64)]  cached estimate sums per 64 consecutive nodes
+// Data layout in HBM (S = counters per node row: 1 for a single run, up to 32 seeds of a
+// batched run side by side):
+//   regs[2]   uint8 [n][S][m]  counters c_t and c_{t+1}, node-major, m = 2^log2m bytes each
+//   bits[2]   uint32 [2 * S * ceil(n/64)]  modified-counter flags (S bits per node) of the
+//             previous / current pass
+//   est       double [n][S]    estimate of each current counter
+//   blocksum  double [ceil(n/64)][S]  cached estimate sums per 64 consecutive nodes
 //
 // One pass (c_t -> c_{t+1}) is one launch of k_union (+ k_finalize when a node's arcs are
 // split over several wavefronts) and two reduction launches. The union is bound by HBM
 // bandwidth: random gathers of m-byte successor counters. Lanes load counters 16 bytes at a
-// time; a counter is handled by G = m/16 lanes (a "slot"); a wavefront holds W = 64/G slots.
+// time; a node row (S counters) is handled by G = S*m/16 lanes (a "slot"); a wavefront holds
+// W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
+// read, one S*m-byte gather); changes, flags and estimates are kept per counter.
 //   - light nodes (few arcs): one slot per node, nodes of a tile sorted by degree so the
 //     slots of a wavefront finish together; tiles are assigned to XCDs in contiguous runs
 //     so neighbouring ids (and their shared successors) meet in the same L2;
@@ -50,8 +54,11 @@ __device__ __forceinline__ void strow(uint8_t *regs, int32_t v, int m, int sub, 
   *reinterpret_cast<uint4 *>(regs + (size_t)v * (size_t)m + (size_t)sub * 16) = x;
 }
 
-__device__ __forceinline__ bool testbit(const uint32_t *bits, int32_t v) {
-  return (bits[v >> 5] >> (v & 31)) & 1u;
+// Was any counter of node v's row modified? (S = 2^sl flag bits per node, never across words.)
+__device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl) {
+  const uint64_t i = (uint64_t)v << sl;
+  const uint32_t field = sl == 5 ? 0xffffffffu : ((1u << (1u << sl)) - 1u);
+  return ((bits[i >> 5] >> (i & 31)) & field) != 0u;
 }
 
 __device__ __forceinline__ uint4 shfl_xor4(uint4 a, int off) {
@@ -72,12 +79,11 @@ __device__ __forceinline__ uint64_t splitmix64_output(uint64_t seed, uint64_t k)
 
 // ------------------------------------------------------------------ estimator (Algorithm 1 size)
 
-// size() of the counter held by the G lanes of a slot (16 registers per lane), with the
-// HyperLogLog small-range rule. S = sum_j 2^(31 - M[j]) is an exact integer (<= 2^39), so
-// raw = alpha m^2 / sum_j 2^-M[j] = K / S with K = alpha m^2 2^31 takes one IEEE division.
-// All G lanes of the slot must be active; every lane returns the estimate.
-template <int G>
-__device__ __forceinline__ double slot_estimate(uint4 acc, const double *lc, double K) {
+// size() of the counter held by an aligned group of gs lanes (16 registers per lane), with
+// the HyperLogLog small-range rule. S = sum_j 2^(31 - M[j]) is an exact integer (<= 2^39),
+// so raw = alpha m^2 / sum_j 2^-M[j] = K / S with K = alpha m^2 2^31 takes one IEEE
+// division. All lanes of the group must be active; every lane returns the estimate.
+__device__ __forceinline__ double slot_estimate(uint4 acc, const double *lc, double K, int gs) {
   const uint32_t w[4] = {acc.x, acc.y, acc.z, acc.w};
   uint64_t S = 0;
   uint32_t V = 0;
@@ -90,14 +96,13 @@ __device__ __forceinline__ double slot_estimate(uint4 acc, const double *lc, dou
       V += (r == 0u);
     }
   }
-#pragma unroll
-  for (int off = 1; off < G; off <<= 1) {
+  for (int off = 1; off < gs; off <<= 1) {
     const uint32_t lo = __shfl_xor((uint32_t)S, off);
     const uint32_t hi = __shfl_xor((uint32_t)(S >> 32), off);
     S += ((uint64_t)hi << 32) | lo;
     V += __shfl_xor(V, off);
   }
-  const double m = 16.0 * G;
+  const double m = 16.0 * gs;
   const double raw = K / (double)S;
   return (raw <= 2.5 * m && V > 0u) ? lc[V] : raw;
 }
@@ -113,6 +118,7 @@ struct Flags {
   bool copy_check;            // next[v] may hold c_{t-1}[v] != c_t[v]: copy when v was modified
   bool systolic;              // only nodes in `todo` (signalled by a modified successor) may change
   const uint8_t *todo;
+  int sl;                     // log2 of the counters per node row
 };
 
 __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *st) {
@@ -127,6 +133,7 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *s
   f.copy_check = !first;
   f.systolic = !f.gather_all && st->systolic;
   f.todo = a.todo;
+  f.sl = a.seed_log2;
   return f;
 }
 
@@ -137,16 +144,17 @@ struct Counters {
 // Writes c_{t+1}[v] for the node of a slot, given `acc`, the max over the successors
 // maximised in (and over c_t[v] when own_loaded). Called with all 64 lanes active; idle
 // slots pass v < 0. Keeps the two register buffers consistent without copying unchanged
-// counters: next[v] already equals c_t[v] unless v was modified by the previous pass.
+// rows: next[v] already equals c_t[v] unless v was modified by the previous pass. Changes
+// and estimates are per counter: counter j of the row is lanes j*gs .. j*gs+gs-1.
 template <int G>
 __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f, int32_t v, int lane,
                                               uint4 acc, bool any, bool own_loaded, uint4 own,
                                               Counters &cnt) {
-  constexpr int m = 16 * G;
+  constexpr int R = 16 * G;  // row bytes
   const int sub = lane % G;
-  const bool pv = (v >= 0 && f.copy_check) ? testbit(f.prev_bits, v) : false;
+  const bool pv = (v >= 0 && f.copy_check) ? node_mod(f.prev_bits, v, f.sl) : false;
   const bool work = v >= 0 && (any || pv);
-  if (work && !own_loaded) own = ldrow(f.cur, v, m, sub);
+  if (work && !own_loaded) own = ldrow(f.cur, v, R, sub);
   if (work) {
     acc = bytemax4(acc, own);
     if (sub == 0) cnt.read++;
@@ -155,16 +163,24 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
   const uint64_t bal = __ballot(diff);
   const int first_lane = lane & ~(G - 1);
   const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-  const bool changed = ((bal >> first_lane) & gmask) != 0ull;
+  const uint64_t rowbits = (bal >> first_lane) & gmask;  // lanes of this row that changed
+  const bool changed = rowbits != 0ull;
   if (work && (changed || pv)) {
-    strow(f.nxt, v, m, sub, acc);
+    strow(f.nxt, v, R, sub, acc);
     if (sub == 0) cnt.written++;
   }
-  if (changed) {
-    const double E = slot_estimate<G>(acc, a.lc, a.K);
+  if (changed) {  // uniform over the row's lanes
+    const int gs = a.gs;
+    const uint64_t smask = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
+    const double E = slot_estimate(acc, a.lc, a.K, gs);
+    const int j = sub / gs;  // counter of this lane
+    if (sub % gs == 0 && ((rowbits >> (j * gs)) & smask)) a.est[((size_t)v << f.sl) + j] = E;
     if (sub == 0) {
-      a.est[v] = E;
-      atomicOr(&f.cur_bits[v >> 5], 1u << (v & 31));
+      uint32_t mask = 0u;
+      for (int k = 0; k < (G / gs); ++k)
+        if ((rowbits >> (k * gs)) & smask) mask |= 1u << k;
+      const uint64_t bit = (uint64_t)v << f.sl;
+      atomicOr(&f.cur_bits[bit >> 5], mask << (bit & 31));
     }
   }
 }
@@ -206,7 +222,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     }
     if (!f.gather_all) {
 #pragma unroll
-      for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
     }
     int32_t total = 0;
 #pragma unroll
@@ -276,7 +292,7 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
     const int32_t deg = r1 - r0;
     const bool heavy = valid && deg > light_max;
     bool act = valid && deg > 0 && !heavy &&
-               (testbit(f.prev_bits, v) || (f.systolic && f.todo[v] != 0));
+               (node_mod(f.prev_bits, v, f.sl) || (f.systolic && f.todo[v] != 0));
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const uint64_t hmask = __ballot(heavy);
@@ -299,7 +315,7 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
           }
 #pragma unroll
           for (int k = 0; k < U; ++k) {
-            const bool h = ok[k] && testbit(f.prev_bits, w[k]);
+            const bool h = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
             if (__any(h)) {
               int32_t src = -1;
               if (h) {  // source node: the last j in [j0, j1) with rps[j] <= arc
@@ -381,7 +397,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     }
     if (!f.gather_all) {
 #pragma unroll
-      for (int k = 0; k < U; ++k) ok[k] = ok[k] && testbit(f.prev_bits, w[k]);
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
     }
     int32_t total = 0;
 #pragma unroll
@@ -571,9 +587,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
 }
 
 // Per 64-node block, one lane each: re-sum the estimates where a counter changed (else
-// reuse the cached sum, Section 3.3), count changed counters, clear the flags of the
+// reuse the cached sums, Section 3.3), count changed counters, clear the flags of the
 // previous pass (and the signals of a systolic pass). A workgroup covers kReduceBlocks
-// consecutive blocks, a quarter per wavefront; sums are taken in a fixed order.
+// consecutive blocks, a quarter per wavefront; sums are taken in a fixed order. With S
+// counters per node a block has 2S flag words and S sums (one per row seed).
 __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int32_t force) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -584,15 +601,25 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
   uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
   const bool sys = st->systolic != 0;  // this pass's signals are cleared with its flags
+  const int sl = a.seed_log2, S = 1 << sl, WB = 2 * S;  // flag words per block
   constexpr int kPerWave = kReduceBlocks / (kBlockThreads / kWave);  // blocks per wavefront
   const int64_t b0 = (int64_t)blockIdx.x * kReduceBlocks + wave * kPerWave;  // the wavefront's first block
   const int64_t b = b0 + lane;
   const bool valid = lane < kPerWave && b < a.n_blocks;
-  uint2 w = make_uint2(0u, 0u);
-  if (valid && !force) w = reinterpret_cast<const uint2 *>(cb)[b];
-  const bool dirty = valid && (force || (w.x | w.y));
-  double bs = (valid && !dirty) ? a.blocksum[b] : 0.0;
-  // the dirty blocks of the wavefront, 4 at a time: 64 estimates each, summed across lanes
+  uint32_t any = 0u;
+  int32_t bc = 0;
+  if (valid && !force) {
+    for (int k = 0; k < WB; ++k) {
+      const uint32_t w = cb[b * WB + k];
+      any |= w;
+      bc += __popc(w);
+    }
+  }
+  const bool dirty = valid && (force || any != 0u);
+  double bs = (S == 1 && valid && !dirty) ? a.blocksum[b] : 0.0;
+  // the dirty blocks of the wavefront, 4 at a time: each block's 64 S estimates are read 64
+  // per step; lane l always holds row seed l mod S, so a butterfly over the offsets S..32
+  // leaves seed j's block sum in lane j
   uint64_t pend = __ballot(dirty);
   while (pend) {
     int32_t jb[4];
@@ -601,32 +628,43 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     for (int k = 0; k < 4; ++k) {
       jb[k] = pend ? __ffsll((long long)pend) - 1 : -1;
       if (pend) pend &= pend - 1;
+      e[k] = 0.0;
     }
+    for (int r = 0; r < S; ++r) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int64_t v = (b0 + jb[k]) * kNodesPerBlock + lane;
-      e[k] = (jb[k] >= 0 && v < a.n) ? a.est[v] : 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const int64_t ei = ((b0 + jb[k]) * kNodesPerBlock << sl) + (int64_t)r * kWave + lane;
+        if (jb[k] >= 0 && (ei >> sl) < a.n) e[k] += a.est[ei];
+      }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (jb[k] >= 0) {  // wavefront-uniform
-        const double sum = wave_sum(e[k]);
-        if (lane == jb[k]) {
-          bs = sum;
-          a.blocksum[b] = sum;
-        }
+        double sum = e[k];
+        for (int off = S; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
+        if (lane < S) a.blocksum[((b0 + jb[k]) << sl) + lane] = sum;
+        if (S == 1 && lane == jb[k]) bs = sum;
       }
     }
   }
-  const int32_t bc = __popc(w.x) + __popc(w.y);
-  if (valid && a.batch.active) a.batch.blkcnt[b] = bc;
-  if (valid && !force) reinterpret_cast<uint2 *>(pb)[b] = make_uint2(0u, 0u);
+  if (valid && a.batch.active) {
+    // changed counters of every row seed j: its flag bits are j, j+S, ... in every word
+    const uint32_t pattern = sl == 5 ? 1u : 0xffffffffu / ((1u << S) - 1u);
+    for (int jj = 0; jj < S; ++jj) {
+      int32_t cj = 0;
+      if (!force)
+        for (int k = 0; k < WB; ++k) cj += __popc(cb[b * WB + k] & (pattern << jj));
+      a.batch.blkcnt[(b << sl) + jj] = cj;
+    }
+  }
+  if (valid && !force)
+    for (int k = 0; k < WB; ++k) pb[b * WB + k] = 0u;
   if (valid && sys) {
     uint4 *tq = reinterpret_cast<uint4 *>(a.todo + b * kNodesPerBlock);
 #pragma unroll
     for (int k = 0; k < kNodesPerBlock / 16; ++k) tq[k] = make_uint4(0u, 0u, 0u, 0u);
   }
-  const double ws = wave_sum(bs);
+  const double ws = wave_sum(bs);  // the total estimate; meaningful for one counter per node
   const int32_t wc = wave_sum(bc);
   if (lane == 0) {
     s_sum[wave] = ws;
@@ -639,8 +677,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   }
 }
 
-// Batched runs: N_hat and changed count of every component (one workgroup per component,
-// fixed summation order over its blocks). Marks a component's fixpoint T the first time a
+// Batched runs: N_hat and changed count of every result component (one workgroup per
+// component, fixed summation order over its blocks' sums of its row seed). Marks a component's fixpoint T the first time a
 // pass leaves it unchanged; until then appends N_hat(t+1) to its history.
 __global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a, int32_t mode) {
   const DevState *st = a.st;
@@ -649,12 +687,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a,
   __shared__ int64_t s_cnt[kBlockThreads];
   const int32_t c = blockIdx.x;
   const int tid = threadIdx.x;
-  const int32_t b0 = a.batch.comp_node_off[c] / kNodesPerBlock, b1 = a.batch.comp_node_off[c + 1] / kNodesPerBlock;
+  const int sl = a.seed_log2;
+  const int32_t row = a.batch.comp_row[c];
+  const int32_t L = row >> sl, jj = row & ((1 << sl) - 1);
+  const int32_t b0 = a.batch.comp_node_off[L] / kNodesPerBlock, b1 = a.batch.comp_node_off[L + 1] / kNodesPerBlock;
   double sum = 0.0;
   int64_t cnt = 0;
   for (int32_t b = b0 + tid; b < b1; b += kBlockThreads) {
-    sum += a.blocksum[b];
-    if (mode == kReducePass) cnt += a.batch.blkcnt[b];
+    sum += a.blocksum[((size_t)b << sl) + jj];
+    if (mode == kReducePass) cnt += a.batch.blkcnt[((size_t)b << sl) + jj];
   }
   s_sum[tid] = sum;
   s_cnt[tid] = cnt;
@@ -703,7 +744,7 @@ __global__ void k_expand(const int32_t *graph_off, const int32_t *rp_in, const i
   }
   int32_t err = 0;
   for (int64_t j = gid; j < e_exp; j += stride) {
-    int32_t lo = 0, hi = a.batch.n_comp;  // component with comp_arc_off[c] <= j < comp_arc_off[c+1]
+    int32_t lo = 0, hi = a.batch.n_lay;  // component with comp_arc_off[c] <= j < comp_arc_off[c+1]
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
       if (comp_arc_off[mid] <= j) lo = mid; else hi = mid;
@@ -751,7 +792,7 @@ __global__ void k_expand_local(const int32_t *graph_off, const int32_t *arc_off,
     }
   }
   for (int64_t j = gid; j < e_exp; j += stride) {
-    int32_t lo = 0, hi = a.batch.n_comp;
+    int32_t lo = 0, hi = a.batch.n_lay;
     while (hi - lo > 1) {
       const int32_t mid = (lo + hi) >> 1;
       if (comp_arc_off[mid] <= j) lo = mid; else hi = mid;
@@ -837,10 +878,10 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       st->changed_last = rec.changed;
       st->first_pass = 0;
       st->dense_next = (st->dense_threshold > 0 && rec.changed >= st->dense_threshold) ? 1 : 0;
-      // Section 3.3, systolic computation: once fewer than n / sys_div counters changed, the
-      // next pass recomputes only the nodes their changes signal
+      // Section 3.3, systolic computation: once fewer than n S / sys_div counters changed,
+      // the next pass recomputes only the nodes their changes signal
       st->systolic = (!st->dense_next && st->frontier && st->sys_div > 0 &&
-                      rec.changed * (int64_t)st->sys_div < (int64_t)a.n) ? 1 : 0;
+                      rec.changed * (int64_t)st->sys_div < ((int64_t)a.n << a.seed_log2)) ? 1 : 0;
       st->sys_acc = 0ull;
       st->sys_units = 0;
       if (rec.changed == 0) {
@@ -898,7 +939,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_list(PassArgs a) {
   constexpr int NW = kBlockThreads / kWave;
   __shared__ unsigned long long s_tot[kSigRounds * NW];
   __shared__ unsigned long long s_base;
-  const int64_t nwords = 2 * (int64_t)a.n_blocks;
+  const int sl = a.seed_log2, S = 1 << sl;
+  const uint32_t field = sl == 5 ? 0xffffffffu : ((1u << S) - 1u);  // one node's flag bits
+  const int64_t nwords = 2 * ((int64_t)a.n_blocks << sl);
   const int64_t base = (int64_t)blockIdx.x * (kBlockThreads * kSigRounds);
   uint32_t word[kSigRounds];
   unsigned long long own[kSigRounds], incl[kSigRounds];
@@ -907,8 +950,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_list(PassArgs a) {
     const int64_t wi = base + r * kBlockThreads + threadIdx.x;  // one flag word per thread and round
     word[r] = wi < nwords ? pb[wi] : 0u;
     uint32_t cnt = 0, deg = 0;
-    for (uint32_t x = word[r]; x; x &= x - 1) {
-      const int64_t v = wi * 32 + __ffs(x) - 1;
+    for (uint32_t x = word[r]; x;) {  // each modified node once, whatever counters of it changed
+      const int64_t i = wi * 32 + __ffs(x) - 1;
+      x &= ~(field << (i & 31 & ~(S - 1)));
+      const int64_t v = i >> sl;
       const int32_t d = v < a.n ? a.trow_ptr[v + 1] - a.trow_ptr[v] : 0;
       if (d > 0) {
         cnt++;
@@ -936,8 +981,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_list(PassArgs a) {
     const unsigned long long off = s_base + s_tot[r * NW + wave] + incl[r] - own[r];
     int32_t idx = (int32_t)(off >> 32);
     int32_t pos = (int32_t)(off & 0xffffffffull);
-    for (uint32_t x = word[r]; x; x &= x - 1) {
-      const int64_t v = wi * 32 + __ffs(x) - 1;
+    for (uint32_t x = word[r]; x;) {
+      const int64_t i = wi * 32 + __ffs(x) - 1;
+      x &= ~(field << (i & 31 & ~(S - 1)));
+      const int64_t v = i >> sl;
       const int32_t d = v < a.n ? a.trow_ptr[v + 1] - a.trow_ptr[v] : 0;
       if (d > 0) {
         a.sys_node[idx] = (int32_t)v;
@@ -1028,16 +1075,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_units(PassArgs a) {
     bool need = false;
     if (u < a.n_chunks) {
       const int32_t v = a.chunks[u].v;
-      need = a.todo[v] != 0 || ((pb[v >> 5] >> (v & 31)) & 1u);
+      need = a.todo[v] != 0 || node_mod(pb, v, a.seed_log2);
     } else if (u < units) {
       const int32_t tile = (int32_t)(u - a.n_chunks);
       need = a.tile_todo[tile] != 0;
       if (need) {
         a.tile_todo[tile] = 0;  // consumed
-      } else {
-        const int32_t lo = tile * a.tile_nodes;
-        const int32_t hi = min(a.n, lo + a.tile_nodes);
-        for (int32_t w = lo >> 5; w <= (hi - 1) >> 5 && !need; ++w) need = pb[w] != 0u;
+      } else {  // the flag words of the tile's nodes
+        const int64_t lo = (int64_t)tile * a.tile_nodes;
+        const int64_t hi = min((int64_t)a.n, lo + a.tile_nodes);
+        for (int64_t w = (lo << a.seed_log2) >> 5; w <= ((hi << a.seed_log2) - 1) >> 5 && !need; ++w)
+          need = pb[w] != 0u;
       }
     }
     bal[r] = __ballot(need);
@@ -1119,31 +1167,41 @@ __global__ __launch_bounds__(kBlockThreads) void k_transpose_fill(const int32_t 
 
 // ------------------------------------------------------------------ kernels: init
 
-// Algorithm 2's initialisation (add v to c[v]) into both register buffers, its estimate,
-// and cleared modified-counter flags. G lanes per node, 16 registers each.
-template <int G>
-__global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed) {
-  constexpr int m = 16 * G;
-  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
-  if (gid < 2 * (int64_t)a.n_blocks) {
+// Clears the modified-counter flags, the systolic signals and the tile flags (every kernel
+// that starts a run does this first; the grid covers init_lanes() threads).
+__device__ __forceinline__ void clear_run_flags(const PassArgs &a, int64_t gid) {
+  if (gid < 2 * ((int64_t)a.n_blocks << a.seed_log2)) {
     a.bits0[gid] = 0u;
     a.bits1[gid] = 0u;
   }
   if (a.todo && gid < (int64_t)(kNodesPerBlock / 4) * a.n_blocks) reinterpret_cast<uint32_t *>(a.todo)[gid] = 0u;
   if (gid < ((int64_t)a.n_tiles + 3) / 4) reinterpret_cast<uint32_t *>(a.tile_todo)[gid] = 0u;
+}
+
+// Algorithm 2's initialisation (add v to c[v]) into both register buffers, the estimates,
+// and cleared flags. G lanes per node row, 16 registers each; counter j of the row is lanes
+// j*gs .. j*gs+gs-1 and is hashed with its own seed.
+template <int G>
+__global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed) {
+  constexpr int R = 16 * G;
+  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
   if (v64 >= a.n) return;  // whole slots leave together (n * G lanes, G | 256)
   const int32_t v = (int32_t)v64;
+  const int gs = a.gs;
+  const int j = sub / gs;
   // the item hashed is the node's id in its own graph; batched runs have a seed per component
   uint64_t key = (uint64_t)v, sd = seed;
   bool real = true;
   if (a.batch.active) {
-    const int32_t c = a.batch.blk_comp[v / kNodesPerBlock];
-    const int32_t local = v - a.batch.comp_node_off[c];
-    real = local < a.batch.comp_n[c];
+    const int32_t L = a.batch.blk_comp[v / kNodesPerBlock];
+    const int32_t local = v - a.batch.comp_node_off[L];
+    const int32_t c = a.batch.slot_comp[((size_t)L << a.seed_log2) + j];
+    real = local < a.batch.comp_n[L] && c >= 0;
     key = (uint64_t)local;
-    sd = a.batch.comp_seed[c];
+    sd = c >= 0 ? a.batch.comp_seed[c] : 0ull;
   }
   const uint64_t h = splitmix64_output(sd, key + 1);
   const int b = a.log2m;
@@ -1152,34 +1210,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
   int r = rest ? __clzll((long long)rest) + 1 : 64 - b + 1;
   r = r > 31 ? 31 : r;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
-  if (real && (int)(idx >> 4) == sub) {
+  if (real && (int)(idx >> 4) == sub % gs) {
     const uint32_t byte = idx & 15u;
     w[byte >> 2] = (uint32_t)r << (8 * (byte & 3u));
   }
   const uint4 c = make_uint4(w[0], w[1], w[2], w[3]);
-  strow(a.regs0, v, m, sub, c);
-  strow(a.regs1, v, m, sub, c);
-  const double E = slot_estimate<G>(c, a.lc, a.K);
-  if (sub == 0) a.est[v] = E;
+  strow(a.regs0, v, R, sub, c);
+  strow(a.regs1, v, R, sub, c);
+  const double E = slot_estimate(c, a.lc, a.K, gs);
+  if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + j] = E;
 }
 
 // Estimates of every counter of `regs` (resume from a checkpoint) and cleared flags.
 template <int G>
 __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, const uint8_t *regs) {
-  constexpr int m = 16 * G;
+  constexpr int R = 16 * G;
   const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
-  if (gid < 2 * (int64_t)a.n_blocks) {
-    a.bits0[gid] = 0u;
-    a.bits1[gid] = 0u;
-  }
-  if (a.todo && gid < (int64_t)(kNodesPerBlock / 4) * a.n_blocks) reinterpret_cast<uint32_t *>(a.todo)[gid] = 0u;
-  if (gid < ((int64_t)a.n_tiles + 3) / 4) reinterpret_cast<uint32_t *>(a.tile_todo)[gid] = 0u;
+  clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
   if (v64 >= a.n) return;
   const int32_t v = (int32_t)v64;
-  const double E = slot_estimate<G>(ldrow(regs, v, m, sub), a.lc, a.K);
-  if (sub == 0) a.est[v] = E;
+  const int gs = a.gs;
+  const double E = slot_estimate(ldrow(regs, v, R, sub), a.lc, a.K, gs);
+  if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + sub / gs] = E;
 }
 
 // ------------------------------------------------------------------ kernels: graph ingest
@@ -1500,28 +1554,41 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
     case 4: { constexpr int G = 4; EXPR; } break;   \
     case 8: { constexpr int G = 8; EXPR; } break;   \
     case 16: { constexpr int G = 16; EXPR; } break; \
+    case 32: { constexpr int G = 32; EXPR; } break; \
+    case 64: { constexpr int G = 64; EXPR; } break; \
     default: return hipErrorInvalidValue;           \
   }
 
+// Lanes per node row (S counters of m/16 lanes each).
+int row_lanes(const PassArgs &a) { return (1 << (a.log2m - 4)) << a.seed_log2; }
+
+// Threads of the kernels that start a run: one per row lane, and enough to clear the flag
+// words, signal bytes and tile flags.
+int64_t init_lanes(const PassArgs &a) {
+  int64_t lanes = (int64_t)a.n * row_lanes(a);
+  lanes = std::max<int64_t>(lanes, 2 * ((int64_t)a.n_blocks << a.seed_log2));
+  lanes = std::max<int64_t>(lanes, (int64_t)(kNodesPerBlock / 4) * a.n_blocks);
+  lanes = std::max<int64_t>(lanes, ((int64_t)a.n_tiles + 3) / 4);
+  return lanes;
+}
+
 hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s) {
-  const int G = 1 << (a.log2m - 4);
-  const int64_t lanes = (int64_t)a.n * G > 2 * (int64_t)a.n_blocks ? (int64_t)a.n * G : 2 * (int64_t)a.n_blocks;
-  const int grid = grid_for(lanes, kBlockThreads, 1 << 30);
+  const int G = row_lanes(a);
+  const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
   HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_init<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, seed));
   return hipGetLastError();
 }
 
 hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s) {
-  const int G = 1 << (a.log2m - 4);
-  const int64_t lanes = (int64_t)a.n * G > 2 * (int64_t)a.n_blocks ? (int64_t)a.n * G : 2 * (int64_t)a.n_blocks;
-  const int grid = grid_for(lanes, kBlockThreads, 1 << 30);
+  const int G = row_lanes(a);
+  const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
   HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_estimate_all<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, regs));
   return hipGetLastError();
 }
 
 hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s) {
   if (!a.trow_ptr) return hipSuccess;
-  hipLaunchKernelGGL(k_sys_list, dim3(grid_for(2 * (int64_t)a.n_blocks, kBlockThreads * kSigRounds, 1 << 30)),
+  hipLaunchKernelGGL(k_sys_list, dim3(grid_for(2 * ((int64_t)a.n_blocks << a.seed_log2), kBlockThreads * kSigRounds, 1 << 30)),
                      dim3(kBlockThreads), 0, s, a);
   hipLaunchKernelGGL(k_sys_mark, dim3(grid_for(arcs, kMarkTile, 2048)), dim3(kBlockThreads), 0, s, a);
   hipLaunchKernelGGL(k_sys_units, dim3(grid_for((int64_t)a.n_chunks + a.n_tiles, kBlockThreads * kSigRounds, 1 << 30)),
@@ -1551,7 +1618,7 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
 }
 
 hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s) {
-  const int G = 1 << (a.log2m - 4);
+  const int G = row_lanes(a);
   const dim3 block(kBlockThreads);
   if (a.n_chunk_wgs + a.n_light_wgs == 0) return hipSuccess;
   if (full) {
@@ -1590,7 +1657,7 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
 
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
   if (a.n_fin_wgs == 0) return hipSuccess;
-  const int G = 1 << (a.log2m - 4);
+  const int G = row_lanes(a);
   HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
                                         s, a));
   return hipGetLastError();

@@ -3,7 +3,8 @@
 The union kernel's schedule has knobs: the largest node handled by one lane group
 (`light_max`), the arcs per wavefront chunk (`chunk_arcs`), nodes per light tile
 (`tile_nodes`), loads in flight per lane (`unroll`), the gather-all switch
-(`dense_switch`), and, for batched runs, how many graphs share one batch (`group`). The
+(`dense_switch`), and, for batched runs, how many seeds share a node row (`seeds_per_row`)
+and how many graphs share one batch (`group`). The
 best values depend on the degree distribution, m and the batch mix. The tuner runs the
 caller's workload under candidate settings and keeps the fastest, by coordinate descent
 from the defaults. Every setting gives identical results (max is order-free), so tuning
@@ -24,6 +25,7 @@ SPACE = {
 }
 
 DEFAULTS = {"light_max": 64, "chunk_arcs": 0, "tile_nodes": 0, "unroll": 4, "dense_switch": 4}
+# batched runs also tune `seeds_per_row` (0 = as many seeds per node row as fit) and `group`
 
 
 def coordinate_descent(measure, space=None, start=None, sweeps=1, repeats=2, log=None):

@@ -26,12 +26,16 @@ def _mixed_graphs():
     return gs
 
 
-@pytest.mark.parametrize("b,S", [(4, 3), (6, 2), (8, 1)])
-def test_batch_components_equal_their_runs(b, S):
+@pytest.mark.parametrize("b,S,per_row", [(4, 3, 0), (6, 2, 0), (8, 1, 0), (6, 8, 0), (8, 8, 0), (4, 40, 0),
+                                         (6, 8, 1), (6, 8, 2), (5, 5, 4)])
+def test_batch_components_equal_their_runs(b, S, per_row):
+    """Seeds side by side in node rows: 3 seeds (a row of 4, one empty), 8 seeds of m = 64
+    (512-byte rows), m = 256 with 8 seeds (two copies of rows of 4), 40 seeds of m = 16 (two
+    copies of rows of 32), and forced 1, 2 and 4 seeds per row."""
     gs = _mixed_graphs()
     seeds = [1000 * g + 17 * s + 1 for g in range(len(gs)) for s in range(S)]
-    _say(f"[batch] {len(gs)} graphs x {S} seeds, b={b}")
-    with hanf.Batch(0) as bt:
+    _say(f"[batch] {len(gs)} graphs x {S} seeds, b={b}, seeds per row {per_row or 'auto'}")
+    with hanf.Batch(0, seeds_per_row=per_row) as bt:
         bt.load_graphs(gs, S).init(b, seeds)
         bt.run()
         T = bt.fixpoints()
@@ -56,11 +60,11 @@ def test_batch_components_equal_their_runs(b, S):
                         assert st[k] == pytest.approx(sp[k], rel=1e-9, abs=1e-12), k
 
 
-@pytest.mark.parametrize("sys_div", [1, 4])
-def test_batch_systolic_components_equal_their_runs(sys_div):
-    """Systolic passes over a batch (transposed union built on the device)."""
+@pytest.mark.parametrize("sys_div,S,b", [(1, 2, 6), (4, 2, 6), (1, 8, 8), (2, 3, 4)])
+def test_batch_systolic_components_equal_their_runs(sys_div, S, b):
+    """Systolic passes over a batch (transposed base built on the device, laid out with the
+    graph, also in two copies for 8 seeds of m = 256)."""
     gs = _mixed_graphs()
-    S, b = 2, 6
     seeds = [500 + 3 * c for c in range(len(gs) * S)]
     with hanf.Batch(0, systolic=sys_div) as bt:
         bt.load_graphs(gs, S).build_transpose().init(b, seeds)
