@@ -206,6 +206,84 @@ def run_batch_mode(args):
     }
 
 
+def run_seeds_mode(args):
+    """Many runs on one graph (the paper's protocol of many low-precision runs, Section 6):
+    the workload graph with `--seeds` hash seeds, once as one batch whose node rows hold the
+    seeds' counters side by side, once as plain runs one after another. Both start from the
+    graph in HBM and end with every run's statistics; every run's N_hat is checked equal.
+    Reports edge-register updates/s over all runs (m x successor counters maximised in,
+    summed over the runs' own passes)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1011_5599_amd as hanf
+
+    spec = graphgen.WORKLOADS[args.workload]
+    rp, ci = graphgen.workload_graph(spec)
+    b, S = spec["log2m"], args.seeds
+    m = 1 << b
+    sym = bool(spec.get("symmetric"))
+    drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
+    seeds = [spec["seed"] + s for s in range(S)]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream().cuda_stream
+    bt = hanf.Batch(0, stream=stream)
+    h = hanf.HyperANF(0, stream=stream, timing=1)
+
+    def rows():
+        bt.load_graphs([(drp, dci)], S)
+        if sym:
+            bt.transpose_self()
+        bt.init(b, seeds)
+        bt.run()
+        return bt.stats_all()
+
+    def plain():
+        out = []
+        for sd in seeds:
+            h.load(drp, dci)
+            if sym:
+                h.load_transpose(drp, dci)
+            h.init(b, sd)
+            nt = h.run()
+            h.stats()
+            out.append((nt, sum(r["arcs_gathered"] for r in h.pass_log())))
+        return out
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            res = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), res
+
+    t_rows, _ = timed(rows)
+    t_plain, res = timed(plain)
+    for s_, (nt, _) in enumerate(res):
+        np.testing.assert_allclose(bt.nt(s_), nt, rtol=1e-12, atol=0)
+    updates = m * sum(g for _, g in res)
+    bt.close()
+    h.close()
+    return {
+        "metric": f"edge-register updates/s ({S} runs of one graph, seeds side by side)",
+        "value": updates / t_rows, "unit": "edge-register updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1000 * t_rows, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": spec_name(args.workload), "seeds": S, "log2m": b,
+                   "row_bytes": S * m, "transpose": "self" if sym else "none"},
+        "plain": {"ms_per_step": round(1000 * t_plain, 3), "updates_per_s": updates / t_plain},
+        "speedup_vs_plain": t_plain / t_rows,
+    }
+
+
 def run_serve_mode(args):
     """Serving workload: a Poisson stream of requests, graphs of 2^10..2^22 nodes (lognormal,
     median 2^16), R-MAT or web-like, log2m in {4, 6, 8}, hash seed = request id. Each request
@@ -300,9 +378,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--opt", action="append", default=[], help="library option name=value")
-    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain",
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "seeds"], default="plain",
                     help="plain: one graph (the default workload); batch: 512 graphs x 8 seeds; "
-                         "serve: Poisson request stream")
+                         "serve: Poisson request stream; seeds: many runs of the workload graph")
+    ap.add_argument("--seeds", type=int, default=8, help="seeds mode: runs of the graph")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
     ap.add_argument("--max-batches", type=int, default=8, help="serve mode: batches in flight")
     ap.add_argument("--transpose", choices=["auto", "self", "build", "none"], default="auto",
@@ -333,6 +412,9 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps(run_serve_mode(args)))
+        return
+    if args.mode == "seeds":
+        print(json.dumps(run_seeds_mode(args)))
         return
 
     import numpy as np

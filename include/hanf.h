@@ -146,6 +146,12 @@ int hanf_load_csr(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr
 int hanf_load_transpose(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr_t,
                         const int32_t *col_idx_t, uint32_t flags);
 
+/* Declares the loaded graph (every graph of a batch) symmetric: its successor lists are
+ * also its predecessor lists, so they serve systolic passes as the transposed graph with no
+ * copy. The symmetry is the caller's guarantee (otherwise the results are undefined). Same
+ * call order as hanf_load_transpose; single graphs and batches. */
+int hanf_transpose_self(hanf_ctx *ctx);
+
 /* Builds the transposed graph of the loaded graph (or batch) on the device: in-degree
  * counts, their prefix sums, then the predecessor lists (4 (n + 1) + 4 arcs bytes, kept
  * until the next graph ingest). Same call order as hanf_load_transpose. */

@@ -117,6 +117,7 @@ def lib():
             "hanf_load_csr": ([vp, i32, i64, vp, vp, u32], ctypes.c_int),
             "hanf_load_transpose": ([vp, i32, i64, vp, vp, u32], ctypes.c_int),
             "hanf_build_transpose": ([vp], ctypes.c_int),
+            "hanf_transpose_self": ([vp], ctypes.c_int),
             "hanf_init_counters": ([vp, i32, u64], ctypes.c_int),
             "hanf_iterate": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_read_nt": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
@@ -220,6 +221,10 @@ def hanf_load_transpose(ctx, row_ptr_t, col_idx_t):
 
 def hanf_build_transpose(ctx) -> None:
     _check(lib().hanf_build_transpose(ctx), ctx)
+
+
+def hanf_transpose_self(ctx) -> None:
+    _check(lib().hanf_transpose_self(ctx), ctx)
 
 
 def hanf_init_counters(ctx, log2m: int, seed: int) -> None:
@@ -378,9 +383,14 @@ def hanf_batch_stats_all(ctx, alpha: float = 0.9, eps: float = 0.0, distinct: bo
     """Statistics of every component: dict of numpy arrays (ed, ied, avg_dist, var, spid,
     n_max, d_lo, d_hi, T)."""
     n, _ = hanf_batch_info(ctx, with_T=False)
-    arr = (hanf_stats_t * max(n, 1))()
-    _check(lib().hanf_batch_stats_all(ctx, alpha, eps, int(distinct), ctypes.cast(arr, ctypes.c_void_p)), ctx)
-    return {f: np.array([getattr(arr[i], f) for i in range(n)]) for f, _ in hanf_stats_t._fields_}
+    # a structured array with the C struct's layout receives the records directly
+    dt = np.dtype({"names": [f for f, _ in hanf_stats_t._fields_],
+                   "formats": [np.float64 if t is ctypes.c_double else np.int32 for _, t in hanf_stats_t._fields_],
+                   "offsets": [getattr(hanf_stats_t, f).offset for f, _ in hanf_stats_t._fields_],
+                   "itemsize": ctypes.sizeof(hanf_stats_t)})
+    arr = np.zeros(max(n, 1), dt)
+    _check(lib().hanf_batch_stats_all(ctx, alpha, eps, int(distinct), arr.ctypes.data), ctx)
+    return {f: arr[f][:n].copy() for f, _ in hanf_stats_t._fields_}
 
 
 # ------------------------------------------------------------------ convenience wrapper
@@ -435,6 +445,12 @@ class HyperANF:
     def build_transpose(self):
         """Builds the predecessor lists on the device, for systolic passes."""
         hanf_build_transpose(self.ctx)
+        return self
+
+    def transpose_self(self):
+        """The graph (every graph of a batch) is symmetric: its successor lists serve as its
+        predecessor lists in systolic passes."""
+        hanf_transpose_self(self.ctx)
         return self
 
     def init(self, log2m: int, seed: int):

@@ -101,6 +101,10 @@ struct hanf_ctx {
   uint64_t *comp_seed = nullptr;
   int32_t *blkcnt = nullptr, *comp_T = nullptr, *slot_comp = nullptr, *comp_row = nullptr;
   double *comp_nt = nullptr;
+  std::vector<int32_t> slot_h, chunk0_h, cchunk_comp_h, cchunk_b0_h;  // row and reduction tables
+  int32_t *comp_chunk0 = nullptr, *cchunk_comp = nullptr, *cchunk_b0 = nullptr;
+  double *cchunk_sum = nullptr;
+  int64_t *cchunk_cnt = nullptr;
 
   // run state
   int log2m = 0;
@@ -245,6 +249,11 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->comp_nt);
   dev_release(c, c->slot_comp);
   dev_release(c, c->comp_row);
+  dev_release(c, c->comp_chunk0);
+  dev_release(c, c->cchunk_comp);
+  dev_release(c, c->cchunk_b0);
+  dev_release(c, c->cchunk_sum);
+  dev_release(c, c->cchunk_cnt);
   dev_release(c, c->todo);
   dev_release(c, c->sys_node);
   dev_release(c, c->sys_pos);
@@ -457,6 +466,12 @@ void fill_args(hanf_ctx *c) {
   a.batch.comp_n = lay ? c->lay_n : c->comp_n;
   a.batch.slot_comp = c->slot_comp;
   a.batch.comp_row = c->comp_row;
+  a.batch.comp_chunk0 = c->comp_chunk0;
+  a.batch.cchunk_comp = c->cchunk_comp;
+  a.batch.cchunk_b0 = c->cchunk_b0;
+  a.batch.cchunk_sum = c->cchunk_sum;
+  a.batch.cchunk_cnt = c->cchunk_cnt;
+  a.batch.n_cchunks = (int32_t)c->cchunk_comp_h.size();
   a.batch.comp_seed = c->comp_seed;
   a.batch.blkcnt = c->blkcnt;
   a.batch.comp_T = c->comp_T;
@@ -500,7 +515,12 @@ int alloc_run(hanf_ctx *c, int log2m, int sl) {
         (rc = dev_alloc(c, &c->comp_T, (size_t)c->n_comp, "component fixpoints")) ||
         (rc = dev_alloc(c, &c->comp_nt, (size_t)c->n_comp * c->nt_cap, "component histories")) ||
         (rc = dev_alloc(c, &c->slot_comp, (size_t)c->n_lay * S, "row seed components")) ||
-        (rc = dev_alloc(c, &c->comp_row, (size_t)c->n_comp, "component rows"))) {
+        (rc = dev_alloc(c, &c->comp_row, (size_t)c->n_comp, "component rows")) ||
+        (rc = dev_alloc(c, &c->comp_chunk0, (size_t)c->n_comp + 1, "component chunks")) ||
+        (rc = dev_alloc(c, &c->cchunk_comp, c->cchunk_comp_h.size(), "chunk components")) ||
+        (rc = dev_alloc(c, &c->cchunk_b0, c->cchunk_b0_h.size(), "chunk blocks")) ||
+        (rc = dev_alloc(c, &c->cchunk_sum, c->cchunk_comp_h.size(), "chunk sums")) ||
+        (rc = dev_alloc(c, &c->cchunk_cnt, c->cchunk_comp_h.size(), "chunk counts"))) {
       free_run(c);
       return rc;
     }
@@ -870,6 +890,25 @@ int hanf_load_transpose(hanf_ctx *c, int32_t n_t, int64_t arcs_t, const int32_t 
   return HANF_OK;
 }
 
+int hanf_transpose_self(hanf_ctx *c) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_transpose_self: NULL context");
+  if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  free_transpose(c);
+  c->inited = false;
+  int rc;
+  if (c->batch) {  // the base's own lists; the next initialisation lays them out with the graph
+    if ((rc = set_layout(c, 1))) return rc;
+    c->trp = c->rp_own;
+    c->tci = c->ci_own;
+  } else {
+    c->trp = c->rp;
+    c->tci = c->ci;
+  }
+  return HANF_OK;
+}
+
 int hanf_build_transpose(hanf_ctx *c) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_build_transpose: NULL context");
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
@@ -933,27 +972,53 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
       want.chunk_arcs != c->sch.chunk_arcs || want.tile_nodes != c->sch.tile_nodes) {
     if ((rc = build_schedule(c, G))) return rc;
   }
-  const int64_t want_cap = default_max_passes(c) + 2;
-  if (c->log2m != log2m || c->sl != sl || !c->regs[0] || want_cap != c->nt_cap) {
-    if ((rc = alloc_run(c, log2m, sl))) return rc;
-  }
-  if (c->batch) {  // which result component every row seed of every layout component runs
+  size_t n_cchunks_before = c->cchunk_comp_h.size();
+  if (c->batch) {
+    // which result component every row seed of every layout component runs, and the
+    // reduction chunks of every result component (kCompChunkBlocks blocks each)
     const int32_t S = 1 << sl;
-    std::vector<int32_t> slot((size_t)c->n_lay * S, -1);
+    c->slot_h.assign((size_t)c->n_lay * S, -1);
     c->comp_row_h.assign((size_t)c->n_comp, 0);
+    c->chunk0_h.assign((size_t)c->n_comp + 1, 0);
+    c->cchunk_comp_h.clear();
+    c->cchunk_b0_h.clear();
     for (int32_t g = 0; g < c->n_graphs; ++g)
       for (int32_t sd = 0; sd < c->n_seeds; ++sd) {
-        const int32_t row = (g * c->copies + sd / S) * S + sd % S;
-        slot[(size_t)row] = g * c->n_seeds + sd;
-        c->comp_row_h[(size_t)g * c->n_seeds + sd] = row;
+        const int32_t comp = g * c->n_seeds + sd;
+        const int32_t L = g * c->copies + sd / S;
+        const int32_t row = L * S + sd % S;
+        c->slot_h[(size_t)row] = comp;
+        c->comp_row_h[(size_t)comp] = row;
+        c->chunk0_h[(size_t)comp] = (int32_t)c->cchunk_comp_h.size();
+        const int32_t b0 = c->lay_node_off_h[L] / kNodesPerBlock, b1 = c->lay_node_off_h[L + 1] / kNodesPerBlock;
+        for (int32_t b = b0; b < b1; b += kCompChunkBlocks) {
+          c->cchunk_comp_h.push_back(comp);
+          c->cchunk_b0_h.push_back(b);
+        }
       }
-    HIP_TRY(c, hipMemcpyAsync(c->slot_comp, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice,
-                              c->stream),
+    c->chunk0_h[(size_t)c->n_comp] = (int32_t)c->cchunk_comp_h.size();
+  }
+  const int64_t want_cap = default_max_passes(c) + 2;
+  if (c->log2m != log2m || c->sl != sl || !c->regs[0] || want_cap != c->nt_cap ||
+      c->cchunk_comp_h.size() != n_cchunks_before) {
+    if ((rc = alloc_run(c, log2m, sl))) return rc;
+  }
+  if (c->batch) {
+    HIP_TRY(c, hipMemcpyAsync(c->slot_comp, c->slot_h.data(), sizeof(int32_t) * c->slot_h.size(),
+                              hipMemcpyHostToDevice, c->stream),
             "row seed upload");
     HIP_TRY(c, hipMemcpyAsync(c->comp_row, c->comp_row_h.data(), sizeof(int32_t) * c->n_comp, hipMemcpyHostToDevice,
                               c->stream),
             "component row upload");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "row tables");  // the host vectors are reused
+    HIP_TRY(c, hipMemcpyAsync(c->comp_chunk0, c->chunk0_h.data(), sizeof(int32_t) * c->chunk0_h.size(),
+                              hipMemcpyHostToDevice, c->stream),
+            "chunk table upload");
+    HIP_TRY(c, hipMemcpyAsync(c->cchunk_comp, c->cchunk_comp_h.data(), sizeof(int32_t) * c->cchunk_comp_h.size(),
+                              hipMemcpyHostToDevice, c->stream),
+            "chunk table upload");
+    HIP_TRY(c, hipMemcpyAsync(c->cchunk_b0, c->cchunk_b0_h.data(), sizeof(int32_t) * c->cchunk_b0_h.size(),
+                              hipMemcpyHostToDevice, c->stream),
+            "chunk table upload");
   }
   if (c->trp && !c->todo) {  // signal buffers for systolic passes
     if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals")) ||

@@ -14,6 +14,7 @@ constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
+constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
@@ -71,6 +72,12 @@ struct BatchArgs {
   int32_t *blkcnt;               // counters changed per (block, row seed) in the last pass
   int32_t *comp_T;               // fixpoint iteration of every result component, -1 while it changes
   double *comp_nt;               // N_hat history: comp_nt[c * nt_cap + t]
+  const int32_t *comp_chunk0;    // first reduction chunk of every result component (n_comp + 1)
+  const int32_t *cchunk_comp;    // result component of every chunk
+  const int32_t *cchunk_b0;      // first block of every chunk
+  double *cchunk_sum;            // per chunk: estimate sum and changed counters of the last pass
+  int64_t *cchunk_cnt;
+  int32_t n_cchunks;
   int32_t n_comp;                // result components
   int32_t n_lay;                 // layout components
   int32_t active;                // 1 for a batched run
@@ -156,7 +163,6 @@ hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out, hipStream_t s);
-hipError_t launch_reduce_components(const PassArgs &a, int32_t mode, hipStream_t s);
 hipError_t launch_expand_local(const int32_t *graph_off, const int32_t *arc_off, const int32_t *rp_in,
                                const int32_t *ci_in, int32_t n_graphs, int32_t n_seeds, const PassArgs &a,
                                const int32_t *comp_arc_off, int32_t *rp_exp, int32_t *ci_exp, int64_t n_exp,

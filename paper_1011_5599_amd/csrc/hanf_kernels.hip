@@ -574,10 +574,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     // systolic pass: the chunks of an unsignalled node gathered nothing (they may have been
     // skipped without clearing their flags)
     const int32_t count = (f.systolic && f.todo[hv.v] == 0) ? 0 : hv.count;
-    for (int32_t j = slot; j < count; j += W) {
-      if (a.partial_any[hv.first + j]) {
-        acc = bytemax4(acc, ldrow(a.partial, hv.first + j, m, sub));
-        any = true;
+    for (int32_t j0 = slot; j0 < count; j0 += 4 * W) {  // 4 partial rows in flight per slot
+      bool ok[4];
+      uint4 x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t j = j0 + k * W;
+        ok[k] = j < count && a.partial_any[hv.first + j];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = ok[k] ? ldrow(a.partial, hv.first + j0 + k * W, m, sub) : zero4();
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc = bytemax4(acc, x[k]);
+        any = any || ok[k];
       }
     }
     combine_slots<G>(acc, any);
@@ -590,7 +600,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
 // reuse the cached sums, Section 3.3), count changed counters, clear the flags of the
 // previous pass (and the signals of a systolic pass). A workgroup covers kReduceBlocks
 // consecutive blocks, a quarter per wavefront; sums are taken in a fixed order. With S
-// counters per node a block has 2S flag words and S sums (one per row seed).
+// counters per node a block has 2S flag words (kept in registers) and S sums.
+template <int S>
 __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int32_t force) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -601,19 +612,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
   uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;
   const bool sys = st->systolic != 0;  // this pass's signals are cleared with its flags
-  const int sl = a.seed_log2, S = 1 << sl, WB = 2 * S;  // flag words per block
+  constexpr int sl = S == 1 ? 0 : S == 2 ? 1 : S == 4 ? 2 : S == 8 ? 3 : S == 16 ? 4 : 5;
+  constexpr int WB = 2 * S;  // flag words per block
   constexpr int kPerWave = kReduceBlocks / (kBlockThreads / kWave);  // blocks per wavefront
   const int64_t b0 = (int64_t)blockIdx.x * kReduceBlocks + wave * kPerWave;  // the wavefront's first block
   const int64_t b = b0 + lane;
   const bool valid = lane < kPerWave && b < a.n_blocks;
+  uint32_t wv[WB];
   uint32_t any = 0u;
   int32_t bc = 0;
-  if (valid && !force) {
-    for (int k = 0; k < WB; ++k) {
-      const uint32_t w = cb[b * WB + k];
-      any |= w;
-      bc += __popc(w);
-    }
+#pragma unroll
+  for (int k = 0; k < WB; ++k) {
+    wv[k] = (valid && !force) ? cb[b * WB + k] : 0u;
+    any |= wv[k];
+    bc += __popc(wv[k]);
   }
   const bool dirty = valid && (force || any != 0u);
   double bs = (S == 1 && valid && !dirty) ? a.blocksum[b] : 0.0;
@@ -630,6 +642,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
       if (pend) pend &= pend - 1;
       e[k] = 0.0;
     }
+#pragma unroll
     for (int r = 0; r < S; ++r) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -641,6 +654,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     for (int k = 0; k < 4; ++k) {
       if (jb[k] >= 0) {  // wavefront-uniform
         double sum = e[k];
+#pragma unroll
         for (int off = S; off < kWave; off <<= 1) sum += __shfl_xor(sum, off);
         if (lane < S) a.blocksum[((b0 + jb[k]) << sl) + lane] = sum;
         if (S == 1 && lane == jb[k]) bs = sum;
@@ -649,15 +663,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   }
   if (valid && a.batch.active) {
     // changed counters of every row seed j: its flag bits are j, j+S, ... in every word
-    const uint32_t pattern = sl == 5 ? 1u : 0xffffffffu / ((1u << S) - 1u);
+    constexpr uint32_t pattern = S == 32 ? 1u : 0xffffffffu / ((S == 32 ? 0u : (1u << S)) - 1u);
+#pragma unroll
     for (int jj = 0; jj < S; ++jj) {
       int32_t cj = 0;
-      if (!force)
-        for (int k = 0; k < WB; ++k) cj += __popc(cb[b * WB + k] & (pattern << jj));
+#pragma unroll
+      for (int k = 0; k < WB; ++k) cj += __popc(wv[k] & (pattern << jj));
       a.batch.blkcnt[(b << sl) + jj] = cj;
     }
   }
   if (valid && !force)
+#pragma unroll
     for (int k = 0; k < WB; ++k) pb[b * WB + k] = 0u;
   if (valid && sys) {
     uint4 *tq = reinterpret_cast<uint4 *>(a.todo + b * kNodesPerBlock);
@@ -677,20 +693,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   }
 }
 
-// Batched runs: N_hat and changed count of every result component (one workgroup per
-// component, fixed summation order over its blocks' sums of its row seed). Marks a component's fixpoint T the first time a
-// pass leaves it unchanged; until then appends N_hat(t+1) to its history.
-__global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a, int32_t mode) {
+// Batched runs, first step: the sums of every chunk of a result component (at most
+// kCompChunkBlocks blocks of its layout component, its row seed's block sums and change
+// counts), one workgroup per chunk, in a fixed order.
+__global__ __launch_bounds__(kBlockThreads) void k_reduce_comp_chunks(PassArgs a, int32_t mode) {
   const DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kBlockThreads];
   __shared__ int64_t s_cnt[kBlockThreads];
-  const int32_t c = blockIdx.x;
+  const int32_t k = blockIdx.x;
   const int tid = threadIdx.x;
   const int sl = a.seed_log2;
+  const int32_t c = a.batch.cchunk_comp[k];
   const int32_t row = a.batch.comp_row[c];
   const int32_t L = row >> sl, jj = row & ((1 << sl) - 1);
-  const int32_t b0 = a.batch.comp_node_off[L] / kNodesPerBlock, b1 = a.batch.comp_node_off[L + 1] / kNodesPerBlock;
+  const int32_t end = a.batch.comp_node_off[L + 1] / kNodesPerBlock;
+  const int32_t b0 = a.batch.cchunk_b0[k], b1 = min(end, b0 + kCompChunkBlocks);
   double sum = 0.0;
   int64_t cnt = 0;
   for (int32_t b = b0 + tid; b < b1; b += kBlockThreads) {
@@ -708,17 +726,35 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a,
     __syncthreads();
   }
   if (tid == 0) {
-    const int32_t t = st->t;
-    double *hist = a.batch.comp_nt + (size_t)c * a.nt_cap;
-    if (mode == kReduceInit) {
-      a.batch.comp_T[c] = -1;
-      if (t < a.nt_cap) hist[t] = s_sum[0];
-    } else if (a.batch.comp_T[c] < 0) {
-      if (s_cnt[0] == 0)
-        a.batch.comp_T[c] = t;
-      else if (t + 1 < a.nt_cap)
-        hist[t + 1] = s_sum[0];
-    }
+    a.batch.cchunk_sum[k] = s_sum[0];
+    a.batch.cchunk_cnt[k] = s_cnt[0];
+  }
+}
+
+// Second step, one thread per result component: N_hat and the changed count from its
+// chunks in order. Marks the component's fixpoint T the first time a pass leaves it
+// unchanged; until then appends N_hat(t+1) to its history.
+__global__ __launch_bounds__(kBlockThreads) void k_reduce_components(PassArgs a, int32_t mode) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const int32_t c = (int32_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  if (c >= a.batch.n_comp) return;
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (int32_t k = a.batch.comp_chunk0[c]; k < a.batch.comp_chunk0[c + 1]; ++k) {
+    sum += a.batch.cchunk_sum[k];
+    cnt += a.batch.cchunk_cnt[k];
+  }
+  const int32_t t = st->t;
+  double *hist = a.batch.comp_nt + (size_t)c * a.nt_cap;
+  if (mode == kReduceInit) {
+    a.batch.comp_T[c] = -1;
+    if (t < a.nt_cap) hist[t] = sum;
+  } else if (a.batch.comp_T[c] < 0) {
+    if (cnt == 0)
+      a.batch.comp_T[c] = t;
+    else if (t + 1 < a.nt_cap)
+      hist[t + 1] = sum;
   }
 }
 
@@ -1664,9 +1700,21 @@ hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_blocks, dim3((unsigned)a.n_reduce_wgs), dim3(kBlockThreads), 0, s, a, force);
-  if (a.batch.active && a.batch.n_comp > 0)
-    hipLaunchKernelGGL(k_reduce_components, dim3((unsigned)a.batch.n_comp), dim3(kBlockThreads), 0, s, a, mode);
+  const dim3 grid((unsigned)a.n_reduce_wgs), block(kBlockThreads);
+  switch (a.seed_log2) {
+    case 0: hipLaunchKernelGGL(k_reduce_blocks<1>, grid, block, 0, s, a, force); break;
+    case 1: hipLaunchKernelGGL(k_reduce_blocks<2>, grid, block, 0, s, a, force); break;
+    case 2: hipLaunchKernelGGL(k_reduce_blocks<4>, grid, block, 0, s, a, force); break;
+    case 3: hipLaunchKernelGGL(k_reduce_blocks<8>, grid, block, 0, s, a, force); break;
+    case 4: hipLaunchKernelGGL(k_reduce_blocks<16>, grid, block, 0, s, a, force); break;
+    case 5: hipLaunchKernelGGL(k_reduce_blocks<32>, grid, block, 0, s, a, force); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (a.batch.active && a.batch.n_comp > 0) {
+    hipLaunchKernelGGL(k_reduce_comp_chunks, dim3((unsigned)a.batch.n_cchunks), dim3(kBlockThreads), 0, s, a, mode);
+    hipLaunchKernelGGL(k_reduce_components, dim3(grid_for(a.batch.n_comp, kBlockThreads, 1 << 30)),
+                       dim3(kBlockThreads), 0, s, a, mode);
+  }
   hipLaunchKernelGGL(k_reduce_top, dim3(1), dim3(kTopThreads), 0, s, a, mode);
   return hipGetLastError();
 }
@@ -1698,12 +1746,6 @@ hipError_t launch_check_offsets(const int32_t *rp, const int32_t *goff, const in
                                 DevState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_check_offsets, dim3(grid_for((int64_t)n_graphs + 1, 256, 1 << 30)), dim3(256), 0, s, rp, goff,
                      aoff, n_graphs, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_reduce_components(const PassArgs &a, int32_t mode, hipStream_t s) {
-  if (!a.batch.active || a.batch.n_comp == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_components, dim3((unsigned)a.batch.n_comp), dim3(kBlockThreads), 0, s, a, mode);
   return hipGetLastError();
 }
 

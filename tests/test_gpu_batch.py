@@ -80,6 +80,27 @@ def test_batch_systolic_components_equal_their_runs(sys_div, S, b):
                 assert np.array_equal(bt.registers(c), regs_ref), (g, s)
 
 
+@pytest.mark.parametrize("S,b", [(8, 6), (8, 8), (3, 4)])
+def test_batch_symmetric_self_transpose(S, b):
+    """Symmetric graphs declared their own transpose (no copy): systolic passes over rows of
+    seeds, also laid out in two copies (8 seeds of m = 256)."""
+    gs = [graphgen.rmat(9 + (i % 3), 2500 + 400 * i, symmetric=True, seed=90 + i) for i in range(6)]
+    gs += [graphgen.complete(30), graphgen.empty(5)]
+    seeds = [77 + 5 * c for c in range(len(gs) * S)]
+    with hanf.Batch(0, systolic=1) as bt:
+        bt.load_graphs(gs, S).transpose_self().init(b, seeds)
+        bt.run()
+        assert any(r["systolic"] for r in bt.pass_log())
+        T = bt.fixpoints()
+        for g, (rp, ci) in enumerate(gs):
+            for s in range(S):
+                c = g * S + s
+                nt_ref, T_ref, regs_ref = oracle.run(rp, ci, b, seeds[c], want_regs=True)
+                assert T[c] == T_ref, (g, s)
+                np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=1e-12, atol=0)
+                assert np.array_equal(bt.registers(c), regs_ref), (g, s)
+
+
 def test_batch_step_by_step_registers():
     """Registers of every component at every t, while other components still change."""
     gs = [graphgen.directed_path(40), graphgen.rmat(10, 6000, seed=3), graphgen.erdos_renyi(500, 1500, seed=4)]

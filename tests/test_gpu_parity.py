@@ -44,6 +44,8 @@ def _load(h, rp, ci, transpose):
         import torch
         drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
         h.load(drp, dci).load_transpose(drp, dci)
+    elif transpose == "declared":
+        h.load(rp, ci).transpose_self()
     else:
         h.load(rp, ci)
         if transpose == "build":
@@ -197,6 +199,7 @@ def test_systolic_symmetric_self_transpose(b):
     rp, ci = graphgen.rmat(13, 60_000, symmetric=True, seed=30 + b)
     step_parity(rp, ci, b, 7, transpose="self")
     step_parity(rp, ci, b, 8, transpose="self", dense_switch=0, systolic=1)
+    step_parity(rp, ci, b, 9, transpose="declared", systolic=2)
 
 
 def test_transpose_errors():
