@@ -192,6 +192,11 @@ int hanf_read_nt(hanf_ctx *ctx, double *out, int32_t cap, int32_t *len);
  * of node v at v*m + j) to `out` (host or device per flags). `bytes` must be n*m. */
 int hanf_read_registers(hanf_ctx *ctx, uint8_t *out, int64_t bytes, uint32_t flags);
 
+/* The estimate size(c_t[v]) of every current counter (Algorithm 1, with the small-range
+ * rule): out[v] for v < n, count = n. Single graphs. The same per-node values the pass
+ * kernels sum into N_hat(t) (exposed so they can be checked one by one). */
+int hanf_read_estimates(hanf_ctx *ctx, double *out, int64_t count, uint32_t flags);
+
 /* Resumes from a checkpoint: counters `in` (n*m bytes, layout of hanf_read_registers,
  * values <= 31) taken at iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
  * Every counter is treated as modified for the next pass, so the continuation is
@@ -257,6 +262,9 @@ int hanf_batch_read_nt(hanf_ctx *ctx, int32_t comp, double *out, int32_t cap, in
 
 /* Current counters of component `comp`: n_g * m bytes, node-major (graph-local ids). */
 int hanf_batch_read_registers(hanf_ctx *ctx, int32_t comp, uint8_t *out, int64_t bytes, uint32_t flags);
+
+/* Per-node estimates of component comp (count = its graph's n), as hanf_read_estimates. */
+int hanf_batch_read_estimates(hanf_ctx *ctx, int32_t comp, double *out, int64_t count, uint32_t flags);
 
 /* hanf_stats of component `comp`. */
 int hanf_batch_stats(hanf_ctx *ctx, int32_t comp, double alpha, double eps, int32_t distinct,

@@ -64,6 +64,8 @@ def _load():
         L.orc_union.restype = None
         L.orc_init.argtypes = [ctypes.c_int32, ctypes.c_int, ctypes.c_uint64, u8p]
         L.orc_init.restype = None
+        L.orc_sizes.argtypes = [ctypes.c_int32, ctypes.c_int, u8p, ctypes.POINTER(ctypes.c_double)]
+        L.orc_sizes.restype = None
         L.orc_sum_sizes.argtypes = [ctypes.c_int32, ctypes.c_int, u8p]
         L.orc_sum_sizes.restype = ctypes.c_double
         L.orc_pass.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int, u8p, u8p,
@@ -145,6 +147,15 @@ def init(n: int, b: int, seed: int) -> np.ndarray:
     c = np.zeros((max(n, 1), 1 << b), np.uint8)
     _load().orc_init(n, b, seed, c)
     return c[:n]
+
+
+def sizes(c: np.ndarray, b: int) -> np.ndarray:
+    """size() of every counter (Algorithm 1), one per row of c."""
+    c = np.ascontiguousarray(c, dtype=np.uint8)
+    out = np.zeros(max(c.shape[0], 1), np.float64)
+    _load().orc_sizes(c.shape[0], b, c if c.size else np.zeros(1, np.uint8),
+                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out[: c.shape[0]]
 
 
 def sum_sizes(c: np.ndarray, b: int) -> float:

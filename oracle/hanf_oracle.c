@@ -116,6 +116,12 @@ void orc_init(int32_t n, int b, uint64_t seed, uint8_t *c) {
 
 /* N_hat(t) = sum over v of size(c[v]), summed in node order with Neumaier's
  * compensated summation. */
+/* size() of every counter of c (n counters of m bytes): out[v]. */
+void orc_sizes(int32_t n, int b, const uint8_t *c, double *out) {
+  int m = 1 << b;
+  for (int32_t v = 0; v < n; v++) out[v] = orc_size(c + (size_t)v * m, b);
+}
+
 double orc_sum_sizes(int32_t n, int b, const uint8_t *c) {
   int m = 1 << b;
   double s = 0.0, comp = 0.0;

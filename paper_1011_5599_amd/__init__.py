@@ -122,6 +122,8 @@ def lib():
             "hanf_iterate": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_read_nt": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
             "hanf_read_registers": ([vp, vp, i64, u32], ctypes.c_int),
+            "hanf_read_estimates": ([vp, vp, i64, u32], ctypes.c_int),
+            "hanf_batch_read_estimates": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_write_registers": ([vp, vp, i64, i32, vp, i32, u32], ctypes.c_int),
             "hanf_stats": ([vp, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
             "hanf_read_pass_log": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
@@ -373,6 +375,18 @@ def hanf_batch_read_registers(ctx, comp: int, n: int, log2m: int) -> np.ndarray:
     return out
 
 
+def hanf_read_estimates(ctx, n: int) -> np.ndarray:
+    out = np.empty(n, np.float64)
+    _check(lib().hanf_read_estimates(ctx, out.ctypes.data, n, HANF_HOST_PTRS), ctx)
+    return out
+
+
+def hanf_batch_read_estimates(ctx, comp: int, n: int) -> np.ndarray:
+    out = np.empty(n, np.float64)
+    _check(lib().hanf_batch_read_estimates(ctx, comp, out.ctypes.data, n, HANF_HOST_PTRS), ctx)
+    return out
+
+
 def hanf_batch_stats(ctx, comp: int, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
     s = hanf_stats_t()
     _check(lib().hanf_batch_stats(ctx, comp, alpha, eps, int(distinct), ctypes.byref(s)), ctx)
@@ -472,6 +486,10 @@ class HyperANF:
     def registers(self, out=None):
         return hanf_read_registers(self.ctx, self.n, self.log2m, out)
 
+    def estimates(self):
+        """Per-node estimates of the current counters."""
+        return hanf_read_estimates(self.ctx, self.n)
+
     def stats(self, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
         return hanf_stats(self.ctx, alpha, eps, distinct)
 
@@ -528,6 +546,9 @@ class Batch(HyperANF):
 
     def registers(self, comp: int):
         return hanf_batch_read_registers(self.ctx, comp, self.sizes[comp // self.n_seeds], self.log2m)
+
+    def estimates(self, comp: int):
+        return hanf_batch_read_estimates(self.ctx, comp, self.sizes[comp // self.n_seeds])
 
     def stats(self, comp: int, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
         return hanf_batch_stats(self.ctx, comp, alpha, eps, distinct)

@@ -1199,6 +1199,19 @@ int hanf_read_registers(hanf_ctx *c, uint8_t *out, int64_t bytes, uint32_t flags
   return sync(c, "register read");
 }
 
+int hanf_read_estimates(hanf_ctx *c, double *out, int64_t count, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_estimates: NULL context");
+  if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
+  if (c->batch) return fail(c, HANF_EINVAL, "batched graph: use hanf_batch_read_estimates");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (count != c->n) return fail(c, HANF_EINVAL, "count must be n");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipMemcpyAsync(out, c->est, sizeof(double) * (size_t)count,
+                            flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+          "estimate read");
+  return sync(c, "estimate read");
+}
+
 int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t t, const double *nt_prefix,
                          int32_t len, uint32_t flags) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_write_registers: NULL context");
@@ -1572,6 +1585,23 @@ int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t b
                               flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
           "register read");
   return sync(c, "register read");
+}
+
+int hanf_batch_read_estimates(hanf_ctx *c, int32_t comp, double *out, int64_t count, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_estimates: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
+  const int32_t row = c->comp_row_h[comp];
+  const int32_t L = row >> c->sl, j = row & ((1 << c->sl) - 1);
+  const size_t S = (size_t)1 << c->sl;
+  const int32_t ng = c->lay_n_h[L];
+  if (count != ng) return fail(c, HANF_EINVAL, "count must be the graph's n");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  const double *src = c->est + (size_t)c->lay_node_off_h[L] * S + (size_t)j;  // counter j of each row
+  HIP_TRY(c, hipMemcpy2DAsync(out, sizeof(double), src, sizeof(double) * S, sizeof(double), (size_t)ng,
+                              flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+          "estimate read");
+  return sync(c, "estimate read");
 }
 
 int hanf_batch_stats(hanf_ctx *c, int32_t comp, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {

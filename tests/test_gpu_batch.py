@@ -47,6 +47,7 @@ def test_batch_components_equal_their_runs(b, S, per_row):
                 assert T[c] == T_ref, (g, s)
                 np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=1e-12, atol=0)
                 assert np.array_equal(bt.registers(c), regs_ref), (g, s)
+                assert np.array_equal(bt.estimates(c), oracle.sizes(regs_ref, b)), (g, s)
                 st = bt.stats(c)
                 with hanf.HyperANF(0) as h:
                     h.load(rp, ci).init(b, seeds[c])

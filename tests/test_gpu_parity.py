@@ -72,6 +72,8 @@ def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
             if t % check_every == 0:
                 got = h.registers()
                 assert np.array_equal(got, c), f"registers differ at t={t}"
+                # every node's estimate bit for bit (the per-node arithmetic of the reduction)
+                assert np.array_equal(h.estimates(), oracle.sizes(c, b)), f"estimates differ at t={t}"
             # the oracle's next pass, for the exact work counters
             _, mod_out, changed, maxed = oracle.step(rp, ci, b, c, mod)
             st, steps, ch_last = h.step(1)

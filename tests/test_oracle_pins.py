@@ -424,3 +424,31 @@ def test_error_against_exact_neighbourhood_function(b, beta):
     assert (errs <= 2 * eta).mean() >= 1 - 4 / 36
     assert (errs <= 3 * eta).mean() >= 1 - 4 / 81
     assert np.abs(means).max() <= eta / 2
+
+
+@pytest.mark.parametrize("b", [4, 6])
+def test_estimate_falls_only_at_the_small_range_switch(b):
+    """Section 4 calls the estimated distance function monotone. Registers only grow, so the
+    raw estimate alpha m^2 / sum_j 2^-M[j] never falls; with the small-range rule a node's
+    estimate can still fall, but only in the pass where its counter leaves the
+    linear-counting range (raw <= 5m/2 with an empty register) for the raw estimate.
+    Checked node by node over whole runs on small random graphs."""
+    m = 1 << b
+    a = oracle.alpha(m)
+    dips = 0
+    for gseed in range(40):
+        rp, ci = graphgen.erdos_renyi(60, 150, seed=gseed)
+        prev = None
+        for t, c, s in oracle.run_steps(rp, ci, b, 1000 + gseed):
+            E = oracle.sizes(c, b)
+            raw = a * m * m / np.power(2.0, -c.astype(np.float64)).sum(axis=1)
+            lc = (raw <= 2.5 * m) & ((c == 0).sum(axis=1) > 0)
+            if prev is not None:
+                pE, praw, plc = prev
+                assert (raw >= praw).all(), t
+                fell = E < pE
+                assert not (fell & ~(plc & ~lc)).any(), t
+                dips += int(fell.sum())
+            prev = (E, raw, lc)
+    if b == 4:
+        assert dips > 0  # the case the monotonicity remark passes over does occur at m = 16
