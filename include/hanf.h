@@ -74,6 +74,11 @@ extern "C" {
                                    all). 0 (default): as many as fit, up to 32 and 1024 bytes
                                    per row; else a power of two up to 32. Results do not change */
 
+/* Tuning and test options (the results never change):
+ *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
+ *   101  the persistent union kernel over listed work units: 0 (default) for systolic
+ *        passes, 1 never, 2 for every pass. */
+
 /* ---- hanf_footprint flags */
 #define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */
 #define HANF_FP_TRANSPOSE 2     /* include the transposed graph and the systolic signal buffers */
