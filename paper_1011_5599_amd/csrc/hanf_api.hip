@@ -626,6 +626,94 @@ int set_layout(hanf_ctx *c, int32_t copies) {
 }
 
 // The switches compare changed counters with the number of counters, n S.
+// The transposed graph of (rp, ci) into trp / tci by the two-level bucket sort of the
+// kernels (graphs of at most kTpMaxNodes nodes). One host read of the bucket sizes splits
+// the buckets into those one workgroup sorts and the hubs' buckets, sorted in chunks.
+int transpose_buckets(hanf_ctx *c, const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs, int32_t *trp,
+                      int32_t *tci) {
+  int32_t bs = 10;
+  while (((((int64_t)n - 1) >> bs) + 1) > kTpNumBuckets) ++bs;
+  const int32_t nb = (int32_t)((((int64_t)n - 1) >> bs) + 1);
+  const int32_t B = 1 << bs;
+  int32_t n_ranges = (int32_t)std::min<int64_t>(512, ((int64_t)n + 63) / 64);
+  const int32_t range = (int32_t)((((int64_t)n + n_ranges - 1) / n_ranges + 63) / 64 * 64);
+  n_ranges = (int32_t)(((int64_t)n + range - 1) / range);
+  const int64_t hn = (int64_t)nb * n_ranges + 1;
+  uint64_t *hist = nullptr, *tmp = nullptr, *pairs = nullptr, *bstart = nullptr;
+  int32_t *lists = nullptr;
+  int64_t *chunks = nullptr;
+  uint32_t *h2 = nullptr;
+  auto release = [&]() {
+    dev_release(c, hist);
+    dev_release(c, tmp);
+    dev_release(c, pairs);
+    dev_release(c, bstart);
+    dev_release(c, lists);
+    dev_release(c, chunks);
+    dev_release(c, h2);
+  };
+  int rc;
+  if ((rc = dev_alloc(c, &hist, (size_t)hn, "transpose histogram")) ||
+      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems(hn), "scan scratch")) ||
+      (rc = dev_alloc(c, &pairs, (size_t)arcs, "transpose pairs")) ||
+      (rc = dev_alloc(c, &bstart, (size_t)nb + 1, "bucket starts"))) {
+    release();
+    return rc;
+  }
+  std::vector<uint64_t> bs_h((size_t)nb + 1);
+  hipError_t e = launch_tp_first(rp, ci, n, range, bs, nb, n_ranges, hist, tmp, pairs, bstart, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bs_h.data(), bstart, sizeof(uint64_t) * (nb + 1), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    release();
+    return hip_fail(c, e, "transpose (first level)");
+  }
+  // light buckets, then hub buckets with their chunks
+  std::vector<int32_t> light, heavy, hchunk0;
+  std::vector<int64_t> clo, chi, cs;
+  for (int32_t b = 0; b < nb; ++b) {
+    const int64_t lo = (int64_t)bs_h[b], hi = (int64_t)bs_h[b + 1];
+    if (hi - lo <= kTpLight) {
+      light.push_back(b);
+    } else {
+      heavy.push_back(b);
+      hchunk0.push_back((int32_t)clo.size());
+      for (int64_t p = lo; p < hi; p += kTpChunk) {
+        clo.push_back(p);
+        chi.push_back(std::min(hi, p + kTpChunk));
+        cs.push_back(lo);
+      }
+    }
+  }
+  hchunk0.push_back((int32_t)clo.size());
+  const int32_t nl = (int32_t)light.size(), nh = (int32_t)heavy.size(), nc = (int32_t)clo.size();
+  if ((rc = dev_alloc(c, &lists, (size_t)nl + nh + nh + 1, "bucket lists")) ||
+      (rc = dev_alloc(c, &chunks, (size_t)3 * nc, "hub chunks")) ||
+      (rc = dev_alloc(c, &h2, (size_t)nc * B, "hub chunk counts"))) {
+    release();
+    return rc;
+  }
+  std::vector<int32_t> lists_h(light);
+  lists_h.insert(lists_h.end(), heavy.begin(), heavy.end());
+  lists_h.insert(lists_h.end(), hchunk0.begin(), hchunk0.end());
+  std::vector<int64_t> chunks_h(clo);
+  chunks_h.insert(chunks_h.end(), chi.begin(), chi.end());
+  chunks_h.insert(chunks_h.end(), cs.begin(), cs.end());
+  const int32_t arcs32 = (int32_t)arcs;
+  e = hipMemcpyAsync(lists, lists_h.data(), sizeof(int32_t) * lists_h.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && nc > 0)
+    e = hipMemcpyAsync(chunks, chunks_h.data(), sizeof(int64_t) * chunks_h.size(), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = launch_tp_second(pairs, bstart, lists, nl, lists + nl, lists + nl + nh, nh, chunks, chunks + nc, chunks + 2 * nc,
+                         nc, h2, bs, n, trp, tci, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(trp + n, &arcs32, sizeof(int32_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  release();
+  if (e != hipSuccess) return hip_fail(c, e, "transpose (second level)");
+  return HANF_OK;
+}
+
 int64_t dense_threshold(const hanf_ctx *c) {
   if (c->dense_div <= 0) return 0;
   return std::max<int64_t>(1, ((int64_t)c->n << c->sl) / c->dense_div);
@@ -930,6 +1018,17 @@ int hanf_build_transpose(hanf_ctx *c) {
     dev_release(c, tmp);
     free_transpose(c);
     return rc;
+  }
+  if (arcs > 0 && n <= kTpMaxNodes) {  // bucket sort; the counting build below is the fallback
+    dev_release(c, keys);
+    dev_release(c, tmp);
+    if ((rc = transpose_buckets(c, c->rp, c->ci, n, arcs, c->trp_own, c->tci_own))) {
+      free_transpose(c);
+      return rc;
+    }
+    c->trp = c->trp_own;
+    c->tci = c->tci_own;
+    return HANF_OK;
   }
   hipError_t e = launch_fill_u64(keys, (int64_t)n + 1, 0ull, c->stream);
   if (e == hipSuccess) e = launch_transpose_count(c->ci, arcs, keys, c->stream);

@@ -159,6 +159,20 @@ hipError_t launch_transpose_count(const int32_t *col_idx, int64_t arcs, uint64_t
 hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, uint64_t *keys,
                                  int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s);
+// transposed graph by buckets (graphs of at most kTpMaxNodes nodes): first level (per node
+// range histograms into nb buckets of 2^bs ids, their scan, the pairs, bucket starts), then
+// second level (light buckets one workgroup each; hub buckets in chunks)
+constexpr int32_t kTpMaxNodes = 1 << 26;
+constexpr int32_t kTpNumBuckets = 8192;
+constexpr int64_t kTpLight = 1 << 18;   // pairs of a bucket sorted by one workgroup
+constexpr int64_t kTpChunk = 1 << 16;   // pairs per chunk of a hub bucket
+hipError_t launch_tp_first(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t range, int32_t bs,
+                           int32_t nb, int32_t n_ranges, uint64_t *hist, uint64_t *scan_tmp, uint64_t *pairs,
+                           uint64_t *bstart, hipStream_t s);
+hipError_t launch_tp_second(const uint64_t *pairs, const uint64_t *bstart, const int32_t *blist, int32_t n_light,
+                            const int32_t *hlist, const int32_t *hchunk0, int32_t n_heavy, const int64_t *chunk_lo,
+                            const int64_t *chunk_hi, const int64_t *chunk_s, int32_t n_hchunks, uint32_t *h2, int32_t bs,
+                            int32_t n, int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s);
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,

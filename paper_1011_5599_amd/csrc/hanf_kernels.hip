@@ -1461,6 +1461,172 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(uint64_t *d, int64_
   }
 }
 
+// ------------------------------------------------------------------ kernels: transpose by buckets
+
+// The transposed graph by a two-level counting sort, with no global atomic per arc. Arcs
+// are first grouped by target into buckets of 2^bs consecutive ids (at most kTpBuckets
+// buckets; node ranges of `range` nodes count and place their arcs with LDS counters),
+// then each bucket is sorted by target in LDS: in one workgroup, or in chunks for the
+// buckets of hubs. The order inside a predecessor list is arbitrary.
+constexpr int kTpBuckets = kTpNumBuckets;  // first-level buckets (LDS counters)
+constexpr int kTpMaxBucket = 8192;  // ids per bucket (LDS counters of the second level)
+constexpr int kTpThreads = 256;     // = kScanThreads (block_exclusive_scan)
+
+// Per node range r: arcs into every bucket b, stored bucket-major at hist[b * n_ranges + r]
+// so that one exclusive scan gives every (bucket, range) its place.
+__global__ __launch_bounds__(kTpThreads) void k_tp_hist(const int32_t *rp, const int32_t *ci, int32_t n, int32_t range,
+                                                       int32_t bs, int32_t nb, int32_t n_ranges, uint64_t *hist) {
+  __shared__ uint32_t cnt[kTpBuckets];
+  for (int i = threadIdx.x; i < nb; i += kTpThreads) cnt[i] = 0u;
+  __syncthreads();
+  const int32_t r = blockIdx.x;
+  const int64_t v0 = (int64_t)r * range, v1 = min((int64_t)n, v0 + range);
+  const int64_t a0 = rp[v0], a1 = rp[v1];
+  for (int64_t a = a0 + threadIdx.x; a < a1; a += kTpThreads) atomicAdd(&cnt[ci[a] >> bs], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kTpThreads) hist[(int64_t)i * n_ranges + r] = cnt[i];
+}
+
+// Places the arcs of node range r as (target - bucket start) << 32 | source at the
+// positions of the scanned histogram (one LDS cursor per bucket). Each wavefront takes 64
+// consecutive nodes at a time and finds an arc's source by binary search over their row
+// pointers in LDS.
+__global__ __launch_bounds__(kTpThreads) void k_tp_scatter(const int32_t *rp, const int32_t *ci, int32_t n, int32_t range,
+                                                          int32_t bs, int32_t nb, int32_t n_ranges, const uint64_t *pos,
+                                                          uint64_t *pairs) {
+  __shared__ uint32_t cur[kTpBuckets];
+  __shared__ int32_t rps[kTpThreads / kWave][kWave + 1];
+  const int32_t r = blockIdx.x;
+  for (int i = threadIdx.x; i < nb; i += kTpThreads) cur[i] = (uint32_t)pos[(int64_t)i * n_ranges + r];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t low = (1u << bs) - 1u;
+  const int64_t v0 = (int64_t)r * range, v1 = min((int64_t)n, v0 + range);
+  for (int64_t g0 = v0 + (int64_t)wave * kWave; g0 < v1; g0 += kTpThreads) {
+    const int32_t cn = (int32_t)min((int64_t)kWave, v1 - g0);
+    if (lane < cn) rps[wave][lane] = rp[g0 + lane];
+    if (lane == cn - 1) rps[wave][cn] = rp[g0 + cn];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int64_t A = rps[wave][0], B = rps[wave][cn];
+    for (int64_t base = A; base < B; base += kWave) {
+      const int64_t p = base + lane;
+      if (p < B) {
+        int32_t l = 0, h = cn;  // the arc's source: the last node j with rps[j] <= p
+        while (h - l > 1) {
+          const int32_t mid = (l + h) >> 1;
+          if (rps[wave][mid] <= p) l = mid; else h = mid;
+        }
+        const uint32_t w = (uint32_t)ci[p];
+        const uint32_t at = atomicAdd(&cur[w >> bs], 1u);
+        pairs[at] = ((uint64_t)(w & low) << 32) | (uint64_t)(uint32_t)(g0 + l);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Start of every bucket's pairs (and the total at bstart[nb]).
+__global__ void k_tp_bounds(const uint64_t *pos, int32_t nb, int32_t n_ranges, uint64_t *bstart) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= nb) bstart[b] = pos[(int64_t)b * n_ranges];
+}
+
+// Counts per target of a run of a bucket's pairs, into LDS.
+__device__ __forceinline__ void tp_count(const uint64_t *pairs, int64_t lo, int64_t hi, uint32_t *cnt) {
+  for (int64_t p = lo + threadIdx.x; p < hi; p += kTpThreads) atomicAdd(&cnt[(uint32_t)(pairs[p] >> 32)], 1u);
+}
+
+// A whole bucket in one workgroup: counts per target, their exclusive scan (the bucket's
+// rows of the transposed graph), then every source placed with LDS cursors.
+__global__ __launch_bounds__(kTpThreads) void k_tp_bucket(const uint64_t *pairs, const uint64_t *bstart,
+                                                         const int32_t *blist, int32_t bs, int32_t n, int32_t *trp,
+                                                         int32_t *tci) {
+  __shared__ uint32_t cnt[kTpMaxBucket];
+  const int32_t b = blist[blockIdx.x];
+  const int32_t B = 1 << bs;
+  const int64_t s = (int64_t)bstart[b], e = (int64_t)bstart[b + 1];
+  for (int i = threadIdx.x; i < B; i += kTpThreads) cnt[i] = 0u;
+  __syncthreads();
+  tp_count(pairs, s, e, cnt);
+  __syncthreads();
+  const int per = B / kTpThreads, i0 = threadIdx.x * per;  // B is a multiple of 256
+  uint64_t sum = 0;
+  for (int k = 0; k < per; ++k) sum += cnt[i0 + k];
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(sum, &total);
+  for (int k = 0; k < per; ++k) {
+    const uint32_t c = cnt[i0 + k];
+    const int64_t v = ((int64_t)b << bs) + i0 + k;
+    if (v < n) trp[v] = (int32_t)(s + (int64_t)run);
+    cnt[i0 + k] = (uint32_t)run;  // cursor, relative to s
+    run += c;
+  }
+  __syncthreads();
+  for (int64_t p = s + threadIdx.x; p < e; p += kTpThreads) {
+    const uint64_t x = pairs[p];
+    const uint32_t at = atomicAdd(&cnt[(uint32_t)(x >> 32)], 1u);
+    tci[s + at] = (int32_t)(uint32_t)x;
+  }
+}
+
+// Buckets of hubs, in chunks: counts per target of every chunk (h2[chunk][target]).
+__global__ __launch_bounds__(kTpThreads) void k_tp_chunk_hist(const uint64_t *pairs, const int64_t *chunk_lo,
+                                                             const int64_t *chunk_hi, int32_t bs, uint32_t *h2) {
+  __shared__ uint32_t cnt[kTpMaxBucket];
+  const int32_t B = 1 << bs;
+  const int32_t k = blockIdx.x;
+  for (int i = threadIdx.x; i < B; i += kTpThreads) cnt[i] = 0u;
+  __syncthreads();
+  tp_count(pairs, chunk_lo[k], chunk_hi[k], cnt);
+  __syncthreads();
+  for (int i = threadIdx.x; i < B; i += kTpThreads) h2[(int64_t)k * B + i] = cnt[i];
+}
+
+// Per hub bucket: rows of the transposed graph from the chunk counts, and every chunk's
+// place in every row (h2 rewritten with positions relative to the bucket start).
+__global__ __launch_bounds__(kTpThreads) void k_tp_heavy_scan(const uint64_t *bstart, const int32_t *hlist,
+                                                             const int32_t *hchunk0, int32_t bs, int32_t n,
+                                                             uint32_t *h2, int32_t *trp) {
+  const int32_t b = hlist[blockIdx.x];
+  const int32_t k0 = hchunk0[blockIdx.x], k1 = hchunk0[blockIdx.x + 1];
+  const int32_t B = 1 << bs;
+  const int64_t s = (int64_t)bstart[b];
+  const int per = B / kTpThreads, i0 = threadIdx.x * per;
+  uint64_t sum = 0;
+  for (int i = i0; i < i0 + per; ++i)
+    for (int32_t k = k0; k < k1; ++k) sum += h2[(int64_t)k * B + i];
+  uint64_t total;
+  uint64_t run = block_exclusive_scan(sum, &total);
+  for (int i = i0; i < i0 + per; ++i) {
+    const int64_t v = ((int64_t)b << bs) + i;
+    if (v < n) trp[v] = (int32_t)(s + (int64_t)run);
+    for (int32_t k = k0; k < k1; ++k) {
+      const uint32_t c = h2[(int64_t)k * B + i];
+      h2[(int64_t)k * B + i] = (uint32_t)run;
+      run += c;
+    }
+  }
+}
+
+// Places the sources of one chunk of a hub bucket with LDS cursors from h2.
+__global__ __launch_bounds__(kTpThreads) void k_tp_chunk_scatter(const uint64_t *pairs, const int64_t *chunk_lo,
+                                                                const int64_t *chunk_hi, const int64_t *chunk_s,
+                                                                int32_t bs, const uint32_t *h2, int32_t *tci) {
+  __shared__ uint32_t cur[kTpMaxBucket];
+  const int32_t B = 1 << bs;
+  const int32_t k = blockIdx.x;
+  for (int i = threadIdx.x; i < B; i += kTpThreads) cur[i] = h2[(int64_t)k * B + i];
+  __syncthreads();
+  const int64_t s = chunk_s[k];
+  for (int64_t p = chunk_lo[k] + threadIdx.x; p < chunk_hi[k]; p += kTpThreads) {
+    const uint64_t x = pairs[p];
+    const uint32_t at = atomicAdd(&cur[(uint32_t)(x >> 32)], 1u);
+    tci[s + at] = (int32_t)(uint32_t)x;
+  }
+}
+
 // ------------------------------------------------------------------ statistics (Sections 4-5)
 
 // Statistics of N_hat(0..T) into out[0..8]: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi,
@@ -1634,6 +1800,40 @@ hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s) {
 
 hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_tp_first(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t range, int32_t bs,
+                           int32_t nb, int32_t n_ranges, uint64_t *hist, uint64_t *scan_tmp, uint64_t *pairs,
+                           uint64_t *bstart, hipStream_t s) {
+  hipLaunchKernelGGL(k_tp_hist, dim3((unsigned)n_ranges), dim3(kTpThreads), 0, s, row_ptr, col_idx, n, range, bs, nb,
+                     n_ranges, hist);
+  hipError_t e = launch_fill_u64(hist + (int64_t)nb * n_ranges, 1, 0ull, s);  // the total's slot
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan_u64(hist, (int64_t)nb * n_ranges + 1, scan_tmp, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tp_scatter, dim3((unsigned)n_ranges), dim3(kTpThreads), 0, s, row_ptr, col_idx, n, range, bs, nb,
+                     n_ranges, hist, pairs);
+  hipLaunchKernelGGL(k_tp_bounds, dim3(grid_for((int64_t)nb + 1, 256, 1 << 30)), dim3(256), 0, s, hist, nb, n_ranges,
+                     bstart);
+  return hipGetLastError();
+}
+
+hipError_t launch_tp_second(const uint64_t *pairs, const uint64_t *bstart, const int32_t *blist, int32_t n_light,
+                            const int32_t *hlist, const int32_t *hchunk0, int32_t n_heavy, const int64_t *chunk_lo,
+                            const int64_t *chunk_hi, const int64_t *chunk_s, int32_t n_hchunks, uint32_t *h2, int32_t bs,
+                            int32_t n, int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s) {
+  if (n_light > 0)
+    hipLaunchKernelGGL(k_tp_bucket, dim3((unsigned)n_light), dim3(kTpThreads), 0, s, pairs, bstart, blist, bs, n,
+                       trow_ptr, tcol_idx);
+  if (n_heavy > 0) {
+    hipLaunchKernelGGL(k_tp_chunk_hist, dim3((unsigned)n_hchunks), dim3(kTpThreads), 0, s, pairs, chunk_lo, chunk_hi, bs,
+                       h2);
+    hipLaunchKernelGGL(k_tp_heavy_scan, dim3((unsigned)n_heavy), dim3(kTpThreads), 0, s, bstart, hlist, hchunk0, bs, n,
+                       h2, trow_ptr);
+    hipLaunchKernelGGL(k_tp_chunk_scatter, dim3((unsigned)n_hchunks), dim3(kTpThreads), 0, s, pairs, chunk_lo, chunk_hi,
+                       chunk_s, bs, h2, tcol_idx);
+  }
   return hipGetLastError();
 }
 
