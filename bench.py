@@ -6,8 +6,8 @@ One step is a whole HyperANF run on a graph already resident in HBM: graph inges
 counter changes, and the statistics (distance distribution, effective diameter, spid).
 The default workload is the symmetric R-MAT graph of scale 22 (2^22 nodes, 2^26 arcs,
 a=.57 b=.19 c=.19 d=.05) with 64 registers per counter and hash seed 7. Late passes are
-systolic (Section 3.3): a symmetric graph is its own transpose, so its device arrays are
-given as the transposed graph too (--transpose self); for a directed workload the
+systolic (Section 3.3): a symmetric graph is its own transpose, so it is declared as such
+(hanf_transpose_self, --transpose self); for a directed workload the
 transpose is built on the device inside the step (--transpose build) or not used (none).
 
 Prints one JSON line. `value` = edge-register updates per second over the whole step:
@@ -244,7 +244,7 @@ def run_seeds_mode(args):
         for sd in seeds:
             h.load(drp, dci)
             if sym:
-                h.load_transpose(drp, dci)
+                h.transpose_self()
             h.init(b, sd)
             nt = h.run()
             h.stats()
@@ -453,7 +453,7 @@ def main():
     def step():
         h.load(trp, tci)
         if tmode == "self":
-            h.load_transpose(trp, tci)
+            h.transpose_self()
         elif tmode == "build":
             h.build_transpose()
         h.init(b, seed)

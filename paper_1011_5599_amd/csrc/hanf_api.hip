@@ -340,8 +340,10 @@ int read_state(hanf_ctx *c) {
 void choose_schedule(hanf_ctx *c, int G, Schedule &s) {
   const int W = kWave / G;
   s.G = G;
-  s.light_max = c->light_max_opt > 0 ? c->light_max_opt : 64;
-  s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, W * c->unroll * 8);
+  // defaults measured on MI355X over light_max 16..128 and chunk_arcs 256..2048: 16 arcs per
+  // row lane (clamped to 32..128) and 16 arcs per slot and unrolled gather in a chunk
+  s.light_max = c->light_max_opt > 0 ? c->light_max_opt : std::max(32, std::min(128, 16 * G));
+  s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, std::min(2048, W * c->unroll * 16));
   int32_t tile = c->tile_opt;
   if (tile <= 0) {
     // about 8 rounds of W nodes per wavefront on large graphs (measured best on MI355X for

@@ -24,7 +24,8 @@ SPACE = {
     "dense_switch": [0, 2, 4, 8],
 }
 
-DEFAULTS = {"light_max": 64, "chunk_arcs": 0, "tile_nodes": 0, "unroll": 4, "dense_switch": 4}
+DEFAULTS = {"light_max": 0, "chunk_arcs": 0, "tile_nodes": 0, "unroll": 4, "dense_switch": 4}
+# 0: the library default for the run's row width (light_max and chunk_arcs grow with it)
 # batched runs also tune `seeds_per_row` (0 = as many seeds per node row as fit) and `group`
 
 
