@@ -74,6 +74,15 @@ extern "C" {
                                    all). 0 (default): as many as fit, up to 32 and 1024 bytes
                                    per row; else a power of two up to 32. Results do not change */
 
+#define HANF_OPT_PACKED5 11     /* 1: single runs keep 5-bit registers packed without gaps, as in
+                                   Section 3.3 (register j of a counter at bits 5j..5j+4 of its
+                                   little-endian bit string: 5m/8 bytes per counter instead of m),
+                                   maximised with the paper's broadword multi-word max. Needs
+                                   m >= 64 (64 registers fill five 64-bit words) and a single
+                                   graph; read from the next hanf_init_counters. Results are
+                                   identical; register I/O stays one byte per register. 0: one
+                                   register per byte (default, faster on MI355X) */
+
 /* Tuning and test options (the results never change):
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
  *   101  the persistent union kernel over listed work units: 0 (default) for systolic
@@ -82,6 +91,7 @@ extern "C" {
 /* ---- hanf_footprint flags */
 #define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */
 #define HANF_FP_TRANSPOSE 2     /* include the transposed graph and the systolic signal buffers */
+#define HANF_FP_PACKED5 4       /* 5-bit registers (HANF_OPT_PACKED5); needs log2m >= 6 */
 
 typedef struct hanf_ctx hanf_ctx;
 
@@ -194,7 +204,9 @@ int hanf_poll(hanf_ctx *ctx, int32_t *t);
 int hanf_read_nt(hanf_ctx *ctx, double *out, int32_t cap, int32_t *len);
 
 /* Copies the current counters c_t (n*m bytes, node-major, m bytes per node, register j
- * of node v at v*m + j) to `out` (host or device per flags). `bytes` must be n*m. */
+ * of node v at v*m + j) to `out` (host or device per flags). `bytes` must be n*m. Packed
+ * 5-bit registers are unpacked on the device (through a staging buffer of at most 64 MiB
+ * when `out` is host memory). */
 int hanf_read_registers(hanf_ctx *ctx, uint8_t *out, int64_t bytes, uint32_t flags);
 
 /* The estimate size(c_t[v]) of every current counter (Algorithm 1, with the small-range
@@ -203,7 +215,8 @@ int hanf_read_registers(hanf_ctx *ctx, uint8_t *out, int64_t bytes, uint32_t fla
 int hanf_read_estimates(hanf_ctx *ctx, double *out, int64_t count, uint32_t flags);
 
 /* Resumes from a checkpoint: counters `in` (n*m bytes, layout of hanf_read_registers,
- * values <= 31) taken at iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
+ * values <= 31; packed on the device when the run keeps 5-bit registers) taken at
+ * iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
  * Every counter is treated as modified for the next pass, so the continuation is
  * identical to an uninterrupted run. Requires a prior hanf_init_counters (fixes m). */
 int hanf_write_registers(hanf_ctx *ctx, const uint8_t *in, int64_t bytes, int32_t t,
@@ -280,6 +293,14 @@ int hanf_batch_stats_all(hanf_ctx *ctx, double alpha, double eps, int32_t distin
 
 /* Last error message of the context, or of the calling thread when ctx is NULL. */
 const char *hanf_last_error(const hanf_ctx *ctx);
+
+/* Section 3.3's broadword register-wise max on 5-bit fields, on its own: `groups` groups of
+ * 64 registers packed in five 64-bit words (40 bytes, register j at bits 5j..5j+4 of the
+ * group's little-endian bit string, so fields 12, 25, 38 and 51 straddle two words);
+ * out = max(x, y) per register. Device pointers, 8-byte aligned, on device `device`.
+ * The same function the union kernel uses with HANF_OPT_PACKED5; exposed for exhaustive
+ * testing. Synchronous. */
+int hanf_max5_groups(int device, const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups);
 
 /* Register-wise maximum of `count` 32-bit words, each holding four registers (values
  * <= 127): out[i] = bytewise max(x[i], y[i]), on device `device`. Device pointers. Exposes

@@ -43,8 +43,10 @@ HANF_OPT_TILE_NODES = 7
 HANF_OPT_DENSE_SWITCH = 8
 HANF_OPT_SYSTOLIC = 9
 HANF_OPT_SEEDS_PER_ROW = 10
+HANF_OPT_PACKED5 = 11
 HANF_FP_COPY_GRAPH = 1
 HANF_FP_TRANSPOSE = 2
+HANF_FP_PACKED5 = 4
 HANF_OPT_UNROLL = 100
 HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
 
@@ -130,6 +132,7 @@ def lib():
             "hanf_footprint": ([i32, i64, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
+            "hanf_max5_groups": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
             "hanf_load_batch": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
             "hanf_load_batch_list": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
             "hanf_enqueue": ([vp, i32], ctypes.c_int),
@@ -301,11 +304,21 @@ def hanf_read_pass_log(ctx) -> list[dict]:
             for i in range(n.value)]
 
 
-def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True, transpose: bool = False) -> int:
+def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True, transpose: bool = False,
+                   packed5: bool = False) -> int:
     out = ctypes.c_int64()
-    flags = (HANF_FP_COPY_GRAPH if copy_graph else 0) | (HANF_FP_TRANSPOSE if transpose else 0)
+    flags = ((HANF_FP_COPY_GRAPH if copy_graph else 0) | (HANF_FP_TRANSPOSE if transpose else 0)
+             | (HANF_FP_PACKED5 if packed5 else 0))
     _check(lib().hanf_footprint(n, arcs, log2m, flags, ctypes.byref(out)))
     return out.value
+
+
+def hanf_max5_groups(device: int, x, y, out) -> None:
+    """Device uint8 tensors of 40-byte groups (64 packed 5-bit registers each);
+    out = register-wise max of x and y."""
+    if x.numel() % 40 or y.numel() != x.numel() or out.numel() != x.numel():
+        raise ValueError("x, y and out must hold the same whole number of 40-byte groups")
+    _check(lib().hanf_max5_groups(device, x.data_ptr(), y.data_ptr(), out.data_ptr(), x.numel() // 40))
 
 
 def hanf_bytemax_words(device: int, x, y, out) -> None:
@@ -422,7 +435,7 @@ class HyperANF:
                  "timing": HANF_OPT_TIMING, "batch": HANF_OPT_BATCH,
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
-                 "seeds_per_row": HANF_OPT_SEEDS_PER_ROW,
+                 "seeds_per_row": HANF_OPT_SEEDS_PER_ROW, "packed5": HANF_OPT_PACKED5,
                  "union_policy": HANF_OPT_UNION_POLICY}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))

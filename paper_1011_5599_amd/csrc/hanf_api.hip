@@ -32,7 +32,8 @@ double alpha_for(int m) {
 }
 
 struct Schedule {
-  int G = 0;  // lanes per counter the schedule was built for
+  int G = 0;          // lanes per node row the schedule was built for
+  int lane_bytes = 0; // bytes per lane of the register format (partial rows)
   int32_t light_max = 0, chunk_arcs = 0, tile_nodes = 0;
   int32_t n_tiles = 0, n_chunks = 0, n_heavy = 0;
   int32_t n_chunk_wgs = 0, n_light_wgs = 0, n_fin_wgs = 0;
@@ -68,6 +69,7 @@ struct hanf_ctx {
   int unroll = 4;
   int sys_div = 4;    // a pass after one that changed < n/sys_div counters is systolic (0 = never)
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
+  int packed_opt = 0;    // 1: 5-bit registers for single runs (HANF_OPT_PACKED5)
   bool sys_seen = false; // the last state read showed a systolic next pass
 
   // graph
@@ -109,6 +111,7 @@ struct hanf_ctx {
   // run state
   int log2m = 0;
   int sl = 0;  // log2 of the counters per node row
+  int packed = 0;  // the run's registers are 5-bit packed
   bool inited = false;
   uint8_t *regs[2] = {nullptr, nullptr};
   uint32_t *bits[2] = {nullptr, nullptr};
@@ -259,6 +262,7 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->sys_pos);
   c->inited = false;
   c->log2m = 0;
+  c->packed = 0;
 }
 
 // Drops an expanded batch layout (the base remains).
@@ -337,9 +341,10 @@ int read_state(hanf_ctx *c) {
 }
 
 // Default schedule parameters for G lanes per counter (W = 64/G slots per wavefront).
-void choose_schedule(hanf_ctx *c, int G, Schedule &s) {
+void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   const int W = kWave / G;
   s.G = G;
+  s.lane_bytes = lane_bytes;
   // defaults measured on MI355X over light_max 16..128 and chunk_arcs 256..2048: 16 arcs per
   // row lane (clamped to 32..128) and 16 arcs per slot and unrolled gather in a chunk
   s.light_max = c->light_max_opt > 0 ? c->light_max_opt : std::max(32, std::min(128, 16 * G));
@@ -356,10 +361,10 @@ void choose_schedule(hanf_ctx *c, int G, Schedule &s) {
   s.tile_nodes = tile;
 }
 
-int build_schedule(hanf_ctx *c, int G) {
+int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   free_schedule(c);
   Schedule &s = c->sch;
-  choose_schedule(c, G, s);
+  choose_schedule(c, G, lane_bytes, s);
   const int32_t n = c->n;
   s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
   int rc;
@@ -385,10 +390,10 @@ int build_schedule(hanf_ctx *c, int G) {
   }
   s.n_chunks = (int32_t)(total >> 32);
   s.n_heavy = (int32_t)(total & 0xffffffffull);
-  const int m = 16 * G;
+  const size_t row_bytes = (size_t)G * s.lane_bytes;
   if ((rc = dev_alloc(c, &s.chunks, (size_t)s.n_chunks, "chunks")) ||
       (rc = dev_alloc(c, &s.heavy, (size_t)s.n_heavy, "heavy nodes")) ||
-      (rc = dev_alloc(c, &s.partial, (size_t)s.n_chunks * m, "chunk partials")) ||
+      (rc = dev_alloc(c, &s.partial, (size_t)s.n_chunks * row_bytes, "chunk partials")) ||
       (rc = dev_alloc(c, &s.partial_any, (size_t)s.n_chunks, "chunk flags"))) {
     dev_release(c, keys);
     dev_release(c, tmp);
@@ -446,7 +451,8 @@ void fill_args(hanf_ctx *c) {
   a.n = c->n;
   a.log2m = c->log2m;
   a.seed_log2 = c->sl;
-  a.gs = c->log2m >= 4 ? 1 << (c->log2m - 4) : 1;
+  a.packed = c->packed;
+  a.gs = c->packed ? 1 << (c->log2m - 6) : 1 << (c->log2m - 4);
   a.n_blocks = c->n_blocks;
   a.n_chunks = c->sch.n_chunks;
   a.n_chunk_wgs = c->sch.n_chunk_wgs;
@@ -487,11 +493,83 @@ int64_t default_max_passes(const hanf_ctx *c) {
   return c->batch ? std::min<int64_t>(1024, (int64_t)c->n + 1) : (int64_t)c->n + 1;
 }
 
-int alloc_run(hanf_ctx *c, int log2m, int sl) {
+// Packed registers move through a device staging buffer of at most this many 64-register
+// groups (64 MiB unpacked) when the caller's buffer is in host memory.
+constexpr int64_t kStageGroups = 1 << 20;
+
+// The counters in `src` (the run's format) as one byte per register: n * m bytes at `out`.
+int regs_to_bytes(hanf_ctx *c, const uint8_t *src, uint8_t *out, uint32_t flags) {
+  const size_t bytes = (size_t)c->n << c->log2m;
+  if (!c->packed) {
+    HIP_TRY(c, hipMemcpyAsync(out, src, bytes,
+                              flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+            "register read");
+    return sync(c, "register read");
+  }
+  const int64_t groups = (int64_t)(bytes / 64);
+  if (flags == HANF_DEVICE_PTRS) {
+    HIP_TRY(c, launch_unpack5(src, out, groups, c->stream), "register unpack");
+    return sync(c, "register read");
+  }
+  const int64_t chunk = std::min<int64_t>(groups, kStageGroups);
+  uint8_t *stage = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &stage, (size_t)chunk * 64, "register staging"))) return rc;
+  hipError_t e = hipSuccess;
+  for (int64_t g0 = 0; g0 < groups && e == hipSuccess; g0 += chunk) {
+    const int64_t cnt = std::min(chunk, groups - g0);
+    e = launch_unpack5(src + g0 * kPacked5LaneBytes, stage, cnt, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + g0 * 64, stage, (size_t)cnt * 64, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  dev_release(c, stage);
+  if (e != hipSuccess) return hip_fail(c, e, "register read");
+  return HANF_OK;
+}
+
+// One byte per register (n * m bytes at `in`, each <= 31) into `dst` in the run's format.
+// Sets DevState::err (16) when a register is above 31; the caller reads the state.
+int bytes_to_regs(hanf_ctx *c, const uint8_t *in, uint8_t *dst, uint32_t flags) {
+  const size_t bytes = (size_t)c->n << c->log2m;
+  const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (!c->packed) {
+    HIP_TRY(c, hipMemcpyAsync(dst, in, bytes, kind, c->stream), "register upload");
+    HIP_TRY(c, launch_check_registers(dst, (int64_t)bytes, c->st, c->stream), "register check");
+    return HANF_OK;
+  }
+  const int64_t groups = (int64_t)(bytes / 64);
+  if (flags == HANF_DEVICE_PTRS) {
+    HIP_TRY(c, launch_check_registers(in, (int64_t)bytes, c->st, c->stream), "register check");
+    HIP_TRY(c, launch_pack5(in, dst, groups, c->stream), "register pack");
+    return HANF_OK;
+  }
+  const int64_t chunk = std::min<int64_t>(groups, kStageGroups);
+  uint8_t *stage = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &stage, (size_t)chunk * 64, "register staging"))) return rc;
+  hipError_t e = hipSuccess;
+  for (int64_t g0 = 0; g0 < groups && e == hipSuccess; g0 += chunk) {
+    const int64_t cnt = std::min(chunk, groups - g0);
+    e = hipMemcpyAsync(stage, in + g0 * 64, (size_t)cnt * 64, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_check_registers(stage, cnt * 64, c->st, c->stream);
+    if (e == hipSuccess) e = launch_pack5(stage, dst + g0 * kPacked5LaneBytes, cnt, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the staging buffer is reused
+  }
+  dev_release(c, stage);
+  if (e != hipSuccess) return hip_fail(c, e, "register upload");
+  return HANF_OK;
+}
+
+// Bytes of one node's row of counters: S counters of m bytes, or one of 5m/8 bytes (packed).
+size_t row_bytes(int log2m, int sl, int packed) {
+  return packed ? ((size_t)kPacked5LaneBytes << (log2m - 6)) : ((size_t)1 << log2m) << sl;
+}
+
+int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
   free_run(c);
   const int m = 1 << log2m;
   const size_t S = (size_t)1 << sl;  // counters per node row
-  const size_t bytes = (size_t)c->n * m * S;
+  const size_t bytes = (size_t)c->n * row_bytes(log2m, sl, packed);
   c->n_blocks = (int32_t)(((int64_t)c->n + kNodesPerBlock - 1) / kNodesPerBlock);
   c->n_reduce_wgs = (c->n_blocks + kReduceBlocks - 1) / kReduceBlocks;
   c->max_passes = (int32_t)std::min<int64_t>(default_max_passes(c), INT32_MAX - 8);
@@ -534,6 +612,7 @@ int alloc_run(hanf_ctx *c, int log2m, int sl) {
           "table upload");
   c->log2m = log2m;
   c->sl = sl;
+  c->packed = packed;
   return HANF_OK;
 }
 
@@ -854,6 +933,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
         return fail(c, HANF_EINVAL, "seeds per row must be 0 or a power of two up to 32");
       c->seeds_row_opt = (int)value;
       break;
+    case HANF_OPT_PACKED5:
+      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "packed5 must be 0 or 1");
+      c->packed_opt = (int)value;
+      break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
       c->union_policy = (int)value;
@@ -1055,6 +1138,9 @@ namespace {
 int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds) {
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
   if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
+  const int packed = c->packed_opt;
+  if (packed && c->batch) return fail(c, HANF_EINVAL, "5-bit registers are for single graphs");
+  if (packed && log2m < 6) return fail(c, HANF_EINVAL, "5-bit registers need m >= 64 (log2m >= 6)");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   int sl = 0;
@@ -1066,12 +1152,14 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
     while ((1 << sl) < S) ++sl;
     if ((rc = set_layout(c, (c->n_seeds + S - 1) / S))) return rc;
   }
-  const int G = (1 << (log2m - 4)) << sl;  // lanes per node row
+  // lanes per node row: 16 byte registers or 64 packed ones per lane
+  const int G = packed ? 1 << (log2m - 6) : (1 << (log2m - 4)) << sl;
+  const int lane_bytes = packed ? kPacked5LaneBytes : 16;
   Schedule want;
-  choose_schedule(c, G, want);
-  if (c->sch.G != G || !c->sch.light || want.light_max != c->sch.light_max ||
+  choose_schedule(c, G, lane_bytes, want);
+  if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
       want.chunk_arcs != c->sch.chunk_arcs || want.tile_nodes != c->sch.tile_nodes) {
-    if ((rc = build_schedule(c, G))) return rc;
+    if ((rc = build_schedule(c, G, lane_bytes))) return rc;
   }
   size_t n_cchunks_before = c->cchunk_comp_h.size();
   if (c->batch) {
@@ -1100,9 +1188,9 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
     c->chunk0_h[(size_t)c->n_comp] = (int32_t)c->cchunk_comp_h.size();
   }
   const int64_t want_cap = default_max_passes(c) + 2;
-  if (c->log2m != log2m || c->sl != sl || !c->regs[0] || want_cap != c->nt_cap ||
+  if (c->log2m != log2m || c->sl != sl || c->packed != packed || !c->regs[0] || want_cap != c->nt_cap ||
       c->cchunk_comp_h.size() != n_cchunks_before) {
-    if ((rc = alloc_run(c, log2m, sl))) return rc;
+    if ((rc = alloc_run(c, log2m, sl, packed))) return rc;
   }
   if (c->batch) {
     HIP_TRY(c, hipMemcpyAsync(c->slot_comp, c->slot_h.data(), sizeof(int32_t) * c->slot_h.size(),
@@ -1293,11 +1381,7 @@ int hanf_read_registers(hanf_ctx *c, uint8_t *out, int64_t bytes, uint32_t flags
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   if ((rc = read_state(c))) return rc;
-  const uint8_t *src = c->regs[c->st_host->t & 1];
-  HIP_TRY(c, hipMemcpyAsync(out, src, (size_t)bytes,
-                            flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
-          "register read");
-  return sync(c, "register read");
+  return regs_to_bytes(c, c->regs[c->st_host->t & 1], out, flags);
 }
 
 int hanf_read_estimates(hanf_ctx *c, double *out, int64_t count, uint32_t flags) {
@@ -1323,18 +1407,17 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   if (t < 0 || len != t + 1) return fail(c, HANF_EINVAL, "len must be t + 1");
   if (t + 2 > c->nt_cap) return fail(c, HANF_ERANGE, "t beyond the pass cap");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  const hipMemcpyKind kind = flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   c->inited = false;
   c->sys_seen = false;
   HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
                                 c->stream),
           "state reset");
-  HIP_TRY(c, hipMemcpyAsync(c->regs[t & 1], in, (size_t)bytes, kind, c->stream), "register upload");
-  HIP_TRY(c, launch_check_registers(c->regs[t & 1], bytes, c->st, c->stream), "register check");
   int rc;
+  if ((rc = bytes_to_regs(c, in, c->regs[t & 1], flags))) return rc;
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) return fail(c, HANF_EINVAL, "register value above 31");
-  HIP_TRY(c, hipMemcpyAsync(c->regs[(t + 1) & 1], c->regs[t & 1], (size_t)bytes, hipMemcpyDeviceToDevice, c->stream),
+  HIP_TRY(c, hipMemcpyAsync(c->regs[(t + 1) & 1], c->regs[t & 1], (size_t)c->n * row_bytes(c->log2m, c->sl, c->packed),
+                            hipMemcpyDeviceToDevice, c->stream),
           "register copy");
   fill_args(c);
   c->host_log.clear();
@@ -1388,9 +1471,12 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   if (!bytes) return fail(nullptr, HANF_EINVAL, "bytes is NULL");
   if (n < 1 || arcs < 0 || arcs >= (int64_t)INT32_MAX || log2m < 4 || log2m > 8)
     return fail(nullptr, HANF_EINVAL, "hanf_footprint: argument out of range");
+  if ((copy_graph & HANF_FP_PACKED5) && log2m < 6)
+    return fail(nullptr, HANF_EINVAL, "hanf_footprint: 5-bit registers need log2m >= 6");
   const int64_t m = 1LL << log2m;
   const int64_t blocks = ((int64_t)n + kNodesPerBlock - 1) / kNodesPerBlock;
-  int64_t b = 2 * (int64_t)n * m;                        // counters + update buffer
+  // counters + update buffer: m bytes per counter, or 5m/8 with 5-bit registers
+  int64_t b = 2 * (int64_t)n * ((copy_graph & HANF_FP_PACKED5) ? m * 5 / 8 : m);
   b += 2 * 2 * blocks * 4;                               // modified flags
   b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
   b += (int64_t)n * 4 + 4096;                            // light tiles
@@ -1764,6 +1850,17 @@ int hanf_batch_stats_all(hanf_ctx *c, double alpha, double eps, int32_t distinct
 }
 
 const char *hanf_last_error(const hanf_ctx *c) { return c ? c->err.c_str() : g_thread_error.c_str(); }
+
+int hanf_max5_groups(int device, const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups) {
+  if (!x || !y || !out || groups < 0) return fail(nullptr, HANF_EINVAL, "hanf_max5_groups: bad argument");
+  if (((uintptr_t)x | (uintptr_t)y | (uintptr_t)out) & 7u)
+    return fail(nullptr, HANF_EINVAL, "hanf_max5_groups: buffers must be 8-byte aligned");
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess && groups > 0) e = launch_max5_groups(x, y, out, groups, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hanf_max5_groups");
+  return HANF_OK;
+}
 
 int hanf_bytemax_words(int device, const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
   if (!x || !y || !out || count < 0) return fail(nullptr, HANF_EINVAL, "hanf_bytemax_words: bad argument");

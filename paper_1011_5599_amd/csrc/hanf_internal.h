@@ -15,6 +15,7 @@ constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
+constexpr int kPacked5LaneBytes = 40;   // 64 registers of 5 bits: one lane of a packed counter
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
@@ -117,7 +118,9 @@ struct PassArgs {
   int32_t n;
   int32_t log2m;             // m = 2^log2m registers per counter
   int32_t seed_log2;         // S = 2^seed_log2 counters per node row (1 for a single run)
-  int32_t gs;                // lanes per counter, m / 16 (a row has S * gs lanes)
+  int32_t gs;                // lanes per counter: m / 16, or m / 64 for 5-bit registers
+                             // (a row has S * gs lanes)
+  int32_t packed;            // 1: 5-bit registers packed in 64-bit words (single runs, m >= 64)
   int32_t n_blocks;          // ceil(n / 64)
   int32_t n_chunks;
   int32_t n_chunk_wgs;       // union workgroups given to chunks (multiple of 8)
@@ -193,5 +196,8 @@ hipError_t launch_set_history(double *nt, const double *prefix, int32_t len, Dev
                               int32_t t, hipStream_t s);
 hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
                                 hipStream_t s);
+hipError_t launch_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups, hipStream_t s);
+hipError_t launch_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups, hipStream_t s);
+hipError_t launch_pack5(const uint8_t *in, uint8_t *packed, int64_t groups, hipStream_t s);
 
 }  // namespace hanf

@@ -4,6 +4,7 @@
 // Data layout in HBM (S = counters per node row: 1 for a single run, up to 32 seeds of a
 // batched run side by side):
 //   regs[2]   uint8 [n][S][m]  counters c_t and c_{t+1}, node-major, m = 2^log2m bytes each
+//             (or [n][5m/8] with 5-bit registers packed without gaps, single runs)
 //   bits[2]   uint32 [2 * S * ceil(n/64)]  modified-counter flags (S bits per node) of the
 //             previous / current pass
 //   est       double [n][S]    estimate of each current counter
@@ -12,8 +13,8 @@
 // One pass (c_t -> c_{t+1}) is one launch of k_union (+ k_finalize when a node's arcs are
 // split over several wavefronts) and two reduction launches. The union is bound by HBM
 // bandwidth: random gathers of m-byte successor counters. Lanes load counters 16 bytes at a
-// time; a node row (S counters) is handled by G = S*m/16 lanes (a "slot"); a wavefront holds
-// W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
+// time (40 bytes, 64 registers, when packed); a node row (S counters) is handled by
+// G = S*m/16 lanes (m/64 packed), a "slot"; a wavefront holds W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
 // read, one S*m-byte gather); changes, flags and estimates are kept per counter.
 //   - light nodes (few arcs): one slot per node, nodes of a tile sorted by degree so the
 //     slots of a wavefront finish together; tiles are assigned to XCDs in contiguous runs
@@ -46,14 +47,6 @@ __device__ __forceinline__ uint4 bytemax4(uint4 a, uint4 b) {
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 
-__device__ __forceinline__ uint4 ldrow(const uint8_t *regs, int32_t v, int m, int sub) {
-  return *reinterpret_cast<const uint4 *>(regs + (size_t)v * (size_t)m + (size_t)sub * 16);
-}
-
-__device__ __forceinline__ void strow(uint8_t *regs, int32_t v, int m, int sub, uint4 x) {
-  *reinterpret_cast<uint4 *>(regs + (size_t)v * (size_t)m + (size_t)sub * 16) = x;
-}
-
 // Was any counter of node v's row modified? (S = 2^sl flag bits per node, never across words.)
 __device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl) {
   const uint64_t i = (uint64_t)v << sl;
@@ -65,6 +58,180 @@ __device__ __forceinline__ uint4 shfl_xor4(uint4 a, int off) {
   return make_uint4(__shfl_xor(a.x, off), __shfl_xor(a.y, off), __shfl_xor(a.z, off),
                     __shfl_xor(a.w, off));
 }
+
+// ------------------------------------------------------------------ register formats
+//
+// The kernels below are written once for a register format F: F::Lane is the part of a
+// counter one lane holds (F::kRegs registers in F::kBytes bytes), a row of G lanes is
+// G * F::kBytes bytes, and F supplies the load, store, register-wise max, comparison,
+// cross-lane shuffle, the terms of the size estimate, and a lane with one register set.
+
+// One register per byte; a lane holds 16 registers (one 16-byte load).
+struct ByteRegs {
+  using Lane = uint4;
+  static constexpr int kRegs = 16;
+  static constexpr int kBytes = 16;
+  static __device__ __forceinline__ Lane zero() { return zero4(); }
+  static __device__ __forceinline__ Lane load(const uint8_t *regs, int64_t row, int G, int sub) {
+    return *reinterpret_cast<const uint4 *>(regs + ((size_t)row * G + sub) * kBytes);
+  }
+  static __device__ __forceinline__ void store(uint8_t *regs, int64_t row, int G, int sub, Lane x) {
+    *reinterpret_cast<uint4 *>(regs + ((size_t)row * G + sub) * kBytes) = x;
+  }
+  static __device__ __forceinline__ Lane max(Lane a, Lane b) { return bytemax4(a, b); }
+  static __device__ __forceinline__ bool differ(Lane a, Lane b) {
+    return a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w;
+  }
+  static __device__ __forceinline__ Lane shfl_xor(Lane a, int off) { return shfl_xor4(a, off); }
+  // sum of 2^(31 - M[j]) and number of zero registers over the lane's registers
+  static __device__ __forceinline__ void size_terms(Lane a, uint64_t &S, uint32_t &V) {
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t r = (w[i] >> (8 * k)) & 0xffu;
+        S += (uint64_t)(1u << (31u - r));
+        V += (r == 0u);
+      }
+    }
+  }
+  // register `j` (0..15) of the lane set to r, the others 0
+  static __device__ __forceinline__ Lane single(uint32_t j, uint32_t r) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if ((j >> 2) == (uint32_t)i) w[i] = r << (8 * (j & 3u));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+  }
+};
+
+// Word `word` (64 bits) of the bit string with ones at positions 5i + bit.
+constexpr uint64_t field_bits5(int word, int bit) {
+  uint64_t x = 0;
+  for (int b = 0; b < 64; ++b)
+    if ((64 * word + b) % 5 == bit) x |= 1ull << b;
+  return x;
+}
+
+// 5-bit registers packed without gaps (Section 3.3): register j of a counter is bits
+// 5j .. 5j+4 of its little-endian bit string, so a counter of m registers is 5m/8 bytes and
+// fields straddle the 64-bit words. A lane holds 64 registers: 320 bits, five words, which
+// start on a word boundary (the paper's "at least w registers per counter", w = 64).
+struct Packed5Regs {
+  struct Lane {
+    uint64_t w[5];
+  };
+  static constexpr int kRegs = 64;
+  static constexpr int kBytes = 40;
+  // the lowest (L) and the highest (H) bit of every 5-bit field, word k of five
+  static __host__ __device__ __forceinline__ constexpr uint64_t L(int k) {
+    return k == 0 ? 0x1084210842108421ull : k == 1 ? 0x2108421084210842ull : k == 2 ? 0x4210842108421084ull
+         : k == 3 ? 0x8421084210842108ull : 0x0842108421084210ull;
+  }
+  static __host__ __device__ __forceinline__ constexpr uint64_t H(int k) {
+    return k == 0 ? 0x0842108421084210ull : k == 1 ? 0x1084210842108421ull : k == 2 ? 0x2108421084210842ull
+         : k == 3 ? 0x4210842108421084ull : 0x8421084210842108ull;
+  }
+  static __device__ __forceinline__ Lane zero() {
+    Lane z;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) z.w[k] = 0ull;
+    return z;
+  }
+  static __device__ __forceinline__ Lane load(const uint8_t *regs, int64_t row, int G, int sub) {
+    const uint64_t *p = reinterpret_cast<const uint64_t *>(regs + ((size_t)row * G + sub) * kBytes);
+    Lane x;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) x.w[k] = p[k];
+    return x;
+  }
+  static __device__ __forceinline__ void store(uint8_t *regs, int64_t row, int G, int sub, Lane x) {
+    uint64_t *p = reinterpret_cast<uint64_t *>(regs + ((size_t)row * G + sub) * kBytes);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) p[k] = x.w[k];
+  }
+  // Broadword register-wise max of Section 3.3 on k = 5-bit fields. The comparison
+  //   lt = (((x | H) - (y & ~H)) | (x ^ y)) ^ (x | ~y)) & H
+  // sets the high bit of every field where x < y. Per field the subtraction is
+  // 2^4 + x_low - y_low >= 1, so it never borrows out of a field; a field that straddles two
+  // words borrows from its low part into its high part, which is the multi-word borrow. The
+  // selection mask moves each result bit to its field's low bit (a multi-word shift right by
+  // 4), ors in H and subtracts L (1 per field, again only borrowing inside a field): a field
+  // becomes 1 0000 where x < y and 0 1111 elsewhere; or-ing H and xor-ing lt turn those into
+  // all zeros and all ones. The result takes x where the mask is set and y elsewhere.
+  static __device__ __forceinline__ Lane max(Lane x, Lane y) {
+    uint64_t lt[5];
+    uint64_t borrow = 0ull;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const uint64_t a = x.w[k] | H(k), b = y.w[k] & ~H(k);
+      const uint64_t d0 = a - b, d = d0 - borrow;
+      borrow = (uint64_t)(a < b) | (uint64_t)(d0 < borrow);
+      lt[k] = ((d | (x.w[k] ^ y.w[k])) ^ (x.w[k] | ~y.w[k])) & H(k);
+    }
+    Lane out;
+    borrow = 0ull;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const uint64_t sh = (lt[k] >> 4) | (k < 4 ? lt[k + 1 < 5 ? k + 1 : 4] << 60 : 0ull);
+      const uint64_t a = sh | H(k);
+      const uint64_t d0 = a - L(k), d = d0 - borrow;
+      borrow = (uint64_t)(a < L(k)) | (uint64_t)(d0 < borrow);
+      const uint64_t mask = (d | H(k)) ^ lt[k];
+      out.w[k] = (x.w[k] & mask) | (y.w[k] & ~mask);
+    }
+    return out;
+  }
+  static __device__ __forceinline__ bool differ(Lane a, Lane b) {
+    uint64_t d = 0ull;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) d |= a.w[k] ^ b.w[k];
+    return d != 0ull;
+  }
+  static __device__ __forceinline__ Lane shfl_xor(Lane a, int off) {
+    Lane r;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const uint32_t lo = __shfl_xor((uint32_t)a.w[k], off);
+      const uint32_t hi = __shfl_xor((uint32_t)(a.w[k] >> 32), off);
+      r.w[k] = ((uint64_t)hi << 32) | lo;
+    }
+    return r;
+  }
+  static __device__ __forceinline__ void size_terms(Lane a, uint64_t &S, uint32_t &V) {
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      const int p = 5 * j, k = p >> 6, o = p & 63;
+      uint64_t f = a.w[k] >> o;
+      if (o > 59) f |= a.w[k + 1 < 5 ? k + 1 : 4] << (64 - o);
+      const uint32_t r = (uint32_t)f & 31u;
+      S += (uint64_t)(1u << (31u - r));
+      V += (r == 0u);
+    }
+  }
+  static __device__ __forceinline__ Lane single(uint32_t j, uint32_t r) {
+    const uint32_t p = 5u * j, k = p >> 6, o = p & 63u;
+    Lane x;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      uint64_t w = 0ull;
+      if ((uint32_t)i == k) w = (uint64_t)r << o;
+      if ((uint32_t)i == k + 1u && o > 59u) w = (uint64_t)r >> (64u - o);
+      x.w[i] = w;
+    }
+    return x;
+  }
+};
+static_assert(Packed5Regs::kBytes == kPacked5LaneBytes, "packed lane size");
+static_assert(Packed5Regs::L(0) == field_bits5(0, 0) && Packed5Regs::L(1) == field_bits5(1, 0) &&
+                  Packed5Regs::L(2) == field_bits5(2, 0) && Packed5Regs::L(3) == field_bits5(3, 0) &&
+                  Packed5Regs::L(4) == field_bits5(4, 0),
+              "low field bits");
+static_assert(Packed5Regs::H(0) == field_bits5(0, 4) && Packed5Regs::H(1) == field_bits5(1, 4) &&
+                  Packed5Regs::H(2) == field_bits5(2, 4) && Packed5Regs::H(3) == field_bits5(3, 4) &&
+                  Packed5Regs::H(4) == field_bits5(4, 4),
+              "high field bits");
 
 // ------------------------------------------------------------------ hash (Algorithm 1 add)
 
@@ -79,30 +246,22 @@ __device__ __forceinline__ uint64_t splitmix64_output(uint64_t seed, uint64_t k)
 
 // ------------------------------------------------------------------ estimator (Algorithm 1 size)
 
-// size() of the counter held by an aligned group of gs lanes (16 registers per lane), with
-// the HyperLogLog small-range rule. S = sum_j 2^(31 - M[j]) is an exact integer (<= 2^39),
-// so raw = alpha m^2 / sum_j 2^-M[j] = K / S with K = alpha m^2 2^31 takes one IEEE
-// division. All lanes of the group must be active; every lane returns the estimate.
-__device__ __forceinline__ double slot_estimate(uint4 acc, const double *lc, double K, int gs) {
-  const uint32_t w[4] = {acc.x, acc.y, acc.z, acc.w};
+// size() of the counter held by an aligned group of gs lanes (F::kRegs registers per lane),
+// with the HyperLogLog small-range rule. S = sum_j 2^(31 - M[j]) is an exact integer
+// (<= 2^39), so raw = alpha m^2 / sum_j 2^-M[j] = K / S with K = alpha m^2 2^31 takes one
+// IEEE division. All lanes of the group must be active; every lane returns the estimate.
+template <class F>
+__device__ __forceinline__ double slot_estimate(typename F::Lane acc, const double *lc, double K, int gs) {
   uint64_t S = 0;
   uint32_t V = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t r = (w[i] >> (8 * k)) & 0xffu;
-      S += (uint64_t)(1u << (31u - r));
-      V += (r == 0u);
-    }
-  }
+  F::size_terms(acc, S, V);
   for (int off = 1; off < gs; off <<= 1) {
     const uint32_t lo = __shfl_xor((uint32_t)S, off);
     const uint32_t hi = __shfl_xor((uint32_t)(S >> 32), off);
     S += ((uint64_t)hi << 32) | lo;
     V += __shfl_xor(V, off);
   }
-  const double m = 16.0 * gs;
+  const double m = (double)F::kRegs * gs;
   const double raw = K / (double)S;
   return (raw <= 2.5 * m && V > 0u) ? lc[V] : raw;
 }
@@ -146,33 +305,32 @@ struct Counters {
 // slots pass v < 0. Keeps the two register buffers consistent without copying unchanged
 // rows: next[v] already equals c_t[v] unless v was modified by the previous pass. Changes
 // and estimates are per counter: counter j of the row is lanes j*gs .. j*gs+gs-1.
-template <int G>
+template <class F, int G>
 __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f, int32_t v, int lane,
-                                              uint4 acc, bool any, bool own_loaded, uint4 own,
-                                              Counters &cnt) {
-  constexpr int R = 16 * G;  // row bytes
+                                              typename F::Lane acc, bool any, bool own_loaded,
+                                              typename F::Lane own, Counters &cnt) {
   const int sub = lane % G;
   const bool pv = (v >= 0 && f.copy_check) ? node_mod(f.prev_bits, v, f.sl) : false;
   const bool work = v >= 0 && (any || pv);
-  if (work && !own_loaded) own = ldrow(f.cur, v, R, sub);
+  if (work && !own_loaded) own = F::load(f.cur, v, G, sub);
   if (work) {
-    acc = bytemax4(acc, own);
+    acc = F::max(acc, own);
     if (sub == 0) cnt.read++;
   }
-  const bool diff = work && (acc.x != own.x || acc.y != own.y || acc.z != own.z || acc.w != own.w);
+  const bool diff = work && F::differ(acc, own);
   const uint64_t bal = __ballot(diff);
   const int first_lane = lane & ~(G - 1);
   const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
   const uint64_t rowbits = (bal >> first_lane) & gmask;  // lanes of this row that changed
   const bool changed = rowbits != 0ull;
   if (work && (changed || pv)) {
-    strow(f.nxt, v, R, sub, acc);
+    F::store(f.nxt, v, G, sub, acc);
     if (sub == 0) cnt.written++;
   }
   if (changed) {  // uniform over the row's lanes
     const int gs = a.gs;
     const uint64_t smask = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
-    const double E = slot_estimate(acc, a.lc, a.K, gs);
+    const double E = slot_estimate<F>(acc, a.lc, a.K, gs);
     const int j = sub / gs;  // counter of this lane
     if (sub % gs == 0 && ((rowbits >> (j * gs)) & smask)) a.est[((size_t)v << f.sl) + j] = E;
     if (sub == 0) {
@@ -189,10 +347,10 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
 // G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
 // in (all of them, or those modified by the previous pass), compact the kept ids into the
 // slot's queue in LDS and gather the queued counters U at a time.
-template <int G, int U>
+template <class F, int G, int U>
 __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
                                             int32_t *queue, Counters &cnt, bool count_scan) {
-  constexpr int m = 16 * G;
+  using Lane = typename F::Lane;
   const int sub = lane % G;
   const int first = lane & ~(G - 1);
   const uint64_t smask = ((G == 64) ? ~0ull : ((1ull << G) - 1ull)) << first;
@@ -203,10 +361,10 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     beg = a.row_ptr[v];
     end = a.row_ptr[v + 1];
   }
-  uint4 own = zero4(), acc = zero4();
+  Lane own = F::zero(), acc = F::zero();
   bool own_loaded = false;
   if (f.gather_all && end > beg) {
-    own = ldrow(f.cur, v, m, sub);
+    own = F::load(f.cur, v, G, sub);
     acc = own;
     own_loaded = true;
   }
@@ -234,11 +392,11 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int32_t j = 0; j < total; j += U) {
-      uint4 x[U];
+      Lane x[U];
 #pragma unroll
-      for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? ldrow(f.cur, q[j + i], m, sub) : zero4();
+      for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
 #pragma unroll
-      for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
+      for (int i = 0; i < U; ++i) acc = F::max(acc, x[i]);
     }
     gathered += total;
     if (count_scan && sub == 0) cnt.scanned += min(G * U, end - p);
@@ -246,16 +404,16 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     __builtin_amdgcn_wave_barrier();
   }
   if (sub == 0) cnt.gathered += gathered;
-  finalize_slot<G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
+  finalize_slot<F, G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
 }
 
 // Max across the W slots of a wavefront (all lanes active).
-template <int G>
-__device__ __forceinline__ void combine_slots(uint4 &acc, bool &any) {
+template <class F, int G>
+__device__ __forceinline__ void combine_slots(typename F::Lane &acc, bool &any) {
   int anyi = any ? 1 : 0;
 #pragma unroll
   for (int off = G; off < kWave; off <<= 1) {
-    acc = bytemax4(acc, shfl_xor4(acc, off));
+    acc = F::max(acc, F::shfl_xor(acc, off));
     anyi |= __shfl_xor(anyi, off);
   }
   any = anyi != 0;
@@ -373,18 +531,18 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
 // A chunk of one node's arcs handled by a whole wavefront: every lane examines its own
 // successor id (64 per load), the ids to maximise in are compacted into the wavefront's
 // queue in LDS, and the W slots gather the queued counters.
-template <int G, int U>
+template <class F, int G, int U>
 __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, int32_t c, int lane,
                                            int32_t *q, Counters &cnt) {
+  using Lane = typename F::Lane;
   constexpr int W = kWave / G;
-  constexpr int m = 16 * G;
   const int slot = lane / G, sub = lane % G;
   const uint64_t below = (1ull << lane) - 1ull;
   const Chunk ch = a.chunks[c];
   // systolic pass: a node no modified successor signalled keeps its counter (its arcs are
   // not read; the copy rule below still applies)
   const int32_t a1 = (f.systolic && f.todo[ch.v] == 0) ? ch.a0 : ch.a1;
-  uint4 acc = zero4();
+  Lane acc = F::zero();
   int32_t gathered = 0;
   for (int32_t base = ch.a0; base < a1; base += kWave * U) {
     int32_t w[U];
@@ -409,14 +567,14 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     for (int32_t j = slot; j < total; j += W * U) {
-      uint4 x[U];
+      Lane x[U];
 #pragma unroll
       for (int i = 0; i < U; ++i) {
         const int32_t e = j + i * W;
-        x[i] = e < total ? ldrow(f.cur, q[e], m, sub) : zero4();
+        x[i] = e < total ? F::load(f.cur, q[e], G, sub) : F::zero();
       }
 #pragma unroll
-      for (int i = 0; i < U; ++i) acc = bytemax4(acc, x[i]);
+      for (int i = 0; i < U; ++i) acc = F::max(acc, x[i]);
     }
     gathered += total;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -427,11 +585,11 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     cnt.gathered += gathered;
   }
   bool any = gathered > 0;  // wavefront-uniform
-  if (any) combine_slots<G>(acc, any);
+  if (any) combine_slots<F, G>(acc, any);
   if (ch.part < 0) {
-    finalize_slot<G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, zero4(), cnt);
+    finalize_slot<F, G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, F::zero(), cnt);
   } else if (slot == 0) {
-    if (any) strow(a.partial, ch.part, m, sub, acc);  // rows of empty chunks are never read
+    if (any) F::store(a.partial, ch.part, G, sub, acc);  // rows of empty chunks are never read
     if (sub == 0) a.partial_any[ch.part] = any ? 1 : 0;
   }
 }
@@ -477,7 +635,7 @@ __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *s
 
 // One light tile handled by one wavefront: every node when the pass maximises with all
 // successors, else the active nodes found by find_active, W nodes per round.
-template <int G, int U>
+template <class F, int G, int U>
 __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int lane, int32_t *qw,
                                              int32_t *act, int32_t *rps, Counters &cnt) {
   constexpr int W = kWave / G;
@@ -494,14 +652,14 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   for (int32_t r = 0; r < count; r += W) {
     const int32_t v = r + slot < count ? list[r + slot] : -1;
     if (!__any(v >= 0)) break;  // empty tile entries sort last
-    light_round<G, U>(a, f, v, lane, qw, cnt, count_scan);
+    light_round<F, G, U>(a, f, v, lane, qw, cnt, count_scan);
   }
 }
 
 // The union step of one pass (Algorithm 2), one work unit per wavefront: workgroups below
 // n_chunk_wgs take 4 chunks each, the others 4 light tiles (XCD-aware order). With
 // `list_too` set, k_union_list runs the systolic passes and this kernel leaves at once.
-template <int G, int U>
+template <class F, int G, int U>
 __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t list_too) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -515,12 +673,12 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
   int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
     const int32_t c = (int32_t)blockIdx.x * 4 + wave;
-    if (c < a.n_chunks) chunk_wave<G, U>(a, f, c, lane, qw, cnt);
+    if (c < a.n_chunks) chunk_wave<F, G, U>(a, f, c, lane, qw, cnt);
   } else {
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
     if (tile < a.n_tiles)
-      process_tile<G, U>(a, f, tile, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1), cnt);
+      process_tile<F, G, U>(a, f, tile, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1), cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
@@ -530,7 +688,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
 // per wavefront at a time. With `full_too` set, k_union runs the other passes and this
 // kernel leaves at once. Its grid is far smaller than one wavefront per unit, so a pass in
 // which few nodes are active costs few launches.
-template <int G, int U>
+template <class F, int G, int U>
 __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_t full_too) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -547,51 +705,51 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
   for (int64_t i = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave; i < total; i += stride) {
     const int32_t u = f.systolic ? a.unit_list[i] : (int32_t)i;
     if (u < a.n_chunks)
-      chunk_wave<G, U>(a, f, u, lane, qw, cnt);
+      chunk_wave<F, G, U>(a, f, u, lane, qw, cnt);
     else
-      process_tile<G, U>(a, f, u - a.n_chunks, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1),
+      process_tile<F, G, U>(a, f, u - a.n_chunks, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1),
                          cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
 
 // Combines the partial maxima of nodes split over several chunks (one wavefront per node).
-template <int G>
+template <class F, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
+  using Lane = typename F::Lane;
   const DevState *st = a.st;
   if (st->halted) return;
   const Flags f = make_flags(a, st);
   Counters cnt;
   constexpr int W = kWave / G;
-  constexpr int m = 16 * G;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot = lane / G, sub = lane % G;
   const int32_t h = (int32_t)blockIdx.x * 4 + wave;
   if (h < a.n_heavy) {
     const Heavy hv = a.heavy[h];
-    uint4 acc = zero4();
+    Lane acc = F::zero();
     bool any = false;
     // systolic pass: the chunks of an unsignalled node gathered nothing (they may have been
     // skipped without clearing their flags)
     const int32_t count = (f.systolic && f.todo[hv.v] == 0) ? 0 : hv.count;
     for (int32_t j0 = slot; j0 < count; j0 += 4 * W) {  // 4 partial rows in flight per slot
       bool ok[4];
-      uint4 x[4];
+      Lane x[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int32_t j = j0 + k * W;
         ok[k] = j < count && a.partial_any[hv.first + j];
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = ok[k] ? ldrow(a.partial, hv.first + j0 + k * W, m, sub) : zero4();
+      for (int k = 0; k < 4; ++k) x[k] = ok[k] ? F::load(a.partial, hv.first + j0 + k * W, G, sub) : F::zero();
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        acc = bytemax4(acc, x[k]);
+        acc = F::max(acc, x[k]);
         any = any || ok[k];
       }
     }
-    combine_slots<G>(acc, any);
-    finalize_slot<G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, zero4(), cnt);
+    combine_slots<F, G>(acc, any);
+    finalize_slot<F, G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, F::zero(), cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
@@ -1215,11 +1373,10 @@ __device__ __forceinline__ void clear_run_flags(const PassArgs &a, int64_t gid) 
 }
 
 // Algorithm 2's initialisation (add v to c[v]) into both register buffers, the estimates,
-// and cleared flags. G lanes per node row, 16 registers each; counter j of the row is lanes
-// j*gs .. j*gs+gs-1 and is hashed with its own seed.
-template <int G>
+// and cleared flags. G lanes per node row, F::kRegs registers each; counter j of the row is
+// lanes j*gs .. j*gs+gs-1 and is hashed with its own seed.
+template <class F, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed) {
-  constexpr int R = 16 * G;
   const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
   clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
@@ -1245,22 +1402,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
   const uint64_t rest = h << b;
   int r = rest ? __clzll((long long)rest) + 1 : 64 - b + 1;
   r = r > 31 ? 31 : r;
-  uint32_t w[4] = {0u, 0u, 0u, 0u};
-  if (real && (int)(idx >> 4) == sub % gs) {
-    const uint32_t byte = idx & 15u;
-    w[byte >> 2] = (uint32_t)r << (8 * (byte & 3u));
-  }
-  const uint4 c = make_uint4(w[0], w[1], w[2], w[3]);
-  strow(a.regs0, v, R, sub, c);
-  strow(a.regs1, v, R, sub, c);
-  const double E = slot_estimate(c, a.lc, a.K, gs);
+  // the lane holding register idx sets it; every other register is 0
+  const bool mine = real && (int)(idx / F::kRegs) == sub % gs;
+  const typename F::Lane c = F::single(idx % F::kRegs, mine ? (uint32_t)r : 0u);
+  F::store(a.regs0, v, G, sub, c);
+  F::store(a.regs1, v, G, sub, c);
+  const double E = slot_estimate<F>(c, a.lc, a.K, gs);
   if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + j] = E;
 }
 
 // Estimates of every counter of `regs` (resume from a checkpoint) and cleared flags.
-template <int G>
+template <class F, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, const uint8_t *regs) {
-  constexpr int R = 16 * G;
   const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
   clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
@@ -1268,7 +1421,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, cons
   if (v64 >= a.n) return;
   const int32_t v = (int32_t)v64;
   const int gs = a.gs;
-  const double E = slot_estimate(ldrow(regs, v, R, sub), a.lc, a.K, gs);
+  const double E = slot_estimate<F>(F::load(regs, v, G, sub), a.lc, a.K, gs);
   if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + sub / gs] = E;
 }
 
@@ -1692,6 +1845,64 @@ __global__ void k_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *
     out[i] = bytemax(x[i], y[i]);
 }
 
+// The packed max on its own: groups of 64 5-bit registers (five 64-bit words each).
+__global__ void k_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups) {
+  using F = Packed5Regs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride)
+    F::store(out, g, 1, 0, F::max(F::load(x, g, 1, 0), F::load(y, g, 1, 0)));
+}
+
+// Packed counters (5 bits per register) to one register per byte and back, 64 registers
+// per thread: group g is bytes 40g .. 40g+39 packed and 64g .. 64g+63 unpacked.
+__global__ void k_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups) {
+  using F = Packed5Regs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const F::Lane x = F::load(packed, g, 1, 0);
+    uint32_t w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = 0u;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      const int p = 5 * j, k = p >> 6, o = p & 63;
+      uint64_t f = x.w[k] >> o;
+      if (o > 59) f |= x.w[k + 1 < 5 ? k + 1 : 4] << (64 - o);
+      w[j >> 2] |= ((uint32_t)f & 31u) << (8 * (j & 3));
+    }
+    uint4 *q = reinterpret_cast<uint4 *>(out + g * 64);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+  }
+}
+
+// Registers must be <= 31 (checked by the caller).
+__global__ void k_pack5(const uint8_t *in, uint8_t *packed, int64_t groups) {
+  using F = Packed5Regs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(in + g * 64);
+    uint32_t w[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint4 t = q[i];
+      w[4 * i] = t.x;
+      w[4 * i + 1] = t.y;
+      w[4 * i + 2] = t.z;
+      w[4 * i + 3] = t.w;
+    }
+    F::Lane x = F::zero();
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      const int p = 5 * j, k = p >> 6, o = p & 63;
+      const uint64_t r = (w[j >> 2] >> (8 * (j & 3))) & 31u;
+      x.w[k] |= r << o;
+      if (o > 59) x.w[k + 1 < 5 ? k + 1 : 4] |= r >> (64 - o);
+    }
+    F::store(packed, g, 1, 0, x);
+  }
+}
+
 int grid_for(int64_t items, int threads, int64_t cap = 1 << 20) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -1749,20 +1960,35 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
   return hipGetLastError();
 }
 
-#define HANF_DISPATCH_G(G_, EXPR) \
-  switch (G_) {                   \
-    case 1: { constexpr int G = 1; EXPR; } break;   \
-    case 2: { constexpr int G = 2; EXPR; } break;   \
-    case 4: { constexpr int G = 4; EXPR; } break;   \
-    case 8: { constexpr int G = 8; EXPR; } break;   \
-    case 16: { constexpr int G = 16; EXPR; } break; \
-    case 32: { constexpr int G = 32; EXPR; } break; \
-    case 64: { constexpr int G = 64; EXPR; } break; \
-    default: return hipErrorInvalidValue;           \
+// Instantiations: byte registers with 1..64 lanes per node row, 5-bit registers with 1, 2
+// or 4 lanes per counter (m = 64, 128, 256; single runs only).
+#define HANF_DISPATCH_FG(P_, G_, EXPR)                          \
+  if (P_) {                                                     \
+    using F = Packed5Regs;                                      \
+    switch (G_) {                                               \
+      case 1: { constexpr int G = 1; EXPR; } break;             \
+      case 2: { constexpr int G = 2; EXPR; } break;             \
+      case 4: { constexpr int G = 4; EXPR; } break;             \
+      default: return hipErrorInvalidValue;                     \
+    }                                                           \
+  } else {                                                      \
+    using F = ByteRegs;                                         \
+    switch (G_) {                                               \
+      case 1: { constexpr int G = 1; EXPR; } break;             \
+      case 2: { constexpr int G = 2; EXPR; } break;             \
+      case 4: { constexpr int G = 4; EXPR; } break;             \
+      case 8: { constexpr int G = 8; EXPR; } break;             \
+      case 16: { constexpr int G = 16; EXPR; } break;           \
+      case 32: { constexpr int G = 32; EXPR; } break;           \
+      case 64: { constexpr int G = 64; EXPR; } break;           \
+      default: return hipErrorInvalidValue;                     \
+    }                                                           \
   }
 
-// Lanes per node row (S counters of m/16 lanes each).
-int row_lanes(const PassArgs &a) { return (1 << (a.log2m - 4)) << a.seed_log2; }
+// Lanes per node row: S counters of m/16 lanes each (bytes), or m/64 lanes (5-bit).
+int row_lanes(const PassArgs &a) {
+  return a.packed ? 1 << (a.log2m - 6) : (1 << (a.log2m - 4)) << a.seed_log2;
+}
 
 // Threads of the kernels that start a run: one per row lane, and enough to clear the flag
 // words, signal bytes and tile flags.
@@ -1777,14 +2003,14 @@ int64_t init_lanes(const PassArgs &a) {
 hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s) {
   const int G = row_lanes(a);
   const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
-  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_init<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, seed));
+  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_init<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, seed));
   return hipGetLastError();
 }
 
 hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s) {
   const int G = row_lanes(a);
   const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
-  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_estimate_all<G>, dim3(grid), dim3(kBlockThreads), 0, s, a, regs));
+  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_estimate_all<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, regs));
   return hipGetLastError();
 }
 
@@ -1862,13 +2088,13 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
     const int32_t list_too = list ? 1 : 0;
     switch (u) {
       case 2:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 2>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 2>), grid, block, 0, s, a, list_too));
         break;
       case 8:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 8>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 8>), grid, block, 0, s, a, list_too));
         break;
       default:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union<G, 4>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 4>), grid, block, 0, s, a, list_too));
         break;
     }
   }
@@ -1878,13 +2104,13 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
     const int32_t full_too = full ? 1 : 0;
     switch (u) {
       case 2:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 2>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 2>), grid, block, 0, s, a, full_too));
         break;
       case 8:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 8>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 8>), grid, block, 0, s, a, full_too));
         break;
       default:
-        HANF_DISPATCH_G(G, hipLaunchKernelGGL((k_union_list<G, 4>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 4>), grid, block, 0, s, a, full_too));
         break;
     }
   }
@@ -1894,7 +2120,7 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
   if (a.n_fin_wgs == 0) return hipSuccess;
   const int G = row_lanes(a);
-  HANF_DISPATCH_G(G, hipLaunchKernelGGL(k_finalize<G>, dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
+  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_finalize<F, G>), dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
                                         s, a));
   return hipGetLastError();
 }
@@ -1968,6 +2194,23 @@ hipError_t launch_check_registers(const uint8_t *regs, int64_t bytes, DevState *
 hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_bytemax_words, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, x, y, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups, hipStream_t s) {
+  hipLaunchKernelGGL(k_max5_groups, dim3(grid_for(groups, 256, 8192)), dim3(256), 0, s, x, y, out, groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups, hipStream_t s) {
+  if (groups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack5, dim3(grid_for(groups, 256, 8192)), dim3(256), 0, s, packed, out, groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack5(const uint8_t *in, uint8_t *packed, int64_t groups, hipStream_t s) {
+  if (groups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack5, dim3(grid_for(groups, 256, 8192)), dim3(256), 0, s, in, packed, groups);
   return hipGetLastError();
 }
 

@@ -1,0 +1,225 @@
+"""5-bit packed registers (HANF_OPT_PACKED5, Section 3.3) against the CPU oracle.
+
+The packed layout is the one the header states: register j of a counter at bits 5j..5j+4
+of its little-endian bit string, 40 bytes per 64 registers. The helpers below write that
+layout with numpy bit operations, independently of the library. Runs with packed registers
+must give byte-identical registers (read back unpacked), the oracle's N_hat(t) and T, and
+N_hat bit-identical to the same run with one register per byte.
+"""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from test_gpu_parity import RTOL, _flush, step_parity, transpose_csr
+
+pytestmark = pytest.mark.gpu
+
+hanf = pytest.importorskip("paper_1011_5599_amd")
+
+
+def pack5(regs):
+    """(groups, 64) register values < 32 -> (groups, 40) bytes."""
+    r = np.asarray(regs, np.uint8).reshape(-1, 64)
+    bits = (r[:, :, None] >> np.arange(5, dtype=np.uint8)) & 1
+    return np.packbits(bits.reshape(len(r), 320), axis=1, bitorder="little")
+
+
+def unpack5(packed):
+    """(groups, 40) bytes -> (groups, 64) register values."""
+    p = np.asarray(packed, np.uint8).reshape(-1, 40)
+    bits = np.unpackbits(p, axis=1, bitorder="little").reshape(len(p), 64, 5)
+    return (bits << np.arange(5, dtype=np.uint8)).sum(axis=2).astype(np.uint8)
+
+
+def test_pack_helpers_roundtrip():
+    rng = np.random.default_rng(1)
+    r = rng.integers(0, 32, (1000, 64)).astype(np.uint8)
+    assert np.array_equal(unpack5(pack5(r)), r)
+    one = np.zeros((1, 64), np.uint8)
+    one[0, 12] = 31  # bits 60..64: the top four bits of word 0 and bit 0 of word 1
+    w = pack5(one).view(np.uint64)[0]
+    assert w[0] == 0xF000000000000000 and w[1] == 1 and not w[2:].any()
+
+
+def _max5(x, y):
+    import torch
+    tx = torch.from_numpy(pack5(x).ravel()).cuda()
+    ty = torch.from_numpy(pack5(y).ravel()).cuda()
+    to = torch.empty_like(tx)
+    hanf.hanf_max5_groups(0, tx, ty, to)
+    return unpack5(to.cpu().numpy())
+
+
+def test_max5_every_pair_at_every_field():
+    """Every pair of 5-bit values in every one of the 64 fields (the four that straddle a
+    64-bit word among them), the other fields random: 65,536 groups in one call."""
+    rng = np.random.default_rng(2)
+    a, b = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    a, b = a.ravel(), b.ravel()
+    x = rng.integers(0, 32, (64 * 1024, 64)).astype(np.uint8)
+    y = rng.integers(0, 32, (64 * 1024, 64)).astype(np.uint8)
+    for j in range(64):
+        x[j * 1024:(j + 1) * 1024, j] = a
+        y[j * 1024:(j + 1) * 1024, j] = b
+    assert np.array_equal(_max5(x, y), np.maximum(x, y))
+
+
+def test_max5_structured_groups():
+    """Equal groups, all-0 against all-31, ties everywhere but one field, and alternating
+    orders: cases where a wrong borrow or shift between words would show."""
+    rng = np.random.default_rng(3)
+    g = []
+    r = rng.integers(0, 32, 64)
+    g += [(r, r), (np.zeros(64), np.full(64, 31)), (np.full(64, 31), np.zeros(64))]
+    for j in range(64):
+        x = np.full(64, 16)
+        y = x.copy()
+        y[j] = 17
+        g += [(x, y), (y, x)]
+        x = np.zeros(64)
+        y = np.zeros(64)
+        x[j], y[j] = 1, 0
+        g += [(x, y), (y, x)]
+    alt = np.arange(64) % 2
+    g += [(alt * 31, (1 - alt) * 31), (alt * 15, (1 - alt) * 16)]
+    x = np.array([p for p, _ in g], np.uint8)
+    y = np.array([q for _, q in g], np.uint8)
+    assert np.array_equal(_max5(x, y), np.maximum(x, y))
+
+
+@pytest.mark.parametrize("b", [6, 7, 8])
+def test_packed_parity_every_iteration(b):
+    """Every m the packed format allows, with rows split over several chunks."""
+    rp, ci = graphgen.rmat(12, 60_000, seed=40 + b)
+    step_parity(rp, ci, b, 1000 + b, chunk_arcs=150, packed5=1)
+    step_parity(rp, ci, b, 2000 + b, packed5=1)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(frontier=0), dict(light_max=4, chunk_arcs=16),
+                                  dict(unroll=8, tile_nodes=256), dict(unroll=2, dense_switch=0)])
+def test_packed_schedules(opts):
+    rp, ci = graphgen.rmat(12, 40_000, seed=6)
+    step_parity(rp, ci, 6, 17, packed5=1, **opts)
+
+
+@pytest.mark.parametrize("opts", [dict(systolic=1), dict(systolic=2, chunk_arcs=150, light_max=8),
+                                  dict(systolic=1, union_policy=2)])
+def test_packed_systolic(opts):
+    rp, ci = graphgen.rmat(13, 100_000, seed=14)
+    step_parity(rp, ci, 7, 3, transpose="build", packed5=1, **opts)
+    rs, cs = graphgen.rmat(12, 40_000, symmetric=True, seed=31)
+    step_parity(rs, cs, 6, 4, transpose="declared", packed5=1, **opts)
+
+
+@pytest.mark.parametrize("name", ["single", "star_out", "star_in", "cycle", "complete", "loops_dups"])
+def test_packed_edge_graphs(name):
+    if name == "single":
+        g = graphgen.empty(1)
+    elif name == "star_out":
+        g = graphgen.star_out(100_001)
+    elif name == "star_in":
+        g = graphgen.star_in(30_000)
+    elif name == "cycle":
+        g = graphgen.directed_cycle(300)
+    elif name == "complete":
+        g = graphgen.complete(120)
+    else:
+        rp, ci = graphgen.erdos_renyi(3000, 20_000, seed=8)
+        n = len(rp) - 1
+        arcs = [(u, int(w)) for u in range(n) for w in ci[rp[u]:rp[u + 1]]]
+        arcs += arcs[::7] + [(u, u) for u in range(0, n, 5)]
+        g = graphgen.from_arcs(n, arcs)
+    step_parity(*g, 6, 99, packed5=1)
+    step_parity(*g, 8, 98, transpose="build", systolic=1, packed5=1)
+
+
+@pytest.mark.parametrize("b", [6, 8])
+def test_packed_equals_bytes(b):
+    """The same run in both formats: N_hat bit for bit, the same T and pass log counts."""
+    rp, ci = graphgen.rmat(14, 262_144, seed=14)
+    with hanf.HyperANF(0) as p, hanf.HyperANF(0, packed5=1) as q:
+        p.load(rp, ci).build_transpose().init(b, 5)
+        q.load(rp, ci).build_transpose().init(b, 5)
+        np_, nq = p.run(), q.run()
+        assert np.array_equal(np_, nq)
+        assert np.array_equal(p.registers(), q.registers())
+        assert np.array_equal(p.estimates(), q.estimates())
+        lp, lq = p.pass_log(), q.pass_log()
+        assert [(r["changed"], r["arcs_gathered"], r["systolic"]) for r in lp] == \
+               [(r["changed"], r["arcs_gathered"], r["systolic"]) for r in lq]
+
+
+def test_packed_checkpoint_resume():
+    """Registers written (packed on the device) from host and device buffers, read back
+    unchanged; the continuation equals the uninterrupted run."""
+    import torch
+    rp, ci = graphgen.rmat(12, 50_000, seed=12)
+    with hanf.HyperANF(0, packed5=1) as h:
+        h.load(rp, ci).init(7, 77)
+        full = h.run()
+        final = h.registers()
+    with hanf.HyperANF(0, packed5=1) as h:
+        h.load(rp, ci).init(7, 77)
+        h.step(3)
+        regs = h.registers()
+        prefix = h.nt()
+    for device in (False, True):
+        with hanf.HyperANF(0, packed5=1) as h2:
+            h2.load(rp, ci).init(7, 1)
+            src = torch.from_numpy(regs.ravel()).cuda() if device else regs
+            hanf.hanf_write_registers(h2.ctx, src, 3, prefix)
+            assert np.array_equal(h2.registers(), regs)
+            out = torch.empty(regs.size, dtype=torch.uint8, device="cuda")
+            h2.registers(out)
+            assert np.array_equal(out.cpu().numpy().reshape(regs.shape), regs)
+            nt = h2.run()
+            assert np.array_equal(h2.registers(), final)
+            np.testing.assert_allclose(nt, full, rtol=RTOL, atol=0)
+    bad = regs.copy()
+    bad[5, 3] = 32
+    with hanf.HyperANF(0, packed5=1) as h3:
+        h3.load(rp, ci).init(7, 1)
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_write_registers(h3.ctx, bad, 3, prefix)
+        assert e.value.code == hanf.HANF_EINVAL
+
+
+def test_packed_errors_and_footprint():
+    rp, ci = graphgen.rmat(8, 1000, seed=1)
+    with hanf.HyperANF(0, packed5=1) as h:
+        h.load(rp, ci)
+        with pytest.raises(hanf.HanfError) as e:
+            h.init(5, 1)  # 32 registers do not fill a 64-bit word group
+        assert e.value.code == hanf.HANF_EINVAL
+        h.init(6, 1)
+        want, _, _ = oracle.run(rp, ci, 6, 1)
+        np.testing.assert_allclose(h.run(), want, rtol=RTOL, atol=0)
+    with hanf.Batch(0) as bt:
+        hanf.hanf_set_option(bt.ctx, hanf.HANF_OPT_PACKED5, 1)
+        bt.load_graphs([(rp, ci)], 2)
+        with pytest.raises(hanf.HanfError) as e:
+            bt.init(6, [1, 2])
+        assert e.value.code == hanf.HANF_EINVAL
+    n, arcs = 1 << 20, 1 << 24
+    for b in (6, 7, 8):
+        full = hanf.hanf_footprint(n, arcs, b, copy_graph=False)
+        packed = hanf.hanf_footprint(n, arcs, b, copy_graph=False, packed5=True)
+        assert full - packed == 2 * n * ((1 << b) - 5 * (1 << b) // 8)
+    with pytest.raises(hanf.HanfError):
+        hanf.hanf_footprint(n, arcs, 5, packed5=True)
+
+
+def test_packed_host_transpose_and_device_graph():
+    import torch
+    rp, ci = graphgen.rmat(13, 100_000, seed=21)
+    _flush("[packed] host transpose, device graph")
+    trp, tci = transpose_csr(rp, ci)
+    with hanf.HyperANF(0, packed5=1) as a, hanf.HyperANF(0, packed5=1) as d:
+        a.load(rp, ci).load_transpose(trp, tci).init(8, 5)
+        d.load(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()).init(8, 5)
+        na, nd = a.run(), d.run()
+        assert np.array_equal(na, nd)
+        assert np.array_equal(a.registers(), d.registers())
+    want, _, _ = oracle.run(rp, ci, 8, 5)
+    np.testing.assert_allclose(na, want, rtol=RTOL, atol=0)
