@@ -31,8 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
 def algorithmic_bytes(rec, n, m):
-    """Bytes a union pass must move: col_idx of every arc scanned (4 B), m bytes per
-    successor counter maximised in, per own counter read and per new counter written; plus,
+    """Bytes a union pass must move: col_idx of every arc scanned (4 B), m bytes (the bytes
+    of one counter: m registers, or 5m/8 when packed) per successor counter maximised in, per
+    own counter read and per new counter written; plus,
     in a pass over every node, row_ptr (4 B/node) and one flag bit per node read and
     written, or, in a systolic pass (only signalled nodes visited), two row_ptr entries per
     node whose counter was read."""
@@ -44,7 +45,8 @@ def algorithmic_bytes(rec, n, m):
 
 def measured_traffic(workload):
     """HBM bytes per union launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded
-    under profiles/, or None when the kernel source changed since they were taken."""
+    under profiles/ (`workload` with a `_packed5` suffix for 5-bit registers), or None when
+    the kernel source changed since they were taken."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", f"k_union_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_1011_5599_amd", "csrc", "hanf_kernels.hip")
@@ -443,6 +445,8 @@ def main():
         k, v = kv.split("=")
         opts[k] = int(v)
     h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
+    packed = bool(opts.get("packed5"))
+    rowb = (5 * m) // 8 if packed else m  # bytes of one counter
     tmode = args.transpose
     if tmode == "auto":
         tmode = "self" if spec.get("symmetric") else "none"
@@ -483,17 +487,18 @@ def main():
     if not args.no_timing:
         all_recs = [r for lg in logs for r in lg]
         union_ms = sum(r["union_ms"] for r in all_recs)
-        byts = sum(algorithmic_bytes(r, n, m) for r in all_recs)
+        byts = sum(algorithmic_bytes(r, n, rowb) for r in all_recs)
         launches = len(all_recs)
         achieved = byts / (union_ms / 1000.0) / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=measured_traffic(args.workload),
+                        frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=measured_traffic(args.workload + ("_packed5" if packed else "")),
                         kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
                         avg_launch_us=round(1000.0 * union_ms / launches, 2),
                         avg_algorithmic_bytes=int(byts / launches))
         p0 = [lg[0] for lg in logs]
         ms0 = sum(r["union_ms"] for r in p0) / len(p0)
-        b0 = algorithmic_bytes(p0[0], n, m)
+        b0 = algorithmic_bytes(p0[0], n, rowb)
         full_pass = dict(union_ms=round(ms0, 4), algorithmic_gb=round(b0 / 1e9, 4),
                          gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
                          updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0),
@@ -522,6 +527,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec_name(args.workload), "n": n, "arcs": arcs, "log2m": b,
                    "hash_seed": seed, "T": st["T"], "passes": len(log), "transpose": tmode,
+                   "registers": "5-bit packed" if packed else "one per byte",
                    "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
                                          for r in log)},
         "roofline": roofline,
@@ -531,7 +537,7 @@ def main():
         "dense_equivalent_updates_per_s": m * arcs * (st["T"] + 1) / (ms_per_step / 1000.0),
         "graphs_per_s": 1000.0 / ms_per_step,
         "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
-        "pass_algorithmic_bytes": [algorithmic_bytes(r, n, m) for r in log],
+        "pass_algorithmic_bytes": [algorithmic_bytes(r, n, rowb) for r in log],
         "pass_union_ms": [round(r["union_ms"], 4) for r in log] if not args.no_timing else None,
     }
     h.close()

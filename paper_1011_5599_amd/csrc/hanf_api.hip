@@ -345,9 +345,11 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   const int W = kWave / G;
   s.G = G;
   s.lane_bytes = lane_bytes;
-  // defaults measured on MI355X over light_max 16..128 and chunk_arcs 256..2048: 16 arcs per
-  // row lane (clamped to 32..128) and 16 arcs per slot and unrolled gather in a chunk
-  s.light_max = c->light_max_opt > 0 ? c->light_max_opt : std::max(32, std::min(128, 16 * G));
+  // defaults measured on MI355X over light_max 16..128 and chunk_arcs 256..2048: one arc per
+  // register of the row (clamped to 32..128) and 16 arcs per slot and unrolled gather in a
+  // chunk
+  const int row_regs = G * (lane_bytes == kPacked5LaneBytes ? 64 : 16);
+  s.light_max = c->light_max_opt > 0 ? c->light_max_opt : std::max(32, std::min(128, row_regs));
   s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, std::min(2048, W * c->unroll * 16));
   int32_t tile = c->tile_opt;
   if (tile <= 0) {
@@ -819,6 +821,7 @@ int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   HIP_TRY(c, launch_union(c->args, c->unroll, full, list, s), "union kernel");
   if (ev) HIP_TRY(c, hipEventRecord(ev[2], s), "event");
   HIP_TRY(c, launch_finalize(c->args, s), "finalize kernel");
+  HIP_TRY(c, launch_estimate_changed(c->args, s), "estimate kernel");
   if (ev) HIP_TRY(c, hipEventRecord(ev[3], s), "event");
   HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s), "reduce kernels");
   if (ev) HIP_TRY(c, hipEventRecord(ev[4], s), "event");

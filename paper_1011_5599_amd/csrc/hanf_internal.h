@@ -177,6 +177,7 @@ hipError_t launch_tp_second(const uint64_t *pairs, const uint64_t *bstart, const
                             const int64_t *chunk_hi, const int64_t *chunk_s, int32_t n_hchunks, uint32_t *h2, int32_t bs,
                             int32_t n, int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s);
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
+hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out, hipStream_t s);

@@ -71,6 +71,7 @@ struct ByteRegs {
   using Lane = uint4;
   static constexpr int kRegs = 16;
   static constexpr int kBytes = 16;
+  static constexpr bool kEstimateInUnion = true;  // the union kernel writes changed estimates
   static __device__ __forceinline__ Lane zero() { return zero4(); }
   static __device__ __forceinline__ Lane load(const uint8_t *regs, int64_t row, int G, int sub) {
     return *reinterpret_cast<const uint4 *>(regs + ((size_t)row * G + sub) * kBytes);
@@ -116,121 +117,138 @@ constexpr uint64_t field_bits5(int word, int bit) {
 
 // 5-bit registers packed without gaps (Section 3.3): register j of a counter is bits
 // 5j .. 5j+4 of its little-endian bit string, so a counter of m registers is 5m/8 bytes and
-// fields straddle the 64-bit words. A lane holds 64 registers: 320 bits, five words, which
-// start on a word boundary (the paper's "at least w registers per counter", w = 64).
+// fields straddle the machine words. A lane holds 64 registers: 320 bits, which start on a
+// 64-bit word boundary (the paper's "at least w registers per counter", w = 64). The lane
+// keeps them as ten 32-bit words, the width of the GPU's carry chain.
 struct Packed5Regs {
   struct Lane {
-    uint64_t w[5];
+    uint32_t w[10];
   };
   static constexpr int kRegs = 64;
   static constexpr int kBytes = 40;
-  // the lowest (L) and the highest (H) bit of every 5-bit field, word k of five
-  static __host__ __device__ __forceinline__ constexpr uint64_t L(int k) {
+  // Estimates of changed counters come from k_estimate_changed after the union step: the
+  // 64 field extractions would otherwise raise the union kernel's register count (and
+  // lower its occupancy) for a step that runs once per changed node.
+  static constexpr bool kEstimateInUnion = false;
+  // the lowest (L) and the highest (H) bit of every 5-bit field, 64-bit word k of five
+  static __host__ __device__ __forceinline__ constexpr uint64_t L64(int k) {
     return k == 0 ? 0x1084210842108421ull : k == 1 ? 0x2108421084210842ull : k == 2 ? 0x4210842108421084ull
          : k == 3 ? 0x8421084210842108ull : 0x0842108421084210ull;
   }
-  static __host__ __device__ __forceinline__ constexpr uint64_t H(int k) {
+  static __host__ __device__ __forceinline__ constexpr uint64_t H64(int k) {
     return k == 0 ? 0x0842108421084210ull : k == 1 ? 0x1084210842108421ull : k == 2 ? 0x2108421084210842ull
          : k == 3 ? 0x4210842108421084ull : 0x8421084210842108ull;
+  }
+  // the same, 32-bit word i of ten
+  static __host__ __device__ __forceinline__ constexpr uint32_t L(int i) {
+    return (uint32_t)(L64(i >> 1) >> (32 * (i & 1)));
+  }
+  static __host__ __device__ __forceinline__ constexpr uint32_t H(int i) {
+    return (uint32_t)(H64(i >> 1) >> (32 * (i & 1)));
   }
   static __device__ __forceinline__ Lane zero() {
     Lane z;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) z.w[k] = 0ull;
+    for (int i = 0; i < 10; ++i) z.w[i] = 0u;
     return z;
   }
   static __device__ __forceinline__ Lane load(const uint8_t *regs, int64_t row, int G, int sub) {
-    const uint64_t *p = reinterpret_cast<const uint64_t *>(regs + ((size_t)row * G + sub) * kBytes);
+    const uint2 *p = reinterpret_cast<const uint2 *>(regs + ((size_t)row * G + sub) * kBytes);
     Lane x;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) x.w[k] = p[k];
+    for (int k = 0; k < 5; ++k) {
+      const uint2 t = p[k];
+      x.w[2 * k] = t.x;
+      x.w[2 * k + 1] = t.y;
+    }
     return x;
   }
   static __device__ __forceinline__ void store(uint8_t *regs, int64_t row, int G, int sub, Lane x) {
-    uint64_t *p = reinterpret_cast<uint64_t *>(regs + ((size_t)row * G + sub) * kBytes);
+    uint2 *p = reinterpret_cast<uint2 *>(regs + ((size_t)row * G + sub) * kBytes);
 #pragma unroll
-    for (int k = 0; k < 5; ++k) p[k] = x.w[k];
+    for (int k = 0; k < 5; ++k) p[k] = make_uint2(x.w[2 * k], x.w[2 * k + 1]);
   }
   // Broadword register-wise max of Section 3.3 on k = 5-bit fields. The comparison
   //   lt = (((x | H) - (y & ~H)) | (x ^ y)) ^ (x | ~y)) & H
   // sets the high bit of every field where x < y. Per field the subtraction is
   // 2^4 + x_low - y_low >= 1, so it never borrows out of a field; a field that straddles two
-  // words borrows from its low part into its high part, which is the multi-word borrow. The
-  // selection mask moves each result bit to its field's low bit (a multi-word shift right by
-  // 4), ors in H and subtracts L (1 per field, again only borrowing inside a field): a field
-  // becomes 1 0000 where x < y and 0 1111 elsewhere; or-ing H and xor-ing lt turn those into
-  // all zeros and all ones. The result takes x where the mask is set and y elsewhere.
+  // words borrows from its low part into its high part, which is the multi-word borrow
+  // (one subtract-with-borrow chain over the ten words). The selection mask moves each
+  // result bit to its field's low bit (a multi-word shift right by 4), ors in H and
+  // subtracts L (1 per field, again only borrowing inside a field): a field becomes 1 0000
+  // where x < y and 0 1111 elsewhere; or-ing H and xor-ing lt turn those into all zeros and
+  // all ones. The result takes x where the mask is set and y elsewhere.
   static __device__ __forceinline__ Lane max(Lane x, Lane y) {
-    uint64_t lt[5];
-    uint64_t borrow = 0ull;
+    uint32_t lt[10];
+    unsigned int borrow = 0u;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const uint64_t a = x.w[k] | H(k), b = y.w[k] & ~H(k);
-      const uint64_t d0 = a - b, d = d0 - borrow;
-      borrow = (uint64_t)(a < b) | (uint64_t)(d0 < borrow);
-      lt[k] = ((d | (x.w[k] ^ y.w[k])) ^ (x.w[k] | ~y.w[k])) & H(k);
+    for (int i = 0; i < 10; ++i) {
+      unsigned int bo;
+      const uint32_t d = __builtin_subc(x.w[i] | H(i), y.w[i] & ~H(i), borrow, &bo);
+      borrow = bo;
+      lt[i] = ((d | (x.w[i] ^ y.w[i])) ^ (x.w[i] | ~y.w[i])) & H(i);
     }
     Lane out;
-    borrow = 0ull;
+    borrow = 0u;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const uint64_t sh = (lt[k] >> 4) | (k < 4 ? lt[k + 1 < 5 ? k + 1 : 4] << 60 : 0ull);
-      const uint64_t a = sh | H(k);
-      const uint64_t d0 = a - L(k), d = d0 - borrow;
-      borrow = (uint64_t)(a < L(k)) | (uint64_t)(d0 < borrow);
-      const uint64_t mask = (d | H(k)) ^ lt[k];
-      out.w[k] = (x.w[k] & mask) | (y.w[k] & ~mask);
+    for (int i = 0; i < 10; ++i) {
+      const uint32_t sh = (lt[i] >> 4) | (i < 9 ? lt[i + 1 < 10 ? i + 1 : 9] << 28 : 0u);
+      unsigned int bo;
+      const uint32_t d = __builtin_subc(sh | H(i), L(i), borrow, &bo);
+      borrow = bo;
+      const uint32_t mask = (d | H(i)) ^ lt[i];
+      out.w[i] = (x.w[i] & mask) | (y.w[i] & ~mask);
     }
     return out;
   }
   static __device__ __forceinline__ bool differ(Lane a, Lane b) {
-    uint64_t d = 0ull;
+    uint32_t d = 0u;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) d |= a.w[k] ^ b.w[k];
-    return d != 0ull;
+    for (int i = 0; i < 10; ++i) d |= a.w[i] ^ b.w[i];
+    return d != 0u;
   }
   static __device__ __forceinline__ Lane shfl_xor(Lane a, int off) {
     Lane r;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const uint32_t lo = __shfl_xor((uint32_t)a.w[k], off);
-      const uint32_t hi = __shfl_xor((uint32_t)(a.w[k] >> 32), off);
-      r.w[k] = ((uint64_t)hi << 32) | lo;
-    }
+    for (int i = 0; i < 10; ++i) r.w[i] = __shfl_xor(a.w[i], off);
     return r;
+  }
+  // register j (0..63) of the lane
+  static __device__ __forceinline__ uint32_t field(const Lane &a, int j) {
+    const int p = 5 * j, i = p >> 5, o = p & 31;
+    uint32_t f = a.w[i] >> o;
+    if (o > 27) f |= a.w[i + 1 < 10 ? i + 1 : 9] << (32 - o);
+    return f & 31u;
   }
   static __device__ __forceinline__ void size_terms(Lane a, uint64_t &S, uint32_t &V) {
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
-      const int p = 5 * j, k = p >> 6, o = p & 63;
-      uint64_t f = a.w[k] >> o;
-      if (o > 59) f |= a.w[k + 1 < 5 ? k + 1 : 4] << (64 - o);
-      const uint32_t r = (uint32_t)f & 31u;
+      const uint32_t r = field(a, j);
       S += (uint64_t)(1u << (31u - r));
       V += (r == 0u);
     }
   }
   static __device__ __forceinline__ Lane single(uint32_t j, uint32_t r) {
-    const uint32_t p = 5u * j, k = p >> 6, o = p & 63u;
+    const uint32_t p = 5u * j, k = p >> 5, o = p & 31u;
     Lane x;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      uint64_t w = 0ull;
-      if ((uint32_t)i == k) w = (uint64_t)r << o;
-      if ((uint32_t)i == k + 1u && o > 59u) w = (uint64_t)r >> (64u - o);
+    for (int i = 0; i < 10; ++i) {
+      uint32_t w = 0u;
+      if ((uint32_t)i == k) w = r << o;
+      if ((uint32_t)i == k + 1u && o > 27u) w = r >> (32u - o);
       x.w[i] = w;
     }
     return x;
   }
 };
 static_assert(Packed5Regs::kBytes == kPacked5LaneBytes, "packed lane size");
-static_assert(Packed5Regs::L(0) == field_bits5(0, 0) && Packed5Regs::L(1) == field_bits5(1, 0) &&
-                  Packed5Regs::L(2) == field_bits5(2, 0) && Packed5Regs::L(3) == field_bits5(3, 0) &&
-                  Packed5Regs::L(4) == field_bits5(4, 0),
+static_assert(Packed5Regs::L64(0) == field_bits5(0, 0) && Packed5Regs::L64(1) == field_bits5(1, 0) &&
+                  Packed5Regs::L64(2) == field_bits5(2, 0) && Packed5Regs::L64(3) == field_bits5(3, 0) &&
+                  Packed5Regs::L64(4) == field_bits5(4, 0),
               "low field bits");
-static_assert(Packed5Regs::H(0) == field_bits5(0, 4) && Packed5Regs::H(1) == field_bits5(1, 4) &&
-                  Packed5Regs::H(2) == field_bits5(2, 4) && Packed5Regs::H(3) == field_bits5(3, 4) &&
-                  Packed5Regs::H(4) == field_bits5(4, 4),
+static_assert(Packed5Regs::H64(0) == field_bits5(0, 4) && Packed5Regs::H64(1) == field_bits5(1, 4) &&
+                  Packed5Regs::H64(2) == field_bits5(2, 4) && Packed5Regs::H64(3) == field_bits5(3, 4) &&
+                  Packed5Regs::H64(4) == field_bits5(4, 4),
               "high field bits");
 
 // ------------------------------------------------------------------ hash (Algorithm 1 add)
@@ -330,9 +348,11 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
   if (changed) {  // uniform over the row's lanes
     const int gs = a.gs;
     const uint64_t smask = (gs == 64) ? ~0ull : ((1ull << gs) - 1ull);
-    const double E = slot_estimate<F>(acc, a.lc, a.K, gs);
-    const int j = sub / gs;  // counter of this lane
-    if (sub % gs == 0 && ((rowbits >> (j * gs)) & smask)) a.est[((size_t)v << f.sl) + j] = E;
+    if constexpr (F::kEstimateInUnion) {
+      const double E = slot_estimate<F>(acc, a.lc, a.K, gs);
+      const int j = sub / gs;  // counter of this lane
+      if (sub % gs == 0 && ((rowbits >> (j * gs)) & smask)) a.est[((size_t)v << f.sl) + j] = E;
+    }
     if (sub == 0) {
       uint32_t mask = 0u;
       for (int k = 0; k < (G / gs); ++k)
@@ -752,6 +772,22 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     finalize_slot<F, G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, F::zero(), cnt);
   }
   add_block_counters(cnt, a.stat_slots);
+}
+
+// Estimates of the counters this pass changed, for formats whose union step leaves them out
+// (one counter per node row; G lanes per node, all lanes of a node take the same branch).
+template <class F, int G>
+__global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st);
+  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+  const int64_t v64 = gid / G;
+  if (v64 >= a.n) return;  // whole nodes leave together (G | 64)
+  const int32_t v = (int32_t)v64;
+  if (!node_mod(f.cur_bits, v, 0)) return;
+  const double E = slot_estimate<F>(F::load(f.nxt, v, G, (int)(gid % G)), a.lc, a.K, G);
+  if (gid % G == 0) a.est[v] = E;
 }
 
 // Per 64-node block, one lane each: re-sum the estimates where a counter changed (else
@@ -1864,12 +1900,7 @@ __global__ void k_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) w[i] = 0u;
 #pragma unroll
-    for (int j = 0; j < 64; ++j) {
-      const int p = 5 * j, k = p >> 6, o = p & 63;
-      uint64_t f = x.w[k] >> o;
-      if (o > 59) f |= x.w[k + 1 < 5 ? k + 1 : 4] << (64 - o);
-      w[j >> 2] |= ((uint32_t)f & 31u) << (8 * (j & 3));
-    }
+    for (int j = 0; j < 64; ++j) w[j >> 2] |= F::field(x, j) << (8 * (j & 3));
     uint4 *q = reinterpret_cast<uint4 *>(out + g * 64);
 #pragma unroll
     for (int i = 0; i < 4; ++i) q[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
@@ -1894,10 +1925,10 @@ __global__ void k_pack5(const uint8_t *in, uint8_t *packed, int64_t groups) {
     F::Lane x = F::zero();
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
-      const int p = 5 * j, k = p >> 6, o = p & 63;
-      const uint64_t r = (w[j >> 2] >> (8 * (j & 3))) & 31u;
-      x.w[k] |= r << o;
-      if (o > 59) x.w[k + 1 < 5 ? k + 1 : 4] |= r >> (64 - o);
+      const int p = 5 * j, i = p >> 5, o = p & 31;
+      const uint32_t r = (w[j >> 2] >> (8 * (j & 3))) & 31u;
+      x.w[i] |= r << o;
+      if (o > 27) x.w[i + 1 < 10 ? i + 1 : 9] |= r >> (32 - o);
     }
     F::store(packed, g, 1, 0, x);
   }
@@ -2122,6 +2153,14 @@ hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
   const int G = row_lanes(a);
   HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_finalize<F, G>), dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
                                         s, a));
+  return hipGetLastError();
+}
+
+hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s) {
+  if (!a.packed) return hipSuccess;  // byte rows: the union step wrote them
+  const int G = row_lanes(a);
+  const int grid = grid_for((int64_t)a.n * G, kBlockThreads, 1 << 30);
+  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_estimate_changed<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a));
   return hipGetLastError();
 }
 

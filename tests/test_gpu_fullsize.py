@@ -1,7 +1,8 @@
 """GPU parity at the full workload sizes, in the benchmark's launch configuration.
 
 * symmetric R-MAT scale 22 (2^26 arcs), 64 registers, hash seed 7: registers byte-equal to
-  the oracle's at every iteration, N_hat(t) within 1e-12, same T;
+  the oracle's at every iteration, N_hat(t) within 1e-12, same T (also with 5-bit packed
+  registers);
 * web-like graph of 2^24 nodes (3.4e8 arcs), 128 registers, hash seed 1: N_hat(0) against
   its closed form, the final counters and T against a full (multi-threaded) oracle run
   (with and without systolic passes, the transposed graph built on the device),
@@ -33,16 +34,17 @@ def _say(msg):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("systolic", [False, True])
-def test_rmat22sym_every_iteration(systolic):
+@pytest.mark.parametrize("systolic,packed", [(False, False), (True, False), (True, True)])
+def test_rmat22sym_every_iteration(systolic, packed):
     """With systolic=True in the benchmark's configuration: the symmetric graph's own
-    device arrays serve as its transpose."""
+    device arrays serve as its transpose. packed: 5-bit registers (read back unpacked)."""
     import torch
     spec = graphgen.WORKLOADS["rmat22sym"]
     rp, ci = graphgen.workload_graph(spec)
     b, seed = spec["log2m"], spec["seed"]
-    _say(f"[fullsize] rmat22sym n={len(rp) - 1} arcs={len(ci)} b={b} seed={seed} systolic={systolic}")
-    with hanf.HyperANF(0) as h:
+    _say(f"[fullsize] rmat22sym n={len(rp) - 1} arcs={len(ci)} b={b} seed={seed} systolic={systolic} "
+         f"packed={packed}")
+    with hanf.HyperANF(0, packed5=int(packed)) as h:
         if systolic:
             drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
             h.load(drp, dci).load_transpose(drp, dci)
