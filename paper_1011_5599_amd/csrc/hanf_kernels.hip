@@ -1463,20 +1463,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, cons
 
 // ------------------------------------------------------------------ kernels: graph ingest
 
+// CSR checks: row_ptr starts at 0, never decreases and ends at `arcs`; every successor id
+// is in [0, n). Successor ids are read 16 bytes per lane when col_idx is 16-byte aligned.
 __global__ void k_validate(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs,
                            DevState *st) {
   int32_t err = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t top = arcs > (int64_t)n + 1 ? arcs : (int64_t)n + 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += stride) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = tid; i <= n; i += stride) {
     if (i == 0 && rp[0] != 0) err |= 1;
     if (i < n && rp[i] > rp[i + 1]) err |= 2;
     if (i == n && (int64_t)rp[n] != arcs) err |= 4;
-    if (i < arcs) {
-      const int32_t w = ci[i];
-      if (w < 0 || w >= n) err |= 8;
-    }
   }
+  const uint32_t un = (uint32_t)n;  // w < 0 becomes >= 2^31 > n
+  const int64_t quads = (reinterpret_cast<uintptr_t>(ci) & 15u) == 0 ? arcs / 4 : 0;
+  const int4 *ci4 = reinterpret_cast<const int4 *>(ci);
+  for (int64_t q = tid; q < quads; q += stride) {
+    const int4 w = ci4[q];
+    if ((uint32_t)w.x >= un || (uint32_t)w.y >= un || (uint32_t)w.z >= un || (uint32_t)w.w >= un) err |= 8;
+  }
+  for (int64_t i = 4 * quads + tid; i < arcs; i += stride)
+    if ((uint32_t)ci[i] >= un) err |= 8;
   if (err) atomicOr(&st->err, err);
 }
 
@@ -1552,11 +1559,13 @@ __global__ void k_fill_chunks(const int32_t *rp, int32_t n, const uint64_t *offs
 }
 
 // One workgroup per tile of consecutive ids: light nodes sorted by decreasing degree (ties
-// by id), the rest of the tile filled with -1.
+// by id), the rest of the tile filled with -1. The workgroup is as wide as the bitonic sort:
+// the power of two >= tile_nodes (at least one wavefront).
 __global__ __launch_bounds__(kMaxTile) void k_build_tiles(const int32_t *rp, int32_t n, int32_t light_max,
                                                           int32_t tile_nodes, int32_t *light) {
   __shared__ uint64_t keys[kMaxTile];
   const int i = threadIdx.x;
+  const int width = (int)blockDim.x;
   const int64_t base = (int64_t)blockIdx.x * tile_nodes;
   const int64_t v = base + i;
   uint64_t key = ~0ull;
@@ -1567,7 +1576,7 @@ __global__ __launch_bounds__(kMaxTile) void k_build_tiles(const int32_t *rp, int
   }
   keys[i] = key;
   __syncthreads();
-  for (int k = 2; k <= kMaxTile; k <<= 1) {
+  for (int k = 2; k <= width; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       const int p = i ^ j;
       if (p > i) {
@@ -1986,7 +1995,10 @@ hipError_t launch_fill_chunks(const int32_t *row_ptr, int32_t n, const uint64_t 
 
 hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t tile_nodes,
                               int32_t n_tiles, int32_t *light, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)n_tiles), dim3(kMaxTile), 0, s, row_ptr, n, light_max,
+  if (tile_nodes < 1 || tile_nodes > kMaxTile) return hipErrorInvalidValue;
+  int width = kWave;
+  while (width < tile_nodes) width <<= 1;
+  hipLaunchKernelGGL(k_build_tiles, dim3((unsigned)n_tiles), dim3(width), 0, s, row_ptr, n, light_max,
                      tile_nodes, light);
   return hipGetLastError();
 }
