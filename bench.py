@@ -151,6 +151,7 @@ def run_batch_mode(args):
     space = dict(tune.SPACE)
     space["group"] = [G, 256, 128, 64]
     space["seeds_per_row"] = [0, 4, 2, 1]  # 0: all 8 seeds of a graph in one row
+    space["packed5"] = [0, 1]  # one register per byte, or 5-bit registers (320-byte rows)
     start = dict(tune.DEFAULTS)
     start["group"] = G
     t_tune = time.perf_counter()

@@ -382,7 +382,14 @@ def hanf_batch_read_nt(ctx, comp: int) -> np.ndarray:
     return out[: n.value]
 
 
-def hanf_batch_read_registers(ctx, comp: int, n: int, log2m: int) -> np.ndarray:
+def hanf_batch_read_registers(ctx, comp: int, n: int, log2m: int, out=None):
+    """Counters of component `comp` as an (n, m) uint8 array, or into `out` (a device
+    tensor of n*m bytes)."""
+    if out is not None and _is_tensor(out) and out.is_cuda:
+        if out.numel() != n << log2m or out.element_size() != 1:
+            raise ValueError("out must be a byte device tensor of n*m bytes")
+        _check(lib().hanf_batch_read_registers(ctx, comp, out.data_ptr(), n << log2m, HANF_DEVICE_PTRS), ctx)
+        return out
     out = np.empty((n, 1 << log2m), np.uint8)
     _check(lib().hanf_batch_read_registers(ctx, comp, out.ctypes.data, out.size, HANF_HOST_PTRS), ctx)
     return out

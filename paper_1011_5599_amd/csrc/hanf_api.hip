@@ -564,7 +564,7 @@ int bytes_to_regs(hanf_ctx *c, const uint8_t *in, uint8_t *dst, uint32_t flags) 
 
 // Bytes of one node's row of counters: S counters of m bytes, or one of 5m/8 bytes (packed).
 size_t row_bytes(int log2m, int sl, int packed) {
-  return packed ? ((size_t)kPacked5LaneBytes << (log2m - 6)) : ((size_t)1 << log2m) << sl;
+  return (packed ? ((size_t)kPacked5LaneBytes << (log2m - 6)) : ((size_t)1 << log2m)) << sl;
 }
 
 int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
@@ -1142,13 +1142,13 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
   if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
   const int packed = c->packed_opt;
-  if (packed && c->batch) return fail(c, HANF_EINVAL, "5-bit registers are for single graphs");
   if (packed && log2m < 6) return fail(c, HANF_EINVAL, "5-bit registers need m >= 64 (log2m >= 6)");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   int sl = 0;
   if (c->batch) {
-    // counters per row: as many seeds as fit, a power of two, at most 32, rows <= 1024 bytes
+    // counters per row: as many seeds as fit, a power of two, at most 32, rows <= 1024
+    // registers (1024 bytes, or 640 packed)
     const int m = 1 << log2m;
     int S = 1;
     while (S < c->n_seeds && S < 32 && 2 * S * m <= 1024 && (c->seeds_row_opt == 0 || S < c->seeds_row_opt)) S *= 2;
@@ -1156,7 +1156,7 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
     if ((rc = set_layout(c, (c->n_seeds + S - 1) / S))) return rc;
   }
   // lanes per node row: 16 byte registers or 64 packed ones per lane
-  const int G = packed ? 1 << (log2m - 6) : (1 << (log2m - 4)) << sl;
+  const int G = (packed ? 1 << (log2m - 6) : 1 << (log2m - 4)) << sl;
   const int lane_bytes = packed ? kPacked5LaneBytes : 16;
   Schedule want;
   choose_schedule(c, G, lane_bytes, want);
@@ -1763,18 +1763,40 @@ int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t b
   if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
   const int32_t row = c->comp_row_h[comp];
   const int32_t L = row >> c->sl, j = row & ((1 << c->sl) - 1);
-  const size_t m = (size_t)1 << c->log2m, R = m << c->sl;
+  const size_t m = (size_t)1 << c->log2m, R = row_bytes(c->log2m, c->sl, c->packed);
+  const size_t cb = R >> c->sl;  // bytes of one counter
   const int32_t ng = c->lay_n_h[L];
   if (bytes != (int64_t)ng * (int64_t)m) return fail(c, HANF_EINVAL, "bytes must be n_graph * m");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   if ((rc = read_state(c))) return rc;
-  // counter j of every row of the component's nodes: a strided copy
-  const uint8_t *src = c->regs[c->st_host->t & 1] + (size_t)c->lay_node_off_h[L] * R + (size_t)j * m;
-  HIP_TRY(c, hipMemcpy2DAsync(out, m, src, R, m, (size_t)ng,
-                              flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
-          "register read");
-  return sync(c, "register read");
+  // counter j of every row of the component's nodes: a strided copy (unpacked on the device)
+  const uint8_t *src = c->regs[c->st_host->t & 1] + (size_t)c->lay_node_off_h[L] * R + (size_t)j * cb;
+  if (!c->packed) {
+    HIP_TRY(c, hipMemcpy2DAsync(out, m, src, R, m, (size_t)ng,
+                                flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+            "register read");
+    return sync(c, "register read");
+  }
+  const int32_t gpr = (int32_t)(m / 64);
+  if (flags == HANF_DEVICE_PTRS) {
+    HIP_TRY(c, launch_unpack5_rows(src, (int64_t)R, gpr, ng, out, c->stream), "register unpack");
+    return sync(c, "register read");
+  }
+  const int64_t rows_per = std::max<int64_t>(1, kStageGroups / gpr);
+  const int64_t chunk = std::min<int64_t>(ng, rows_per);
+  uint8_t *stage = nullptr;
+  if ((rc = dev_alloc(c, &stage, (size_t)chunk * m, "register staging"))) return rc;
+  hipError_t e = hipSuccess;
+  for (int64_t r0 = 0; r0 < ng && e == hipSuccess; r0 += chunk) {
+    const int64_t cnt = std::min<int64_t>(chunk, ng - r0);
+    e = launch_unpack5_rows(src + r0 * (int64_t)R, (int64_t)R, gpr, cnt, stage, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out + r0 * (int64_t)m, stage, (size_t)cnt * m, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  }
+  dev_release(c, stage);
+  if (e != hipSuccess) return hip_fail(c, e, "register read");
+  return HANF_OK;
 }
 
 int hanf_batch_read_estimates(hanf_ctx *c, int32_t comp, double *out, int64_t count, uint32_t flags) {

@@ -120,7 +120,7 @@ struct PassArgs {
   int32_t seed_log2;         // S = 2^seed_log2 counters per node row (1 for a single run)
   int32_t gs;                // lanes per counter: m / 16, or m / 64 for 5-bit registers
                              // (a row has S * gs lanes)
-  int32_t packed;            // 1: 5-bit registers packed in 64-bit words (single runs, m >= 64)
+  int32_t packed;            // 1: 5-bit registers packed without gaps (m >= 64)
   int32_t n_blocks;          // ceil(n / 64)
   int32_t n_chunks;
   int32_t n_chunk_wgs;       // union workgroups given to chunks (multiple of 8)
@@ -200,5 +200,7 @@ hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *
 hipError_t launch_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups, hipStream_t s);
 hipError_t launch_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups, hipStream_t s);
 hipError_t launch_pack5(const uint8_t *in, uint8_t *packed, int64_t groups, hipStream_t s);
+hipError_t launch_unpack5_rows(const uint8_t *src, int64_t row_stride, int32_t gpr, int64_t rows, uint8_t *out,
+                               hipStream_t s);
 
 }  // namespace hanf

@@ -774,8 +774,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
   add_block_counters(cnt, a.stat_slots);
 }
 
-// Estimates of the counters this pass changed, for formats whose union step leaves them out
-// (one counter per node row; G lanes per node, all lanes of a node take the same branch).
+// Estimates of the counters this pass changed, for formats whose union step leaves them out.
+// G lanes per node row; counter j of the row is lanes j*gs .. j*gs+gs-1, which take the
+// same branch (their flag bit), so the estimate's shuffles stay inside active groups.
 template <class F, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a) {
   const DevState *st = a.st;
@@ -785,9 +786,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a) 
   const int64_t v64 = gid / G;
   if (v64 >= a.n) return;  // whole nodes leave together (G | 64)
   const int32_t v = (int32_t)v64;
-  if (!node_mod(f.cur_bits, v, 0)) return;
-  const double E = slot_estimate<F>(F::load(f.nxt, v, G, (int)(gid % G)), a.lc, a.K, G);
-  if (gid % G == 0) a.est[v] = E;
+  const int sub = (int)(gid % G), gs = a.gs, j = sub / gs;
+  const uint64_t bit = ((uint64_t)v << f.sl) + j;
+  if (((f.cur_bits[bit >> 5] >> (bit & 31)) & 1u) == 0u) return;
+  const double E = slot_estimate<F>(F::load(f.nxt, v, G, sub), a.lc, a.K, gs);
+  if (sub % gs == 0) a.est[((size_t)v << f.sl) + j] = E;
 }
 
 // Per 64-node block, one lane each: re-sum the estimates where a counter changed (else
@@ -1898,6 +1901,27 @@ __global__ void k_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, 
     F::store(out, g, 1, 0, F::max(F::load(x, g, 1, 0), F::load(y, g, 1, 0)));
 }
 
+// One counter of every row of a packed layout to one register per byte: `rows` rows of
+// `row_stride` bytes from `src` (the counter's first byte in the first row), `gpr` groups of
+// 64 registers per counter; group q of row r goes to out + (r * gpr + q) * 64.
+__global__ void k_unpack5_rows(const uint8_t *src, int64_t row_stride, int32_t gpr, int64_t rows, uint8_t *out) {
+  using F = Packed5Regs;
+  const int64_t groups = rows * gpr;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += stride) {
+    const int64_t r = g / gpr, q = g % gpr;
+    const F::Lane x = F::load(src + r * row_stride + q * F::kBytes, 0, 1, 0);
+    uint32_t w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = 0u;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) w[j >> 2] |= F::field(x, j) << (8 * (j & 3));
+    uint4 *o = reinterpret_cast<uint4 *>(out + g * 64);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
+  }
+}
+
 // Packed counters (5 bits per register) to one register per byte and back, 64 registers
 // per thread: group g is bytes 40g .. 40g+39 packed and 64g .. 64g+63 unpacked.
 __global__ void k_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups) {
@@ -2003,8 +2027,8 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
   return hipGetLastError();
 }
 
-// Instantiations: byte registers with 1..64 lanes per node row, 5-bit registers with 1, 2
-// or 4 lanes per counter (m = 64, 128, 256; single runs only).
+// Instantiations: byte registers with 1..64 lanes per node row (rows up to 1024 bytes),
+// 5-bit registers with 1..16 (rows up to 1024 registers, 640 bytes).
 #define HANF_DISPATCH_FG(P_, G_, EXPR)                          \
   if (P_) {                                                     \
     using F = Packed5Regs;                                      \
@@ -2012,6 +2036,8 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
       case 1: { constexpr int G = 1; EXPR; } break;             \
       case 2: { constexpr int G = 2; EXPR; } break;             \
       case 4: { constexpr int G = 4; EXPR; } break;             \
+      case 8: { constexpr int G = 8; EXPR; } break;             \
+      case 16: { constexpr int G = 16; EXPR; } break;           \
       default: return hipErrorInvalidValue;                     \
     }                                                           \
   } else {                                                      \
@@ -2028,9 +2054,9 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
     }                                                           \
   }
 
-// Lanes per node row: S counters of m/16 lanes each (bytes), or m/64 lanes (5-bit).
+// Lanes per node row: S counters of m/16 lanes each (bytes), or of m/64 lanes (5-bit).
 int row_lanes(const PassArgs &a) {
-  return a.packed ? 1 << (a.log2m - 6) : (1 << (a.log2m - 4)) << a.seed_log2;
+  return (a.packed ? 1 << (a.log2m - 6) : 1 << (a.log2m - 4)) << a.seed_log2;
 }
 
 // Threads of the kernels that start a run: one per row lane, and enough to clear the flag
@@ -2256,6 +2282,14 @@ hipError_t launch_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, 
 hipError_t launch_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups, hipStream_t s) {
   if (groups == 0) return hipSuccess;
   hipLaunchKernelGGL(k_unpack5, dim3(grid_for(groups, 256, 8192)), dim3(256), 0, s, packed, out, groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack5_rows(const uint8_t *src, int64_t row_stride, int32_t gpr, int64_t rows, uint8_t *out,
+                               hipStream_t s) {
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack5_rows, dim3(grid_for(rows * gpr, 256, 8192)), dim3(256), 0, s, src, row_stride, gpr,
+                     rows, out);
   return hipGetLastError();
 }
 

@@ -195,11 +195,10 @@ def test_packed_errors_and_footprint():
         h.init(6, 1)
         want, _, _ = oracle.run(rp, ci, 6, 1)
         np.testing.assert_allclose(h.run(), want, rtol=RTOL, atol=0)
-    with hanf.Batch(0) as bt:
-        hanf.hanf_set_option(bt.ctx, hanf.HANF_OPT_PACKED5, 1)
+    with hanf.Batch(0, packed5=1) as bt:
         bt.load_graphs([(rp, ci)], 2)
         with pytest.raises(hanf.HanfError) as e:
-            bt.init(6, [1, 2])
+            bt.init(5, [1, 2])
         assert e.value.code == hanf.HANF_EINVAL
     n, arcs = 1 << 20, 1 << 24
     for b in (6, 7, 8):
@@ -223,3 +222,63 @@ def test_packed_host_transpose_and_device_graph():
         assert np.array_equal(a.registers(), d.registers())
     want, _, _ = oracle.run(rp, ci, 8, 5)
     np.testing.assert_allclose(na, want, rtol=RTOL, atol=0)
+
+
+def _mixed_graphs():
+    gs = [graphgen.erdos_renyi(200 + 37 * i, 5 * (200 + 37 * i), seed=60 + i) for i in range(5)]
+    gs += [graphgen.rmat(9 + (i % 3), 3000 + 500 * i, seed=70 + i) for i in range(5)]
+    gs += [graphgen.empty(1), graphgen.empty(70), graphgen.directed_path(150), graphgen.star_out(3000),
+           graphgen.complete(40)]
+    return gs
+
+
+@pytest.mark.parametrize("b,S,opts", [(6, 8, {}), (7, 3, {}), (8, 4, {}), (6, 40, {}), (6, 8, dict(seeds_per_row=2)),
+                                      (7, 2, dict(systolic=1, transpose=True))])
+def test_packed_batch_components_equal_their_runs(b, S, opts):
+    """Rows of S packed counters (8 seeds of m = 64: 320-byte rows; 40 seeds: copies of rows
+    of 16), every component against the oracle and against the byte-register batch."""
+    gs = _mixed_graphs()
+    seeds = [1000 * g + 17 * s + 1 for g in range(len(gs)) for s in range(S)]
+    opts = dict(opts)
+    transpose = opts.pop("transpose", False)
+    _flush(f"[packed batch] {len(gs)} graphs x {S} seeds, b={b}, opts={opts} transpose={transpose}")
+    with hanf.Batch(0, packed5=1, **opts) as bt, hanf.Batch(0, **opts) as by:
+        for x in (bt, by):
+            x.load_graphs(gs, S)
+            if transpose:
+                x.build_transpose()
+            x.init(b, seeds)
+            x.run()
+        if transpose:
+            assert any(r["systolic"] for r in bt.pass_log())
+        T = bt.fixpoints()
+        assert np.array_equal(T, by.fixpoints())
+        for g, (rp, ci) in enumerate(gs):
+            for s in range(S):
+                c = g * S + s
+                if s >= 3 and s != S - 1:
+                    # every component against the byte batch; a few per graph against the oracle
+                    assert np.array_equal(bt.nt(c), by.nt(c)), (g, s)
+                    assert np.array_equal(bt.registers(c), by.registers(c)), (g, s)
+                    continue
+                nt_ref, T_ref, regs_ref = oracle.run(rp, ci, b, seeds[c], want_regs=True)
+                assert T[c] == T_ref, (g, s)
+                np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=RTOL, atol=0)
+                assert np.array_equal(bt.registers(c), regs_ref), (g, s)
+                assert np.array_equal(bt.estimates(c), oracle.sizes(regs_ref, b)), (g, s)
+                assert np.array_equal(bt.nt(c), by.nt(c)), (g, s)
+
+
+def test_packed_batch_registers_to_device():
+    import torch
+    gs = _mixed_graphs()[:6]
+    S, b = 4, 7
+    seeds = [5 + c for c in range(len(gs) * S)]
+    with hanf.Batch(0, packed5=1) as bt:
+        bt.load_graphs(gs, S).init(b, seeds)
+        bt.run()
+        for c in (0, 5, len(seeds) - 1):
+            n = len(gs[c // S][0]) - 1
+            out = torch.empty(n << b, dtype=torch.uint8, device="cuda")
+            hanf.hanf_batch_read_registers(bt.ctx, c, n, b, out)
+            assert np.array_equal(out.cpu().numpy().reshape(n, 1 << b), bt.registers(c))
