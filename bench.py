@@ -231,7 +231,9 @@ def run_seeds_mode(args):
     seeds = [spec["seed"] + s for s in range(S)]
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream
-    bt = hanf.Batch(0, stream=stream)
+    opts = {k: int(v) for k, v in (kv.split("=") for kv in args.opt)}  # for the batched runs
+    packed = bool(opts.get("packed5"))
+    bt = hanf.Batch(0, stream=stream, **opts)
     h = hanf.HyperANF(0, stream=stream, timing=1)
 
     def rows():
@@ -281,7 +283,8 @@ def run_seeds_mode(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": spec_name(args.workload), "seeds": S, "log2m": b,
-                   "row_bytes": S * m, "transpose": "self" if sym else "none"},
+                   "row_bytes": S * (5 * m // 8 if packed else m), "transpose": "self" if sym else "none",
+                   "registers": "5-bit packed" if packed else "one per byte", "options": opts},
         "plain": {"ms_per_step": round(1000 * t_plain, 3), "updates_per_s": updates / t_plain},
         "speedup_vs_plain": t_plain / t_rows,
     }
