@@ -151,7 +151,7 @@ def run_batch_mode(args):
     space = dict(tune.SPACE)
     space["group"] = [G, 256, 128, 64]
     space["seeds_per_row"] = [0, 4, 2, 1]  # 0: all 8 seeds of a graph in one row
-    space["packed5"] = [0, 1]  # one register per byte, or 5-bit registers (320-byte rows)
+    space["packed5"] = [2, 0, 1]  # chosen by row width (the default), bytes, 5-bit (320-byte rows)
     start = dict(tune.DEFAULTS)
     start["group"] = G
     t_tune = time.perf_counter()
@@ -232,7 +232,12 @@ def run_seeds_mode(args):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream().cuda_stream
     opts = {k: int(v) for k, v in (kv.split("=") for kv in args.opt)}  # for the batched runs
-    packed = bool(opts.get("packed5"))
+    fmt = opts.get("packed5", 2)  # the library chooses 5-bit rows from 512 registers on
+    row_seeds = 1
+    while (row_seeds < S and row_seeds < 32 and 2 * row_seeds * m <= 1024
+           and (not opts.get("seeds_per_row") or row_seeds < opts["seeds_per_row"])):
+        row_seeds *= 2
+    packed = fmt == 1 or (fmt == 2 and m >= 64 and row_seeds * m >= 512)
     bt = hanf.Batch(0, stream=stream, **opts)
     h = hanf.HyperANF(0, stream=stream, timing=1)
 
@@ -283,7 +288,8 @@ def run_seeds_mode(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": spec_name(args.workload), "seeds": S, "log2m": b,
-                   "row_bytes": S * (5 * m // 8 if packed else m), "transpose": "self" if sym else "none",
+                   "row_bytes": row_seeds * (5 * m // 8 if packed else m),
+                   "transpose": "self" if sym else "none",
                    "registers": "5-bit packed" if packed else "one per byte", "options": opts},
         "plain": {"ms_per_step": round(1000 * t_plain, 3), "updates_per_s": updates / t_plain},
         "speedup_vs_plain": t_plain / t_rows,
@@ -449,7 +455,7 @@ def main():
         k, v = kv.split("=")
         opts[k] = int(v)
     h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
-    packed = bool(opts.get("packed5"))
+    packed = opts.get("packed5") == 1  # single runs keep byte registers unless told otherwise
     rowb = (5 * m) // 8 if packed else m  # bytes of one counter
     tmode = args.transpose
     if tmode == "auto":

@@ -74,15 +74,16 @@ extern "C" {
                                    all). 0 (default): as many as fit, up to 32 and 1024 bytes
                                    per row; else a power of two up to 32. Results do not change */
 
-#define HANF_OPT_PACKED5 11     /* 1: keep 5-bit registers packed without gaps, as in Section 3.3
-                                   (register j of a counter at bits 5j..5j+4 of its
-                                   little-endian bit string: 5m/8 bytes per counter instead of m),
-                                   maximised with the paper's broadword multi-word max. Needs
-                                   m >= 64 (64 registers fill five 64-bit words); single graphs
-                                   and batches (a batch row holds up to 1024 registers); read by
-                                   the next hanf_init_counters / hanf_init_batch. Results are
-                                   identical; register I/O stays one byte per register. 0: one
-                                   register per byte (default) */
+#define HANF_OPT_PACKED5 11     /* register format, read by the next hanf_init_counters /
+                                   hanf_init_batch. 1: 5-bit registers packed without gaps, as
+                                   in Section 3.3 (register j of a counter at bits 5j..5j+4 of
+                                   its little-endian bit string: 5m/8 bytes per counter instead
+                                   of m), maximised with the paper's broadword multi-word max;
+                                   needs m >= 64 (64 registers fill five 64-bit words). 0: one
+                                   register per byte. 2 (default): 5-bit when a node's row
+                                   holds at least 512 registers (m >= 64 and seeds side by side
+                                   in a batch), else one per byte. Results are identical; register
+                                   I/O stays one byte per register */
 
 /* Tuning and test options (the results never change):
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;

@@ -69,7 +69,7 @@ struct hanf_ctx {
   int unroll = 4;
   int sys_div = 4;    // a pass after one that changed < n/sys_div counters is systolic (0 = never)
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
-  int packed_opt = 0;    // 1: 5-bit registers for single runs (HANF_OPT_PACKED5)
+  int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   bool sys_seen = false; // the last state read showed a systolic next pass
 
   // graph
@@ -937,7 +937,7 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       c->seeds_row_opt = (int)value;
       break;
     case HANF_OPT_PACKED5:
-      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "packed5 must be 0 or 1");
+      if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "packed5 must be 0, 1 or 2");
       c->packed_opt = (int)value;
       break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
@@ -1141,8 +1141,7 @@ namespace {
 int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds) {
   if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
   if (log2m < 4 || log2m > 8) return fail(c, HANF_EINVAL, "log2m must be in 4..8");
-  const int packed = c->packed_opt;
-  if (packed && log2m < 6) return fail(c, HANF_EINVAL, "5-bit registers need m >= 64 (log2m >= 6)");
+  if (c->packed_opt == 1 && log2m < 6) return fail(c, HANF_EINVAL, "5-bit registers need m >= 64 (log2m >= 6)");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
   int sl = 0;
@@ -1155,6 +1154,10 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
     while ((1 << sl) < S) ++sl;
     if ((rc = set_layout(c, (c->n_seeds + S - 1) / S))) return rc;
   }
+  // Register format: rows of at least 512 registers (several seeds side by side) are bound
+  // by their bytes, and 5-bit registers are faster there; narrower rows are bound by the
+  // rate of row requests, and one register per byte is faster (measured on MI355X).
+  const int packed = c->packed_opt == 1 || (c->packed_opt == 2 && log2m >= 6 && ((1 << log2m) << sl) >= 512);
   // lanes per node row: 16 byte registers or 64 packed ones per lane
   const int G = (packed ? 1 << (log2m - 6) : 1 << (log2m - 4)) << sl;
   const int lane_bytes = packed ? kPacked5LaneBytes : 16;

@@ -26,16 +26,19 @@ def _mixed_graphs():
     return gs
 
 
-@pytest.mark.parametrize("b,S,per_row", [(4, 3, 0), (6, 2, 0), (8, 1, 0), (6, 8, 0), (8, 8, 0), (4, 40, 0),
-                                         (6, 8, 1), (6, 8, 2), (5, 5, 4)])
-def test_batch_components_equal_their_runs(b, S, per_row):
+@pytest.mark.parametrize("b,S,per_row,fmt", [(4, 3, 0, 2), (6, 2, 0, 2), (8, 1, 0, 2), (6, 8, 0, 2), (8, 8, 0, 2),
+                                             (6, 8, 0, 0), (8, 8, 0, 0), (4, 40, 0, 2), (6, 8, 1, 2), (6, 8, 2, 2),
+                                             (5, 5, 4, 2)])
+def test_batch_components_equal_their_runs(b, S, per_row, fmt):
     """Seeds side by side in node rows: 3 seeds (a row of 4, one empty), 8 seeds of m = 64
-    (512-byte rows), m = 256 with 8 seeds (two copies of rows of 4), 40 seeds of m = 16 (two
-    copies of rows of 32), and forced 1, 2 and 4 seeds per row."""
+    (rows of 512 registers), m = 256 with 8 seeds (two copies of rows of 4), 40 seeds of
+    m = 16 (two copies of rows of 32), and forced 1, 2 and 4 seeds per row. fmt: the register
+    format option (2: chosen by row width, 5-bit for the rows of 512 registers and more; 0:
+    one register per byte for those too)."""
     gs = _mixed_graphs()
     seeds = [1000 * g + 17 * s + 1 for g in range(len(gs)) for s in range(S)]
-    _say(f"[batch] {len(gs)} graphs x {S} seeds, b={b}, seeds per row {per_row or 'auto'}")
-    with hanf.Batch(0, seeds_per_row=per_row) as bt:
+    _say(f"[batch] {len(gs)} graphs x {S} seeds, b={b}, seeds per row {per_row or 'auto'}, format {fmt}")
+    with hanf.Batch(0, seeds_per_row=per_row, packed5=fmt) as bt:
         bt.load_graphs(gs, S).init(b, seeds)
         bt.run()
         T = bt.fixpoints()

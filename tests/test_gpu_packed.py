@@ -138,7 +138,7 @@ def test_packed_edge_graphs(name):
 def test_packed_equals_bytes(b):
     """The same run in both formats: N_hat bit for bit, the same T and pass log counts."""
     rp, ci = graphgen.rmat(14, 262_144, seed=14)
-    with hanf.HyperANF(0) as p, hanf.HyperANF(0, packed5=1) as q:
+    with hanf.HyperANF(0, packed5=0) as p, hanf.HyperANF(0, packed5=1) as q:
         p.load(rp, ci).build_transpose().init(b, 5)
         q.load(rp, ci).build_transpose().init(b, 5)
         np_, nq = p.run(), q.run()
@@ -242,7 +242,7 @@ def test_packed_batch_components_equal_their_runs(b, S, opts):
     opts = dict(opts)
     transpose = opts.pop("transpose", False)
     _flush(f"[packed batch] {len(gs)} graphs x {S} seeds, b={b}, opts={opts} transpose={transpose}")
-    with hanf.Batch(0, packed5=1, **opts) as bt, hanf.Batch(0, **opts) as by:
+    with hanf.Batch(0, packed5=1, **opts) as bt, hanf.Batch(0, packed5=0, **opts) as by:
         for x in (bt, by):
             x.load_graphs(gs, S)
             if transpose:
