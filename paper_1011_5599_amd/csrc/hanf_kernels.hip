@@ -381,11 +381,14 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     beg = a.row_ptr[v];
     end = a.row_ptr[v + 1];
   }
+  // every node handed to a light round produces a new counter (all nodes in a pass over
+  // all successors; otherwise nodes with a modified successor or a stale update row), so
+  // its own counter is loaded up front, in parallel with the scan
   Lane own = F::zero(), acc = F::zero();
   bool own_loaded = false;
-  if (f.gather_all && end > beg) {
+  if (end > beg) {
     own = F::load(f.cur, v, G, sub);
-    acc = own;
+    if (f.gather_all) acc = own;
     own_loaded = true;
   }
   int32_t gathered = 0;
@@ -563,6 +566,12 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   // not read; the copy rule below still applies)
   const int32_t a1 = (f.systolic && f.todo[ch.v] == 0) ? ch.a0 : ch.a1;
   Lane acc = F::zero();
+  // a node in a single chunk is finalised here: its own counter is loaded up front, in
+  // parallel with the scan (it is needed unless no successor was modified and its update
+  // row is current, which is rare where chunks are read)
+  Lane own = F::zero();
+  const bool own_loaded = ch.part < 0 && slot == 0 && a1 > ch.a0;
+  if (own_loaded) own = F::load(f.cur, ch.v, G, sub);
   int32_t gathered = 0;
   for (int32_t base = ch.a0; base < a1; base += kWave * U) {
     int32_t w[U];
@@ -607,7 +616,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   bool any = gathered > 0;  // wavefront-uniform
   if (any) combine_slots<F, G>(acc, any);
   if (ch.part < 0) {
-    finalize_slot<F, G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, false, F::zero(), cnt);
+    finalize_slot<F, G>(a, f, slot == 0 ? ch.v : -1, lane, acc, any, own_loaded, own, cnt);
   } else if (slot == 0) {
     if (any) F::store(a.partial, ch.part, G, sub, acc);  // rows of empty chunks are never read
     if (sub == 0) a.partial_any[ch.part] = any ? 1 : 0;
