@@ -4,18 +4,20 @@
 // Data layout in HBM (S = counters per node row: 1 for a single run, up to 32 seeds of a
 // batched run side by side):
 //   regs[2]   uint8 [n][S][m]  counters c_t and c_{t+1}, node-major, m = 2^log2m bytes each
-//             (or [n][5m/8] with 5-bit registers packed without gaps, single runs)
+//             (or [n][S][5m/8] with 5-bit registers packed without gaps)
 //   bits[2]   uint32 [2 * S * ceil(n/64)]  modified-counter flags (S bits per node) of the
 //             previous / current pass
 //   est       double [n][S]    estimate of each current counter
 //   blocksum  double [ceil(n/64)][S]  cached estimate sums per 64 consecutive nodes
 //
-// One pass (c_t -> c_{t+1}) is one launch of k_union (+ k_finalize when a node's arcs are
-// split over several wavefronts) and two reduction launches. The union is bound by HBM
-// bandwidth: random gathers of m-byte successor counters. Lanes load counters 16 bytes at a
-// time (40 bytes, 64 registers, when packed); a node row (S counters) is handled by
-// G = S*m/16 lanes (m/64 packed), a "slot"; a wavefront holds W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
-// read, one S*m-byte gather); changes, flags and estimates are kept per counter.
+// One pass (c_t -> c_{t+1}) is the signal kernels (systolic passes only do work), one
+// union launch (k_union, or k_union_list over listed work units), k_finalize when a node's
+// arcs are split over several wavefronts, k_estimate_changed for packed registers, and two
+// reduction launches. The union is bound by HBM: random gathers of successor counters.
+// Lanes load counters 16 bytes at a time (40 bytes, 64 registers, when packed); a node row
+// (S counters) is handled by G = S*m/16 lanes (S*m/64 packed), a "slot"; a wavefront holds
+// W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
+// read, one row gather); changes, flags and estimates are kept per counter.
 //   - light nodes (few arcs): one slot per node, nodes of a tile sorted by degree so the
 //     slots of a wavefront finish together; tiles are assigned to XCDs in contiguous runs
 //     so neighbouring ids (and their shared successors) meet in the same L2;
