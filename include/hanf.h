@@ -121,7 +121,8 @@ typedef struct {
   int64_t rows_written;  /* counters written to the next buffer */
   int64_t rows_read;     /* own counters read to build a new counter */
   float union_ms;        /* union kernel time (HANF_OPT_TIMING), else 0 */
-  float finalize_ms;     /* multi-chunk combine kernel time, else 0 */
+  float finalize_ms;     /* multi-chunk combine kernel time (and, with 5-bit registers, the
+                            estimates of changed counters), else 0 */
   float reduce_ms;       /* estimate reduction kernels time, else 0 */
   int32_t gather_all;    /* 1 if the pass maximised with every successor */
   int32_t systolic;      /* 1 if only nodes signalled by a modified successor were recomputed */
@@ -169,9 +170,12 @@ int hanf_load_transpose(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *r
  * call order as hanf_load_transpose; single graphs and batches. */
 int hanf_transpose_self(hanf_ctx *ctx);
 
-/* Builds the transposed graph of the loaded graph (or batch) on the device: in-degree
- * counts, their prefix sums, then the predecessor lists (4 (n + 1) + 4 arcs bytes, kept
- * until the next graph ingest). Same call order as hanf_load_transpose. */
+/* Builds the transposed graph of the loaded graph (or batch) on the device: the arcs are
+ * counting-sorted by target in two levels (per-bucket counts from LDS histograms over node
+ * ranges, prefix sums, a scatter of (target, source) pairs, then a sort inside each bucket;
+ * graphs beyond 2^26 nodes use per-node counters instead). The predecessor lists take
+ * 4 (n + 1) + 4 arcs bytes, kept until the next graph ingest; transient buffers are freed
+ * before returning. Same call order as hanf_load_transpose. */
 int hanf_build_transpose(hanf_ctx *ctx);
 
 /* Counter initialisation (Algorithm 2: add v to c[v]; Algorithm 1 add). m = 2^log2m
@@ -235,10 +239,11 @@ int hanf_stats(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_s
 int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *len);
 
 /* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers:
- * two register arrays (the counters and the update buffer, Section 3.2), flags and estimate
- * sums, plus the graph copy (HANF_FP_COPY_GRAPH in `copy_graph`) and the transposed graph
- * with the systolic signal buffers (HANF_FP_TRANSPOSE). Pure host function; the memory
- * figure of Section 3.4 (O(n m) register bytes) is its dominant term. */
+ * two register arrays (the counters and the update buffer, Section 3.2; 5m/8 bytes per
+ * counter with HANF_FP_PACKED5 in `copy_graph`), flags and estimate sums, plus the graph copy
+ * (HANF_FP_COPY_GRAPH) and the transposed graph with the systolic signal buffers
+ * (HANF_FP_TRANSPOSE). Pure host function; the memory figure of Section 3.4 (O(n m) register
+ * bytes) is its dominant term. HANF_EINVAL for arguments out of range. */
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
 
 /* ---- Batched runs: many independent HyperANF runs in the same passes.
@@ -280,7 +285,9 @@ int hanf_batch_info(hanf_ctx *ctx, int32_t *n_components, int32_t *T);
 /* N_hat(0..T) of component `comp` (or up to the current iteration while it still changes). */
 int hanf_batch_read_nt(hanf_ctx *ctx, int32_t comp, double *out, int32_t cap, int32_t *len);
 
-/* Current counters of component `comp`: n_g * m bytes, node-major (graph-local ids). */
+/* Current counters of component `comp`: n_g * m bytes, node-major (graph-local ids), one
+ * byte per register (5-bit rows are unpacked on the device), to host or device memory per
+ * flags. HANF_EINVAL for a bad component or size. */
 int hanf_batch_read_registers(hanf_ctx *ctx, int32_t comp, uint8_t *out, int64_t bytes, uint32_t flags);
 
 /* Per-node estimates of component comp (count = its graph's n), as hanf_read_estimates. */
