@@ -174,8 +174,8 @@ int hanf_transpose_self(hanf_ctx *ctx);
  * counting-sorted by target in two levels (per-bucket counts from LDS histograms over node
  * ranges, prefix sums, a scatter of (target, source) pairs, then a sort inside each bucket;
  * graphs beyond 2^26 nodes use per-node counters instead). The predecessor lists take
- * 4 (n + 1) + 4 arcs bytes, kept until the next graph ingest; transient buffers are freed
- * before returning. Same call order as hanf_load_transpose. */
+ * 4 (n + 1) + 4 arcs bytes, kept until the next graph ingest; the sort's buffers go back
+ * to the context's pool before returning. Same call order as hanf_load_transpose. */
 int hanf_build_transpose(hanf_ctx *ctx);
 
 /* Counter initialisation (Algorithm 2: add v to c[v]; Algorithm 1 add). m = 2^log2m
