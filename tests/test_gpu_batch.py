@@ -206,3 +206,43 @@ def test_batch_512_graphs_8_seeds():
                         assert np.array_equal(bt.registers(c), regs_ref)
                 if g % 64 == 0:
                     _say(f"[batch512] graph {g} ok")
+
+
+@pytest.mark.parametrize("distinct", [False, True])
+def test_batch_seed_statistics(distinct):
+    """The statistics of many runs per graph (Section 6's protocol): every component's
+    hanf_stats values from the one-launch hanf_batch_stats_all equal the oracle's on its own
+    N_hat (Sections 4-5 and Algorithm 3 with eps), and seed_summary's mean and standard
+    deviation over the seeds equal those of the oracle's per-seed values."""
+    from oracle import stats as ostats
+    gs = [graphgen.rmat(10, 8000, seed=3), graphgen.erdos_renyi(900, 4000, seed=5),
+          graphgen.clique_path_clique(12, 6), graphgen.directed_cycle(80)]
+    S, b, eps = 6, 6, 0.05
+    seeds = [31 * c + 7 for c in range(len(gs) * S)]
+    keys = ("ed", "ied", "avg_dist", "spid")
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, S).init(b, seeds)
+        bt.run()
+        st = bt.stats_all(0.9, eps, distinct)
+        summ = bt.seed_summary(0.9) if not distinct else None
+    ref = {k: np.zeros((len(gs), S)) for k in keys}
+    for g, (rp, ci) in enumerate(gs):
+        for s in range(S):
+            c = g * S + s
+            nt_ref, T_ref, _ = oracle.run(rp, ci, b, seeds[c])
+            r = ostats.stats(list(nt_ref), 0.9, distinct)
+            assert st["T"][c] == T_ref == r["T"]
+            for k in keys + ("var", "n_max"):
+                if np.isnan(r[k]):
+                    assert np.isnan(st[k][c]), (g, s, k)
+                else:
+                    assert st[k][c] == pytest.approx(r[k], rel=1e-9, abs=1e-12), (g, s, k)
+            lo, hi = ostats.diameter_interval(list(nt_ref), eps, 0.9)
+            assert st["d_lo"][c] == (-1 if lo is None else lo), (g, s)
+            assert st["d_hi"][c] == (-1 if hi is None else hi), (g, s)
+            for k in keys:
+                ref[k][g, s] = r[k]
+    if summ is not None:
+        for k in keys:
+            np.testing.assert_allclose(summ[k + "_mean"], ref[k].mean(axis=1), rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(summ[k + "_std"], ref[k].std(axis=1, ddof=1), rtol=1e-7, atol=1e-12)
