@@ -4,7 +4,6 @@ Registers must be byte-identical at every iteration checked, N_hat(t) within 1e-
 relative (FP64 sums in a different order), the fixpoint iteration T equal, and the
 per-pass work counters (counters changed, successor unions) exactly the oracle's.
 """
-import math
 import os
 import sys
 

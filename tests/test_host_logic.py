@@ -1,7 +1,5 @@
 """Host-side logic without a GPU: the schedule autotuner's search and the grouping of
 profiler dispatches into passes."""
-import pytest
-
 from paper_1011_5599_amd import prof, tune
 
 
