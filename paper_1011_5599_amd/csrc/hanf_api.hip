@@ -124,6 +124,7 @@ struct hanf_ctx {
   DevState *st = nullptr;
   DevState *st_host = nullptr;  // pinned
   DevState *st_poll = nullptr;  // pinned, written by the copy hanf_enqueue leaves on the stream
+  PassLog *log_host = nullptr;  // pinned, kMaxPassesPerCheck records read with the state
   hipEvent_t poll_ev = nullptr;
   bool poll_pending = false;
   int32_t nt_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
@@ -859,6 +860,8 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_poll, sizeof(DevState), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&c->log_host, sizeof(PassLog) * kMaxPassesPerCheck, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     std::string msg = std::string("hanf_create: ") + hipGetErrorString(e);
@@ -888,6 +891,7 @@ void hanf_destroy(hanf_ctx *c) {
   c->pool.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->st_poll) (void)hipHostFree(c->st_poll);
+  if (c->log_host) (void)hipHostFree(c->log_host);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -916,7 +920,7 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       c->timing = value ? 1 : 0;
       break;
     case HANF_OPT_BATCH:
-      if (value < 1 || value > 1024) return fail(c, HANF_EINVAL, "batch must be in 1..1024");
+      if (value < 1 || value > kMaxPassesPerCheck) return fail(c, HANF_EINVAL, "batch must be in 1..1024");
       c->passes_per_check = (int)value;
       break;
     case HANF_OPT_TILE_NODES:
@@ -1290,14 +1294,19 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
       rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * kPassEvents] : nullptr);
       if (rc) return rc;
     }
-    if ((rc = read_state(c))) return rc;
-    const int32_t ran = c->st_host->passes - s0.passes;
-    if (ran > 0) {
-      std::vector<PassLog> recs((size_t)ran);
-      HIP_TRY(c, hipMemcpyAsync(recs.data(), c->log + s0.passes, sizeof(PassLog) * ran, hipMemcpyDeviceToHost,
+    // the run state and the records of every pass the batch may have run, in one wait
+    const int32_t cnt = (int32_t)std::min<int64_t>(B, (int64_t)c->nt_cap - s0.passes);
+    HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
+            "state read");
+    if (cnt > 0)
+      HIP_TRY(c, hipMemcpyAsync(c->log_host, c->log + s0.passes, sizeof(PassLog) * cnt, hipMemcpyDeviceToHost,
                                 c->stream),
               "pass log read");
-      if ((rc = sync(c, "pass log read"))) return rc;
+    if ((rc = sync(c, "state read"))) return rc;
+    const int32_t ran = c->st_host->passes - s0.passes;
+    if (ran > cnt) return fail(c, HANF_EDEVICE, "more passes recorded than enqueued");
+    if (ran > 0) {
+      const PassLog *recs = c->log_host;
       for (int32_t i = 0; i < ran; ++i) {
         hanf_pass_t r{};
         r.changed = recs[i].changed;

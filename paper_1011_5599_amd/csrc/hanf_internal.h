@@ -16,6 +16,7 @@ constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
 constexpr int kPacked5LaneBytes = 40;   // 64 registers of 5 bits: one lane of a packed counter
+constexpr int kMaxPassesPerCheck = 1024;  // passes enqueued between host reads of the run state
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
