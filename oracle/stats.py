@@ -70,8 +70,8 @@ def stats(nt, alpha: float = 0.9, distinct: bool = False):
     """Returns dict(ed, ied, avg_dist, var, spid, n_max, T)."""
     H = distance_cdf(nt, distinct)
     h = density(H)
-    if distinct and len(h):
-        h[0] = 0.0  # no self-pairs in the distinct variant
+    if distinct and len(h) and not math.isnan(H[0]):
+        h[0] = 0.0  # no self-pairs in the distinct variant (undefined without any other pair)
     mean, var = moments(h)
     return dict(
         ed=effective_diameter(H, alpha),
