@@ -235,6 +235,12 @@ int hanf_write_registers(hanf_ctx *ctx, const uint8_t *in, int64_t bytes, int32_
  * (N_hat(t) - N_hat(0)) / (max N_hat - N_hat(0)). */
 int hanf_stats(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);
 
+/* The same statistics from a caller's N_hat(0..len-1) (host memory, len >= 1, T = len-1):
+ * a pure host function, no context or device (the code hanf_stats runs on the device).
+ * HANF_EINVAL for NULL pointers, len < 1, alpha outside (0, 1] or eps < 0. */
+int hanf_stats_nt(const double *nt, int32_t len, double alpha, double eps, int32_t distinct,
+                  hanf_stats_t *out);
+
 /* Per-pass records of the current run (one per executed pass). *len = passes so far. */
 int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *len);
 

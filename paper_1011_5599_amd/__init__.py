@@ -133,6 +133,8 @@ def lib():
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
             "hanf_max5_groups": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
+            "hanf_stats_nt": ([vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp],
+                              ctypes.c_int),
             "hanf_load_batch": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
             "hanf_load_batch_list": ([vp, i32, vp, vp, vp, vp, i32, u32], ctypes.c_int),
             "hanf_enqueue": ([vp, i32], ctypes.c_int),
@@ -286,6 +288,14 @@ def hanf_write_registers(ctx, regs, t: int, nt_prefix) -> None:
     nbytes = keep.numel() if _is_tensor(keep) else keep.size
     pre = np.ascontiguousarray(nt_prefix, dtype=np.float64)
     _check(lib().hanf_write_registers(ctx, p, nbytes, t, pre.ctypes.data, pre.size, flags), ctx)
+
+
+def hanf_stats_nt(nt, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
+    """Statistics of a caller's N_hat(0..T) (host function, no device)."""
+    a = np.ascontiguousarray(nt, dtype=np.float64)
+    s = hanf_stats_t()
+    _check(lib().hanf_stats_nt(a.ctypes.data, a.size, alpha, eps, int(distinct), ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in hanf_stats_t._fields_}
 
 
 def hanf_stats(ctx, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:

@@ -1471,6 +1471,25 @@ int hanf_stats(hanf_ctx *c, double alpha, double eps, int32_t distinct, hanf_sta
   return HANF_OK;
 }
 
+int hanf_stats_nt(const double *nt, int32_t len, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {
+  if (!nt || !out || len < 1) return fail(nullptr, HANF_EINVAL, "hanf_stats_nt: need nt, out and len >= 1");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(nullptr, HANF_EINVAL, "alpha must be in (0, 1]");
+  if (!(eps >= 0.0)) return fail(nullptr, HANF_EINVAL, "eps must be >= 0");
+  double buf[9];
+  stats_of(nt, len - 1, alpha, eps, distinct ? 1 : 0, buf);
+  out->ed = buf[0];
+  out->ied = buf[1];
+  out->avg_dist = buf[2];
+  out->var = buf[3];
+  out->spid = buf[4];
+  out->n_max = buf[5];
+  out->d_lo = buf[6];
+  out->d_hi = buf[7];
+  out->T = len - 1;
+  out->distinct = distinct ? 1 : 0;
+  return HANF_OK;
+}
+
 int hanf_read_pass_log(hanf_ctx *c, hanf_pass_t *out, int32_t cap, int32_t *len) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_pass_log: NULL context");
   if (!len) return fail(c, HANF_EINVAL, "len is NULL");

@@ -57,6 +57,50 @@ struct Heavy {   // a node split in several chunks, combined by the finalize ker
 
 enum ReduceMode : int32_t { kReduceInit = 0, kReducePass = 1 };
 
+// Statistics of N_hat(0..T) into out[0..8]: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi,
+// T (Sections 4-5 and Algorithm 3). Sequential O(T) work; the same code serves the device
+// kernels (k_stats, k_stats_all) and the host entry point hanf_stats_nt.
+__host__ __device__ inline void stats_of(const double *nt, int32_t T, double alpha, double eps, int32_t distinct,
+                         double *out) {
+  double M = nt[0];
+  for (int32_t t = 1; t <= T; ++t) M = nt[t] > M ? nt[t] : M;
+  const double base = distinct ? nt[0] : 0.0;
+  const double den = M - base;
+  const double nan = __builtin_nan("");
+  double ed = nan, ied = nan, mean = 0.0, second = 0.0;
+  double Hprev = 0.0;
+  bool found = false;
+  for (int32_t t = 0; t <= T; ++t) {
+    const double H = den > 0.0 ? (nt[t] - base) / den : nan;
+    const double h = H - Hprev;
+    mean += (double)t * h;
+    second += (double)t * (double)t * h;
+    if (!found && H >= alpha) {
+      found = true;
+      ed = (double)t;
+      ied = t == 0 ? 0.0 : (double)(t - 1) + (alpha - Hprev) / (H - Hprev);
+    }
+    Hprev = H;
+  }
+  const double var = second - mean * mean;
+  double d_lo = -1.0, d_hi = -1.0;
+  for (int32_t t = 0; t <= T; ++t) {
+    const double r = nt[t] / M;
+    if (r <= alpha * (1.0 - 2.0 * eps)) d_lo = (double)t;
+    if (d_hi < 0.0 && r >= alpha * (1.0 + 2.0 * eps)) d_hi = (double)t;
+  }
+  out[0] = ed;
+  out[1] = ied;
+  out[2] = mean;
+  out[3] = var;
+  out[4] = mean != 0.0 ? var / mean : nan;
+  out[5] = M;
+  out[6] = d_lo;
+  out[7] = d_hi;
+  out[8] = (double)T;
+}
+
+
 // Layout of a batched run. Its results are components c = (graph g, seed s), independent
 // runs. Every node row holds S = 2^seed_log2 counters ("row seeds" j = 0..S-1), so the
 // graphs are laid side by side as one graph in copies ("layout components" L), each

@@ -1841,47 +1841,6 @@ __global__ __launch_bounds__(kTpThreads) void k_tp_chunk_scatter(const uint64_t 
 
 // ------------------------------------------------------------------ statistics (Sections 4-5)
 
-// Statistics of N_hat(0..T) into out[0..8]: ed, ied, avg_dist, var, spid, n_max, d_lo, d_hi,
-// T. Sequential O(T) work.
-__device__ void stats_of(const double *nt, int32_t T, double alpha, double eps, int32_t distinct,
-                         double *out) {
-  double M = nt[0];
-  for (int32_t t = 1; t <= T; ++t) M = nt[t] > M ? nt[t] : M;
-  const double base = distinct ? nt[0] : 0.0;
-  const double den = M - base;
-  const double nan = __builtin_nan("");
-  double ed = nan, ied = nan, mean = 0.0, second = 0.0;
-  double Hprev = 0.0;
-  bool found = false;
-  for (int32_t t = 0; t <= T; ++t) {
-    const double H = den > 0.0 ? (nt[t] - base) / den : nan;
-    const double h = H - Hprev;
-    mean += (double)t * h;
-    second += (double)t * (double)t * h;
-    if (!found && H >= alpha) {
-      found = true;
-      ed = (double)t;
-      ied = t == 0 ? 0.0 : (double)(t - 1) + (alpha - Hprev) / (H - Hprev);
-    }
-    Hprev = H;
-  }
-  const double var = second - mean * mean;
-  double d_lo = -1.0, d_hi = -1.0;
-  for (int32_t t = 0; t <= T; ++t) {
-    const double r = nt[t] / M;
-    if (r <= alpha * (1.0 - 2.0 * eps)) d_lo = (double)t;
-    if (d_hi < 0.0 && r >= alpha * (1.0 + 2.0 * eps)) d_hi = (double)t;
-  }
-  out[0] = ed;
-  out[1] = ied;
-  out[2] = mean;
-  out[3] = var;
-  out[4] = mean != 0.0 ? var / mean : nan;
-  out[5] = M;
-  out[6] = d_lo;
-  out[7] = d_hi;
-  out[8] = (double)T;
-}
 
 __global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out) {

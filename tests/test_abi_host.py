@@ -96,3 +96,41 @@ def test_single_hip_runtime_in_process():
             "rts = h._hip_runtimes(); assert len(rts) == 1, rts; print('ok')")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
     assert r.returncode == 0 and "ok" in r.stdout, r.stderr
+
+
+def test_host_stats_match_the_oracle():
+    """hanf_stats_nt (the statistics code the device kernels run, here on the host) against
+    the oracle's Sections 4-5 and Algorithm 3 on the N_hat sequences of small oracle runs
+    and on crafted sequences (one value; a plateau; a cycle's closed-form moments)."""
+    import math
+
+    import numpy as np
+
+    import graphgen
+    import oracle
+    from oracle import stats as ostats
+    seqs = []
+    for g in (graphgen.rmat(9, 3000, seed=2), graphgen.clique_path_clique(10, 5),
+              graphgen.directed_cycle(50), graphgen.erdos_renyi(400, 1600, seed=3)):
+        nt, _, _ = oracle.run(*g, 6, 11)
+        seqs.append(list(nt))
+    n = 40  # exact N(t) of a directed cycle: n (t + 1) pairs at distance <= t
+    seqs += [[5.0], [3.0, 3.0, 3.0], [float(n * (t + 1)) for t in range(n)]]
+    for nt in seqs:
+        for alpha, eps, distinct in ((0.9, 0.0, False), (0.5, 0.05, False), (0.9, 0.1, True)):
+            got = hanf.hanf_stats_nt(nt, alpha, eps, distinct)
+            want = ostats.stats(nt, alpha, distinct)
+            for k in ("ed", "ied", "avg_dist", "var", "spid", "n_max"):
+                if isinstance(want[k], float) and math.isnan(want[k]):
+                    assert math.isnan(got[k]), (k, nt[:3])
+                else:
+                    assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-12), (k, nt[:3])
+            assert got["T"] == want["T"] == len(nt) - 1
+            lo, hi = ostats.diameter_interval(nt, eps, alpha)
+            assert got["d_lo"] == (-1 if lo is None else lo) and got["d_hi"] == (-1 if hi is None else hi)
+    cyc = hanf.hanf_stats_nt([float(n * (t + 1)) for t in range(n)], 0.9, 0.0, True)
+    assert cyc["avg_dist"] == pytest.approx(n / 2) and cyc["var"] == pytest.approx(n * (n - 2) / 12)
+    for bad in (([], 0.9, 0.0), ([1.0], 0.0, 0.0), ([1.0], 0.9, -1.0)):
+        with pytest.raises(hanf.HanfError) as e:
+            hanf.hanf_stats_nt(*bad)
+        assert e.value.code == hanf.HANF_EINVAL
