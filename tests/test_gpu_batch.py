@@ -216,7 +216,7 @@ def test_batch_seed_statistics(distinct):
     deviation over the seeds equal those of the oracle's per-seed values."""
     from oracle import stats as ostats
     gs = [graphgen.rmat(10, 8000, seed=3), graphgen.erdos_renyi(900, 4000, seed=5),
-          graphgen.clique_path_clique(12, 6), graphgen.directed_cycle(80)]
+          graphgen.clique_path_clique(12, 6), graphgen.directed_cycle(80), graphgen.empty(5)]
     S, b, eps = 6, 6, 0.05
     seeds = [31 * c + 7 for c in range(len(gs) * S)]
     keys = ("ed", "ied", "avg_dist", "spid")
