@@ -90,6 +90,28 @@ def run_cpu_baseline(rp, ci, b, seed, passes, threads):
                        f"node segments")
 
 
+def copy_ceiling_gbs(mib: int = 1024, reps: int = 5):
+    """Bytes read + written per second by a plain 1 GiB device copy (torch), best of `reps`:
+    a measured streaming ceiling beside the 8 TB/s HBM3E specification."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    torch.cuda.empty_cache()
+    return nbytes / (best / 1000.0) / 1e9
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
@@ -410,7 +432,9 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": src.numel() * 4}))
+        del src, dst
+        print(json.dumps({"copy_calibration_bytes": (args.copy_calibration << 20),
+                          "copy_gbs_read_plus_write": round(copy_ceiling_gbs(args.copy_calibration), 1)}))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -517,6 +541,11 @@ def main():
                      finalize_ms=round(sum(r["finalize_ms"] for r in log), 4),
                      reduce_ms=round(sum(r["reduce_ms"] for r in log), 4),
                      union_ms=round(sum(r["union_ms"] for r in log), 4))
+    if roofline is not None:
+        # context for the peak: a plain device copy measured on the same GPU, after the timed region
+        cgbs = copy_ceiling_gbs()
+        roofline["copy_ceiling"] = {"gbs": round(cgbs, 1), "frac_of_peak": round(cgbs / HBM_PEAK_GBS, 4),
+                                    "achieved_over_copy": round(roofline["achieved"] / cgbs, 4)}
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
