@@ -282,3 +282,31 @@ def test_packed_batch_registers_to_device():
             out = torch.empty(n << b, dtype=torch.uint8, device="cuda")
             hanf.hanf_batch_read_registers(bt.ctx, c, n, b, out)
             assert np.array_equal(out.cpu().numpy().reshape(n, 1 << b), bt.registers(c))
+
+
+def test_format_switch_in_one_context():
+    """One context runs byte, packed and byte registers again (and a batch switches too):
+    every run equals the oracle, so buffers and schedules follow the format."""
+    rp, ci = graphgen.rmat(12, 40_000, seed=23)
+    want, T, regs = oracle.run(rp, ci, 7, 9, want_regs=True)
+    with hanf.HyperANF(0) as h:
+        h.load(rp, ci)
+        for fmt in (0, 1, 0, 1):
+            hanf.hanf_set_option(h.ctx, hanf.HANF_OPT_PACKED5, fmt)
+            h.init(7, 9)
+            np.testing.assert_allclose(h.run(), want, rtol=RTOL, atol=0)
+            assert np.array_equal(h.registers(), regs), fmt
+    gs = [graphgen.rmat(10, 6000, seed=41), graphgen.erdos_renyi(700, 3000, seed=42)]
+    S = 8
+    seeds = [100 + c for c in range(len(gs) * S)]
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, S)
+        for fmt in (1, 0, 2):
+            hanf.hanf_set_option(bt.ctx, hanf.HANF_OPT_PACKED5, fmt)
+            bt.init(6, seeds)
+            bt.run()
+            for c in (0, 5, 11, 15):
+                g = c // S
+                nt_ref, T_ref, regs_ref = oracle.run(*gs[g], 6, seeds[c], want_regs=True)
+                np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=RTOL, atol=0)
+                assert np.array_equal(bt.registers(c), regs_ref), (fmt, c)
