@@ -225,9 +225,9 @@ struct Packed5Regs {
   static __device__ __forceinline__ void size_terms(Lane a, uint64_t &S, uint32_t &V) {
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
-      const uint32_t r = field(a, j);
-      S += (uint64_t)(1u << (31u - r));
-      V += (r == 0u);
+      const uint32_t t = 0x80000000u >> field(a, j);  // 2^(31 - M[j])
+      S += (uint64_t)t;
+      V += t >> 31;  // M[j] == 0
     }
   }
   static __device__ __forceinline__ Lane single(uint32_t j, uint32_t r) {
