@@ -71,6 +71,7 @@ struct hanf_ctx {
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   bool sys_seen = false; // the last state read showed a systolic next pass
+  bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
   // graph
   int32_t n = 0;
@@ -811,7 +812,9 @@ constexpr int kPassEvents = 5;
 int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   hipStream_t s = c->stream;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
-  HIP_TRY(c, launch_signal(c->args, c->arcs, s), "signal kernels");
+  // the first pass of a run maximises with every successor and is never systolic
+  if (c->first_enqueued) HIP_TRY(c, launch_signal(c->args, c->arcs, s), "signal kernels");
+  c->first_enqueued = true;
   if (ev) HIP_TRY(c, hipEventRecord(ev[1], s), "event");
   // The per-unit kernel is skipped once the last state read showed systolic passes (the
   // persistent kernel then runs every pass, whatever its kind); otherwise both are launched
@@ -1229,6 +1232,7 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   }
   c->inited = false;
   c->sys_seen = false;
+  c->first_enqueued = false;
   fill_args(c);
   c->host_log.clear();
   if (seeds)
@@ -1424,6 +1428,7 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   c->inited = false;
   c->sys_seen = false;
+  c->first_enqueued = false;
   HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
                                 c->stream),
           "state reset");
