@@ -487,18 +487,36 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
       if (j1 > j0) {
         const int32_t A = rps[j0], B = rps[j1];
         if (lane == 0) cnt.scanned += B - A;
+        // successor ids of the next step are loaded while the flags of this step are
+        // tested, and the U flag words of a step are all requested before any is used
+        int32_t wn[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const int32_t p = A + k * kWave + lane;
+          wn[k] = p < B ? a.col_idx[p] : 0;
+        }
         for (int32_t base = A; base < B; base += kWave * U) {
           int32_t w[U];
           bool ok[U];
 #pragma unroll
           for (int k = 0; k < U; ++k) {
-            const int32_t p = base + k * kWave + lane;
-            ok[k] = p < B;
-            w[k] = ok[k] ? a.col_idx[p] : 0;
+            ok[k] = base + k * kWave + lane < B;
+            w[k] = wn[k];
           }
+          const int32_t nb = base + kWave * U;
+          if (nb < B) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+              const int32_t p = nb + k * kWave + lane;
+              wn[k] = p < B ? a.col_idx[p] : 0;
+            }
+          }
+          bool hk[U];
+#pragma unroll
+          for (int k = 0; k < U; ++k) hk[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
 #pragma unroll
           for (int k = 0; k < U; ++k) {
-            const bool h = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
+            const bool h = hk[k];
             if (__any(h)) {
               int32_t src = -1;
               if (h) {  // source node: the last j in [j0, j1) with rps[j] <= arc
