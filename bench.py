@@ -439,7 +439,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: the benchmark runs on one GPU only; runs on several GPUs are not implemented "
               f"(asked for {max(args.gpus, world)}).", file=sys.stderr)
         sys.exit(2)
 
