@@ -88,7 +88,9 @@ extern "C" {
 /* Tuning and test options (the results never change):
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
  *   101  the persistent union kernel over listed work units: 0 (default) for systolic
- *        passes, 1 never, 2 for every pass. */
+ *        passes, 1 never, 2 for every pass;
+ *   102  hanf_build_transpose: 0 (default) the bucket sort up to 2^26 nodes and per-node
+ *        counters above, 1 per-node counters always. */
 
 /* ---- hanf_footprint flags */
 #define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */

@@ -49,6 +49,7 @@ HANF_FP_TRANSPOSE = 2
 HANF_FP_PACKED5 = 4
 HANF_OPT_UNROLL = 100
 HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
+HANF_OPT_TRANSPOSE_COUNTING = 102  # 1: build transposes with per-node counters (test option)
 
 ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
                HANF_ESTATE: "ESTATE", HANF_ERANGE: "ERANGE", HANF_EMAXITER: "EMAXITER"}
@@ -453,7 +454,8 @@ class HyperANF:
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
                  "seeds_per_row": HANF_OPT_SEEDS_PER_ROW, "packed5": HANF_OPT_PACKED5,
-                 "union_policy": HANF_OPT_UNION_POLICY}
+                 "union_policy": HANF_OPT_UNION_POLICY,
+                 "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))
 

@@ -70,6 +70,7 @@ struct hanf_ctx {
   int sys_div = 4;    // a pass after one that changed < n/sys_div counters is systolic (0 = never)
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
+  int tp_counting = 0;   // 1: build transposes by per-node counters even below kTpMaxNodes
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
@@ -951,6 +952,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
       c->union_policy = (int)value;
       break;
+    case 102:  // transpose build: 0 bucket sort up to 2^26 nodes, 1 always per-node counters; used by tests
+      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "transpose build must be 0 or 1");
+      c->tp_counting = (int)value;
+      break;
     case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
       if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
       c->unroll = (int)value;
@@ -1114,7 +1119,7 @@ int hanf_build_transpose(hanf_ctx *c) {
     free_transpose(c);
     return rc;
   }
-  if (arcs > 0 && n <= kTpMaxNodes) {  // bucket sort; the counting build below is the fallback
+  if (arcs > 0 && n <= kTpMaxNodes && !c->tp_counting) {  // bucket sort; the counting build below is the fallback
     dev_release(c, keys);
     dev_release(c, tmp);
     if ((rc = transpose_buckets(c, c->rp, c->ci, n, arcs, c->trp_own, c->tci_own))) {

@@ -64,13 +64,15 @@ def test_batch_components_equal_their_runs(b, S, per_row, fmt):
                         assert st[k] == pytest.approx(sp[k], rel=1e-9, abs=1e-12), k
 
 
-@pytest.mark.parametrize("sys_div,S,b", [(1, 2, 6), (4, 2, 6), (1, 8, 8), (2, 3, 4)])
-def test_batch_systolic_components_equal_their_runs(sys_div, S, b):
-    """Systolic passes over a batch (transposed base built on the device, laid out with the
-    graph, also in two copies for 8 seeds of m = 256)."""
+@pytest.mark.parametrize("sys_div,S,b,counting", [(1, 2, 6, 0), (4, 2, 6, 0), (1, 8, 8, 0), (2, 3, 4, 0),
+                                                  (1, 8, 8, 1)])
+def test_batch_systolic_components_equal_their_runs(sys_div, S, b, counting):
+    """Systolic passes over a batch (transposed base built on the device by the bucket sort,
+    or by per-node counters, laid out with the graph, also in two copies for 8 seeds of
+    m = 256)."""
     gs = _mixed_graphs()
     seeds = [500 + 3 * c for c in range(len(gs) * S)]
-    with hanf.Batch(0, systolic=sys_div) as bt:
+    with hanf.Batch(0, systolic=sys_div, transpose_counting=counting) as bt:
         bt.load_graphs(gs, S).build_transpose().init(b, seeds)
         bt.run()
         assert any(r["systolic"] for r in bt.pass_log())

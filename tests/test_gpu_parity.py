@@ -171,12 +171,14 @@ def test_schedules_identical(opts):
     step_parity(rp, ci, 6, 17, **opts)
 
 
-@pytest.mark.parametrize("transpose", ["build", "host"])
-def test_systolic_rmat14_every_iteration(transpose):
+@pytest.mark.parametrize("transpose,opts", [("build", {}), ("host", {}), ("build", dict(transpose_counting=1))])
+def test_systolic_rmat14_every_iteration(transpose, opts):
     """Systolic passes (Section 3.3): same registers, N_hat and work counters at every t;
-    the arcs signalled in a systolic pass are exactly the arcs into modified counters."""
+    the arcs signalled in a systolic pass are exactly the arcs into modified counters. The
+    transposed graph comes from the bucket sort, the host, or the per-node counting build
+    that graphs of more than 2^26 nodes use."""
     rp, ci = graphgen.rmat(14, 262_144, seed=14)
-    step_parity(rp, ci, 4, 1, transpose=transpose)
+    step_parity(rp, ci, 4, 1, transpose=transpose, **opts)
 
 
 @pytest.mark.parametrize("opts", [dict(systolic=1), dict(systolic=1, dense_switch=0),
