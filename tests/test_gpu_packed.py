@@ -310,3 +310,22 @@ def test_format_switch_in_one_context():
                 nt_ref, T_ref, regs_ref = oracle.run(*gs[g], 6, seeds[c], want_regs=True)
                 np.testing.assert_allclose(bt.nt(c), nt_ref, rtol=RTOL, atol=0)
                 assert np.array_equal(bt.registers(c), regs_ref), (fmt, c)
+
+
+def test_packed_register_io_in_several_staging_chunks():
+    """Writing and reading 5-bit registers through host memory in more than one staging
+    chunk (2^20 groups of 64 registers each): 1.2M nodes at m = 64."""
+    import torch
+    n = 1_200_000
+    rp = np.arange(n + 1, dtype=np.int32) // 2  # every odd node has one arc
+    ci = ((np.arange(rp[-1], dtype=np.int64) * 7919) % n).astype(np.int32)
+    rng = np.random.default_rng(17)
+    regs = rng.integers(0, 32, (n, 64)).astype(np.uint8)
+    with hanf.HyperANF(0, packed5=1) as h:
+        h.load(rp, ci).init(6, 3)
+        hanf.hanf_write_registers(h.ctx, regs, 0, [123.0])
+        assert np.array_equal(h.registers(), regs)
+        out = torch.empty(regs.size, dtype=torch.uint8, device="cuda")
+        h.registers(out)
+        assert np.array_equal(out.cpu().numpy().reshape(regs.shape), regs)
+        assert np.array_equal(h.estimates(), oracle.sizes(regs, 6))
