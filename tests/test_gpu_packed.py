@@ -329,3 +329,28 @@ def test_packed_register_io_in_several_staging_chunks():
         h.registers(out)
         assert np.array_equal(out.cpu().numpy().reshape(regs.shape), regs)
         assert np.array_equal(h.estimates(), oracle.sizes(regs, 6))
+
+
+def test_packed_batch_of_one_large_graph():
+    """One graph of 1.2M nodes with 8 seeds in 5-bit rows (the many-runs protocol): every
+    component's registers, read through several staging chunks, equal the plain run's with
+    the same seed, and so does N_hat up to summation order."""
+    n = 1_200_000
+    rng = np.random.default_rng(5)
+    deg = rng.integers(0, 4, n)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(deg, out=rp[1:])
+    ci = rng.integers(0, n, int(rp[-1])).astype(np.int32)
+    rp = rp.astype(np.int32)
+    S, b = 8, 6
+    seeds = [900 + s for s in range(S)]
+    with hanf.Batch(0, packed5=1) as bt, hanf.HyperANF(0, packed5=0) as h:
+        bt.load_graphs([(rp, ci)], S).init(b, seeds)
+        bt.run()
+        for s in (0, 3, 7):
+            h.load(rp, ci).init(b, seeds[s])
+            nt = h.run()
+            got = bt.nt(s)
+            assert len(got) == len(nt), s
+            np.testing.assert_allclose(got, nt, rtol=RTOL, atol=0)
+            assert np.array_equal(bt.registers(s), h.registers()), s
