@@ -418,6 +418,9 @@ def main():
     ap.add_argument("--seeds", type=int, default=8, help="seeds mode: runs of the graph")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
     ap.add_argument("--max-batches", type=int, default=8, help="serve mode: batches in flight")
+    ap.add_argument("--runs-per-load", type=int, default=1, metavar="R",
+                    help="plain mode: runs (hash seeds seed .. seed + R - 1) after each ingest of the "
+                         "graph; a step is the ingest and its R runs")
     ap.add_argument("--transpose", choices=["auto", "self", "build", "none"], default="auto",
                     help="transposed graph for systolic passes: auto = self for symmetric workloads, "
                          "none otherwise")
@@ -488,15 +491,20 @@ def main():
         print("bench.py: --transpose self needs a symmetric workload", file=sys.stderr)
         sys.exit(2)
 
+    R = max(1, args.runs_per_load)
+
     def step():
         h.load(trp, tci)
         if tmode == "self":
             h.transpose_self()
         elif tmode == "build":
             h.build_transpose()
-        h.init(b, seed)
-        nt = h.run()
-        return nt, h.stats(), h.pass_log()
+        run_logs = []
+        for r in range(R):
+            h.init(b, seed + r)
+            nt = h.run()
+            run_logs.append(h.pass_log())
+        return nt, h.stats(), run_logs
 
     for i in range(args.warmup):
         step()
@@ -505,15 +513,15 @@ def main():
     t0 = time.perf_counter()
     logs = []
     for i in range(args.steps):
-        nt, st, log = step()
-        logs.append(log)
+        nt, st, run_logs = step()
+        logs.extend(run_logs)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1000.0 * elapsed / args.steps
     print(f"[bench] {args.steps} steps in {elapsed:.3f}s, T={st['T']}", file=sys.stderr, flush=True)
 
     log = logs[-1]
-    updates = m * sum(r["arcs_gathered"] for r in log)
+    updates = m * sum(r["arcs_gathered"] for lg in logs[-R:] for r in lg)  # the last step's R runs
     value = updates / (ms_per_step / 1000.0)
 
     roofline = None
@@ -537,10 +545,11 @@ def main():
                          gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
                          updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0),
                          frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4))
-        other = dict(signal_ms=round(sum(r["signal_ms"] for r in log), 4),
-                     finalize_ms=round(sum(r["finalize_ms"] for r in log), 4),
-                     reduce_ms=round(sum(r["reduce_ms"] for r in log), 4),
-                     union_ms=round(sum(r["union_ms"] for r in log), 4))
+        last = [r for lg in logs[-R:] for r in lg]  # the last step's passes
+        other = dict(signal_ms=round(sum(r["signal_ms"] for r in last), 4),
+                     finalize_ms=round(sum(r["finalize_ms"] for r in last), 4),
+                     reduce_ms=round(sum(r["reduce_ms"] for r in last), 4),
+                     union_ms=round(sum(r["union_ms"] for r in last), 4))
     if roofline is not None:
         # context for the peak: a plain device copy measured on the same GPU, after the timed region
         cgbs = copy_ceiling_gbs()
@@ -566,6 +575,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec_name(args.workload), "n": n, "arcs": arcs, "log2m": b,
                    "hash_seed": seed, "T": st["T"], "passes": len(log), "transpose": tmode,
+                   "runs_per_load": R,
                    "registers": "5-bit packed" if packed else "one per byte",
                    "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
                                          for r in log)},
@@ -573,8 +583,8 @@ def main():
         "cpu_baseline": cpu,
         "full_pass": full_pass,
         "per_step_kernel_ms": other if not args.no_timing else None,
-        "dense_equivalent_updates_per_s": m * arcs * (st["T"] + 1) / (ms_per_step / 1000.0),
-        "graphs_per_s": 1000.0 / ms_per_step,
+        "dense_equivalent_updates_per_s": m * arcs * sum(len(lg) for lg in logs[-R:]) / (ms_per_step / 1000.0),
+        "graphs_per_s": R * 1000.0 / ms_per_step,
         "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
         "pass_algorithmic_bytes": [algorithmic_bytes(r, n, rowb) for r in log],
         "pass_union_ms": [round(r["union_ms"], 4) for r in log] if not args.no_timing else None,

@@ -84,6 +84,24 @@ extern "C" {
                                    holds at least 512 registers (m >= 64 and seeds side by side
                                    in a batch), else one per byte. Results are identical; register
                                    I/O stays one byte per register */
+#define HANF_OPT_HUBS 12        /* node order of a single graph, chosen at the first
+                                   hanf_init_counters after ingest (a layout choice: every
+                                   register, N_hat(t) up to the order of its sum, and T are those
+                                   of the caller's order, and all I/O stays in the caller's node
+                                   ids). K > 0: the K nodes with the largest in-degree (the
+                                   counters the union step of Algorithm 2 reads most) first, by
+                                   class of in-degree (8 per octave, largest first) and id, fewer
+                                   when a class would cross K; every other node after them in id
+                                   order. Their rows then share cache lines and stay in one XCD's
+                                   L2. In-degrees come from the transposed graph if one is set,
+                                   else from a count of col_idx. Choosing the order rewrites the
+                                   graph, which costs about one pass over every node (one random
+                                   read per arc), once per ingest; later hanf_init_counters on the
+                                   same graph reuse it. It pays when the passes over every node
+                                   it speeds up outnumber that (several runs on one loaded graph,
+                                   or long runs). 0 (default): the caller's order. -1: K = 4 MiB /
+                                   row bytes (65536 at m = 64) for graphs of at least 16 K nodes
+                                   with a transposed graph, else the caller's order */
 
 /* Tuning and test options (the results never change):
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
@@ -96,6 +114,9 @@ extern "C" {
 #define HANF_FP_COPY_GRAPH 1    /* include the graph copy (HANF_HOST_PTRS ingest) */
 #define HANF_FP_TRANSPOSE 2     /* include the transposed graph and the systolic signal buffers */
 #define HANF_FP_PACKED5 4       /* 5-bit registers (HANF_OPT_PACKED5); needs log2m >= 6 */
+#define HANF_FP_ORDER 8         /* the graph (and, with HANF_FP_TRANSPOSE, its transpose) rewritten
+                                   in the library's node order, and the order tables
+                                   (HANF_OPT_HUBS); an upper bound, a self-transpose needs no copy */
 
 typedef struct hanf_ctx hanf_ctx;
 
@@ -222,6 +243,12 @@ int hanf_read_registers(hanf_ctx *ctx, uint8_t *out, int64_t bytes, uint32_t fla
  * kernels sum into N_hat(t) (exposed so they can be checked one by one). */
 int hanf_read_estimates(hanf_ctx *ctx, double *out, int64_t count, uint32_t flags);
 
+/* The node order the library runs a single graph in (HANF_OPT_HUBS): out[i] = the caller's
+ * id of the node whose counter is the library's row i (count = n int32, host or device per
+ * flags). The identity until the first hanf_init_counters after ingest chooses the order,
+ * and when that order is the caller's. HANF_EINVAL for batches or a wrong count. */
+int hanf_read_order(hanf_ctx *ctx, int32_t *out, int32_t count, uint32_t flags);
+
 /* Resumes from a checkpoint: counters `in` (n*m bytes, layout of hanf_read_registers,
  * values <= 31; packed on the device when the run keeps 5-bit registers) taken at
  * iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
@@ -249,8 +276,8 @@ int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *le
 /* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers:
  * two register arrays (the counters and the update buffer, Section 3.2; 5m/8 bytes per
  * counter with HANF_FP_PACKED5 in `copy_graph`), flags and estimate sums, plus the graph copy
- * (HANF_FP_COPY_GRAPH) and the transposed graph with the systolic signal buffers
- * (HANF_FP_TRANSPOSE). Pure host function; the memory figure of Section 3.4 (O(n m) register
+ * (HANF_FP_COPY_GRAPH), the transposed graph with the systolic signal buffers
+ * (HANF_FP_TRANSPOSE) and the reordered graph (HANF_FP_ORDER). Pure host function; the memory figure of Section 3.4 (O(n m) register
  * bytes) is its dominant term. HANF_EINVAL for arguments out of range. */
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
 

@@ -44,9 +44,11 @@ HANF_OPT_DENSE_SWITCH = 8
 HANF_OPT_SYSTOLIC = 9
 HANF_OPT_SEEDS_PER_ROW = 10
 HANF_OPT_PACKED5 = 11
+HANF_OPT_HUBS = 12
 HANF_FP_COPY_GRAPH = 1
 HANF_FP_TRANSPOSE = 2
 HANF_FP_PACKED5 = 4
+HANF_FP_ORDER = 8
 HANF_OPT_UNROLL = 100
 HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
 HANF_OPT_TRANSPOSE_COUNTING = 102  # 1: build transposes with per-node counters (test option)
@@ -126,6 +128,7 @@ def lib():
             "hanf_read_nt": ([vp, vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
             "hanf_read_registers": ([vp, vp, i64, u32], ctypes.c_int),
             "hanf_read_estimates": ([vp, vp, i64, u32], ctypes.c_int),
+            "hanf_read_order": ([vp, vp, i32, u32], ctypes.c_int),
             "hanf_batch_read_estimates": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_write_registers": ([vp, vp, i64, i32, vp, i32, u32], ctypes.c_int),
             "hanf_stats": ([vp, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
@@ -316,10 +319,10 @@ def hanf_read_pass_log(ctx) -> list[dict]:
 
 
 def hanf_footprint(n: int, arcs: int, log2m: int, copy_graph: bool = True, transpose: bool = False,
-                   packed5: bool = False) -> int:
+                   packed5: bool = False, order: bool = False) -> int:
     out = ctypes.c_int64()
     flags = ((HANF_FP_COPY_GRAPH if copy_graph else 0) | (HANF_FP_TRANSPOSE if transpose else 0)
-             | (HANF_FP_PACKED5 if packed5 else 0))
+             | (HANF_FP_PACKED5 if packed5 else 0) | (HANF_FP_ORDER if order else 0))
     _check(lib().hanf_footprint(n, arcs, log2m, flags, ctypes.byref(out)))
     return out.value
 
@@ -412,6 +415,17 @@ def hanf_read_estimates(ctx, n: int) -> np.ndarray:
     return out
 
 
+def hanf_read_order(ctx, n: int, out=None):
+    """The library's node order: out[i] = the caller's id of row i (int32; `out` may be a
+    device tensor of n int32)."""
+    if out is not None:
+        _check(lib().hanf_read_order(ctx, out.data_ptr(), n, HANF_DEVICE_PTRS), ctx)
+        return out
+    arr = np.empty(n, np.int32)
+    _check(lib().hanf_read_order(ctx, arr.ctypes.data, n, HANF_HOST_PTRS), ctx)
+    return arr
+
+
 def hanf_batch_read_estimates(ctx, comp: int, n: int) -> np.ndarray:
     out = np.empty(n, np.float64)
     _check(lib().hanf_batch_read_estimates(ctx, comp, out.ctypes.data, n, HANF_HOST_PTRS), ctx)
@@ -454,6 +468,7 @@ class HyperANF:
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
                  "seeds_per_row": HANF_OPT_SEEDS_PER_ROW, "packed5": HANF_OPT_PACKED5,
+                 "hubs": HANF_OPT_HUBS,
                  "union_policy": HANF_OPT_UNION_POLICY,
                  "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING}
         for k, v in options.items():
@@ -521,6 +536,10 @@ class HyperANF:
     def estimates(self):
         """Per-node estimates of the current counters."""
         return hanf_read_estimates(self.ctx, self.n)
+
+    def order(self, out=None):
+        """The library's node order (row i holds the caller's node order()[i])."""
+        return hanf_read_order(self.ctx, self.n, out)
 
     def stats(self, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
         return hanf_stats(self.ctx, alpha, eps, distinct)

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_PATH = os.path.join(HERE, "libhanf.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hanf_kernels.hip", "hanf_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("hanf_kernels.hip", "hanf_order.hip", "hanf_api.hip")]
 
 
 def hipcc() -> str:

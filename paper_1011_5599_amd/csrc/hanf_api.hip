@@ -71,6 +71,7 @@ struct hanf_ctx {
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   int tp_counting = 0;   // 1: build transposes by per-node counters even below kTpMaxNodes
+  int64_t hubs_opt = 0;  // HANF_OPT_HUBS: -1 auto, 0 the caller's order, K: up to K hubs first
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
@@ -83,6 +84,10 @@ struct hanf_ctx {
   // transposed graph (systolic passes): owned, or the caller's device arrays
   const int32_t *trp = nullptr, *tci = nullptr;
   int32_t *trp_own = nullptr, *tci_own = nullptr;
+  // node order chosen at the first initialisation after ingest (single graphs): the graph
+  // and its transpose above are then in that order, row v holding the caller's node perm[v]
+  bool ordered = false;
+  int32_t *perm = nullptr, *inv = nullptr;  // new id -> caller's id, and back; NULL: the same
 
   Schedule sch;
 
@@ -292,6 +297,9 @@ void free_transpose(hanf_ctx *c) {
 void free_graph(hanf_ctx *c) {
   free_transpose(c);
   free_layout(c);
+  dev_release(c, c->perm);
+  dev_release(c, c->inv);
+  c->ordered = false;
   dev_release(c, c->rp_own);
   dev_release(c, c->ci_own);
   dev_release(c, c->blk_comp);
@@ -470,6 +478,7 @@ void fill_args(hanf_ctx *c) {
   a.n_reduce_wgs = c->n_reduce_wgs;
   a.nt_cap = c->nt_cap;
   a.arcs = c->arcs;
+  a.node_id = c->batch ? nullptr : c->perm;
   a.batch.active = c->batch ? 1 : 0;
   a.batch.n_comp = c->n_comp;
   a.batch.n_lay = c->n_lay;
@@ -568,6 +577,122 @@ int bytes_to_regs(hanf_ctx *c, const uint8_t *in, uint8_t *dst, uint32_t flags) 
 // Bytes of one node's row of counters: S counters of m bytes, or one of 5m/8 bytes (packed).
 size_t row_bytes(int log2m, int sl, int packed) {
   return (packed ? ((size_t)kPacked5LaneBytes << (log2m - 6)) : ((size_t)1 << log2m)) << sl;
+}
+
+bool device_pointer(const hanf_ctx *c, const void *p) {
+  hipPointerAttribute_t attr;
+  const hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice && attr.device == c->device;
+}
+
+// (rp, ci) with rows and targets in the node order of perm / inv, into new buffers of the
+// context's pool (queued on the stream; the caller synchronises).
+int permute_graph(hanf_ctx *c, const int32_t *rp, const int32_t *ci, int32_t **rp_new, int32_t **ci_new) {
+  const int32_t n = c->n;
+  const int64_t arcs = c->arcs;
+  uint64_t *keys = nullptr, *tmp = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, rp_new, (size_t)n + 1, "reordered row_ptr")) ||
+      (rc = dev_alloc(c, ci_new, (size_t)arcs, "reordered col_idx")) ||
+      (rc = dev_alloc(c, &keys, (size_t)n + 1, "reorder keys")) ||
+      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
+    dev_release(c, *rp_new);
+    dev_release(c, *ci_new);
+    dev_release(c, keys);
+    dev_release(c, tmp);
+    return rc;
+  }
+  const hipError_t e =
+      launch_permute_csr(rp, ci, n, arcs, c->perm, c->inv, keys, tmp, *rp_new, *ci_new, c->stream);
+  dev_release(c, keys);  // pooled: reused only by work queued later on the same stream
+  dev_release(c, tmp);
+  if (e != hipSuccess) {
+    dev_release(c, *rp_new);
+    dev_release(c, *ci_new);
+    return hip_fail(c, e, "graph reorder");
+  }
+  return HANF_OK;
+}
+
+// Rows of the K most-read counters (the hubs: largest in-degree) fit one XCD's L2 together.
+constexpr int64_t kHubCacheBytes = 4 << 20;
+
+// Chooses the node order of a single graph once per ingest (HANF_OPT_HUBS): with K > 0,
+// hubs first (by class of in-degree, then id) and the other nodes after them in id order;
+// the graph and its transpose are rewritten in that order. Auto: K rows fill kHubCacheBytes,
+// for graphs with at least 16 K nodes whose transposed graph gives the in-degrees.
+int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
+  c->ordered = true;
+  const int32_t n = c->n;
+  const int64_t arcs = c->arcs;
+  int64_t K = c->hubs_opt;
+  if (K < 0) {
+    K = kHubCacheBytes / (int64_t)row_bytes(log2m, 0, packed);
+    if (!c->trp || (int64_t)n < 16 * K) K = 0;
+  }
+  K = std::min<int64_t>(K, n);
+  if (K == 0 || arcs == 0) return HANF_OK;
+  const bool self_t = c->trp && c->trp == c->rp;
+  uint32_t *deg = nullptr, *hist = nullptr;
+  int32_t *plan = nullptr;
+  uint64_t *counts = nullptr, *tmp = nullptr;
+  const int64_t ncnt = order_counts_elems(n);
+  int rc;
+  if ((rc = dev_alloc(c, &c->perm, (size_t)n, "node order")) || (rc = dev_alloc(c, &c->inv, (size_t)n, "node order")) ||
+      (rc = dev_alloc(c, &deg, (size_t)n, "in-degrees")) ||
+      (rc = dev_alloc(c, &hist, (size_t)kOrderLevels, "in-degree classes")) ||
+      (rc = dev_alloc(c, &plan, 1, "order plan")) || (rc = dev_alloc(c, &counts, (size_t)ncnt, "order counts")) ||
+      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems(ncnt), "scan scratch"))) {
+    dev_release(c, c->perm);
+    dev_release(c, c->inv);
+    dev_release(c, deg);
+    dev_release(c, hist);
+    dev_release(c, plan);
+    dev_release(c, counts);
+    dev_release(c, tmp);
+    return rc;
+  }
+  hipError_t e = launch_in_degrees(c->trp, c->ci, n, arcs, deg, c->stream);
+  if (e == hipSuccess) e = launch_order_select(deg, n, K, hist, plan, counts, tmp, c->perm, c->inv, c->stream);
+  dev_release(c, deg);
+  dev_release(c, hist);
+  dev_release(c, plan);
+  dev_release(c, counts);
+  dev_release(c, tmp);
+  int32_t *rp_new = nullptr, *ci_new = nullptr, *trp_new = nullptr, *tci_new = nullptr;
+  if (e != hipSuccess) rc = hip_fail(c, e, "node order");
+  if (!rc) rc = permute_graph(c, c->rp, c->ci, &rp_new, &ci_new);
+  if (!rc && c->trp && !self_t) rc = permute_graph(c, c->trp, c->tci, &trp_new, &tci_new);
+  if (!rc && (e = hipStreamSynchronize(c->stream)) != hipSuccess) rc = hip_fail(c, e, "node order");
+  if (rc) {
+    (void)hipStreamSynchronize(c->stream);
+    dev_release(c, rp_new);
+    dev_release(c, ci_new);
+    dev_release(c, trp_new);
+    dev_release(c, tci_new);
+    dev_release(c, c->perm);
+    dev_release(c, c->inv);
+    return rc;
+  }
+  // the reordered graph replaces the caller's arrays (or their copy)
+  dev_release(c, c->rp_own);
+  dev_release(c, c->ci_own);
+  c->rp = c->rp_own = rp_new;
+  c->ci = c->ci_own = ci_new;
+  if (self_t) {
+    c->trp = rp_new;
+    c->tci = ci_new;
+  } else if (c->trp) {
+    dev_release(c, c->trp_own);
+    dev_release(c, c->tci_own);
+    c->trp = c->trp_own = trp_new;
+    c->tci = c->tci_own = tci_new;
+  }
+  return HANF_OK;
 }
 
 int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
@@ -948,6 +1073,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "packed5 must be 0, 1 or 2");
       c->packed_opt = (int)value;
       break;
+    case HANF_OPT_HUBS:
+      if (value < -1 || value > INT32_MAX) return fail(c, HANF_EINVAL, "hubs must be -1 (auto), 0 or a count");
+      c->hubs_opt = value;
+      break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
       c->union_policy = (int)value;
@@ -1075,6 +1204,22 @@ int hanf_load_transpose(hanf_ctx *c, int32_t n_t, int64_t arcs_t, const int32_t 
     free_transpose(c);
     return fail(c, HANF_EINVAL, "malformed transposed CSR (it must have the graph's n and arcs)");
   }
+  if (c->perm) {  // the caller's ids, into the node order already chosen
+    int32_t *trp_new = nullptr, *tci_new = nullptr;
+    if ((rc = permute_graph(c, c->trp, c->tci, &trp_new, &tci_new))) {
+      free_transpose(c);
+      return rc;
+    }
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    free_transpose(c);
+    if (e != hipSuccess) {
+      dev_release(c, trp_new);
+      dev_release(c, tci_new);
+      return hip_fail(c, e, "transpose reorder");
+    }
+    c->trp = c->trp_own = trp_new;
+    c->tci = c->tci_own = tci_new;
+  }
   return HANF_OK;
 }
 
@@ -1173,6 +1318,10 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   // lanes per node row: 16 byte registers or 64 packed ones per lane
   const int G = (packed ? 1 << (log2m - 6) : 1 << (log2m - 4)) << sl;
   const int lane_bytes = packed ? kPacked5LaneBytes : 16;
+  if (!c->batch && !c->ordered) {
+    if ((rc = order_nodes(c, log2m, packed))) return rc;
+    free_schedule(c);  // built on the caller's order, if at all
+  }
   Schedule want;
   choose_schedule(c, G, lane_bytes, want);
   if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
@@ -1402,10 +1551,23 @@ int hanf_read_registers(hanf_ctx *c, uint8_t *out, int64_t bytes, uint32_t flags
   if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
   if (!out) return fail(c, HANF_EINVAL, "out is NULL");
   if (bytes != (int64_t)c->n << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n * m");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
   int rc;
   if ((rc = read_state(c))) return rc;
-  return regs_to_bytes(c, c->regs[c->st_host->t & 1], out, flags);
+  const uint8_t *src = c->regs[c->st_host->t & 1];
+  if (!c->perm) return regs_to_bytes(c, src, out, flags);
+  // rows back in the caller's order first
+  const size_t rb = row_bytes(c->log2m, c->sl, c->packed);
+  uint8_t *tmp = nullptr;
+  if ((rc = dev_alloc(c, &tmp, (size_t)c->n * rb, "register reorder"))) return rc;
+  const hipError_t e = launch_gather_rows(src, tmp, c->inv, c->n, (int64_t)rb, c->stream);
+  rc = e != hipSuccess ? hip_fail(c, e, "register reorder") : regs_to_bytes(c, tmp, out, flags);
+  (void)hipStreamSynchronize(c->stream);
+  dev_release(c, tmp);
+  return rc;
 }
 
 int hanf_read_estimates(hanf_ctx *c, double *out, int64_t count, uint32_t flags) {
@@ -1414,11 +1576,55 @@ int hanf_read_estimates(hanf_ctx *c, double *out, int64_t count, uint32_t flags)
   if (c->batch) return fail(c, HANF_EINVAL, "batched graph: use hanf_batch_read_estimates");
   if (!out) return fail(c, HANF_EINVAL, "out is NULL");
   if (count != c->n) return fail(c, HANF_EINVAL, "count must be n");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  HIP_TRY(c, hipMemcpyAsync(out, c->est, sizeof(double) * (size_t)count,
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
+  if (!c->perm) {
+    HIP_TRY(c, hipMemcpyAsync(out, c->est, sizeof(double) * (size_t)count,
+                              flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
+            "estimate read");
+    return sync(c, "estimate read");
+  }
+  // estimates back in the caller's node order
+  if (flags == HANF_DEVICE_PTRS) {
+    HIP_TRY(c, launch_gather_rows((const uint8_t *)c->est, (uint8_t *)out, c->inv, c->n, 8, c->stream),
+            "estimate reorder");
+    return sync(c, "estimate read");
+  }
+  double *tmp = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &tmp, (size_t)count, "estimate reorder"))) return rc;
+  hipError_t e = launch_gather_rows((const uint8_t *)c->est, (uint8_t *)tmp, c->inv, c->n, 8, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, sizeof(double) * (size_t)count, hipMemcpyDeviceToHost, c->stream);
+  const hipError_t e2 = hipStreamSynchronize(c->stream);
+  dev_release(c, tmp);
+  if (e != hipSuccess || e2 != hipSuccess) return hip_fail(c, e != hipSuccess ? e : e2, "estimate read");
+  return HANF_OK;
+}
+
+int hanf_read_order(hanf_ctx *c, int32_t *out, int32_t count, uint32_t flags) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_read_order: NULL context");
+  if (!c->graph_ok) return fail(c, HANF_ESTATE, "no graph loaded");
+  if (c->batch) return fail(c, HANF_EINVAL, "batched graphs keep the caller's order");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (count != c->n) return fail(c, HANF_EINVAL, "count must be n");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
+  if (!c->perm) {
+    if (flags == HANF_HOST_PTRS) {
+      for (int32_t i = 0; i < count; ++i) out[i] = i;
+      return HANF_OK;
+    }
+    HIP_TRY(c, launch_iota(out, count, c->stream), "order read");
+    return sync(c, "order read");
+  }
+  HIP_TRY(c, hipMemcpyAsync(out, c->perm, sizeof(int32_t) * (size_t)count,
                             flags == HANF_DEVICE_PTRS ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream),
-          "estimate read");
-  return sync(c, "estimate read");
+          "order read");
+  return sync(c, "order read");
 }
 
 int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t t, const double *nt_prefix,
@@ -1434,11 +1640,28 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   c->inited = false;
   c->sys_seen = false;
   c->first_enqueued = false;
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, in))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: in is not device memory of this device");
   HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
                                 c->stream),
           "state reset");
   int rc;
-  if ((rc = bytes_to_regs(c, in, c->regs[t & 1], flags))) return rc;
+  if (!c->perm) {
+    if ((rc = bytes_to_regs(c, in, c->regs[t & 1], flags))) return rc;
+  } else {  // rows in the caller's order, then into the library's
+    const size_t rb = row_bytes(c->log2m, c->sl, c->packed);
+    uint8_t *tmp = nullptr;
+    if ((rc = dev_alloc(c, &tmp, (size_t)c->n * rb, "register reorder"))) return rc;
+    rc = bytes_to_regs(c, in, tmp, flags);
+    if (!rc) {
+      const hipError_t e = launch_gather_rows(tmp, c->regs[t & 1], c->perm, c->n, (int64_t)rb, c->stream);
+      if (e != hipSuccess) rc = hip_fail(c, e, "register reorder");
+    }
+    (void)hipStreamSynchronize(c->stream);
+    dev_release(c, tmp);
+    if (rc) return rc;
+  }
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) return fail(c, HANF_EINVAL, "register value above 31");
   HIP_TRY(c, hipMemcpyAsync(c->regs[(t + 1) & 1], c->regs[t & 1], (size_t)c->n * row_bytes(c->log2m, c->sl, c->packed),
@@ -1529,6 +1752,10 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   if (copy_graph & HANF_FP_TRANSPOSE) {
     b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
     b += blocks * kNodesPerBlock + (int64_t)n * 8;  // signals and signal list
+  }
+  if (copy_graph & HANF_FP_ORDER) {
+    b += ((int64_t)n + 1) * 4 + arcs * 4 + (int64_t)n * 8;  // the reordered graph, perm and inv
+    if (copy_graph & HANF_FP_TRANSPOSE) b += ((int64_t)n + 1) * 4 + arcs * 4;  // a transpose of its own
   }
   *bytes = b;
   return HANF_OK;

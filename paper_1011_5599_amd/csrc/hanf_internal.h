@@ -178,6 +178,8 @@ struct PassArgs {
   int32_t n_reduce_wgs;
   int32_t nt_cap;
   int64_t arcs;
+  const int32_t *node_id;    // the caller's id of node v (hashed at initialisation) when the
+                             //   library chose its own node order, else NULL (the same id)
   BatchArgs batch;
 };
 
@@ -221,6 +223,28 @@ hipError_t launch_tp_second(const uint64_t *pairs, const uint64_t *bstart, const
                             const int32_t *hlist, const int32_t *hchunk0, int32_t n_heavy, const int64_t *chunk_lo,
                             const int64_t *chunk_hi, const int64_t *chunk_s, int32_t n_hchunks, uint32_t *h2, int32_t bs,
                             int32_t n, int32_t *trow_ptr, int32_t *tcol_idx, hipStream_t s);
+// ---- node order (hanf_order.hip): hubs first, by class of in-degree, then the other nodes
+constexpr int kOrderLevels = 240;                 // in-degree classes 0..239 (0: no arcs in)
+constexpr int kOrderTopLevel = kOrderLevels - 1;  // hub of level l has output class top - l
+constexpr int kOrderRest = kOrderLevels;          // output class of the other nodes
+constexpr int kOrderClasses = kOrderLevels + 1;
+int64_t order_counts_elems(int32_t n);  // uint64 counters of launch_order_select
+// in-degrees: from the transposed graph's rows when trp is set, else by counting targets
+hipError_t launch_in_degrees(const int32_t *trp, const int32_t *ci, int32_t n, int64_t arcs, uint32_t *deg,
+                             hipStream_t s);
+// perm (new id -> old id) and inv (old -> new): at most K hubs by class of in-degree, then
+// the rest by id. hist: kOrderLevels uint32; plan: 1 int32; counts: order_counts_elems(n)
+// uint64 with scan_tmp of scan_tmp_elems of that many
+hipError_t launch_order_select(const uint32_t *deg, int32_t n, int64_t K, uint32_t *hist, int32_t *plan,
+                               uint64_t *counts, uint64_t *scan_tmp, int32_t *perm, int32_t *inv, hipStream_t s);
+// the CSR (rp, ci) in the new order: keys n + 1 uint64 (with scan_tmp for n + 1)
+hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs, const int32_t *perm,
+                              const int32_t *inv, uint64_t *keys, uint64_t *scan_tmp, int32_t *rp_new,
+                              int32_t *ci_new, hipStream_t s);
+// dst row i = src row idx[i]; row_bytes a multiple of 8
+hipError_t launch_gather_rows(const uint8_t *src, uint8_t *dst, const int32_t *idx, int32_t n, int64_t row_bytes,
+                              hipStream_t s);
+hipError_t launch_iota(int32_t *p, int32_t n, hipStream_t s);
 hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
 hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s);
 hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);

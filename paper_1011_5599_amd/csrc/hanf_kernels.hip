@@ -1453,8 +1453,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
   const int32_t v = (int32_t)v64;
   const int gs = a.gs;
   const int j = sub / gs;
-  // the item hashed is the node's id in its own graph; batched runs have a seed per component
-  uint64_t key = (uint64_t)v, sd = seed;
+  // the item hashed is the node's id in its own graph (the caller's id when the library
+  // chose its own node order); batched runs have a seed per component
+  uint64_t key = a.node_id ? (uint64_t)a.node_id[v] : (uint64_t)v, sd = seed;
   bool real = true;
   if (a.batch.active) {
     const int32_t L = a.batch.blk_comp[v / kNodesPerBlock];

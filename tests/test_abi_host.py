@@ -134,3 +134,14 @@ def test_host_stats_match_the_oracle():
         with pytest.raises(hanf.HanfError) as e:
             hanf.hanf_stats_nt(*bad)
         assert e.value.code == hanf.HANF_EINVAL
+
+
+def test_footprint_counts_the_reordered_graph():
+    """HANF_FP_ORDER adds the graph rewritten in the library's node order (row_ptr, col_idx)
+    and the two order tables; with HANF_FP_TRANSPOSE a reordered transpose as well."""
+    n, arcs = 1 << 20, 1 << 24
+    graph = (n + 1) * 4 + arcs * 4
+    base = hanf.hanf_footprint(n, arcs, 6, copy_graph=False)
+    assert hanf.hanf_footprint(n, arcs, 6, copy_graph=False, order=True) - base == graph + 8 * n
+    t = hanf.hanf_footprint(n, arcs, 6, copy_graph=False, transpose=True)
+    assert hanf.hanf_footprint(n, arcs, 6, copy_graph=False, transpose=True, order=True) - t == 2 * graph + 8 * n
