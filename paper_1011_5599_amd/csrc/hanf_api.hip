@@ -130,6 +130,9 @@ struct hanf_ctx {
   PassLog *log = nullptr;
   DevState *st = nullptr;
   DevState *st_host = nullptr;  // pinned
+  bool st_fresh = false;  // st_host equals the device state: nothing queued since could change it
+  double *nt_host = nullptr;  // pinned: N_hat(0 .. nt_host_len - 1), read with the state
+  int32_t nt_host_len = 0;
   DevState *st_poll = nullptr;  // pinned, written by the copy hanf_enqueue leaves on the stream
   PassLog *log_host = nullptr;  // pinned, kMaxPassesPerCheck records read with the state
   hipEvent_t poll_ev = nullptr;
@@ -346,9 +349,48 @@ int sync(hanf_ctx *c, const char *what) {
 }
 
 int read_state(hanf_ctx *c) {
+  c->st_fresh = false;
   HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
           "state read");
-  return sync(c, "state read");
+  const int rc = sync(c, "state read");
+  c->st_fresh = rc == HANF_OK;
+  return rc;
+}
+
+// A state reset whose result the host reads back before using it.
+hipError_t reset_state_unread(hanf_ctx *c) {
+  c->st_fresh = false;
+  c->nt_host_len = 0;
+  return launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
+}
+
+// The run state, read from the device unless the host copy is current.
+int current_state(hanf_ctx *c) { return c->st_fresh ? HANF_OK : read_state(c); }
+
+// N_hat values kept on the host with the state (a prefix of the history).
+constexpr int32_t kNtHostCache = 1024;
+
+// The state k_state_reset writes (the host copy is current once it ran, as long as nothing
+// queued after it changes the state).
+void mirror_state_reset(hanf_ctx *c, int32_t t, int32_t max_passes, int64_t dense_threshold, int32_t sys_div) {
+  DevState &s = *c->st_host;
+  s.t = t;
+  s.halted = 0;
+  s.done = 0;
+  s.capped = 0;
+  s.first_pass = 1;
+  s.frontier = c->frontier;
+  s.max_passes = max_passes;
+  s.passes = 0;
+  s.err = 0;
+  s.changed_last = -1;
+  s.dense_next = 0;
+  s.dense_threshold = dense_threshold;
+  s.systolic = 0;
+  s.sys_div = sys_div;
+  s.sys_acc = 0ull;
+  s.sys_units = 0;
+  c->st_fresh = true;
 }
 
 // Default schedule parameters for G lanes per counter (W = 64/G slots per wavefront).
@@ -413,8 +455,7 @@ int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
     return rc;
   }
   e = launch_fill_chunks(c->rp, n, keys, s.chunk_arcs, s.chunks, s.heavy, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  dev_release(c, keys);
+  dev_release(c, keys);  // pooled: reused only by work queued later on the same stream
   dev_release(c, tmp);
   if (e != hipSuccess) return hip_fail(c, e, "fill chunks");
   s.n_chunk_wgs = (s.n_chunks + 3) / 4;
@@ -812,7 +853,7 @@ int set_layout(hanf_ctx *c, int32_t copies) {
   la.batch.blk_comp = c->lay_blk;
   la.batch.comp_node_off = c->lay_node_off;
   la.batch.n_lay = L;
-  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
+  if (e == hipSuccess) e = reset_state_unread(c);
   if (e == hipSuccess)
     e = launch_expand(d_goff, c->rp_own, c->ci_own, copies, la, d_aoff, c->rp_lay, c->ci_lay, nacc, aacc, c->st,
                       c->stream);
@@ -937,6 +978,7 @@ constexpr int kPassEvents = 5;
 
 int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   hipStream_t s = c->stream;
+  c->st_fresh = false;
   if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
   // the first pass of a run maximises with every successor and is never systolic
   if (c->first_enqueued) HIP_TRY(c, launch_signal(c->args, c->arcs, s), "signal kernels");
@@ -989,6 +1031,7 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_host, sizeof(DevState), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->st_poll, sizeof(DevState), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->nt_host, sizeof(double) * kNtHostCache, hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void **)&c->log_host, sizeof(PassLog) * kMaxPassesPerCheck, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev, hipEventDisableTiming);
@@ -1020,6 +1063,7 @@ void hanf_destroy(hanf_ctx *c) {
   c->pool.clear();
   if (c->st_host) (void)hipHostFree(c->st_host);
   if (c->st_poll) (void)hipHostFree(c->st_poll);
+  if (c->nt_host) (void)hipHostFree(c->nt_host);
   if (c->log_host) (void)hipHostFree(c->log_host);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1136,7 +1180,7 @@ int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, 
   }
   c->n = n;
   c->arcs = arcs;
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream), "state reset");
+  HIP_TRY(c, reset_state_unread(c), "state reset");
   HIP_TRY(c, launch_validate(c->rp, c->ci, n, arcs, c->st, c->stream), "validate");
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) {
@@ -1197,7 +1241,7 @@ int hanf_load_transpose(hanf_ctx *c, int32_t n_t, int64_t arcs_t, const int32_t 
     c->trp = c->trp_own;
     c->tci = c->tci_own;
   }
-  HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream), "state reset");
+  HIP_TRY(c, reset_state_unread(c), "state reset");
   HIP_TRY(c, launch_validate(c->trp, c->tci, n, arcs, c->st, c->stream), "validate");
   if ((rc = read_state(c))) return rc;
   if (c->st_host->err) {
@@ -1392,9 +1436,12 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (seeds)
     HIP_TRY(c, hipMemcpyAsync(c->comp_seed, seeds, sizeof(uint64_t) * c->n_comp, hipMemcpyHostToDevice, c->stream),
             "seed upload");
+  c->nt_host_len = 0;
   HIP_TRY(c, launch_state_reset(c->st, 0, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
                                 c->stream),
           "state reset");
+  // neither the init kernel nor the first reduction changes the state
+  mirror_state_reset(c, 0, c->max_passes, dense_threshold(c), systolic_div(c));
   HIP_TRY(c, launch_init(c->args, seed, c->stream), "init kernel");
   HIP_TRY(c, launch_reduce(c->args, kReduceInit, 1, c->stream), "reduce kernels");
   if (seeds && (rc = sync(c, "batch init"))) return rc;  // the seed array is the caller's
@@ -1425,7 +1472,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
   if (!c->inited) return fail(c, HANF_ESTATE, "counters not initialised");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
-  if ((rc = read_state(c))) return rc;
+  if ((rc = current_state(c))) return rc;
   int32_t steps = 0;
   std::vector<hipEvent_t> ev;
   for (;;) {
@@ -1452,15 +1499,23 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
       rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * kPassEvents] : nullptr);
       if (rc) return rc;
     }
-    // the run state and the records of every pass the batch may have run, in one wait
+    // the run state, the records of every pass the batch may have run and the start of the
+    // N_hat history, in one wait
     const int32_t cnt = (int32_t)std::min<int64_t>(B, (int64_t)c->nt_cap - s0.passes);
+    const int32_t nt_cnt = std::min(c->nt_cap, kNtHostCache);
+    c->nt_host_len = 0;
     HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
             "state read");
     if (cnt > 0)
       HIP_TRY(c, hipMemcpyAsync(c->log_host, c->log + s0.passes, sizeof(PassLog) * cnt, hipMemcpyDeviceToHost,
                                 c->stream),
               "pass log read");
+    if (!c->batch)
+      HIP_TRY(c, hipMemcpyAsync(c->nt_host, c->nt, sizeof(double) * nt_cnt, hipMemcpyDeviceToHost, c->stream),
+              "history read");
     if ((rc = sync(c, "state read"))) return rc;
+    c->st_fresh = true;
+    if (!c->batch) c->nt_host_len = std::min(c->st_host->t + 1, nt_cnt);
     const int32_t ran = c->st_host->passes - s0.passes;
     if (ran > cnt) return fail(c, HANF_EDEVICE, "more passes recorded than enqueued");
     if (ran > 0) {
@@ -1537,11 +1592,15 @@ int hanf_read_nt(hanf_ctx *c, double *out, int32_t cap, int32_t *len) {
   if (!len) return fail(c, HANF_EINVAL, "len is NULL");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
-  if ((rc = read_state(c))) return rc;
+  if ((rc = current_state(c))) return rc;
   const int32_t have = c->st_host->t + 1;
   *len = have;
   if (cap < have) return fail(c, HANF_ERANGE, "output capacity below t+1");
   if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (c->st_fresh && have <= c->nt_host_len) {  // read with the state by the last wait
+    std::memcpy(out, c->nt_host, sizeof(double) * have);
+    return HANF_OK;
+  }
   HIP_TRY(c, hipMemcpyAsync(out, c->nt, sizeof(double) * have, hipMemcpyDeviceToHost, c->stream), "history read");
   return sync(c, "history read");
 }
@@ -1556,7 +1615,7 @@ int hanf_read_registers(hanf_ctx *c, uint8_t *out, int64_t bytes, uint32_t flags
   if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
     return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
   int rc;
-  if ((rc = read_state(c))) return rc;
+  if ((rc = current_state(c))) return rc;
   const uint8_t *src = c->regs[c->st_host->t & 1];
   if (!c->perm) return regs_to_bytes(c, src, out, flags);
   // rows back in the caller's order first
@@ -1643,6 +1702,8 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   if (flags == HANF_DEVICE_PTRS && !device_pointer(c, in))
     return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: in is not device memory of this device");
+  c->st_fresh = false;
+  c->nt_host_len = 0;
   HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),
                                 c->stream),
           "state reset");
@@ -1846,7 +1907,7 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
+  if (e == hipSuccess) e = reset_state_unread(c);
   if (e == hipSuccess) e = launch_validate(d_rp, d_ci, N, arcs, c->st, c->stream);
   if (e == hipSuccess) e = launch_check_offsets(d_rp, d_goff, d_gaoff, n_graphs, c->st, c->stream);
   c->batch = true;
@@ -1962,7 +2023,7 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->comp_node_off, node_off.data(), sizeof(int32_t) * (C + 1), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(c->comp_n, ncomp.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = launch_state_reset(c->st, 0, c->frontier, 1, 0, 0, c->stream);
+  if (e == hipSuccess) e = reset_state_unread(c);
   c->batch = true;
   c->n_graphs = n_graphs;
   c->n_seeds = n_seeds;
