@@ -974,29 +974,36 @@ int64_t dense_threshold(const hanf_ctx *c) {
 // Systolic passes need the transposed graph and the signal buffers of the run.
 int32_t systolic_div(const hanf_ctx *c) { return (c->args.trow_ptr && c->frontier) ? c->sys_div : 0; }
 
-constexpr int kPassEvents = 5;
+// Timed passes: start and end of the signal kernels, the union step, finalize (with the
+// estimates of packed rows) and the reduction, each pair taken from the kernels' own
+// dispatches.
+constexpr int kPassEvents = 8;
 
 int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   hipStream_t s = c->stream;
   c->st_fresh = false;
-  if (ev) HIP_TRY(c, hipEventRecord(ev[0], s), "event");
+  hipEvent_t e[kPassEvents] = {};
+  if (ev)
+    for (int i = 0; i < kPassEvents; ++i) e[i] = ev[i];
   // the first pass of a run maximises with every successor and is never systolic
-  if (c->first_enqueued) HIP_TRY(c, launch_signal(c->args, c->arcs, s), "signal kernels");
+  if (c->first_enqueued) {
+    HIP_TRY(c, launch_signal(c->args, c->arcs, s, e[0], e[1]), "signal kernels");
+  } else if (ev) {
+    HIP_TRY(c, hipEventRecord(e[0], s), "event");
+    HIP_TRY(c, hipEventRecord(e[1], s), "event");
+  }
   c->first_enqueued = true;
-  if (ev) HIP_TRY(c, hipEventRecord(ev[1], s), "event");
   // The per-unit kernel is skipped once the last state read showed systolic passes (the
   // persistent kernel then runs every pass, whatever its kind); otherwise both are launched
   // and each leaves the passes that are not its own.
   const bool has_sys = c->args.trow_ptr != nullptr;
   const int list = c->union_policy == 2 || (c->union_policy == 0 && has_sys);
   const int full = c->union_policy == 1 || (c->union_policy == 0 && !(has_sys && c->sys_seen));
-  HIP_TRY(c, launch_union(c->args, c->unroll, full, list, s), "union kernel");
-  if (ev) HIP_TRY(c, hipEventRecord(ev[2], s), "event");
-  HIP_TRY(c, launch_finalize(c->args, s), "finalize kernel");
-  HIP_TRY(c, launch_estimate_changed(c->args, s), "estimate kernel");
-  if (ev) HIP_TRY(c, hipEventRecord(ev[3], s), "event");
-  HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s), "reduce kernels");
-  if (ev) HIP_TRY(c, hipEventRecord(ev[4], s), "event");
+  HIP_TRY(c, launch_union(c->args, c->unroll, full, list, s, e[2], e[3]), "union kernel");
+  const bool est = c->args.packed != 0;  // packed rows: estimates in a kernel of their own
+  HIP_TRY(c, launch_finalize(c->args, s, e[4], est ? nullptr : e[5]), "finalize kernel");
+  HIP_TRY(c, launch_estimate_changed(c->args, s, nullptr, est ? e[5] : nullptr), "estimate kernel");
+  HIP_TRY(c, launch_reduce(c->args, kReducePass, 0, s, e[6], e[7]), "reduce kernels");
   return HANF_OK;
 }
 
@@ -1533,9 +1540,9 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * kPassEvents];
           (void)hipEventElapsedTime(&r.signal_ms, e[0], e[1]);
-          (void)hipEventElapsedTime(&r.union_ms, e[1], e[2]);
-          (void)hipEventElapsedTime(&r.finalize_ms, e[2], e[3]);
-          (void)hipEventElapsedTime(&r.reduce_ms, e[3], e[4]);
+          (void)hipEventElapsedTime(&r.union_ms, e[2], e[3]);
+          (void)hipEventElapsedTime(&r.finalize_ms, e[4], e[5]);
+          (void)hipEventElapsedTime(&r.reduce_ms, e[6], e[7]);
         }
         c->host_log.push_back(r);
       }

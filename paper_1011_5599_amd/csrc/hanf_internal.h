@@ -199,10 +199,14 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
                               int32_t n_tiles, int32_t *light, hipStream_t s);
 hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s);
 hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s);
-hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s);
+// Pass launchers take optional events recorded at the start of their first kernel (e0) and
+// the end of their last (e1).
+hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 // full: the kernel with one wavefront per work unit; list: the persistent kernel, which
 // runs the systolic passes when both are launched and every pass when it runs alone
-hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s);
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 // transposed graph: in-degree counts into keys (n + 1 zeroed uint64), then, after their
 // exclusive scan, the predecessor lists (keys are consumed as fill cursors)
 hipError_t launch_transpose_count(const int32_t *col_idx, int64_t arcs, uint64_t *keys, hipStream_t s);
@@ -245,9 +249,11 @@ hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, i
 hipError_t launch_gather_rows(const uint8_t *src, uint8_t *dst, const int32_t *idx, int32_t n, int64_t row_bytes,
                               hipStream_t s);
 hipError_t launch_iota(int32_t *p, int32_t n, hipStream_t s);
-hipError_t launch_finalize(const PassArgs &a, hipStream_t s);
-hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s);
-hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s);
+hipError_t launch_finalize(const PassArgs &a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s, hipEvent_t e0 = nullptr,
+                                   hipEvent_t e1 = nullptr);
+hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s, hipEvent_t e0 = nullptr,
+                         hipEvent_t e1 = nullptr);
 hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevState *st, double alpha,
                         double eps, int32_t distinct, double *out, hipStream_t s);
 hipError_t launch_expand_local(const int32_t *graph_off, const int32_t *arc_off, const int32_t *rp_in,

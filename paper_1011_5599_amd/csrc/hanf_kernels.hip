@@ -23,6 +23,8 @@
 //     so neighbouring ids (and their shared successors) meet in the same L2;
 //   - other nodes: one wavefront per chunk of arcs, its W slots striding over the chunk;
 //     nodes with several chunks leave per-chunk partial maxima combined by k_finalize.
+#include <hip/hip_ext.h>
+
 #include "hanf_internal.h"
 
 namespace hanf {
@@ -2043,6 +2045,24 @@ hipError_t launch_build_tiles(const int32_t *row_ptr, int32_t n, int32_t light_m
     }                                                           \
   }
 
+// A launch whose start and end record `e0` and `e1` (either may be NULL): the events are
+// taken from the kernel's own dispatch, so timing a pass adds no marker between its kernels.
+template <typename... KArgs, typename... Args>
+void launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+              Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
+// Events of a group that launched no kernel: recorded on the stream instead.
+hipError_t record_empty(hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
+  if (e0) (void)hipEventRecord(e0, s);
+  if (e1) (void)hipEventRecord(e1, s);
+  return hipGetLastError();
+}
+
 // Lanes per node row: S counters of m/16 lanes each (bytes), or of m/64 lanes (5-bit).
 int row_lanes(const PassArgs &a) {
   return (a.packed ? 1 << (a.log2m - 6) : 1 << (a.log2m - 4)) << a.seed_log2;
@@ -2072,13 +2092,13 @@ hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s) {
-  if (!a.trow_ptr) return hipSuccess;
-  hipLaunchKernelGGL(k_sys_list, dim3(grid_for(2 * ((int64_t)a.n_blocks << a.seed_log2), kBlockThreads * kSigRounds, 1 << 30)),
-                     dim3(kBlockThreads), 0, s, a);
+hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!a.trow_ptr) return record_empty(e0, e1, s);
+  launch_k(k_sys_list, dim3(grid_for(2 * ((int64_t)a.n_blocks << a.seed_log2), kBlockThreads * kSigRounds, 1 << 30)),
+           dim3(kBlockThreads), s, e0, nullptr, a);
   hipLaunchKernelGGL(k_sys_mark, dim3(grid_for(arcs, kMarkTile, 2048)), dim3(kBlockThreads), 0, s, a);
-  hipLaunchKernelGGL(k_sys_units, dim3(grid_for((int64_t)a.n_chunks + a.n_tiles, kBlockThreads * kSigRounds, 1 << 30)),
-                     dim3(kBlockThreads), 0, s, a);
+  launch_k(k_sys_units, dim3(grid_for((int64_t)a.n_chunks + a.n_tiles, kBlockThreads * kSigRounds, 1 << 30)),
+           dim3(kBlockThreads), s, nullptr, e1, a);
   return hipGetLastError();
 }
 
@@ -2137,22 +2157,23 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
   return hipGetLastError();
 }
 
-hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s) {
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int G = row_lanes(a);
   const dim3 block(kBlockThreads);
-  if (a.n_chunk_wgs + a.n_light_wgs == 0) return hipSuccess;
+  if (a.n_chunk_wgs + a.n_light_wgs == 0 || (!full && !list)) return record_empty(e0, e1, s);
   if (full) {
     const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
     const int32_t list_too = list ? 1 : 0;
+    hipEvent_t end = list ? nullptr : e1;
     switch (u) {
       case 2:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 2>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 2>, grid, block, s, e0, end, a, list_too));
         break;
       case 8:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 8>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 8>, grid, block, s, e0, end, a, list_too));
         break;
       default:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union<F, G, 4>), grid, block, 0, s, a, list_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 4>, grid, block, s, e0, end, a, list_too));
         break;
     }
   }
@@ -2160,46 +2181,47 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
     const int64_t units = (int64_t)a.n_chunks + a.n_tiles;
     const dim3 grid((unsigned)grid_for(units, kBlockThreads / kWave, kListWgs));
     const int32_t full_too = full ? 1 : 0;
+    hipEvent_t start = full ? nullptr : e0;
     switch (u) {
       case 2:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 2>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 2>, grid, block, s, start, e1, a, full_too));
         break;
       case 8:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 8>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 8>, grid, block, s, start, e1, a, full_too));
         break;
       default:
-        HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_union_list<F, G, 4>), grid, block, 0, s, a, full_too));
+        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 4>, grid, block, s, start, e1, a, full_too));
         break;
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const PassArgs &a, hipStream_t s) {
-  if (a.n_fin_wgs == 0) return hipSuccess;
+hipError_t launch_finalize(const PassArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (a.n_fin_wgs == 0) return record_empty(e0, e1, s);
   const int G = row_lanes(a);
-  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_finalize<F, G>), dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), 0,
-                                        s, a));
+  HANF_DISPATCH_FG(a.packed, G, launch_k(k_finalize<F, G>, dim3((unsigned)a.n_fin_wgs), dim3(kBlockThreads), s, e0, e1, a));
   return hipGetLastError();
 }
 
-hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s) {
-  if (!a.packed) return hipSuccess;  // byte rows: the union step wrote them
+hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (!a.packed) return record_empty(e0, e1, s);  // byte rows: the union step wrote them
   const int G = row_lanes(a);
   const int grid = grid_for((int64_t)a.n * G, kBlockThreads, 1 << 30);
-  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_estimate_changed<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a));
+  HANF_DISPATCH_FG(a.packed, G, launch_k(k_estimate_changed<F, G>, dim3(grid), dim3(kBlockThreads), s, e0, e1, a));
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s) {
+hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1) {
   const dim3 grid((unsigned)a.n_reduce_wgs), block(kBlockThreads);
   switch (a.seed_log2) {
-    case 0: hipLaunchKernelGGL(k_reduce_blocks<1>, grid, block, 0, s, a, force); break;
-    case 1: hipLaunchKernelGGL(k_reduce_blocks<2>, grid, block, 0, s, a, force); break;
-    case 2: hipLaunchKernelGGL(k_reduce_blocks<4>, grid, block, 0, s, a, force); break;
-    case 3: hipLaunchKernelGGL(k_reduce_blocks<8>, grid, block, 0, s, a, force); break;
-    case 4: hipLaunchKernelGGL(k_reduce_blocks<16>, grid, block, 0, s, a, force); break;
-    case 5: hipLaunchKernelGGL(k_reduce_blocks<32>, grid, block, 0, s, a, force); break;
+    case 0: launch_k(k_reduce_blocks<1>, grid, block, s, e0, nullptr, a, force); break;
+    case 1: launch_k(k_reduce_blocks<2>, grid, block, s, e0, nullptr, a, force); break;
+    case 2: launch_k(k_reduce_blocks<4>, grid, block, s, e0, nullptr, a, force); break;
+    case 3: launch_k(k_reduce_blocks<8>, grid, block, s, e0, nullptr, a, force); break;
+    case 4: launch_k(k_reduce_blocks<16>, grid, block, s, e0, nullptr, a, force); break;
+    case 5: launch_k(k_reduce_blocks<32>, grid, block, s, e0, nullptr, a, force); break;
     default: return hipErrorInvalidValue;
   }
   if (a.batch.active && a.batch.n_comp > 0) {
@@ -2207,7 +2229,7 @@ hipError_t launch_reduce(const PassArgs &a, int32_t mode, int32_t force, hipStre
     hipLaunchKernelGGL(k_reduce_components, dim3(grid_for(a.batch.n_comp, kBlockThreads, 1 << 30)),
                        dim3(kBlockThreads), 0, s, a, mode);
   }
-  hipLaunchKernelGGL(k_reduce_top, dim3(1), dim3(kTopThreads), 0, s, a, mode);
+  launch_k(k_reduce_top, dim3(1), dim3(kTopThreads), s, nullptr, e1, a, mode);
   return hipGetLastError();
 }
 
