@@ -699,11 +699,19 @@ int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
   }
   hipError_t e = launch_in_degrees(c->trp, c->ci, n, arcs, deg, c->stream);
   if (e == hipSuccess) e = launch_order_select(deg, n, K, hist, plan, counts, tmp, c->perm, c->inv, c->stream);
+  int32_t lstar = 0;  // kOrderLevels: no class of in-degree fits under K, the order is the caller's
+  if (e == hipSuccess) e = hipMemcpyAsync(&lstar, plan, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   dev_release(c, deg);
   dev_release(c, hist);
   dev_release(c, plan);
   dev_release(c, counts);
   dev_release(c, tmp);
+  if (e == hipSuccess && lstar >= kOrderLevels) {
+    dev_release(c, c->perm);
+    dev_release(c, c->inv);
+    return HANF_OK;
+  }
   int32_t *rp_new = nullptr, *ci_new = nullptr, *trp_new = nullptr, *tci_new = nullptr;
   if (e != hipSuccess) rc = hip_fail(c, e, "node order");
   if (!rc) rc = permute_graph(c, c->rp, c->ci, &rp_new, &ci_new);
