@@ -46,8 +46,8 @@ def algorithmic_bytes(rec, n, m):
 def measured_traffic(workload):
     """HBM bytes per union launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded
     under profiles/ (`workload` with a `_packed5` suffix for 5-bit registers and `_hubs` for
-    the hubs-first node order), or None when the kernel source changed since they were taken
-    or no such run was recorded."""
+    the hubs-first node order from the first run, --opt hubs=K), or None when the kernel
+    source changed since they were taken or no such run was recorded."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", f"k_union_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_1011_5599_amd", "csrc", "hanf_kernels.hip")
@@ -536,7 +536,7 @@ def main():
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4),
                         traffic=measured_traffic(args.workload + ("_packed5" if packed else "")
-                                                 + ("_hubs" if opts.get("hubs", 0) != 0 else "")),
+                                                 + ("_hubs" if opts.get("hubs", -1) > 0 else "")),
                         kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
                         avg_launch_us=round(1000.0 * union_ms / launches, 2),
                         avg_algorithmic_bytes=int(byts / launches))

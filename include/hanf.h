@@ -84,8 +84,7 @@ extern "C" {
                                    holds at least 512 registers (m >= 64 and seeds side by side
                                    in a batch), else one per byte. Results are identical; register
                                    I/O stays one byte per register */
-#define HANF_OPT_HUBS 12        /* node order of a single graph, chosen at the first
-                                   hanf_init_counters after ingest (a layout choice: every
+#define HANF_OPT_HUBS 12        /* node order of a single graph (a layout choice: every
                                    register, N_hat(t) up to the order of its sum, and T are those
                                    of the caller's order, and all I/O stays in the caller's node
                                    ids). K > 0: the K nodes with the largest in-degree (the
@@ -93,15 +92,17 @@ extern "C" {
                                    class of in-degree (8 per octave, largest first) and id, fewer
                                    when a class would cross K; every other node after them in id
                                    order. Their rows then share cache lines and stay in one XCD's
-                                   L2. In-degrees come from the transposed graph if one is set,
-                                   else from a count of col_idx. Choosing the order rewrites the
-                                   graph, which costs about one pass over every node (one random
-                                   read per arc), once per ingest; later hanf_init_counters on the
-                                   same graph reuse it. It pays when the passes over every node
-                                   it speeds up outnumber that (several runs on one loaded graph,
-                                   or long runs). 0 (default): the caller's order. -1: K = 4 MiB /
-                                   row bytes (65536 at m = 64) for graphs of at least 16 K nodes
-                                   with a transposed graph, else the caller's order */
+                                   L2: passes over every node run about 18% faster. In-degrees
+                                   come from the transposed graph if one is set, else from a
+                                   count of col_idx. Choosing the order rewrites the graph, which
+                                   costs about one pass over every node (one random read per
+                                   arc), once per ingest; K > 0 chooses it at the first
+                                   hanf_init_counters after ingest. -1 (default): K = 4 MiB / row
+                                   bytes (65536 at m = 64), for graphs of at least 16 K nodes
+                                   with a transposed graph, chosen at the second
+                                   hanf_init_counters on the same ingest (a single run keeps the
+                                   caller's order; from the second run on, the rewrite pays for
+                                   itself). 0: the caller's order */
 
 /* Tuning and test options (the results never change):
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
@@ -245,8 +246,9 @@ int hanf_read_estimates(hanf_ctx *ctx, double *out, int64_t count, uint32_t flag
 
 /* The node order the library runs a single graph in (HANF_OPT_HUBS): out[i] = the caller's
  * id of the node whose counter is the library's row i (count = n int32, host or device per
- * flags). The identity until the first hanf_init_counters after ingest chooses the order,
- * and when that order is the caller's. HANF_EINVAL for batches or a wrong count. */
+ * flags). The identity until the initialisation that chooses the order (the first after
+ * ingest with K > 0, the second with -1), and when that order is the caller's. HANF_EINVAL
+ * for batches or a wrong count. */
 int hanf_read_order(hanf_ctx *ctx, int32_t *out, int32_t count, uint32_t flags);
 
 /* Resumes from a checkpoint: counters `in` (n*m bytes, layout of hanf_read_registers,

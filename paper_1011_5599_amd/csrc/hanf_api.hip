@@ -71,7 +71,7 @@ struct hanf_ctx {
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   int tp_counting = 0;   // 1: build transposes by per-node counters even below kTpMaxNodes
-  int64_t hubs_opt = 0;  // HANF_OPT_HUBS: -1 auto, 0 the caller's order, K: up to K hubs first
+  int64_t hubs_opt = -1; // HANF_OPT_HUBS: -1 auto, 0 the caller's order, K: up to K hubs first
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
@@ -86,7 +86,8 @@ struct hanf_ctx {
   int32_t *trp_own = nullptr, *tci_own = nullptr;
   // node order chosen at the first initialisation after ingest (single graphs): the graph
   // and its transpose above are then in that order, row v holding the caller's node perm[v]
-  bool ordered = false;
+  bool ordered = false;  // the order of this ingest is decided
+  int32_t inits = 0;     // initialisations since ingest
   int32_t *perm = nullptr, *inv = nullptr;  // new id -> caller's id, and back; NULL: the same
 
   Schedule sch;
@@ -303,6 +304,7 @@ void free_graph(hanf_ctx *c) {
   dev_release(c, c->perm);
   dev_release(c, c->inv);
   c->ordered = false;
+  c->inits = 0;
   dev_release(c, c->rp_own);
   dev_release(c, c->ci_own);
   dev_release(c, c->blk_comp);
@@ -665,7 +667,9 @@ constexpr int64_t kHubCacheBytes = 4 << 20;
 // Chooses the node order of a single graph once per ingest (HANF_OPT_HUBS): with K > 0,
 // hubs first (by class of in-degree, then id) and the other nodes after them in id order;
 // the graph and its transpose are rewritten in that order. Auto: K rows fill kHubCacheBytes,
-// for graphs with at least 16 K nodes whose transposed graph gives the in-degrees.
+// for graphs with at least 16 K nodes whose transposed graph gives the in-degrees, chosen
+// at the second initialisation on the ingest (the rewrite costs about one pass over every
+// node, which a second run already earns back; a single run keeps the caller's order).
 int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
   c->ordered = true;
   const int32_t n = c->n;
@@ -1377,10 +1381,11 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   // lanes per node row: 16 byte registers or 64 packed ones per lane
   const int G = (packed ? 1 << (log2m - 6) : 1 << (log2m - 4)) << sl;
   const int lane_bytes = packed ? kPacked5LaneBytes : 16;
-  if (!c->batch && !c->ordered) {
+  if (!c->batch && !c->ordered && (c->hubs_opt >= 0 || c->inits > 0)) {
     if ((rc = order_nodes(c, log2m, packed))) return rc;
-    free_schedule(c);  // built on the caller's order, if at all
+    if (c->perm) free_schedule(c);  // built on the caller's order
   }
+  ++c->inits;
   Schedule want;
   choose_schedule(c, G, lane_bytes, want);
   if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
