@@ -98,7 +98,9 @@ extern "C" {
                                    costs about one pass over every node (one random read per
                                    arc), once per ingest; K > 0 chooses it at the first
                                    hanf_init_counters after ingest. -1 (default): K = 4 MiB / row
-                                   bytes (65536 at m = 64), for graphs of at least 16 K nodes
+                                   bytes (65536 at m = 64) when rows are shorter than a 128-byte
+                                   L2 line (m <= 64 in bytes, m <= 128 packed: longer rows share
+                                   no lines and gain nothing), for graphs of at least 16 K nodes
                                    with a transposed graph, chosen at the second
                                    hanf_init_counters on the same ingest (a single run keeps the
                                    caller's order; from the second run on, the rewrite pays for

@@ -663,11 +663,15 @@ int permute_graph(hanf_ctx *c, const int32_t *rp, const int32_t *ci, int32_t **r
 
 // Rows of the K most-read counters (the hubs: largest in-degree) fit one XCD's L2 together.
 constexpr int64_t kHubCacheBytes = 4 << 20;
+// The order gains only where rows are shorter than an L2 line (hubs then share lines); at a
+// line or more per row, passes over every node run no faster (measured at m = 128).
+constexpr int64_t kL2LineBytes = 128;
 
 // Chooses the node order of a single graph once per ingest (HANF_OPT_HUBS): with K > 0,
 // hubs first (by class of in-degree, then id) and the other nodes after them in id order;
 // the graph and its transpose are rewritten in that order. Auto: K rows fill kHubCacheBytes,
-// for graphs with at least 16 K nodes whose transposed graph gives the in-degrees, chosen
+// for rows shorter than an L2 line and graphs with at least 16 K nodes whose transposed
+// graph gives the in-degrees, chosen
 // at the second initialisation on the ingest (the rewrite costs about one pass over every
 // node, which a second run already earns back; a single run keeps the caller's order).
 int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
@@ -676,8 +680,9 @@ int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
   const int64_t arcs = c->arcs;
   int64_t K = c->hubs_opt;
   if (K < 0) {
-    K = kHubCacheBytes / (int64_t)row_bytes(log2m, 0, packed);
-    if (!c->trp || (int64_t)n < 16 * K) K = 0;
+    const int64_t rb = (int64_t)row_bytes(log2m, 0, packed);
+    K = kHubCacheBytes / rb;
+    if (!c->trp || rb >= kL2LineBytes || (int64_t)n < 16 * K) K = 0;
   }
   K = std::min<int64_t>(K, n);
   if (K == 0 || arcs == 0) return HANF_OK;

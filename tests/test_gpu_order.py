@@ -209,33 +209,37 @@ def test_transpose_loaded_after_the_order():
 
 
 def test_auto_order_on_a_large_graph():
-    """The default order (auto) on a symmetric R-MAT of 2^18 nodes at m = 256: the first run
+    """The default order (auto) on a symmetric R-MAT of 2^20 nodes at m = 64: the first run
     on an ingest keeps the caller's order (bit for bit the run with the order off); the
-    second initialisation chooses 16384 hubs by definition, with the same registers,
-    estimates, N_hat and T as the caller's order; a new ingest starts over."""
+    second initialisation chooses 65536 hubs by definition, with the same registers,
+    estimates, N_hat and T as the caller's order; a new ingest starts over. At m = 128 (a
+    row per 128-byte line) auto keeps the caller's order."""
     import torch
-    rp, ci = graphgen.rmat(18, 1 << 22, symmetric=True, seed=64)
+    rp, ci = graphgen.rmat(20, 1 << 23, symmetric=True, seed=64)
     n = len(rp) - 1
     drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
-    want, hubs = expected_order(np.diff(rp), 16384)
+    want, hubs = expected_order(np.diff(rp), 65536)
     _flush(f"[order] auto n={n} arcs={len(ci)} hubs={hubs}")
     with hanf.HyperANF(0) as a, hanf.HyperANF(0, hubs=0) as p:
-        p.load(drp, dci).transpose_self().init(8, 5)
+        p.load(drp, dci).transpose_self().init(6, 5)
         npl = p.run()
         regs_p, est_p = p.registers(), p.estimates()
-        a.load(drp, dci).transpose_self().init(8, 5)
+        a.load(drp, dci).transpose_self().init(6, 5)
         assert np.array_equal(a.order(), np.arange(n))
         assert np.array_equal(a.run(), npl)
-        a.init(8, 5)  # the second run on this ingest: the order is chosen now
+        a.init(6, 5)  # the second run on this ingest: the order is chosen now
         assert np.array_equal(a.order(), want)
         na = a.run()
         assert len(na) == len(npl)
         np.testing.assert_allclose(na, npl, rtol=RTOL, atol=0)
         assert np.array_equal(a.registers(), regs_p)
         assert np.array_equal(a.estimates(), est_p)
-        a.init(8, 6)  # kept for later runs
+        a.init(6, 6)  # kept for later runs
         assert np.array_equal(a.order(), want)
-        a.load(drp, dci).transpose_self().init(8, 5)  # a new ingest
+        a.load(drp, dci).transpose_self().init(6, 5)  # a new ingest
+        assert np.array_equal(a.order(), np.arange(n))
+        a.load(drp, dci).transpose_self().init(7, 5)
+        a.init(7, 5)  # m = 128: rows fill a line, no order
         assert np.array_equal(a.order(), np.arange(n))
 
 
