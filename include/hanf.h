@@ -17,11 +17,14 @@
  *   - The caller owns every buffer it passes in or receives into; the library owns the
  *     device memory it allocates and the context handle.
  *   - Work is ordered on the context's HIP stream. Calls that hand results to the
- *     host (hanf_iterate, hanf_read_*, hanf_stats, hanf_load_csr) synchronise that
- *     stream before returning.
+ *     host (hanf_iterate, hanf_read_*, hanf_stats, hanf_load_csr) return complete
+ *     results: they synchronise that stream, unless nothing was queued since the values
+ *     were last read with the run state (then they are served from that read).
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - Device pointers are HIP device addresses on the context's device (for instance
- *     torch.Tensor.data_ptr() of a tensor on that device).
+ *     torch.Tensor.data_ptr() of a tensor on that device). Buffers passed with
+ *     HANF_DEVICE_PTRS that are not device memory of that device are refused with
+ *     HANF_EINVAL before any kernel touches them.
  */
 #ifndef HANF_H
 #define HANF_H
