@@ -1855,6 +1855,8 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
   if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   const int64_t arcs = arc_off[n_graphs];
   if (arcs > 0 && !col_idx) return fail(c, HANF_EINVAL, "col_idx is NULL");
+  if (flags == HANF_DEVICE_PTRS && (!device_pointer(c, row_ptr) || (arcs > 0 && !device_pointer(c, col_idx))))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: pointer is not device memory of this device");
   if (arc_off[0] != 0 || arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
   if ((int64_t)n_graphs * n_seeds >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "too many components");
   if (graph_off[0] != 0) return fail(c, HANF_EINVAL, "graph_off[0] must be 0");
@@ -1977,6 +1979,9 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
   std::vector<int32_t> goff((size_t)n_graphs + 1), aoff((size_t)n_graphs + 1);
   int64_t nacc = 0, aacc = 0;
   for (int32_t g = 0; g < n_graphs; ++g) {
+    if (flags == HANF_DEVICE_PTRS && row_ptrs[g] &&
+        (!device_pointer(c, row_ptrs[g]) || (n_arcs[g] > 0 && col_idxs[g] && !device_pointer(c, col_idxs[g]))))
+      return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: pointer is not device memory of this device");
     if (n_nodes[g] < 1 || n_arcs[g] < 0 || !row_ptrs[g] || (n_arcs[g] > 0 && !col_idxs[g]))
       return fail(c, HANF_EINVAL, "every graph needs at least one node and its arrays");
     goff[g] = (int32_t)nacc;
@@ -2115,6 +2120,9 @@ int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t b
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_registers: NULL context");
   if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
   if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
   const int32_t row = c->comp_row_h[comp];
   const int32_t L = row >> c->sl, j = row & ((1 << c->sl) - 1);
   const size_t m = (size_t)1 << c->log2m, R = row_bytes(c->log2m, c->sl, c->packed);
@@ -2157,6 +2165,9 @@ int hanf_batch_read_estimates(hanf_ctx *c, int32_t comp, double *out, int64_t co
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_read_estimates: NULL context");
   if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
   if (comp < 0 || comp >= c->n_comp || !out) return fail(c, HANF_EINVAL, "bad component or out");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, out))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: out is not device memory of this device");
   const int32_t row = c->comp_row_h[comp];
   const int32_t L = row >> c->sl, j = row & ((1 << c->sl) - 1);
   const size_t S = (size_t)1 << c->sl;

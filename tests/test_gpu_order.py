@@ -276,3 +276,11 @@ def test_order_errors():
         with pytest.raises(hanf.HanfError) as e:
             hanf.hanf_read_order(bt.ctx, 100)
         assert e.value.code == hanf.HANF_EINVAL
+        # batch reads refuse host buffers passed as device memory, too
+        lib = hanf.lib()
+        regs = np.empty(100 * 16, np.uint8)
+        assert lib.hanf_batch_read_registers(bt.ctx, 0, regs.ctypes.data, regs.size,
+                                             hanf.HANF_DEVICE_PTRS) == hanf.HANF_EINVAL
+        est = np.empty(100, np.float64)
+        assert lib.hanf_batch_read_estimates(bt.ctx, 0, est.ctypes.data, 100, hanf.HANF_DEVICE_PTRS) == hanf.HANF_EINVAL
+        assert bt.registers(0).shape == (100, 16) and bt.estimates(0).shape == (100,)  # still usable
