@@ -166,7 +166,8 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out);
 /* Releases every device allocation of the context. Safe on NULL and after errors. */
 void hanf_destroy(hanf_ctx *ctx);
 
-/* Sets one HANF_OPT_* option. Schedule options take effect at the next hanf_load_csr. */
+/* Sets one HANF_OPT_* option. Schedule options take effect at the next initialisation
+ * (hanf_init_counters / hanf_init_batch), which rebuilds the schedule when they changed. */
 int hanf_set_option(hanf_ctx *ctx, int option, int64_t value);
 
 /* Graph ingest (the graph G of Section 3.2, as successor lists). CSR: the successors of
@@ -175,8 +176,9 @@ int hanf_set_option(hanf_ctx *ctx, int option, int64_t value);
  * row_ptr[n] = arcs, 0 <= col_idx[a] < n (HANF_EINVAL otherwise). Duplicate arcs and
  * self-loops are allowed and change nothing. With HANF_HOST_PTRS the arrays are copied;
  * with HANF_DEVICE_PTRS they are borrowed and must stay alive and unchanged until the
- * context is destroyed or another graph is loaded. Builds the degree-aware work
- * schedule on the device. Discards any previous run state. */
+ * context is destroyed or another graph is loaded. The degree-aware work schedule is
+ * built on the device at the next initialisation (it depends on m). Discards any
+ * previous run state. */
 int hanf_load_csr(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr,
                   const int32_t *col_idx, uint32_t flags);
 
