@@ -134,6 +134,8 @@ struct hanf_ctx {
   bool st_fresh = false;  // st_host equals the device state: nothing queued since could change it
   double *nt_host = nullptr;  // pinned: N_hat(0 .. nt_host_len - 1), read with the state
   int32_t nt_host_len = 0;
+  std::vector<int32_t> comp_T_host;  // batches: every component's fixpoint, read with the state
+  bool comp_T_fresh = false;         // valid while st_fresh also holds
   DevState *st_poll = nullptr;  // pinned, written by the copy hanf_enqueue leaves on the stream
   PassLog *log_host = nullptr;  // pinned, kMaxPassesPerCheck records read with the state
   hipEvent_t poll_ev = nullptr;
@@ -352,6 +354,7 @@ int sync(hanf_ctx *c, const char *what) {
 
 int read_state(hanf_ctx *c) {
   c->st_fresh = false;
+  c->comp_T_fresh = false;
   HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
           "state read");
   const int rc = sync(c, "state read");
@@ -393,6 +396,23 @@ void mirror_state_reset(hanf_ctx *c, int32_t t, int32_t max_passes, int64_t dens
   s.sys_acc = 0ull;
   s.sys_units = 0;
   c->st_fresh = true;
+  c->comp_T_fresh = false;
+}
+
+// Batches: the run state and every component's fixpoint T, from the device unless the host
+// copies are current (one wait for all the components a caller then reads).
+int batch_state(hanf_ctx *c) {
+  if (c->st_fresh && c->comp_T_fresh && (int32_t)c->comp_T_host.size() == c->n_comp) return HANF_OK;
+  c->st_fresh = false;
+  c->comp_T_fresh = false;
+  c->comp_T_host.resize((size_t)c->n_comp);
+  HIP_TRY(c, hipMemcpyAsync(c->comp_T_host.data(), c->comp_T, sizeof(int32_t) * c->n_comp, hipMemcpyDeviceToHost,
+                            c->stream),
+          "fixpoint read");
+  HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream), "state read");
+  const int rc = sync(c, "state read");
+  c->st_fresh = c->comp_T_fresh = rc == HANF_OK;
+  return rc;
 }
 
 // Default schedule parameters for G lanes per counter (W = 64/G slots per wavefront).
@@ -1540,6 +1560,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
               "history read");
     if ((rc = sync(c, "state read"))) return rc;
     c->st_fresh = true;
+    c->comp_T_fresh = false;
     if (!c->batch) c->nt_host_len = std::min(c->st_host->t + 1, nt_cnt);
     const int32_t ran = c->st_host->passes - s0.passes;
     if (ran > cnt) return fail(c, HANF_EDEVICE, "more passes recorded than enqueued");
@@ -2102,10 +2123,9 @@ int hanf_batch_read_nt(hanf_ctx *c, int32_t comp, double *out, int32_t cap, int3
   if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
   if (comp < 0 || comp >= c->n_comp || !len) return fail(c, HANF_EINVAL, "bad component or len");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  int32_t Tc = -1;
-  HIP_TRY(c, hipMemcpyAsync(&Tc, c->comp_T + comp, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "fixpoint read");
   int rc;
-  if ((rc = read_state(c))) return rc;
+  if ((rc = batch_state(c))) return rc;
+  const int32_t Tc = c->comp_T_host[(size_t)comp];
   const int32_t have = (Tc >= 0 ? Tc : c->st_host->t) + 1;
   *len = have;
   if (cap < have) return fail(c, HANF_ERANGE, "output capacity below the history length");
@@ -2131,7 +2151,7 @@ int hanf_batch_read_registers(hanf_ctx *c, int32_t comp, uint8_t *out, int64_t b
   if (bytes != (int64_t)ng * (int64_t)m) return fail(c, HANF_EINVAL, "bytes must be n_graph * m");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
   int rc;
-  if ((rc = read_state(c))) return rc;
+  if ((rc = current_state(c))) return rc;
   // counter j of every row of the component's nodes: a strided copy (unpacked on the device)
   const uint8_t *src = c->regs[c->st_host->t & 1] + (size_t)c->lay_node_off_h[L] * R + (size_t)j * cb;
   if (!c->packed) {
