@@ -1,0 +1,165 @@
+"""The serving loop's host policy without a GPU: admission by device footprint, batches of
+one register count, first-come order, per-request completion inside a batch, memory
+returned when a batch ends, and contexts kept for later batches. The device calls are
+replaced by a stand-in batch whose fixpoints the test sets by hand; the footprints are
+the library's own (`hanf_footprint` is a host function)."""
+import numpy as np
+import pytest
+
+from paper_1011_5599_amd import HANF_BUSY, HANF_DONE, HANF_OK
+from paper_1011_5599_amd import serve
+
+
+class FakeBatch:
+    made = []
+
+    def __init__(self, device, **options):
+        self.ctx = self
+        self.enqueued = 0
+        self.loads = []
+        FakeBatch.made.append(self)
+
+    def load_graphs(self, graphs, seeds_per_graph):
+        assert seeds_per_graph == 1
+        self.graphs = graphs
+        self.loads.append(len(graphs))
+
+    def init(self, log2m, seeds):
+        self.log2m, self.seeds = log2m, list(seeds)
+        self.T = [-1] * len(seeds)
+        self.status = HANF_BUSY
+
+    def close(self):
+        pass
+
+
+@pytest.fixture
+def fake(monkeypatch):
+    FakeBatch.made = []
+    monkeypatch.setattr(serve, "Batch", FakeBatch)
+
+    def enqueue(ctx, passes):
+        ctx.enqueued += passes
+        ctx.status = HANF_BUSY
+
+    monkeypatch.setattr(serve, "hanf_enqueue", enqueue)
+    monkeypatch.setattr(serve, "hanf_poll", lambda ctx: (ctx.status, 0))
+    monkeypatch.setattr(serve, "hanf_batch_info", lambda ctx: (None, np.array(ctx.T)))
+    monkeypatch.setattr(serve, "hanf_batch_stats_all",
+                        lambda ctx: {"spid": np.arange(len(ctx.seeds), dtype=np.float64)})
+    monkeypatch.setattr(serve, "hanf_batch_read_nt",
+                        lambda ctx, c: np.arange(max(ctx.T[c], 0) + 1, dtype=np.float64))
+    return FakeBatch
+
+
+def ring(n):
+    row_ptr = np.arange(n + 1, dtype=np.int32)
+    col_idx = ((np.arange(n) + 1) % n).astype(np.int32)
+    return row_ptr, col_idx
+
+
+def req(rid, n=1000, log2m=6):
+    rp, ci = ring(n)
+    return serve.Request(rid, rp, ci, log2m, seed=rid + 1)
+
+
+def finish(bt, comps, T=3, done=False):
+    for c in comps:
+        bt.T[c] = T
+    bt.status = HANF_DONE if done else HANF_OK
+
+
+def test_footprint_is_the_library_figure_plus_the_graph_copy():
+    r = req(0, n=1000)
+    assert serve.footprint(r) > 2 * 1024 * 64       # two register arrays at least
+    assert serve.footprint(req(1, n=1000, log2m=8)) > serve.footprint(r)
+    assert serve.footprint(req(2, n=4000)) > serve.footprint(r)
+
+
+def test_admits_within_the_budget_and_keeps_the_rest_waiting(fake):
+    fp = serve.footprint(req(0))
+    srv = serve.Server(hbm_budget=3 * fp + fp // 2)
+    for i in range(5):
+        srv.submit(req(i))
+    srv.pump()
+    assert len(srv.flights) == 1
+    assert [r.rid for r in srv.flights[0].requests] == [0, 1, 2]
+    assert srv.used == 3 * fp <= srv.budget
+    assert [r.rid for r in srv.waiting] == [3, 4]
+    assert all(r.admitted is not None for r in srv.flights[0].requests)
+
+
+def test_a_batch_holds_one_register_count(fake):
+    srv = serve.Server(hbm_budget=1 << 30)
+    for i, b in enumerate([6, 4, 6, 8, 4]):
+        srv.submit(req(i, log2m=b))
+    srv.pump()
+    groups = [[r.rid for r in fl.requests] for fl in srv.flights]
+    assert groups == [[0, 2], [1, 4], [3]]
+    assert [fl.batch.log2m for fl in srv.flights] == [6, 4, 8]
+    assert [fl.batch.seeds for fl in srv.flights] == [[1, 3], [2, 5], [4]]
+
+
+def test_batch_caps(fake):
+    srv = serve.Server(hbm_budget=1 << 30, max_batches=2, max_batch_requests=2)
+    for i in range(7):
+        srv.submit(req(i))
+    srv.pump()
+    assert [[r.rid for r in fl.requests] for fl in srv.flights] == [[0, 1], [2, 3]]
+    assert [r.rid for r in srv.waiting] == [4, 5, 6]
+
+
+def test_the_oldest_request_is_not_passed_by_smaller_ones(fake):
+    big, small = req(0, n=20000), req(1, n=100)
+    fp_big, fp_small = serve.footprint(big), serve.footprint(small)
+    srv = serve.Server(hbm_budget=fp_big + fp_small // 2)
+    first = req(9, n=100)
+    srv.submit(first)
+    srv.pump()                                     # the first small one takes some memory
+    assert srv.used == fp_small
+    srv.submit(big)
+    srv.submit(small)
+    srv.pump()                                     # the big one does not fit yet: nothing else enters
+    assert len(srv.flights) == 1 and [r.rid for r in srv.waiting] == [0, 1]
+    finish(srv.flights[0].batch, [0], done=True)
+    srv.pump()                                     # admission runs before the poll: memory back
+    assert [r.rid for r in srv.done] == [9] and srv.used == 0 and srv.flights == []
+    srv.pump()                                     # the big one enters first
+    assert [[r.rid for r in fl.requests] for fl in srv.flights] == [[0]]
+    assert [r.rid for r in srv.waiting] == [1]
+
+
+def test_requests_finish_one_by_one_and_memory_returns_with_the_batch(fake):
+    fp = serve.footprint(req(0))
+    srv = serve.Server(hbm_budget=1 << 30, passes_per_poll=3)
+    for i in range(3):
+        srv.submit(req(i))
+    srv.pump()
+    (fl,) = srv.flights
+    bt = fl.batch
+    assert bt.enqueued == 3
+    assert srv.pump() == []                        # passes still in flight
+    finish(bt, [1], T=4)                           # one component at its fixpoint
+    out = srv.pump()
+    assert [r.rid for r in out] == [1]
+    assert out[0].T == 4 and list(out[0].nt) == [0, 1, 2, 3, 4] and out[0].stats == {"spid": 1.0}
+    assert out[0].finish is not None and out[0].latency is not None
+    assert fl.open == {0, 2} and srv.used == 3 * fp
+    assert bt.enqueued == 6                        # the rest keep going
+    finish(bt, [0, 2], T=2, done=True)
+    out = srv.pump()
+    assert sorted(r.rid for r in out) == [0, 2]
+    assert srv.used == 0 and srv.flights == [] and srv.idle()
+    assert srv.idle_batches == [bt]
+    srv.submit(req(3))
+    srv.pump()                                     # the context is reused, not made again
+    assert srv.flights[0].batch is bt and len(FakeBatch.made) == 1
+    assert bt.loads == [3, 1]
+
+
+def test_a_request_larger_than_the_budget_is_refused(fake):
+    r = req(0, n=5000)
+    srv = serve.Server(hbm_budget=serve.footprint(r) - 1)
+    with pytest.raises(ValueError):
+        srv.submit(r)
+    assert srv.idle()
