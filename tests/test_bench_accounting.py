@@ -1,0 +1,64 @@
+"""bench.py's byte accounting without a GPU: the algorithmic bytes of a pass follow the
+per-unit figures (arc 4 B, counter m B, row_ptr 4 B per node, one flag bit read and one
+written per node of a pass over every node, two row_ptr entries per node a systolic pass
+visits), and measured HBM traffic is reported only for the kernel source it was taken
+on."""
+import hashlib
+import importlib.util
+import json
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_dense_pass_at_full_size(bench):
+    # symmetric R-MAT scale 22, 64 registers: every arc scanned and gathered, every own
+    # counter read and every new counter written
+    n, e, m = 1 << 22, 1 << 26, 64
+    rec = {"arcs_scanned": e, "arcs_gathered": e, "rows_read": n, "rows_written": n}
+    want = 4 * (n + 1) + 4 * e + m * e + m * n + m * n + n // 4
+    assert bench.algorithmic_bytes(rec, n, m) == want == 5_118_099_460
+
+
+def test_each_unit_counts_once(bench):
+    n, m = 1000, 128
+    base = {"arcs_scanned": 10, "arcs_gathered": 7, "rows_read": 5, "rows_written": 3}
+    b0 = bench.algorithmic_bytes(base, n, m)
+    for key, per_unit in [("arcs_scanned", 4), ("arcs_gathered", m), ("rows_read", m), ("rows_written", m)]:
+        rec = dict(base, **{key: base[key] + 1})
+        assert bench.algorithmic_bytes(rec, n, m) - b0 == per_unit, key
+    # nodes of a pass over every node: row_ptr (4 B) and a quarter byte of flags each
+    assert bench.algorithmic_bytes(base, n + 4, m) - b0 == 4 * 4 + 1
+
+
+def test_systolic_pass_counts_only_visited_nodes(bench):
+    n, m = 1 << 20, 64
+    rec = {"systolic": True, "arcs_scanned": 100, "arcs_gathered": 60, "rows_read": 9, "rows_written": 4}
+    assert bench.algorithmic_bytes(rec, n, m) == 8 * 9 + 4 * 100 + m * (60 + 9 + 4)
+    assert bench.algorithmic_bytes(rec, 2 * n, m) == bench.algorithmic_bytes(rec, n, m)
+
+
+def test_traffic_only_for_the_profiled_kernel_source(bench, tmp_path, monkeypatch):
+    src_dir = tmp_path / "paper_1011_5599_amd" / "csrc"
+    src_dir.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    src = src_dir / "hanf_kernels.hip"
+    src.write_text("// kernels as profiled\n")
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    rec = {"kernel_source_sha256": sha, "traffic_bytes_per_launch": 1234}
+    (tmp_path / "profiles" / "k_union_w_traffic.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("w") == 1234
+    assert bench.measured_traffic("other") is None          # no counter run recorded
+    src.write_text("// kernels changed since\n")
+    assert bench.measured_traffic("w") is None
