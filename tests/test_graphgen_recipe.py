@@ -1,0 +1,104 @@
+"""The seeded input generators against their recipe, on the CPU at small sizes: valid CSR
+with sorted successor lists and no duplicates or self-loops, exact arc counts, symmetric
+R-MAT equal to its own transpose, R-MAT skew, the web-like graph's out-degree law after
+duplicate removal, its local arcs and its power-law in-degree of the inter-host arcs, and
+determinism under the graph seed."""
+import numpy as np
+import pytest
+
+import graphgen
+
+
+def check_csr(rp, ci):
+    n = len(rp) - 1
+    assert rp[0] == 0 and rp[-1] == len(ci) and np.all(np.diff(rp) >= 0)
+    assert len(ci) == 0 or (ci.min() >= 0 and ci.max() < n)
+    src = np.repeat(np.arange(n), np.diff(rp))
+    assert not np.any(src == ci), "self-loop"
+    same_row = src[1:] == src[:-1]
+    assert np.all(ci[1:][same_row] > ci[:-1][same_row]), "successors not strictly increasing"
+    return n, src
+
+
+def test_rmat_directed():
+    rp, ci = graphgen.rmat(14, 1 << 18, seed=14)
+    n, _ = check_csr(rp, ci)
+    assert n == 1 << 14 and len(ci) == 1 << 18
+    deg = np.diff(rp)
+    assert deg.max() > 50 * deg.mean()          # (a,b,c,d) = (.57,.19,.19,.05): heavy hubs
+    rp2, ci2 = graphgen.rmat(14, 1 << 18, seed=14)
+    assert np.array_equal(rp, rp2) and np.array_equal(ci, ci2)
+    rp3, ci3 = graphgen.rmat(14, 1 << 18, seed=15)
+    assert not np.array_equal(ci, ci3)
+
+
+def test_rmat_symmetric_is_its_own_transpose():
+    rp, ci = graphgen.rmat(12, 1 << 15, symmetric=True, seed=3)
+    n, src = check_csr(rp, ci)
+    assert len(ci) == 2 << 15
+    fwd = np.sort(src.astype(np.int64) * n + ci)
+    bwd = np.sort(ci.astype(np.int64) * n + src)
+    assert np.array_equal(fwd, bwd)
+
+
+def test_rmat_node_cap_rejects_far_endpoints():
+    rp, ci = graphgen.rmat(10, 8000, seed=9, n=700)
+    n, _ = check_csr(rp, ci)
+    assert n == 700 and len(ci) == 8000
+
+
+def test_erdos_renyi_exact_arc_count():
+    rp, ci = graphgen.erdos_renyi(3000, 24000, seed=5)
+    n, _ = check_csr(rp, ci)
+    assert n == 3000 and len(ci) == 24000
+    deg = np.diff(rp)
+    assert abs(deg.var() / deg.mean() - 1.0) < 0.15    # binomial out-degrees: variance ~ mean
+
+
+@pytest.fixture(scope="module")
+def web16():
+    return graphgen.web(1 << 16, seed=5)
+
+
+def test_web_out_degree_law_after_dedupe(web16):
+    rp, ci = web16
+    n, _ = check_csr(rp, ci)
+    deg = np.diff(rp)
+    assert abs(deg.mean() - 20.0) < 0.5                 # LogNormal with mean 20
+    logs = np.log(deg[deg > 0])
+    assert abs(logs.std() - 1.0) < 0.05                 # sigma 1
+    assert abs(logs.mean() - (np.log(20.0) - 0.5)) < 0.05
+
+
+def test_web_local_and_power_law_arcs(web16):
+    rp, ci = web16
+    n = len(rp) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    dist = np.abs(ci.astype(np.int64) - src)
+    near = (dist <= 64).mean()
+    # Intra-host with probability 0.8 per draw; a duplicate target is drawn again with a
+    # new intra/inter choice, and nearby ids repeat far more often than power-law targets,
+    # so a little over half of the kept arcs are local.
+    assert 0.5 < near < 0.6
+    # local arcs stay within a few ids: between 64 and 256 only the inter-host arcs that
+    # land there by chance (about 384/n of them)
+    assert (dist <= 256).mean() - near < 0.01
+    # Inter-host targets: weight rank^(-1/(gamma-1)) with gamma = 2.1 (Chung-Lu), so the
+    # r-th largest in-degree from inter-host arcs is about inter * r^(-1/1.1) / sum_k k^(-1/1.1).
+    # Ranks 30..1000: past the top few, whose in-degree saturates at one arc per source.
+    local = dist <= 64
+    inter_in = np.sort(np.bincount(ci[~local], minlength=n))[::-1]
+    inter = int((~local).sum())
+    ex = -1 / 1.1
+    norm = np.sum(np.arange(1, n + 1, dtype=np.float64) ** ex)
+    r = np.arange(30, 1001)
+    slope = np.polyfit(np.log(r), np.log(inter_in[r - 1]), 1)[0]
+    assert abs(slope - ex) < 0.05
+    for k in (30, 100, 300, 1000):
+        assert inter_in[k - 1] == pytest.approx(inter * k ** ex / norm, rel=0.15), k
+
+
+def test_web_is_deterministic(web16):
+    rp, ci = graphgen.web(1 << 16, seed=5)
+    assert np.array_equal(rp, web16[0]) and np.array_equal(ci, web16[1])
+    assert not np.array_equal(graphgen.web(1 << 16, seed=6)[1][:1000], ci[:1000])
