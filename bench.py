@@ -599,7 +599,7 @@ def spec_name(name):
     return {
         "rmat22sym": "symmetric R-MAT scale 22 (a=.57,b=.19,c=.19), 2^26 arcs, 64 registers, hash seed 7",
         "rmat14": "directed R-MAT scale 14, 262144 arcs, 16 registers, hash seed 1",
-        "web24": "web-like 2^24 nodes, lognormal hosts (mean 1000), out-degree mean 20, local arcs drawn with p=0.8 (53% kept), "
+        "web24": "web-like 2^24 nodes, lognormal hosts (mean 1000), out-degree mean 20, intra-host arcs drawn with p=0.8 (53% kept), "
                  "power-law in-degree 2.1, 128 registers, hash seed 1",
     }.get(name, name)
 

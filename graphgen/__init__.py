@@ -45,8 +45,10 @@ def _load():
         lib.gg_rmat.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64] + out
         lib.gg_er.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64] + out
-        lib.gg_web.argtypes = [ctypes.c_int32] + [ctypes.c_double] * 7 + [ctypes.c_uint64] + out
-        for f in (lib.gg_rmat, lib.gg_er, lib.gg_web):
+        lib.gg_web.argtypes = ([ctypes.c_int32] + [ctypes.c_double] * 7 + [ctypes.c_uint64, ctypes.c_int32]
+                               + out)
+        lib.gg_web_hosts.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_uint64, i32p]
+        for f in (lib.gg_rmat, lib.gg_er, lib.gg_web, lib.gg_web_hosts):
             f.restype = ctypes.c_int
         lib.gg_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -86,11 +88,24 @@ def erdos_renyi(n: int, target: int, seed=1):
 
 
 def web(n: int, host_mean=1000.0, host_sigma=1.0, deg_mean=20.0, deg_sigma=1.0, p_intra=0.8,
-        geo_p=0.25, gamma=2.1, seed=24):
-    """Web-like directed graph: lognormal hosts, local intra-host arcs, power-law in-degree."""
+        geo_p=0.25, gamma=2.1, seed=24, keep_kind=False):
+    """Web-like directed graph: lognormal hosts, local intra-host arcs, power-law in-degree.
+    A duplicate target is drawn again: with keep_kind=False with a new intra/inter choice
+    (fewer than p_intra of the kept arcs are then intra-host), with keep_kind=True within
+    the arc's own kind (p_intra holds for the kept arcs, up to nodes whose nearby ids run
+    out)."""
     lib = _load()
     return _call(lib.gg_web, n, host_mean, host_sigma, deg_mean, deg_sigma, p_intra, geo_p,
-                 gamma, seed)
+                 gamma, seed, int(keep_kind))
+
+
+def web_hosts(n: int, host_mean=1000.0, host_sigma=1.0, seed=24) -> np.ndarray:
+    """First id of each node's host in `web` with the same arguments (int32[n])."""
+    lib = _load()
+    out = np.zeros(n, np.int32)
+    if lib.gg_web_hosts(n, host_mean, host_sigma, seed, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) != 0:
+        raise ValueError("web_hosts: bad arguments")
+    return out
 
 
 # ---------------------------------------------------------------- small structured graphs

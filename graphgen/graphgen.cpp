@@ -254,30 +254,51 @@ int gg_er(int32_t n, int64_t target, uint64_t seed, int32_t *n_out, int64_t *arc
   return build_csr(n, src, dst, row_ptr, col_idx, arcs_out);
 }
 
+// Hosts of the web-like graph: contiguous id ranges with LogNormal sizes of mean
+// host_mean (shape host_sigma), drawn from one sequential stream of the graph seed.
+static void web_hosts(int32_t n, double host_mean, double host_sigma, uint64_t seed,
+                      std::vector<int32_t> &host_lo, std::vector<int32_t> &host_hi) {
+  host_lo.assign((size_t)n, 0);
+  host_hi.assign((size_t)n, 0);
+  Rng r(seed, 1);
+  const double mu = std::log(host_mean) - 0.5 * host_sigma * host_sigma;
+  int64_t lo = 0;
+  while (lo < n) {
+    int64_t sz = std::llround(std::exp(mu + host_sigma * r.normal()));
+    if (sz < 1) sz = 1;
+    const int64_t hi = std::min<int64_t>(n, lo + sz);
+    for (int64_t v = lo; v < hi; v++) { host_lo[v] = (int32_t)lo; host_hi[v] = (int32_t)(hi - 1); }
+    lo = hi;
+  }
+}
+
+// First id of each node's host (n entries), as gg_web draws the hosts.
+int gg_web_hosts(int32_t n, double host_mean, double host_sigma, uint64_t seed, int32_t *host_first) {
+  if (n < 2 || host_mean < 1 || !host_first) return -1;
+  std::vector<int32_t> lo, hi;
+  web_hosts(n, host_mean, host_sigma, seed, lo, hi);
+  std::memcpy(host_first, lo.data(), sizeof(int32_t) * (size_t)n);
+  return 0;
+}
+
 // Web-like directed graph. Hosts are contiguous id ranges with LogNormal sizes of mean
 // `host_mean` (shape host_sigma); out-degrees are round(LogNormal) with mean `deg_mean`
 // (shape deg_sigma). Each arc is intra-host with probability p_intra, to v +/- a
 // Geometric(geo_p) offset clamped into the host, else inter-host, to a node drawn with
 // weight rank^(-1/(gamma-1)) over a seeded random ranking (Chung-Lu; power-law in-degree
 // with exponent gamma) through a Vose alias table.
+// A duplicate or self-loop target is drawn again. With keep_kind = 0 every draw takes a
+// new intra/inter choice; nearby ids repeat far more often than power-law targets, so
+// fewer than p_intra of the kept arcs are intra-host. With keep_kind = 1 the choice is
+// taken once per arc and only the target is drawn again: an intra-host arc that finds no
+// free nearby id draws over the whole host, and one that finds no free id in the host
+// becomes inter-host, so p_intra holds for the kept arcs up to nodes whose host runs out.
 int gg_web(int32_t n, double host_mean, double host_sigma, double deg_mean, double deg_sigma,
-           double p_intra, double geo_p, double gamma, uint64_t seed, int32_t *n_out,
-           int64_t *arcs_out, int32_t **row_ptr, int32_t **col_idx) {
+           double p_intra, double geo_p, double gamma, uint64_t seed, int32_t keep_kind,
+           int32_t *n_out, int64_t *arcs_out, int32_t **row_ptr, int32_t **col_idx) {
   if (n < 2 || host_mean < 1 || deg_mean < 0 || geo_p <= 0 || geo_p > 1 || gamma <= 1) return -1;
-  // Hosts (one sequential stream).
-  std::vector<int32_t> host_lo((size_t)n), host_hi((size_t)n);
-  {
-    Rng r(seed, 1);
-    const double mu = std::log(host_mean) - 0.5 * host_sigma * host_sigma;
-    int64_t lo = 0;
-    while (lo < n) {
-      int64_t sz = std::llround(std::exp(mu + host_sigma * r.normal()));
-      if (sz < 1) sz = 1;
-      const int64_t hi = std::min<int64_t>(n, lo + sz);
-      for (int64_t v = lo; v < hi; v++) { host_lo[v] = (int32_t)lo; host_hi[v] = (int32_t)(hi - 1); }
-      lo = hi;
-    }
-  }
+  std::vector<int32_t> host_lo, host_hi;
+  web_hosts(n, host_mean, host_sigma, seed, host_lo, host_hi);
   // Alias table over ranks; rank r (0-based) has weight (r+1)^(-1/(gamma-1)).
   std::vector<int32_t> rank_node;
   random_permutation(n, seed, 2, rank_node);
@@ -327,26 +348,54 @@ int gg_web(int32_t n, double host_mean, double host_sigma, double deg_mean, doub
     const int64_t d = off[(size_t)v + 1] - off[v];
     // Draw until d distinct non-loop targets (bounded retries), so the degree law holds
     // after duplicate removal.
+    auto intra_target = [&]() -> int64_t {
+      double u = r.uniform();
+      while (u <= 0.0) u = r.uniform();
+      const int64_t g = 1 + (int64_t)std::floor(std::log(u) / lq);  // Geometric on {1,2,...}
+      const int64_t delta = (r.next() & 1) ? g : -g;
+      return std::min<int64_t>(host_hi[v], std::max<int64_t>(host_lo[v], (int64_t)v + delta));
+    };
+    auto host_target = [&]() -> int64_t {  // uniform over v's host
+      return host_lo[v] + (int64_t)r.below((uint64_t)(host_hi[v] - host_lo[v] + 1));
+    };
+    auto inter_target = [&]() -> int64_t {
+      const uint64_t i2 = r.below((uint64_t)n);
+      const int32_t rk = (r.uniform() < prob[i2]) ? (int32_t)i2 : alias[i2];
+      return rank_node[rk];
+    };
     int64_t k = 0;
-    const int64_t max_draws = 8 * d + 64;
-    for (int64_t draw = 0; k < d && draw < max_draws; draw++) {
-      int64_t t;
-      if (r.uniform() < p_intra) {
-        double u = r.uniform();
-        while (u <= 0.0) u = r.uniform();
-        const int64_t g = 1 + (int64_t)std::floor(std::log(u) / lq);  // Geometric on {1,2,...}
-        const int64_t delta = (r.next() & 1) ? g : -g;
-        t = std::min<int64_t>(host_hi[v], std::max<int64_t>(host_lo[v], (int64_t)v + delta));
-      } else {
-        const uint64_t i2 = r.below((uint64_t)n);
-        const int32_t rk = (r.uniform() < prob[i2]) ? (int32_t)i2 : alias[i2];
-        t = rank_node[rk];
-      }
-      if (t == v) continue;
-      bool dup = false;
+    auto take = [&](int64_t t) -> bool {  // keeps t if it is new and not v itself
+      if (t == v) return false;
       for (int64_t j = 0; j < k; j++)
-        if (b[j] == (int32_t)t) { dup = true; break; }
-      if (!dup) b[k++] = (int32_t)t;
+        if (b[j] == (int32_t)t) return false;
+      b[k++] = (int32_t)t;
+      return true;
+    };
+    const int64_t max_draws = 8 * d + 64;
+    if (!keep_kind) {
+      for (int64_t draw = 0; k < d && draw < max_draws; draw++)
+        take(r.uniform() < p_intra ? intra_target() : inter_target());
+    } else {
+      // An intra-host arc draws a nearby id up to 32 times, then any id of the host up to
+      // 32 times, then becomes inter-host. Once the nearby ids of v are taken (a first
+      // intra-host arc found none), later intra-host arcs start at the host-wide draws,
+      // and once the host is taken, at the inter-host draws, so the draw budget still
+      // covers d.
+      int64_t draws = 0;
+      int level_min = 0;  // 0 nearby, 1 host-wide, 2 inter-host
+      while (k < d && draws < max_draws) {
+        int level = r.uniform() < p_intra ? level_min : 2;
+        bool kept = false;
+        for (int tries = 0; !kept && draws < max_draws; tries++, draws++) {
+          if (tries == 32 && level < 2) {
+            level_min = std::max(level_min, ++level);
+            tries = 0;
+          } else if (tries == 32) {
+            break;
+          }
+          kept = take(level == 0 ? intra_target() : level == 1 ? host_target() : inter_target());
+        }
+      }
     }
     std::sort(b, b + k);
     int32_t *w = b + k;

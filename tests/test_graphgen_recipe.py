@@ -2,7 +2,8 @@
 with sorted successor lists and no duplicates or self-loops, exact arc counts, symmetric
 R-MAT equal to its own transpose, R-MAT skew, the web-like graph's out-degree law after
 duplicate removal, its local arcs and its power-law in-degree of the inter-host arcs, and
-determinism under the graph seed."""
+determinism under the graph seed; the per-arc intra/inter choice gives 80% intra-host
+arcs."""
 import numpy as np
 import pytest
 
@@ -70,25 +71,17 @@ def test_web_out_degree_law_after_dedupe(web16):
     assert abs(logs.mean() - (np.log(20.0) - 0.5)) < 0.05
 
 
-def test_web_local_and_power_law_arcs(web16):
-    rp, ci = web16
+def intra_host_share_and_inter_indeg(rp, ci, hosts):
     n = len(rp) - 1
-    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
-    dist = np.abs(ci.astype(np.int64) - src)
-    near = (dist <= 64).mean()
-    # Intra-host with probability 0.8 per draw; a duplicate target is drawn again with a
-    # new intra/inter choice, and nearby ids repeat far more often than power-law targets,
-    # so a little over half of the kept arcs are local.
-    assert 0.5 < near < 0.6
-    # local arcs stay within a few ids: between 64 and 256 only the inter-host arcs that
-    # land there by chance (about 384/n of them)
-    assert (dist <= 256).mean() - near < 0.01
+    src = np.repeat(np.arange(n), np.diff(rp))
+    intra = hosts[ci] == hosts[src]
+    return intra.mean(), np.sort(np.bincount(ci[~intra], minlength=n))[::-1], int((~intra).sum())
+
+
+def check_inter_power_law(inter_in, inter, n):
     # Inter-host targets: weight rank^(-1/(gamma-1)) with gamma = 2.1 (Chung-Lu), so the
-    # r-th largest in-degree from inter-host arcs is about inter * r^(-1/1.1) / sum_k k^(-1/1.1).
+    # r-th largest inter-host in-degree is about inter * r^(-1/1.1) / sum_k k^(-1/1.1).
     # Ranks 30..1000: past the top few, whose in-degree saturates at one arc per source.
-    local = dist <= 64
-    inter_in = np.sort(np.bincount(ci[~local], minlength=n))[::-1]
-    inter = int((~local).sum())
     ex = -1 / 1.1
     norm = np.sum(np.arange(1, n + 1, dtype=np.float64) ** ex)
     r = np.arange(30, 1001)
@@ -96,6 +89,38 @@ def test_web_local_and_power_law_arcs(web16):
     assert abs(slope - ex) < 0.05
     for k in (30, 100, 300, 1000):
         assert inter_in[k - 1] == pytest.approx(inter * k ** ex / norm, rel=0.15), k
+
+
+def test_web_hosts(web16):
+    hosts = graphgen.web_hosts(1 << 16, seed=5)
+    assert hosts[0] == 0 and np.all(np.diff(hosts) >= 0) and np.all(hosts <= np.arange(1 << 16))
+    first = np.unique(hosts)
+    sizes = np.diff(np.append(first, 1 << 16))
+    assert np.all(hosts[first] == first)
+    assert 500 < sizes[:-1].mean() < 2000               # LogNormal sizes of mean 1000
+
+
+def test_web_default_draws(web16):
+    rp, ci = web16
+    n = len(rp) - 1
+    share, inter_in, inter = intra_host_share_and_inter_indeg(rp, ci, graphgen.web_hosts(n, seed=5))
+    # Intra-host with probability 0.8 per draw; a duplicate target is drawn again with a
+    # new intra/inter choice, and nearby ids repeat far more often than power-law targets,
+    # so only a little over half of the kept arcs are intra-host.
+    assert 0.5 < share < 0.6
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    assert (np.abs(ci.astype(np.int64) - src) <= 64).mean() > 0.95 * share   # and nearby
+    check_inter_power_law(inter_in, inter, n)
+
+
+def test_web_kind_kept_per_arc(web16):
+    n = 1 << 16
+    rp, ci = graphgen.web(n, seed=5, keep_kind=True)
+    check_csr(rp, ci)
+    assert np.array_equal(rp, web16[0])                 # the same out-degrees
+    share, inter_in, inter = intra_host_share_and_inter_indeg(rp, ci, graphgen.web_hosts(n, seed=5))
+    assert abs(share - 0.8) < 0.01
+    check_inter_power_law(inter_in, inter, n)
 
 
 def test_web_is_deterministic(web16):
