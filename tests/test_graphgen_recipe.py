@@ -127,3 +127,40 @@ def test_web_is_deterministic(web16):
     rp, ci = graphgen.web(1 << 16, seed=5)
     assert np.array_equal(rp, web16[0]) and np.array_equal(ci, web16[1])
     assert not np.array_equal(graphgen.web(1 << 16, seed=6)[1][:1000], ci[:1000])
+
+
+def test_batch_workload_recipe():
+    sizes = graphgen.batch_sizes(512, seed=4)
+    assert len(sizes) == 512 and min(sizes) >= 1 << 8 and max(sizes) <= 1 << 16
+    assert 0.75 < np.median(sizes) / 4096 < 1.3        # lognormal, median 2^12
+    graphs = graphgen.batch_graphs(16, seed=4)
+    for i, ((rp, ci), n) in enumerate(zip(graphs, graphgen.batch_sizes(16, seed=4))):
+        m, _ = check_csr(rp, ci)
+        assert m == n
+        # first half Erdos-Renyi with 8n arcs, second half R-MAT with 16n arcs
+        assert len(ci) == (8 * n if i < 8 else 16 * n)
+
+
+def test_disjoint_union_layout():
+    gs = [graphgen.directed_cycle(5), graphgen.empty(3), graphgen.erdos_renyi(40, 200, seed=2)]
+    off, rp, ci = graphgen.disjoint_union(gs)
+    assert list(off) == [0, 5, 8, 48]
+    check_csr(rp, ci)
+    for g, (a, b) in zip(gs, zip(off[:-1], off[1:])):
+        grp = rp[a:b + 1] - rp[a]
+        assert np.array_equal(grp, g[0])
+        assert np.array_equal(ci[rp[a]:rp[b]] - a, g[1])
+
+
+def test_serve_request_recipe():
+    reqs = graphgen.serve_requests(40, trace_seed=5, hi=1 << 13, median=1 << 11, sigma=1.0)
+    assert [r["rid"] for r in reqs] == list(range(40))
+    assert {r["log2m"] for r in reqs} <= {4, 6, 8} and len({r["log2m"] for r in reqs}) == 3
+    assert {r["kind"] for r in reqs} == {"rmat", "web"}
+    for r in reqs:
+        rp, ci = r["graph"]
+        n, _ = check_csr(rp, ci)
+        assert n == r["n"] and (1 << 10) <= n <= (1 << 13)
+        assert r["seed"] == r["rid"] + 1
+        if r["kind"] == "rmat":
+            assert len(ci) == 16 * n
