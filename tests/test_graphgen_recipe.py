@@ -164,3 +164,14 @@ def test_serve_request_recipe():
         assert r["seed"] == r["rid"] + 1
         if r["kind"] == "rmat":
             assert len(ci) == 16 * n
+
+
+def test_benchmark_graph_at_full_size():
+    """The symmetric R-MAT graph of scale 22 the benchmark runs on: 2^22 nodes, 2^26 arcs
+    (2^25 distinct edges, both directions), its largest degree and its nodes without arcs
+    as generated from graph seed 22."""
+    rp, ci = graphgen.workload_graph(graphgen.WORKLOADS["rmat22sym"])
+    deg = np.diff(rp)
+    assert len(rp) - 1 == 1 << 22 and len(ci) == 1 << 26
+    assert int(deg.max()) == 99_802 and int((deg == 0).sum()) == 2_168_332
+    assert not np.any(np.repeat(np.arange(1 << 22, dtype=np.int32), deg) == ci)
