@@ -367,7 +367,7 @@ def run_serve_mode(args):
         seq_lat = fin - arrivals
         reqs = [serve.Request(sp["rid"], sp["graph"][0], sp["graph"][1], sp["log2m"], sp["seed"], float(a))
                 for sp, a in zip(specs, arrivals)]
-        srv = serve.Server(0, max_batches=args.max_batches)
+        srv = serve.Server(0, max_batches=args.max_batches, size_classes=bool(args.size_classes))
         srv.warm_up(reqs)
         srv.batch_sizes, srv.max_flights = [], 0
         srv.serve_trace(reqs)
@@ -426,6 +426,8 @@ def main():
     ap.add_argument("--seeds", type=int, default=8, help="seeds mode: runs of the graph")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
     ap.add_argument("--max-batches", type=int, default=8, help="serve mode: batches in flight")
+    ap.add_argument("--size-classes", type=int, default=1, choices=(0, 1),
+                    help="serve mode: batch only requests whose footprints are within 4x")
     ap.add_argument("--runs-per-load", type=int, default=1, metavar="R",
                     help="plain mode: runs (hash seeds seed .. seed + R - 1) after each ingest of the "
                          "graph; a step is the ingest and its R runs")

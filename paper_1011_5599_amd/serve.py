@@ -3,9 +3,9 @@
 A request is one graph, a register count m = 2^log2m and a hash seed. The server:
 - admits arrived requests while their device footprint (graph, two register arrays,
   flags, sums; `hanf_footprint`) fits the HBM budget;
-- puts the requests admitted together that share m into one batch, whose passes advance
-  all of them at once (cross-graph iteration batching; the disjoint-union batch of the
-  library);
+- puts the requests admitted together that share m (and, by default, a size class:
+  footprints within a factor of 4) into one batch, whose passes advance all of them at
+  once (cross-graph iteration batching; the disjoint-union batch of the library);
 - keeps every batch's counters resident on the device until its last request is done, each
   batch on its own HIP stream, so batches admitted at different times overlap;
 - polls without blocking (`hanf_poll`) and completes a request as soon as its own component
@@ -72,13 +72,17 @@ def footprint(req: Request) -> int:
 class Server:
     def __init__(self, device: int = 0, hbm_budget: int = 96 << 30, max_batches: int = 8,
                  passes_per_poll: int = 2, keep_registers: bool = False, max_batch_requests: int = 64,
-                 clock=time.perf_counter, **options):
+                 size_classes: bool = True, clock=time.perf_counter, **options):
         self.device = device
         self.budget = hbm_budget
         self.max_batches = max_batches
         self.passes_per_poll = passes_per_poll
         self.keep_registers = keep_registers
         self.max_batch_requests = max_batch_requests
+        # With size classes, a batch also holds only requests whose footprints are within a
+        # factor of 4 of each other: a batch's pass covers every component, so a small graph
+        # batched with a large one would advance at the large one's pass time.
+        self.size_classes = size_classes
         self.clock = clock
         self.options = options
         self.waiting = collections.deque()
@@ -106,9 +110,10 @@ class Server:
     def _admit_groups(self):
         while self.waiting and len(self.flights) < self.max_batches:
             m = self.waiting[0].log2m
+            key = self._class(self.waiting[0])
             group, room = [], self.budget - self.used
             for r in list(self.waiting):
-                if r.log2m != m or len(group) >= self.max_batch_requests:
+                if r.log2m != m or len(group) >= self.max_batch_requests or self._class(r) != key:
                     continue
                 fp = footprint(r)
                 if fp > room:
@@ -133,6 +138,9 @@ class Server:
             self.flights.append(_Flight(bt, group, fp, set(range(len(group)))))
             self.batch_sizes.append(len(group))
             self.max_flights = max(self.max_flights, len(self.flights))
+
+    def _class(self, r: Request) -> int:
+        return footprint(r).bit_length() // 2 if self.size_classes else 0
 
     # -- completion
     def _collect(self, fl: _Flight, finished_all: bool):

@@ -163,3 +163,17 @@ def test_a_request_larger_than_the_budget_is_refused(fake):
     with pytest.raises(ValueError):
         srv.submit(r)
     assert srv.idle()
+
+
+def test_size_classes_keep_small_requests_apart_from_large_ones(fake):
+    srv = serve.Server(hbm_budget=1 << 30, size_classes=True)
+    sizes = [1000, 64000, 1100, 900, 70000]
+    for i, n in enumerate(sizes):
+        srv.submit(req(i, n=n))
+    srv.pump()
+    assert [[r.rid for r in fl.requests] for fl in srv.flights] == [[0, 2, 3], [1, 4]]
+    plain = serve.Server(hbm_budget=1 << 30, size_classes=False)
+    for i, n in enumerate(sizes):
+        plain.submit(req(i, n=n))
+    plain.pump()
+    assert [[r.rid for r in fl.requests] for fl in plain.flights] == [[0, 1, 2, 3, 4]]
