@@ -425,7 +425,7 @@ def main():
                          "serve: Poisson request stream; seeds: many runs of the workload graph")
     ap.add_argument("--seeds", type=int, default=8, help="seeds mode: runs of the graph")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
-    ap.add_argument("--max-batches", type=int, default=8, help="serve mode: batches in flight")
+    ap.add_argument("--max-batches", type=int, default=4, help="serve mode: batches in flight")
     ap.add_argument("--size-classes", type=int, default=1, choices=(0, 1),
                     help="serve mode: batch only requests whose footprints are within 4x")
     ap.add_argument("--runs-per-load", type=int, default=1, metavar="R",

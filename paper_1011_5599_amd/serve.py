@@ -70,7 +70,7 @@ def footprint(req: Request) -> int:
 
 
 class Server:
-    def __init__(self, device: int = 0, hbm_budget: int = 96 << 30, max_batches: int = 8,
+    def __init__(self, device: int = 0, hbm_budget: int = 96 << 30, max_batches: int = 4,
                  passes_per_poll: int = 2, keep_registers: bool = False, max_batch_requests: int = 64,
                  size_classes: bool = True, clock=time.perf_counter, **options):
         self.device = device
