@@ -113,6 +113,17 @@ def copy_ceiling_gbs(mib: int = 1024, reps: int = 5):
     return nbytes / (best / 1000.0) / 1e9
 
 
+def fifo_finish(arrivals, service):
+    """Completion times of one-at-a-time, first-come-first-served runs: request i starts
+    when it has arrived and request i-1 is done, and takes service[i]."""
+    import numpy as np
+    fin, t = np.zeros(len(arrivals)), 0.0
+    for i, (a, s) in enumerate(zip(arrivals, service)):
+        t = max(t, a) + s
+        fin[i] = t
+    return fin
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
@@ -359,11 +370,7 @@ def run_serve_mode(args):
         lam = factor * capacity
         arrivals = np.cumsum(gaps) / lam
         arrivals -= arrivals[0]
-        # sequential FIFO with the measured service times
-        fin, t = np.zeros(count), 0.0
-        for i in range(count):
-            t = max(t, arrivals[i]) + service[i]
-            fin[i] = t
+        fin = fifo_finish(arrivals, service)
         seq_lat = fin - arrivals
         reqs = [serve.Request(sp["rid"], sp["graph"][0], sp["graph"][1], sp["log2m"], sp["seed"], float(a))
                 for sp, a in zip(specs, arrivals)]

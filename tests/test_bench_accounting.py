@@ -62,3 +62,12 @@ def test_traffic_only_for_the_profiled_kernel_source(bench, tmp_path, monkeypatc
     assert bench.measured_traffic("other") is None          # no counter run recorded
     src.write_text("// kernels changed since\n")
     assert bench.measured_traffic("w") is None
+
+
+def test_sequential_fifo_baseline(bench):
+    # worked by hand: an idle gap, a queue, and a request that arrives as the queue empties
+    arrivals = [0.0, 1.0, 1.5, 2.0, 10.0, 12.0]
+    service = [0.5, 2.0, 1.0, 0.5, 2.0, 1.0]
+    fin = bench.fifo_finish(arrivals, service)
+    assert list(fin) == [0.5, 3.0, 4.0, 4.5, 12.0, 13.0]
+    assert list(fin - arrivals) == [0.5, 2.0, 2.5, 2.5, 2.0, 1.0]
