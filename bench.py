@@ -411,6 +411,7 @@ def run_serve_mode(args):
                    "nodes": int(sum(sp["n"] for sp in specs)),
                    "arcs": int(sum(len(sp["graph"][1]) for sp in specs)),
                    "sequential_capacity_req_per_s": capacity,
+                   "policy": {"size_classes": bool(args.size_classes), "max_batches": args.max_batches},
                    "service_ms": {"p50": 1000 * float(np.percentile(service, 50)),
                                   "p99": 1000 * float(np.percentile(service, 99))}},
         "rates": rows,
