@@ -360,6 +360,20 @@ def test_cycle_moments_closed_form(n):
     assert s["ed"] == math.ceil(0.9 * n - 1 - 1e-12)
 
 
+@pytest.mark.parametrize("n", [2, 5, 12, 40])
+def test_cycle_moments_distinct_pairs_closed_form(n):
+    """Directed cycle, pairs at distance >= 1 only (self-pairs dropped from the distance
+    distribution): H(t) = t/(n-1), so h(t) = 1/(n-1) for t = 1..n-1, average distance n/2,
+    variance n(n-2)/12, spid (n-2)/6, and H crosses 0.9 at t = 0.9(n-1)."""
+    rp, ci = graphgen.directed_cycle(n)
+    s = stats.stats(list(exact.neighbourhood_function(rp, ci)), distinct=True)
+    assert s["avg_dist"] == pytest.approx(n / 2, rel=1e-12)
+    assert s["var"] == pytest.approx(n * (n - 2) / 12, rel=1e-12, abs=1e-12)
+    assert s["spid"] == pytest.approx((n - 2) / 6, rel=1e-12, abs=1e-12)
+    assert s["ied"] == pytest.approx(0.9 * (n - 1), rel=1e-12)
+    assert s["ed"] == math.ceil(0.9 * (n - 1) - 1e-12)
+
+
 def test_diameter_interval_algorithm3():
     """Algorithm 3 on a hand-checked sequence: H = [.1 .3 .6 .85 .95 1]; with alpha = .9 and
     eps = .02: D- = largest t with H <= .864 -> 3; D+ = smallest t with H >= .936 -> 4."""
