@@ -68,6 +68,8 @@ def _load():
         L.orc_sizes.restype = None
         L.orc_sum_sizes.argtypes = [ctypes.c_int32, ctypes.c_int, u8p]
         L.orc_sum_sizes.restype = ctypes.c_double
+        L.orc_sum_sizes_mt.argtypes = [ctypes.c_int32, ctypes.c_int, u8p, ctypes.c_int]
+        L.orc_sum_sizes_mt.restype = ctypes.c_double
         L.orc_pass.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int, u8p, u8p,
                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_int64)]
@@ -80,6 +82,12 @@ def _load():
                                        ctypes.c_int32, ctypes.c_int32, u8p,
                                        ctypes.POINTER(ctypes.c_int64)]
         L.orc_ball_counter.restype = ctypes.c_int
+        L.orc_balls_check.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int, ctypes.c_uint64,
+                                      u8p, ctypes.c_int32, ctypes.c_int,
+                                      np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS"),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
+        L.orc_balls_check.restype = ctypes.c_int64
         for f in (L.orc_broadword_L,):
             f.argtypes = [ctypes.c_int]
             f.restype = ctypes.c_uint64
@@ -158,8 +166,12 @@ def sizes(c: np.ndarray, b: int) -> np.ndarray:
     return out[: c.shape[0]]
 
 
-def sum_sizes(c: np.ndarray, b: int) -> float:
+def sum_sizes(c: np.ndarray, b: int, nthreads: int = 1) -> float:
+    """N_hat = sum of size() over the counters, in node order (Neumaier summation); the
+    sizes may be computed by several threads (the same value)."""
     c = np.ascontiguousarray(c, dtype=np.uint8)
+    if nthreads > 1 and c.shape[0] > 0:
+        return _load().orc_sum_sizes_mt(c.shape[0], b, c, nthreads)
     return _load().orc_sum_sizes(c.shape[0], b, c if c.size else np.zeros(1, np.uint8))
 
 
@@ -212,7 +224,7 @@ def run_steps(row_ptr, col_idx, b: int, seed: int, max_passes: int | None = None
     mod = np.ones(n, np.uint8) if skip_unmodified else None
     t = 0
     while True:
-        yield t, cur, sum_sizes(cur, b)
+        yield t, cur, sum_sizes(cur, b, nthreads)
         if t >= max_passes:
             raise RuntimeError("oracle did not stabilise")
         nxt, mod_out, changed, _ = step(rp, ci, b, cur, mod if skip_unmodified else None, nthreads)
@@ -233,3 +245,22 @@ def ball_counter(row_ptr, col_idx, b: int, seed: int, v: int, t: int):
     if rc != 0:
         raise MemoryError("oracle ball counter")
     return M, int(sz.value)
+
+
+def balls_check(row_ptr, col_idx, b: int, seed: int, counters, nthreads: int = 1):
+    """Checks c_t[v] == counter of B(v, t) (Section 3.2) for every node v and every t, by a
+    breadth-first search from every node; `counters` holds c_0 .. c_T (each n x m uint8).
+    Returns (mismatches, (first bad v, t) or None, exact N(0..D)) where N(t) counts the
+    pairs at distance <= t, self-pairs included, and D is the largest finite distance."""
+    rp, ci = _csr(row_ptr, col_idx)
+    n = rp.size - 1
+    T = len(counters) - 1
+    regs = np.ascontiguousarray(np.stack([np.asarray(c, np.uint8).reshape(n, -1) for c in counters]))
+    hist = np.zeros(n + 1, np.int64)
+    bv, bt = ctypes.c_int32(), ctypes.c_int32()
+    bad = _load().orc_balls_check(n, rp, ci, b, seed, regs.reshape(-1), T, nthreads, hist, hist.size,
+                                  ctypes.byref(bv), ctypes.byref(bt))
+    if bad < 0:
+        raise MemoryError("oracle balls check")
+    D = int(np.nonzero(hist)[0].max())
+    return int(bad), ((bv.value, bt.value) if bad else None), np.cumsum(hist[: D + 1]).astype(np.float64)

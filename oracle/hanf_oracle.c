@@ -137,6 +137,64 @@ double orc_sum_sizes(int32_t n, int b, const uint8_t *c) {
   return s + comp;
 }
 
+/* orc_sum_sizes with the per-node sizes computed by nthreads threads over contiguous
+ * segments, then summed in node order exactly as orc_sum_sizes does (same value). */
+typedef struct {
+  int32_t n, seg;
+  int b;
+  const uint8_t *c;
+  double *out;
+  atomic_int next_task;
+} sizes_job;
+
+static void *sizes_worker(void *arg) {
+  sizes_job *job = (sizes_job *)arg;
+  int m = 1 << job->b;
+  for (;;) {
+    int task = atomic_fetch_add(&job->next_task, 1);
+    int64_t lo = (int64_t)task * job->seg;
+    if (lo >= job->n) break;
+    int64_t hi = lo + job->seg < job->n ? lo + job->seg : job->n;
+    for (int64_t v = lo; v < hi; v++) job->out[v] = orc_size(job->c + (size_t)v * m, job->b);
+  }
+  return NULL;
+}
+
+double orc_sum_sizes_mt(int32_t n, int b, const uint8_t *c, int nthreads) {
+  double *x = (double *)malloc(sizeof(double) * (n ? (size_t)n : 1));
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)(nthreads > 0 ? nthreads : 1));
+  if (!x || !th || nthreads <= 1) {
+    free(x);
+    free(th);
+    return orc_sum_sizes(n, b, c);
+  }
+  sizes_job job;
+  job.n = n;
+  job.seg = 4096;
+  job.b = b;
+  job.c = c;
+  job.out = x;
+  atomic_init(&job.next_task, 0);
+  int started = 0;
+  for (int i = 0; i < nthreads; i++)
+    if (pthread_create(&th[i], NULL, sizes_worker, &job) == 0) started++;
+    else break;
+  if (started == 0) sizes_worker(&job);
+  for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+  double s = 0.0, comp = 0.0;
+  for (int32_t v = 0; v < n; v++) {
+    double t = s + x[v];
+    if (fabs(s) >= fabs(x[v]))
+      comp += (s - t) + x[v];
+    else
+      comp += (x[v] - t) + s;
+    s = t;
+  }
+  free(x);
+  free(th);
+  return s + comp;
+}
+
 /* One pass of the main loop for the nodes lo..hi-1: m <- c[v]; for each v -> w,
  * m <- union(c[w], m); the new counter goes to `next` (the update file), so every
  * read sees the counters of the previous iteration. With `modified` non-NULL, the
@@ -337,4 +395,139 @@ uint64_t orc_broadword_max(uint64_t x, uint64_t y, int k) {
   uint64_t c = orc_broadword_less(x, y, k);
   uint64_t mask = ((((c >> (k - 1)) | H) - L) | H) ^ c;
   return (x & mask) | (y & ~mask);
+}
+
+/* ---------------------------------------------------------------- balls of every node (Section 3.2) */
+
+/* Section 3.2: after t passes, c_t[v] is the counter of the ball B(v, t). This checks the
+ * identity for every node and every t against counters the caller computed by iteration:
+ * regs holds c_0 .. c_T one after another (T+1 arrays of n*m bytes). For each v a
+ * breadth-first search visits the nodes in order of distance; a counter fed with them is
+ * compared with c_d[v] each time the distance d is complete, and, once the search ends,
+ * with c_d[v] for every remaining d <= T (the ball no longer grows). Distances beyond T
+ * are compared with c_T[v] (the counters are stable from T on). The exact distance counts
+ * go to hist (hist[d] = pairs at distance d, for d < hist_len; longer distances add to the
+ * last slot), so N(t) is their running sum. Returns the number of (v, d) mismatches;
+ * *bad_v / *bad_t receive the first one found by the lowest thread (or -1). nthreads
+ * workers take segments of 64 nodes. -2 on allocation failure. */
+typedef struct {
+  int32_t n, T, hist_len;
+  const int32_t *row_ptr, *col_idx;
+  int b;
+  uint64_t seed;
+  const uint8_t *regs;
+  int64_t *hist;
+  atomic_int next_task;
+  atomic_llong mismatches;
+  atomic_int bad_v, bad_t;
+  pthread_mutex_t lock;
+  int failed;
+} balls_job;
+
+static void *balls_worker(void *arg) {
+  balls_job *job = (balls_job *)arg;
+  const int m = 1 << job->b;
+  const size_t layer = (size_t)job->n * (size_t)m;
+  int32_t *dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)job->n);
+  int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)job->n);
+  int64_t *hist = (int64_t *)calloc((size_t)job->hist_len, sizeof(int64_t));
+  uint8_t *M = (uint8_t *)malloc((size_t)m);
+  if (!dist || !queue || !hist || !M) {
+    pthread_mutex_lock(&job->lock);
+    job->failed = 1;
+    pthread_mutex_unlock(&job->lock);
+    free(dist); free(queue); free(hist); free(M);
+    return NULL;
+  }
+  for (int32_t i = 0; i < job->n; i++) dist[i] = -1;
+  int64_t bad = 0;
+  for (;;) {
+    int task = atomic_fetch_add(&job->next_task, 1);
+    int32_t lo = task * 64;
+    if (lo >= job->n) break;
+    int32_t hi = lo + 64 < job->n ? lo + 64 : job->n;
+    for (int32_t v = lo; v < hi; v++) {
+      memset(M, 0, (size_t)m);
+      int64_t head = 0, tail = 0;
+      int32_t level = 0;
+      dist[v] = 0;
+      queue[tail++] = v;
+      while (head < tail) {
+        int32_t u = queue[head];
+        if (dist[u] != level) {  /* B(v, level) is complete */
+          int32_t t = level < job->T ? level : job->T;
+          if (memcmp(M, job->regs + (size_t)t * layer + (size_t)v * m, (size_t)m) != 0) {
+            bad++;
+            int expect = -1;
+            if (atomic_compare_exchange_strong(&job->bad_v, &expect, v)) atomic_store(&job->bad_t, level);
+          }
+          level = dist[u];
+        }
+        head++;
+        orc_add(M, job->b, job->seed, (uint64_t)u);
+        hist[dist[u] < job->hist_len ? dist[u] : job->hist_len - 1]++;
+        for (int32_t a = job->row_ptr[u]; a < job->row_ptr[u + 1]; a++) {
+          int32_t w = job->col_idx[a];
+          if (dist[w] < 0) {
+            dist[w] = dist[u] + 1;
+            queue[tail++] = w;
+          }
+        }
+      }
+      /* the ball stops growing at the last level: every later c_t[v] equals its counter */
+      for (int32_t d = level; d <= job->T || d == level; d++) {
+        int32_t t = d < job->T ? d : job->T;
+        if (memcmp(M, job->regs + (size_t)t * layer + (size_t)v * m, (size_t)m) != 0) {
+          bad++;
+          int expect = -1;
+          if (atomic_compare_exchange_strong(&job->bad_v, &expect, v)) atomic_store(&job->bad_t, d);
+        }
+        if (d >= job->T) break;
+      }
+      for (int64_t i = 0; i < tail; i++) dist[queue[i]] = -1;
+    }
+  }
+  pthread_mutex_lock(&job->lock);
+  for (int32_t d = 0; d < job->hist_len; d++) job->hist[d] += hist[d];
+  pthread_mutex_unlock(&job->lock);
+  atomic_fetch_add(&job->mismatches, bad);
+  free(dist); free(queue); free(hist); free(M);
+  return NULL;
+}
+
+int64_t orc_balls_check(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int b, uint64_t seed,
+                        const uint8_t *regs, int32_t T, int nthreads, int64_t *hist, int32_t hist_len,
+                        int32_t *bad_v, int32_t *bad_t) {
+  balls_job job;
+  job.n = n;
+  job.T = T;
+  job.hist_len = hist_len;
+  job.row_ptr = row_ptr;
+  job.col_idx = col_idx;
+  job.b = b;
+  job.seed = seed;
+  job.regs = regs;
+  job.hist = hist;
+  job.failed = 0;
+  memset(hist, 0, sizeof(int64_t) * (size_t)hist_len);
+  atomic_init(&job.next_task, 0);
+  atomic_init(&job.mismatches, 0);
+  atomic_init(&job.bad_v, -1);
+  atomic_init(&job.bad_t, -1);
+  pthread_mutex_init(&job.lock, NULL);
+  if (nthreads < 1) nthreads = 1;
+  pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
+  int started = 0;
+  if (th)
+    for (int i = 0; i < nthreads; i++)
+      if (pthread_create(&th[i], NULL, balls_worker, &job) == 0) started++;
+      else break;
+  if (started == 0) balls_worker(&job);
+  for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+  free(th);
+  pthread_mutex_destroy(&job.lock);
+  *bad_v = atomic_load(&job.bad_v);
+  *bad_t = atomic_load(&job.bad_t);
+  if (job.failed) return -2;
+  return atomic_load(&job.mismatches);
 }

@@ -440,6 +440,59 @@ def test_error_against_exact_neighbourhood_function(b, beta):
     assert np.abs(means).max() <= eta / 2
 
 
+# ------------------------------------------------------------------ the parity workload itself
+
+@pytest.fixture(scope="module")
+def rmat14_balls():
+    """The directed R-MAT scale 14 parity workload (16,384 nodes, 262,144 arcs, m = 16,
+    hash seed 1): the oracle's counters at every t and the exact N(t) by BFS."""
+    spec = graphgen.WORKLOADS["rmat14"]
+    rp, ci = graphgen.workload_graph(spec)
+    b, seed = spec["log2m"], spec["seed"]
+    counters = [c for _, c, _ in oracle.run_steps(rp, ci, b, seed)]
+    bad, first, N = oracle.balls_check(rp, ci, b, seed, counters, nthreads=os.cpu_count() or 1)
+    return rp, ci, b, seed, counters, bad, first, N
+
+
+def test_rmat14_every_counter_is_its_ball(rmat14_balls):
+    """Section 3.2: c_t[v] is the counter of B(v, t). Checked for all 16,384 nodes of the
+    parity workload at every t (and for every later distance against the stable c_T), by a
+    breadth-first search from each node."""
+    rp, ci, b, seed, counters, bad, first, N = rmat14_balls
+    assert len(counters) >= 4
+    assert bad == 0, f"{bad} (node, t) pairs differ; first {first}"
+
+
+def test_rmat14_ball_check_catches_a_changed_register(rmat14_balls):
+    rp, ci, b, seed, counters, _, _, _ = rmat14_balls
+    planted = [c.copy() for c in counters]
+    planted[2][1234, 5] += 1
+    bad, first, _ = oracle.balls_check(rp, ci, b, seed, planted, nthreads=os.cpu_count() or 1)
+    assert bad >= 1 and first == (1234, 2)
+
+
+def test_rmat14_within_theorem1_over_seeds(rmat14_balls):
+    """Theorem 1 with the Vysochanskii-Petunin bound (Section 3.4) on the parity workload:
+    over 32 hash seeds, N_hat(t) is within 2 eta of the exact N(t) (BFS) for at least
+    1 - 4/36 of the (seed, t) points and within 3 eta for at least 1 - 4/81, with
+    eta = 1.106/sqrt(16) at m = 16; the seed mean is within eta/2 (almost unbiased).
+    N(0) = n exactly (Section 4: self-pairs count) and N(t) ends at the reachable pairs."""
+    rp, ci, b, _, _, _, _, N = rmat14_balls
+    n = len(rp) - 1
+    assert N[0] == n and np.all(np.diff(N) > 0)
+    eta = 1.106 / math.sqrt(1 << b)
+    errs, runs = [], []
+    for seed in range(1, 33):
+        nt, T, _ = oracle.run(rp, ci, b, seed, nthreads=os.cpu_count() or 1)
+        ext = np.array([nt[min(t, T)] for t in range(len(N))])
+        runs.append(ext)
+        errs.extend(np.abs(ext / N - 1))
+    errs = np.array(errs)
+    assert (errs <= 2 * eta).mean() >= 1 - 4 / 36
+    assert (errs <= 3 * eta).mean() >= 1 - 4 / 81
+    assert np.abs(np.mean(runs, axis=0) / N - 1).max() <= eta / 2
+
+
 @pytest.mark.parametrize("b", [4, 6])
 def test_estimate_falls_only_at_the_small_range_switch(b):
     """Section 4 calls the estimated distance function monotone. Registers only grow, so the
