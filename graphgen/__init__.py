@@ -173,8 +173,9 @@ WORKLOADS = {
     # symmetric R-MAT scale 22, 2^25 edges -> 2^26 arcs; log2m 6, hash seed 7
     "rmat22sym": dict(kind="rmat", scale=22, target=1 << 25, symmetric=True, graph_seed=22,
                       log2m=6, seed=7),
-    # web-like, 2^24 nodes; log2m 7, hash seed 1
-    "web24": dict(kind="web", n=1 << 24, graph_seed=24, log2m=7, seed=1),
+    # web-like, 2^24 nodes, 80% of the kept arcs intra-host (the intra/inter choice is kept
+    # when a duplicate target is redrawn); log2m 7, hash seed 1
+    "web24": dict(kind="web", n=1 << 24, graph_seed=24, keep_kind=True, log2m=7, seed=1),
 }
 
 
@@ -251,7 +252,7 @@ def workload_graph(spec: dict):
         return rmat(spec["scale"], spec["target"], symmetric=spec["symmetric"],
                     seed=spec["graph_seed"])
     if spec["kind"] == "web":
-        return web(spec["n"], seed=spec["graph_seed"])
+        return web(spec["n"], seed=spec["graph_seed"], keep_kind=spec.get("keep_kind", False))
     if spec["kind"] == "er":
         return erdos_renyi(spec["n"], spec["target"], seed=spec["graph_seed"])
     raise ValueError(spec["kind"])

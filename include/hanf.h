@@ -290,6 +290,17 @@ int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *le
  * bytes) is its dominant term. HANF_EINVAL for arguments out of range. */
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
 
+/* Device memory the context holds (pure host function): *held (may be NULL) = every device
+ * buffer it allocated and has not returned to HIP, in use or kept in its pool for reuse by
+ * later runs (allocations are rounded up to size classes); *pooled (may be NULL) = the part
+ * kept in the pool. What a caller budgeting device memory (a serving loop admitting graphs by
+ * footprint, Section 3.4's memory bound) must count for this context. */
+int hanf_device_bytes(const hanf_ctx *ctx, int64_t *held, int64_t *pooled);
+
+/* Returns the pooled buffers (see hanf_device_bytes) to HIP. Waits for the context's stream;
+ * freeing device memory also waits for the device. Buffers in use are kept. */
+int hanf_trim(hanf_ctx *ctx);
+
 /* ---- Batched runs: many independent HyperANF runs in the same passes.
  * Each input graph g is run with n_seeds hash seeds; component c = g * n_seeds + s is an
  * independent run of Algorithm 2 on graph g with seed seeds[c]. The components are laid
@@ -319,7 +330,9 @@ int hanf_load_batch_list(hanf_ctx *ctx, int32_t n_graphs, const int32_t *const *
 
 /* Initialises every component (Algorithm 2's initialisation with the graph-local node id as
  * the item and seeds[c] as the hash seed; seeds has n_graphs * n_seeds entries, host). Passes
- * allowed default to 1024 (HANF_OPT_MAX_PASSES changes it). */
+ * allowed default to the largest graph's n + 1 (every component then stops as it would alone),
+ * lowered to what 64 MiB of per-component N_hat histories hold but never below 1024
+ * (HANF_OPT_MAX_PASSES changes it). */
 int hanf_init_batch(hanf_ctx *ctx, int32_t log2m, const uint64_t *seeds);
 
 /* Number of components and, if T is non-NULL (n_components entries, host), each one's

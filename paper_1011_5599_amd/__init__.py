@@ -149,6 +149,8 @@ def lib():
             "hanf_batch_read_registers": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_batch_stats": ([vp, i32, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
             "hanf_batch_stats_all": ([vp, dbl, dbl, i32, vp], ctypes.c_int),
+            "hanf_device_bytes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+            "hanf_trim": ([vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -292,6 +294,18 @@ def hanf_write_registers(ctx, regs, t: int, nt_prefix) -> None:
     nbytes = keep.numel() if _is_tensor(keep) else keep.size
     pre = np.ascontiguousarray(nt_prefix, dtype=np.float64)
     _check(lib().hanf_write_registers(ctx, p, nbytes, t, pre.ctypes.data, pre.size, flags), ctx)
+
+
+def hanf_device_bytes(ctx) -> tuple[int, int]:
+    """(held, pooled): device bytes the context holds, and the part kept for reuse."""
+    held, pooled = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().hanf_device_bytes(ctx, ctypes.byref(held), ctypes.byref(pooled)), ctx)
+    return held.value, pooled.value
+
+
+def hanf_trim(ctx) -> None:
+    """Returns the context's pooled device buffers to HIP."""
+    _check(lib().hanf_trim(ctx), ctx)
 
 
 def hanf_stats_nt(nt, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:

@@ -140,7 +140,7 @@ struct hanf_ctx {
   PassLog *log_host = nullptr;  // pinned, kMaxPassesPerCheck records read with the state
   hipEvent_t poll_ev = nullptr;
   bool poll_pending = false;
-  int32_t nt_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
+  int32_t nt_cap = 0, log_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
   std::vector<double> lc_host;
   std::vector<hanf_pass_t> host_log;
   PassArgs args{};
@@ -540,6 +540,7 @@ void fill_args(hanf_ctx *c) {
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;
   a.nt_cap = c->nt_cap;
+  a.log_cap = c->log_cap;
   a.arcs = c->arcs;
   a.node_id = c->batch ? nullptr : c->perm;
   a.batch.active = c->batch ? 1 : 0;
@@ -563,11 +564,21 @@ void fill_args(hanf_ctx *c) {
   a.batch.comp_nt = c->comp_nt;
 }
 
+// Per-component N_hat histories of a batch are kept within this many bytes when the pass cap
+// is the default.
+constexpr int64_t kBatchHistoryBytes = 64 << 20;
+
 // Passes allowed before HANF_EMAXITER: the option, else n + 1 for one graph (T is below the
-// number of nodes), else 1024 for batches (their per-component histories are kept).
+// number of nodes). For a batch, the largest graph's n + 1, so every component stops as it
+// would alone; its histories hold cap + 2 values per component, so the cap is lowered to
+// what kBatchHistoryBytes holds, but never below 1024 passes.
 int64_t default_max_passes(const hanf_ctx *c) {
   if (c->max_passes_opt > 0) return c->max_passes_opt;
-  return c->batch ? std::min<int64_t>(1024, (int64_t)c->n + 1) : (int64_t)c->n + 1;
+  if (!c->batch) return (int64_t)c->n + 1;
+  int64_t nmax = 1;
+  for (int32_t g : c->g_n_h) nmax = std::max<int64_t>(nmax, g);
+  const int64_t fits = kBatchHistoryBytes / 8 / std::max<int64_t>(1, c->n_comp) - 2;
+  return std::min<int64_t>(nmax + 1, std::max<int64_t>(1024, fits));
 }
 
 // Packed registers move through a device staging buffer of at most this many 64-register
@@ -782,6 +793,7 @@ int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
   c->n_reduce_wgs = (c->n_blocks + kReduceBlocks - 1) / kReduceBlocks;
   c->max_passes = (int32_t)std::min<int64_t>(default_max_passes(c), INT32_MAX - 8);
   c->nt_cap = c->max_passes + 2;
+  c->log_cap = std::min(c->nt_cap, kMaxLogRecords);
   int rc;
   if ((rc = dev_alloc(c, &c->regs[0], bytes, "counters")) || (rc = dev_alloc(c, &c->regs[1], bytes, "counters")) ||
       (rc = dev_alloc(c, &c->bits[0], (size_t)2 * c->n_blocks * S, "flags")) ||
@@ -792,7 +804,7 @@ int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
       (rc = dev_alloc(c, &c->wgcnt, (size_t)c->n_reduce_wgs, "partial counts")) ||
       (rc = dev_alloc(c, &c->lc, (size_t)m + 1, "linear-counting table")) ||
       (rc = dev_alloc(c, &c->nt, (size_t)c->nt_cap, "N history")) ||
-      (rc = dev_alloc(c, &c->log, (size_t)c->nt_cap, "pass log")) ||
+      (rc = dev_alloc(c, &c->log, (size_t)c->log_cap, "pass log")) ||
       (rc = dev_alloc(c, &c->stats_out, 16, "statistics"))) {
     free_run(c);
     return rc;
@@ -1546,7 +1558,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
     }
     // the run state, the records of every pass the batch may have run and the start of the
     // N_hat history, in one wait
-    const int32_t cnt = (int32_t)std::min<int64_t>(B, (int64_t)c->nt_cap - s0.passes);
+    const int32_t cnt = (int32_t)std::max<int64_t>(0, std::min<int64_t>(B, (int64_t)c->log_cap - s0.passes));
     const int32_t nt_cnt = std::min(c->nt_cap, kNtHostCache);
     c->nt_host_len = 0;
     HIP_TRY(c, hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
@@ -1563,10 +1575,10 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
     c->comp_T_fresh = false;
     if (!c->batch) c->nt_host_len = std::min(c->st_host->t + 1, nt_cnt);
     const int32_t ran = c->st_host->passes - s0.passes;
-    if (ran > cnt) return fail(c, HANF_EDEVICE, "more passes recorded than enqueued");
+    if (ran > B) return fail(c, HANF_EDEVICE, "more passes recorded than enqueued");
     if (ran > 0) {
       const PassLog *recs = c->log_host;
-      for (int32_t i = 0; i < ran; ++i) {
+      for (int32_t i = 0; i < std::min(ran, cnt); ++i) {  // passes beyond log_cap are not recorded
         hanf_pass_t r{};
         r.changed = recs[i].changed;
         r.arcs_scanned = recs[i].scanned;
@@ -1855,6 +1867,8 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
   b += (int64_t)n * 4 + 4096;                            // light tiles
   b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)
+  b += ((int64_t)n + 3) * 8;                             // N_hat history (pass cap n + 1)
+  b += std::min<int64_t>((int64_t)n + 3, kMaxLogRecords) * (int64_t)sizeof(PassLog);  // pass records
   if (copy_graph & HANF_FP_COPY_GRAPH) b += ((int64_t)n + 1) * 4 + arcs * 4;
   if (copy_graph & HANF_FP_TRANSPOSE) {
     b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
@@ -2256,6 +2270,28 @@ int hanf_batch_stats_all(hanf_ctx *c, double alpha, double eps, int32_t distinct
     out[k].T = (int32_t)b[8];
     out[k].distinct = distinct ? 1 : 0;
   }
+  return HANF_OK;
+}
+
+int hanf_device_bytes(const hanf_ctx *c, int64_t *held, int64_t *pooled) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_device_bytes: NULL context");
+  int64_t h = 0, p = 0;
+  for (const auto &kv : c->sizes) h += (int64_t)kv.second;
+  for (const auto &kv : c->pool) p += (int64_t)kv.first;
+  if (held) *held = h;
+  if (pooled) *pooled = p;
+  return HANF_OK;
+}
+
+int hanf_trim(hanf_ctx *c) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_trim: NULL context");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  for (auto &kv : c->pool) {
+    c->sizes.erase(kv.second);
+    (void)hipFree(kv.second);
+  }
+  c->pool.clear();
   return HANF_OK;
 }
 

@@ -17,6 +17,7 @@ constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgro
 constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
 constexpr int kPacked5LaneBytes = 40;   // 64 registers of 5 bits: one lane of a packed counter
 constexpr int kMaxPassesPerCheck = 1024;  // passes enqueued between host reads of the run state
+constexpr int32_t kMaxLogRecords = 1 << 16;  // pass records kept per run (the first 65536 passes)
 
 // Run state kept in device memory, so consecutive passes can be enqueued without a host
 // round trip: kernels read the iteration t and stop early once the run has halted.
@@ -176,7 +177,8 @@ struct PassArgs {
   int32_t n_heavy;
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;
-  int32_t nt_cap;
+  int32_t nt_cap;             // N_hat history capacity (values)
+  int32_t log_cap;            // pass records kept (passes beyond it run unrecorded)
   int64_t arcs;
   const int32_t *node_id;    // the caller's id of node v (hashed at initialisation) when the
                              //   library chose its own node order, else NULL (the same id)

@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       rec.read = s_i[4][0];
       rec.systolic = st->systolic;
       rec.signalled = rec.systolic ? (int64_t)(st->sys_acc & 0xffffffffull) : 0;
-      if (p < a.nt_cap) a.log[p] = rec;
+      if (p < a.log_cap) a.log[p] = rec;
       st->passes = p + 1;
       st->changed_last = rec.changed;
       st->first_pass = 0;

@@ -11,12 +11,16 @@ from paper_1011_5599_amd import serve
 
 
 class FakeBatch:
+    """Stands in for a library batch context. Like the library, it keeps the device memory
+    of its largest batch until it is destroyed (`held`)."""
     made = []
 
     def __init__(self, device, **options):
         self.ctx = self
         self.enqueued = 0
         self.loads = []
+        self.held = 0
+        self.closed = False
         FakeBatch.made.append(self)
 
     def load_graphs(self, graphs, seeds_per_graph):
@@ -28,9 +32,12 @@ class FakeBatch:
         self.log2m, self.seeds = log2m, list(seeds)
         self.T = [-1] * len(seeds)
         self.status = HANF_BUSY
+        fp = sum(serve.footprint_of(len(rp) - 1, len(ci), log2m) for rp, ci in self.graphs)
+        self.held = max(self.held, fp)
 
     def close(self):
-        pass
+        self.closed = True
+        self.held = 0
 
 
 @pytest.fixture
@@ -49,6 +56,7 @@ def fake(monkeypatch):
                         lambda ctx: {"spid": np.arange(len(ctx.seeds), dtype=np.float64)})
     monkeypatch.setattr(serve, "hanf_batch_read_nt",
                         lambda ctx, c: np.arange(max(ctx.T[c], 0) + 1, dtype=np.float64))
+    monkeypatch.setattr(serve, "hanf_device_bytes", lambda ctx: (ctx.held, 0))
     return FakeBatch
 
 
@@ -78,7 +86,7 @@ def test_footprint_is_the_library_figure_plus_the_graph_copy():
 
 def test_admits_within_the_budget_and_keeps_the_rest_waiting(fake):
     fp = serve.footprint(req(0))
-    srv = serve.Server(hbm_budget=3 * fp + fp // 2)
+    srv = serve.Server(hbm_budget=3 * fp + fp // 2, alloc_slack=1.0)
     for i in range(5):
         srv.submit(req(i))
     srv.pump()
@@ -112,7 +120,7 @@ def test_batch_caps(fake):
 def test_the_oldest_request_is_not_passed_by_smaller_ones(fake):
     big, small = req(0, n=20000), req(1, n=100)
     fp_big, fp_small = serve.footprint(big), serve.footprint(small)
-    srv = serve.Server(hbm_budget=fp_big + fp_small // 2)
+    srv = serve.Server(hbm_budget=fp_big + fp_small // 2, alloc_slack=1.0)
     first = req(9, n=100)
     srv.submit(first)
     srv.pump()                                     # the first small one takes some memory
@@ -121,12 +129,16 @@ def test_the_oldest_request_is_not_passed_by_smaller_ones(fake):
     srv.submit(small)
     srv.pump()                                     # the big one does not fit yet: nothing else enters
     assert len(srv.flights) == 1 and [r.rid for r in srv.waiting] == [0, 1]
-    finish(srv.flights[0].batch, [0], done=True)
-    srv.pump()                                     # admission runs before the poll: memory back
+    small_ctx = srv.flights[0].batch
+    finish(small_ctx, [0], done=True)
+    srv.pump()                                     # admission runs before the poll
     assert [r.rid for r in srv.done] == [9] and srv.used == 0 and srv.flights == []
-    srv.pump()                                     # the big one enters first
+    assert srv.held() == fp_small                  # the idle context still holds its memory
+    srv.pump()                                     # it is destroyed so the big one enters first
+    assert small_ctx.closed and srv.idle_batches == []
     assert [[r.rid for r in fl.requests] for fl in srv.flights] == [[0]]
     assert [r.rid for r in srv.waiting] == [1]
+    assert srv.held() <= srv.budget
 
 
 def test_requests_finish_one_by_one_and_memory_returns_with_the_batch(fake):
@@ -150,7 +162,7 @@ def test_requests_finish_one_by_one_and_memory_returns_with_the_batch(fake):
     out = srv.pump()
     assert sorted(r.rid for r in out) == [0, 2]
     assert srv.used == 0 and srv.flights == [] and srv.idle()
-    assert srv.idle_batches == [bt]
+    assert srv.idle_batches == [bt] and srv.held() == 3 * fp
     srv.submit(req(3))
     srv.pump()                                     # the context is reused, not made again
     assert srv.flights[0].batch is bt and len(FakeBatch.made) == 1
@@ -159,7 +171,7 @@ def test_requests_finish_one_by_one_and_memory_returns_with_the_batch(fake):
 
 def test_a_request_larger_than_the_budget_is_refused(fake):
     r = req(0, n=5000)
-    srv = serve.Server(hbm_budget=serve.footprint(r) - 1)
+    srv = serve.Server(hbm_budget=serve.footprint(r) - 1, alloc_slack=1.0)
     with pytest.raises(ValueError):
         srv.submit(r)
     assert srv.idle()
@@ -177,3 +189,104 @@ def test_size_classes_keep_small_requests_apart_from_large_ones(fake):
         plain.submit(req(i, n=n))
     plain.pump()
     assert [[r.rid for r in fl.requests] for fl in plain.flights] == [[0, 1, 2, 3, 4]]
+
+
+def test_memory_held_by_idle_contexts_counts_against_the_budget(fake):
+    """A context keeps the buffers of its largest batch; a later small batch on it does not
+    give them back, and the server counts what is held, not only what it admitted."""
+    big, fp_big = req(0, n=20000), serve.footprint(req(0, n=20000))
+    fp_small = serve.footprint(req(1, n=100))
+    srv = serve.Server(hbm_budget=fp_big + 2 * fp_small, alloc_slack=1.0, max_batches=1)
+    srv.submit(big)
+    srv.pump()
+    finish(srv.flights[0].batch, [0], done=True)
+    srv.pump()
+    (ctx,) = srv.idle_batches
+    srv.submit(req(2, n=100))
+    srv.pump()                                    # reuses the context: it still holds fp_big
+    assert srv.flights[0].batch is ctx and srv.used == fp_small
+    assert srv.held() == fp_big
+    srv.submit(req(3, n=100))
+    srv.submit(req(4, n=100))
+    finish(ctx, [0], done=True)
+    srv.pump()
+    srv.pump()
+    assert srv.held() <= srv.budget
+
+
+def test_slack_for_size_classes(fake):
+    fp = serve.footprint(req(0))
+    srv = serve.Server(hbm_budget=2 * fp)         # default slack 1.5: one request, not two
+    for i in range(2):
+        srv.submit(req(i))
+    srv.pump()
+    assert [len(fl.requests) for fl in srv.flights] == [1]
+
+
+def test_a_batch_at_its_pass_cap_finishes_its_requests_alone(fake, monkeypatch):
+    """HANF_EMAXITER from a batch: finished components are collected, the others are run
+    alone through the plain path (cap n + 1); serving goes on."""
+    from paper_1011_5599_amd import HANF_EMAXITER, HanfError
+
+    ran = []
+
+    class FakePlain:
+        def __init__(self, device):
+            pass
+
+        def __enter__(self):
+            return self
+
+        def __exit__(self, *a):
+            pass
+
+        def load(self, rp, ci):
+            self.n = len(rp) - 1
+            return self
+
+        def init(self, b, seed):
+            ran.append(seed)
+            return self
+
+        def run(self):
+            return np.arange(7, dtype=np.float64)
+
+        def stats(self):
+            return {"spid": -1.0}
+
+    monkeypatch.setattr(serve, "HyperANF", FakePlain)
+    srv = serve.Server(hbm_budget=1 << 30)
+    for i in range(3):
+        srv.submit(req(i))
+    srv.pump()
+    bt = srv.flights[0].batch
+    bt.T[1] = 2
+
+    def poll(ctx):
+        raise HanfError(HANF_EMAXITER, "pass cap reached before the fixpoint")
+
+    monkeypatch.setattr(serve, "hanf_poll", poll)
+    out = srv.pump()
+    assert sorted(r.rid for r in out) == [0, 1, 2]
+    by = {r.rid: r for r in out}
+    assert by[1].T == 2 and not by[1].alone
+    assert by[0].alone and by[2].alone and by[0].T == 6 and ran == [1, 3]
+    assert srv.flights == [] and srv.idle_batches == [bt]
+    srv.submit(req(5))
+    monkeypatch.setattr(serve, "hanf_poll", lambda ctx: (ctx.status, 0))
+    srv.pump()
+    assert len(srv.flights) == 1
+
+
+def test_out_of_device_memory_at_admission_retries_then_fails_alone(fake, monkeypatch):
+    from paper_1011_5599_amd import HANF_ENOMEM, HanfError
+
+    def boom(self, log2m, seeds):
+        raise HanfError(HANF_ENOMEM, "hipMalloc failed")
+
+    monkeypatch.setattr(FakeBatch, "init", boom)
+    srv = serve.Server(hbm_budget=1 << 30)
+    srv.submit(req(0))
+    srv.pump()                                    # nothing in flight to wait for: it fails
+    assert srv.idle() and len(srv.done) == 1 and srv.done[0].error
+    assert all(b.closed for b in FakeBatch.made)
