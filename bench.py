@@ -4,17 +4,23 @@
 One step is a whole HyperANF run on a graph already resident in HBM: graph ingest
 (device-side validation and work schedule), counter initialisation, passes until no
 counter changes, and the statistics (distance distribution, effective diameter, spid).
-The default workload is the symmetric R-MAT graph of scale 22 (2^22 nodes, 2^26 arcs,
-a=.57 b=.19 c=.19 d=.05) with 64 registers per counter and hash seed 7. Late passes are
-systolic (Section 3.3): a symmetric graph is its own transpose, so it is declared as such
-(hanf_transpose_self, --transpose self); for a directed workload the
-transpose is built on the device inside the step (--transpose build) or not used (none).
+The default workload is the web-like graph of 2^24 nodes (lognormal hosts of mean 1000,
+out-degree mean 20, 80% of the arcs intra-host to nearby ids, the rest to a power-law
+in-degree target) with 128 registers per counter and hash seed 1. The same run also times
+the symmetric R-MAT graph of scale 22 (2^26 arcs, 64 registers, hash seed 7), the batched
+workload (512 graphs x 8 hash seeds) against plain runs one after another, and the
+serving workload (a Poisson stream of requests) against sequential first-come runs, each
+under its own key, and each checked for equal results.
 
-Prints one JSON line. `value` = edge-register updates per second over the whole step:
-m * (successor counters actually maximised in, summed over the passes) / step time.
-`roofline` is for the union kernel (the dominant kernel), timed with HIP events on the
-library's stream; `cpu_baseline` times the CPU oracle on the whole run of the same graph,
-multi-threaded over node segments.
+Prints one JSON line. `value` = edge-register updates per second over the whole step of the
+default workload: m * (successor counters actually maximised in, summed over the passes) /
+step time. `method_updates_per_s` counts only the unions the paper's modified-counter
+tracking performs (Section 3.3), taken from a run with the gather-all switch off.
+`roofline` is for the union step (the dominant kernel), timed with HIP events on the
+library's stream: `achieved` counts the bytes it must move through device memory (the
+algorithmic bytes less the successor counters read from a light tile's counters staged in
+LDS), `algorithmic_cache_inclusive` the same rate with every successor counter counted.
+`cpu_baseline` times the CPU oracle on a bounded sample of the default workload.
 """
 from __future__ import annotations
 
@@ -41,6 +47,24 @@ def algorithmic_bytes(rec, n, m):
     if rec.get("systolic"):
         return 8 * rec["rows_read"] + 4 * rec["arcs_scanned"] + rows
     return 4 * (n + 1) + 4 * rec["arcs_scanned"] + rows + n // 4
+
+
+def model_bytes(rec, n, m):
+    """Bytes a union pass must move through device memory: the algorithmic bytes less the
+    successor counters read from a light tile's counters staged in LDS (those rows are read
+    once, as the tile's own counters)."""
+    return algorithmic_bytes(rec, n, m) - m * rec.get("arcs_local", 0)
+
+
+def cpu_threads():
+    """(nproc, threads to use): the CPUs this process may run on, capped by the thread
+    count the machine's share sets (OMP_NUM_THREADS) when there is one."""
+    nproc = len(os.sched_getaffinity(0))
+    try:
+        share = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        share = 0
+    return nproc, (min(nproc, share) if share > 0 else nproc)
 
 
 def measured_traffic(workload):
@@ -73,7 +97,7 @@ def run_cpu_baseline(rp, ci, b, seed, passes, threads):
     maxed_total = 0
     done = 0
     while True:
-        oracle.sum_sizes(c, b)
+        oracle.sum_sizes(c, b, threads)
         if passes > 0 and done >= passes:
             break
         nxt, mod, changed, maxed = oracle.step(rp, ci, b, c, mod, nthreads=threads)
@@ -83,12 +107,32 @@ def run_cpu_baseline(rp, ci, b, seed, passes, threads):
             break
         c = nxt
     el = time.perf_counter() - t0
-    what = "the whole run to the fixpoint" if passes <= 0 else f"initialisation and the first {done} passes"
+    what = "the whole run to the fixpoint" if passes <= 0 else f"initialisation and the first {done} pass(es)"
     return dict(value=(1 << b) * maxed_total / el, unit="edge-register updates/s", cores=threads,
-                kind="oracle",
+                kind="oracle", seconds=round(el, 3), unions=maxed_total,
                 sample=f"{what} of the same graph ({done} passes, {maxed_total} successor unions, "
                        f"N_hat every iteration) in {el:.2f} s, {threads} threads over contiguous "
                        f"node segments")
+
+
+def run_cpu_single_prefix(rp, ci, b, seed, frac_div):
+    """One thread: the first pass (every successor) over the first n / frac_div nodes,
+    from the initial counters (initialisation not timed)."""
+    import numpy as np
+
+    import oracle
+    n = len(rp) - 1
+    k = max(1, n // frac_div)
+    c = oracle.init(n, b, seed)
+    rp_k = np.ascontiguousarray(rp[:k + 1])
+    t0 = time.perf_counter()
+    # the oracle's pass over nodes 0..k-1; their successors may be any node of c
+    _, _, _, maxed = oracle.step(rp_k, ci, b, c, None, nthreads=1)
+    el = time.perf_counter() - t0
+    return dict(value=(1 << b) * maxed / el, unit="edge-register updates/s", cores=1, seconds=round(el, 3),
+                unions=maxed,
+                sample=f"the first pass over the first {k} of {n} nodes ({maxed} successor unions), "
+                       f"initialisation not timed, in {el:.2f} s on one thread")
 
 
 def copy_ceiling_gbs(mib: int = 1024, reps: int = 5):
@@ -129,7 +173,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q)) if len(xs) else None
 
 
-def run_batch_mode(args):
+def run_batch_mode(args, steps=None, warmup=None):
     """Many-graph workload: 512 graphs (lognormal 2^8..2^16 nodes; half Erdos-Renyi with
     8n arcs, half R-MAT with 16n arcs) x 8 hash seeds, m = 64. All 4096 runs are submitted
     at once. Batched: the runs go through batched passes, with grouping and schedule chosen
@@ -194,29 +238,48 @@ def run_batch_mode(args):
                                                    log=lambda m: print(m, file=sys.stderr, flush=True))
     t_tune = time.perf_counter() - t_tune
     print(f"[bench] tuned {best} in {trials} trials, {t_tune:.1f}s", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    for _ in range(warmup):
         run_batched(best)
     torch.cuda.synchronize()
     times, lat = [], []
-    for _ in range(args.steps):
+    for _ in range(steps):
         el, done = run_batched(best)
         times.append(el)
         lat += done
     batched_s = float(np.median(times))
+    # every run's N_hat and T from the last batched step, to compare with its plain run
+    group = best.get("group", G)
+    batched_nt = {}
+    for gi, lo in enumerate(range(0, G, group)):
+        ids = order[lo:lo + group]
+        bt = ctxs[(group, gi)]
+        T = bt.fixpoints()
+        for k, g in enumerate(ids):
+            for s_ in range(S):
+                c = k * S + s_
+                batched_nt[(g, s_)] = (bt.nt(c), int(T[c]))
     # plain runs, one after another, each graph already in HBM
     dev_graphs = [(torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()) for rp, ci in graphs]
     torch.cuda.synchronize()
     h = hanf.HyperANF(0, stream=stream)
     t0 = time.perf_counter()
     plain_lat = []
+    plain_nt = {}
     for g, (rp, ci) in enumerate(dev_graphs):
         h.load(rp, ci)
         for s in range(S):
             h.init(b, seeds[g * S + s])
-            h.run()
+            plain_nt[(g, s)] = h.run()
             h.stats()
             plain_lat.append(time.perf_counter() - t0)
     plain_s = time.perf_counter() - t0
+    for key, nt in plain_nt.items():  # equal results: N_hat within 1e-12, the same T
+        bnt, bT = batched_nt[key]
+        if bT != len(nt) - 1:
+            raise AssertionError(f"batched run {key}: T={bT}, plain T={len(nt) - 1}")
+        np.testing.assert_allclose(bnt, nt, rtol=1e-12, atol=0)
     h.close()
     for bt in ctxs.values():
         bt.close()
@@ -226,7 +289,7 @@ def run_batch_mode(args):
         "metric": "graphs/s (512 graphs x 8 seeds, batched)",
         "value": G / batched_s,
         "unit": "graphs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": round(1000 * batched_s, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
@@ -240,7 +303,19 @@ def run_batch_mode(args):
                   "latency_ms": {"p50": 1000 * percentile(plain_lat, 50),
                                  "p99": 1000 * percentile(plain_lat, 99)}},
         "speedup_vs_plain": plain_s / batched_s,
+        "equal_results": "every run's N_hat within 1e-12 of its plain run, the same T",
     }
+
+
+def batched_leg(args):
+    """The batched workload under its own key: graphs/s and latency batched (tuned) against
+    plain runs one after another, equal results checked."""
+    r = run_batch_mode(args, steps=3, warmup=1)
+    keep = ("value", "unit", "ms_per_step", "config", "runs_per_s", "latency_ms", "plain", "speedup_vs_plain",
+            "equal_results")
+    out = {k: r[k] for k in keep}
+    out["graphs_per_s"] = out.pop("value")
+    return out
 
 
 def run_seeds_mode(args):
@@ -330,7 +405,7 @@ def run_seeds_mode(args):
     }
 
 
-def run_serve_mode(args):
+def run_serve_mode(args, count=None, rates=(0.25, 0.5, 1.0, 2.0)):
     """Serving workload: a Poisson stream of requests, graphs of 2^10..2^22 nodes (lognormal,
     median 2^16), R-MAT or web-like, log2m in {4, 6, 8}, hash seed = request id. Each request
     is first run alone through the plain path to get its service time; sequential serving
@@ -344,7 +419,7 @@ def run_serve_mode(args):
     import paper_1011_5599_amd as hanf
     from paper_1011_5599_amd import serve
 
-    count = args.requests
+    count = args.requests if count is None else count
     specs = graphgen.serve_requests(count)
     torch.cuda.init()
     h = hanf.HyperANF(0)
@@ -353,20 +428,22 @@ def run_serve_mode(args):
         rp, ci = sp["graph"]
         h.load(rp, ci).init(sp["log2m"], sp["seed"])
         h.run()
+    alone = []
     for sp in specs:
         rp, ci = sp["graph"]
         t0 = time.perf_counter()
         h.load(rp, ci).init(sp["log2m"], sp["seed"])
-        h.run()
+        nt = h.run()
         h.stats()
         service.append(time.perf_counter() - t0)
+        alone.append(nt)
     h.close()
     service = np.array(service)
     capacity = count / service.sum()
     rng = np.random.default_rng(7)
     gaps = rng.exponential(1.0, count)
     rows = []
-    for factor in (0.25, 0.5, 1.0, 2.0):
+    for factor in rates:
         lam = factor * capacity
         arrivals = np.cumsum(gaps) / lam
         arrivals -= arrivals[0]
@@ -379,6 +456,10 @@ def run_serve_mode(args):
         srv.batch_sizes, srv.max_flights = [], 0
         srv.serve_trace(reqs)
         srv.close()
+        for r, nt in zip(reqs, alone):  # each result equal to the same request run alone
+            if r.error is not None or r.T != len(nt) - 1:
+                raise AssertionError(f"request {r.rid}: served T={r.T} error={r.error}, alone T={len(nt) - 1}")
+            np.testing.assert_allclose(r.nt, nt, rtol=1e-12, atol=0)
         lat = np.array([r.latency for r in reqs])
         wait = np.array([r.admitted - r.arrival for r in reqs])    # queued before admission
         run = np.array([r.finish - r.admitted for r in reqs])      # admitted to completed
@@ -415,7 +496,156 @@ def run_serve_mode(args):
                    "service_ms": {"p50": 1000 * float(np.percentile(service, 50)),
                                   "p99": 1000 * float(np.percentile(service, 99))}},
         "rates": rows,
+        "equal_results": "every served request's N_hat within 1e-12 of the same request run alone, the same T",
     }
+
+
+def served_leg(args):
+    """The serving workload under its own key: 48 requests at 1x and 2x the sequential
+    capacity, served against sequential first-come runs, equal results checked."""
+    r = run_serve_mode(args, count=48, rates=(1.0, 2.0))
+    out = {k: r[k] for k in ("config", "rates", "equal_results")}
+    out["graphs_per_s_at_2x"] = r["value"]
+    top = r["rates"][-1]
+    out["p50_ms_at_2x"] = top["served"]["p50_ms"]
+    out["p99_ms_at_2x"] = top["served"]["p99_ms"]
+    out["sequential_at_2x"] = top["sequential"]
+    return out
+
+
+def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, with_method=True, log_prefix="[bench]"):
+    """Times whole runs of workload `name` (the graph resident in HBM, ingest included in
+    each step). Returns (result dict, graph) where the dict carries the workload's rate,
+    roofline and per-pass figures."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1011_5599_amd as hanf
+
+    spec = graphgen.WORKLOADS[name]
+    t0 = time.perf_counter()
+    rp, ci = graphgen.workload_graph(spec)
+    gen_s = time.perf_counter() - t0
+    n, arcs = len(rp) - 1, len(ci)
+    b, seed = spec["log2m"], spec["seed"]
+    m = 1 << b
+    print(f"{log_prefix} workload={name} n={n} arcs={arcs} m={m} gen={gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    trp = torch.from_numpy(rp).to(dev)
+    tci = torch.from_numpy(ci).to(dev)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    opts = dict(h_opts)
+    h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
+    packed = opts.get("packed5") == 1  # single runs keep byte registers unless told otherwise
+    rowb = (5 * m) // 8 if packed else m  # bytes of one counter
+    tmode = tmode_arg
+    if tmode == "auto":
+        tmode = "self" if spec.get("symmetric") else "none"
+    if tmode == "self" and not spec.get("symmetric"):
+        print("bench.py: --transpose self needs a symmetric workload", file=sys.stderr)
+        sys.exit(2)
+    R = max(1, runs_per_load)
+
+    def step(ctx):
+        ctx.load(trp, tci)
+        if tmode == "self":
+            ctx.transpose_self()
+        elif tmode == "build":
+            ctx.build_transpose()
+        run_logs = []
+        for r in range(R):
+            ctx.init(b, seed + r)
+            nt = ctx.run()
+            run_logs.append(ctx.pass_log())
+        return nt, ctx.stats(), run_logs
+
+    for i in range(args.warmup):
+        step(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    logs = []
+    for i in range(args.steps):
+        nt, st, run_logs = step(h)
+        logs.extend(run_logs)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    print(f"{log_prefix} {name}: {args.steps} steps in {elapsed:.3f}s, T={st['T']}", file=sys.stderr, flush=True)
+
+    log = logs[-1]
+    gathered = sum(r["arcs_gathered"] for lg in logs[-R:] for r in lg)  # the last step's R runs
+    updates = m * gathered
+    out = {
+        "value": updates / (ms_per_step / 1000.0),
+        "ms_per_step": round(ms_per_step, 4),
+        "config": {"workload": spec_name(name), "n": n, "arcs": arcs, "log2m": b,
+                   "hash_seed": seed, "T": st["T"], "passes": len(log), "transpose": tmode,
+                   "runs_per_load": R,
+                   "registers": "5-bit packed" if packed else "one per byte",
+                   "staged_tiles": any(r.get("arcs_local", 0) > 0 for r in log),
+                   "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
+                                         for r in log)},
+        "gathered_unions": gathered,
+        "dense_equivalent_updates_per_s": m * arcs * sum(len(lg) for lg in logs[-R:]) / (ms_per_step / 1000.0),
+        "graphs_per_s": R * 1000.0 / ms_per_step,
+        "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
+    }
+    if with_method:
+        # the unions of the paper's modified-counter tracking alone: the same run with the
+        # gather-all switch off (untimed); its results must be the timed run's
+        with hanf.HyperANF(0, stream=stream.cuda_stream, dense_switch=0, **{k: v for k, v in opts.items()
+                                                                             if k not in ("dense_switch", "timing")}) as hm:
+            nt_m, _, mlogs = step(hm)
+        np.testing.assert_allclose(nt_m, nt, rtol=1e-12, atol=0)
+        method = sum(r["arcs_gathered"] for lg in mlogs for r in lg)
+        out["method_unions"] = method
+        out["method_updates_per_s"] = m * method / (ms_per_step / 1000.0)
+    if not args.no_timing:
+        all_recs = [r for lg in logs for r in lg]
+        union_ms = sum(r["union_ms"] for r in all_recs)
+        byts = sum(model_bytes(r, n, rowb) for r in all_recs)
+        algo = sum(algorithmic_bytes(r, n, rowb) for r in all_recs)
+        launches = len(all_recs)
+        achieved = byts / (union_ms / 1000.0) / 1e9
+        algo_gbs = algo / (union_ms / 1000.0) / 1e9
+        out["roofline"] = dict(
+            bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+            frac=round(achieved / HBM_PEAK_GBS, 4),
+            traffic=measured_traffic(name + ("_packed5" if packed else "")
+                                     + ("_hubs" if opts.get("hubs", -1) > 0 else "")),
+            kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
+            avg_launch_us=round(1000.0 * union_ms / launches, 2),
+            avg_model_bytes=int(byts / launches),
+            model="per pass: col_idx of the arcs scanned, row_ptr and modified flags, own counters "
+                  "read, new counters written, successor counters gathered from device memory "
+                  "(those read from a light tile's counters staged in LDS are not counted)",
+            algorithmic_cache_inclusive=dict(avg_bytes=int(algo / launches), gbs=round(algo_gbs, 1),
+                                             frac=round(algo_gbs / HBM_PEAK_GBS, 4)))
+        p0 = [lg[0] for lg in logs]
+        ms0 = sum(r["union_ms"] for r in p0) / len(p0)
+        b0 = model_bytes(p0[0], n, rowb)
+        a0 = algorithmic_bytes(p0[0], n, rowb)
+        out["full_pass"] = dict(union_ms=round(ms0, 4), model_gb=round(b0 / 1e9, 4),
+                                gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
+                                frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
+                                algorithmic_gb=round(a0 / 1e9, 4),
+                                algorithmic_gbs=round(a0 / (ms0 / 1000.0) / 1e9, 1),
+                                local_share=round(p0[0].get("arcs_local", 0) / max(1, p0[0]["arcs_gathered"]), 4),
+                                updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0))
+        last = [r for lg in logs[-R:] for r in lg]  # the last step's passes
+        out["per_step_kernel_ms"] = dict(signal_ms=round(sum(r["signal_ms"] for r in last), 4),
+                                         finalize_ms=round(sum(r["finalize_ms"] for r in last), 4),
+                                         reduce_ms=round(sum(r["reduce_ms"] for r in last), 4),
+                                         union_ms=round(sum(r["union_ms"] for r in last), 4))
+        out["pass_model_bytes"] = [model_bytes(r, n, rowb) for r in log]
+        out["pass_union_ms"] = [round(r["union_ms"], 4) for r in log]
+    h.close()
+    del trp, tci
+    torch.cuda.empty_cache()
+    return out, (rp, ci, b, seed)
 
 
 def main():
@@ -423,14 +653,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat22sym")
-    ap.add_argument("--cpu-passes", type=int, default=0, help="0 = whole run to the fixpoint")
+    ap.add_argument("--workload", default="web24")
+    ap.add_argument("--cpu-passes", type=int, default=1,
+                    help="CPU baseline: oracle passes timed on all threads (0 = the whole run)")
+    ap.add_argument("--cpu-single-div", type=int, default=32,
+                    help="CPU baseline: the single-thread leg runs the first pass over n / this many nodes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
     ap.add_argument("--opt", action="append", default=[], help="library option name=value")
+    ap.add_argument("--legs", default="rmat22sym,batched,served",
+                    help="plain mode: comma-separated extra legs after the main workload "
+                         "(rmat22sym, batched, served; empty for none)")
     ap.add_argument("--mode", choices=["plain", "batch", "serve", "seeds"], default="plain",
-                    help="plain: one graph (the default workload); batch: 512 graphs x 8 seeds; "
-                         "serve: Poisson request stream; seeds: many runs of the workload graph")
+                    help="plain: one graph (the default workload) and the extra legs; batch: 512 graphs "
+                         "x 8 seeds; serve: Poisson request stream; seeds: many runs of the workload graph")
     ap.add_argument("--seeds", type=int, default=8, help="seeds mode: runs of the graph")
     ap.add_argument("--requests", type=int, default=96, help="serve mode: number of requests")
     ap.add_argument("--max-batches", type=int, default=4, help="serve mode: batches in flight")
@@ -474,141 +710,58 @@ def main():
         print(json.dumps(run_seeds_mode(args)))
         return
 
-    import numpy as np
-    import torch
-
-    import graphgen
-    import paper_1011_5599_amd as hanf
-
-    spec = graphgen.WORKLOADS[args.workload]
-    t0 = time.perf_counter()
-    rp, ci = graphgen.workload_graph(spec)
-    gen_s = time.perf_counter() - t0
-    n, arcs = len(rp) - 1, len(ci)
-    b, seed = spec["log2m"], spec["seed"]
-    m = 1 << b
-    print(f"[bench] workload={args.workload} n={n} arcs={arcs} m={m} gen={gen_s:.1f}s",
-          file=sys.stderr, flush=True)
-
-    dev = torch.device("cuda:0")
-    trp = torch.from_numpy(rp).to(dev)
-    tci = torch.from_numpy(ci).to(dev)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream(dev)
     opts = dict(timing=0 if args.no_timing else 1)
     for kv in args.opt:
         k, v = kv.split("=")
         opts[k] = int(v)
-    h = hanf.HyperANF(0, stream=stream.cuda_stream, **opts)
-    packed = opts.get("packed5") == 1  # single runs keep byte registers unless told otherwise
-    rowb = (5 * m) // 8 if packed else m  # bytes of one counter
-    tmode = args.transpose
-    if tmode == "auto":
-        tmode = "self" if spec.get("symmetric") else "none"
-    if tmode == "self" and not spec.get("symmetric"):
-        print("bench.py: --transpose self needs a symmetric workload", file=sys.stderr)
-        sys.exit(2)
-
-    R = max(1, args.runs_per_load)
-
-    def step():
-        h.load(trp, tci)
-        if tmode == "self":
-            h.transpose_self()
-        elif tmode == "build":
-            h.build_transpose()
-        run_logs = []
-        for r in range(R):
-            h.init(b, seed + r)
-            nt = h.run()
-            run_logs.append(h.pass_log())
-        return nt, h.stats(), run_logs
-
-    for i in range(args.warmup):
-        step()
-        print(f"[bench] warmup {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    logs = []
-    for i in range(args.steps):
-        nt, st, run_logs = step()
-        logs.extend(run_logs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s, T={st['T']}", file=sys.stderr, flush=True)
-
-    log = logs[-1]
-    updates = m * sum(r["arcs_gathered"] for lg in logs[-R:] for r in lg)  # the last step's R runs
-    value = updates / (ms_per_step / 1000.0)
-
-    roofline = None
-    full_pass = None
-    if not args.no_timing:
-        all_recs = [r for lg in logs for r in lg]
-        union_ms = sum(r["union_ms"] for r in all_recs)
-        byts = sum(algorithmic_bytes(r, n, rowb) for r in all_recs)
-        launches = len(all_recs)
-        achieved = byts / (union_ms / 1000.0) / 1e9
-        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=measured_traffic(args.workload + ("_packed5" if packed else "")
-                                                 + ("_hubs" if opts.get("hubs", -1) > 0 else "")),
-                        kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
-                        avg_launch_us=round(1000.0 * union_ms / launches, 2),
-                        avg_algorithmic_bytes=int(byts / launches))
-        p0 = [lg[0] for lg in logs]
-        ms0 = sum(r["union_ms"] for r in p0) / len(p0)
-        b0 = algorithmic_bytes(p0[0], n, rowb)
-        full_pass = dict(union_ms=round(ms0, 4), algorithmic_gb=round(b0 / 1e9, 4),
-                         gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
-                         updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0),
-                         frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4))
-        last = [r for lg in logs[-R:] for r in lg]  # the last step's passes
-        other = dict(signal_ms=round(sum(r["signal_ms"] for r in last), 4),
-                     finalize_ms=round(sum(r["finalize_ms"] for r in last), 4),
-                     reduce_ms=round(sum(r["reduce_ms"] for r in last), 4),
-                     union_ms=round(sum(r["union_ms"] for r in last), 4))
-    if roofline is not None:
-        # context for the peak: a plain device copy measured on the same GPU, after the timed region
-        cgbs = copy_ceiling_gbs()
-        roofline["copy_ceiling"] = {"gbs": round(cgbs, 1), "frac_of_peak": round(cgbs / HBM_PEAK_GBS, 4),
-                                    "achieved_over_copy": round(roofline["achieved"] / cgbs, 4)}
-    cpu = None
-    if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        cpu = run_cpu_baseline(rp, ci, b, seed, args.cpu_passes, threads)
-
+    main_res, (rp, ci, b, seed) = run_plain(args.workload, args, opts, args.transpose, args.runs_per_load)
     out = {
         "metric": "edge-register updates/s",
-        "value": value,
+        "value": main_res["value"],
         "unit": "edge-register updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": spec_name(args.workload), "n": n, "arcs": arcs, "log2m": b,
-                   "hash_seed": seed, "T": st["T"], "passes": len(log), "transpose": tmode,
-                   "runs_per_load": R,
-                   "registers": "5-bit packed" if packed else "one per byte",
-                   "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
-                                         for r in log)},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "full_pass": full_pass,
-        "per_step_kernel_ms": other if not args.no_timing else None,
-        "dense_equivalent_updates_per_s": m * arcs * sum(len(lg) for lg in logs[-R:]) / (ms_per_step / 1000.0),
-        "graphs_per_s": R * 1000.0 / ms_per_step,
-        "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
-        "pass_algorithmic_bytes": [algorithmic_bytes(r, n, rowb) for r in log],
-        "pass_union_ms": [round(r["union_ms"], 4) for r in log] if not args.no_timing else None,
+        "config": main_res["config"],
+        "roofline": main_res.get("roofline"),
+        "cpu_baseline": None,
     }
-    h.close()
+    for k, v in main_res.items():
+        if k not in out:
+            out[k] = v
+    if out["roofline"] is not None:
+        # context for the peak: a plain device copy measured on the same GPU, after the timed region
+        cgbs = copy_ceiling_gbs()
+        out["roofline"]["copy_ceiling"] = {"gbs": round(cgbs, 1), "frac_of_peak": round(cgbs / HBM_PEAK_GBS, 4),
+                                           "achieved_over_copy": round(out["roofline"]["achieved"] / cgbs, 4)}
+    if not args.no_cpu_baseline:
+        nproc, threads = cpu_threads()
+        cpu = run_cpu_baseline(rp, ci, b, seed, args.cpu_passes, threads)
+        cpu["nproc"] = nproc
+        cpu["single_thread"] = run_cpu_single_prefix(rp, ci, b, seed, args.cpu_single_div)
+        out["cpu_baseline"] = cpu
+        print(f"[bench] cpu baseline: {cpu['sample']}; single thread: {cpu['single_thread']['sample']}",
+              file=sys.stderr, flush=True)
+    del rp, ci
+    legs = [x for x in args.legs.split(",") if x]
+    if "rmat22sym" in legs and args.workload != "rmat22sym":
+        res, g = run_plain("rmat22sym", args, dict(timing=opts["timing"]), "auto", 1)
+        if not args.no_cpu_baseline:
+            nproc, threads = cpu_threads()
+            res["cpu_baseline"] = run_cpu_baseline(*g, 0, threads)
+            res["cpu_baseline"]["nproc"] = nproc
+        out["rmat22sym"] = res
+        del g
+    if "batched" in legs:
+        out["batched"] = batched_leg(args)
+    if "served" in legs:
+        out["served"] = served_leg(args)
     print(json.dumps(out))
 
 
@@ -616,8 +769,9 @@ def spec_name(name):
     return {
         "rmat22sym": "symmetric R-MAT scale 22 (a=.57,b=.19,c=.19), 2^26 arcs, 64 registers, hash seed 7",
         "rmat14": "directed R-MAT scale 14, 262144 arcs, 16 registers, hash seed 1",
-        "web24": "web-like 2^24 nodes, lognormal hosts (mean 1000), out-degree mean 20, intra-host arcs drawn with p=0.8 (53% kept), "
-                 "power-law in-degree 2.1, 128 registers, hash seed 1",
+        "web24": "web-like 2^24 nodes, lognormal hosts (mean 1000), out-degree mean 20, 80% of the arcs "
+                 "intra-host to nearby ids, the rest to power-law in-degree targets (2.1), 128 registers, "
+                 "hash seed 1",
     }.get(name, name)
 
 

@@ -109,7 +109,19 @@ extern "C" {
                                    caller's order; from the second run on, the rewrite pays for
                                    itself). 0: the caller's order */
 
+#define HANF_OPT_STAGE 13       /* LDS staging of light tiles, in passes over every successor: the
+                                   wavefront of a light tile (consecutive ids) first copies the
+                                   tile's counters into LDS, then maximises successors inside
+                                   the tile's id range from there (a tile holds 4 KiB of
+                                   counters: 32 nodes at m = 128). Pays on graphs whose ids
+                                   follow their locality (the hosts of a web graph). -1
+                                   (default): when a sample shows at least a quarter of the
+                                   light nodes' arcs inside their tile; 0 never; 1 always
+                                   (one register per byte only). Results do not change */
+
 /* Tuning and test options (the results never change):
+ *   103  LDS bytes per wavefront for the counters of a staged light tile (HANF_OPT_STAGE):
+ *        2048, 4096 (default), 8192 or 16384;
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
  *   101  the persistent union kernel over listed work units: 0 (default) for systolic
  *        passes, 1 never, 2 for every pass;
@@ -157,6 +169,8 @@ typedef struct {
   int32_t systolic;      /* 1 if only nodes signalled by a modified successor were recomputed */
   int64_t arcs_signalled;/* systolic pass: predecessor arcs of the modified counters followed */
   float signal_ms;       /* systolic signal kernels time (HANF_OPT_TIMING), else 0 */
+  int64_t arcs_local;    /* of arcs_gathered: successor counters read from a light tile's
+                            counters staged in LDS (HANF_OPT_STAGE) instead of device memory */
 } hanf_pass_t;
 
 /* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work
@@ -353,6 +367,24 @@ int hanf_batch_read_estimates(hanf_ctx *ctx, int32_t comp, double *out, int64_t 
 /* hanf_stats of component `comp`. */
 int hanf_batch_stats(hanf_ctx *ctx, int32_t comp, double alpha, double eps, int32_t distinct,
                      hanf_stats_t *out);
+
+/* The paper's a-posteriori figures over many runs of one graph (Section 6; Table 2 reports
+ * them as mean +- standard deviation over 100 runs): for every graph g of the batch, over its
+ * n_seeds runs (components g * n_seeds + s), the mean and the sample standard deviation of
+ * the effective diameter at alpha, the interpolated effective diameter, the average distance
+ * and spid (Sections 4-5; distinct = 1 drops the self-pairs as in hanf_stats). */
+typedef struct {
+  double ed, ied, avg_dist, spid;              /* means over the graph's runs */
+  double ed_sd, ied_sd, avg_dist_sd, spid_sd;  /* sample standard deviations (divisor runs - 1);
+                                                  NaN with one run */
+  int32_t runs;                                /* n_seeds */
+  int32_t distinct;
+} hanf_seed_summary_t;
+
+/* Fills out[0 .. n_graphs-1] (host) for the loaded batch, computed on the device from every
+ * component's N_hat (a component still changing contributes its N_hat so far). HANF_ESTATE
+ * without an initialised batch, HANF_EINVAL for alpha outside (0, 1] or a NULL out. */
+int hanf_batch_seed_summary(hanf_ctx *ctx, double alpha, int32_t distinct, hanf_seed_summary_t *out);
 
 /* hanf_stats of every component in one launch; out has n_components entries (host). */
 int hanf_batch_stats_all(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);

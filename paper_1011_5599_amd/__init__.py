@@ -45,6 +45,7 @@ HANF_OPT_SYSTOLIC = 9
 HANF_OPT_SEEDS_PER_ROW = 10
 HANF_OPT_PACKED5 = 11
 HANF_OPT_HUBS = 12
+HANF_OPT_STAGE = 13
 HANF_FP_COPY_GRAPH = 1
 HANF_FP_TRANSPOSE = 2
 HANF_FP_PACKED5 = 4
@@ -52,6 +53,7 @@ HANF_FP_ORDER = 8
 HANF_OPT_UNROLL = 100
 HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
 HANF_OPT_TRANSPOSE_COUNTING = 102  # 1: build transposes with per-node counters (test option)
+HANF_OPT_STAGE_BYTES = 103  # LDS bytes per wavefront of a staged light tile (tuning option)
 
 ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
                HANF_ESTATE: "ESTATE", HANF_ERANGE: "ERANGE", HANF_EMAXITER: "EMAXITER"}
@@ -71,7 +73,7 @@ class hanf_pass_t(ctypes.Structure):
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
                 ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32),
                 ("systolic", ctypes.c_int32), ("arcs_signalled", ctypes.c_int64),
-                ("signal_ms", ctypes.c_float)]
+                ("signal_ms", ctypes.c_float), ("arcs_local", ctypes.c_int64)]
 
 
 class HanfError(RuntimeError):
@@ -149,15 +151,29 @@ def lib():
             "hanf_batch_read_registers": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_batch_stats": ([vp, i32, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
             "hanf_batch_stats_all": ([vp, dbl, dbl, i32, vp], ctypes.c_int),
+            "hanf_batch_seed_summary": ([vp, dbl, i32, vp], ctypes.c_int),
             "hanf_device_bytes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_trim": ([vp], ctypes.c_int),
         }
+        missing = []
         for name, (args, res) in sig.items():
-            f = getattr(L, name)
+            try:
+                f = getattr(L, name)
+            except AttributeError:  # a library built from older sources: that call raises
+                missing.append(name)
+                continue
             f.argtypes = args
             f.restype = res
+        for name in missing:
+            setattr(L, name, _missing_symbol(name))
         _lib = L
     return _lib
+
+
+def _missing_symbol(name):
+    def call(*_args):
+        raise ImportError(f"{LIB_PATH} does not export {name}: rebuild it from the current sources")
+    return call
 
 
 def hanf_last_error(ctx=None) -> str:
@@ -452,18 +468,39 @@ def hanf_batch_stats(ctx, comp: int, alpha: float = 0.9, eps: float = 0.0, disti
     return {f: getattr(s, f) for f, _ in hanf_stats_t._fields_}
 
 
+STATS_DTYPE = np.dtype({"names": [f for f, _ in hanf_stats_t._fields_],
+                        "formats": [np.float64 if t is ctypes.c_double else np.int32 for _, t in hanf_stats_t._fields_],
+                        "offsets": [getattr(hanf_stats_t, f).offset for f, _ in hanf_stats_t._fields_],
+                        "itemsize": ctypes.sizeof(hanf_stats_t)})  # numpy view of hanf_stats_t
+
+
 def hanf_batch_stats_all(ctx, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False) -> dict:
     """Statistics of every component: dict of numpy arrays (ed, ied, avg_dist, var, spid,
     n_max, d_lo, d_hi, T)."""
     n, _ = hanf_batch_info(ctx, with_T=False)
     # a structured array with the C struct's layout receives the records directly
-    dt = np.dtype({"names": [f for f, _ in hanf_stats_t._fields_],
-                   "formats": [np.float64 if t is ctypes.c_double else np.int32 for _, t in hanf_stats_t._fields_],
-                   "offsets": [getattr(hanf_stats_t, f).offset for f, _ in hanf_stats_t._fields_],
-                   "itemsize": ctypes.sizeof(hanf_stats_t)})
-    arr = np.zeros(max(n, 1), dt)
+    arr = np.zeros(max(n, 1), STATS_DTYPE)
     _check(lib().hanf_batch_stats_all(ctx, alpha, eps, int(distinct), arr.ctypes.data), ctx)
     return {f: arr[f][:n].copy() for f, _ in hanf_stats_t._fields_}
+
+
+class hanf_seed_summary_t(ctypes.Structure):
+    _fields_ = [("ed", ctypes.c_double), ("ied", ctypes.c_double), ("avg_dist", ctypes.c_double),
+                ("spid", ctypes.c_double), ("ed_sd", ctypes.c_double), ("ied_sd", ctypes.c_double),
+                ("avg_dist_sd", ctypes.c_double), ("spid_sd", ctypes.c_double), ("runs", ctypes.c_int32),
+                ("distinct", ctypes.c_int32)]
+
+
+def hanf_batch_seed_summary(ctx, n_graphs: int, alpha: float = 0.9, distinct: bool = False) -> dict:
+    """Per graph: {k_mean, k_std} for k in ed, ied, avg_dist, spid, and runs."""
+    arr = (hanf_seed_summary_t * max(n_graphs, 1))()
+    _check(lib().hanf_batch_seed_summary(ctx, alpha, int(distinct), ctypes.cast(arr, ctypes.c_void_p)), ctx)
+    out = {}
+    for k in ("ed", "ied", "avg_dist", "spid"):
+        out[k + "_mean"] = np.array([getattr(arr[g], k) for g in range(n_graphs)])
+        out[k + "_std"] = np.array([getattr(arr[g], k + "_sd") for g in range(n_graphs)])
+    out["runs"] = np.array([arr[g].runs for g in range(n_graphs)], np.int32)
+    return out
 
 
 # ------------------------------------------------------------------ convenience wrapper
@@ -482,9 +519,9 @@ class HyperANF:
                  "tile_nodes": HANF_OPT_TILE_NODES, "unroll": HANF_OPT_UNROLL,
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
                  "seeds_per_row": HANF_OPT_SEEDS_PER_ROW, "packed5": HANF_OPT_PACKED5,
-                 "hubs": HANF_OPT_HUBS,
+                 "hubs": HANF_OPT_HUBS, "stage": HANF_OPT_STAGE,
                  "union_policy": HANF_OPT_UNION_POLICY,
-                 "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING}
+                 "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING, "stage_bytes": HANF_OPT_STAGE_BYTES}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))
 
@@ -621,18 +658,11 @@ class Batch(HyperANF):
     def stats_all(self, alpha: float = 0.9, eps: float = 0.0, distinct: bool = False):
         return hanf_batch_stats_all(self.ctx, alpha, eps, distinct)
 
-    def seed_summary(self, alpha: float = 0.9):
+    def seed_summary(self, alpha: float = 0.9, distinct: bool = False):
         """A-posteriori statistics over the seeds of each graph (the paper's many low-precision
-        runs, Section 6): mean and empirical standard deviation of ed, ied, average distance
-        and spid, per graph."""
-        st = self.stats_all(alpha)
-        S = self.n_seeds
-        out = {}
-        for k in ("ed", "ied", "avg_dist", "spid"):
-            v = st[k].reshape(-1, S)
-            out[k + "_mean"] = v.mean(axis=1)
-            out[k + "_std"] = v.std(axis=1, ddof=1) if S > 1 else np.zeros(v.shape[0])
-        return out
+        runs, Section 6), computed by the library: mean and sample standard deviation of ed,
+        ied, average distance and spid, per graph (keys k_mean, k_std)."""
+        return hanf_batch_seed_summary(self.ctx, len(self.sizes), alpha, distinct)
 
 
 def rsd(log2m: int, beta: float = 1.06) -> float:

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <new>
@@ -35,6 +36,12 @@ struct Schedule {
   int G = 0;          // lanes per node row the schedule was built for
   int lane_bytes = 0; // bytes per lane of the register format (partial rows)
   int32_t light_max = 0, chunk_arcs = 0, tile_nodes = 0;
+  int32_t tile_base = 0;   // nodes per light tile without staging (option or default)
+  int32_t stage_tile = 0;  // nodes per light tile when staging (0: the format cannot stage)
+  int stage_opt = -1;      // HANF_OPT_STAGE the schedule was built with
+  int stage = 0;           // light tiles stage their rows in LDS (passes over every successor)
+  double near_frac = -1.0; // sampled share of light arcs inside their stage tile (-1: not measured)
+  int32_t lds_wave_bytes = 0;
   int32_t n_tiles = 0, n_chunks = 0, n_heavy = 0;
   int32_t n_chunk_wgs = 0, n_light_wgs = 0, n_fin_wgs = 0;
   int32_t *light = nullptr;
@@ -72,6 +79,8 @@ struct hanf_ctx {
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   int tp_counting = 0;   // 1: build transposes by per-node counters even below kTpMaxNodes
   int64_t hubs_opt = -1; // HANF_OPT_HUBS: -1 auto, 0 the caller's order, K: up to K hubs first
+  int stage_opt = -1;    // HANF_OPT_STAGE: -1 auto, 0 never, 1 whenever the format allows
+  int32_t stage_bytes = kStageWaveBytes;  // LDS per wavefront for a staged tile's counters
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
@@ -435,38 +444,65 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
     tile = (int32_t)(rounds * W);
   }
   tile = std::max(W, std::min(kMaxTile, (tile / W) * W));
-  s.tile_nodes = tile;
+  s.tile_base = s.tile_nodes = tile;
+  // staged tiles: as many rows as kStageWaveBytes of LDS hold, at least one round of W
+  const int32_t row_bytes = G * lane_bytes;
+  const int32_t st = std::min(kMaxTile, (c->stage_bytes / row_bytes) / W * W);
+  s.stage_tile = (lane_bytes == 16 && G <= 16 && c->unroll == 4 && st >= W) ? st : 0;
+  s.stage_opt = c->stage_opt;
 }
+
+// Staging pays when most arcs of light nodes stay inside their tile's id range (the share
+// measured on a sample of the graph); elsewhere it only costs LDS (fewer wavefronts per CU).
+constexpr double kStageMinNear = 0.25;
+constexpr int32_t kLocalityStride = 8;  // every 8th node is sampled
 
 int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   free_schedule(c);
   Schedule &s = c->sch;
   choose_schedule(c, G, lane_bytes, s);
   const int32_t n = c->n;
-  s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
   int rc;
-  if ((rc = dev_alloc(c, &s.light, (size_t)s.n_tiles * s.tile_nodes, "light tiles"))) return rc;
-  HIP_TRY(c, launch_build_tiles(c->rp, n, s.light_max, s.tile_nodes, s.n_tiles, s.light, c->stream),
-          "build tiles");
-  // chunk counts, prefix sums, chunk and heavy lists
+  // chunk counts, prefix sums, chunk and heavy lists; with automatic staging, the locality
+  // sample is read in the same wait
+  const bool measure = s.stage_opt < 0 && s.stage_tile > 0;
   uint64_t *keys = nullptr, *tmp = nullptr;
-  if ((rc = dev_alloc(c, &keys, (size_t)n + 1, "schedule keys"))) return rc;
+  if ((rc = dev_alloc(c, &keys, (size_t)n + 3, "schedule keys"))) return rc;
   if ((rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
     dev_release(c, keys);
     return rc;
   }
   hipError_t e = launch_classify(c->rp, n, s.light_max, s.chunk_arcs, keys, c->stream);
   if (e == hipSuccess) e = launch_exclusive_scan_u64(keys, (int64_t)n + 1, tmp, c->stream);
-  uint64_t total = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&total, keys + n, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && measure)
+    e = launch_locality(c->rp, c->ci, n, s.light_max, s.stage_tile, kLocalityStride, keys + n + 1, c->stream);
+  uint64_t total[3] = {0, 0, 0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(total, keys + n, sizeof(uint64_t) * (measure ? 3 : 1), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     dev_release(c, keys);
     dev_release(c, tmp);
     return hip_fail(c, e, "schedule scan");
   }
-  s.n_chunks = (int32_t)(total >> 32);
-  s.n_heavy = (int32_t)(total & 0xffffffffull);
+  s.n_chunks = (int32_t)(total[0] >> 32);
+  s.n_heavy = (int32_t)(total[0] & 0xffffffffull);
+  if (measure) s.near_frac = total[1] ? (double)total[2] / (double)total[1] : 0.0;
+  s.stage = s.stage_tile > 0 && (s.stage_opt == 1 || (measure && s.near_frac >= kStageMinNear));
+  if (s.stage) s.tile_nodes = s.stage_tile;
+  s.lds_wave_bytes = s.stage ? s.tile_nodes * G * lane_bytes : ((s.tile_nodes * 4 + 15) / 16) * 16;
+  s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
+  if ((rc = dev_alloc(c, &s.light, (size_t)s.n_tiles * s.tile_nodes, "light tiles"))) {
+    dev_release(c, keys);
+    dev_release(c, tmp);
+    return rc;
+  }
+  e = launch_build_tiles(c->rp, n, s.light_max, s.tile_nodes, s.n_tiles, s.light, c->stream);
+  if (e != hipSuccess) {
+    dev_release(c, keys);
+    dev_release(c, tmp);
+    return hip_fail(c, e, "build tiles");
+  }
   const size_t row_bytes = (size_t)G * s.lane_bytes;
   if ((rc = dev_alloc(c, &s.chunks, (size_t)s.n_chunks, "chunks")) ||
       (rc = dev_alloc(c, &s.heavy, (size_t)s.n_heavy, "heavy nodes")) ||
@@ -484,7 +520,7 @@ int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
   s.n_light_wgs = (s.n_tiles + 3) / 4;
   s.n_fin_wgs = (s.n_heavy + 3) / 4;
-  if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * 4, "work counters")) ||
+  if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * kStatFields, "work counters")) ||
       (rc = dev_alloc(c, &s.tile_todo, ((size_t)s.n_tiles + 3) / 4 * 4, "tile flags")) ||
       (rc = dev_alloc(c, &s.unit_list, (size_t)s.n_chunks + s.n_tiles, "work unit list")))
     return rc;
@@ -536,6 +572,8 @@ void fill_args(hanf_ctx *c) {
   a.n_tiles = c->sch.n_tiles;
   a.tile_nodes = c->sch.tile_nodes;
   a.light_max = c->sch.light_max;
+  a.stage = c->sch.stage;
+  a.lds_wave_bytes = c->sch.lds_wave_bytes;
   a.n_heavy = c->sch.n_heavy;
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;
@@ -1177,6 +1215,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < -1 || value > INT32_MAX) return fail(c, HANF_EINVAL, "hubs must be -1 (auto), 0 or a count");
       c->hubs_opt = value;
       break;
+    case HANF_OPT_STAGE:
+      if (value < -1 || value > 1) return fail(c, HANF_EINVAL, "stage must be -1 (auto), 0 or 1");
+      c->stage_opt = (int)value;
+      break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
       if (value < 0 || value > 2) return fail(c, HANF_EINVAL, "union policy must be 0, 1 or 2");
       c->union_policy = (int)value;
@@ -1184,6 +1226,11 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
     case 102:  // transpose build: 0 bucket sort up to 2^26 nodes, 1 always per-node counters; used by tests
       if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "transpose build must be 0 or 1");
       c->tp_counting = (int)value;
+      break;
+    case 103:  // LDS bytes per wavefront for a staged tile (2048, 4096, 8192 or 16384); used by the tuner
+      if (value != 2048 && value != 4096 && value != 8192 && value != 16384)
+        return fail(c, HANF_EINVAL, "stage bytes must be 2048, 4096, 8192 or 16384");
+      c->stage_bytes = (int32_t)value;
       break;
     case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
       if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
@@ -1426,7 +1473,8 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   Schedule want;
   choose_schedule(c, G, lane_bytes, want);
   if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
-      want.chunk_arcs != c->sch.chunk_arcs || want.tile_nodes != c->sch.tile_nodes) {
+      want.chunk_arcs != c->sch.chunk_arcs || want.tile_base != c->sch.tile_base ||
+      want.stage_opt != c->sch.stage_opt || want.stage_tile != c->sch.stage_tile) {
     if ((rc = build_schedule(c, G, lane_bytes))) return rc;
   }
   size_t n_cchunks_before = c->cchunk_comp_h.size();
@@ -1588,6 +1636,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.gather_all = (int32_t)recs[i].gather_all;
         r.systolic = (int32_t)recs[i].systolic;
         r.arcs_signalled = recs[i].signalled;
+        r.arcs_local = recs[i].local;
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * kPassEvents];
           (void)hipEventElapsedTime(&r.signal_ms, e[0], e[1]);
@@ -2247,31 +2296,44 @@ int hanf_batch_stats_all(hanf_ctx *c, double alpha, double eps, int32_t distinct
   if (!out) return fail(c, HANF_EINVAL, "out is NULL");
   if (!(alpha > 0.0 && alpha <= 1.0) || !(eps >= 0.0)) return fail(c, HANF_EINVAL, "alpha or eps out of range");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
-  double *dbuf = nullptr;
+  StatsRec *dbuf = nullptr;
   int rc;
-  if ((rc = dev_alloc(c, &dbuf, (size_t)c->n_comp * 9, "statistics"))) return rc;
-  std::vector<double> buf((size_t)c->n_comp * 9);
+  if ((rc = dev_alloc(c, &dbuf, (size_t)c->n_comp, "statistics"))) return rc;
   hipError_t e = launch_stats_all(c->args, alpha, eps, distinct ? 1 : 0, dbuf, c->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(buf.data(), dbuf, sizeof(double) * buf.size(), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(out, dbuf, sizeof(StatsRec) * (size_t)c->n_comp, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   dev_release(c, dbuf);
   if (e != hipSuccess) return hip_fail(c, e, "statistics");
-  for (int32_t k = 0; k < c->n_comp; ++k) {
-    const double *b = &buf[(size_t)k * 9];
-    out[k].ed = b[0];
-    out[k].ied = b[1];
-    out[k].avg_dist = b[2];
-    out[k].var = b[3];
-    out[k].spid = b[4];
-    out[k].n_max = b[5];
-    out[k].d_lo = b[6];
-    out[k].d_hi = b[7];
-    out[k].T = (int32_t)b[8];
-    out[k].distinct = distinct ? 1 : 0;
-  }
   return HANF_OK;
 }
+
+int hanf_batch_seed_summary(hanf_ctx *c, double alpha, int32_t distinct, hanf_seed_summary_t *out) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_seed_summary: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (!(alpha > 0.0 && alpha <= 1.0)) return fail(c, HANF_EINVAL, "alpha must be in (0, 1]");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  SummaryRec *dbuf = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &dbuf, (size_t)c->n_graphs, "seed summary"))) return rc;
+  hipError_t e = launch_seed_summary(c->args, c->n_graphs, c->n_seeds, alpha, distinct ? 1 : 0, dbuf, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dbuf, sizeof(SummaryRec) * (size_t)c->n_graphs, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_release(c, dbuf);
+  if (e != hipSuccess) return hip_fail(c, e, "seed summary");
+  return HANF_OK;
+}
+
+static_assert(sizeof(SummaryRec) == sizeof(hanf_seed_summary_t), "SummaryRec must have hanf_seed_summary_t's layout");
+static_assert(offsetof(SummaryRec, runs) == offsetof(hanf_seed_summary_t, runs),
+              "SummaryRec must have hanf_seed_summary_t's layout");
+
+static_assert(sizeof(StatsRec) == sizeof(hanf_stats_t), "StatsRec must have hanf_stats_t's layout");
+static_assert(offsetof(StatsRec, T) == offsetof(hanf_stats_t, T), "StatsRec must have hanf_stats_t's layout");
+static_assert(offsetof(StatsRec, distinct) == offsetof(hanf_stats_t, distinct),
+              "StatsRec must have hanf_stats_t's layout");
 
 int hanf_device_bytes(const hanf_ctx *c, int64_t *held, int64_t *pooled) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_device_bytes: NULL context");

@@ -14,6 +14,8 @@ constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
+constexpr int kStatFields = 5;     // work counters per row: scanned, gathered, written, read, local
+constexpr int kStageWaveBytes = 4096;  // LDS per wavefront for the rows of a staged light tile
 constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
 constexpr int kPacked5LaneBytes = 40;   // 64 registers of 5 bits: one lane of a packed counter
 constexpr int kMaxPassesPerCheck = 1024;  // passes enqueued between host reads of the run state
@@ -46,6 +48,7 @@ struct DevState {
 
 struct PassLog {  // per executed pass, filled on the device
   int64_t changed, scanned, gathered, written, read, gather_all, systolic, signalled;
+  int64_t local;  // successor counters maximised in from a light tile's rows staged in LDS
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
@@ -102,6 +105,23 @@ __host__ __device__ inline void stats_of(const double *nt, int32_t T, double alp
 }
 
 
+// One component's statistics as the public hanf_stats_t lays them out (ed, ied, avg_dist,
+// var, spid, n_max, d_lo, d_hi, then T and distinct), so records written on the device can
+// be copied into the caller's array as they are.
+struct StatsRec {
+  double v[8];
+  int32_t T;
+  int32_t distinct;
+};
+
+// Per-graph summary of a batch's runs as the public hanf_seed_summary_t lays it out: means
+// of ed, ied, avg_dist, spid, then their sample standard deviations, then runs and distinct.
+struct SummaryRec {
+  double v[8];
+  int32_t runs;
+  int32_t distinct;
+};
+
 // Layout of a batched run. Its results are components c = (graph g, seed s), independent
 // runs. Every node row holds S = 2^seed_log2 counters ("row seeds" j = 0..S-1), so the
 // graphs are laid side by side as one graph in copies ("layout components" L), each
@@ -142,7 +162,7 @@ struct PassArgs {
   double *blocksum;          // per 64 nodes and row seed, [b * S + j]
   double *wgsum;             // per reduce workgroup
   int64_t *wgcnt;            // per reduce workgroup: changed counters
-  int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read}
+  int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read, local}
   const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
   const Chunk *chunks;
   const Heavy *heavy;
@@ -174,6 +194,11 @@ struct PassArgs {
   int32_t n_tiles;
   int32_t tile_nodes;
   int32_t light_max;         // nodes with more arcs are handled by chunks
+  int32_t stage;             // 1: in passes over every successor, a light tile's wavefront first
+                             //   copies the rows of c_t of the tile's id range into LDS, and
+                             //   successors in that range are maximised in from there
+  int32_t lds_wave_bytes;    // dynamic LDS per wavefront of the union kernels: the list of
+                             //   active nodes of a tile or, when staging, its rows (shared)
   int32_t n_heavy;
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;
@@ -190,6 +215,10 @@ hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32
                            DevState *st, hipStream_t s);
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
                               int64_t dense_threshold, int32_t sys_div, hipStream_t s);
+// Near arcs of light nodes, sampled: out[0] += light arcs of every `stride`-th node, out[1] +=
+// those whose target lies in the source's aligned block of `block` ids. out is zeroed here.
+hipError_t launch_locality(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t light_max,
+                           int32_t block, int32_t stride, uint64_t *out, hipStream_t s);
 hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
                            uint64_t *keys, hipStream_t s);
 // exclusive scan of n uint64 values in place; `tmp` needs scan_tmp_elems(n) elements
@@ -264,8 +293,10 @@ hipError_t launch_expand_local(const int32_t *graph_off, const int32_t *arc_off,
                                int64_t e_exp, DevState *st, hipStream_t s);
 hipError_t launch_check_offsets(const int32_t *rp, const int32_t *goff, const int32_t *aoff, int32_t n_graphs,
                                 DevState *st, hipStream_t s);
-hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, double *out,
+hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, StatsRec *out,
                             hipStream_t s);
+hipError_t launch_seed_summary(const PassArgs &a, int32_t n_graphs, int32_t n_seeds, double alpha, int32_t distinct,
+                               SummaryRec *out, hipStream_t s);
 hipError_t launch_expand(const int32_t *graph_off, const int32_t *rp_in, const int32_t *ci_in,
                          int32_t n_seeds, const PassArgs &a, const int32_t *comp_arc_off, int32_t *rp_exp,
                          int32_t *ci_exp, int64_t n_exp, int64_t e_exp, DevState *st, hipStream_t s);

@@ -76,6 +76,7 @@ struct ByteRegs {
   static constexpr int kRegs = 16;
   static constexpr int kBytes = 16;
   static constexpr bool kEstimateInUnion = true;  // the union kernel writes changed estimates
+  static constexpr bool kStageable = true;        // light tiles may stage their rows in LDS
   static __device__ __forceinline__ Lane zero() { return zero4(); }
   static __device__ __forceinline__ Lane load(const uint8_t *regs, int64_t row, int G, int sub) {
     return *reinterpret_cast<const uint4 *>(regs + ((size_t)row * G + sub) * kBytes);
@@ -130,6 +131,7 @@ struct Packed5Regs {
   };
   static constexpr int kRegs = 64;
   static constexpr int kBytes = 40;
+  static constexpr bool kStageable = false;
   // Estimates of changed counters come from k_estimate_changed after the union step: the
   // 64 field extractions would otherwise raise the union kernel's register count (and
   // lower its occupancy) for a step that runs once per changed node.
@@ -319,8 +321,13 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *s
 }
 
 struct Counters {
-  int32_t scanned = 0, gathered = 0, written = 0, read = 0;
+  int32_t scanned = 0, gathered = 0, written = 0, read = 0, local = 0;
 };
+
+// A lane's part of row r of a light tile staged in LDS (byte registers, rows of G lanes).
+__device__ __forceinline__ uint4 stage_row(const uint8_t *stage, int32_t r, int G, int sub) {
+  return *reinterpret_cast<const uint4 *>(stage + ((size_t)r * G + sub) * 16);
+}
 
 // Writes c_{t+1}[v] for the node of a slot, given `acc`, the max over the successors
 // maximised in (and over c_t[v] when own_loaded). Called with all 64 lanes active; idle
@@ -371,9 +378,10 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
 // G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
 // in (all of them, or those modified by the previous pass), compact the kept ids into the
 // slot's queue in LDS and gather the queued counters U at a time.
-template <class F, int G, int U>
+template <class F, int G, int U, bool ST>
 __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
-                                            int32_t *queue, Counters &cnt, bool count_scan) {
+                                            int32_t *queue, Counters &cnt, bool count_scan,
+                                            const uint8_t *stage, bool staged, int32_t lo) {
   using Lane = typename F::Lane;
   const int sub = lane % G;
   const int first = lane & ~(G - 1);
@@ -391,11 +399,16 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
   Lane own = F::zero(), acc = F::zero();
   bool own_loaded = false;
   if (end > beg) {
-    own = F::load(f.cur, v, G, sub);
+    // (two one-sided branches, not an if-else: the compiler would merge the two loads into
+    // one flat load through a selected pointer)
+    if (!staged) own = F::load(f.cur, v, G, sub);
+    if constexpr (ST) {
+      if (staged) own = stage_row(stage, v - lo, G, sub);
+    }
     if (f.gather_all) acc = own;
     own_loaded = true;
   }
-  int32_t gathered = 0;
+  int32_t gathered = 0, local = 0;
   for (int32_t p = beg; p < end; p += G * U) {
     int32_t w[U];
     bool ok[U];
@@ -420,8 +433,34 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     __builtin_amdgcn_wave_barrier();
     for (int32_t j = 0; j < total; j += U) {
       Lane x[U];
+      if constexpr (ST) {
+        if (staged) {  // successors in the tile's id range come from its rows in LDS
+          int32_t w[U];
+          bool in[U];
 #pragma unroll
-      for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
+          for (int i = 0; i < U; ++i) {
+            w[i] = j + i < total ? q[j + i] : lo - 1;
+            in[i] = (uint32_t)(w[i] - lo) < (uint32_t)a.tile_nodes;
+            x[i] = F::zero();
+          }
+#pragma unroll
+          for (int i = 0; i < U; ++i)
+            if (j + i < total && !in[i]) x[i] = F::load(f.cur, w[i], G, sub);
+#pragma unroll
+          for (int i = 0; i < U; ++i) {
+            if (in[i]) {
+              x[i] = stage_row(stage, w[i] - lo, G, sub);
+              ++local;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
+      }
 #pragma unroll
       for (int i = 0; i < U; ++i) acc = F::max(acc, x[i]);
     }
@@ -430,7 +469,10 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
-  if (sub == 0) cnt.gathered += gathered;
+  if (sub == 0) {
+    cnt.gathered += gathered;
+    cnt.local += local;
+  }
   finalize_slot<F, G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
 }
 
@@ -663,22 +705,24 @@ __device__ __forceinline__ T wave_sum(T x) {
 // Adds the workgroup's work counters to one of kStatSlots slot rows (spread to avoid
 // contention); k_reduce_top sums and clears the slots.
 __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *slots) {
-  __shared__ int32_t red[4][kBlockThreads / kWave];
+  __shared__ int32_t red[kStatFields][kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written),
-                s3 = wave_sum(c.read);
+                s3 = wave_sum(c.read), s4 = wave_sum(c.local);
   if (lane == 0) {
     red[0][wave] = s0;
     red[1][wave] = s1;
     red[2][wave] = s2;
     red[3][wave] = s3;
+    red[4][wave] = s4;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (threadIdx.x < kStatFields) {
     int64_t tot = 0;
     for (int i = 0; i < kBlockThreads / kWave; ++i) tot += red[threadIdx.x][i];
-    if (tot) atomicAdd(reinterpret_cast<unsigned long long *>(slots + (blockIdx.x % kStatSlots) * 4 + threadIdx.x),
-                       (unsigned long long)tot);
+    if (tot)
+      atomicAdd(reinterpret_cast<unsigned long long *>(slots + (blockIdx.x % kStatSlots) * kStatFields + threadIdx.x),
+                (unsigned long long)tot);
   }
 }
 
@@ -686,24 +730,65 @@ __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *s
 
 // One light tile handled by one wavefront: every node when the pass maximises with all
 // successors, else the active nodes found by find_active, W nodes per round.
-template <class F, int G, int U>
+// In a pass over every successor with a.stage set, the wavefront first copies the rows of c_t
+// of the tile's id range [lo, hi) into `lds` (the wavefront's share of the dynamic LDS;
+// 16 bytes per lane and load, four loads in flight): the tile's own counters, and the
+// successor counters of arcs that stay inside the range (most arcs of a graph whose ids
+// follow its locality, such as the hosts of a web graph), are then read from LDS. In other
+// passes `lds` holds the list of active nodes.
+template <class F, int G, int U, bool ST>
 __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int lane, int32_t *qw,
-                                             int32_t *act, int32_t *rps, Counters &cnt) {
+                                             uint8_t *lds, int32_t *rps, Counters &cnt) {
   constexpr int W = kWave / G;
   const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
+  const int32_t lo = tile * a.tile_nodes;
   const int slot = lane / G;
-  const int32_t *list = tl;
+  int32_t *act = reinterpret_cast<int32_t *>(lds);
   int32_t count = a.tile_nodes;
+  bool staged = false;  // `lds` holds the tile's rows (never a null pointer: its address space stays known)
   if (!f.gather_all) {
     count = find_active<U>(a, f, tl, tile, a.light_max, lane, rps, act, cnt);
-    list = act;
+  } else if constexpr (ST) {
+    {
+      const int32_t hi = min(a.n, lo + a.tile_nodes);
+      const int32_t n16 = (int32_t)(((int64_t)(hi - lo) * G * F::kBytes) >> 4);
+      const uint4 *src = reinterpret_cast<const uint4 *>(f.cur + (size_t)lo * G * F::kBytes);
+      uint4 *dst = reinterpret_cast<uint4 *>(lds);
+      for (int32_t b = 0; b < n16; b += 4 * kWave) {
+        uint4 t[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int32_t i = b + k * kWave + lane;
+          t[k] = i < n16 ? src[i] : zero4();
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int32_t i = b + k * kWave + lane;
+          if (i < n16) dst[i] = t[k];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      staged = true;
+    }
   }
   // arcs read here are counted unless find_active already scanned them
   const bool count_scan = f.gather_all || f.systolic;
   for (int32_t r = 0; r < count; r += W) {
-    const int32_t v = r + slot < count ? list[r + slot] : -1;
+    // the node list is the tile's (device memory) or the active nodes (LDS); staged kernels
+    // read it with two one-sided loads, so that neither becomes a flat load through a
+    // selected pointer
+    const bool in = r + slot < count;
+    int32_t v = -1;
+    if constexpr (ST) {
+      if (in && f.gather_all) v = tl[r + slot];
+      if (in && !f.gather_all) v = act[r + slot];
+    } else {  // (a selected pointer here costs one flat load per round but one VGPR less)
+      const int32_t *list = f.gather_all ? tl : act;
+      v = in ? list[r + slot] : -1;
+    }
     if (!__any(v >= 0)) break;  // empty tile entries sort last
-    light_round<F, G, U>(a, f, v, lane, qw, cnt, count_scan);
+    light_round<F, G, U, ST>(a, f, v, lane, qw, cnt, count_scan, lds, staged, lo);
   }
 }
 
@@ -720,7 +805,7 @@ __device__ __forceinline__ bool wide_systolic(const PassArgs &a, const DevState 
 // n_chunk_wgs take 4 chunks each, the others 4 light tiles (XCD-aware order). With
 // `list_too` set, k_union_list runs the systolic passes that signal few arcs and this
 // kernel leaves them at once.
-template <class F, int G, int U>
+template <class F, int G, int U, bool ST>
 __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t list_too) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -728,8 +813,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
   if (list_too && f.systolic && !wide_systolic(a, st)) return;
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
-  __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
   __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
@@ -739,7 +824,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
     if (tile < a.n_tiles)
-      process_tile<F, G, U>(a, f, tile, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1), cnt);
+      process_tile<F, G, U, ST>(a, f, tile, lane, qw, reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
+                            rp_buf + wave * (kWave + 1), cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
@@ -749,7 +835,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
 // per wavefront at a time. With `full_too` set, k_union runs the other passes (and the
 // systolic ones that signal many arcs) and this kernel leaves at once. Its grid is far smaller than one wavefront per unit, so a pass in
 // which few nodes are active costs few launches.
-template <class F, int G, int U>
+template <class F, int G, int U, bool ST>
 __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_t full_too) {
   const DevState *st = a.st;
   if (st->halted) return;
@@ -757,8 +843,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
   if (full_too && !(f.systolic && !wide_systolic(a, st))) return;
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
-  __shared__ int32_t act_buf[(kBlockThreads / kWave) * kMaxTile];
   __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int32_t *qw = queue + wave * kWave * U;
   const int64_t total = f.systolic ? (int64_t)st->sys_units : (int64_t)a.n_chunks + a.n_tiles;
@@ -768,8 +854,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
     if (u < a.n_chunks)
       chunk_wave<F, G, U>(a, f, u, lane, qw, cnt);
     else
-      process_tile<F, G, U>(a, f, u - a.n_chunks, lane, qw, act_buf + wave * kMaxTile, rp_buf + wave * (kWave + 1),
-                         cnt);
+      process_tile<F, G, U, ST>(a, f, u - a.n_chunks, lane, qw,
+                            reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
+                            rp_buf + wave * (kWave + 1), cnt);
   }
   add_block_counters(cnt, a.stat_slots);
 }
@@ -1099,23 +1186,24 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kTopThreads];
-  __shared__ int64_t s_i[5][kTopThreads];
+  __shared__ int64_t s_i[6][kTopThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
-  int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0;
+  int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0, lo = 0;
   for (int32_t i = tid; i < a.n_reduce_wgs; i += kTopThreads) {
     s += a.wgsum[i];
     c += a.wgcnt[i];
   }
   if (tid < kStatSlots) {
-    int64_t *sl = a.stat_slots + tid * 4;
+    int64_t *sl = a.stat_slots + tid * kStatFields;
     if (mode == kReducePass) {
       sc = sl[0];
       ga = sl[1];
       wr = sl[2];
       rd = sl[3];
+      lo = sl[4];
     }
-    sl[0] = sl[1] = sl[2] = sl[3] = 0;
+    sl[0] = sl[1] = sl[2] = sl[3] = sl[4] = 0;
   }
   s_sum[tid] = s;
   s_i[0][tid] = c;
@@ -1123,11 +1211,12 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   s_i[2][tid] = ga;
   s_i[3][tid] = wr;
   s_i[4][tid] = rd;
+  s_i[5][tid] = lo;
   __syncthreads();
   for (int off = kTopThreads / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_sum[tid] += s_sum[tid + off];
-      for (int k = 0; k < 5; ++k) s_i[k][tid] += s_i[k][tid + off];
+      for (int k = 0; k < 6; ++k) s_i[k][tid] += s_i[k][tid + off];
     }
     __syncthreads();
   }
@@ -1145,6 +1234,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       rec.gathered = s_i[2][0];
       rec.written = s_i[3][0];
       rec.read = s_i[4][0];
+      rec.local = s_i[5][0];
       rec.systolic = st->systolic;
       rec.signalled = rec.systolic ? (int64_t)(st->sys_acc & 0xffffffffull) : 0;
       if (p < a.log_cap) a.log[p] = rec;
@@ -1386,6 +1476,31 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_units(PassArgs a) {
 }
 
 // ------------------------------------------------------------------ kernels: transposed graph
+
+// Sampled locality of the light nodes' arcs: for every `stride`-th node with 1..light_max
+// arcs, its arcs and those whose target lies in the source's aligned block of `block` ids
+// (the id range of a light tile), summed into out[0] and out[1].
+__global__ __launch_bounds__(kBlockThreads) void k_locality(const int32_t *rp, const int32_t *ci, int32_t n,
+                                                           int32_t light_max, int32_t block, int32_t stride,
+                                                           unsigned long long *out) {
+  const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
+  uint32_t tot = 0, near = 0;
+  if (v64 < n) {
+    const int32_t v = (int32_t)v64;
+    const int32_t b = rp[v], e = rp[v + 1];
+    if (e - b <= light_max) {
+      const int32_t lo = v - v % block;
+      for (int32_t p = b; p < e; ++p) near += (uint32_t)(ci[p] - lo) < (uint32_t)block ? 1u : 0u;
+      tot = (uint32_t)(e - b);
+    }
+  }
+  tot = wave_sum(tot);
+  near = wave_sum(near);
+  if ((threadIdx.x & 63) == 0 && tot) {
+    atomicAdd(out, (unsigned long long)tot);
+    atomicAdd(out + 1, (unsigned long long)near);
+  }
+}
 
 __global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t value) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1880,12 +1995,62 @@ __global__ void k_stats(const double *nt, const int32_t *T_or_null, const DevSta
   stats_of(nt, T, alpha, eps, distinct, out);
 }
 
-// Statistics of every component of a batch, one thread each: out[c * 9 + k].
-__global__ void k_stats_all(PassArgs a, double alpha, double eps, int32_t distinct, double *out) {
+// Statistics of every component of a batch, one thread each: record out[c] (every field
+// written, so `out` needs no clearing).
+__global__ void k_stats_all(PassArgs a, double alpha, double eps, int32_t distinct, StatsRec *out) {
   const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.batch.n_comp) return;
   const int32_t Tc = a.batch.comp_T[c];
-  stats_of(a.batch.comp_nt + (size_t)c * a.nt_cap, Tc >= 0 ? Tc : a.st->t, alpha, eps, distinct, out + (size_t)c * 9);
+  double b[9];
+  stats_of(a.batch.comp_nt + (size_t)c * a.nt_cap, Tc >= 0 ? Tc : a.st->t, alpha, eps, distinct, b);
+  StatsRec r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r.v[k] = b[k];
+  r.T = (int32_t)b[8];
+  r.distinct = distinct;
+  out[c] = r;
+}
+
+// The paper's a-posteriori figures over many runs of one graph (Section 6): for graph g
+// (components g * n_seeds .. g * n_seeds + n_seeds - 1, one thread per graph), the mean of
+// ed, ied, the average distance and spid over its runs, then their sample standard deviation
+// (n_seeds - 1 in the denominator, two passes over the runs; NaN with one run).
+__global__ void k_seed_summary(PassArgs a, int32_t n_graphs, int32_t n_seeds, double alpha, int32_t distinct,
+                               SummaryRec *out) {
+  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_graphs) return;
+  constexpr int kPick[4] = {0, 1, 2, 4};  // ed, ied, avg_dist, spid in stats_of's output
+  double mean[4] = {0.0, 0.0, 0.0, 0.0}, ss[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int32_t s = 0; s < n_seeds; ++s) {
+      const int32_t c = g * n_seeds + s;
+      const int32_t Tc = a.batch.comp_T[c];
+      double b[9];
+      stats_of(a.batch.comp_nt + (size_t)c * a.nt_cap, Tc >= 0 ? Tc : a.st->t, alpha, 0.0, distinct, b);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double x = b[kPick[k]];
+        if (pass == 0) {
+          mean[k] += x;
+        } else {
+          const double d = x - mean[k];
+          ss[k] += d * d;
+        }
+      }
+    }
+    if (pass == 0)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) mean[k] /= (double)n_seeds;
+  }
+  SummaryRec r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.v[k] = mean[k];
+    r.v[4 + k] = n_seeds > 1 ? sqrt(ss[k] / (double)(n_seeds - 1)) : __builtin_nan("");
+  }
+  r.runs = n_seeds;
+  r.distinct = distinct;
+  out[g] = r;
 }
 
 __global__ void k_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
@@ -2066,6 +2231,16 @@ void launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, hi
     hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
 }
 
+// The same with `lds` bytes of dynamic LDS per workgroup.
+template <typename... KArgs, typename... Args>
+void launch_k_lds(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t e0,
+                  hipEvent_t e1, Args... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
 // Events of a group that launched no kernel: recorded on the stream instead.
 hipError_t record_empty(hipEvent_t e0, hipEvent_t e1, hipStream_t s) {
   if (e0) (void)hipEventRecord(e0, s);
@@ -2114,6 +2289,16 @@ hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEven
 
 hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_locality(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t light_max,
+                           int32_t block, int32_t stride, uint64_t *out, hipStream_t s) {
+  hipError_t e = launch_fill_u64(out, 2, 0ull, s);
+  if (e != hipSuccess) return e;
+  const int64_t sampled = ((int64_t)n + stride - 1) / stride;
+  hipLaunchKernelGGL(k_locality, dim3((unsigned)((sampled + kBlockThreads - 1) / kBlockThreads)), dim3(kBlockThreads),
+                     0, s, row_ptr, col_idx, n, light_max, block, stride, reinterpret_cast<unsigned long long *>(out));
   return hipGetLastError();
 }
 
@@ -2167,24 +2352,45 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
   return hipGetLastError();
 }
 
+// Kernels of light tiles that stage their rows in LDS (a.stage): byte registers, rows of at
+// most 16 lanes (256 bytes), 4 loads in flight (the schedule allows staging only there).
+#define HANF_DISPATCH_STAGED(G_, EXPR)                          \
+  {                                                             \
+    using F = ByteRegs;                                         \
+    switch (G_) {                                               \
+      case 1: { constexpr int G = 1; EXPR; } break;             \
+      case 2: { constexpr int G = 2; EXPR; } break;             \
+      case 4: { constexpr int G = 4; EXPR; } break;             \
+      case 8: { constexpr int G = 8; EXPR; } break;             \
+      case 16: { constexpr int G = 16; EXPR; } break;           \
+      default: return hipErrorInvalidValue;                     \
+    }                                                           \
+  }
+
 hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int G = row_lanes(a);
   const dim3 block(kBlockThreads);
+  const size_t lds = (size_t)a.lds_wave_bytes * (kBlockThreads / kWave);
   if (a.n_chunk_wgs + a.n_light_wgs == 0 || (!full && !list)) return record_empty(e0, e1, s);
+  if (a.stage && (a.packed || u != 4)) return hipErrorInvalidValue;
   if (full) {
     const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
     const int32_t list_too = list ? 1 : 0;
     hipEvent_t end = list ? nullptr : e1;
-    switch (u) {
-      case 2:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 2>, grid, block, s, e0, end, a, list_too));
-        break;
-      case 8:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 8>, grid, block, s, e0, end, a, list_too));
-        break;
-      default:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union<F, G, 4>, grid, block, s, e0, end, a, list_too));
-        break;
+    if (a.stage) {
+      HANF_DISPATCH_STAGED(G, launch_k_lds(k_union<F, G, 4, true>, grid, block, lds, s, e0, end, a, list_too));
+    } else {
+      switch (u) {
+        case 2:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union<F, G, 2, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+        case 8:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union<F, G, 8, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+        default:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union<F, G, 4, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+      }
     }
   }
   if (list) {
@@ -2192,16 +2398,23 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
     const dim3 grid((unsigned)grid_for(units, kBlockThreads / kWave, kListWgs));
     const int32_t full_too = full ? 1 : 0;
     hipEvent_t start = full ? nullptr : e0;
-    switch (u) {
-      case 2:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 2>, grid, block, s, start, e1, a, full_too));
-        break;
-      case 8:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 8>, grid, block, s, start, e1, a, full_too));
-        break;
-      default:
-        HANF_DISPATCH_FG(a.packed, G, launch_k(k_union_list<F, G, 4>, grid, block, s, start, e1, a, full_too));
-        break;
+    if (a.stage) {
+      HANF_DISPATCH_STAGED(G, launch_k_lds(k_union_list<F, G, 4, true>, grid, block, lds, s, start, e1, a, full_too));
+    } else {
+      switch (u) {
+        case 2:
+          HANF_DISPATCH_FG(a.packed, G,
+                           launch_k_lds(k_union_list<F, G, 2, false>, grid, block, lds, s, start, e1, a, full_too));
+          break;
+        case 8:
+          HANF_DISPATCH_FG(a.packed, G,
+                           launch_k_lds(k_union_list<F, G, 8, false>, grid, block, lds, s, start, e1, a, full_too));
+          break;
+        default:
+          HANF_DISPATCH_FG(a.packed, G,
+                           launch_k_lds(k_union_list<F, G, 4, false>, grid, block, lds, s, start, e1, a, full_too));
+          break;
+      }
     }
   }
   return hipGetLastError();
@@ -2249,7 +2462,14 @@ hipError_t launch_stats(const double *nt, const int32_t *T_or_null, const DevSta
   return hipGetLastError();
 }
 
-hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, double *out,
+hipError_t launch_seed_summary(const PassArgs &a, int32_t n_graphs, int32_t n_seeds, double alpha, int32_t distinct,
+                               SummaryRec *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_summary, dim3(grid_for(n_graphs, 64, 1 << 30)), dim3(64), 0, s, a, n_graphs, n_seeds,
+                     alpha, distinct, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stats_all(const PassArgs &a, double alpha, double eps, int32_t distinct, StatsRec *out,
                             hipStream_t s) {
   hipLaunchKernelGGL(k_stats_all, dim3(grid_for(a.batch.n_comp, 64, 1 << 30)), dim3(64), 0, s, a, alpha, eps, distinct,
                      out);

@@ -71,3 +71,26 @@ def test_sequential_fifo_baseline(bench):
     fin = bench.fifo_finish(arrivals, service)
     assert list(fin) == [0.5, 3.0, 4.0, 4.5, 12.0, 13.0]
     assert list(fin - arrivals) == [0.5, 2.0, 2.5, 2.5, 2.0, 1.0]
+
+
+def test_model_bytes_leave_out_staged_gathers(bench):
+    # successor counters read from a light tile's counters staged in LDS are not device
+    # memory traffic; everything else is counted as in the algorithmic bytes
+    n, m = 1 << 24, 128
+    rec = {"arcs_scanned": 1000, "arcs_gathered": 900, "rows_read": 50, "rows_written": 40, "arcs_local": 600}
+    assert bench.model_bytes(rec, n, m) == bench.algorithmic_bytes(rec, n, m) - 600 * m
+    rec0 = dict(rec, arcs_local=0)
+    assert bench.model_bytes(rec0, n, m) == bench.algorithmic_bytes(rec0, n, m)
+    sysrec = dict(rec, systolic=True)
+    assert bench.model_bytes(sysrec, n, m) == 8 * 50 + 4 * 1000 + m * (900 - 600 + 50 + 40)
+
+
+def test_cpu_threads_follow_affinity_and_share(bench, monkeypatch):
+    monkeypatch.setattr(bench.os, "sched_getaffinity", lambda pid: set(range(96)))
+    monkeypatch.setenv("OMP_NUM_THREADS", "16")
+    assert bench.cpu_threads() == (96, 16)
+    monkeypatch.delenv("OMP_NUM_THREADS")
+    assert bench.cpu_threads() == (96, 96)
+    monkeypatch.setattr(bench.os, "sched_getaffinity", lambda pid: set(range(8)))
+    monkeypatch.setenv("OMP_NUM_THREADS", "16")
+    assert bench.cpu_threads() == (8, 8)

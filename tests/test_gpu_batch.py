@@ -226,7 +226,7 @@ def test_batch_seed_statistics(distinct):
         bt.load_graphs(gs, S).init(b, seeds)
         bt.run()
         st = bt.stats_all(0.9, eps, distinct)
-        summ = bt.seed_summary(0.9) if not distinct else None
+        summ = bt.seed_summary(0.9, distinct)  # computed by the library (hanf_batch_seed_summary)
     ref = {k: np.zeros((len(gs), S)) for k in keys}
     for g, (rp, ci) in enumerate(gs):
         for s in range(S):
@@ -244,7 +244,21 @@ def test_batch_seed_statistics(distinct):
             assert st["d_hi"][c] == (-1 if hi is None else hi), (g, s)
             for k in keys:
                 ref[k][g, s] = r[k]
-    if summ is not None:
-        for k in keys:
-            np.testing.assert_allclose(summ[k + "_mean"], ref[k].mean(axis=1), rtol=1e-9, atol=1e-12)
-            np.testing.assert_allclose(summ[k + "_std"], ref[k].std(axis=1, ddof=1), rtol=1e-7, atol=1e-12)
+    assert (summ["runs"] == S).all()
+    for k in keys:
+        np.testing.assert_allclose(summ[k + "_mean"], ref[k].mean(axis=1), rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(summ[k + "_std"], ref[k].std(axis=1, ddof=1), rtol=1e-7, atol=1e-12)
+
+
+def test_seed_summary_of_single_runs():
+    """With one run per graph the means are that run's statistics and the sample standard
+    deviations are undefined (NaN)."""
+    gs = [graphgen.rmat(9, 3000, seed=8), graphgen.directed_cycle(40)]
+    with hanf.Batch(0) as bt:
+        bt.load_graphs(gs, 1).init(6, [5, 6])
+        bt.run()
+        st = bt.stats_all(0.9)
+        summ = bt.seed_summary(0.9)
+    for k in ("ed", "ied", "avg_dist", "spid"):
+        assert np.array_equal(summ[k + "_mean"], st[k])
+        assert np.isnan(summ[k + "_std"]).all()
