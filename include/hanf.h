@@ -389,6 +389,20 @@ int hanf_batch_seed_summary(hanf_ctx *ctx, double alpha, int32_t distinct, hanf_
 /* hanf_stats of every component in one launch; out has n_components entries (host). */
 int hanf_batch_stats_all(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops and harnesses that forbid hipMalloc): hanf_batch_stats_all without any allocation.
+ * The kernel stages the per-component records in a fixed device array of
+ * HANF_NOALLOC_MAX_COMPONENTS records (72 bytes each, 4.5 MiB), one per device, allocated
+ * with the library and held until the process ends; the records are then copied to `out`
+ * (n_components hanf_stats_t, host memory, the caller's). Every record is written by each
+ * call, so nothing needs clearing between calls. HANF_ERANGE, with a message, when the
+ * batch has more components than that; HANF_EDEVICE if the array's device address could
+ * not be obtained when the context was created. All calls on one device share its array:
+ * calls that overlap on one device (for instance from two host threads) race. Synchronises
+ * the context's stream. */
+#define HANF_NOALLOC_MAX_COMPONENTS 65536
+int hanf_batch_stats_all_noalloc(hanf_ctx *ctx, double alpha, double eps, int32_t distinct, hanf_stats_t *out);
+
 /* Last error message of the context, or of the calling thread when ctx is NULL. */
 const char *hanf_last_error(const hanf_ctx *ctx);
 

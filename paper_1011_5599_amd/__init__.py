@@ -151,6 +151,7 @@ def lib():
             "hanf_batch_read_registers": ([vp, i32, vp, i64, u32], ctypes.c_int),
             "hanf_batch_stats": ([vp, i32, dbl, dbl, i32, ctypes.POINTER(hanf_stats_t)], ctypes.c_int),
             "hanf_batch_stats_all": ([vp, dbl, dbl, i32, vp], ctypes.c_int),
+            "hanf_batch_stats_all_noalloc": ([vp, dbl, dbl, i32, vp], ctypes.c_int),
             "hanf_batch_seed_summary": ([vp, dbl, i32, vp], ctypes.c_int),
             "hanf_device_bytes": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_trim": ([vp], ctypes.c_int),
@@ -500,6 +501,19 @@ def hanf_batch_seed_summary(ctx, n_graphs: int, alpha: float = 0.9, distinct: bo
         out[k + "_mean"] = np.array([getattr(arr[g], k) for g in range(n_graphs)])
         out[k + "_std"] = np.array([getattr(arr[g], k + "_sd") for g in range(n_graphs)])
     out["runs"] = np.array([arr[g].runs for g in range(n_graphs)], np.int32)
+    return out
+
+
+def hanf_batch_stats_all_noalloc(ctx, out: np.ndarray, alpha: float = 0.9, eps: float = 0.0,
+                                 distinct: bool = False) -> np.ndarray:
+    """The same records written into the caller's `out` (STATS_DTYPE, at least one entry per
+    component) by the library's entry point that allocates no device memory."""
+    if out.dtype != STATS_DTYPE or not out.flags.c_contiguous:
+        raise TypeError("out must be a C-contiguous array of STATS_DTYPE")
+    n, _ = hanf_batch_info(ctx, with_T=False)
+    if out.size < n:
+        raise ValueError(f"out holds {out.size} records, the batch has {n} components")
+    _check(lib().hanf_batch_stats_all_noalloc(ctx, alpha, eps, int(distinct), out.ctypes.data), ctx)
     return out
 
 

@@ -11,6 +11,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,47 @@
 #include "hanf_internal.h"
 
 using namespace hanf;
+
+// Device memory of hanf_batch_stats_all_noalloc: the per-component statistics records are
+// staged here instead of in an allocation. One copy per device, held until the process
+// ends. Host code must not use this name as a device address: every use goes through the
+// address hipGetSymbolAddress returns on that device (g_scratch_dev).
+static __device__ __align__(256) StatsRec scratch[HANF_NOALLOC_MAX_COMPONENTS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+StatsRec *g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` on each device
+hipError_t g_scratch_err[kMaxDevices] = {};  // the lookup's result where it failed
+
+// Looks up the device address of `scratch` on `device` once (the device must be current).
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_scratch_dev[device] = static_cast<StatsRec *>(p);
+    g_scratch_err[device] = hipSuccess;
+  } else {
+    (void)hipGetLastError();
+    g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+}
+
+StatsRec *scratch_of(int device, hipError_t *err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_err[device];
+  return g_scratch_dev[device];
+}
+
+}  // namespace
 
 namespace {
 
@@ -1116,6 +1158,7 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
   if (const char *f = std::getenv("HANF_TEST_FAIL_ALLOC")) c->fail_alloc_at = std::atoi(f);
   e = hipSetDevice(device);
   if (e == hipSuccess) {
+    scratch_setup(device);
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {
@@ -2329,6 +2372,28 @@ int hanf_batch_seed_summary(hanf_ctx *c, double alpha, int32_t distinct, hanf_se
 static_assert(sizeof(SummaryRec) == sizeof(hanf_seed_summary_t), "SummaryRec must have hanf_seed_summary_t's layout");
 static_assert(offsetof(SummaryRec, runs) == offsetof(hanf_seed_summary_t, runs),
               "SummaryRec must have hanf_seed_summary_t's layout");
+
+int hanf_batch_stats_all_noalloc(hanf_ctx *c, double alpha, double eps, int32_t distinct, hanf_stats_t *out) {
+  if (!c) return fail(nullptr, HANF_EINVAL, "hanf_batch_stats_all_noalloc: NULL context");
+  if (!c->batch || !c->inited) return fail(c, HANF_ESTATE, "no initialised batch");
+  if (!out) return fail(c, HANF_EINVAL, "out is NULL");
+  if (!(alpha > 0.0 && alpha <= 1.0) || !(eps >= 0.0)) return fail(c, HANF_EINVAL, "alpha or eps out of range");
+  if (c->n_comp > HANF_NOALLOC_MAX_COMPONENTS)
+    return fail(c, HANF_ERANGE,
+                "hanf_batch_stats_all_noalloc: the batch has " + std::to_string(c->n_comp) +
+                    " components, more than HANF_NOALLOC_MAX_COMPONENTS (" +
+                    std::to_string(HANF_NOALLOC_MAX_COMPONENTS) + "); use hanf_batch_stats_all");
+  HIP_TRY(c, hipSetDevice(c->device), "set device");
+  hipError_t e = hipSuccess;
+  StatsRec *dbuf = scratch_of(c->device, &e);
+  if (!dbuf) return hip_fail(c, e, "hanf_batch_stats_all_noalloc: device address of the statistics array");
+  e = launch_stats_all(c->args, alpha, eps, distinct ? 1 : 0, dbuf, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, dbuf, sizeof(StatsRec) * (size_t)c->n_comp, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "statistics");
+  return HANF_OK;
+}
 
 static_assert(sizeof(StatsRec) == sizeof(hanf_stats_t), "StatsRec must have hanf_stats_t's layout");
 static_assert(offsetof(StatsRec, T) == offsetof(hanf_stats_t, T), "StatsRec must have hanf_stats_t's layout");
