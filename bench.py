@@ -49,11 +49,14 @@ def algorithmic_bytes(rec, n, m):
     return 4 * (n + 1) + 4 * rec["arcs_scanned"] + rows + n // 4
 
 
-def model_bytes(rec, n, m):
-    """Bytes a union pass must move through device memory: the algorithmic bytes less the
-    successor counters read from a light tile's counters staged in LDS (those rows are read
-    once, as the tile's own counters)."""
-    return algorithmic_bytes(rec, n, m) - m * rec.get("arcs_local", 0)
+def model_bytes(rec, n, m, near=None):
+    """Bytes a union pass must move through HBM (the roofline's bytes): the algorithmic
+    bytes less the successor counters that need not come from HBM: those within the near
+    window of their node (`near`, counted by the instrumented kernels: rows that the XCD
+    sweeping that id range read moments before as their own counters, held in its L2), or,
+    when no near count is given, those read from a light tile's counters staged in LDS."""
+    cached = rec.get("arcs_local", 0) if near is None or near < 0 else near
+    return algorithmic_bytes(rec, n, m) - m * cached
 
 
 def cpu_threads():
@@ -513,7 +516,7 @@ def served_leg(args):
     return out
 
 
-def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, with_method=True, log_prefix="[bench]"):
+def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, log_prefix="[bench]"):
     """Times whole runs of workload `name` (the graph resident in HBM, ingest included in
     each step). Returns (result dict, graph) where the dict carries the workload's rate,
     roofline and per-pass figures."""
@@ -586,14 +589,27 @@ def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, with_method
                    "runs_per_load": R,
                    "registers": "5-bit packed" if packed else "one per byte",
                    "staged_tiles": any(r.get("arcs_local", 0) > 0 for r in log),
-                   "pass_kinds": "".join("S" if r["systolic"] else ("D" if r["gather_all"] else "F")
+                   "pass_kinds": "".join({1: "S", 2: "M"}.get(r["systolic"]) or ("D" if r["gather_all"] else "F")
                                          for r in log)},
         "gathered_unions": gathered,
         "dense_equivalent_updates_per_s": m * arcs * sum(len(lg) for lg in logs[-R:]) / (ms_per_step / 1000.0),
         "graphs_per_s": R * 1000.0 / ms_per_step,
         "stats": {k: st[k] for k in ("ed", "ied", "avg_dist", "var", "spid")},
     }
-    if with_method:
+    # per-pass near successors, from the same run through the instrumented kernels (untimed;
+    # the same passes, checked): the roofline's bytes leave out those cached rows
+    near = [None] * len(log)
+    extra = not getattr(args, "no_extra_runs", False)
+    if extra and not packed:
+        iopts = {k: v for k, v in opts.items() if k != "timing"}
+        with hanf.HyperANF(0, stream=stream.cuda_stream, count_near=1, **iopts) as hn:
+            nt_n, _, nlogs = step(hn)
+        np.testing.assert_allclose(nt_n, nt, rtol=1e-12, atol=0)
+        nlog = nlogs[-1]
+        if ([r["arcs_gathered"] for r in nlog] == [r["arcs_gathered"] for r in log]
+                and all(r["arcs_near"] >= 0 for r in nlog)):
+            near = [r["arcs_near"] for r in nlog]
+    if extra:
         # the unions of the paper's modified-counter tracking alone: the same run with the
         # gather-all switch off (untimed); its results must be the timed run's
         with hanf.HyperANF(0, stream=stream.cuda_stream, dense_switch=0, **{k: v for k, v in opts.items()
@@ -603,10 +619,16 @@ def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, with_method
         method = sum(r["arcs_gathered"] for lg in mlogs for r in lg)
         out["method_unions"] = method
         out["method_updates_per_s"] = m * method / (ms_per_step / 1000.0)
+    out["pass_model_bytes"] = [model_bytes(r, n, rowb, near[i]) for i, r in enumerate(log)]
+    out["pass_algorithmic_bytes"] = [algorithmic_bytes(r, n, rowb) for r in log]
+    out["pass_near"] = near
     if not args.no_timing:
         all_recs = [r for lg in logs for r in lg]
         union_ms = sum(r["union_ms"] for r in all_recs)
-        byts = sum(model_bytes(r, n, rowb) for r in all_recs)
+        # every timed run makes the same passes as the last one (R = 1), so the near counts of
+        # the instrumented run apply pass by pass
+        near_of = (lambda i: near[i % len(log)]) if R == 1 else (lambda i: None)
+        byts = sum(model_bytes(r, n, rowb, near_of(i)) for i, r in enumerate(all_recs))
         algo = sum(algorithmic_bytes(r, n, rowb) for r in all_recs)
         launches = len(all_recs)
         achieved = byts / (union_ms / 1000.0) / 1e9
@@ -616,32 +638,37 @@ def run_plain(name, args, h_opts, tmode_arg="auto", runs_per_load=1, with_method
             frac=round(achieved / HBM_PEAK_GBS, 4),
             traffic=measured_traffic(name + ("_packed5" if packed else "")
                                      + ("_hubs" if opts.get("hubs", -1) > 0 else "")),
+            traffic_kind="bytes beyond L2 per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a "
+                         "device copy): HBM and Infinity Cache, an upper bound on HBM bytes",
             kernel="union step (k_union; k_union_list in systolic passes)", launches=launches,
             avg_launch_us=round(1000.0 * union_ms / launches, 2),
             avg_model_bytes=int(byts / launches),
             model="per pass: col_idx of the arcs scanned, row_ptr and modified flags, own counters "
-                  "read, new counters written, successor counters gathered from device memory "
-                  "(those read from a light tile's counters staged in LDS are not counted)",
+                  "read, new counters written, and the successor counters gathered except those "
+                  "within the near window of their node (held in the L2 of the XCD sweeping that "
+                  "id range; counted per pass by the instrumented kernels)",
+            near_window=(2 << 20) // rowb, near_counted=near[0] is not None,
             algorithmic_cache_inclusive=dict(avg_bytes=int(algo / launches), gbs=round(algo_gbs, 1),
                                              frac=round(algo_gbs / HBM_PEAK_GBS, 4)))
         p0 = [lg[0] for lg in logs]
         ms0 = sum(r["union_ms"] for r in p0) / len(p0)
-        b0 = model_bytes(p0[0], n, rowb)
+        b0 = model_bytes(p0[0], n, rowb, near[0])
         a0 = algorithmic_bytes(p0[0], n, rowb)
         out["full_pass"] = dict(union_ms=round(ms0, 4), model_gb=round(b0 / 1e9, 4),
                                 gbs=round(b0 / (ms0 / 1000.0) / 1e9, 1),
                                 frac=round(b0 / (ms0 / 1000.0) / 1e9 / HBM_PEAK_GBS, 4),
                                 algorithmic_gb=round(a0 / 1e9, 4),
                                 algorithmic_gbs=round(a0 / (ms0 / 1000.0) / 1e9, 1),
-                                local_share=round(p0[0].get("arcs_local", 0) / max(1, p0[0]["arcs_gathered"]), 4),
+                                near_share=(None if near[0] is None
+                                            else round(near[0] / max(1, p0[0]["arcs_gathered"]), 4)),
                                 updates_per_s=m * p0[0]["arcs_gathered"] / (ms0 / 1000.0))
         last = [r for lg in logs[-R:] for r in lg]  # the last step's passes
         out["per_step_kernel_ms"] = dict(signal_ms=round(sum(r["signal_ms"] for r in last), 4),
                                          finalize_ms=round(sum(r["finalize_ms"] for r in last), 4),
                                          reduce_ms=round(sum(r["reduce_ms"] for r in last), 4),
                                          union_ms=round(sum(r["union_ms"] for r in last), 4))
-        out["pass_model_bytes"] = [model_bytes(r, n, rowb) for r in log]
         out["pass_union_ms"] = [round(r["union_ms"], 4) for r in log]
+        out["pass_signal_ms"] = [round(r["signal_ms"], 4) for r in log]
     h.close()
     del trp, tci
     torch.cuda.empty_cache()
@@ -660,6 +687,8 @@ def main():
                     help="CPU baseline: the single-thread leg runs the first pass over n / this many nodes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="no per-kernel HIP events")
+    ap.add_argument("--no-extra-runs", action="store_true",
+                    help="no untimed diagnostic runs (method unions, near counts): for kernel traces")
     ap.add_argument("--opt", action="append", default=[], help="library option name=value")
     ap.add_argument("--legs", default="rmat22sym,batched,served",
                     help="plain mode: comma-separated extra legs after the main workload "

@@ -109,19 +109,34 @@ extern "C" {
                                    caller's order; from the second run on, the rewrite pays for
                                    itself). 0: the caller's order */
 
+#define HANF_OPT_FORWARD 14     /* systolic passes without a transposed graph (Section 3.3): when none
+                                   is set, the pass after one that changed fewer than n/s counters
+                                   (s = HANF_OPT_SYSTOLIC) finds the nodes to recompute by a
+                                   forward scan of the successor lists in a kernel of its own
+                                   (each node with a modified successor is marked), then
+                                   recomputes only the marked nodes, as systolic passes do (pass
+                                   records show systolic = 2). 0 (default) off: such passes test
+                                   every successor's flag inside the union step, which on MI355X
+                                   costs about as much as the scan alone (web24's last passes:
+                                   0.68-0.71 ms, against 0.61 ms of scan plus the recomputation),
+                                   and far less where many counters still change; 1 on. Results
+                                   do not change */
 #define HANF_OPT_STAGE 13       /* LDS staging of light tiles, in passes over every successor: the
                                    wavefront of a light tile (consecutive ids) first copies the
                                    tile's counters into LDS, then maximises successors inside
                                    the tile's id range from there (a tile holds 4 KiB of
-                                   counters: 32 nodes at m = 128). Pays on graphs whose ids
-                                   follow their locality (the hosts of a web graph). -1
-                                   (default): when a sample shows at least a quarter of the
-                                   light nodes' arcs inside their tile; 0 never; 1 always
-                                   (one register per byte only). Results do not change */
+                                   counters: 32 nodes at m = 128). 0 (default) never; 1 when
+                                   the format allows (one register per byte, rows of at most
+                                   256 bytes, 4 loads in flight). On MI355X the caches already
+                                   serve such successors and staging is slower (fewer
+                                   wavefronts per CU); it is kept as an option. Results do not
+                                   change */
 
 /* Tuning and test options (the results never change):
  *   103  LDS bytes per wavefront for the counters of a staged light tile (HANF_OPT_STAGE):
  *        2048, 4096 (default), 8192 or 16384;
+ *   104  1: run the instrumented union kernels, which count arcs_near in the pass records
+ *        (byte registers, rows of at most 256 bytes, 4 loads in flight; elsewhere -1);
  *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
  *   101  the persistent union kernel over listed work units: 0 (default) for systolic
  *        passes, 1 never, 2 for every pass;
@@ -166,11 +181,17 @@ typedef struct {
                             estimates of changed counters), else 0 */
   float reduce_ms;       /* estimate reduction kernels time, else 0 */
   int32_t gather_all;    /* 1 if the pass maximised with every successor */
-  int32_t systolic;      /* 1 if only nodes signalled by a modified successor were recomputed */
+  int32_t systolic;      /* 1 if only nodes signalled by a modified successor were recomputed
+                            (signals through the transposed graph), 2 if so with the nodes
+                            found by a forward scan of the successor lists (HANF_OPT_FORWARD) */
   int64_t arcs_signalled;/* systolic pass: predecessor arcs of the modified counters followed */
   float signal_ms;       /* systolic signal kernels time (HANF_OPT_TIMING), else 0 */
   int64_t arcs_local;    /* of arcs_gathered: successor counters read from a light tile's
                             counters staged in LDS (HANF_OPT_STAGE) instead of device memory */
+  int64_t arcs_near;     /* of arcs_gathered: successors w of v with |w - v| < W, W = the rows
+                            4 MiB (one XCD's L2) holds, halved: 16384 at 128-byte rows.
+                            Counted by instrumented kernels only (option 104, or staging),
+                            else -1 */
 } hanf_pass_t;
 
 /* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work

@@ -46,6 +46,7 @@ HANF_OPT_SEEDS_PER_ROW = 10
 HANF_OPT_PACKED5 = 11
 HANF_OPT_HUBS = 12
 HANF_OPT_STAGE = 13
+HANF_OPT_FORWARD = 14
 HANF_FP_COPY_GRAPH = 1
 HANF_FP_TRANSPOSE = 2
 HANF_FP_PACKED5 = 4
@@ -54,6 +55,7 @@ HANF_OPT_UNROLL = 100
 HANF_OPT_UNION_POLICY = 101  # 0 auto, 1 one wavefront per work unit, 2 persistent sparse kernel
 HANF_OPT_TRANSPOSE_COUNTING = 102  # 1: build transposes with per-node counters (test option)
 HANF_OPT_STAGE_BYTES = 103  # LDS bytes per wavefront of a staged light tile (tuning option)
+HANF_OPT_COUNT_NEAR = 104  # 1: instrumented union kernels count arcs_near (measurement option)
 
 ERROR_NAMES = {HANF_EINVAL: "EINVAL", HANF_ENOMEM: "ENOMEM", HANF_EDEVICE: "EDEVICE",
                HANF_ESTATE: "ESTATE", HANF_ERANGE: "ERANGE", HANF_EMAXITER: "EMAXITER"}
@@ -73,7 +75,7 @@ class hanf_pass_t(ctypes.Structure):
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
                 ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32),
                 ("systolic", ctypes.c_int32), ("arcs_signalled", ctypes.c_int64),
-                ("signal_ms", ctypes.c_float), ("arcs_local", ctypes.c_int64)]
+                ("signal_ms", ctypes.c_float), ("arcs_local", ctypes.c_int64), ("arcs_near", ctypes.c_int64)]
 
 
 class HanfError(RuntimeError):
@@ -534,8 +536,10 @@ class HyperANF:
                  "dense_switch": HANF_OPT_DENSE_SWITCH, "systolic": HANF_OPT_SYSTOLIC,
                  "seeds_per_row": HANF_OPT_SEEDS_PER_ROW, "packed5": HANF_OPT_PACKED5,
                  "hubs": HANF_OPT_HUBS, "stage": HANF_OPT_STAGE,
+                 "forward": HANF_OPT_FORWARD,
                  "union_policy": HANF_OPT_UNION_POLICY,
-                 "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING, "stage_bytes": HANF_OPT_STAGE_BYTES}
+                 "transpose_counting": HANF_OPT_TRANSPOSE_COUNTING, "stage_bytes": HANF_OPT_STAGE_BYTES,
+                 "count_near": HANF_OPT_COUNT_NEAR}
         for k, v in options.items():
             hanf_set_option(self.ctx, names[k], int(v))
 

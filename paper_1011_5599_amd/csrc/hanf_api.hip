@@ -80,9 +80,8 @@ struct Schedule {
   int32_t light_max = 0, chunk_arcs = 0, tile_nodes = 0;
   int32_t tile_base = 0;   // nodes per light tile without staging (option or default)
   int32_t stage_tile = 0;  // nodes per light tile when staging (0: the format cannot stage)
-  int stage_opt = -1;      // HANF_OPT_STAGE the schedule was built with
+  int stage_opt = 0;       // HANF_OPT_STAGE the schedule was built with
   int stage = 0;           // light tiles stage their rows in LDS (passes over every successor)
-  double near_frac = -1.0; // sampled share of light arcs inside their stage tile (-1: not measured)
   int32_t lds_wave_bytes = 0;
   int32_t n_tiles = 0, n_chunks = 0, n_heavy = 0;
   int32_t n_chunk_wgs = 0, n_light_wgs = 0, n_fin_wgs = 0;
@@ -121,8 +120,10 @@ struct hanf_ctx {
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
   int tp_counting = 0;   // 1: build transposes by per-node counters even below kTpMaxNodes
   int64_t hubs_opt = -1; // HANF_OPT_HUBS: -1 auto, 0 the caller's order, K: up to K hubs first
-  int stage_opt = -1;    // HANF_OPT_STAGE: -1 auto, 0 never, 1 whenever the format allows
+  int stage_opt = 0;     // HANF_OPT_STAGE: 0 never, 1 whenever the format allows
   int32_t stage_bytes = kStageWaveBytes;  // LDS per wavefront for a staged tile's counters
+  int count_near = 0;    // 1: instrumented union kernels count near successors (option 104)
+  int forward = 0;       // HANF_OPT_FORWARD: systolic passes without a transposed graph
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
 
@@ -494,33 +495,23 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   s.stage_opt = c->stage_opt;
 }
 
-// Staging pays when most arcs of light nodes stay inside their tile's id range (the share
-// measured on a sample of the graph); elsewhere it only costs LDS (fewer wavefronts per CU).
-constexpr double kStageMinNear = 0.25;
-constexpr int32_t kLocalityStride = 8;  // every 8th node is sampled
-
 int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   free_schedule(c);
   Schedule &s = c->sch;
   choose_schedule(c, G, lane_bytes, s);
   const int32_t n = c->n;
   int rc;
-  // chunk counts, prefix sums, chunk and heavy lists; with automatic staging, the locality
-  // sample is read in the same wait
-  const bool measure = s.stage_opt < 0 && s.stage_tile > 0;
+  // chunk counts, prefix sums, chunk and heavy lists
   uint64_t *keys = nullptr, *tmp = nullptr;
-  if ((rc = dev_alloc(c, &keys, (size_t)n + 3, "schedule keys"))) return rc;
+  if ((rc = dev_alloc(c, &keys, (size_t)n + 1, "schedule keys"))) return rc;
   if ((rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
     dev_release(c, keys);
     return rc;
   }
   hipError_t e = launch_classify(c->rp, n, s.light_max, s.chunk_arcs, keys, c->stream);
   if (e == hipSuccess) e = launch_exclusive_scan_u64(keys, (int64_t)n + 1, tmp, c->stream);
-  if (e == hipSuccess && measure)
-    e = launch_locality(c->rp, c->ci, n, s.light_max, s.stage_tile, kLocalityStride, keys + n + 1, c->stream);
-  uint64_t total[3] = {0, 0, 0};
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(total, keys + n, sizeof(uint64_t) * (measure ? 3 : 1), hipMemcpyDeviceToHost, c->stream);
+  uint64_t total[1] = {0};
+  if (e == hipSuccess) e = hipMemcpyAsync(total, keys + n, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     dev_release(c, keys);
@@ -529,8 +520,7 @@ int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   }
   s.n_chunks = (int32_t)(total[0] >> 32);
   s.n_heavy = (int32_t)(total[0] & 0xffffffffull);
-  if (measure) s.near_frac = total[1] ? (double)total[2] / (double)total[1] : 0.0;
-  s.stage = s.stage_tile > 0 && (s.stage_opt == 1 || (measure && s.near_frac >= kStageMinNear));
+  s.stage = s.stage_tile > 0 && s.stage_opt == 1;
   if (s.stage) s.tile_nodes = s.stage_tile;
   s.lds_wave_bytes = s.stage ? s.tile_nodes * G * lane_bytes : ((s.tile_nodes * 4 + 15) / 16) * 16;
   s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
@@ -615,7 +605,13 @@ void fill_args(hanf_ctx *c) {
   a.tile_nodes = c->sch.tile_nodes;
   a.light_max = c->sch.light_max;
   a.stage = c->sch.stage;
+  // the instrumented kernels exist where staging could run (byte rows up to 256 bytes, 4 loads
+  // in flight); elsewhere near successors are not counted
+  a.count_near = (c->count_near && c->sch.stage_tile > 0) ? 1 : 0;
   a.lds_wave_bytes = c->sch.lds_wave_bytes;
+  // rows one XCD's 4 MiB L2 holds, half on either side of the node (see the pass record)
+  const int64_t rb = (int64_t)c->sch.G * c->sch.lane_bytes;  // 0 until a schedule is built
+  a.near_window = rb > 0 ? (int32_t)std::max<int64_t>(1, (int64_t)(kL2Bytes / 2) / rb) : 1;
   a.n_heavy = c->sch.n_heavy;
   a.n_fin_wgs = c->sch.n_fin_wgs;
   a.n_reduce_wgs = c->n_reduce_wgs;
@@ -1100,8 +1096,10 @@ int64_t dense_threshold(const hanf_ctx *c) {
   return std::max<int64_t>(1, ((int64_t)c->n << c->sl) / c->dense_div);
 }
 
-// Systolic passes need the transposed graph and the signal buffers of the run.
-int32_t systolic_div(const hanf_ctx *c) { return (c->args.trow_ptr && c->frontier) ? c->sys_div : 0; }
+// Systolic passes need the signal buffers of the run, and the transposed graph or the forward
+// scan (HANF_OPT_FORWARD).
+bool has_signals(const hanf_ctx *c) { return c->args.trow_ptr || (c->forward && c->args.todo); }
+int32_t systolic_div(const hanf_ctx *c) { return (has_signals(c) && c->frontier) ? c->sys_div : 0; }
 
 // Timed passes: start and end of the signal kernels, the union step, finalize (with the
 // estimates of packed rows) and the reduction, each pair taken from the kernels' own
@@ -1125,7 +1123,7 @@ int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   // The per-unit kernel is skipped once the last state read showed systolic passes (the
   // persistent kernel then runs every pass, whatever its kind); otherwise both are launched
   // and each leaves the passes that are not its own.
-  const bool has_sys = c->args.trow_ptr != nullptr;
+  const bool has_sys = has_signals(c);
   const int list = c->union_policy == 2 || (c->union_policy == 0 && has_sys);
   const int full = c->union_policy == 1 || (c->union_policy == 0 && !(has_sys && c->sys_seen));
   HIP_TRY(c, launch_union(c->args, c->unroll, full, list, s, e[2], e[3]), "union kernel");
@@ -1258,8 +1256,12 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value < -1 || value > INT32_MAX) return fail(c, HANF_EINVAL, "hubs must be -1 (auto), 0 or a count");
       c->hubs_opt = value;
       break;
+    case HANF_OPT_FORWARD:
+      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "forward must be 0 or 1");
+      c->forward = (int)value;
+      break;
     case HANF_OPT_STAGE:
-      if (value < -1 || value > 1) return fail(c, HANF_EINVAL, "stage must be -1 (auto), 0 or 1");
+      if (value < 0 || value > 1) return fail(c, HANF_EINVAL, "stage must be 0 or 1");
       c->stage_opt = (int)value;
       break;
     case 101:  // persistent union kernel: 0 for systolic passes, 1 never, 2 always; used by tests
@@ -1269,6 +1271,10 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
     case 102:  // transpose build: 0 bucket sort up to 2^26 nodes, 1 always per-node counters; used by tests
       if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "transpose build must be 0 or 1");
       c->tp_counting = (int)value;
+      break;
+    case 104:  // instrumented union kernels that count near successors (0 or 1); used by the benchmark
+      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "count_near must be 0 or 1");
+      c->count_near = (int)value;
       break;
     case 103:  // LDS bytes per wavefront for a staged tile (2048, 4096, 8192 or 16384); used by the tuner
       if (value != 2048 && value != 4096 && value != 8192 && value != 16384)
@@ -1568,9 +1574,14 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
                               hipMemcpyHostToDevice, c->stream),
             "chunk table upload");
   }
-  if (c->trp && !c->todo) {  // signal buffers for systolic passes
-    if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals")) ||
-        (rc = dev_alloc(c, &c->sys_node, (size_t)c->n, "systolic list")) ||
+  if ((c->trp || c->forward) && !c->todo) {  // signal marks for systolic passes
+    if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals"))) {
+      free_run(c);
+      return rc;
+    }
+  }
+  if (c->trp && !c->sys_node) {  // the list of modified nodes that signal through the transpose
+    if ((rc = dev_alloc(c, &c->sys_node, (size_t)c->n, "systolic list")) ||
         (rc = dev_alloc(c, &c->sys_pos, (size_t)c->n, "systolic list"))) {
       free_run(c);
       return rc;
@@ -1680,6 +1691,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.systolic = (int32_t)recs[i].systolic;
         r.arcs_signalled = recs[i].signalled;
         r.arcs_local = recs[i].local;
+        r.arcs_near = (c->args.count_near || c->args.stage) ? recs[i].near : -1;
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * kPassEvents];
           (void)hipEventElapsedTime(&r.signal_ms, e[0], e[1]);
@@ -1961,10 +1973,11 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)
   b += ((int64_t)n + 3) * 8;                             // N_hat history (pass cap n + 1)
   b += std::min<int64_t>((int64_t)n + 3, kMaxLogRecords) * (int64_t)sizeof(PassLog);  // pass records
+  b += blocks * kNodesPerBlock;                          // systolic marks (forward scan or transpose)
   if (copy_graph & HANF_FP_COPY_GRAPH) b += ((int64_t)n + 1) * 4 + arcs * 4;
   if (copy_graph & HANF_FP_TRANSPOSE) {
     b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
-    b += blocks * kNodesPerBlock + (int64_t)n * 8;  // signals and signal list
+    b += (int64_t)n * 8;                   // signal list
   }
   if (copy_graph & HANF_FP_ORDER) {
     b += ((int64_t)n + 1) * 4 + arcs * 4 + (int64_t)n * 8;  // the reordered graph, perm and inv

@@ -14,7 +14,8 @@ constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
-constexpr int kStatFields = 5;     // work counters per row: scanned, gathered, written, read, local
+constexpr int kStatFields = 6;     // work counters per row: scanned, gathered, written, read, local, near
+constexpr int64_t kL2Bytes = 4 << 20;  // L2 of one XCD
 constexpr int kStageWaveBytes = 4096;  // LDS per wavefront for the rows of a staged light tile
 constexpr int kCompChunkBlocks = 1024;  // blocks per chunk of a batch component's reduction
 constexpr int kPacked5LaneBytes = 40;   // 64 registers of 5 bits: one lane of a packed counter
@@ -49,6 +50,8 @@ struct DevState {
 struct PassLog {  // per executed pass, filled on the device
   int64_t changed, scanned, gathered, written, read, gather_all, systolic, signalled;
   int64_t local;  // successor counters maximised in from a light tile's rows staged in LDS
+  int64_t near;   // successor counters maximised in whose id is within near_window of the node's
+                  //   (counted only by the instrumented kernels: count_near or stage)
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront
@@ -162,7 +165,7 @@ struct PassArgs {
   double *blocksum;          // per 64 nodes and row seed, [b * S + j]
   double *wgsum;             // per reduce workgroup
   int64_t *wgcnt;            // per reduce workgroup: changed counters
-  int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read, local}
+  int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read, local, near}
   const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
   const Chunk *chunks;
   const Heavy *heavy;
@@ -199,6 +202,8 @@ struct PassArgs {
                              //   successors in that range are maximised in from there
   int32_t lds_wave_bytes;    // dynamic LDS per wavefront of the union kernels: the list of
                              //   active nodes of a tile or, when staging, its rows (shared)
+  int32_t near_window;       // a gathered successor w of v is counted as near if |w - v| < this
+  int32_t count_near;        // 1: the union kernels count near successors (instrumented kernels)
   int32_t n_heavy;
   int32_t n_fin_wgs;
   int32_t n_reduce_wgs;
@@ -215,10 +220,6 @@ hipError_t launch_validate(const int32_t *row_ptr, const int32_t *col_idx, int32
                            DevState *st, hipStream_t s);
 hipError_t launch_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t max_passes,
                               int64_t dense_threshold, int32_t sys_div, hipStream_t s);
-// Near arcs of light nodes, sampled: out[0] += light arcs of every `stride`-th node, out[1] +=
-// those whose target lies in the source's aligned block of `block` ids. out is zeroed here.
-hipError_t launch_locality(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t light_max,
-                           int32_t block, int32_t stride, uint64_t *out, hipStream_t s);
 hipError_t launch_classify(const int32_t *row_ptr, int32_t n, int32_t light_max, int32_t chunk_arcs,
                            uint64_t *keys, hipStream_t s);
 // exclusive scan of n uint64 values in place; `tmp` needs scan_tmp_elems(n) elements

@@ -58,6 +58,18 @@ __device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl
   return ((bits[i >> 5] >> (i & 31)) & field) != 0u;
 }
 
+// The flag word holding node v's modified bits, and the test of those bits in it. Loops load
+// the words of all their nodes first (v clamped to a valid id where there is none), so the
+// loads are in flight together instead of one round trip after another.
+__device__ __forceinline__ uint32_t mod_word(const uint32_t *bits, int32_t v, int sl) {
+  return bits[((uint64_t)v << sl) >> 5];
+}
+__device__ __forceinline__ bool mod_in_word(uint32_t word, int32_t v, int sl) {
+  const uint64_t i = (uint64_t)v << sl;
+  const uint32_t field = sl == 5 ? 0xffffffffu : ((1u << (1u << sl)) - 1u);
+  return ((word >> (i & 31)) & field) != 0u;
+}
+
 __device__ __forceinline__ uint4 shfl_xor4(uint4 a, int off) {
   return make_uint4(__shfl_xor(a.x, off), __shfl_xor(a.y, off), __shfl_xor(a.z, off),
                     __shfl_xor(a.w, off));
@@ -322,6 +334,7 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *s
 
 struct Counters {
   int32_t scanned = 0, gathered = 0, written = 0, read = 0, local = 0;
+  int32_t near = 0;  // per lane: the lane's own gathered successor ids within near_window
 };
 
 // A lane's part of row r of a light tile staged in LDS (byte registers, rows of G lanes).
@@ -408,7 +421,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     if (f.gather_all) acc = own;
     own_loaded = true;
   }
-  int32_t gathered = 0, local = 0;
+  int32_t gathered = 0, local = 0, near = 0;
   for (int32_t p = beg; p < end; p += G * U) {
     int32_t w[U];
     bool ok[U];
@@ -419,8 +432,11 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
       w[k] = ok[k] ? a.col_idx[idx] : 0;
     }
     if (!f.gather_all) {
+      uint32_t fw[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) ok[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
+      for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+#pragma unroll
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
     }
     int32_t total = 0;
 #pragma unroll
@@ -428,6 +444,8 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
       const uint64_t bk = __ballot(ok[k]) & smask;
       if (ok[k]) q[total + __popcll(bk & below)] = w[k];
       total += __popcll(bk);
+      if constexpr (ST)
+        near += (ok[k] && (uint32_t)(w[k] - v + a.near_window - 1) < 2u * (uint32_t)a.near_window - 1u) ? 1 : 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -473,6 +491,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     cnt.gathered += gathered;
     cnt.local += local;
   }
+  if constexpr (ST) cnt.near += near;
   finalize_slot<F, G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
 }
 
@@ -556,8 +575,11 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
             }
           }
           bool hk[U];
+          uint32_t fw[U];
 #pragma unroll
-          for (int k = 0; k < U; ++k) hk[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
+          for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+#pragma unroll
+          for (int k = 0; k < U; ++k) hk[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
 #pragma unroll
           for (int k = 0; k < U; ++k) {
             const bool h = hk[k];
@@ -618,7 +640,7 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
 // A chunk of one node's arcs handled by a whole wavefront: every lane examines its own
 // successor id (64 per load), the ids to maximise in are compacted into the wavefront's
 // queue in LDS, and the W slots gather the queued counters.
-template <class F, int G, int U>
+template <class F, int G, int U, bool ST>
 __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, int32_t c, int lane,
                                            int32_t *q, Counters &cnt) {
   using Lane = typename F::Lane;
@@ -636,7 +658,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   Lane own = F::zero();
   const bool own_loaded = ch.part < 0 && slot == 0 && a1 > ch.a0;
   if (own_loaded) own = F::load(f.cur, ch.v, G, sub);
-  int32_t gathered = 0;
+  int32_t gathered = 0, near = 0;  // (wavefront-uniform)
   for (int32_t base = ch.a0; base < a1; base += kWave * U) {
     int32_t w[U];
     bool ok[U];
@@ -647,8 +669,11 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
       w[k] = ok[k] ? a.col_idx[p] : 0;
     }
     if (!f.gather_all) {
+      uint32_t fw[U];
 #pragma unroll
-      for (int k = 0; k < U; ++k) ok[k] = ok[k] && node_mod(f.prev_bits, w[k], f.sl);
+      for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+#pragma unroll
+      for (int k = 0; k < U; ++k) ok[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
     }
     int32_t total = 0;
 #pragma unroll
@@ -656,6 +681,8 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
       const uint64_t bk = __ballot(ok[k]);
       if (ok[k]) q[total + __popcll(bk & below)] = w[k];
       total += __popcll(bk);
+      if constexpr (ST)
+        near += __popcll(__ballot(ok[k] && (uint32_t)(w[k] - ch.v + a.near_window - 1) < 2u * (uint32_t)a.near_window - 1u));
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -676,6 +703,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   if (lane == 0) {
     cnt.scanned += a1 - ch.a0;
     cnt.gathered += gathered;
+    if constexpr (ST) cnt.near += near;
   }
   bool any = gathered > 0;  // wavefront-uniform
   if (any) combine_slots<F, G>(acc, any);
@@ -708,13 +736,14 @@ __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *s
   __shared__ int32_t red[kStatFields][kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written),
-                s3 = wave_sum(c.read), s4 = wave_sum(c.local);
+                s3 = wave_sum(c.read), s4 = wave_sum(c.local), s5 = wave_sum(c.near);
   if (lane == 0) {
     red[0][wave] = s0;
     red[1][wave] = s1;
     red[2][wave] = s2;
     red[3][wave] = s3;
     red[4][wave] = s4;
+    red[5][wave] = s5;
   }
   __syncthreads();
   if (threadIdx.x < kStatFields) {
@@ -749,7 +778,7 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   if (!f.gather_all) {
     count = find_active<U>(a, f, tl, tile, a.light_max, lane, rps, act, cnt);
   } else if constexpr (ST) {
-    {
+    if (a.stage) {
       const int32_t hi = min(a.n, lo + a.tile_nodes);
       const int32_t n16 = (int32_t)(((int64_t)(hi - lo) * G * F::kBytes) >> 4);
       const uint4 *src = reinterpret_cast<const uint4 *>(f.cur + (size_t)lo * G * F::kBytes);
@@ -819,7 +848,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
   int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
     const int32_t c = (int32_t)blockIdx.x * 4 + wave;
-    if (c < a.n_chunks) chunk_wave<F, G, U>(a, f, c, lane, qw, cnt);
+    if (c < a.n_chunks) chunk_wave<F, G, U, ST>(a, f, c, lane, qw, cnt);
   } else {
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
     const int32_t tile = L * 4 + wave;
@@ -852,7 +881,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
   for (int64_t i = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave; i < total; i += stride) {
     const int32_t u = f.systolic ? a.unit_list[i] : (int32_t)i;
     if (u < a.n_chunks)
-      chunk_wave<F, G, U>(a, f, u, lane, qw, cnt);
+      chunk_wave<F, G, U, ST>(a, f, u, lane, qw, cnt);
     else
       process_tile<F, G, U, ST>(a, f, u - a.n_chunks, lane, qw,
                             reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
@@ -1186,10 +1215,10 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kTopThreads];
-  __shared__ int64_t s_i[6][kTopThreads];
+  __shared__ int64_t s_i[7][kTopThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
-  int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0, lo = 0;
+  int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0, lo = 0, ne = 0;
   for (int32_t i = tid; i < a.n_reduce_wgs; i += kTopThreads) {
     s += a.wgsum[i];
     c += a.wgcnt[i];
@@ -1202,8 +1231,9 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       wr = sl[2];
       rd = sl[3];
       lo = sl[4];
+      ne = sl[5];
     }
-    sl[0] = sl[1] = sl[2] = sl[3] = sl[4] = 0;
+    sl[0] = sl[1] = sl[2] = sl[3] = sl[4] = sl[5] = 0;
   }
   s_sum[tid] = s;
   s_i[0][tid] = c;
@@ -1212,11 +1242,12 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   s_i[3][tid] = wr;
   s_i[4][tid] = rd;
   s_i[5][tid] = lo;
+  s_i[6][tid] = ne;
   __syncthreads();
   for (int off = kTopThreads / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_sum[tid] += s_sum[tid + off];
-      for (int k = 0; k < 6; ++k) s_i[k][tid] += s_i[k][tid + off];
+      for (int k = 0; k < 7; ++k) s_i[k][tid] += s_i[k][tid + off];
     }
     __syncthreads();
   }
@@ -1235,7 +1266,8 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
       rec.written = s_i[3][0];
       rec.read = s_i[4][0];
       rec.local = s_i[5][0];
-      rec.systolic = st->systolic;
+      rec.near = s_i[6][0];
+      rec.systolic = st->systolic ? (a.trow_ptr ? 1 : 2) : 0;  // 2: marks from a forward scan
       rec.signalled = rec.systolic ? (int64_t)(st->sys_acc & 0xffffffffull) : 0;
       if (p < a.log_cap) a.log[p] = rec;
       st->passes = p + 1;
@@ -1416,6 +1448,111 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
   }
 }
 
+// Systolic passes without a transposed graph (Section 3.3: only a node with a successor whose
+// counter the previous pass modified can change). With no predecessor lists to follow from the
+// modified counters, the successor lists are scanned forward: a node is marked (todo, and its
+// light tile's flag) when some successor's modified flag is set. One wavefront per work unit
+// of the union step: a chunk of a heavy node's arcs, or a light tile, whose light nodes' arcs
+// form one contiguous CSR range per 64 consecutive ids (heavy nodes' arcs are skipped: their
+// chunks cover them). Arc ids are streamed 64 per load, kFwdLoads loads in flight per lane, and
+// the flag words of all of them are loaded before any is tested; a lane that hits looks up its
+// source node by binary search over the 65 row pointers of its 64 ids, kept in LDS, and marks
+// it in a per-wavefront byte array there. The counts (marked light nodes and chunks with a hit, arcs into modified counters) go to the run
+// state's signal counter, as k_sys_list's do. The union step then runs on the marks.
+constexpr int kFwdLoads = 8;
+
+__global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
+  DevState *st = a.st;
+  if (st->halted || !st->systolic) return;
+  const int32_t t = st->t;
+  const uint32_t *pb = (t & 1) ? a.bits1 : a.bits0;  // counters modified by pass t-1
+  const int sl = a.seed_log2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ int32_t s_rp[kBlockThreads / kWave][kWave + 1];
+  __shared__ uint8_t s_mark[kBlockThreads / kWave][kWave];
+  int32_t *rps = s_rp[wave];
+  uint8_t *mark = s_mark[wave];
+  const int64_t u = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave;
+  uint32_t marked = 0, arcs_hit = 0;  // wavefront-uniform
+  if (u < a.n_chunks) {
+    const Chunk ch = a.chunks[u];
+    for (int32_t base = ch.a0; base < ch.a1; base += kWave * kFwdLoads) {
+      int32_t w[kFwdLoads];
+      uint32_t fw[kFwdLoads];
+#pragma unroll
+      for (int k = 0; k < kFwdLoads; ++k) w[k] = a.col_idx[min(base + k * kWave + lane, ch.a1 - 1)];
+#pragma unroll
+      for (int k = 0; k < kFwdLoads; ++k) fw[k] = mod_word(pb, w[k], sl);
+#pragma unroll
+      for (int k = 0; k < kFwdLoads; ++k)
+        arcs_hit += __popcll(__ballot(base + k * kWave + lane < ch.a1 && mod_in_word(fw[k], w[k], sl)));
+    }
+    if (arcs_hit) {
+      marked = 1;
+      if (lane == 0) a.todo[ch.v] = 1;
+    }
+  } else if (u < (int64_t)a.n_chunks + a.n_tiles) {
+    const int32_t tile = (int32_t)(u - a.n_chunks);
+    const int32_t lo = tile * a.tile_nodes;
+    const int32_t hi = min(a.n, lo + a.tile_nodes);
+    for (int32_t s0 = lo; s0 < hi; s0 += kWave) {
+      const int32_t cnt = min(kWave, hi - s0);
+      const int32_t v = s0 + lane;
+      const bool valid = lane < cnt;
+      const int32_t r0 = valid ? a.row_ptr[v] : 0;
+      const int32_t r1 = valid ? a.row_ptr[v + 1] : 0;
+      if (valid) rps[lane] = r0;
+      if (lane == cnt - 1) rps[cnt] = r1;
+      mark[lane] = 0;
+      const uint64_t heavy = __ballot(valid && r1 - r0 > a.light_max);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int32_t j0 = 0;
+      while (j0 < cnt) {
+        const uint64_t rest = heavy >> j0;
+        const int32_t j1 = rest ? j0 + __ffsll((long long)rest) - 1 : cnt;  // light run [j0, j1)
+        if (j1 > j0) {
+          const int32_t A = rps[j0], B = rps[j1];
+          for (int32_t base = A; base < B; base += kWave * kFwdLoads) {
+            int32_t w[kFwdLoads];
+            uint32_t fw[kFwdLoads];
+#pragma unroll
+            for (int k = 0; k < kFwdLoads; ++k) w[k] = a.col_idx[min(base + k * kWave + lane, B - 1)];
+#pragma unroll
+            for (int k = 0; k < kFwdLoads; ++k) fw[k] = mod_word(pb, w[k], sl);
+#pragma unroll
+            for (int k = 0; k < kFwdLoads; ++k) {
+              const int32_t arc = base + k * kWave + lane;
+              const bool h = arc < B && mod_in_word(fw[k], w[k], sl);
+              arcs_hit += __popcll(__ballot(h));
+              if (h) {  // the source node: the last j in [j0, j1) with rps[j] <= arc
+                int32_t l = j0, r = j1;
+                while (r - l > 1) {
+                  const int32_t mid = (l + r) >> 1;
+                  if (rps[mid] <= arc) l = mid; else r = mid;
+                }
+                mark[l] = 1;  // the same value from every lane that hits this node
+              }
+            }
+          }
+        }
+        j0 = j1 + 1;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const bool hit = mark[lane] != 0;
+      if (hit) a.todo[v] = 1;
+      marked += (uint32_t)__popcll(__ballot(hit));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (marked && lane == 0) a.tile_todo[tile] = 1;
+  }
+  if (lane == 0 && (marked || arcs_hit))
+    atomicAdd(reinterpret_cast<unsigned long long *>(&st->sys_acc),
+              ((unsigned long long)marked << 32) | (unsigned long long)arcs_hit);
+}
+
 // Third signal kernel: the work units of the systolic pass (appended per workgroup, as in
 // k_sys_list): a chunk whose node was signalled or modified by the previous pass (the copy
 // rule), a light tile whose flag k_sys_mark set (the flag is consumed here) or that holds a
@@ -1476,31 +1613,6 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_units(PassArgs a) {
 }
 
 // ------------------------------------------------------------------ kernels: transposed graph
-
-// Sampled locality of the light nodes' arcs: for every `stride`-th node with 1..light_max
-// arcs, its arcs and those whose target lies in the source's aligned block of `block` ids
-// (the id range of a light tile), summed into out[0] and out[1].
-__global__ __launch_bounds__(kBlockThreads) void k_locality(const int32_t *rp, const int32_t *ci, int32_t n,
-                                                           int32_t light_max, int32_t block, int32_t stride,
-                                                           unsigned long long *out) {
-  const int64_t v64 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * stride;
-  uint32_t tot = 0, near = 0;
-  if (v64 < n) {
-    const int32_t v = (int32_t)v64;
-    const int32_t b = rp[v], e = rp[v + 1];
-    if (e - b <= light_max) {
-      const int32_t lo = v - v % block;
-      for (int32_t p = b; p < e; ++p) near += (uint32_t)(ci[p] - lo) < (uint32_t)block ? 1u : 0u;
-      tot = (uint32_t)(e - b);
-    }
-  }
-  tot = wave_sum(tot);
-  near = wave_sum(near);
-  if ((threadIdx.x & 63) == 0 && tot) {
-    atomicAdd(out, (unsigned long long)tot);
-    atomicAdd(out + 1, (unsigned long long)near);
-  }
-}
 
 __global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t value) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -2278,7 +2390,15 @@ hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream
 }
 
 hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  if (!a.trow_ptr) return record_empty(e0, e1, s);
+  if (!a.trow_ptr) {
+    if (!a.todo) return record_empty(e0, e1, s);
+    // no transposed graph: the marks come from a forward scan of the successor lists
+    const int64_t units = (int64_t)a.n_chunks + a.n_tiles;
+    launch_k(k_fwd_mark, dim3(grid_for(units, kBlockThreads / kWave, 1 << 30)), dim3(kBlockThreads), s, e0, nullptr, a);
+    launch_k(k_sys_units, dim3(grid_for(units, kBlockThreads * kSigRounds, 1 << 30)), dim3(kBlockThreads), s, nullptr,
+             e1, a);
+    return hipGetLastError();
+  }
   launch_k(k_sys_list, dim3(grid_for(2 * ((int64_t)a.n_blocks << a.seed_log2), kBlockThreads * kSigRounds, 1 << 30)),
            dim3(kBlockThreads), s, e0, nullptr, a);
   hipLaunchKernelGGL(k_sys_mark, dim3(grid_for(arcs, kMarkTile, 2048)), dim3(kBlockThreads), 0, s, a);
@@ -2289,16 +2409,6 @@ hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEven
 
 hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, count, value);
-  return hipGetLastError();
-}
-
-hipError_t launch_locality(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t light_max,
-                           int32_t block, int32_t stride, uint64_t *out, hipStream_t s) {
-  hipError_t e = launch_fill_u64(out, 2, 0ull, s);
-  if (e != hipSuccess) return e;
-  const int64_t sampled = ((int64_t)n + stride - 1) / stride;
-  hipLaunchKernelGGL(k_locality, dim3((unsigned)((sampled + kBlockThreads - 1) / kBlockThreads)), dim3(kBlockThreads),
-                     0, s, row_ptr, col_idx, n, light_max, block, stride, reinterpret_cast<unsigned long long *>(out));
   return hipGetLastError();
 }
 
@@ -2352,8 +2462,9 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
   return hipGetLastError();
 }
 
-// Kernels of light tiles that stage their rows in LDS (a.stage): byte registers, rows of at
-// most 16 lanes (256 bytes), 4 loads in flight (the schedule allows staging only there).
+// The instantiation that stages light tiles in LDS (a.stage) and counts near successors
+// (a.count_near; always counted when staging): byte registers, rows of at most 16 lanes
+// (256 bytes), 4 loads in flight (the schedule allows either only there).
 #define HANF_DISPATCH_STAGED(G_, EXPR)                          \
   {                                                             \
     using F = ByteRegs;                                         \
@@ -2372,12 +2483,13 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
   const dim3 block(kBlockThreads);
   const size_t lds = (size_t)a.lds_wave_bytes * (kBlockThreads / kWave);
   if (a.n_chunk_wgs + a.n_light_wgs == 0 || (!full && !list)) return record_empty(e0, e1, s);
-  if (a.stage && (a.packed || u != 4)) return hipErrorInvalidValue;
+  const bool st = a.stage || a.count_near;  // the instantiation that stages and counts near successors
+  if (st && (a.packed || u != 4)) return hipErrorInvalidValue;
   if (full) {
     const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
     const int32_t list_too = list ? 1 : 0;
     hipEvent_t end = list ? nullptr : e1;
-    if (a.stage) {
+    if (st) {
       HANF_DISPATCH_STAGED(G, launch_k_lds(k_union<F, G, 4, true>, grid, block, lds, s, e0, end, a, list_too));
     } else {
       switch (u) {
@@ -2398,7 +2510,7 @@ hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_
     const dim3 grid((unsigned)grid_for(units, kBlockThreads / kWave, kListWgs));
     const int32_t full_too = full ? 1 : 0;
     hipEvent_t start = full ? nullptr : e0;
-    if (a.stage) {
+    if (st) {
       HANF_DISPATCH_STAGED(G, launch_k_lds(k_union_list<F, G, 4, true>, grid, block, lds, s, start, e1, a, full_too));
     } else {
       switch (u) {

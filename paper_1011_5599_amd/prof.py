@@ -2,9 +2,12 @@
 
 * the kernel-time table of a `rocprofv3 --kernel-trace --stats` run, with the union step's
   average time per pass beside bench.py's own HIP-event figure from the same run;
-* the HBM bytes of the union step per pass, from two `rocprofv3 --pmc` runs (FETCH_SIZE,
-  then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for a
-  plain device copy of known size (`bench.py --copy-calibration MIB`).
+* the bytes the union step moves beyond L2 per pass, from two `rocprofv3 --pmc` runs
+  (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+  for a plain device copy of known size (`bench.py --copy-calibration MIB`). These count the
+  L2's requests to the memory fabric, so reads served by the Infinity Cache are included:
+  an upper bound on the bytes that reach HBM. Beside them, per pass, the algorithmic bytes
+  and the bytes of the roofline model bench.py reports.
 
 The union step of a pass is every k_union / k_union_list dispatch between two k_reduce_top
 dispatches (in a systolic pass both may be launched, one of them leaving at once); passes
@@ -60,17 +63,22 @@ def _dispatches(path: str):
     return out
 
 
-def union_per_pass(dispatches, passes_per_run):
+def union_per_pass(dispatches, passes_per_run, max_runs=None):
     """Sums of the union-step values of every executed pass: a run starts at k_init, its
     first k_reduce_top is the initial estimate, and each later k_reduce_top closes a pass.
     Only the first `passes_per_run` passes of a run count: passes enqueued after the fixpoint
-    return at once."""
+    return at once. With max_runs, runs after the first max_runs (bench.py's untimed
+    diagnostic runs) are left out."""
     out, run, cur = [], None, None
+    runs = 0
     for _, name, val in dispatches:
         s = _short(name)
         if s.startswith("k_init"):
             if run:
                 out += run[:passes_per_run]
+            if max_runs is not None and runs >= max_runs:
+                return out
+            runs += 1
             run, cur = [], None
         elif run is None:
             continue
@@ -82,6 +90,19 @@ def union_per_pass(dispatches, passes_per_run):
             cur += val
     if run:
         out += run[:passes_per_run]
+    return out
+
+
+def counter_runs(path: str):
+    """{counter name: [(dispatch id, kernel name, value)]} of a counter-collection CSV that may
+    hold several counters per dispatch."""
+    out = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            out.setdefault(r["Counter_Name"], []).append(
+                (int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    for v in out.values():
+        v.sort()
     return out
 
 
@@ -106,6 +127,9 @@ def main():
     ap.add_argument("--copy-fetch")
     ap.add_argument("--copy-write")
     ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--counters", action="append", default=[],
+                    help="rocprofv3 --pmc output dir of a run with other counters (repeatable); its "
+                         "bench.py JSON line is DIR.json")
     ap.add_argument("--commands", required=True, help="text file with the commands that were run")
     ap.add_argument("--out-md", required=True)
     ap.add_argument("--out-json")
@@ -114,7 +138,7 @@ def main():
     bench = json.loads(open(args.trace_json).read().strip().splitlines()[-1])
     table = kernel_table(args.trace)
     trace = _dispatches(os.path.join(args.trace, "run_kernel_trace.csv"))
-    per_pass_ns = union_per_pass(trace, bench["config"]["passes"])
+    per_pass_ns = union_per_pass(trace, bench["config"]["passes"], bench["steps"] + bench["warmup"])
     step_avg_us = sum(per_pass_ns) / len(per_pass_ns) / 1e3 if per_pass_ns else float("nan")
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
 
@@ -127,7 +151,7 @@ def main():
     L += [f"{runs} HyperANF runs ({bench['warmup']} warm-up + {bench['steps']} timed), "
           f"{bench['config']['passes']} passes each (T = {bench['config']['T']}, pass kinds "
           f"{bench['config'].get('pass_kinds', '?')}: D all successors, F modified-flag frontier, "
-          f"S systolic).", ""]
+          f"S systolic through the transposed graph, M systolic marked by a forward scan).", ""]
     L += ["| kernel | calls | avg µs | total ms | % |", "|---|---:|---:|---:|---:|"]
     for r in table:
         L.append(f"| {r['name']} | {r['calls']} | {r['avg_us']:.1f} | {r['total_ms']:.3f} | {r['pct']:.2f} |")
@@ -140,31 +164,53 @@ def main():
     if args.fetch and args.write and args.pmc_json and args.copy_fetch and args.copy_write:
         pmc = json.loads(open(args.pmc_json).read().strip().splitlines()[-1])
         alg = pmc["pass_algorithmic_bytes"]
+        model = pmc.get("pass_model_bytes", alg)
         pr = pmc["config"]["passes"]
-        fetch = union_per_pass(_dispatches(os.path.join(args.fetch, "run_counter_collection.csv")), pr)
-        write = union_per_pass(_dispatches(os.path.join(args.write, "run_counter_collection.csv")), pr)
+        runs_pmc = pmc["steps"] + pmc["warmup"]
+        fetch = union_per_pass(_dispatches(os.path.join(args.fetch, "run_counter_collection.csv")), pr, runs_pmc)
+        write = union_per_pass(_dispatches(os.path.join(args.write, "run_counter_collection.csv")), pr, runs_pmc)
         copy_bytes = args.copy_mib << 20
         fs = copy_scale(args.copy_fetch, copy_bytes)
         ws = copy_scale(args.copy_write, copy_bytes)
         n = min(len(fetch), len(write), len(alg))
-        L += ["## HBM byte counters", ""]
+        L += ["## Bytes beyond L2 (FETCH_SIZE, WRITE_SIZE)", ""]
         L += [f"Calibration: a plain {args.copy_mib} MiB device copy reads FETCH_SIZE and WRITE_SIZE such "
-              f"that FETCH_SIZE is scaled by {fs:.3f} and WRITE_SIZE by {ws:.3f} to bytes.", ""]
-        L += ["| pass t | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM GB | algorithmic GB | ratio |",
-              "|---:|---:|---:|---:|---:|---:|"]
-        tot_hbm = tot_alg = 0.0
+              f"that FETCH_SIZE is scaled by {fs:.3f} and WRITE_SIZE by {ws:.3f} to bytes. The counters "
+              "count the L2's requests to the memory fabric: reads the Infinity Cache serves are "
+              "included, so these bytes bound the HBM bytes from above. Model: the roofline's bytes "
+              "(algorithmic, less the successor counters within the near window of their node).", ""]
+        L += ["| pass t | FETCH_SIZE KiB | WRITE_SIZE KiB | beyond L2 GB | algorithmic GB | model GB | "
+              "beyond L2 / model |", "|---:|---:|---:|---:|---:|---:|---:|"]
+        tot_hbm = tot_alg = tot_mod = 0.0
         for t in range(n):
             hbm = fetch[t] * 1024 * fs + write[t] * 1024 * ws
             tot_hbm += hbm
             tot_alg += alg[t]
+            tot_mod += model[t]
             L.append(f"| {t} | {fetch[t]:.0f} | {write[t]:.0f} | {hbm / 1e9:.3f} | {alg[t] / 1e9:.3f} | "
-                     f"{hbm / alg[t]:.2f} |")
-        L += ["", f"Per pass (average of {n}): {tot_hbm / n / 1e9:.3f} GB moved beyond L2 vs "
-                  f"{tot_alg / n / 1e9:.3f} GB algorithmic (ratio {tot_hbm / tot_alg:.2f}).", ""]
+                     f"{model[t] / 1e9:.3f} | {hbm / model[t]:.2f} |")
+        L += ["", f"Per pass (average of {n}): {tot_hbm / n / 1e9:.3f} GB moved beyond L2, "
+                  f"{tot_alg / n / 1e9:.3f} GB algorithmic, {tot_mod / n / 1e9:.3f} GB in the model "
+                  f"(beyond L2 / model {tot_hbm / tot_mod:.2f}).", ""]
         rec = dict(kernel="union step (k_union, k_union_list)", workload=args.workload,
                    kernel_source_sha256=sha, traffic_bytes_per_launch=int(tot_hbm / n),
-                   algorithmic_bytes_per_launch=int(tot_alg / n), fetch_scale=fs, write_scale=ws,
-                   launches=n)
+                   traffic_kind="bytes beyond L2 (FETCH_SIZE + WRITE_SIZE, scaled by a device copy; "
+                                "Infinity Cache hits included)",
+                   algorithmic_bytes_per_launch=int(tot_alg / n), model_bytes_per_launch=int(tot_mod / n),
+                   fetch_scale=fs, write_scale=ws, launches=n)
+    if args.counters:
+        L += ["## Other counters of the union step", "",
+              "Summed over the union dispatches of a pass (k_union, k_union_list); first pass (every "
+              "successor gathered) and the average over the passes of one run.", "",
+              "| counter | first pass | average per pass |", "|---|---:|---:|"]
+        for d in args.counters:
+            cj = json.loads(open(d.rstrip("/") + ".json").read().strip().splitlines()[-1])
+            pr, runs_c = cj["config"]["passes"], cj["steps"] + cj["warmup"]
+            for name, rows in sorted(counter_runs(os.path.join(d, "run_counter_collection.csv")).items()):
+                per = union_per_pass(rows, pr, runs_c)
+                if per:
+                    L.append(f"| {name} | {per[0]:.4g} | {sum(per) / len(per):.4g} |")
+        L += [""]
     L += [f"Kernel source at measurement: `paper_1011_5599_amd/csrc/hanf_kernels.hip` sha256 `{sha[:16]}…` "
           "(bench.py reports `traffic` only while the source is unchanged)."]
     with open(args.out_md, "w") as f:

@@ -94,3 +94,12 @@ def test_cpu_threads_follow_affinity_and_share(bench, monkeypatch):
     monkeypatch.setattr(bench.os, "sched_getaffinity", lambda pid: set(range(8)))
     monkeypatch.setenv("OMP_NUM_THREADS", "16")
     assert bench.cpu_threads() == (8, 8)
+
+
+def test_model_bytes_leave_out_near_gathers(bench):
+    # with a near count from the instrumented kernels, those successor counters are left out
+    # (and the LDS count is not subtracted again: staged reads are near ones)
+    n, m = 1 << 24, 128
+    rec = {"arcs_scanned": 1000, "arcs_gathered": 900, "rows_read": 50, "rows_written": 40, "arcs_local": 300}
+    assert bench.model_bytes(rec, n, m, near=700) == bench.algorithmic_bytes(rec, n, m) - 700 * m
+    assert bench.model_bytes(rec, n, m, near=-1) == bench.algorithmic_bytes(rec, n, m) - 300 * m

@@ -4,9 +4,10 @@
   the oracle's at every iteration, N_hat(t) within 1e-12, same T (also with 5-bit packed
   registers);
 * web-like graph of 2^24 nodes (3.4e8 arcs, 80% intra-host), 128 registers, hash seed 1:
-  registers byte-equal to the oracle's at every iteration in two runs side by side (flag
-  frontier, and systolic passes over a transposed graph built on the device), N_hat(t)
-  within 1e-12, same T; N_hat(0) against its closed form and, for sampled nodes, c_t[v]
+  registers byte-equal to the oracle's at every iteration in three runs side by side
+  (flag-frontier passes, the benchmark's configuration; systolic passes marked by a forward
+  scan; systolic passes over a transposed graph built on the device), N_hat(t) within
+  1e-12, same T; N_hat(0) against its closed form and, for sampled nodes, c_t[v]
   against the counter of the ball B(v, t) built by BFS (the identity of Section 3.2) at
   t = 1, 2, 3.
 * directed R-MAT scale 14 at every iteration is in test_gpu_parity.py.
@@ -34,18 +35,20 @@ def _say(msg):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("systolic,packed", [(False, False), (True, False), (True, True)])
+@pytest.mark.parametrize("systolic,packed", [(False, False), (True, False), (True, True), ("forward", False)])
 def test_rmat22sym_every_iteration(systolic, packed):
     """With systolic=True in the benchmark's configuration: the symmetric graph's own
-    device arrays serve as its transpose. packed: 5-bit registers (read back unpacked)."""
+    device arrays serve as its transpose; "forward": no transpose, systolic passes marked by
+    a forward scan; False: no transpose and flag-frontier passes. packed: 5-bit registers
+    (read back unpacked)."""
     import torch
     spec = graphgen.WORKLOADS["rmat22sym"]
     rp, ci = graphgen.workload_graph(spec)
     b, seed = spec["log2m"], spec["seed"]
     _say(f"[fullsize] rmat22sym n={len(rp) - 1} arcs={len(ci)} b={b} seed={seed} systolic={systolic} "
          f"packed={packed}")
-    with hanf.HyperANF(0, packed5=int(packed)) as h:
-        if systolic:
+    with hanf.HyperANF(0, packed5=int(packed), forward=int(systolic == "forward")) as h:  # (forward: option)
+        if systolic is True:
             drp, dci = torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda()
             h.load(drp, dci).load_transpose(drp, dci)
         else:
@@ -64,15 +67,17 @@ def test_rmat22sym_every_iteration(systolic, packed):
         nt = h.nt()
         assert len(nt) == T + 1
         np.testing.assert_allclose(nt, np.array(want), rtol=1e-12, atol=0)
-        assert any(r["systolic"] for r in h.pass_log()) == systolic
+        kinds = {r["systolic"] for r in h.pass_log()}
+        assert kinds == ({0, 1} if systolic is True else {0, 2} if systolic == "forward" else {0}), kinds
 
 
 @pytest.mark.timeout(1200)
 def test_web24_every_iteration():
     """The web-like workload at full size (2^24 nodes, 80% of the arcs intra-host), run
-    twice side by side: flag-frontier passes (no transposed graph, the benchmark's
-    configuration) and systolic passes (transposed graph built on the device). At every t
-    both runs' registers equal the oracle's c_t byte for byte; N_hat(t) within 1e-12; same
+    three times side by side: no transposed graph with flag-frontier passes (the benchmark's
+    configuration), the same with systolic passes marked by a forward scan, and systolic
+    passes through a transposed graph built on the device. At every t every run's registers
+    equal the oracle's c_t byte for byte; N_hat(t) within 1e-12; same
     T. Also N_hat(0) against its closed form and, for sampled nodes, c_t[v] against the
     counter of the ball B(v, t) (Section 3.2) at t = 1, 2, 3."""
     spec = graphgen.WORKLOADS["web24"]
@@ -83,14 +88,15 @@ def test_web24_every_iteration():
     _say(f"[fullsize] web24 n={n} arcs={len(ci)} b={b} seed={seed} threads={THREADS}")
     rng = np.random.default_rng(2024)
     sample = rng.choice(n, 8, replace=False)
-    with hanf.HyperANF(0) as h, hanf.HyperANF(0) as hs:
+    with hanf.HyperANF(0, forward=1) as hf, hanf.HyperANF(0) as h, hanf.HyperANF(0) as hs:
+        hf.load(rp, ci).init(b, seed)
         h.load(rp, ci).init(b, seed)
         hs.load(rp, ci).build_transpose().init(b, seed)
         want = []
         T = None
         for t, c, s in oracle.run_steps(rp, ci, b, seed, nthreads=THREADS):
             want.append(s)
-            for name, ctx in (("frontier", h), ("systolic", hs)):
+            for name, ctx in (("forward", hf), ("frontier", h), ("systolic", hs)):
                 got = ctx.registers()
                 assert np.array_equal(got, c), f"{name}: registers differ at t={t}"
                 del got
@@ -100,15 +106,17 @@ def test_web24_every_iteration():
                     assert np.array_equal(c[v], M), (t, int(v))
             st, _, _ = h.step(1)
             st_s, _, _ = hs.step(1)
+            st_f, _, _ = hf.step(1)
             T = t
             _say(f"[fullsize] web24 t={t} ok")
-        assert st == hanf.HANF_DONE and st_s == hanf.HANF_DONE
+        assert st == hanf.HANF_DONE and st_s == hanf.HANF_DONE and st_f == hanf.HANF_DONE
         assert T >= 10  # a long diameter: many passes, frontier skipping exercised
-        for ctx in (h, hs):
+        for ctx in (hf, h, hs):
             nt = ctx.nt()
             assert len(nt) == T + 1
             np.testing.assert_allclose(nt, np.array(want), rtol=1e-12, atol=0)
         assert want[0] == pytest.approx(n * m * math.log(m / (m - 1)), rel=1e-12)
-        kinds = [r["systolic"] for r in hs.pass_log()]
-        assert any(kinds) and not any(r["systolic"] for r in h.pass_log())
+        assert {r["systolic"] for r in hs.pass_log()} == {0, 1}
+        assert {r["systolic"] for r in hf.pass_log()} == {0, 2}
+        assert not any(r["systolic"] for r in h.pass_log())
         assert any(not r["gather_all"] for r in h.pass_log())  # flag-frontier passes ran

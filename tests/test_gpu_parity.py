@@ -54,14 +54,28 @@ def _load(h, rp, ci, transpose):
     return h
 
 
+def near_window(b, packed=False):
+    """W of the pass records' arcs_near: the rows 4 MiB holds, halved (one counter per row)."""
+    m = 1 << b
+    row = (m // 64) * 40 if packed else m
+    return (2 << 20) // row
+
+
 def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
     """Runs GPU and oracle side by side one pass at a time; checks everything."""
     n = len(rp) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    W = near_window(b, opts.get("packed5", 0) == 1 and b >= 6)
+    near_arc = np.abs(np.asarray(ci, np.int64) - src) < W  # in the caller's ids
+    check_near = opts.get("hubs", 0) <= 0  # (a chosen node order renumbers the ids)
     _flush(f"[parity] n={n} arcs={len(ci)} b={b} seed={seed} transpose={transpose} opts={opts}")
     ref = oracle.run_steps(rp, ci, b, seed, skip_unmodified=True)
     mod = np.ones(n, np.uint8)
     prev_changed = 0
-    sys_div = opts.get("systolic", 4) if transpose else 0
+    # without a transposed graph, systolic passes can take their marks from a forward scan of
+    # the successor lists (HANF_OPT_FORWARD, off by default)
+    forward = not transpose and opts.get("forward", 0)
+    sys_div = opts.get("systolic", 4) if (transpose or forward) else 0
     with hanf.HyperANF(0, **opts) as h:
         _load(h, rp, ci, transpose).init(b, seed)
         nts = []
@@ -83,17 +97,25 @@ def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
                 assert log["arcs_gathered"] == log["arcs_scanned"], (t, log)
             else:
                 assert log["arcs_gathered"] == maxed, (t, log, maxed)
+            if check_near and log["arcs_near"] >= 0:  # (counted by the instrumented kernels)
+                # gathered successors within W ids of their node
+                gathered = near_arc if log["gather_all"] else near_arc & (mod[ci] != 0)
+                assert log["arcs_near"] == int(np.count_nonzero(gathered)), (t, log)
+            elif not (opts.get("stage") or opts.get("count_near")):
+                assert log["arcs_near"] == -1, (t, log)
             assert log["gather_all"] == (t == 0 or not opts.get("frontier", 1)
                                          or (opts.get("dense_switch", 4) > 0
                                              and prev_changed >= max(1, n // opts.get("dense_switch", 4))))
-            # systolic after a pass that changed < n / sys_div counters, unless it would signal
-            # more than arcs / 16 arcs
+            # systolic after a pass that changed < n / sys_div counters, unless signals through
+            # the transpose would follow more than arcs / 16 arcs (a forward scan has no such
+            # fallback: it has read every arc already)
             want_sys = (not log["gather_all"] and opts.get("frontier", 1) and sys_div > 0
-                        and prev_changed * sys_div < n and maxed * 16 <= len(ci))
-            assert log["systolic"] == int(bool(want_sys)), (t, log)
+                        and prev_changed * sys_div < n and (forward or maxed * 16 <= len(ci)))
+            assert log["systolic"] == (0 if not want_sys else 2 if forward else 1), (t, log)
             if log["systolic"]:
                 # every arc into a counter modified by the previous pass is signalled once:
-                # the same arcs the frontier gathers, counted from the other end
+                # the same arcs the frontier gathers (counted from the other end through the
+                # transpose)
                 assert log["arcs_signalled"] == maxed, (t, log, maxed)
             prev_changed = changed
             assert ch_last == changed
@@ -372,3 +394,29 @@ def test_forced_allocation_failure():
             h.load(rp, ci).init(6, 1)
         assert e.value.code == hanf.HANF_ENOMEM
         h.close()
+
+
+@pytest.mark.parametrize("case", ["rmat14", "web", "star", "cycle", "packed", "persistent"])
+def test_forward_scan_systolic_every_iteration(case):
+    """Systolic passes without a transposed graph (HANF_OPT_FORWARD = 1): the nodes to
+    recompute are found by a forward scan of the successor lists. Registers, estimates,
+    N_hat, T and the work counters equal the oracle's at every t; each systolic pass's
+    signalled arcs equal the oracle's count of arcs into modified counters."""
+    if case == "rmat14":
+        rp, ci = graphgen.workload_graph(graphgen.WORKLOADS["rmat14"])
+        step_parity(rp, ci, 4, 1, forward=1)
+    elif case == "web":
+        rp, ci = graphgen.web(1 << 14, host_mean=100.0, seed=61, keep_kind=True)
+        step_parity(rp, ci, 7, 2, forward=1, systolic=2)
+    elif case == "star":  # one heavy row split into chunks
+        rp, ci = graphgen.star_out(20000)
+        step_parity(rp, ci, 6, 3, forward=1, systolic=1)
+    elif case == "cycle":
+        rp, ci = graphgen.directed_cycle(700)
+        step_parity(rp, ci, 5, 4, forward=1)
+    elif case == "packed":
+        rp, ci = graphgen.rmat(12, 50000, seed=62)
+        step_parity(rp, ci, 6, 5, forward=1, packed5=1)
+    else:  # every pass through the persistent kernel over listed units
+        rp, ci = graphgen.rmat(12, 50000, seed=63)
+        step_parity(rp, ci, 6, 6, forward=1, union_policy=2, chunk_arcs=256)

@@ -36,17 +36,22 @@ GRAPHS = {
 
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("b", [4, 6, 7, 8])
-def test_staged_every_iteration(name, b):
+@pytest.mark.parametrize("mode", ["stage", "count_near"])
+def test_staged_every_iteration(name, b, mode):
+    """mode stage: staged tiles (near successors counted too); count_near: the instrumented
+    kernels without staging. step_parity also checks every pass's near count against numpy."""
     rp, ci = GRAPHS[name]()
-    step_parity(rp, ci, b, seed=5 + b, stage=1)
-    with hanf.HyperANF(0, stage=1) as h:
+    step_parity(rp, ci, b, seed=5 + b, **{mode: 1})
+    with hanf.HyperANF(0, **{mode: 1}) as h:
         h.load(rp, ci).init(b, 5 + b)
         h.run()
         log = h.pass_log()
     dense = [r for r in log if r["gather_all"]]
-    assert dense and all(0 <= r["arcs_local"] <= r["arcs_gathered"] for r in log)
+    assert dense and all(0 <= r["arcs_local"] <= r["arcs_near"] <= r["arcs_gathered"] for r in log)
     assert all(r["arcs_local"] == 0 for r in log if not r["gather_all"])  # staging only there
-    if name.startswith("web") or name in ("cycle_1000", "path_130"):
+    if mode == "count_near":
+        assert all(r["arcs_local"] == 0 for r in log)
+    elif name.startswith("web") or name in ("cycle_1000", "path_130"):
         assert dense[0]["arcs_local"] > 0, dense[0]
 
 
@@ -57,34 +62,36 @@ def test_staged_with_systolic_passes(b):
     step_parity(rp, ci, b, seed=3, transpose="build", stage=1)
 
 
-def test_auto_choice_follows_locality():
-    """Automatic staging (the default) is chosen for a web-like graph, whose intra-host arcs
-    stay inside a tile, and not for R-MAT ids; both give the same results as staging off."""
+def test_staging_is_off_by_default_and_changes_nothing():
+    """Staging is off by default; forced on, a web-like graph (its intra-host arcs mostly
+    inside a tile) reads a third or more of its first pass's successors from LDS, R-MAT ids
+    none beyond their own tile; N_hat (same sums, same order), registers and the gathered
+    counts are identical either way, and equal the oracle's."""
     cases = {"web": graphgen.web(1 << 16, seed=35, keep_kind=True),
              "rmat": graphgen.rmat(16, 1 << 20, seed=36)}
     for name, (rp, ci) in cases.items():
         b, seed = 7, 9
         out = {}
-        for stage in (-1, 0, 1):
-            with hanf.HyperANF(0, stage=stage) as h:
+        for stage in (None, 0, 1):
+            opts = {} if stage is None else {"stage": stage}
+            with hanf.HyperANF(0, **opts) as h:
                 h.load(rp, ci).init(b, seed)
                 nt = h.run()
                 out[stage] = (nt, h.registers().copy(), h.pass_log())
-        _say(f"[stage] {name}: first pass local {out[-1][2][0]['arcs_local']} of "
-             f"{out[-1][2][0]['arcs_gathered']}")
-        for stage in (-1, 1):
+        first = out[1][2][0]
+        _say(f"[stage] {name}: first pass local {first['arcs_local']} near {first['arcs_near']} of "
+             f"{first['arcs_gathered']}")
+        for stage in (None, 1):
             assert np.array_equal(out[stage][0], out[0][0])  # same sums in the same order
             assert np.array_equal(out[stage][1], out[0][1])
             assert [r["arcs_gathered"] for r in out[stage][2]] == [r["arcs_gathered"] for r in out[0][2]]
-        first = out[-1][2][0]
+        assert all(r["arcs_local"] == 0 and r["arcs_near"] == -1 for r in out[None][2] + out[0][2])
         if name == "web":  # (the intra-host arcs of a node of ~20 reach beyond +-16 ids)
             assert first["arcs_local"] > 0.3 * first["arcs_gathered"], first
-        else:
-            assert first["arcs_local"] == 0, first
-        assert out[0][2][0]["arcs_local"] == 0
+        assert first["arcs_local"] <= first["arcs_near"] <= first["arcs_gathered"]
         nt_o, T_o, _ = oracle.run(rp, ci, b, seed, nthreads=8)
-        assert len(out[-1][0]) == T_o + 1
-        np.testing.assert_allclose(out[-1][0], nt_o, rtol=1e-12, atol=0)
+        assert len(out[1][0]) == T_o + 1
+        np.testing.assert_allclose(out[1][0], nt_o, rtol=1e-12, atol=0)
 
 
 def test_staged_batch_components():
