@@ -51,6 +51,13 @@ __device__ __forceinline__ uint4 bytemax4(uint4 a, uint4 b) {
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 
+// Maxima of the two 16-bit halves of a and b (one v_pk_max_u16).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(u16x2, a),
+                                                                __builtin_bit_cast(u16x2, b)));
+}
+
 // Was any counter of node v's row modified? (S = 2^sl flag bits per node, never across words.)
 __device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl) {
   const uint64_t i = (uint64_t)v << sl;
@@ -97,6 +104,38 @@ struct ByteRegs {
     *reinterpret_cast<uint4 *>(regs + ((size_t)row * G + sub) * kBytes) = x;
   }
   static __device__ __forceinline__ Lane max(Lane a, Lane b) { return bytemax4(a, b); }
+  // The part of row `row` a lane holds, given lane_base = regs + sub * kBytes (of the lane's
+  // row position) and G lanes per row.
+  static __device__ __forceinline__ Lane load_at(const uint8_t *lane_base, uint32_t row, int G) {
+    // (rows of G * 16 bytes, a power of two: one 64-bit shift-and-add per address)
+    return *reinterpret_cast<const uint4 *>(lane_base + ((uint64_t)row << __builtin_ctz((uint32_t)(G * kBytes))));
+  }
+  // Accumulator of the register-wise max of many gathered counters. Two sets of 16-bit
+  // maxima: `hi` over the 16-bit halves of each word as they are, `lo` over the words
+  // shifted up by one byte. Of two pairs (h, l) of bytes the larger 16-bit value has the
+  // larger h, so the high byte of a 16-bit maximum is the largest high byte: bytes 1 and 3
+  // of the register-wise max are the high bytes of `hi`, bytes 0 and 2 those of `lo` (the low
+  // bytes are not used). Three instructions per gathered 32-bit word (a shift and two
+  // packed maxima) instead of the six of bytemax; the counter is put together once.
+  struct Acc {
+    uint4 hi, lo;
+  };
+  static __device__ __forceinline__ Acc acc_zero() { return Acc{zero4(), zero4()}; }
+  static __device__ __forceinline__ Acc acc_from(Lane x) {
+    return Acc{x, make_uint4(x.x << 8, x.y << 8, x.z << 8, x.w << 8)};
+  }
+  static __device__ __forceinline__ void acc_add(Acc &a, Lane x) {
+    a.hi = make_uint4(max_u16x2(a.hi.x, x.x), max_u16x2(a.hi.y, x.y), max_u16x2(a.hi.z, x.z), max_u16x2(a.hi.w, x.w));
+    a.lo = make_uint4(max_u16x2(a.lo.x, x.x << 8), max_u16x2(a.lo.y, x.y << 8), max_u16x2(a.lo.z, x.z << 8),
+                      max_u16x2(a.lo.w, x.w << 8));
+  }
+  static __device__ __forceinline__ Lane acc_value(const Acc &a) {
+    // bytes 3, 2, 1, 0 from hi.byte3, lo.byte3, hi.byte1, lo.byte1 (v_perm: bytes 4..7 are
+    // the first operand's, 0..3 the second's)
+    constexpr uint32_t sel = 0x07030501u;
+    return make_uint4(__builtin_amdgcn_perm(a.hi.x, a.lo.x, sel), __builtin_amdgcn_perm(a.hi.y, a.lo.y, sel),
+                      __builtin_amdgcn_perm(a.hi.z, a.lo.z, sel), __builtin_amdgcn_perm(a.hi.w, a.lo.w, sel));
+  }
   static __device__ __forceinline__ bool differ(Lane a, Lane b) {
     return a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w;
   }
@@ -219,6 +258,23 @@ struct Packed5Regs {
     }
     return out;
   }
+  static __device__ __forceinline__ Lane load_at(const uint8_t *lane_base, uint32_t row, int G) {
+    const uint2 *p = reinterpret_cast<const uint2 *>(lane_base + (uint64_t)row * (uint32_t)(G * kBytes));
+    Lane x;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const uint2 t = p[k];
+      x.w[2 * k] = t.x;
+      x.w[2 * k + 1] = t.y;
+    }
+    return x;
+  }
+  // the gather accumulator is the lane itself (broadword max per counter gathered)
+  using Acc = Lane;
+  static __device__ __forceinline__ Acc acc_zero() { return zero(); }
+  static __device__ __forceinline__ Acc acc_from(Lane x) { return x; }
+  static __device__ __forceinline__ void acc_add(Acc &a, Lane x) { a = max(a, x); }
+  static __device__ __forceinline__ Lane acc_value(const Acc &a) { return a; }
   static __device__ __forceinline__ bool differ(Lane a, Lane b) {
     uint32_t d = 0u;
 #pragma unroll
@@ -387,13 +443,14 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
   }
 }
 
-// One round of a light tile: each slot handles one node. Per step the slot's G lanes load
-// G*U consecutive successor ids (lane `sub` takes ids p + k*G + sub), keep those to maximise
-// in (all of them, or those modified by the previous pass), compact the kept ids into the
-// slot's queue in LDS and gather the queued counters U at a time.
+// One round of a light tile: each slot handles one node v (-1: none), whose arcs are
+// [beg, end). Per step the slot's G lanes load G*U consecutive successor ids (lane `sub`
+// takes ids p + k*G + sub), keep those to maximise in (all of them, or those modified by
+// the previous pass), compact the kept ids into the slot's queue in LDS and gather the
+// queued counters U at a time.
 template <class F, int G, int U, bool ST>
-__device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int lane,
-                                            int32_t *queue, Counters &cnt, bool count_scan,
+__device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, int32_t v, int32_t beg, int32_t end,
+                                            int lane, int32_t *queue, Counters &cnt, bool count_scan,
                                             const uint8_t *stage, bool staged, int32_t lo) {
   using Lane = typename F::Lane;
   const int sub = lane % G;
@@ -401,15 +458,11 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
   const uint64_t smask = ((G == 64) ? ~0ull : ((1ull << G) - 1ull)) << first;
   const uint64_t below = (1ull << lane) - 1ull;
   int32_t *q = queue + first * U;  // G*U entries per slot
-  int32_t beg = 0, end = 0;
-  if (v >= 0) {
-    beg = a.row_ptr[v];
-    end = a.row_ptr[v + 1];
-  }
   // every node handed to a light round produces a new counter (all nodes in a pass over
   // all successors; otherwise nodes with a modified successor or a stale update row), so
   // its own counter is loaded up front, in parallel with the scan
-  Lane own = F::zero(), acc = F::zero();
+  Lane own = F::zero();
+  typename F::Acc acc = F::acc_zero();
   bool own_loaded = false;
   if (end > beg) {
     // (two one-sided branches, not an if-else: the compiler would merge the two loads into
@@ -418,9 +471,10 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     if constexpr (ST) {
       if (staged) own = stage_row(stage, v - lo, G, sub);
     }
-    if (f.gather_all) acc = own;
+    if (f.gather_all) acc = F::acc_from(own);
     own_loaded = true;
   }
+  const uint8_t *lane_base = f.cur + sub * F::kBytes;
   int32_t gathered = 0, local = 0, near = 0;
   for (int32_t p = beg; p < end; p += G * U) {
     int32_t w[U];
@@ -449,6 +503,8 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // Queue entries past the slot's last are read as its last one: a counter maximised in
+    // twice changes nothing, and every load is then unconditional.
     for (int32_t j = 0; j < total; j += U) {
       Lane x[U];
       if constexpr (ST) {
@@ -473,14 +529,14 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
           }
         } else {
 #pragma unroll
-          for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
+          for (int i = 0; i < U; ++i) x[i] = F::load_at(lane_base, (uint32_t)q[min(j + i, total - 1)], G);
         }
       } else {
 #pragma unroll
-        for (int i = 0; i < U; ++i) x[i] = (j + i < total) ? F::load(f.cur, q[j + i], G, sub) : F::zero();
+        for (int i = 0; i < U; ++i) x[i] = F::load_at(lane_base, (uint32_t)q[min(j + i, total - 1)], G);
       }
 #pragma unroll
-      for (int i = 0; i < U; ++i) acc = F::max(acc, x[i]);
+      for (int i = 0; i < U; ++i) F::acc_add(acc, x[i]);
     }
     gathered += total;
     if (count_scan && sub == 0) cnt.scanned += min(G * U, end - p);
@@ -492,7 +548,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     cnt.local += local;
   }
   if constexpr (ST) cnt.near += near;
-  finalize_slot<F, G>(a, f, v, lane, acc, gathered > 0, own_loaded, own, cnt);
+  finalize_slot<F, G>(a, f, v, lane, F::acc_value(acc), gathered > 0, own_loaded, own, cnt);
 }
 
 // Max across the W slots of a wavefront (all lanes active).
@@ -651,7 +707,8 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   // systolic pass: a node no modified successor signalled keeps its counter (its arcs are
   // not read; the copy rule below still applies)
   const int32_t a1 = (f.systolic && f.todo[ch.v] == 0) ? ch.a0 : ch.a1;
-  Lane acc = F::zero();
+  typename F::Acc acc_s = F::acc_zero();
+  const uint8_t *lane_base = f.cur + sub * F::kBytes;
   // a node in a single chunk is finalised here: its own counter is loaded up front, in
   // parallel with the scan (it is needed unless no successor was modified and its update
   // row is current, which is rare where chunks are read)
@@ -686,15 +743,12 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    for (int32_t j = slot; j < total; j += W * U) {
+    for (int32_t j = slot; j < total; j += W * U) {  // (entries past the last read as the last)
       Lane x[U];
 #pragma unroll
-      for (int i = 0; i < U; ++i) {
-        const int32_t e = j + i * W;
-        x[i] = e < total ? F::load(f.cur, q[e], G, sub) : F::zero();
-      }
+      for (int i = 0; i < U; ++i) x[i] = F::load_at(lane_base, (uint32_t)q[min(j + i * W, total - 1)], G);
 #pragma unroll
-      for (int i = 0; i < U; ++i) acc = F::max(acc, x[i]);
+      for (int i = 0; i < U; ++i) F::acc_add(acc_s, x[i]);
     }
     gathered += total;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -705,6 +759,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     cnt.gathered += gathered;
     if constexpr (ST) cnt.near += near;
   }
+  Lane acc = F::acc_value(acc_s);
   bool any = gathered > 0;  // wavefront-uniform
   if (any) combine_slots<F, G>(acc, any);
   if (ch.part < 0) {
@@ -730,29 +785,19 @@ __device__ __forceinline__ T wave_sum(T x) {
   return x;
 }
 
-// Adds the workgroup's work counters to one of kStatSlots slot rows (spread to avoid
-// contention); k_reduce_top sums and clears the slots.
-__device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *slots) {
-  __shared__ int32_t red[kStatFields][kBlockThreads / kWave];
+// Adds the wavefront's work counters to one of kStatSlots slot rows (spread to avoid
+// contention; lane k adds field k); k_reduce_top sums and clears the slots. Per wavefront
+// and without a workgroup barrier, so that a wavefront that finishes its unit leaves at
+// once instead of holding its slot until the workgroup's slowest wavefront is done.
+__device__ __forceinline__ void add_wave_counters(const Counters &c, int64_t *slots) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t s0 = wave_sum(c.scanned), s1 = wave_sum(c.gathered), s2 = wave_sum(c.written),
                 s3 = wave_sum(c.read), s4 = wave_sum(c.local), s5 = wave_sum(c.near);
-  if (lane == 0) {
-    red[0][wave] = s0;
-    red[1][wave] = s1;
-    red[2][wave] = s2;
-    red[3][wave] = s3;
-    red[4][wave] = s4;
-    red[5][wave] = s5;
-  }
-  __syncthreads();
-  if (threadIdx.x < kStatFields) {
-    int64_t tot = 0;
-    for (int i = 0; i < kBlockThreads / kWave; ++i) tot += red[threadIdx.x][i];
-    if (tot)
-      atomicAdd(reinterpret_cast<unsigned long long *>(slots + (blockIdx.x % kStatSlots) * kStatFields + threadIdx.x),
-                (unsigned long long)tot);
-  }
+  static_assert(kStatFields == 6, "one lane per counter field");
+  const int32_t mine = lane == 0 ? s0 : lane == 1 ? s1 : lane == 2 ? s2 : lane == 3 ? s3 : lane == 4 ? s4 : s5;
+  const int64_t row = ((int64_t)blockIdx.x * (kBlockThreads / kWave) + wave) % kStatSlots;
+  if (lane < kStatFields && mine != 0)
+    atomicAdd(reinterpret_cast<unsigned long long *>(slots + row * kStatFields + lane), (unsigned long long)(int64_t)mine);
 }
 
 // ------------------------------------------------------------------ kernels: one pass
@@ -765,9 +810,14 @@ __device__ __forceinline__ void add_block_counters(const Counters &c, int64_t *s
 // successor counters of arcs that stay inside the range (most arcs of a graph whose ids
 // follow its locality, such as the hosts of a web graph), are then read from LDS. In other
 // passes `lds` holds the list of active nodes.
+// In a pass over every successor, 2^split_log2 wavefronts share the tile: wavefront `part`
+// takes rounds part, part + 2^split_log2, ... (the tile's degree order keeps their work
+// even), so the tile's ids are worked on for a shorter time and rows gathered by several of
+// its nodes are more often still in L2. Other passes give the whole tile to part 0.
 template <class F, int G, int U, bool ST>
-__device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int lane, int32_t *qw,
-                                             uint8_t *lds, int32_t *rps, Counters &cnt) {
+__device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int32_t part,
+                                             int32_t split_log2, int lane, int32_t *qw, uint8_t *lds, int32_t *rps,
+                                             int32_t *ent, Counters &cnt) {
   constexpr int W = kWave / G;
   const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
   const int32_t lo = tile * a.tile_nodes;
@@ -776,6 +826,7 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   int32_t count = a.tile_nodes;
   bool staged = false;  // `lds` holds the tile's rows (never a null pointer: its address space stays known)
   if (!f.gather_all) {
+    if (part != 0) return;
     count = find_active<U>(a, f, tl, tile, a.light_max, lane, rps, act, cnt);
   } else if constexpr (ST) {
     if (a.stage) {
@@ -803,21 +854,37 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   }
   // arcs read here are counted unless find_active already scanned them
   const bool count_scan = f.gather_all || f.systolic;
-  for (int32_t r = 0; r < count; r += W) {
-    // the node list is the tile's (device memory) or the active nodes (LDS); staged kernels
-    // read it with two one-sided loads, so that neither becomes a flat load through a
-    // selected pointer
-    const bool in = r + slot < count;
-    int32_t v = -1;
-    if constexpr (ST) {
-      if (in && f.gather_all) v = tl[r + slot];
-      if (in && !f.gather_all) v = act[r + slot];
-    } else {  // (a selected pointer here costs one flat load per round but one VGPR less)
-      const int32_t *list = f.gather_all ? tl : act;
-      v = in ? list[r + slot] : -1;
+  const int32_t r0 = f.gather_all ? part * W : 0;
+  const int32_t r_step = f.gather_all ? W << split_log2 : W;
+  // The node ids of 64 entries of the list at a time, and their arc ranges, one entry per
+  // lane, are loaded together (one coalesced load each) and handed to the rounds through
+  // `ent` (3 x 64 ints of LDS per wavefront): a round then waits for no device load before it
+  // reads its successor ids. The list is
+  // the tile's (device memory) or the active nodes (LDS), read with two one-sided loads so
+  // that neither becomes a flat load through a selected pointer.
+  int32_t held = -1;
+  for (int32_t r = r0; r < count; r += r_step) {
+    const int32_t c64 = r & ~(kWave - 1);
+    if (c64 != held) {  // (wavefront-uniform)
+      held = c64;
+      const bool in = c64 + lane < count;
+      int32_t hv = -1;
+      if (in && f.gather_all) hv = tl[c64 + lane];
+      if (in && !f.gather_all) hv = act[c64 + lane];
+      const int32_t hb = hv >= 0 ? a.row_ptr[hv] : 0;
+      const int32_t he = hv >= 0 ? a.row_ptr[hv + 1] : 0;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      ent[lane] = hv;
+      ent[kWave + lane] = hb;
+      ent[2 * kWave + lane] = he;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
+    const int src = (r & (kWave - 1)) + slot;  // (r is a multiple of W, and W divides 64)
+    const int32_t v = ent[src], beg = ent[kWave + src], end = ent[2 * kWave + src];
     if (!__any(v >= 0)) break;  // empty tile entries sort last
-    light_round<F, G, U, ST>(a, f, v, lane, qw, cnt, count_scan, lds, staged, lo);
+    light_round<F, G, U, ST>(a, f, v, beg, end, lane, qw, cnt, count_scan, lds, staged, lo);
   }
 }
 
@@ -831,7 +898,8 @@ __device__ __forceinline__ bool wide_systolic(const PassArgs &a, const DevState 
 }
 
 // The union step of one pass (Algorithm 2), one work unit per wavefront: workgroups below
-// n_chunk_wgs take 4 chunks each, the others 4 light tiles (XCD-aware order). With
+// n_chunk_wgs take 4 chunks each, the others 4 light-tile units (XCD-aware order; a tile is
+// 2^tile_split_log2 consecutive units). With
 // `list_too` set, k_union_list runs the systolic passes that signal few arcs and this
 // kernel leaves them at once.
 template <class F, int G, int U, bool ST>
@@ -843,20 +911,76 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
   __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  __shared__ int32_t ent_buf[(kBlockThreads / kWave) * 3 * kWave];
   extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (scalar: per-wavefront LDS bases in SGPRs)
   int32_t *qw = queue + wave * kWave * U;
   if ((int32_t)blockIdx.x < a.n_chunk_wgs) {
     const int32_t c = (int32_t)blockIdx.x * 4 + wave;
     if (c < a.n_chunks) chunk_wave<F, G, U, ST>(a, f, c, lane, qw, cnt);
   } else {
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
-    const int32_t tile = L * 4 + wave;
+    const int32_t unit = L * 4 + wave;  // 2^tile_split_log2 consecutive units per tile
+    const int32_t tile = unit >> a.tile_split_log2;
     if (tile < a.n_tiles)
-      process_tile<F, G, U, ST>(a, f, tile, lane, qw, reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
-                            rp_buf + wave * (kWave + 1), cnt);
+      process_tile<F, G, U, ST>(a, f, tile, unit & ((1 << a.tile_split_log2) - 1), a.tile_split_log2, lane, qw,
+                                reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
+                                rp_buf + wave * (kWave + 1), ent_buf + wave * 3 * kWave, cnt);
   }
-  add_block_counters(cnt, a.stat_slots);
+  add_wave_counters(cnt, a.stat_slots);
+}
+
+// First element of part x of 0..n-1 cut into kXcds near-equal consecutive parts.
+__device__ __forceinline__ int32_t xcd_part(int32_t n, int x) {
+  return x * (n / kXcds) + min(x, n % kXcds);
+}
+
+// The union step as a sweep (the passes k_union takes, from a grid of a.sweep_wgs
+// workgroups): the work units are cut into kXcds consecutive parts, one per XCD (workgroup b
+// runs on XCD b % kXcds), each part its chunks and then its light-tile units in id order,
+// and every wavefront claims its XCD's next unit from that part's counter until none is
+// left; it then helps the other parts. Units are claimed in order, so each XCD works on a
+// narrow, moving range of ids (its L2 holds the rows near that range), and a wavefront runs
+// many units, so its start and end costs are paid once per pass instead of once per unit.
+template <class F, int G, int U, bool ST>
+__global__ __launch_bounds__(kBlockThreads) void k_union_sweep(PassArgs a, int32_t list_too) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st);
+  if (list_too && f.systolic && !wide_systolic(a, st)) return;
+  Counters cnt;
+  __shared__ int32_t queue[kBlockThreads * U];
+  __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  __shared__ int32_t ent_buf[(kBlockThreads / kWave) * 3 * kWave];
+  extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (scalar: per-wavefront LDS bases in SGPRs)
+  int32_t *qw = queue + wave * kWave * U;
+  uint8_t *lds = reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes;
+  int32_t *rps = rp_buf + wave * (kWave + 1);
+  const int32_t split = f.gather_all ? a.tile_split_log2 : 0;
+  const int home = (int)(blockIdx.x % kXcds);
+  for (int i = 0; i < kXcds; ++i) {
+    const int x = (home + i) % kXcds;
+    const int32_t c0 = xcd_part(a.n_chunks, x), nc = xcd_part(a.n_chunks, x + 1) - c0;
+    const int32_t t0 = xcd_part(a.n_tiles, x), nt = xcd_part(a.n_tiles, x + 1) - t0;
+    const int64_t units = (int64_t)nc + ((int64_t)nt << split);
+    for (;;) {
+      int32_t k = 0;
+      if (lane == 0) k = atomicAdd(a.sweep_ctr + x * kSweepStride, 1);
+      k = __shfl(k, 0);
+      if ((int64_t)k >= units) break;
+      if (k < nc) {
+        chunk_wave<F, G, U, ST>(a, f, c0 + k, lane, qw, cnt);
+      } else {
+        const int32_t u = k - nc;
+        process_tile<F, G, U, ST>(a, f, t0 + (u >> split), u & ((1 << split) - 1), split, lane, qw, lds, rps,
+                                  ent_buf + wave * 3 * kWave, cnt);
+      }
+    }
+  }
+  add_wave_counters(cnt, a.stat_slots);
 }
 
 // The union step from a persistent grid (kListWgs workgroups): in a systolic pass over the
@@ -873,8 +997,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
   Counters cnt;
   __shared__ int32_t queue[kBlockThreads * U];
   __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
+  __shared__ int32_t ent_buf[(kBlockThreads / kWave) * 3 * kWave];
   extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (scalar: per-wavefront LDS bases in SGPRs)
   int32_t *qw = queue + wave * kWave * U;
   const int64_t total = f.systolic ? (int64_t)st->sys_units : (int64_t)a.n_chunks + a.n_tiles;
   const int64_t stride = (int64_t)gridDim.x * (kBlockThreads / kWave);
@@ -883,11 +1009,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
     if (u < a.n_chunks)
       chunk_wave<F, G, U, ST>(a, f, u, lane, qw, cnt);
     else
-      process_tile<F, G, U, ST>(a, f, u - a.n_chunks, lane, qw,
-                            reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
-                            rp_buf + wave * (kWave + 1), cnt);
+      process_tile<F, G, U, ST>(a, f, u - a.n_chunks, 0, 0, lane, qw,
+                                reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
+                                rp_buf + wave * (kWave + 1), ent_buf + wave * 3 * kWave, cnt);
   }
-  add_block_counters(cnt, a.stat_slots);
+  add_wave_counters(cnt, a.stat_slots);
 }
 
 // Combines the partial maxima of nodes split over several chunks (one wavefront per node).
@@ -928,7 +1054,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
     combine_slots<F, G>(acc, any);
     finalize_slot<F, G>(a, f, slot == 0 ? hv.v : -1, lane, acc, any, false, F::zero(), cnt);
   }
-  add_block_counters(cnt, a.stat_slots);
+  add_wave_counters(cnt, a.stat_slots);
 }
 
 // Estimates of the counters this pass changed, for formats whose union step leaves them out.
@@ -1235,6 +1361,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
     }
     sl[0] = sl[1] = sl[2] = sl[3] = sl[4] = sl[5] = 0;
   }
+  if (tid < kXcds && a.sweep_ctr) a.sweep_ctr[tid * kSweepStride] = 0;  // the sweep's claim counters
   s_sum[tid] = s;
   s_i[0][tid] = c;
   s_i[1][tid] = sc;
@@ -2478,14 +2605,35 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
     }                                                           \
   }
 
-hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, int sweep, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
   const int G = row_lanes(a);
   const dim3 block(kBlockThreads);
   const size_t lds = (size_t)a.lds_wave_bytes * (kBlockThreads / kWave);
   if (a.n_chunk_wgs + a.n_light_wgs == 0 || (!full && !list)) return record_empty(e0, e1, s);
   const bool st = a.stage || a.count_near;  // the instantiation that stages and counts near successors
   if (st && (a.packed || u != 4)) return hipErrorInvalidValue;
-  if (full) {
+  if (full && sweep) {
+    if (a.sweep_wgs <= 0 || a.sweep_wgs % kXcds != 0 || !a.sweep_ctr) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)a.sweep_wgs);
+    const int32_t list_too = list ? 1 : 0;
+    hipEvent_t end = list ? nullptr : e1;
+    if (st) {
+      HANF_DISPATCH_STAGED(G, launch_k_lds(k_union_sweep<F, G, 4, true>, grid, block, lds, s, e0, end, a, list_too));
+    } else {
+      switch (u) {
+        case 2:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 2, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+        case 8:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 8, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+        default:
+          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 4, false>, grid, block, lds, s, e0, end, a, list_too));
+          break;
+      }
+    }
+  } else if (full) {
     const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
     const int32_t list_too = list ? 1 : 0;
     hipEvent_t end = list ? nullptr : e1;
