@@ -147,7 +147,8 @@ extern "C" {
  *        2048, 4096 (default), 8192 or 16384;
  *   104  1: run the instrumented union kernels, which count arcs_near in the pass records
  *        (byte registers, rows of at most 256 bytes, 4 loads in flight; elsewhere -1);
- *   100  loads in flight per lane in the gather loops: 2, 4 (default) or 8;
+ *   100  loads in flight per lane in the gather loops: 2, 4 or 8; 0 (default): 8 for one
+ *        register per byte, 4 for 5-bit registers and for staged or instrumented kernels;
  *   101  the persistent union kernel over listed work units: 0 (default) for systolic
  *        passes, 1 never, 2 for every pass;
  *   102  hanf_build_transpose: 0 (default) the bucket sort up to 2^26 nodes and per-node

@@ -83,6 +83,7 @@ struct Schedule {
   int32_t stage_tile = 0;  // nodes per light tile when staging (0: the format cannot stage)
   int stage_opt = 0;       // HANF_OPT_STAGE the schedule was built with
   int32_t split_opt_log2 = 0;  // HANF_OPT_TILE_SPLIT (or its default) as log2
+  int unroll = 4;              // loads in flight per lane in the union kernels
   int stage = 0;           // light tiles stage their rows in LDS (passes over every successor)
   int32_t lds_wave_bytes = 0;
   int32_t n_tiles = 0, n_chunks = 0, n_heavy = 0;
@@ -118,7 +119,7 @@ struct hanf_ctx {
   int timing = 0;
   int dense_div = 4;  // a pass after one that changed >= n/dense_div counters maximises with all successors
   int passes_per_check = 4;
-  int unroll = 4;
+  int unroll = 0;  // loads in flight per lane in the gather loops (option 100); 0: automatic
   int sys_div = 4;    // a pass after one that changed < n/sys_div counters is systolic (0 = never)
   int union_policy = 0;  // 0: persistent union kernel for systolic passes, 1: never, 2: always
   int packed_opt = 2;    // HANF_OPT_PACKED5: 0 bytes, 1 5-bit registers, 2 chosen by row width
@@ -486,7 +487,11 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   // chunk
   const int row_regs = G * (lane_bytes == kPacked5LaneBytes ? 64 : 16);
   s.light_max = c->light_max_opt > 0 ? c->light_max_opt : std::max(32, std::min(128, row_regs));
-  s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, std::min(2048, W * c->unroll * 16));
+  // loads in flight per lane: 8 for byte registers (at 80 VGPRs or fewer, so 6 wavefronts per
+  // SIMD still fit), 4 for 5-bit ones (ten VGPRs a counter) and for the staged and
+  // instrumented kernels, which exist for 4 only
+  s.unroll = c->unroll > 0 ? c->unroll : (lane_bytes != 16 || c->stage_opt == 1 || c->count_near) ? 4 : 8;
+  s.chunk_arcs = c->chunk_opt > 0 ? c->chunk_opt : std::max(256, std::min(2048, W * s.unroll * 16));
   int32_t tile = c->tile_opt;
   if (tile <= 0) {
     // about 8 rounds of W nodes per wavefront on large graphs (measured best on MI355X for
@@ -500,7 +505,7 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   // staged tiles: as many rows as kStageWaveBytes of LDS hold, at least one round of W
   const int32_t row_bytes = G * lane_bytes;
   const int32_t st = std::min(kMaxTile, (c->stage_bytes / row_bytes) / W * W);
-  s.stage_tile = (lane_bytes == 16 && G <= 16 && c->unroll == 4 && st >= W) ? st : 0;
+  s.stage_tile = (lane_bytes == 16 && G <= 16 && s.unroll == 4 && st >= W) ? st : 0;
   s.stage_opt = c->stage_opt;
   int split = c->split_opt > 0 ? c->split_opt : 1;
   split = std::min(split, tile / W);  // at most one round per wavefront
@@ -1148,7 +1153,7 @@ int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   const bool has_sys = has_signals(c);
   const int list = c->union_policy == 2 || (c->union_policy == 0 && has_sys);
   const int full = c->union_policy == 1 || (c->union_policy == 0 && !(has_sys && c->sys_seen));
-  HIP_TRY(c, launch_union(c->args, c->unroll, full, list, c->sweep, s, e[2], e[3]), "union kernel");
+  HIP_TRY(c, launch_union(c->args, c->sch.unroll, full, list, c->sweep, s, e[2], e[3]), "union kernel");
   const bool est = c->args.packed != 0;  // packed rows: estimates in a kernel of their own
   HIP_TRY(c, launch_finalize(c->args, s, e[4], est ? nullptr : e[5]), "finalize kernel");
   HIP_TRY(c, launch_estimate_changed(c->args, s, nullptr, est ? e[5] : nullptr), "estimate kernel");
@@ -1315,8 +1320,8 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "sweep must be 0 or 1");
       c->sweep = (int)value;
       break;
-    case 100:  // unroll of the gather loops (2, 4 or 8); used by the tuner
-      if (value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 2, 4 or 8");
+    case 100:  // unroll of the gather loops (0 automatic, 2, 4 or 8); used by the tuner
+      if (value != 0 && value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 0, 2, 4 or 8");
       c->unroll = (int)value;
       break;
     default:
@@ -1558,7 +1563,7 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
       want.chunk_arcs != c->sch.chunk_arcs || want.tile_base != c->sch.tile_base ||
       want.stage_opt != c->sch.stage_opt || want.stage_tile != c->sch.stage_tile ||
-      want.split_opt_log2 != c->sch.split_opt_log2) {
+      want.split_opt_log2 != c->sch.split_opt_log2 || want.unroll != c->sch.unroll) {
     if ((rc = build_schedule(c, G, lane_bytes))) return rc;
   }
   size_t n_cchunks_before = c->cchunk_comp_h.size();

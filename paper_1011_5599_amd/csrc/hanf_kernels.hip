@@ -58,23 +58,20 @@ __device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
                                                                 __builtin_bit_cast(u16x2, b)));
 }
 
-// Was any counter of node v's row modified? (S = 2^sl flag bits per node, never across words.)
-__device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl) {
-  const uint64_t i = (uint64_t)v << sl;
-  const uint32_t field = sl == 5 ? 0xffffffffu : ((1u << (1u << sl)) - 1u);
-  return ((bits[i >> 5] >> (i & 31)) & field) != 0u;
-}
-
-// The flag word holding node v's modified bits, and the test of those bits in it. Loops load
-// the words of all their nodes first (v clamped to a valid id where there is none), so the
-// loads are in flight together instead of one round trip after another.
+// Modified flags: S = 2^sl bits per node (sl <= 5, at most 32 counters per row), so a
+// node's bits never cross a 32-bit word: word v >> (5 - sl), from bit (v << sl) mod 32.
+// Loops load the words of all their nodes first (v clamped to a valid id where there is
+// none), so the loads are in flight together instead of one round trip after another.
 __device__ __forceinline__ uint32_t mod_word(const uint32_t *bits, int32_t v, int sl) {
-  return bits[((uint64_t)v << sl) >> 5];
+  return bits[(uint32_t)v >> (5 - sl)];
 }
 __device__ __forceinline__ bool mod_in_word(uint32_t word, int32_t v, int sl) {
-  const uint64_t i = (uint64_t)v << sl;
   const uint32_t field = sl == 5 ? 0xffffffffu : ((1u << (1u << sl)) - 1u);
-  return ((word >> (i & 31)) & field) != 0u;
+  return ((word >> (((uint32_t)v << sl) & 31u)) & field) != 0u;
+}
+// Was any counter of node v's row modified?
+__device__ __forceinline__ bool node_mod(const uint32_t *bits, int32_t v, int sl) {
+  return mod_in_word(mod_word(bits, v, sl), v, sl);
 }
 
 __device__ __forceinline__ uint4 shfl_xor4(uint4 a, int off) {
@@ -437,8 +434,7 @@ __device__ __forceinline__ void finalize_slot(const PassArgs &a, const Flags &f,
       uint32_t mask = 0u;
       for (int k = 0; k < (G / gs); ++k)
         if ((rowbits >> (k * gs)) & smask) mask |= 1u << k;
-      const uint64_t bit = (uint64_t)v << f.sl;
-      atomicOr(&f.cur_bits[bit >> 5], mask << (bit & 31));
+      atomicOr(&f.cur_bits[(uint32_t)v >> (5 - f.sl)], mask << (((uint32_t)v << f.sl) & 31u));
     }
   }
 }

@@ -20,12 +20,13 @@ SPACE = {
     "light_max": [16, 32, 64, 128],
     "chunk_arcs": [256, 512, 1024, 2048],
     "tile_nodes": [0, 64, 128, 256],
-    "unroll": [2, 4, 8],
+    "unroll": [0, 2, 4, 8],
     "dense_switch": [0, 2, 4, 8],
 }
 
-DEFAULTS = {"light_max": 0, "chunk_arcs": 0, "tile_nodes": 0, "unroll": 4, "dense_switch": 4}
-# 0: the library default for the run's row width (light_max and chunk_arcs grow with it)
+DEFAULTS = {"light_max": 0, "chunk_arcs": 0, "tile_nodes": 0, "unroll": 0, "dense_switch": 4}
+# 0: the library default for the run's row width (light_max and chunk_arcs grow with it) and
+# register format (unroll)
 # batched runs also tune `seeds_per_row` (0 = as many seeds per node row as fit) and `group`
 
 
