@@ -132,16 +132,6 @@ extern "C" {
                                    wavefronts per CU); it is kept as an option. Results do not
                                    change */
 
-#define HANF_OPT_TILE_SPLIT 15  /* wavefronts that share one light tile (consecutive ids, nodes
-                                   sorted by degree) in passes over every successor, taking its
-                                   rounds of nodes in turn: 1, 2, 4 or 8 (at most one round of
-                                   nodes each; 0 = default). Sharing shortens the time in which a
-                                   tile's ids are being worked on, so that successors near a
-                                   node (the rows of its own host in a web graph) are gathered
-                                   by their other predecessors while they are still in L2.
-                                   Frontier and systolic passes keep one wavefront per tile; so
-                                   do staged tiles (HANF_OPT_STAGE). Results do not change */
-
 /* Tuning and test options (the results never change):
  *   103  LDS bytes per wavefront for the counters of a staged light tile (HANF_OPT_STAGE):
  *        2048, 4096 (default), 8192 or 16384;

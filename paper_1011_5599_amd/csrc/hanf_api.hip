@@ -79,10 +79,8 @@ struct Schedule {
   int lane_bytes = 0; // bytes per lane of the register format (partial rows)
   int32_t light_max = 0, chunk_arcs = 0, tile_nodes = 0;
   int32_t tile_base = 0;   // nodes per light tile without staging (option or default)
-  int32_t split_log2 = 0;  // log2 of the wavefronts per light tile in passes over every successor
   int32_t stage_tile = 0;  // nodes per light tile when staging (0: the format cannot stage)
   int stage_opt = 0;       // HANF_OPT_STAGE the schedule was built with
-  int32_t split_opt_log2 = 0;  // HANF_OPT_TILE_SPLIT (or its default) as log2
   int unroll = 4;              // loads in flight per lane in the union kernels
   int stage = 0;           // light tiles stage their rows in LDS (passes over every successor)
   int32_t lds_wave_bytes = 0;
@@ -96,7 +94,6 @@ struct Schedule {
   uint8_t *tile_todo = nullptr;   // systolic flags of the light tiles
   int32_t *unit_list = nullptr;   // systolic work units
   int64_t *stat_slots = nullptr;  // kStatSlots x 4 work counters
-  int32_t *sweep_ctr = nullptr;   // kXcds claim counters of k_union_sweep
 };
 
 }  // namespace
@@ -115,7 +112,6 @@ struct hanf_ctx {
   int frontier = 1;
   int64_t max_passes_opt = 0;
   int32_t light_max_opt = 0, chunk_opt = 0, tile_opt = 0;
-  int split_opt = 0;  // HANF_OPT_TILE_SPLIT: 0 default, else 1, 2, 4 or 8
   int timing = 0;
   int dense_div = 4;  // a pass after one that changed >= n/dense_div counters maximises with all successors
   int passes_per_check = 4;
@@ -128,8 +124,6 @@ struct hanf_ctx {
   int stage_opt = 0;     // HANF_OPT_STAGE: 0 never, 1 whenever the format allows
   int32_t stage_bytes = kStageWaveBytes;  // LDS per wavefront for a staged tile's counters
   int count_near = 0;    // 1: instrumented union kernels count near successors (option 104)
-  int sweep = 0;         // 1: k_union_sweep takes the passes k_union would (option 105)
-  int n_cus = 256;       // compute units of the device
   int forward = 0;       // HANF_OPT_FORWARD: systolic passes without a transposed graph
   bool sys_seen = false; // the last state read showed a systolic next pass
   bool first_enqueued = false;  // the first pass of the run (always over every successor) is queued
@@ -303,7 +297,6 @@ void free_schedule(hanf_ctx *c) {
   dev_release(c, s.tile_todo);
   dev_release(c, s.unit_list);
   dev_release(c, s.stat_slots);
-  dev_release(c, s.sweep_ctr);
   s = Schedule();
 }
 
@@ -434,8 +427,6 @@ int current_state(hanf_ctx *c) { return c->st_fresh ? HANF_OK : read_state(c); }
 
 // N_hat values kept on the host with the state (a prefix of the history).
 constexpr int32_t kNtHostCache = 1024;
-constexpr int kSweepWgsPerCu = 8;  // k_union_sweep workgroups per compute unit (more than fit: late
-                                   // workgroups find the counters spent and leave)
 
 // The state k_state_reset writes (the host copy is current once it ran, as long as nothing
 // queued after it changes the state).
@@ -507,10 +498,6 @@ void choose_schedule(hanf_ctx *c, int G, int lane_bytes, Schedule &s) {
   const int32_t st = std::min(kMaxTile, (c->stage_bytes / row_bytes) / W * W);
   s.stage_tile = (lane_bytes == 16 && G <= 16 && s.unroll == 4 && st >= W) ? st : 0;
   s.stage_opt = c->stage_opt;
-  int split = c->split_opt > 0 ? c->split_opt : 1;
-  split = std::min(split, tile / W);  // at most one round per wavefront
-  s.split_opt_log2 = 0;
-  while ((2 << s.split_opt_log2) <= split) ++s.split_opt_log2;
 }
 
 int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
@@ -568,18 +555,12 @@ int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
   if (e != hipSuccess) return hip_fail(c, e, "fill chunks");
   s.n_chunk_wgs = (s.n_chunks + 3) / 4;
   s.n_chunk_wgs = ((s.n_chunk_wgs + kXcds - 1) / kXcds) * kXcds;  // light workgroups start on XCD 0
-  // a staged tile is copied to LDS by its one wavefront, so staging never splits tiles
-  s.split_log2 = s.stage ? 0 : s.split_opt_log2;
-  s.n_light_wgs = (int32_t)((((int64_t)s.n_tiles << s.split_log2) + 3) / 4);
+  s.n_light_wgs = (s.n_tiles + 3) / 4;
   s.n_fin_wgs = (s.n_heavy + 3) / 4;
   if ((rc = dev_alloc(c, &s.stat_slots, (size_t)kStatSlots * kStatFields, "work counters")) ||
       (rc = dev_alloc(c, &s.tile_todo, ((size_t)s.n_tiles + 3) / 4 * 4, "tile flags")) ||
-      (rc = dev_alloc(c, &s.unit_list, (size_t)s.n_chunks + s.n_tiles, "work unit list")) ||
-      (rc = dev_alloc(c, &s.sweep_ctr, (size_t)kXcds * kSweepStride, "sweep counters")))
+      (rc = dev_alloc(c, &s.unit_list, (size_t)s.n_chunks + s.n_tiles, "work unit list")))
     return rc;
-  // zero before the first pass (k_reduce_top clears them after every union step)
-  e = hipMemsetAsync(s.sweep_ctr, 0, sizeof(int32_t) * kXcds * kSweepStride, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "sweep counters");
   return HANF_OK;
 }
 
@@ -627,9 +608,6 @@ void fill_args(hanf_ctx *c) {
   a.n_light_wgs = c->sch.n_light_wgs;
   a.n_tiles = c->sch.n_tiles;
   a.tile_nodes = c->sch.tile_nodes;
-  a.tile_split_log2 = c->sch.split_log2;
-  a.sweep_ctr = c->sch.sweep_ctr;
-  a.sweep_wgs = (kSweepWgsPerCu * c->n_cus + kXcds - 1) / kXcds * kXcds;
   a.light_max = c->sch.light_max;
   a.stage = c->sch.stage;
   // the instrumented kernels exist where staging could run (byte rows up to 256 bytes, 4 loads
@@ -1153,7 +1131,7 @@ int enqueue_pass(hanf_ctx *c, hipEvent_t *ev) {
   const bool has_sys = has_signals(c);
   const int list = c->union_policy == 2 || (c->union_policy == 0 && has_sys);
   const int full = c->union_policy == 1 || (c->union_policy == 0 && !(has_sys && c->sys_seen));
-  HIP_TRY(c, launch_union(c->args, c->sch.unroll, full, list, c->sweep, s, e[2], e[3]), "union kernel");
+  HIP_TRY(c, launch_union(c->args, c->sch.unroll, full, list, s, e[2], e[3]), "union kernel");
   const bool est = c->args.packed != 0;  // packed rows: estimates in a kernel of their own
   HIP_TRY(c, launch_finalize(c->args, s, e[4], est ? nullptr : e[5]), "finalize kernel");
   HIP_TRY(c, launch_estimate_changed(c->args, s, nullptr, est ? e[5] : nullptr), "estimate kernel");
@@ -1184,9 +1162,6 @@ int hanf_create(int device, void *hip_stream, hanf_ctx **out) {
   e = hipSetDevice(device);
   if (e == hipSuccess) {
     scratch_setup(device);
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
-      c->n_cus = cus;
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {
@@ -1290,11 +1265,6 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "forward must be 0 or 1");
       c->forward = (int)value;
       break;
-    case HANF_OPT_TILE_SPLIT:
-      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
-        return fail(c, HANF_EINVAL, "tile split must be 0, 1, 2, 4 or 8");
-      c->split_opt = (int)value;
-      break;
     case HANF_OPT_STAGE:
       if (value < 0 || value > 1) return fail(c, HANF_EINVAL, "stage must be 0 or 1");
       c->stage_opt = (int)value;
@@ -1315,10 +1285,6 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
       if (value != 2048 && value != 4096 && value != 8192 && value != 16384)
         return fail(c, HANF_EINVAL, "stage bytes must be 2048, 4096, 8192 or 16384");
       c->stage_bytes = (int32_t)value;
-      break;
-    case 105:  // 1: the union step as a sweep with per-XCD work counters (k_union_sweep)
-      if (value != 0 && value != 1) return fail(c, HANF_EINVAL, "sweep must be 0 or 1");
-      c->sweep = (int)value;
       break;
     case 100:  // unroll of the gather loops (0 automatic, 2, 4 or 8); used by the tuner
       if (value != 0 && value != 2 && value != 4 && value != 8) return fail(c, HANF_EINVAL, "unroll must be 0, 2, 4 or 8");
@@ -1563,7 +1529,7 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
   if (c->sch.G != G || c->sch.lane_bytes != lane_bytes || !c->sch.light || want.light_max != c->sch.light_max ||
       want.chunk_arcs != c->sch.chunk_arcs || want.tile_base != c->sch.tile_base ||
       want.stage_opt != c->sch.stage_opt || want.stage_tile != c->sch.stage_tile ||
-      want.split_opt_log2 != c->sch.split_opt_log2 || want.unroll != c->sch.unroll) {
+      want.unroll != c->sch.unroll) {
     if ((rc = build_schedule(c, G, lane_bytes))) return rc;
   }
   size_t n_cchunks_before = c->cchunk_comp_h.size();

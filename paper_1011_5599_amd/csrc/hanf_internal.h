@@ -12,7 +12,6 @@ constexpr int kBlockThreads = 256; // 4 wavefronts per workgroup
 constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 consecutive nodes
 constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
-constexpr int kSweepStride = 64;   // int32 stride of the per-XCD claim counters (own 256 B each)
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 constexpr int kStatFields = 6;     // work counters per row: scanned, gathered, written, read, local, near
@@ -197,11 +196,6 @@ struct PassArgs {
   int32_t n_light_wgs;
   int32_t n_tiles;
   int32_t tile_nodes;
-  int32_t *sweep_ctr;        // k_union_sweep: per-XCD count of claimed work units (kXcds
-                             //   counters kSweepStride apart; k_reduce_top clears them)
-  int32_t sweep_wgs;         // k_union_sweep grid (a multiple of kXcds)
-  int32_t tile_split_log2;   // in passes over every successor, 2^this wavefronts share a light
-                             //   tile, taking its rounds in turn (one wavefront in other passes)
   int32_t light_max;         // nodes with more arcs are handled by chunks
   int32_t stage;             // 1: in passes over every successor, a light tile's wavefront first
                              //   copies the rows of c_t of the tile's id range into LDS, and
@@ -243,7 +237,7 @@ hipError_t launch_signal(const PassArgs &a, int64_t arcs, hipStream_t s, hipEven
                          hipEvent_t e1 = nullptr);
 // full: the kernel with one wavefront per work unit; list: the persistent kernel, which
 // runs the systolic passes when both are launched and every pass when it runs alone
-hipError_t launch_union(const PassArgs &a, int u, int full, int list, int sweep, hipStream_t s, hipEvent_t e0 = nullptr,
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 // transposed graph: in-degree counts into keys (n + 1 zeroed uint64), then, after their
 // exclusive scan, the predecessor lists (keys are consumed as fill cursors)

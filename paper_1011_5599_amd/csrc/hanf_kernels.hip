@@ -806,14 +806,9 @@ __device__ __forceinline__ void add_wave_counters(const Counters &c, int64_t *sl
 // successor counters of arcs that stay inside the range (most arcs of a graph whose ids
 // follow its locality, such as the hosts of a web graph), are then read from LDS. In other
 // passes `lds` holds the list of active nodes.
-// In a pass over every successor, 2^split_log2 wavefronts share the tile: wavefront `part`
-// takes rounds part, part + 2^split_log2, ... (the tile's degree order keeps their work
-// even), so the tile's ids are worked on for a shorter time and rows gathered by several of
-// its nodes are more often still in L2. Other passes give the whole tile to part 0.
 template <class F, int G, int U, bool ST>
-__device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int32_t part,
-                                             int32_t split_log2, int lane, int32_t *qw, uint8_t *lds, int32_t *rps,
-                                             int32_t *ent, Counters &cnt) {
+__device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, int32_t tile, int lane, int32_t *qw,
+                                             uint8_t *lds, int32_t *rps, int32_t *ent, Counters &cnt) {
   constexpr int W = kWave / G;
   const int32_t *tl = a.light + (size_t)tile * a.tile_nodes;
   const int32_t lo = tile * a.tile_nodes;
@@ -822,7 +817,6 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   int32_t count = a.tile_nodes;
   bool staged = false;  // `lds` holds the tile's rows (never a null pointer: its address space stays known)
   if (!f.gather_all) {
-    if (part != 0) return;
     count = find_active<U>(a, f, tl, tile, a.light_max, lane, rps, act, cnt);
   } else if constexpr (ST) {
     if (a.stage) {
@@ -850,8 +844,6 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   }
   // arcs read here are counted unless find_active already scanned them
   const bool count_scan = f.gather_all || f.systolic;
-  const int32_t r0 = f.gather_all ? part * W : 0;
-  const int32_t r_step = f.gather_all ? W << split_log2 : W;
   // The node ids of 64 entries of the list at a time, and their arc ranges, one entry per
   // lane, are loaded together (one coalesced load each) and handed to the rounds through
   // `ent` (3 x 64 ints of LDS per wavefront): a round then waits for no device load before it
@@ -859,7 +851,7 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
   // the tile's (device memory) or the active nodes (LDS), read with two one-sided loads so
   // that neither becomes a flat load through a selected pointer.
   int32_t held = -1;
-  for (int32_t r = r0; r < count; r += r_step) {
+  for (int32_t r = 0; r < count; r += W) {
     const int32_t c64 = r & ~(kWave - 1);
     if (c64 != held) {  // (wavefront-uniform)
       held = c64;
@@ -894,8 +886,7 @@ __device__ __forceinline__ bool wide_systolic(const PassArgs &a, const DevState 
 }
 
 // The union step of one pass (Algorithm 2), one work unit per wavefront: workgroups below
-// n_chunk_wgs take 4 chunks each, the others 4 light-tile units (XCD-aware order; a tile is
-// 2^tile_split_log2 consecutive units). With
+// n_chunk_wgs take 4 chunks each, the others 4 light tiles (XCD-aware order). With
 // `list_too` set, k_union_list runs the systolic passes that signal few arcs and this
 // kernel leaves them at once.
 template <class F, int G, int U, bool ST>
@@ -917,64 +908,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_union(PassArgs a, int32_t lis
     if (c < a.n_chunks) chunk_wave<F, G, U, ST>(a, f, c, lane, qw, cnt);
   } else {
     const int32_t L = xcd_remap((int32_t)blockIdx.x - a.n_chunk_wgs, a.n_light_wgs);
-    const int32_t unit = L * 4 + wave;  // 2^tile_split_log2 consecutive units per tile
-    const int32_t tile = unit >> a.tile_split_log2;
+    const int32_t tile = L * 4 + wave;
     if (tile < a.n_tiles)
-      process_tile<F, G, U, ST>(a, f, tile, unit & ((1 << a.tile_split_log2) - 1), a.tile_split_log2, lane, qw,
-                                reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
+      process_tile<F, G, U, ST>(a, f, tile, lane, qw, reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
                                 rp_buf + wave * (kWave + 1), ent_buf + wave * 3 * kWave, cnt);
-  }
-  add_wave_counters(cnt, a.stat_slots);
-}
-
-// First element of part x of 0..n-1 cut into kXcds near-equal consecutive parts.
-__device__ __forceinline__ int32_t xcd_part(int32_t n, int x) {
-  return x * (n / kXcds) + min(x, n % kXcds);
-}
-
-// The union step as a sweep (the passes k_union takes, from a grid of a.sweep_wgs
-// workgroups): the work units are cut into kXcds consecutive parts, one per XCD (workgroup b
-// runs on XCD b % kXcds), each part its chunks and then its light-tile units in id order,
-// and every wavefront claims its XCD's next unit from that part's counter until none is
-// left; it then helps the other parts. Units are claimed in order, so each XCD works on a
-// narrow, moving range of ids (its L2 holds the rows near that range), and a wavefront runs
-// many units, so its start and end costs are paid once per pass instead of once per unit.
-template <class F, int G, int U, bool ST>
-__global__ __launch_bounds__(kBlockThreads) void k_union_sweep(PassArgs a, int32_t list_too) {
-  const DevState *st = a.st;
-  if (st->halted) return;
-  const Flags f = make_flags(a, st);
-  if (list_too && f.systolic && !wide_systolic(a, st)) return;
-  Counters cnt;
-  __shared__ int32_t queue[kBlockThreads * U];
-  __shared__ int32_t rp_buf[(kBlockThreads / kWave) * (kWave + 1)];
-  __shared__ int32_t ent_buf[(kBlockThreads / kWave) * 3 * kWave];
-  extern __shared__ uint4 wave_lds[];  // a.lds_wave_bytes per wavefront
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (scalar: per-wavefront LDS bases in SGPRs)
-  int32_t *qw = queue + wave * kWave * U;
-  uint8_t *lds = reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes;
-  int32_t *rps = rp_buf + wave * (kWave + 1);
-  const int32_t split = f.gather_all ? a.tile_split_log2 : 0;
-  const int home = (int)(blockIdx.x % kXcds);
-  for (int i = 0; i < kXcds; ++i) {
-    const int x = (home + i) % kXcds;
-    const int32_t c0 = xcd_part(a.n_chunks, x), nc = xcd_part(a.n_chunks, x + 1) - c0;
-    const int32_t t0 = xcd_part(a.n_tiles, x), nt = xcd_part(a.n_tiles, x + 1) - t0;
-    const int64_t units = (int64_t)nc + ((int64_t)nt << split);
-    for (;;) {
-      int32_t k = 0;
-      if (lane == 0) k = atomicAdd(a.sweep_ctr + x * kSweepStride, 1);
-      k = __shfl(k, 0);
-      if ((int64_t)k >= units) break;
-      if (k < nc) {
-        chunk_wave<F, G, U, ST>(a, f, c0 + k, lane, qw, cnt);
-      } else {
-        const int32_t u = k - nc;
-        process_tile<F, G, U, ST>(a, f, t0 + (u >> split), u & ((1 << split) - 1), split, lane, qw, lds, rps,
-                                  ent_buf + wave * 3 * kWave, cnt);
-      }
-    }
   }
   add_wave_counters(cnt, a.stat_slots);
 }
@@ -1005,7 +942,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_union_list(PassArgs a, int32_
     if (u < a.n_chunks)
       chunk_wave<F, G, U, ST>(a, f, u, lane, qw, cnt);
     else
-      process_tile<F, G, U, ST>(a, f, u - a.n_chunks, 0, 0, lane, qw,
+      process_tile<F, G, U, ST>(a, f, u - a.n_chunks, lane, qw,
                                 reinterpret_cast<uint8_t *>(wave_lds) + wave * a.lds_wave_bytes,
                                 rp_buf + wave * (kWave + 1), ent_buf + wave * 3 * kWave, cnt);
   }
@@ -1357,7 +1294,6 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
     }
     sl[0] = sl[1] = sl[2] = sl[3] = sl[4] = sl[5] = 0;
   }
-  if (tid < kXcds && a.sweep_ctr) a.sweep_ctr[tid * kSweepStride] = 0;  // the sweep's claim counters
   s_sum[tid] = s;
   s_i[0][tid] = c;
   s_i[1][tid] = sc;
@@ -2601,35 +2537,14 @@ hipError_t launch_transpose_fill(const int32_t *row_ptr, const int32_t *col_idx,
     }                                                           \
   }
 
-hipError_t launch_union(const PassArgs &a, int u, int full, int list, int sweep, hipStream_t s, hipEvent_t e0,
-                        hipEvent_t e1) {
+hipError_t launch_union(const PassArgs &a, int u, int full, int list, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int G = row_lanes(a);
   const dim3 block(kBlockThreads);
   const size_t lds = (size_t)a.lds_wave_bytes * (kBlockThreads / kWave);
   if (a.n_chunk_wgs + a.n_light_wgs == 0 || (!full && !list)) return record_empty(e0, e1, s);
   const bool st = a.stage || a.count_near;  // the instantiation that stages and counts near successors
   if (st && (a.packed || u != 4)) return hipErrorInvalidValue;
-  if (full && sweep) {
-    if (a.sweep_wgs <= 0 || a.sweep_wgs % kXcds != 0 || !a.sweep_ctr) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)a.sweep_wgs);
-    const int32_t list_too = list ? 1 : 0;
-    hipEvent_t end = list ? nullptr : e1;
-    if (st) {
-      HANF_DISPATCH_STAGED(G, launch_k_lds(k_union_sweep<F, G, 4, true>, grid, block, lds, s, e0, end, a, list_too));
-    } else {
-      switch (u) {
-        case 2:
-          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 2, false>, grid, block, lds, s, e0, end, a, list_too));
-          break;
-        case 8:
-          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 8, false>, grid, block, lds, s, e0, end, a, list_too));
-          break;
-        default:
-          HANF_DISPATCH_FG(a.packed, G, launch_k_lds(k_union_sweep<F, G, 4, false>, grid, block, lds, s, e0, end, a, list_too));
-          break;
-      }
-    }
-  } else if (full) {
+  if (full) {
     const dim3 grid((unsigned)(a.n_chunk_wgs + a.n_light_wgs));
     const int32_t list_too = list ? 1 : 0;
     hipEvent_t end = list ? nullptr : e1;
