@@ -177,6 +177,7 @@ struct hanf_ctx {
   uint8_t *regs[2] = {nullptr, nullptr};
   uint32_t *bits[2] = {nullptr, nullptr};
   uint8_t *todo = nullptr;                             // systolic signals, one byte per node
+  int32_t *sig_list = nullptr, *sig_cnt = nullptr;     // signalled successors per node
   int32_t *sys_node = nullptr, *sys_pos = nullptr;     // systolic signal list
   double *est = nullptr, *blocksum = nullptr, *wgsum = nullptr, *lc = nullptr, *nt = nullptr;
   double *stats_out = nullptr;
@@ -325,6 +326,8 @@ void free_run(hanf_ctx *c) {
   dev_release(c, c->cchunk_sum);
   dev_release(c, c->cchunk_cnt);
   dev_release(c, c->todo);
+  dev_release(c, c->sig_list);
+  dev_release(c, c->sig_cnt);
   dev_release(c, c->sys_node);
   dev_release(c, c->sys_pos);
   c->inited = false;
@@ -591,6 +594,8 @@ void fill_args(hanf_ctx *c) {
   a.todo = c->todo;
   a.sys_node = c->sys_node;
   a.sys_pos = c->sys_pos;
+  a.sig_list = c->sig_list;
+  a.sig_cnt = c->sig_cnt;
   a.st = c->st;
   a.nt = c->nt;
   a.log = c->log;
@@ -1580,11 +1585,16 @@ int init_common(hanf_ctx *c, int32_t log2m, uint64_t seed, const uint64_t *seeds
                               hipMemcpyHostToDevice, c->stream),
             "chunk table upload");
   }
-  if ((c->trp || c->forward) && !c->todo) {  // signal marks for systolic passes
-    if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals"))) {
+  if ((c->trp || c->forward) && !c->todo) {  // signal marks and lists for systolic passes
+    if ((rc = dev_alloc(c, &c->todo, (size_t)kNodesPerBlock * c->n_blocks, "systolic signals")) ||
+        (rc = dev_alloc(c, &c->sig_list, (size_t)std::max<int64_t>(1, c->arcs), "signalled successors")) ||
+        (rc = dev_alloc(c, &c->sig_cnt, (size_t)kNodesPerBlock * c->n_blocks, "signalled successors"))) {
       free_run(c);
       return rc;
     }
+    // zero before the first systolic pass; every pass clears the counts it used
+    HIP_TRY(c, hipMemsetAsync(c->sig_cnt, 0, sizeof(int32_t) * kNodesPerBlock * c->n_blocks, c->stream),
+            "signal counts");
   }
   if (c->trp && !c->sys_node) {  // the list of modified nodes that signal through the transpose
     if ((rc = dev_alloc(c, &c->sys_node, (size_t)c->n, "systolic list")) ||
@@ -1984,6 +1994,7 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   if (copy_graph & HANF_FP_TRANSPOSE) {
     b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
     b += (int64_t)n * 8;                   // signal list
+    b += arcs * 4 + blocks * kNodesPerBlock * 4;  // signalled successors and their counts
   }
   if (copy_graph & HANF_FP_ORDER) {
     b += ((int64_t)n + 1) * 4 + arcs * 4 + (int64_t)n * 8;  // the reordered graph, perm and inv

@@ -179,6 +179,10 @@ struct PassArgs {
   int32_t *unit_list;        // systolic pass: work units with something to do (chunks, then tiles)
   int32_t *sys_node;         // systolic pass: modified nodes with predecessors ...
   int32_t *sys_pos;          //   ... and the offset of their predecessor arcs in the signal list
+  int32_t *sig_list;         // systolic pass: the signalled successors of node v (those whose
+                             //   counter the previous pass modified, one entry per arc) at
+                             //   sig_list[row_ptr[v] ..], in no particular order (arcs entries) ...
+  int32_t *sig_cnt;          //   ... and how many (one per node, 64 per block; cleared with todo)
   DevState *st;
   double *nt;                // N_hat history
   PassLog *log;

@@ -472,6 +472,9 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
   }
   const uint8_t *lane_base = f.cur + sub * F::kBytes;
   int32_t gathered = 0, local = 0, near = 0;
+  // successor ids: the node's arcs, or in a systolic pass its signalled successors (every
+  // one of them maximised in, no flag to test)
+  const int32_t *succ = f.systolic ? a.sig_list : a.col_idx;
   for (int32_t p = beg; p < end; p += G * U) {
     int32_t w[U];
     bool ok[U];
@@ -479,9 +482,9 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     for (int k = 0; k < U; ++k) {
       const int32_t idx = p + k * G + sub;
       ok[k] = idx < end;
-      w[k] = ok[k] ? a.col_idx[idx] : 0;
+      w[k] = ok[k] ? succ[idx] : 0;
     }
-    if (!f.gather_all) {
+    if (!f.gather_all && !f.systolic) {
       uint32_t fw[U];
 #pragma unroll
       for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
@@ -700,9 +703,11 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
   const int slot = lane / G, sub = lane % G;
   const uint64_t below = (1ull << lane) - 1ull;
   const Chunk ch = a.chunks[c];
-  // systolic pass: a node no modified successor signalled keeps its counter (its arcs are
-  // not read; the copy rule below still applies)
-  const int32_t a1 = (f.systolic && f.todo[ch.v] == 0) ? ch.a0 : ch.a1;
+  // systolic pass: the chunk reads the part of its node's signalled successors that falls
+  // in its arc range (none for a node no modified successor signalled, which keeps its
+  // counter; the copy rule below still applies)
+  const int32_t *succ = f.systolic ? a.sig_list : a.col_idx;
+  const int32_t a1 = f.systolic ? max(ch.a0, min(ch.a1, a.row_ptr[ch.v] + a.sig_cnt[ch.v])) : ch.a1;
   typename F::Acc acc_s = F::acc_zero();
   const uint8_t *lane_base = f.cur + sub * F::kBytes;
   // a node in a single chunk is finalised here: its own counter is loaded up front, in
@@ -719,9 +724,9 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     for (int k = 0; k < U; ++k) {
       const int32_t p = base + k * kWave + lane;
       ok[k] = p < a1;
-      w[k] = ok[k] ? a.col_idx[p] : 0;
+      w[k] = ok[k] ? succ[p] : 0;
     }
-    if (!f.gather_all) {
+    if (!f.gather_all && !f.systolic) {
       uint32_t fw[U];
 #pragma unroll
       for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
@@ -860,7 +865,8 @@ __device__ __forceinline__ void process_tile(const PassArgs &a, const Flags &f, 
       if (in && f.gather_all) hv = tl[c64 + lane];
       if (in && !f.gather_all) hv = act[c64 + lane];
       const int32_t hb = hv >= 0 ? a.row_ptr[hv] : 0;
-      const int32_t he = hv >= 0 ? a.row_ptr[hv + 1] : 0;
+      // (a systolic pass reads the node's signalled successors, which start where its arcs do)
+      const int32_t he = hv < 0 ? 0 : f.systolic ? hb + a.sig_cnt[hv] : a.row_ptr[hv + 1];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
       ent[lane] = hv;
@@ -1092,6 +1098,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     uint4 *tq = reinterpret_cast<uint4 *>(a.todo + b * kNodesPerBlock);
 #pragma unroll
     for (int k = 0; k < kNodesPerBlock / 16; ++k) tq[k] = make_uint4(0u, 0u, 0u, 0u);
+    uint4 *tc = reinterpret_cast<uint4 *>(a.sig_cnt + b * kNodesPerBlock);
+#pragma unroll
+    for (int k = 0; k < kNodesPerBlock / 4; ++k) tc[k] = make_uint4(0u, 0u, 0u, 0u);
   }
   const double ws = wave_sum(bs);  // the total estimate; meaningful for one counter per node
   const int32_t wc = wave_sum(bc);
@@ -1461,7 +1470,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->systolic = 0;
     return;
   }
-  __shared__ int32_t s_pos[kMarkTile], s_base[kMarkTile];
+  __shared__ int32_t s_pos[kMarkTile], s_base[kMarkTile], s_node[kMarkTile];
   __shared__ int32_t s_red[kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t t0 = (int64_t)blockIdx.x * kMarkTile; t0 < P; t0 += (int64_t)gridDim.x * kMarkTile) {
@@ -1485,8 +1494,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
     for (int j = threadIdx.x; j < kMarkTile; j += kBlockThreads) {
       if (j < cnt) {
         const int32_t p = a.sys_pos[lo + j];
+        const int32_t w = a.sys_node[lo + j];
         s_pos[j] = p;
-        s_base[j] = a.trow_ptr[a.sys_node[lo + j]] - p;
+        s_base[j] = a.trow_ptr[w] - p;
+        s_node[j] = w;
       }
     }
     __syncthreads();
@@ -1501,6 +1512,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
         const int32_t u = a.tcol_idx[s_base[l] + (int32_t)i];
         a.todo[u] = 1;  // same value from every writer: no atomic needed at byte granularity
         a.tile_todo[u / a.tile_nodes] = 1;
+        // the arc (u -> w) into the modified counter w goes to u's list of signalled
+        // successors: at most one entry per arc of u, so the list fits u's own arc range
+        // (an entry beyond it, from a transposed graph that does not match the graph, is
+        // dropped)
+        const int32_t r0 = a.row_ptr[u];
+        const int32_t k = atomicAdd(&a.sig_cnt[u], 1);
+        if (k < a.row_ptr[u + 1] - r0) a.sig_list[r0 + k] = s_node[l];
       }
     }
     __syncthreads();
@@ -1529,12 +1547,16 @@ __global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ int32_t s_rp[kBlockThreads / kWave][kWave + 1];
   __shared__ uint8_t s_mark[kBlockThreads / kWave][kWave];
+  __shared__ int32_t s_nsig[kBlockThreads / kWave][kWave];
   int32_t *rps = s_rp[wave];
   uint8_t *mark = s_mark[wave];
+  int32_t *nsig = s_nsig[wave];  // signalled successors of the sub-round's nodes so far
   const int64_t u = (int64_t)blockIdx.x * (kBlockThreads / kWave) + wave;
   uint32_t marked = 0, arcs_hit = 0;  // wavefront-uniform
   if (u < a.n_chunks) {
     const Chunk ch = a.chunks[u];
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int32_t r0 = a.row_ptr[ch.v];  // the node's list of signalled successors
     for (int32_t base = ch.a0; base < ch.a1; base += kWave * kFwdLoads) {
       int32_t w[kFwdLoads];
       uint32_t fw[kFwdLoads];
@@ -1543,8 +1565,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
 #pragma unroll
       for (int k = 0; k < kFwdLoads; ++k) fw[k] = mod_word(pb, w[k], sl);
 #pragma unroll
-      for (int k = 0; k < kFwdLoads; ++k)
-        arcs_hit += __popcll(__ballot(base + k * kWave + lane < ch.a1 && mod_in_word(fw[k], w[k], sl)));
+      for (int k = 0; k < kFwdLoads; ++k) {
+        const bool h = base + k * kWave + lane < ch.a1 && mod_in_word(fw[k], w[k], sl);
+        const uint64_t hits = __ballot(h);
+        if (hits) {  // one atomic per load for the node's other chunks, then one entry per hit
+          int32_t at = 0;
+          if (lane == 0) at = atomicAdd(&a.sig_cnt[ch.v], __popcll(hits));
+          at = __shfl(at, 0);
+          if (h) a.sig_list[r0 + at + __popcll(hits & below)] = w[k];
+          arcs_hit += __popcll(hits);
+        }
+      }
     }
     if (arcs_hit) {
       marked = 1;
@@ -1563,6 +1594,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
       if (valid) rps[lane] = r0;
       if (lane == cnt - 1) rps[cnt] = r1;
       mark[lane] = 0;
+      nsig[lane] = 0;
       const uint64_t heavy = __ballot(valid && r1 - r0 > a.light_max);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1591,6 +1623,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
                   if (rps[mid] <= arc) l = mid; else r = mid;
                 }
                 mark[l] = 1;  // the same value from every lane that hits this node
+                a.sig_list[rps[l] + atomicAdd(&nsig[l], 1)] = w[k];  // (a light node's arcs are all here)
               }
             }
           }
@@ -1600,7 +1633,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_fwd_mark(PassArgs a) {
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
       const bool hit = mark[lane] != 0;
-      if (hit) a.todo[v] = 1;
+      if (hit) {
+        a.todo[v] = 1;
+        a.sig_cnt[v] = nsig[lane];
+      }
       marked += (uint32_t)__popcll(__ballot(hit));
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();

@@ -117,6 +117,9 @@ def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
                 # the same arcs the frontier gathers (counted from the other end through the
                 # transpose)
                 assert log["arcs_signalled"] == maxed, (t, log, maxed)
+                # and the union step reads exactly those arcs (each node's list of signalled
+                # successors), not the whole successor lists of the signalled nodes
+                assert log["arcs_scanned"] == log["arcs_gathered"] == maxed, (t, log, maxed)
             prev_changed = changed
             assert ch_last == changed
             mod = mod_out
