@@ -115,6 +115,35 @@ def copy_scale(copy_dir: str, copy_bytes: int) -> float:
     return copy_bytes / (kib * 1024.0)
 
 
+def derived_utilisation(c, cus=256, simds=1024, xcds=8):
+    """Utilisation of the vector memory path and the vector ALUs in the first pass, from
+    counters of separate runs (so only roughly comparable): GRBM_GUI_ACTIVE counts busy
+    cycles per XCD (summed over the 8); TA and TD busy cycles are per compute unit; a
+    wavefront's VALU instruction occupies its SIMD for one quad-cycle."""
+    if "GRBM_GUI_ACTIVE" not in c:
+        return []
+    cyc = c["GRBM_GUI_ACTIVE"] / xcds
+    rows = []
+    if "TA_TA_BUSY_sum" in c:
+        rows.append(("texture addresser (TA) busy", c["TA_TA_BUSY_sum"] / cus / cyc))
+    if "TD_TD_BUSY_sum" in c:
+        rows.append(("texture data (TD) busy", c["TD_TD_BUSY_sum"] / cus / cyc))
+    if "TD_TC_STALL_sum" in c:
+        rows.append(("TD stalled waiting for the L1 cache", c["TD_TC_STALL_sum"] / cus / cyc))
+    if "TCP_PENDING_STALL_CYCLES_sum" in c:
+        rows.append(("L1 cache stalled on pending L2 requests", c["TCP_PENDING_STALL_CYCLES_sum"] / cus / cyc))
+    if "SQ_INSTS_VALU" in c:
+        rows.append(("VALU issue (instructions x 4 cycles / SIMD cycles)", 4 * c["SQ_INSTS_VALU"] / simds / cyc))
+    L = ["Derived, first pass (cycles per XCD from GRBM_GUI_ACTIVE / 8; counters from separate runs):", "",
+         "| quantity | value |", "|---|---:|"]
+    L += [f"| {k} | {v:.0%} |" for k, v in rows]
+    if "TCP_TCC_READ_REQ_LATENCY_sum" in c and c.get("TCP_TCC_READ_REQ_sum"):
+        L.append(f"| L1 to L2 read latency, average (cycles) | {c['TCP_TCC_READ_REQ_LATENCY_sum'] / c['TCP_TCC_READ_REQ_sum']:.0f} |")
+    if "TCC_HIT_sum" in c and "TCC_MISS_sum" in c:
+        L.append(f"| L2 hit rate | {c['TCC_HIT_sum'] / (c['TCC_HIT_sum'] + c['TCC_MISS_sum']):.0%} |")
+    return L + [""]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", required=True)
@@ -203,6 +232,7 @@ def main():
               "Summed over the union dispatches of a pass (k_union, k_union_list); first pass (every "
               "successor gathered) and the average over the passes of one run.", "",
               "| counter | first pass | average per pass |", "|---|---:|---:|"]
+        first = {}
         for d in args.counters:
             cj = json.loads(open(d.rstrip("/") + ".json").read().strip().splitlines()[-1])
             pr, runs_c = cj["config"]["passes"], cj["steps"] + cj["warmup"]
@@ -210,7 +240,9 @@ def main():
                 per = union_per_pass(rows, pr, runs_c)
                 if per:
                     L.append(f"| {name} | {per[0]:.4g} | {sum(per) / len(per):.4g} |")
+                    first[name] = per[0]
         L += [""]
+        L += derived_utilisation(first)
     L += [f"Kernel source at measurement: `paper_1011_5599_amd/csrc/hanf_kernels.hip` sha256 `{sha[:16]}…` "
           "(bench.py reports `traffic` only while the source is unchanged)."]
     with open(args.out_md, "w") as f:
