@@ -1375,6 +1375,7 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
 // in-degrees, and marks every predecessor; k_sys_units lists the work units (chunks, light
 // tiles) that hold a marked or modified node.
 constexpr int kMarkTile = 1024;
+static_assert(kMarkTile % kBlockThreads == 0, "whole arcs per thread in k_sys_mark");
 constexpr int kListWgs = 2048;  // persistent union grid: 8 workgroups per compute unit
 constexpr int kSigRounds = 4;   // items per thread in the signal compaction kernels
 constexpr int kSysArcDiv = 16;  // a systolic pass that would signal more than arcs/16 arcs falls
@@ -1501,26 +1502,42 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
       }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < kMarkTile; j += kBlockThreads) {
-      const int64_t i = t0 + j;
+    // each thread's kMarkTile / kBlockThreads arcs go through every step together, so their
+    // loads and atomics are in flight at the same time
+    constexpr int kPer = kMarkTile / kBlockThreads;
+    int32_t u[kPer], wl[kPer], r0[kPer], r1[kPer], k[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int64_t i = t0 + threadIdx.x + q * kBlockThreads;
+      u[q] = -1;
+      wl[q] = 0;
       if (i < P) {
         int32_t l = 0, r = cnt;  // last entry with s_pos <= i
         while (r - l > 1) {
           const int32_t mid = (l + r) >> 1;
           if (s_pos[mid] <= i) l = mid; else r = mid;
         }
-        const int32_t u = a.tcol_idx[s_base[l] + (int32_t)i];
-        a.todo[u] = 1;  // same value from every writer: no atomic needed at byte granularity
-        a.tile_todo[u / a.tile_nodes] = 1;
+        u[q] = a.tcol_idx[s_base[l] + (int32_t)i];
+        wl[q] = s_node[l];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (u[q] >= 0) {
+        a.todo[u[q]] = 1;  // same value from every writer: no atomic needed at byte granularity
+        a.tile_todo[u[q] / a.tile_nodes] = 1;
+        r0[q] = a.row_ptr[u[q]];
+        r1[q] = a.row_ptr[u[q] + 1];
         // the arc (u -> w) into the modified counter w goes to u's list of signalled
         // successors: at most one entry per arc of u, so the list fits u's own arc range
         // (an entry beyond it, from a transposed graph that does not match the graph, is
         // dropped)
-        const int32_t r0 = a.row_ptr[u];
-        const int32_t k = atomicAdd(&a.sig_cnt[u], 1);
-        if (k < a.row_ptr[u + 1] - r0) a.sig_list[r0 + k] = s_node[l];
+        k[q] = atomicAdd(&a.sig_cnt[u[q]], 1);
       }
     }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (u[q] >= 0 && k[q] < r1[q] - r0[q]) a.sig_list[r0[q] + k[q]] = wl[q];
     __syncthreads();
   }
 }
