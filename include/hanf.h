@@ -320,11 +320,13 @@ int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *le
 
 /* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers:
  * two register arrays (the counters and the update buffer, Section 3.2; 5m/8 bytes per
- * counter with HANF_FP_PACKED5 in `copy_graph`), flags and estimate sums, plus the graph copy
- * (HANF_FP_COPY_GRAPH), the transposed graph with the systolic signal buffers
- * (HANF_FP_TRANSPOSE) and the reordered graph (HANF_FP_ORDER). Pure host function; the memory figure of Section 3.4 (O(n m) register
- * bytes) is its dominant term. HANF_EINVAL for arguments out of range. */
-int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes);
+ * counter with HANF_FP_PACKED5 in `flags`), modified flags and estimate sums, plus, by the
+ * bits of `flags` (HANF_FP_*): the graph copy (HANF_FP_COPY_GRAPH), the transposed graph
+ * with the systolic signal buffers and the lists of signalled successors (HANF_FP_TRANSPOSE;
+ * systolic passes from a forward scan need the same buffers less the transposed graph) and
+ * the reordered graph (HANF_FP_ORDER). Pure host function; the memory figure of Section 3.4
+ * (O(n m) register bytes) is its dominant term. HANF_EINVAL for arguments out of range. */
+int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t flags, int64_t *bytes);
 
 /* Device memory the context holds (pure host function): *held (may be NULL) = every device
  * buffer it allocated and has not returned to HIP, in use or kept in its pool for reuse by

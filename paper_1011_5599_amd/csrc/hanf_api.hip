@@ -1973,16 +1973,16 @@ int hanf_read_pass_log(hanf_ctx *c, hanf_pass_t *out, int32_t cap, int32_t *len)
   return HANF_OK;
 }
 
-int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, int64_t *bytes) {
+int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t flags, int64_t *bytes) {
   if (!bytes) return fail(nullptr, HANF_EINVAL, "bytes is NULL");
   if (n < 1 || arcs < 0 || arcs >= (int64_t)INT32_MAX || log2m < 4 || log2m > 8)
     return fail(nullptr, HANF_EINVAL, "hanf_footprint: argument out of range");
-  if ((copy_graph & HANF_FP_PACKED5) && log2m < 6)
+  if ((flags & HANF_FP_PACKED5) && log2m < 6)
     return fail(nullptr, HANF_EINVAL, "hanf_footprint: 5-bit registers need log2m >= 6");
   const int64_t m = 1LL << log2m;
   const int64_t blocks = ((int64_t)n + kNodesPerBlock - 1) / kNodesPerBlock;
   // counters + update buffer: m bytes per counter, or 5m/8 with 5-bit registers
-  int64_t b = 2 * (int64_t)n * ((copy_graph & HANF_FP_PACKED5) ? m * 5 / 8 : m);
+  int64_t b = 2 * (int64_t)n * ((flags & HANF_FP_PACKED5) ? m * 5 / 8 : m);
   b += 2 * 2 * blocks * 4;                               // modified flags
   b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
   b += (int64_t)n * 4 + 4096;                            // light tiles
@@ -1990,15 +1990,15 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t copy_graph, i
   b += ((int64_t)n + 3) * 8;                             // N_hat history (pass cap n + 1)
   b += std::min<int64_t>((int64_t)n + 3, kMaxLogRecords) * (int64_t)sizeof(PassLog);  // pass records
   b += blocks * kNodesPerBlock;                          // systolic marks (forward scan or transpose)
-  if (copy_graph & HANF_FP_COPY_GRAPH) b += ((int64_t)n + 1) * 4 + arcs * 4;
-  if (copy_graph & HANF_FP_TRANSPOSE) {
+  if (flags & HANF_FP_COPY_GRAPH) b += ((int64_t)n + 1) * 4 + arcs * 4;
+  if (flags & HANF_FP_TRANSPOSE) {
     b += ((int64_t)n + 1) * 4 + arcs * 4;  // predecessor lists
     b += (int64_t)n * 8;                   // signal list
     b += arcs * 4 + blocks * kNodesPerBlock * 4;  // signalled successors and their counts
   }
-  if (copy_graph & HANF_FP_ORDER) {
+  if (flags & HANF_FP_ORDER) {
     b += ((int64_t)n + 1) * 4 + arcs * 4 + (int64_t)n * 8;  // the reordered graph, perm and inv
-    if (copy_graph & HANF_FP_TRANSPOSE) b += ((int64_t)n + 1) * 4 + arcs * 4;  // a transpose of its own
+    if (flags & HANF_FP_TRANSPOSE) b += ((int64_t)n + 1) * 4 + arcs * 4;  // a transpose of its own
   }
   *bytes = b;
   return HANF_OK;
