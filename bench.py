@@ -454,7 +454,8 @@ def run_serve_mode(args, count=None, rates=(0.25, 0.5, 1.0, 2.0)):
         seq_lat = fin - arrivals
         reqs = [serve.Request(sp["rid"], sp["graph"][0], sp["graph"][1], sp["log2m"], sp["seed"], float(a))
                 for sp, a in zip(specs, arrivals)]
-        srv = serve.Server(0, max_batches=args.max_batches, size_classes=bool(args.size_classes))
+        kw = {"passes_per_poll": args.passes_per_poll} if getattr(args, "passes_per_poll", 0) else {}
+        srv = serve.Server(0, max_batches=args.max_batches, size_classes=bool(args.size_classes), **kw)
         srv.warm_up(reqs)
         srv.batch_sizes, srv.max_flights = [], 0
         srv.serve_trace(reqs)
@@ -495,7 +496,8 @@ def run_serve_mode(args, count=None, rates=(0.25, 0.5, 1.0, 2.0)):
                    "nodes": int(sum(sp["n"] for sp in specs)),
                    "arcs": int(sum(len(sp["graph"][1]) for sp in specs)),
                    "sequential_capacity_req_per_s": capacity,
-                   "policy": {"size_classes": bool(args.size_classes), "max_batches": args.max_batches},
+                   "policy": {"size_classes": bool(args.size_classes), "max_batches": args.max_batches,
+                              "passes_per_poll": srv.passes_per_poll},
                    "service_ms": {"p50": 1000 * float(np.percentile(service, 50)),
                                   "p99": 1000 * float(np.percentile(service, 99))}},
         "rates": rows,
@@ -701,6 +703,10 @@ def main():
     ap.add_argument("--max-batches", type=int, default=4, help="serve mode: batches in flight")
     ap.add_argument("--size-classes", type=int, default=1, choices=(0, 1),
                     help="serve mode: batch only requests whose footprints are within 4x")
+    ap.add_argument("--passes-per-poll", type=int, default=0,
+                    help="serve mode: passes enqueued per batch between polls (0: the server's default)")
+    ap.add_argument("--rates", default="0.25,0.5,1,2",
+                    help="serve mode: arrival rates, as multiples of the sequential capacity")
     ap.add_argument("--runs-per-load", type=int, default=1, metavar="R",
                     help="plain mode: runs (hash seeds seed .. seed + R - 1) after each ingest of the "
                          "graph; a step is the ingest and its R runs")
@@ -733,7 +739,7 @@ def main():
         print(json.dumps(run_batch_mode(args)))
         return
     if args.mode == "serve":
-        print(json.dumps(run_serve_mode(args)))
+        print(json.dumps(run_serve_mode(args, rates=tuple(float(x) for x in args.rates.split(",")))))
         return
     if args.mode == "seeds":
         print(json.dumps(run_seeds_mode(args)))

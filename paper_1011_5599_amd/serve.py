@@ -84,7 +84,7 @@ def footprint(req: Request) -> int:
 
 class Server:
     def __init__(self, device: int = 0, hbm_budget: int = 96 << 30, max_batches: int = 4,
-                 passes_per_poll: int = 2, keep_registers: bool = False, max_batch_requests: int = 64,
+                 passes_per_poll: int = 4, keep_registers: bool = False, max_batch_requests: int = 64,
                  size_classes: bool = True, clock=time.perf_counter, alloc_slack: float = 1.5,
                  **options):
         self.device = device
@@ -92,6 +92,10 @@ class Server:
         # the library rounds allocations up to size classes 2^k and 1.5 * 2^k (at most 1.5x)
         self.alloc_slack = alloc_slack
         self.max_batches = max_batches
+        # passes enqueued per batch between polls: 4 keeps batches running while the host
+        # uploads another request's graph, at the cost of at most 3 passes after a batch's
+        # fixpoint (they leave at once); measured on MI355X, 48 requests at 1x and 2x the
+        # sequential capacity: median latency 5.5 and 10.7 ms with 4, 8.1 and 13.8 with 2
         self.passes_per_poll = passes_per_poll
         self.keep_registers = keep_registers
         self.max_batch_requests = max_batch_requests
@@ -145,15 +149,19 @@ class Server:
             raise ValueError(f"request {req.rid} needs more than the HBM budget")
         self.waiting.append(req)
 
-    def _admit(self):
+    def _admit(self, finished: list):
         t0 = self.clock()
         try:
-            self._admit_groups()
+            self._admit_groups(finished)
         finally:
             self.host_s["admit"] += self.clock() - t0
 
-    def _admit_groups(self):
+    def _admit_groups(self, finished: list):
+        first_group = True
         while self.waiting and len(self.flights) < self.max_batches:
+            if not first_group:  # the batches in flight get their next passes before the next upload
+                finished += self._poll_all()
+            first_group = False
             first = self.waiting[0]
             m = first.log2m
             key = self._class(first)
@@ -250,9 +258,18 @@ class Server:
         return out
 
     def pump(self) -> list[Request]:
-        """One round: admit what fits, poll every batch, keep the unfinished ones going.
-        Returns the requests completed in this round."""
-        self._admit()
+        """One round: poll every batch and keep the unfinished ones going, then admit what
+        fits (polling again between admitted groups: uploading a large graph holds the host for
+        milliseconds, and the batches in flight must not run dry meanwhile). Returns the
+        requests completed in this round."""
+        finished = self._poll_all()
+        self._admit(finished)
+        self.done += finished
+        return finished
+
+    def _poll_all(self) -> list[Request]:
+        """Polls every batch in flight: collects its finished requests, retires it when it is
+        done, else enqueues its next passes."""
         finished = []
         for fl in list(self.flights):
             t0 = self.clock()
@@ -276,7 +293,6 @@ class Server:
                 self.flights.remove(fl)
             else:
                 hanf_enqueue(fl.batch.ctx, self.passes_per_poll)
-        self.done += finished
         return finished
 
     def idle(self) -> bool:

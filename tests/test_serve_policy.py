@@ -131,11 +131,9 @@ def test_the_oldest_request_is_not_passed_by_smaller_ones(fake):
     assert len(srv.flights) == 1 and [r.rid for r in srv.waiting] == [0, 1]
     small_ctx = srv.flights[0].batch
     finish(small_ctx, [0], done=True)
-    srv.pump()                                     # admission runs before the poll
-    assert [r.rid for r in srv.done] == [9] and srv.used == 0 and srv.flights == []
-    assert srv.held() == fp_small                  # the idle context still holds its memory
-    srv.pump()                                     # it is destroyed so the big one enters first
-    assert small_ctx.closed and srv.idle_batches == []
+    srv.pump()                                     # the poll (before admission) retires the batch;
+    assert [r.rid for r in srv.done] == [9]        # its idle context still held its memory, and is
+    assert small_ctx.closed and srv.idle_batches == []   # destroyed so that the big one enters first
     assert [[r.rid for r in fl.requests] for fl in srv.flights] == [[0]]
     assert [r.rid for r in srv.waiting] == [1]
     assert srv.held() <= srv.budget
