@@ -445,6 +445,15 @@ int hanf_max5_groups(int device, const uint8_t *x, const uint8_t *y, uint8_t *ou
 int hanf_bytemax_words(int device, const uint32_t *x, const uint32_t *y, uint32_t *out,
                        int64_t count);
 
+/* The union step's accumulator for the successor counters it gathers (Algorithm 2 union),
+ * on its own: `count` groups of k 16-byte lanes (16 registers each, one per byte),
+ * out[i] = the register-wise max of x[i*k .. i*k+k), accumulated from empty (from_first 0)
+ * or starting from the first lane (1), the two ways the union kernel starts it. Device
+ * pointers, 16-byte aligned, on device `device`; x holds count * k lanes, out count lanes.
+ * Exposed for exhaustive testing. Synchronous. */
+int hanf_gathermax_lanes(int device, const uint32_t *x, int32_t k, int32_t from_first, uint32_t *out,
+                         int64_t count);
+
 #ifdef __cplusplus
 }
 #endif

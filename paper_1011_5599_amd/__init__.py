@@ -140,6 +140,7 @@ def lib():
             "hanf_footprint": ([i32, i64, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
             "hanf_last_error": ([vp], ctypes.c_char_p),
             "hanf_bytemax_words": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
+            "hanf_gathermax_lanes": ([ctypes.c_int, vp, ctypes.c_int32, ctypes.c_int32, vp, i64], ctypes.c_int),
             "hanf_max5_groups": ([ctypes.c_int, vp, vp, vp, i64], ctypes.c_int),
             "hanf_stats_nt": ([vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp],
                               ctypes.c_int),
@@ -366,6 +367,16 @@ def hanf_max5_groups(device: int, x, y, out) -> None:
     if x.numel() % 40 or y.numel() != x.numel() or out.numel() != x.numel():
         raise ValueError("x, y and out must hold the same whole number of 40-byte groups")
     _check(lib().hanf_max5_groups(device, x.data_ptr(), y.data_ptr(), out.data_ptr(), x.numel() // 40))
+
+
+def hanf_gathermax_lanes(device: int, x, k: int, from_first: bool, out) -> None:
+    """Device tensors: x of count * k * 4 int32 words (16-byte lanes), out of count * 4;
+    out lane i = register-wise max of lanes i*k .. i*k+k of x, by the union step's gather
+    accumulator."""
+    if out.numel() % 4 or x.numel() != out.numel() * int(k):
+        raise ValueError("hanf_gathermax_lanes: x must hold k lanes of 4 words per lane of out")
+    _check(lib().hanf_gathermax_lanes(device, x.data_ptr(), int(k), 1 if from_first else 0, out.data_ptr(),
+                                      out.numel() // 4))
 
 
 def hanf_bytemax_words(device: int, x, y, out) -> None:

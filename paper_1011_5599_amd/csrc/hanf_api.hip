@@ -2465,6 +2465,20 @@ int hanf_max5_groups(int device, const uint8_t *x, const uint8_t *y, uint8_t *ou
   return HANF_OK;
 }
 
+int hanf_gathermax_lanes(int device, const uint32_t *x, int32_t k, int32_t from_first, uint32_t *out, int64_t count) {
+  if (!x || !out || k < 1 || count < 0 || (from_first != 0 && from_first != 1))
+    return fail(nullptr, HANF_EINVAL, "hanf_gathermax_lanes: bad argument");
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15)
+    return fail(nullptr, HANF_EINVAL, "hanf_gathermax_lanes: buffers must be 16-byte aligned");
+  hipError_t e = hipSetDevice(device);
+  if (e == hipSuccess && count > 0)
+    e = launch_gathermax_lanes(reinterpret_cast<const uint4 *>(x), k, from_first, reinterpret_cast<uint4 *>(out),
+                               count, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hanf_gathermax_lanes");
+  return HANF_OK;
+}
+
 int hanf_bytemax_words(int device, const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count) {
   if (!x || !y || !out || count < 0) return fail(nullptr, HANF_EINVAL, "hanf_bytemax_words: bad argument");
   hipError_t e = hipSetDevice(device);

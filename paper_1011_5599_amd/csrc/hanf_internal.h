@@ -310,6 +310,8 @@ hipError_t launch_set_history(double *nt, const double *prefix, int32_t len, Dev
                               int32_t t, hipStream_t s);
 hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
                                 hipStream_t s);
+hipError_t launch_gathermax_lanes(const uint4 *x, int32_t k, int32_t from_first, uint4 *out, int64_t count,
+                                 hipStream_t s);
 hipError_t launch_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups, hipStream_t s);
 hipError_t launch_unpack5(const uint8_t *packed, uint8_t *out, int64_t groups, hipStream_t s);
 hipError_t launch_pack5(const uint8_t *in, uint8_t *packed, int64_t groups, hipStream_t s);

@@ -2283,6 +2283,19 @@ __global__ void k_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *
     out[i] = bytemax(x[i], y[i]);
 }
 
+// The union step's gather accumulator on its own: out[i] = the register-wise max of the k
+// lanes x[i*k .. i*k+k), accumulated from empty (from_first 0) or from the first lane.
+__global__ void k_gathermax_lanes(const uint4 *x, int32_t k, int32_t from_first, uint4 *out, int64_t count) {
+  using F = ByteRegs;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const uint4 *g = x + i * k;
+    F::Acc a = from_first ? F::acc_from(g[0]) : F::acc_zero();
+    for (int32_t j = from_first ? 1 : 0; j < k; ++j) F::acc_add(a, g[j]);
+    out[i] = F::acc_value(a);
+  }
+}
+
 // The packed max on its own: groups of 64 5-bit registers (five 64-bit words each).
 __global__ void k_max5_groups(const uint8_t *x, const uint8_t *y, uint8_t *out, int64_t groups) {
   using F = Packed5Regs;
@@ -2736,6 +2749,12 @@ hipError_t launch_check_registers(const uint8_t *regs, int64_t bytes, DevState *
 hipError_t launch_bytemax_words(const uint32_t *x, const uint32_t *y, uint32_t *out, int64_t count,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_bytemax_words, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, x, y, out, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gathermax_lanes(const uint4 *x, int32_t k, int32_t from_first, uint4 *out, int64_t count,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_gathermax_lanes, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, x, k, from_first, out, count);
   return hipGetLastError();
 }
 

@@ -160,6 +160,32 @@ def test_bytemax_exhaustive():
         assert np.array_equal(to.cpu().numpy().view(np.uint32), want_w)
 
 
+@pytest.mark.parametrize("from_first", [0, 1])
+def test_gather_accumulator_exhaustive(from_first):
+    """The union step's gather accumulator (packed 16-bit maxima of the words and of the
+    words shifted up a byte, put together by a byte permute) equals np.maximum for every
+    pair of byte values 0..255 in every byte position of a 16-byte lane, the other bytes
+    random; and over random groups of 2..9 lanes."""
+    import torch
+    vals = np.arange(256, dtype=np.uint8)
+    X, Y = np.meshgrid(vals, vals, indexing="ij")
+    X, Y = X.ravel(), Y.ravel()
+    rng = np.random.default_rng(1 + from_first)
+    for pos in range(16):
+        a = rng.integers(0, 256, (X.size, 16), dtype=np.uint8)
+        b = rng.integers(0, 256, (X.size, 16), dtype=np.uint8)
+        a[:, pos], b[:, pos] = X, Y
+        x = np.stack([a, b], axis=1)  # groups of k = 2 lanes
+        out = torch.empty(X.size * 4, dtype=torch.int32, device="cuda")
+        hanf.hanf_gathermax_lanes(0, torch.from_numpy(x.reshape(-1).view(np.int32).copy()).cuda(), 2, from_first, out)
+        assert np.array_equal(out.cpu().numpy().view(np.uint8).reshape(-1, 16), np.maximum(a, b)), pos
+    for k in range(2, 10):
+        x = rng.integers(0, 256, (4096, k, 16), dtype=np.uint8)
+        out = torch.empty(4096 * 4, dtype=torch.int32, device="cuda")
+        hanf.hanf_gathermax_lanes(0, torch.from_numpy(x.reshape(-1).view(np.int32).copy()).cuda(), k, from_first, out)
+        assert np.array_equal(out.cpu().numpy().view(np.uint8).reshape(-1, 16), x.max(axis=1)), k
+
+
 def test_rmat14_every_iteration():
     """Directed R-MAT scale 14, 262,144 arcs, 16 registers, hash seed 1: registers at every
     t, N_hat, T, work counters; statistics against the oracle's."""
