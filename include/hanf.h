@@ -225,16 +225,17 @@ int hanf_load_csr(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr
  * arrays are borrowed and must outlive the context's use of this graph; for a symmetric
  * graph the graph's own arrays may be passed. The CSR shape is checked on the device
  * (HANF_EINVAL); that it is the transpose is the caller's guarantee (otherwise the results
- * are undefined). Single graphs only. Call after hanf_load_csr and before
- * hanf_init_counters (a run in progress must be initialised again). Replaced by the next
- * graph ingest. */
+ * are undefined, though every access stays inside the context's arrays). Single graphs
+ * only. Call after hanf_load_csr and before hanf_init_counters (a run in progress must be
+ * initialised again). Replaced by the next graph ingest. */
 int hanf_load_transpose(hanf_ctx *ctx, int32_t n, int64_t arcs, const int32_t *row_ptr_t,
                         const int32_t *col_idx_t, uint32_t flags);
 
 /* Declares the loaded graph (every graph of a batch) symmetric: its successor lists are
  * also its predecessor lists, so they serve systolic passes as the transposed graph with no
- * copy. The symmetry is the caller's guarantee (otherwise the results are undefined). Same
- * call order as hanf_load_transpose; single graphs and batches. */
+ * copy. The symmetry is the caller's guarantee (otherwise the results are undefined, though
+ * every access stays inside the context's arrays). Same call order as hanf_load_transpose;
+ * single graphs and batches. */
 int hanf_transpose_self(hanf_ctx *ctx);
 
 /* Builds the transposed graph of the loaded graph (or batch) on the device: the arcs are

@@ -1530,14 +1530,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_sys_mark(PassArgs a) {
         r1[q] = a.row_ptr[u[q] + 1];
         // the arc (u -> w) into the modified counter w goes to u's list of signalled
         // successors: at most one entry per arc of u, so the list fits u's own arc range
-        // (an entry beyond it, from a transposed graph that does not match the graph, is
-        // dropped)
         k[q] = atomicAdd(&a.sig_cnt[u[q]], 1);
       }
     }
+    // An entry beyond u's arc range (possible only with a transposed graph that does not
+    // match the graph) is dropped and its add taken back: the count then ends at u's
+    // degree, never above, so the union step reads only entries written here. (Once the
+    // count has passed the degree it never falls below it, so later adds cannot reuse a
+    // slot inside the range.)
 #pragma unroll
-    for (int q = 0; q < kPer; ++q)
-      if (u[q] >= 0 && k[q] < r1[q] - r0[q]) a.sig_list[r0[q] + k[q]] = wl[q];
+    for (int q = 0; q < kPer; ++q) {
+      if (u[q] < 0) continue;
+      if (k[q] < r1[q] - r0[q]) a.sig_list[r0[q] + k[q]] = wl[q];
+      else atomicSub(&a.sig_cnt[u[q]], 1);
+    }
     __syncthreads();
   }
 }

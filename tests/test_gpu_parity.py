@@ -295,6 +295,55 @@ def test_transpose_errors():
         assert e.value.code == hanf.HANF_EINVAL
 
 
+@pytest.mark.parametrize("kind", ["loaded", "declared", "declared_batch"])
+def test_mismatched_transpose_stays_in_bounds(kind):
+    """A transposed graph that is not the graph's transpose has the right shape, so it is
+    accepted; its results are undefined, but the run must end normally. Here nodes with one
+    successor (or none) are named as predecessors of thousands of nodes: a systolic pass
+    signals them far more often than they have arcs, and the surplus must be dropped, not
+    read. 'declared' calls a non-symmetric graph symmetric, which does the same to nodes
+    whose in-degree is above their out-degree. Afterwards the same context runs the graph
+    with its true transpose, and that run equals the oracle's."""
+    rp, ci = graphgen.rmat(12, 40_000, seed=6)
+    n = len(rp) - 1
+    deg = np.diff(rp)
+    trp, tci = transpose_csr(rp, ci)
+    few = np.flatnonzero(deg <= 1)[:4]  # out-degree 0 or 1
+    assert len(few) == 4 and (deg[few] == 0).any() and (deg[few] == 1).any()
+    bad = tci.copy()
+    bad[: len(bad) // 2] = np.resize(few, len(bad) // 2)
+    assert np.bincount(bad, minlength=n)[few].min() > 1000
+    b, seed = 6, 17
+    nt_o, T_o, regs_o = oracle.run(rp, ci, b, seed, want_regs=True)
+    _flush(f"[mismatched transpose] kind={kind} n={n} arcs={len(ci)} b={b} seed={seed}")
+    if kind == "declared_batch":
+        with hanf.Batch(0, systolic=1) as bt:
+            bt.load_graphs([(rp, ci)], 1).transpose_self().init(b, [seed])
+            bt.run()
+            assert any(r["systolic"] for r in bt.pass_log())
+            assert bt.registers(0).max() <= 31
+            assert np.isfinite(bt.nt(0)).all()
+        return
+    with hanf.HyperANF(0, systolic=1) as h:
+        h.load(rp, ci)
+        if kind == "loaded":
+            h.load_transpose(trp, bad)
+        else:
+            h.transpose_self()
+        h.init(b, seed)
+        st = h.step(0)[0]
+        assert st == hanf.HANF_DONE
+        log = h.pass_log()
+        assert any(r["systolic"] and r["arcs_signalled"] > 0 for r in log), log
+        assert h.registers().max() <= 31 and np.isfinite(h.nt()).all()
+        h.load(rp, ci).load_transpose(trp, tci).init(b, seed)
+        nt = h.run()
+        assert any(r["systolic"] for r in h.pass_log())
+        assert len(nt) == T_o + 1
+        np.testing.assert_allclose(nt, nt_o, rtol=RTOL, atol=0)
+        assert np.array_equal(h.registers(), regs_o)
+
+
 @pytest.mark.parametrize("name", ["single", "empty100", "star_out", "star_in", "cycle", "path",
                                   "complete", "cpc", "loops_dups"])
 def test_edge_graphs(name):
