@@ -13,7 +13,9 @@
 // One pass (c_t -> c_{t+1}) is the signal kernels (systolic passes only do work), one
 // union launch (k_union, or k_union_list over listed work units), k_finalize when a node's
 // arcs are split over several wavefronts, k_estimate_changed for packed registers, and two
-// reduction launches. The union is bound by HBM: random gathers of successor counters.
+// reduction launches. The union's cost is its random gathers of successor counters: row
+// requests through each compute unit's memory path (address and data units, L1 misses to
+// L2) rather than HBM bytes, with the byte maxima's vector ALU work close behind.
 // Lanes load counters 16 bytes at a time (40 bytes, 64 registers, when packed); a node row
 // (S counters) is handled by G = S*m/16 lanes (S*m/64 packed), a "slot"; a wavefront holds
 // W = 64/G slots. The max of a whole row serves its S counters at once (one successor id
