@@ -142,6 +142,7 @@ struct hanf_ctx {
   bool ordered = false;  // the order of this ingest is decided
   int32_t inits = 0;     // initialisations since ingest
   int32_t *perm = nullptr, *inv = nullptr;  // new id -> caller's id, and back; NULL: the same
+  int32_t n_hubs = 0;                        // the order's hubs (new ids 0 .. n_hubs - 1)
 
   Schedule sch;
 
@@ -361,6 +362,7 @@ void free_graph(hanf_ctx *c) {
   free_layout(c);
   dev_release(c, c->perm);
   dev_release(c, c->inv);
+  c->n_hubs = 0;
   c->ordered = false;
   c->inits = 0;
   dev_release(c, c->rp_own);
@@ -755,21 +757,29 @@ int permute_graph(hanf_ctx *c, const int32_t *rp, const int32_t *ci, int32_t **r
   const int32_t n = c->n;
   const int64_t arcs = c->arcs;
   uint64_t *keys = nullptr, *tmp = nullptr;
+  uint4 *rec = nullptr;
+  int32_t *hub_new = nullptr;
   int rc;
   if ((rc = dev_alloc(c, rp_new, (size_t)n + 1, "reordered row_ptr")) ||
       (rc = dev_alloc(c, ci_new, (size_t)arcs, "reordered col_idx")) ||
       (rc = dev_alloc(c, &keys, (size_t)n + 1, "reorder keys")) ||
-      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch"))) {
+      (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch")) ||
+      (rc = dev_alloc(c, &rec, (size_t)rename_groups(n), "renaming table")) ||
+      (rc = dev_alloc(c, &hub_new, (size_t)std::max(c->n_hubs, 1), "renaming table"))) {
     dev_release(c, *rp_new);
     dev_release(c, *ci_new);
     dev_release(c, keys);
     dev_release(c, tmp);
+    dev_release(c, rec);
+    dev_release(c, hub_new);
     return rc;
   }
-  const hipError_t e =
-      launch_permute_csr(rp, ci, n, arcs, c->perm, c->inv, keys, tmp, *rp_new, *ci_new, c->stream);
+  const hipError_t e = launch_permute_csr(rp, ci, n, arcs, c->perm, c->inv, c->n_hubs, keys, tmp, rec, hub_new,
+                                          *rp_new, *ci_new, c->stream);
   dev_release(c, keys);  // pooled: reused only by work queued later on the same stream
   dev_release(c, tmp);
+  dev_release(c, rec);
+  dev_release(c, hub_new);
   if (e != hipSuccess) {
     dev_release(c, *rp_new);
     dev_release(c, *ci_new);
@@ -826,8 +836,13 @@ int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
   hipError_t e = launch_in_degrees(c->trp, c->ci, n, arcs, deg, c->stream);
   if (e == hipSuccess) e = launch_order_select(deg, n, K, hist, plan, counts, tmp, c->perm, c->inv, c->stream);
   int32_t lstar = 0;  // kOrderLevels: no class of in-degree fits under K, the order is the caller's
+  uint64_t hubs = 0;  // the first new id of the other nodes: the count of hubs
   if (e == hipSuccess) e = hipMemcpyAsync(&lstar, plan, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&hubs, counts + (int64_t)kOrderRest * (ncnt / kOrderClasses), sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  c->n_hubs = (int32_t)hubs;
   dev_release(c, deg);
   dev_release(c, hist);
   dev_release(c, plan);

@@ -160,20 +160,72 @@ __global__ void k_keys_to_rp(const uint64_t *keys, int32_t n, int32_t *rp) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += stride) rp[v] = (int32_t)keys[v];
 }
 
+// Renaming table of the order, for the arcs' targets. The H hubs take new ids 0 .. H - 1 and
+// every other node keeps its place among the others, so a non-hub w becomes H + w - (hubs
+// with an id below w), and a hub becomes hub_new[hubs with an id below w], where hub_new
+// lists the hubs' new ids in old-id order. Per group of 64 consecutive old ids a 16-byte
+// record holds the group's hub bits and the hubs in earlier groups, so one record read and
+// a popcount give the count. Records (n / 4 bytes) and hub_new (4 bytes per hub) stay in an
+// XCD's L2 at sizes where inv (4 bytes per node, read at random) would not: 2^22 nodes take
+// 1 MiB of records against 16 MiB of inv.
+// First step: each group's hub bits (the nodes with inv < H) and hub count; gcount[n_groups]
+// = 0 closes the array for an exclusive scan.
+__global__ __launch_bounds__(kBlockThreads) void k_rename_bits(const int32_t *inv, int32_t n, int32_t H,
+                                                               int64_t n_groups, uint4 *rec, uint64_t *gcount) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * kBlockThreads) >> 6;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gcount[n_groups] = 0;
+  for (int64_t g = ((int64_t)blockIdx.x * kBlockThreads + threadIdx.x) >> 6; g < n_groups; g += waves) {
+    const int64_t v = g * kWave + lane;
+    const uint64_t bits = __ballot(v < n && inv[v] < H);
+    if (lane == 0) {
+      rec[g] = make_uint4((uint32_t)bits, (uint32_t)(bits >> 32), 0u, 0u);
+      gcount[g] = (uint64_t)__popcll(bits);
+    }
+  }
+}
+
+// Second step, after the exclusive scan of gcount: each record's count of earlier hubs, and
+// every hub's new id at its rank in old-id order.
+__global__ __launch_bounds__(kBlockThreads) void k_rename_hubs(const int32_t *inv, int32_t n, int64_t n_groups,
+                                                               const uint64_t *gprefix, uint4 *rec,
+                                                               int32_t *hub_new) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = ((int64_t)gridDim.x * kBlockThreads) >> 6;
+  for (int64_t g = ((int64_t)blockIdx.x * kBlockThreads + threadIdx.x) >> 6; g < n_groups; g += waves) {
+    const uint4 r = rec[g];
+    const uint64_t bits = ((uint64_t)r.y << 32) | r.x;
+    const uint32_t before = (uint32_t)gprefix[g];
+    const int64_t v = g * kWave + lane;
+    if ((bits >> lane) & 1ull) hub_new[before + __popcll(bits & ((1ull << lane) - 1ull))] = inv[v];
+    if (lane == 0) rec[g].z = before;
+  }
+}
+
 // The arcs in the new order: the arc at old position p, in old row u, goes to new position
-// rp_new[inv[u]] + (p - rp[u]) with its target renamed inv[ci[p]]. The renaming is one
-// random read per arc, the same kind of request as a pass's gather of the target's counter,
-// so this kernel costs about as much as one pass over every node. One wavefront per window of
-// kPermWindow consecutive old positions (reads in order; each row's arcs are written in
-// order). The rows of the window's first and last arcs come from one interleaved 64-ary
-// search; the starts of the rows between them are staged in LDS (up to kPermRows), so the
-// row of every arc is an LDS search and the window's steps have no chain between them.
-__global__ __launch_bounds__(kBlockThreads) void k_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n,
-                                                               int32_t arcs, const int32_t *inv,
-                                                               const int32_t *rp_new, int32_t *ci_new) {
+// rp_new[inv[u]] + (p - rp[u]) with its target renamed (inv[ci[p]], taken from the renaming
+// table). One wavefront per window of kPermWindow consecutive old positions (reads in order;
+// each row's arcs are written in order). The rows of the window's first and last arcs come
+// from one interleaved 64-ary search; the rows between them (up to kPermRows) are staged in
+// LDS with their start and the shift to their new place, so an arc's row and destination
+// come from an LDS search. The window's positions go in batches of kPermBatch steps of 64:
+// first every successor id of the batch is loaded, then every renaming record, then the hub
+// entries, so each kind of load has a batch in flight at once.
+constexpr int kPermBatch = 8;
+static_assert(kPermWindow % (kPermBatch * kWave) == 0, "whole batches per window");
+
+__global__ __launch_bounds__(kBlockThreads) void k_permute_csr(const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci, int32_t n,
+                                                               int32_t arcs, const int32_t *__restrict__ inv,
+                                                               const uint4 *__restrict__ rec,
+                                                               const int32_t *__restrict__ hub_new, int32_t H,
+                                                               const int32_t *__restrict__ rp_new,
+                                                               int32_t *__restrict__ ci_new) {
   __shared__ int32_t starts_all[kBlockThreads / kWave][kPermRows];
+  __shared__ int32_t shift_all[kBlockThreads / kWave][kPermRows];
   const int lane = threadIdx.x & 63;
   int32_t *starts = starts_all[threadIdx.x >> 6];
+  int32_t *shift = shift_all[threadIdx.x >> 6];
   const int64_t wave = ((int64_t)blockIdx.x * kBlockThreads + threadIdx.x) >> 6;
   const int64_t p0_64 = wave * kPermWindow;
   if (p0_64 >= arcs) return;  // wavefront-uniform
@@ -196,31 +248,51 @@ __global__ __launch_bounds__(kBlockThreads) void k_permute_csr(const int32_t *rp
   const int32_t r0 = lo0, rows = lo1 - lo0 + 1;
   const bool staged = rows <= kPermRows;
   if (staged)
-    for (int32_t i = lane; i < rows; i += kWave) starts[i] = rp[r0 + i];
+    for (int32_t i = lane; i < rows; i += kWave) {
+      const int32_t st = rp[r0 + i];
+      starts[i] = st;
+      shift[i] = rp_new[inv[r0 + i]] - st;  // arc p of the row goes to p + shift
+    }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-#pragma unroll 4
-  for (int s = 0; s < kPermWindow; s += kWave) {
-    const int32_t p = p0 + s + lane;
-    if (p <= p1) {
-      const int32_t w = ci[p];
+  for (int s0 = 0; s0 < kPermWindow; s0 += kPermBatch * kWave) {
+    int32_t w[kPermBatch], nw[kPermBatch];
+    uint4 r[kPermBatch];
+#pragma unroll
+    for (int k = 0; k < kPermBatch; ++k) {
+      const int32_t p = p0 + s0 + k * kWave + lane;
+      w[k] = p <= p1 ? ci[p] : 0;  // (id 0 past the window: renamed, never stored)
+    }
+#pragma unroll
+    for (int k = 0; k < kPermBatch; ++k) r[k] = rec[(uint32_t)w[k] >> 6];
+#pragma unroll
+    for (int k = 0; k < kPermBatch; ++k) {
+      const uint64_t bits = ((uint64_t)r[k].y << 32) | r[k].x;
+      const int b = w[k] & 63;
+      const int32_t below = (int32_t)r[k].z + __popcll(bits & ((1ull << b) - 1ull));
+      nw[k] = ((bits >> b) & 1ull) ? hub_new[below] : H + (w[k] - below);
+    }
+#pragma unroll
+    for (int k = 0; k < kPermBatch; ++k) {
+      const int32_t p = p0 + s0 + k * kWave + lane;
+      if (p > p1) continue;
       // the last of rows r0 .. r0 + rows - 1 starting at or before p
       int32_t a = 0, b = rows;
+      int32_t dst;
       if (staged) {
         while (b - a > 1) {
           const int32_t mid = (a + b) >> 1;
           if (starts[mid] <= p) a = mid; else b = mid;
         }
+        dst = p + shift[a];
       } else {
         while (b - a > 1) {
           const int32_t mid = (a + b) >> 1;
           if (rp[r0 + mid] <= p) a = mid; else b = mid;
         }
+        dst = rp_new[inv[r0 + a]] + (p - rp[r0 + a]);
       }
-      const int32_t row = r0 + a;
-      const int32_t start = staged ? starts[a] : rp[row];
-      const int32_t dst = rp_new[inv[row]] + (p - start);
-      ci_new[dst] = inv[w];
+      ci_new[dst] = nw[k];
     }
   }
 }
@@ -280,9 +352,11 @@ hipError_t launch_order_select(const uint32_t *deg, int32_t n, int64_t K, uint32
   return hipGetLastError();
 }
 
+int64_t rename_groups(int32_t n) { return ((int64_t)n + kWave - 1) / kWave; }
+
 hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs, const int32_t *perm,
-                              const int32_t *inv, uint64_t *keys, uint64_t *scan_tmp, int32_t *rp_new,
-                              int32_t *ci_new, hipStream_t s) {
+                              const int32_t *inv, int32_t H, uint64_t *keys, uint64_t *scan_tmp, uint4 *rec,
+                              int32_t *hub_new, int32_t *rp_new, int32_t *ci_new, hipStream_t s) {
   hipLaunchKernelGGL(k_order_degrees, dim3(grid_of((int64_t)n + 1, kBlockThreads, 4096)), dim3(kBlockThreads), 0, s,
                      rp, perm, n, keys);
   hipError_t e = hipGetLastError();
@@ -291,9 +365,18 @@ hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, i
   hipLaunchKernelGGL(k_keys_to_rp, dim3(grid_of((int64_t)n + 1, kBlockThreads, 4096)), dim3(kBlockThreads), 0, s,
                      keys, n, rp_new);
   if (arcs > 0) {
+    // the renaming table; keys (n + 1 entries, read by k_keys_to_rp before) holds the group
+    // counts (n_groups + 1 <= n + 1 entries)
+    const int64_t n_groups = rename_groups(n);
+    const unsigned wgs = grid_of(n_groups, kBlockThreads / kWave, 4096);
+    hipLaunchKernelGGL(k_rename_bits, dim3(wgs), dim3(kBlockThreads), 0, s, inv, n, H, n_groups, rec, keys);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan_u64(keys, n_groups + 1, scan_tmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rename_hubs, dim3(wgs), dim3(kBlockThreads), 0, s, inv, n, n_groups, keys, rec, hub_new);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t waves = (arcs + kPermWindow - 1) / kPermWindow;
     hipLaunchKernelGGL(k_permute_csr, dim3((unsigned)((waves + 3) / 4)), dim3(kBlockThreads), 0, s, rp, ci, n,
-                       (int32_t)arcs, inv, rp_new, ci_new);
+                       (int32_t)arcs, inv, rec, hub_new, H, rp_new, ci_new);
   }
   return hipGetLastError();
 }
