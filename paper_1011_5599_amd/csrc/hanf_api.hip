@@ -758,28 +758,31 @@ int permute_graph(hanf_ctx *c, const int32_t *rp, const int32_t *ci, int32_t **r
   const int64_t arcs = c->arcs;
   uint64_t *keys = nullptr, *tmp = nullptr;
   uint4 *rec = nullptr;
-  int32_t *hub_new = nullptr;
+  int32_t *hub_new = nullptr, *wrow = nullptr;
   int rc;
   if ((rc = dev_alloc(c, rp_new, (size_t)n + 1, "reordered row_ptr")) ||
       (rc = dev_alloc(c, ci_new, (size_t)arcs, "reordered col_idx")) ||
       (rc = dev_alloc(c, &keys, (size_t)n + 1, "reorder keys")) ||
       (rc = dev_alloc(c, &tmp, (size_t)scan_tmp_elems((int64_t)n + 1), "scan scratch")) ||
       (rc = dev_alloc(c, &rec, (size_t)rename_groups(n), "renaming table")) ||
-      (rc = dev_alloc(c, &hub_new, (size_t)std::max(c->n_hubs, 1), "renaming table"))) {
+      (rc = dev_alloc(c, &hub_new, (size_t)std::max(c->n_hubs, 1), "renaming table")) ||
+      (rc = dev_alloc(c, &wrow, (size_t)permute_windows(arcs) + 1, "reorder windows"))) {
     dev_release(c, *rp_new);
     dev_release(c, *ci_new);
     dev_release(c, keys);
     dev_release(c, tmp);
     dev_release(c, rec);
     dev_release(c, hub_new);
+    dev_release(c, wrow);
     return rc;
   }
   const hipError_t e = launch_permute_csr(rp, ci, n, arcs, c->perm, c->inv, c->n_hubs, keys, tmp, rec, hub_new,
-                                          *rp_new, *ci_new, c->stream);
+                                          wrow, *rp_new, *ci_new, c->stream);
   dev_release(c, keys);  // pooled: reused only by work queued later on the same stream
   dev_release(c, tmp);
   dev_release(c, rec);
   dev_release(c, hub_new);
+  dev_release(c, wrow);
   if (e != hipSuccess) {
     dev_release(c, *rp_new);
     dev_release(c, *ci_new);

@@ -279,11 +279,12 @@ hipError_t launch_order_select(const uint32_t *deg, int32_t n, int64_t K, uint32
                                uint64_t *counts, uint64_t *scan_tmp, int32_t *perm, int32_t *inv, hipStream_t s);
 // the CSR (rp, ci) in the new order, whose first H ids are the hubs: keys n + 1 uint64 (with
 // scan_tmp for n + 1), rec rename_groups(n) records and hub_new max(H, 1) int32 (the
-// renaming table of the arcs' targets)
+// renaming table of the arcs' targets), wrow permute_windows(arcs) + 1 int32
 int64_t rename_groups(int32_t n);
+int64_t permute_windows(int64_t arcs);
 hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs, const int32_t *perm,
                               const int32_t *inv, int32_t H, uint64_t *keys, uint64_t *scan_tmp, uint4 *rec,
-                              int32_t *hub_new, int32_t *rp_new, int32_t *ci_new, hipStream_t s);
+                              int32_t *hub_new, int32_t *wrow, int32_t *rp_new, int32_t *ci_new, hipStream_t s);
 // dst row i = src row idx[i]; row_bytes a multiple of 8
 hipError_t launch_gather_rows(const uint8_t *src, uint8_t *dst, const int32_t *idx, int32_t n, int64_t row_bytes,
                               hipStream_t s);

@@ -202,15 +202,28 @@ __global__ __launch_bounds__(kBlockThreads) void k_rename_hubs(const int32_t *in
   }
 }
 
+// wrow[k]: the row that holds old position k * kPermWindow (every such position lies in
+// exactly one row with arcs, so each entry is written once); wrow[windows] = n - 1 closes the
+// last window.
+__global__ void k_window_rows(const int32_t *rp, int32_t n, int64_t windows, int32_t *wrow) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) wrow[windows] = n - 1;
+  for (int64_t r = gid; r < n; r += stride) {
+    const int64_t a = rp[r], b = rp[r + 1];
+    for (int64_t q = (a + kPermWindow - 1) / kPermWindow; q * kPermWindow < b; ++q) wrow[q] = (int32_t)r;
+  }
+}
+
 // The arcs in the new order: the arc at old position p, in old row u, goes to new position
 // rp_new[inv[u]] + (p - rp[u]) with its target renamed (inv[ci[p]], taken from the renaming
 // table). One wavefront per window of kPermWindow consecutive old positions (reads in order;
-// each row's arcs are written in order). The rows of the window's first and last arcs come
-// from one interleaved 64-ary search; the rows between them (up to kPermRows) are staged in
-// LDS with their start and the shift to their new place, so an arc's row and destination
-// come from an LDS search. The window's positions go in batches of kPermBatch steps of 64:
-// first every successor id of the batch is loaded, then every renaming record, then the hub
-// entries, so each kind of load has a batch in flight at once.
+// each row's arcs are written in order). The window's rows run from the row of its first
+// position to the row of the next window's first position (k_window_rows); up to kPermRows
+// of them are staged in LDS with their start and the shift to their new place, so an arc's
+// row and destination come from an LDS search. The window's positions go in batches of
+// kPermBatch steps of 64: first every successor id of the batch is loaded, then every
+// renaming record, then the hub entries, so each kind of load has a batch in flight at once.
 constexpr int kPermBatch = 8;
 static_assert(kPermWindow % (kPermBatch * kWave) == 0, "whole batches per window");
 
@@ -219,6 +232,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_permute_csr(const int32_t *__
                                                                int32_t arcs, const int32_t *__restrict__ inv,
                                                                const uint4 *__restrict__ rec,
                                                                const int32_t *__restrict__ hub_new, int32_t H,
+                                                               const int32_t *__restrict__ wrow,
                                                                const int32_t *__restrict__ rp_new,
                                                                int32_t *__restrict__ ci_new) {
   __shared__ int32_t starts_all[kBlockThreads / kWave][kPermRows];
@@ -231,21 +245,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_permute_csr(const int32_t *__
   if (p0_64 >= arcs) return;  // wavefront-uniform
   const int32_t p0 = (int32_t)p0_64;
   const int32_t p1 = (int32_t)min((int64_t)arcs, p0_64 + kPermWindow) - 1;
-  // the last row starting at or before p0, and at or before p1: rp[lo] <= p < rp[hi]
-  // (rp[0] = 0, rp[n] = arcs); each round narrows both ranges 64-fold, down to one row
-  int32_t lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;
-  while (hi0 - lo0 > 1 || hi1 - lo1 > 1) {
-    const int32_t st0 = (hi0 - lo0 + kWave - 1) / kWave, st1 = (hi1 - lo1 + kWave - 1) / kWave;
-    const int32_t x0 = lo0 + lane * st0, x1 = lo1 + lane * st1;
-    const bool a0 = x0 < hi0 && rp[x0] <= p0;
-    const bool a1 = x1 < hi1 && rp[x1] <= p1;
-    const uint64_t b0 = __ballot(a0), b1 = __ballot(a1);  // prefixes of the lanes, lane 0 included
-    lo0 += (63 - __clzll((long long)b0)) * st0;
-    hi0 = min(hi0, lo0 + st0);
-    lo1 += (63 - __clzll((long long)b1)) * st1;
-    hi1 = min(hi1, lo1 + st1);
-  }
-  const int32_t r0 = lo0, rows = lo1 - lo0 + 1;
+  // rows r0 .. r0 + rows - 1 hold every position of the window (and possibly a row after it,
+  // which starts past the window and is never the row of a position in it)
+  const int32_t r0 = wrow[wave], rows = wrow[wave + 1] - r0 + 1;
   const bool staged = rows <= kPermRows;
   if (staged)
     for (int32_t i = lane; i < rows; i += kWave) {
@@ -353,10 +355,11 @@ hipError_t launch_order_select(const uint32_t *deg, int32_t n, int64_t K, uint32
 }
 
 int64_t rename_groups(int32_t n) { return ((int64_t)n + kWave - 1) / kWave; }
+int64_t permute_windows(int64_t arcs) { return (arcs + kPermWindow - 1) / kPermWindow; }
 
 hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, int64_t arcs, const int32_t *perm,
                               const int32_t *inv, int32_t H, uint64_t *keys, uint64_t *scan_tmp, uint4 *rec,
-                              int32_t *hub_new, int32_t *rp_new, int32_t *ci_new, hipStream_t s) {
+                              int32_t *hub_new, int32_t *wrow, int32_t *rp_new, int32_t *ci_new, hipStream_t s) {
   hipLaunchKernelGGL(k_order_degrees, dim3(grid_of((int64_t)n + 1, kBlockThreads, 4096)), dim3(kBlockThreads), 0, s,
                      rp, perm, n, keys);
   hipError_t e = hipGetLastError();
@@ -374,9 +377,12 @@ hipError_t launch_permute_csr(const int32_t *rp, const int32_t *ci, int32_t n, i
     if ((e = launch_exclusive_scan_u64(keys, n_groups + 1, scan_tmp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rename_hubs, dim3(wgs), dim3(kBlockThreads), 0, s, inv, n, n_groups, keys, rec, hub_new);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t waves = (arcs + kPermWindow - 1) / kPermWindow;
+    const int64_t waves = permute_windows(arcs);
+    hipLaunchKernelGGL(k_window_rows, dim3(grid_of(n, kBlockThreads, 4096)), dim3(kBlockThreads), 0, s, rp, n, waves,
+                       wrow);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_permute_csr, dim3((unsigned)((waves + 3) / 4)), dim3(kBlockThreads), 0, s, rp, ci, n,
-                       (int32_t)arcs, inv, rec, hub_new, H, rp_new, ci_new);
+                       (int32_t)arcs, inv, rec, hub_new, H, wrow, rp_new, ci_new);
   }
   return hipGetLastError();
 }
