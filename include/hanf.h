@@ -98,7 +98,7 @@ extern "C" {
                                    L2: passes over every node run about 18% faster. In-degrees
                                    come from the transposed graph if one is set, else from a
                                    count of col_idx. Choosing the order rewrites the graph, which
-                                   costs about one pass over every node (one random read per
+                                   costs about 70% of a pass over every node (one rename per
                                    arc), once per ingest; K > 0 chooses it at the first
                                    hanf_init_counters after ingest. -1 (default): K = 4 MiB / row
                                    bytes (65536 at m = 64) when rows are shorter than a 128-byte

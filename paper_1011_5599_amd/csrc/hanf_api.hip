@@ -801,9 +801,9 @@ constexpr int64_t kL2LineBytes = 128;
 // hubs first (by class of in-degree, then id) and the other nodes after them in id order;
 // the graph and its transpose are rewritten in that order. Auto: K rows fill kHubCacheBytes,
 // for rows shorter than an L2 line and graphs with at least 16 K nodes whose transposed
-// graph gives the in-degrees, chosen
-// at the second initialisation on the ingest (the rewrite costs about one pass over every
-// node, which a second run already earns back; a single run keeps the caller's order).
+// graph gives the in-degrees, chosen at the second initialisation on the ingest (the
+// rewrite costs about 70% of a pass over every node, which a second run earns back; a
+// single run gains little more than the rewrite, so it keeps the caller's order).
 int order_nodes(hanf_ctx *c, int32_t log2m, int packed) {
   c->ordered = true;
   const int32_t n = c->n;
