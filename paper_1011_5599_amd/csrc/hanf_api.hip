@@ -194,6 +194,9 @@ struct hanf_ctx {
   DevState *st_poll = nullptr;  // pinned, written by the copy hanf_enqueue leaves on the stream
   PassLog *log_host = nullptr;  // pinned, kMaxPassesPerCheck records read with the state
   hipEvent_t poll_ev = nullptr;
+  // per-kernel timing events of hanf_iterate, created once and reused by every batch of
+  // passes (the host then creates and destroys none between batches)
+  std::vector<hipEvent_t> ev_pool;
   bool poll_pending = false;
   int32_t nt_cap = 0, log_cap = 0, max_passes = 0, n_blocks = 0, n_reduce_wgs = 0;
   std::vector<double> lc_host;
@@ -1229,6 +1232,7 @@ void hanf_destroy(hanf_ctx *c) {
   if (c->nt_host) (void)hipHostFree(c->nt_host);
   if (c->log_host) (void)hipHostFree(c->log_host);
   if (c->poll_ev) (void)hipEventDestroy(c->poll_ev);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1667,7 +1671,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
   int rc;
   if ((rc = current_state(c))) return rc;
   int32_t steps = 0;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> &ev = c->ev_pool;
   for (;;) {
     DevState s0 = *c->st_host;
     c->sys_seen = s0.systolic != 0;
@@ -1683,11 +1687,12 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
     if (max_steps > 0 && steps >= max_steps) break;
     int B = c->passes_per_check;
     if (max_steps > 0) B = std::min(B, max_steps - steps);
-    if (c->timing) {
-      ev.resize((size_t)B * kPassEvents);
-      for (auto &x : ev)
+    if (c->timing)
+      while (ev.size() < (size_t)B * kPassEvents) {
+        hipEvent_t x = nullptr;
         if (hipEventCreate(&x) != hipSuccess) return fail(c, HANF_EDEVICE, "event create");
-    }
+        ev.push_back(x);
+      }
     for (int i = 0; i < B; ++i) {
       rc = enqueue_pass(c, c->timing ? &ev[(size_t)i * kPassEvents] : nullptr);
       if (rc) return rc;
@@ -1735,10 +1740,6 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         }
         c->host_log.push_back(r);
       }
-    }
-    if (c->timing) {
-      for (auto &x : ev) (void)hipEventDestroy(x);
-      ev.clear();
     }
     steps += ran;
     if (ran == 0 && !c->st_host->done && !c->st_host->capped)
