@@ -115,8 +115,8 @@ def copy_scale(copy_dir: str, copy_bytes: int) -> float:
     return copy_bytes / (kib * 1024.0)
 
 
-def derived_utilisation(c, cus=256, simds=1024, xcds=8):
-    """Utilisation of the vector memory path and the vector ALUs in the first pass, from
+def derived_utilisation(c, label="first pass", cus=256, simds=1024, xcds=8):
+    """Utilisation of the vector memory path and the vector ALUs in one pass (`label`), from
     counters of separate runs (so only roughly comparable): GRBM_GUI_ACTIVE counts busy
     cycles per XCD (summed over the 8); TA and TD busy cycles are per compute unit; a
     wavefront's VALU instruction occupies its SIMD for one quad-cycle."""
@@ -134,7 +134,7 @@ def derived_utilisation(c, cus=256, simds=1024, xcds=8):
         rows.append(("L1 cache stalled on pending L2 requests", c["TCP_PENDING_STALL_CYCLES_sum"] / cus / cyc))
     if "SQ_INSTS_VALU" in c:
         rows.append(("VALU issue (instructions x 4 cycles / SIMD cycles)", 4 * c["SQ_INSTS_VALU"] / simds / cyc))
-    L = ["Derived, first pass (cycles per XCD from GRBM_GUI_ACTIVE / 8; counters from separate runs):", "",
+    L = [f"Derived, {label} (cycles per XCD from GRBM_GUI_ACTIVE / 8; counters from separate runs):", "",
          "| quantity | value |", "|---|---:|"]
     L += [f"| {k} | {v:.0%} |" for k, v in rows]
     if "TCP_TCC_READ_REQ_LATENCY_sum" in c and c.get("TCP_TCC_READ_REQ_sum"):
@@ -229,20 +229,23 @@ def main():
                    fetch_scale=fs, write_scale=ws, launches=n)
     if args.counters:
         L += ["## Other counters of the union step", "",
-              "Summed over the union dispatches of a pass (k_union, k_union_list); first pass (every "
-              "successor gathered) and the average over the passes of one run.", "",
-              "| counter | first pass | average per pass |", "|---|---:|---:|"]
-        first = {}
+              "Summed over the union dispatches of a pass (k_union, k_union_list); the first pass "
+              "(every successor gathered), the last pass (the fixpoint's, which changes no counter) "
+              "and the average over the passes of one run.", "",
+              "| counter | first pass | last pass | average per pass |", "|---|---:|---:|---:|"]
+        first, last = {}, {}
         for d in args.counters:
             cj = json.loads(open(d.rstrip("/") + ".json").read().strip().splitlines()[-1])
             pr, runs_c = cj["config"]["passes"], cj["steps"] + cj["warmup"]
             for name, rows in sorted(counter_runs(os.path.join(d, "run_counter_collection.csv")).items()):
                 per = union_per_pass(rows, pr, runs_c)
                 if per:
-                    L.append(f"| {name} | {per[0]:.4g} | {sum(per) / len(per):.4g} |")
+                    L.append(f"| {name} | {per[0]:.4g} | {per[-1]:.4g} | {sum(per) / len(per):.4g} |")
                     first[name] = per[0]
+                    last[name] = per[-1]
         L += [""]
-        L += derived_utilisation(first)
+        L += derived_utilisation(first, "first pass")
+        L += derived_utilisation(last, "last pass")
     L += [f"Kernel source at measurement: `paper_1011_5599_amd/csrc/hanf_kernels.hip` sha256 `{sha[:16]}…` "
           "(bench.py reports `traffic` only while the source is unchanged)."]
     with open(args.out_md, "w") as f:
