@@ -46,6 +46,13 @@ extern "C" {
 #define HANF_ERANGE -5   /* output capacity too small */
 #define HANF_EMAXITER -6 /* the pass cap was reached before the fixpoint */
 
+/* ---- size limits: the most nodes and arcs of a graph, of a batch of graphs and of a
+ * batch's row layout (2^31 - 2^20 each). Node ids and arc positions are 32-bit in the
+ * kernels, which step up to a few thousand positions past the end of a range before
+ * testing it, so both counts stay this far below 2^31 (HANF_EINVAL beyond). */
+#define HANF_MAX_NODES 2146435072
+#define HANF_MAX_ARCS 2146435072
+
 /* ---- flags for buffers handed to the library */
 #define HANF_HOST_PTRS 0u   /* host memory: copied */
 #define HANF_DEVICE_PTRS 1u /* device memory: borrowed (load_csr) or copied (registers) */
@@ -208,7 +215,7 @@ int hanf_set_option(hanf_ctx *ctx, int option, int64_t value);
 
 /* Graph ingest (the graph G of Section 3.2, as successor lists). CSR: the successors of
  * v are col_idx[row_ptr[v] .. row_ptr[v+1]), 0 <= v < n. Requirements, checked on the
- * device: n >= 1, 0 <= arcs < 2^31, row_ptr[0] = 0, row_ptr nondecreasing,
+ * device: 1 <= n <= HANF_MAX_NODES, 0 <= arcs <= HANF_MAX_ARCS, row_ptr[0] = 0, row_ptr nondecreasing,
  * row_ptr[n] = arcs, 0 <= col_idx[a] < n (HANF_EINVAL otherwise). Duplicate arcs and
  * self-loops are allowed and change nothing. With HANF_HOST_PTRS the arrays are copied;
  * with HANF_DEVICE_PTRS they are borrowed and must stay alive and unchanged until the

@@ -32,6 +32,8 @@ HANF_EMAXITER = -6
 
 HANF_HOST_PTRS = 0
 HANF_DEVICE_PTRS = 1
+HANF_MAX_NODES = 2146435072  # 2^31 - 2^20: the most nodes, and arcs, of a graph or batch
+HANF_MAX_ARCS = 2146435072
 
 HANF_OPT_FRONTIER = 1
 HANF_OPT_MAX_PASSES = 2

@@ -976,8 +976,8 @@ int set_layout(hanf_ctx *c, int32_t copies) {
       n[k] = c->g_n_h[g];
       nacc += c->g_node_off_h[g + 1] - c->g_node_off_h[g];
       aacc += c->g_aoff_h[g + 1] - c->g_aoff_h[g];
-      if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
-        return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices in its row layout");
+      if (nacc > HANF_MAX_NODES || aacc > HANF_MAX_ARCS)
+        return fail(c, HANF_EINVAL, "batch row layout above HANF_MAX_NODES nodes or HANF_MAX_ARCS arcs");
     }
   off[L] = (int32_t)nacc;
   aoff[L] = (int32_t)aacc;
@@ -1326,8 +1326,8 @@ int hanf_set_option(hanf_ctx *c, int option, int64_t value) {
 int hanf_load_csr(hanf_ctx *c, int32_t n, int64_t arcs, const int32_t *row_ptr, const int32_t *col_idx,
                   uint32_t flags) {
   if (!c) return fail(nullptr, HANF_EINVAL, "hanf_load_csr: NULL context");
-  if (n < 1) return fail(c, HANF_EINVAL, "n must be >= 1");
-  if (arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
+  if (n < 1 || n > HANF_MAX_NODES) return fail(c, HANF_EINVAL, "n must be in [1, HANF_MAX_NODES]");
+  if (arcs < 0 || arcs > HANF_MAX_ARCS) return fail(c, HANF_EINVAL, "arcs must be in [0, HANF_MAX_ARCS]");
   if (!row_ptr || (arcs > 0 && !col_idx)) return fail(c, HANF_EINVAL, "NULL CSR array");
   if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
@@ -1994,7 +1994,7 @@ int hanf_read_pass_log(hanf_ctx *c, hanf_pass_t *out, int32_t cap, int32_t *len)
 
 int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t flags, int64_t *bytes) {
   if (!bytes) return fail(nullptr, HANF_EINVAL, "bytes is NULL");
-  if (n < 1 || arcs < 0 || arcs >= (int64_t)INT32_MAX || log2m < 4 || log2m > 8)
+  if (n < 1 || n > HANF_MAX_NODES || arcs < 0 || arcs > HANF_MAX_ARCS || log2m < 4 || log2m > 8)
     return fail(nullptr, HANF_EINVAL, "hanf_footprint: argument out of range");
   if ((flags & HANF_FP_PACKED5) && log2m < 6)
     return fail(nullptr, HANF_EINVAL, "hanf_footprint: 5-bit registers need log2m >= 6");
@@ -2033,7 +2033,8 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
   if (arcs > 0 && !col_idx) return fail(c, HANF_EINVAL, "col_idx is NULL");
   if (flags == HANF_DEVICE_PTRS && (!device_pointer(c, row_ptr) || (arcs > 0 && !device_pointer(c, col_idx))))
     return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: pointer is not device memory of this device");
-  if (arc_off[0] != 0 || arcs < 0 || arcs >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "arcs must be in [0, 2^31)");
+  if (arc_off[0] != 0 || arcs < 0 || arcs > HANF_MAX_ARCS)
+    return fail(c, HANF_EINVAL, "arcs must be in [0, HANF_MAX_ARCS]");
   if ((int64_t)n_graphs * n_seeds >= (int64_t)INT32_MAX) return fail(c, HANF_EINVAL, "too many components");
   if (graph_off[0] != 0) return fail(c, HANF_EINVAL, "graph_off[0] must be 0");
   for (int32_t g = 0; g < n_graphs; ++g) {
@@ -2053,8 +2054,8 @@ int hanf_load_batch(hanf_ctx *c, int32_t n_graphs, const int32_t *graph_off, con
     ncomp[g] = (int32_t)ng;
     nacc += (ng + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
     aacc += ag;
-    if (nacc >= (int64_t)INT32_MAX - kNodesPerBlock || aacc >= (int64_t)INT32_MAX)
-      return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
+    if (nacc > HANF_MAX_NODES || aacc > HANF_MAX_ARCS)
+      return fail(c, HANF_EINVAL, "batch above HANF_MAX_NODES nodes or HANF_MAX_ARCS arcs");
   }
   node_off[C] = (int32_t)nacc;
   comp_aoff[C] = (int32_t)aacc;
@@ -2164,8 +2165,8 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
     aoff[g] = (int32_t)aacc;
     nacc += n_nodes[g];
     aacc += n_arcs[g];
-    if (nacc + n_graphs >= (int64_t)INT32_MAX || aacc >= (int64_t)INT32_MAX)
-      return fail(c, HANF_EINVAL, "batch too large for 32-bit indices");
+    if (nacc + n_graphs > HANF_MAX_NODES || aacc > HANF_MAX_ARCS)
+      return fail(c, HANF_EINVAL, "batch above HANF_MAX_NODES nodes or HANF_MAX_ARCS arcs");
   }
   goff[n_graphs] = (int32_t)nacc;
   aoff[n_graphs] = (int32_t)aacc;
@@ -2178,8 +2179,8 @@ int hanf_load_batch_list(hanf_ctx *c, int32_t n_graphs, const int32_t *const *ro
     ncomp[g] = n_nodes[g];
     en += ((int64_t)n_nodes[g] + kNodesPerBlock - 1) / kNodesPerBlock * kNodesPerBlock;
     ea += n_arcs[g];
-    if (en >= (int64_t)INT32_MAX - kNodesPerBlock || ea >= (int64_t)INT32_MAX)
-      return fail(c, HANF_EINVAL, "batch too large for 32-bit node / arc indices");
+    if (en > HANF_MAX_NODES || ea > HANF_MAX_ARCS)
+      return fail(c, HANF_EINVAL, "batch above HANF_MAX_NODES nodes or HANF_MAX_ARCS arcs");
   }
   node_off[C] = (int32_t)en;
   comp_aoff[C] = (int32_t)ea;

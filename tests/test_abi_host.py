@@ -41,12 +41,23 @@ def test_footprint_matches_memory_model():
 
 
 @pytest.mark.parametrize("args", [(0, 10, 6, 1), (10, -1, 6, 1), (10, 1 << 31, 6, 1), (10, 10, 3, 1),
-                                  (10, 10, 9, 1)])
+                                  (10, 10, 9, 1), (hanf.HANF_MAX_NODES + 1, 10, 6, 1),
+                                  (10, hanf.HANF_MAX_ARCS + 1, 6, 1)])
 def test_footprint_rejects_bad_arguments(args):
     with pytest.raises(hanf.HanfError) as e:
         hanf.hanf_footprint(*args)
     assert e.value.code == hanf.HANF_EINVAL
     assert "out of range" in hanf.hanf_last_error(None)
+
+
+def test_size_limits_match_the_header():
+    """The binding's size limits are the header's, 2^31 - 2^20, and a graph at both limits is
+    accepted by the footprint (whose arithmetic is 64-bit)."""
+    text = open(os.path.join(ROOT, "include", "hanf.h")).read()
+    for name in ("HANF_MAX_NODES", "HANF_MAX_ARCS"):
+        value = int(re.search(rf"#define {name} (\d+)", text).group(1))
+        assert value == getattr(hanf, name) == (1 << 31) - (1 << 20)
+    assert hanf.hanf_footprint(hanf.HANF_MAX_NODES, hanf.HANF_MAX_ARCS, 4, 0) > 16 * hanf.HANF_MAX_NODES
 
 
 def test_null_context_calls_fail_cleanly():

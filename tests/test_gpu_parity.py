@@ -4,6 +4,7 @@ Registers must be byte-identical at every iteration checked, N_hat(t) within 1e-
 relative (FP64 sums in a different order), the fixpoint iteration T equal, and the
 per-pass work counters (counters changed, successor unions) exactly the oracle's.
 """
+import ctypes
 import os
 import sys
 
@@ -440,6 +441,12 @@ def test_errors():
         badc[10] = -1
         with pytest.raises(hanf.HanfError):
             h.load(rp, badc)
+        # sizes beyond HANF_MAX_NODES / HANF_MAX_ARCS are refused before the arrays are read
+        lib = hanf.lib()
+        prp, pci = rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p)
+        for n_bad, arcs_bad in ((hanf.HANF_MAX_NODES + 1, len(ci)), (len(rp) - 1, hanf.HANF_MAX_ARCS + 1)):
+            assert lib.hanf_load_csr(h.ctx, n_bad, arcs_bad, prp, pci, hanf.HANF_HOST_PTRS) == hanf.HANF_EINVAL
+            assert "HANF_MAX" in hanf.hanf_last_error(h.ctx)
         h.load(rp, ci)
         for b in (3, 9):
             with pytest.raises(hanf.HanfError) as e:
