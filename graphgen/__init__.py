@@ -164,6 +164,32 @@ def clique_path_clique(k: int, l: int):
     return from_arcs(n, arcs)
 
 
+def limit_graph(heavy_log2: int = 21, degree: int = 1023, light_log2: int = 20):
+    """A graph with exactly the library's largest arc count, 2^31 - 2^20, at the default sizes
+    (2^21 * 1023 + 2^20 = 2,146,435,072 arcs, 8.6 GB of col_idx), with arc positions near
+    2^31 in both kinds of rows: the first 2^heavy_log2 nodes have
+    `degree` successors each, (v * degree + j) mod N for j < degree (an expander: every node
+    is reached within a few steps); the last 2^light_log2 nodes have one successor each,
+    (7 u + 3) mod N, and their rows sit at the end of col_idx. N is the node count.
+    Deterministic, no random draws."""
+    H, L = 1 << heavy_log2, 1 << light_log2
+    N = H + L
+    if (H - 1) * degree + degree - 1 >= 1 << 31:
+        raise ValueError("v * degree + j must fit in int32")
+    row_ptr = np.empty(N + 1, np.int64)
+    row_ptr[: H + 1] = np.arange(H + 1, dtype=np.int64) * degree
+    row_ptr[H + 1:] = H * degree + np.arange(1, L + 1, dtype=np.int64)
+    col_idx = np.empty(H * degree + L, np.int32)
+    j = np.arange(degree, dtype=np.int32)
+    step = 1 << 16
+    for s in range(0, H, step):
+        v = np.arange(s, min(H, s + step), dtype=np.int32)
+        col_idx[s * degree:(s + v.size) * degree] = ((v[:, None] * np.int32(degree) + j) % np.int32(N)).ravel()
+    u = np.arange(H, N, dtype=np.int64)
+    col_idx[H * degree:] = ((7 * u + 3) % N).astype(np.int32)
+    return row_ptr.astype(np.int32), col_idx
+
+
 # ---------------------------------------------------------------- the named workloads
 
 WORKLOADS = {

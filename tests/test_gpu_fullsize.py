@@ -10,6 +10,10 @@
   1e-12, same T; N_hat(0) against its closed form and, for sampled nodes, c_t[v]
   against the counter of the ball B(v, t) built by BFS (the identity of Section 3.2) at
   t = 1, 2, 3.
+* a graph with the largest arc count the library takes (2^31 - 2^20 arcs: 2^21 nodes of
+  1023 successors, then 2^20 nodes of one successor whose rows end at that count), 16
+  registers: registers byte-equal to the oracle's at every iteration, N_hat(t) within
+  1e-12, same T.
 * directed R-MAT scale 14 at every iteration is in test_gpu_parity.py.
 """
 import math
@@ -120,3 +124,32 @@ def test_web24_every_iteration():
         assert {r["systolic"] for r in hf.pass_log()} == {0, 2}
         assert not any(r["systolic"] for r in h.pass_log())
         assert any(not r["gather_all"] for r in h.pass_log())  # flag-frontier passes ran
+
+
+@pytest.mark.timeout(900)
+def test_arc_limit_every_iteration():
+    """Arc positions up to 2^31 - 2^20 (int32 throughout the kernels): the heavy rows are
+    split into chunks, the light rows at the end of col_idx go through the light rounds."""
+    rp, ci = graphgen.limit_graph()
+    n, arcs = len(rp) - 1, len(ci)
+    assert arcs == hanf.HANF_MAX_ARCS and int(rp[-1]) == arcs
+    b, seed = 4, 11
+    _say(f"[fullsize] arc limit n={n} arcs={arcs} b={b} seed={seed}")
+    with hanf.HyperANF(0) as h:
+        h.load(rp, ci).init(b, seed)
+        _say("[fullsize] arc limit: loaded")
+        want = []
+        T = None
+        for t, c, s in oracle.run_steps(rp, ci, b, seed, nthreads=THREADS):
+            want.append(s)
+            assert np.array_equal(h.registers(), c), f"registers differ at t={t}"
+            st, steps, _ = h.step(1)
+            assert steps == 1
+            _say(f"[fullsize] arc limit t={t} ok")
+            T = t
+        assert st == hanf.HANF_DONE
+        kinds = "".join("D" if r["gather_all"] else "F" for r in h.pass_log())
+        assert kinds.startswith("D") and "F" in kinds, kinds
+        got = h.nt()
+        assert len(got) == len(want) == T + 1
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)

@@ -175,3 +175,24 @@ def test_benchmark_graph_at_full_size():
     assert len(rp) - 1 == 1 << 22 and len(ci) == 1 << 26
     assert int(deg.max()) == 99_802 and int((deg == 0).sum()) == 2_168_332
     assert not np.any(np.repeat(np.arange(1 << 22, dtype=np.int32), deg) == ci)
+
+
+def test_limit_graph_recipe():
+    """The arc-limit graph's recipe on a small instance (the full one, 2^21 * 1023 + 2^20 =
+    2^31 - 2^20 arcs, is generated by the GPU test): heavy rows first with their arithmetic
+    targets, one-successor rows after them; parameters whose targets would overflow int32
+    are refused. (Node 0's first arc is a self-loop, which the library accepts.)"""
+    H, D, L = 1 << 6, 15, 1 << 5
+    rp, ci = graphgen.limit_graph(heavy_log2=6, degree=D, light_log2=5)
+    n, arcs = len(rp) - 1, len(ci)
+    assert rp.dtype == ci.dtype == np.int32 and rp[0] == 0 and rp[-1] == arcs
+    assert ci.min() >= 0 and ci.max() < n
+    assert n == H + L and arcs == H * D + L
+    assert np.array_equal(np.diff(rp), [D] * H + [1] * L)
+    for v in (0, 1, H // 2, H - 1):
+        assert ci[rp[v]:rp[v + 1]].tolist() == [(v * D + j) % n for j in range(D)]
+    for u in (H, H + 1, n - 1):
+        assert ci[rp[u]:rp[u + 1]].tolist() == [(7 * u + 3) % n]
+    assert (1 << 21) * 1023 + (1 << 20) == (1 << 31) - (1 << 20)
+    with pytest.raises(ValueError):
+        graphgen.limit_graph(heavy_log2=22, degree=1023, light_log2=1)
