@@ -531,10 +531,26 @@ int build_schedule(hanf_ctx *c, int G, int lane_bytes) {
     dev_release(c, tmp);
     return hip_fail(c, e, "schedule scan");
   }
-  s.n_chunks = (int32_t)(total[0] >> 32);
-  s.n_heavy = (int32_t)(total[0] & 0xffffffffull);
   s.stage = s.stage_tile > 0 && s.stage_opt == 1;
   if (s.stage) s.tile_nodes = s.stage_tile;
+  {
+    // One launch holds fewer than 2^32 threads: the union step runs a wavefront per work
+    // unit (chunk or light tile) and the tile builder a workgroup of at least a wavefront
+    // per tile. Only very small tiles or chunks on graphs of ~10^9 nodes or arcs exceed it.
+    const int64_t chunks = (int64_t)(total[0] >> 32);
+    const int64_t tiles = ((int64_t)n + s.tile_nodes - 1) / s.tile_nodes;
+    int64_t width = kWave;
+    while (width < s.tile_nodes) width <<= 1;
+    const int64_t most = (int64_t)1 << 32;
+    if ((chunks + tiles + 40) * kWave >= most || tiles * width >= most) {
+      dev_release(c, keys);
+      dev_release(c, tmp);
+      return fail(c, HANF_EINVAL,
+                  "schedule too large for one launch: raise HANF_OPT_TILE_NODES or HANF_OPT_CHUNK_ARCS");
+    }
+  }
+  s.n_chunks = (int32_t)(total[0] >> 32);
+  s.n_heavy = (int32_t)(total[0] & 0xffffffffull);
   s.lds_wave_bytes = s.stage ? s.tile_nodes * G * lane_bytes : ((s.tile_nodes * 4 + 15) / 16) * 16;
   s.n_tiles = (int32_t)(((int64_t)n + s.tile_nodes - 1) / s.tile_nodes);
   if ((rc = dev_alloc(c, &s.light, (size_t)s.n_tiles * s.tile_nodes, "light tiles"))) {

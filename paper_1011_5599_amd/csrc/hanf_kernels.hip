@@ -1002,11 +1002,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_finalize(PassArgs a) {
 // G lanes per node row; counter j of the row is lanes j*gs .. j*gs+gs-1, which take the
 // same branch (their flag bit), so the estimate's shuffles stay inside active groups.
 template <class F, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a) {
-  const DevState *st = a.st;
-  if (st->halted) return;
-  const Flags f = make_flags(a, st);
-  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+__device__ __forceinline__ void estimate_changed_lane(const PassArgs &a, const Flags &f, int64_t gid) {
   const int64_t v64 = gid / G;
   if (v64 >= a.n) return;  // whole nodes leave together (G | 64)
   const int32_t v = (int32_t)v64;
@@ -1015,6 +1011,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a) 
   if (((f.cur_bits[bit >> 5] >> (bit & 31)) & 1u) == 0u) return;
   const double E = slot_estimate<F>(F::load(f.nxt, v, G, sub), a.lc, a.K, gs);
   if (sub % gs == 0) a.est[((size_t)v << f.sl) + j] = E;
+}
+
+// (a sweep over n * G row lanes, as k_init's)
+template <class F, int G>
+__global__ __launch_bounds__(kBlockThreads) void k_estimate_changed(PassArgs a, int64_t lanes) {
+  const DevState *st = a.st;
+  if (st->halted) return;
+  const Flags f = make_flags(a, st);
+  const int64_t stride = (int64_t)gridDim.x * kBlockThreads;
+  for (int64_t base = (int64_t)blockIdx.x * kBlockThreads; base < lanes; base += stride)
+    estimate_changed_lane<F, G>(a, f, base + threadIdx.x);
 }
 
 // Per 64-node block, one lane each: re-sum the estimates where a counter changed (else
@@ -1803,8 +1810,7 @@ __device__ __forceinline__ void clear_run_flags(const PassArgs &a, int64_t gid) 
 // and cleared flags. G lanes per node row, F::kRegs registers each; counter j of the row is
 // lanes j*gs .. j*gs+gs-1 and is hashed with its own seed.
 template <class F, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+__device__ __forceinline__ void init_lane(const PassArgs &a, uint64_t seed, int64_t gid) {
   clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
@@ -1839,10 +1845,19 @@ __global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t see
   if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + j] = E;
 }
 
+// The kernels over row lanes sweep `lanes` threads with a grid of at most 2^28 (a launch
+// holds fewer than 2^32 threads; n * G reaches that at 2^28 nodes of 256 registers). The
+// sweep advances a whole workgroup at a time, so slots stay whole in every step.
+template <class F, int G>
+__global__ __launch_bounds__(kBlockThreads) void k_init(PassArgs a, uint64_t seed, int64_t lanes) {
+  const int64_t stride = (int64_t)gridDim.x * kBlockThreads;
+  for (int64_t base = (int64_t)blockIdx.x * kBlockThreads; base < lanes; base += stride)
+    init_lane<F, G>(a, seed, base + threadIdx.x);
+}
+
 // Estimates of every counter of `regs` (resume from a checkpoint) and cleared flags.
 template <class F, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, const uint8_t *regs) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlockThreads + threadIdx.x;
+__device__ __forceinline__ void estimate_all_lane(const PassArgs &a, const uint8_t *regs, int64_t gid) {
   clear_run_flags(a, gid);
   const int64_t v64 = gid / G;
   const int sub = (int)(gid % G);
@@ -1851,6 +1866,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, cons
   const int gs = a.gs;
   const double E = slot_estimate<F>(F::load(regs, v, G, sub), a.lc, a.K, gs);
   if (sub % gs == 0) a.est[((size_t)v << a.seed_log2) + sub / gs] = E;
+}
+
+template <class F, int G>
+__global__ __launch_bounds__(kBlockThreads) void k_estimate_all(PassArgs a, const uint8_t *regs, int64_t lanes) {
+  const int64_t stride = (int64_t)gridDim.x * kBlockThreads;
+  for (int64_t base = (int64_t)blockIdx.x * kBlockThreads; base < lanes; base += stride)
+    estimate_all_lane<F, G>(a, regs, base + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ kernels: graph ingest
@@ -2378,6 +2400,9 @@ __global__ void k_pack5(const uint8_t *in, uint8_t *packed, int64_t groups) {
   }
 }
 
+// Workgroups of a sweep over row lanes: 2^28 threads per step of the sweep.
+constexpr int64_t kLaneSweepWgs = (int64_t)1 << 20;
+
 int grid_for(int64_t items, int threads, int64_t cap = 1 << 20) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -2510,15 +2535,19 @@ int64_t init_lanes(const PassArgs &a) {
 
 hipError_t launch_init(const PassArgs &a, uint64_t seed, hipStream_t s) {
   const int G = row_lanes(a);
-  const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
-  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_init<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, seed));
+  const int64_t lanes = init_lanes(a);
+  const int grid = grid_for(lanes, kBlockThreads, kLaneSweepWgs);
+  HANF_DISPATCH_FG(a.packed, G,
+                   hipLaunchKernelGGL((k_init<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, seed, lanes));
   return hipGetLastError();
 }
 
 hipError_t launch_estimate_all(const PassArgs &a, const uint8_t *regs, hipStream_t s) {
   const int G = row_lanes(a);
-  const int grid = grid_for(init_lanes(a), kBlockThreads, 1 << 30);
-  HANF_DISPATCH_FG(a.packed, G, hipLaunchKernelGGL((k_estimate_all<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, regs));
+  const int64_t lanes = init_lanes(a);
+  const int grid = grid_for(lanes, kBlockThreads, kLaneSweepWgs);
+  HANF_DISPATCH_FG(a.packed, G,
+                   hipLaunchKernelGGL((k_estimate_all<F, G>), dim3(grid), dim3(kBlockThreads), 0, s, a, regs, lanes));
   return hipGetLastError();
 }
 
@@ -2675,8 +2704,9 @@ hipError_t launch_finalize(const PassArgs &a, hipStream_t s, hipEvent_t e0, hipE
 hipError_t launch_estimate_changed(const PassArgs &a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (!a.packed) return record_empty(e0, e1, s);  // byte rows: the union step wrote them
   const int G = row_lanes(a);
-  const int grid = grid_for((int64_t)a.n * G, kBlockThreads, 1 << 30);
-  HANF_DISPATCH_FG(a.packed, G, launch_k(k_estimate_changed<F, G>, dim3(grid), dim3(kBlockThreads), s, e0, e1, a));
+  const int64_t lanes = (int64_t)a.n * G;
+  const int grid = grid_for(lanes, kBlockThreads, kLaneSweepWgs);
+  HANF_DISPATCH_FG(a.packed, G, launch_k(k_estimate_changed<F, G>, dim3(grid), dim3(kBlockThreads), s, e0, e1, a, lanes));
   return hipGetLastError();
 }
 

@@ -14,6 +14,9 @@
   1023 successors, then 2^20 nodes of one successor whose rows end at that count), 16
   registers: registers byte-equal to the oracle's at every iteration, N_hat(t) within
   1e-12, same T.
+* 2^28 nodes of 256 registers (2^32 row lanes, more threads than one launch holds):
+  initialisation and the estimates of a resumed run sweep the lanes in steps; every node's
+  estimate, N_hat(0) and sampled counters against closed forms and the oracle.
 * directed R-MAT scale 14 at every iteration is in test_gpu_parity.py.
 """
 import math
@@ -153,3 +156,65 @@ def test_arc_limit_every_iteration():
         got = h.nt()
         assert len(got) == len(want) == T + 1
         np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.timeout(600)
+def test_row_lanes_beyond_one_launch():
+    """2^28 nodes without arcs, 256 registers each: n * 16 = 2^32 row lanes. Each counter
+    holds the one register its node's hash sets (Algorithm 1, add), so V = m - 1 registers
+    are zero, the raw estimate (about 0.72 m) is below 5m/2, and every estimate is the
+    linear-counting value m ln(m / (m - 1)); N_hat(0) = n times that, and the run stops at
+    T = 0. An all-zero counter (a lane never initialised) would estimate 0. Checked: every
+    node's estimate, N_hat(0), and sampled counters (the last node's included) against the
+    oracle's initialisation; then the same after a checkpoint round trip through device
+    memory, whose estimates come from the other lane sweep."""
+    import torch
+    n, b, seed = 1 << 28, 8, 5
+    m = 1 << b
+    e1 = m * math.log(m / (m - 1))
+    sample = [0, 1, 12_345, n // 2 + 7, n - 2, n - 1]
+    rp = np.zeros(n + 1, np.int32)
+    _say(f"[fullsize] row lanes n={n} m={m} lanes={n * (m // 16)}")
+    with hanf.HyperANF(0) as h:
+        h.load(rp, np.zeros(0, np.int32)).init(b, seed)
+        _say("[fullsize] row lanes: initialised")
+
+        def check(label):
+            est = h.estimates()
+            assert np.all(est == e1), (label, np.unique(est)[:4])
+            nt = h.nt()
+            assert len(nt) == 1
+            np.testing.assert_allclose(nt[0], n * e1, rtol=1e-12, atol=0)
+            regs = torch.empty(n * m, dtype=torch.uint8, device="cuda")
+            h.registers(out=regs)
+            rows = regs.view(n, m)[torch.tensor(sample, device="cuda")].cpu().numpy()
+            for v, row in zip(sample, rows):
+                want = np.zeros(m, np.uint8)
+                oracle.add(want, b, seed, v)
+                assert np.array_equal(row, want), (label, v)
+            _say(f"[fullsize] row lanes: {label} ok")
+            return regs
+
+        assert len(h.run()) == 1
+        regs = check("run")
+        nt0 = h.nt()
+        hanf.hanf_write_registers(h.ctx, regs, 0, nt0)
+        del regs
+        check("resumed")
+        assert len(h.run()) == 1
+
+
+def test_schedule_beyond_one_launch_is_refused():
+    """A schedule whose union launch would need 2^32 threads or more (one wavefront per
+    chunk of one arc: node 0 holds all 2^26 arcs) is refused at initialisation, not
+    launched."""
+    n, arcs = 1 << 16, 1 << 26
+    rp = np.full(n + 1, arcs, np.int32)
+    rp[0] = 0
+    ci = (np.arange(arcs, dtype=np.int64) % n).astype(np.int32)
+    with hanf.HyperANF(0, chunk_arcs=1) as h:
+        h.load(rp, ci)
+        with pytest.raises(hanf.HanfError) as e:
+            h.init(4, 1)
+        assert e.value.code == hanf.HANF_EINVAL
+        assert "one launch" in hanf.hanf_last_error(h.ctx)
