@@ -15,7 +15,8 @@
   registers: registers byte-equal to the oracle's at every iteration, N_hat(t) within
   1e-12, same T.
 * 2^28 nodes of 256 registers (2^32 row lanes, more threads than one launch holds):
-  initialisation and the estimates of a resumed run sweep the lanes in steps; every node's
+  initialisation and the estimates of a resumed run sweep the lanes in steps; and the
+  largest node count the library takes, 2^31 - 2^20 nodes of 16 registers: every node's
   estimate, N_hat(0) and sampled counters against closed forms and the oracle.
 * directed R-MAT scale 14 at every iteration is in test_gpu_parity.py.
 """
@@ -158,50 +159,62 @@ def test_arc_limit_every_iteration():
         np.testing.assert_allclose(got, want, rtol=1e-12, atol=0)
 
 
-@pytest.mark.timeout(600)
-def test_row_lanes_beyond_one_launch():
-    """2^28 nodes without arcs, 256 registers each: n * 16 = 2^32 row lanes. Each counter
-    holds the one register its node's hash sets (Algorithm 1, add), so V = m - 1 registers
-    are zero, the raw estimate (about 0.72 m) is below 5m/2, and every estimate is the
-    linear-counting value m ln(m / (m - 1)); N_hat(0) = n times that, and the run stops at
-    T = 0. An all-zero counter (a lane never initialised) would estimate 0. Checked: every
-    node's estimate, N_hat(0), and sampled counters (the last node's included) against the
-    oracle's initialisation; then the same after a checkpoint round trip through device
-    memory, whose estimates come from the other lane sweep."""
+def _one_register_counters(h, n, b, seed, label):
+    """Checks a run on a graph without arcs, where each counter holds the one register its
+    node's hash sets (Algorithm 1, add): V = m - 1 registers are zero, the raw estimate
+    (under 0.8 m) is below 5m/2, so every estimate is the linear-counting value
+    m ln(m / (m - 1)) and N_hat(0) is n times it; an all-zero counter (a node never
+    initialised) would estimate 0. Also checks sampled counters, the last node's included,
+    against the oracle's initialisation. Returns the registers (a device tensor)."""
     import torch
-    n, b, seed = 1 << 28, 8, 5
     m = 1 << b
     e1 = m * math.log(m / (m - 1))
+    est = h.estimates()
+    assert np.all(est == e1), (label, np.unique(est)[:4])
+    del est
+    nt = h.nt()
+    assert len(nt) == 1
+    np.testing.assert_allclose(nt[0], n * e1, rtol=1e-12, atol=0)
+    regs = torch.empty(n * m, dtype=torch.uint8, device="cuda")
+    h.registers(out=regs)
     sample = [0, 1, 12_345, n // 2 + 7, n - 2, n - 1]
-    rp = np.zeros(n + 1, np.int32)
-    _say(f"[fullsize] row lanes n={n} m={m} lanes={n * (m // 16)}")
+    rows = regs.view(n, m)[torch.tensor(sample, device="cuda")].cpu().numpy()
+    for v, row in zip(sample, rows):
+        want = np.zeros(m, np.uint8)
+        oracle.add(want, b, seed, v)
+        assert np.array_equal(row, want), (label, v)
+    _say(f"[fullsize] {label} ok")
+    return regs
+
+
+@pytest.mark.timeout(600)
+def test_row_lanes_beyond_one_launch():
+    """2^28 nodes without arcs, 256 registers each: n * 16 = 2^32 row lanes, more threads
+    than one launch holds, so initialisation and the estimates of a resumed run sweep the
+    lanes in steps. Checked after the run and after a checkpoint round trip through device
+    memory (whose estimates come from the other sweep)."""
+    n, b, seed = 1 << 28, 8, 5
+    _say(f"[fullsize] row lanes n={n} m={1 << b} lanes={n * ((1 << b) // 16)}")
     with hanf.HyperANF(0) as h:
-        h.load(rp, np.zeros(0, np.int32)).init(b, seed)
-        _say("[fullsize] row lanes: initialised")
-
-        def check(label):
-            est = h.estimates()
-            assert np.all(est == e1), (label, np.unique(est)[:4])
-            nt = h.nt()
-            assert len(nt) == 1
-            np.testing.assert_allclose(nt[0], n * e1, rtol=1e-12, atol=0)
-            regs = torch.empty(n * m, dtype=torch.uint8, device="cuda")
-            h.registers(out=regs)
-            rows = regs.view(n, m)[torch.tensor(sample, device="cuda")].cpu().numpy()
-            for v, row in zip(sample, rows):
-                want = np.zeros(m, np.uint8)
-                oracle.add(want, b, seed, v)
-                assert np.array_equal(row, want), (label, v)
-            _say(f"[fullsize] row lanes: {label} ok")
-            return regs
-
+        h.load(np.zeros(n + 1, np.int32), np.zeros(0, np.int32)).init(b, seed)
         assert len(h.run()) == 1
-        regs = check("run")
-        nt0 = h.nt()
-        hanf.hanf_write_registers(h.ctx, regs, 0, nt0)
+        regs = _one_register_counters(h, n, b, seed, "row lanes: run")
+        hanf.hanf_write_registers(h.ctx, regs, 0, h.nt())
         del regs
-        check("resumed")
+        _one_register_counters(h, n, b, seed, "row lanes: resumed")
         assert len(h.run()) == 1
+
+
+@pytest.mark.timeout(600)
+def test_node_limit():
+    """The largest node count the library takes, HANF_MAX_NODES = 2^31 - 2^20 nodes (no
+    arcs, 16 registers): node ids up to 2^31 - 2^20 - 1 in every kernel of a run."""
+    n, b, seed = hanf.HANF_MAX_NODES, 4, 3
+    _say(f"[fullsize] node limit n={n} m={1 << b}")
+    with hanf.HyperANF(0) as h:
+        h.load(np.zeros(n + 1, np.int32), np.zeros(0, np.int32)).init(b, seed)
+        assert len(h.run()) == 1
+        _one_register_counters(h, n, b, seed, "node limit")
 
 
 def test_schedule_beyond_one_launch_is_refused():
