@@ -306,7 +306,10 @@ int hanf_read_order(hanf_ctx *ctx, int32_t *out, int32_t count, uint32_t flags);
  * values <= 31; packed on the device when the run keeps 5-bit registers) taken at
  * iteration t, and N_hat(0..t) in nt_prefix (len = t+1, host).
  * Every counter is treated as modified for the next pass, so the continuation is
- * identical to an uninterrupted run. Requires a prior hanf_init_counters (fixes m). */
+ * identical to an uninterrupted run. Requires a prior hanf_init_counters (fixes m).
+ * Argument errors (sizes, t, flags, pointers) leave the run in progress untouched; a
+ * register value above 31 (HANF_EINVAL) or a device error discards it, and the context
+ * must then be initialised again. */
 int hanf_write_registers(hanf_ctx *ctx, const uint8_t *in, int64_t bytes, int32_t t,
                          const double *nt_prefix, int32_t len, uint32_t flags);
 

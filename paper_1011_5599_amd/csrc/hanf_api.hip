@@ -1908,13 +1908,14 @@ int hanf_write_registers(hanf_ctx *c, const uint8_t *in, int64_t bytes, int32_t 
   if (bytes != (int64_t)c->n << c->log2m) return fail(c, HANF_EINVAL, "bytes must be n * m");
   if (t < 0 || len != t + 1) return fail(c, HANF_EINVAL, "len must be t + 1");
   if (t + 2 > c->nt_cap) return fail(c, HANF_ERANGE, "t beyond the pass cap");
+  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
   HIP_TRY(c, hipSetDevice(c->device), "set device");
+  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, in))
+    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: in is not device memory of this device");
+  // from here on the run in progress is replaced (on an error it must be initialised again)
   c->inited = false;
   c->sys_seen = false;
   c->first_enqueued = false;
-  if (flags != HANF_HOST_PTRS && flags != HANF_DEVICE_PTRS) return fail(c, HANF_EINVAL, "bad flags");
-  if (flags == HANF_DEVICE_PTRS && !device_pointer(c, in))
-    return fail(c, HANF_EINVAL, "HANF_DEVICE_PTRS: in is not device memory of this device");
   c->st_fresh = false;
   c->nt_host_len = 0;
   HIP_TRY(c, launch_state_reset(c->st, t, c->frontier, c->max_passes, dense_threshold(c), systolic_div(c),

@@ -453,6 +453,21 @@ def test_errors():
                 h.init(b, 1)
             assert e.value.code == hanf.HANF_EINVAL
         h.init(6, 1)
+        # argument errors of a resume leave the run in progress untouched
+        h.step(2)
+        regs2, nt2 = h.registers().copy(), h.nt()
+        pre = np.asarray(nt2, np.float64)
+        pin, ppre = regs2.ctypes.data_as(ctypes.c_void_p), pre.ctypes.data_as(ctypes.c_void_p)
+        for bytes_, t_, len_, flags_ in ((regs2.size - 1, 2, 3, 0), (regs2.size, -1, 0, 0),
+                                         (regs2.size, 2, 2, 0), (regs2.size, 2, 3, 7)):
+            assert lib.hanf_write_registers(h.ctx, pin, bytes_, t_, ppre, len_, flags_) == hanf.HANF_EINVAL
+        assert lib.hanf_write_registers(h.ctx, pin, regs2.size, 2, ppre, 3,
+                                        hanf.HANF_DEVICE_PTRS) == hanf.HANF_EINVAL  # host memory
+        h.step(1)
+        want = [x for _, _, x in oracle.run_steps(rp, ci, 6, 1)][:4]
+        got = h.nt()
+        assert len(want) == 4 and len(got) >= 4
+        np.testing.assert_allclose(got[:4], want, rtol=RTOL, atol=0)
         bad_regs = np.full((len(rp) - 1, 64), 32, np.uint8)
         with pytest.raises(hanf.HanfError) as e:
             hanf.hanf_write_registers(h.ctx, bad_regs, 0, [1.0])
