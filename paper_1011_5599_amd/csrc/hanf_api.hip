@@ -30,6 +30,13 @@ static __device__ __align__(256) StatsRec scratch[HANF_NOALLOC_MAX_COMPONENTS];
 namespace {
 
 constexpr int kMaxDevices = 64;
+
+// Bytes of the modified-flag summary: one per 2^kSumShift nodes (2^(kSumShift-6) blocks),
+// padded to a multiple of 4.
+int64_t sum_bytes(int64_t n_blocks) {
+  const int64_t per = (int64_t)1 << (kSumShift - 6);
+  return ((n_blocks + per - 1) / per + 3) / 4 * 4;
+}
 std::mutex g_scratch_mu;
 StatsRec *g_scratch_dev[kMaxDevices] = {};  // device address of `scratch` on each device
 hipError_t g_scratch_err[kMaxDevices] = {};  // the lookup's result where it failed
@@ -177,6 +184,7 @@ struct hanf_ctx {
   bool inited = false;
   uint8_t *regs[2] = {nullptr, nullptr};
   uint32_t *bits[2] = {nullptr, nullptr};
+  uint8_t *mod_sum = nullptr;  // summary of the modified flags (PassArgs::mod_sum)
   uint8_t *todo = nullptr;                             // systolic signals, one byte per node
   int32_t *sig_list = nullptr, *sig_cnt = nullptr;     // signalled successors per node
   int32_t *sys_node = nullptr, *sys_pos = nullptr;     // systolic signal list
@@ -310,6 +318,7 @@ void free_run(hanf_ctx *c) {
     dev_release(c, c->regs[i]);
     dev_release(c, c->bits[i]);
   }
+  dev_release(c, c->mod_sum);
   dev_release(c, c->est);
   dev_release(c, c->blocksum);
   dev_release(c, c->wgsum);
@@ -456,6 +465,7 @@ void mirror_state_reset(hanf_ctx *c, int32_t t, int32_t max_passes, int64_t dens
   s.sys_div = sys_div;
   s.sys_acc = 0ull;
   s.sys_units = 0;
+  s.use_sum = 0;
   c->st_fresh = true;
   c->comp_T_fresh = false;
 }
@@ -596,6 +606,8 @@ void fill_args(hanf_ctx *c) {
   a.regs1 = c->regs[1];
   a.bits0 = c->bits[0];
   a.bits1 = c->bits[1];
+  a.mod_sum = c->mod_sum;
+  a.n_sum = sum_bytes(c->n_blocks);
   a.est = c->est;
   a.blocksum = c->blocksum;
   a.wgsum = c->wgsum;
@@ -921,6 +933,7 @@ int alloc_run(hanf_ctx *c, int log2m, int sl, int packed) {
   if ((rc = dev_alloc(c, &c->regs[0], bytes, "counters")) || (rc = dev_alloc(c, &c->regs[1], bytes, "counters")) ||
       (rc = dev_alloc(c, &c->bits[0], (size_t)2 * c->n_blocks * S, "flags")) ||
       (rc = dev_alloc(c, &c->bits[1], (size_t)2 * c->n_blocks * S, "flags")) ||
+      (rc = dev_alloc(c, &c->mod_sum, (size_t)sum_bytes(c->n_blocks), "flag summary")) ||
       (rc = dev_alloc(c, &c->est, (size_t)c->n * S, "estimates")) ||
       (rc = dev_alloc(c, &c->blocksum, (size_t)c->n_blocks * S, "block sums")) ||
       (rc = dev_alloc(c, &c->wgsum, (size_t)c->n_reduce_wgs, "partial sums")) ||
@@ -2020,6 +2033,7 @@ int hanf_footprint(int32_t n, int64_t arcs, int32_t log2m, int32_t flags, int64_
   // counters + update buffer: m bytes per counter, or 5m/8 with 5-bit registers
   int64_t b = 2 * (int64_t)n * ((flags & HANF_FP_PACKED5) ? m * 5 / 8 : m);
   b += 2 * 2 * blocks * 4;                               // modified flags
+  b += sum_bytes(blocks);                                // their summary
   b += (int64_t)n * 8 + blocks * 8 + 2 * ((blocks + 3) / 4) * 8;  // estimates and sums
   b += (int64_t)n * 4 + 4096;                            // light tiles
   b += ((int64_t)n + 1) * 8 * 2;                         // schedule scan (transient)

@@ -13,6 +13,11 @@ constexpr int kNodesPerBlock = 64; // estimate partial sums are cached per 64 co
 constexpr int kMaxTile = 256;      // largest light tile (bitonic sort width)
 constexpr int kXcds = 8;           // MI355X accelerator complex dies
 constexpr int kReduceBlocks = 64;  // 64-node blocks per reduction workgroup (16 per wavefront)
+constexpr int kSumShift = 10;      // modified-flag summary: one byte per 2^10 nodes (16 blocks,
+                                   //   one reduction wavefront's)
+constexpr int kSumDiv = 8;         // summary read when at most 1/8 of its bytes are set
+constexpr int kMarkedShift = 40;   // per reduction workgroup, the marked summary bytes are
+                                   //   added to its changed-counter count from this bit
 constexpr int kStatSlots = 1024;   // rows of work counters, spread over workgroups
 constexpr int kStatFields = 6;     // work counters per row: scanned, gathered, written, read, local, near
 constexpr int64_t kL2Bytes = 4 << 20;  // L2 of one XCD
@@ -44,7 +49,8 @@ struct DevState {
   int64_t dense_threshold;  // 0 = never
   uint64_t sys_acc;   // systolic pass: (signalling nodes << 32) | their predecessor arcs
   int32_t sys_units;  // systolic pass: work units listed for the union kernel
-  int32_t pad_;
+  int32_t use_sum;    // 1: the next pass reads a group's summary byte before a flag word
+                      //   (set when at most 1 / kSumDiv of the groups are marked)
 };
 
 struct PassLog {  // per executed pass, filled on the device
@@ -161,10 +167,13 @@ struct PassArgs {
                              //   of m bytes per node (row seed j at byte j * m)
   uint32_t *bits0, *bits1;   // changed flags, S bits per node (bit v * S + j): bits[t & 1] written
                              //   by pass t-1, bits[(t+1) & 1] by pass t
+  uint8_t *mod_sum;          // per 2^kSumShift nodes: 1 if the last pass modified a counter there
+  int32_t n_sum;             // its bytes
   double *est;               // estimate of every current counter, [v * S + j]
   double *blocksum;          // per 64 nodes and row seed, [b * S + j]
   double *wgsum;             // per reduce workgroup
-  int64_t *wgcnt;            // per reduce workgroup: changed counters
+  int64_t *wgcnt;            // per reduce workgroup: changed counters, plus its marked summary
+                             //   bytes << kMarkedShift
   int64_t *stat_slots;       // kStatSlots x {scanned, gathered, written, read, local, near}
   const int32_t *light;      // light tiles: tile_nodes entries per tile, -1 = empty
   const Chunk *chunks;

@@ -367,6 +367,7 @@ struct Flags {
   bool gather_all;            // maximise with every successor (first pass, or frontier off)
   bool copy_check;            // next[v] may hold c_{t-1}[v] != c_t[v]: copy when v was modified
   bool systolic;              // only nodes in `todo` (signalled by a modified successor) may change
+  bool use_sum;               // few groups were modified: test a group's summary byte first
   const uint8_t *todo;
   int sl;                     // log2 of the counters per node row
 };
@@ -382,9 +383,29 @@ __device__ __forceinline__ Flags make_flags(const PassArgs &a, const DevState *s
   f.gather_all = first || !st->frontier || st->dense_next;
   f.copy_check = !first;
   f.systolic = !f.gather_all && st->systolic;
+  f.use_sum = !f.gather_all && !f.systolic && st->use_sum;
   f.todo = a.todo;
   f.sl = a.seed_log2;
   return f;
+}
+
+// The flag words of U successor ids (0 where a successor's counter cannot have changed).
+// When few groups of 2^kSumShift nodes hold a counter the previous pass modified, each
+// successor's group byte is read first (the summary is n / 1024 bytes, so it stays in the
+// L1 cache) and only the words of marked groups are loaded: in the last passes of a run
+// nearly every flag-word load, an L1 miss each, is skipped.
+template <int U>
+__device__ __forceinline__ void load_flag_words(const PassArgs &a, const Flags &f, const int32_t (&w)[U],
+                                                uint32_t (&fw)[U]) {
+  if (f.use_sum) {  // (the summary byte goes to the word's own register: no extra registers)
+#pragma unroll
+    for (int k = 0; k < U; ++k) fw[k] = a.mod_sum[(uint32_t)w[k] >> kSumShift];
+#pragma unroll
+    for (int k = 0; k < U; ++k) fw[k] = fw[k] ? mod_word(f.prev_bits, w[k], f.sl) : 0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);
+  }
 }
 
 struct Counters {
@@ -488,8 +509,7 @@ __device__ __forceinline__ void light_round(const PassArgs &a, const Flags &f, i
     }
     if (!f.gather_all && !f.systolic) {
       uint32_t fw[U];
-#pragma unroll
-      for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+      load_flag_words<U>(a, f, w, fw);  // (w = 0 where !ok)
 #pragma unroll
       for (int k = 0; k < U; ++k) ok[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
     }
@@ -633,8 +653,7 @@ __device__ __forceinline__ int32_t find_active(const PassArgs &a, const Flags &f
           }
           bool hk[U];
           uint32_t fw[U];
-#pragma unroll
-          for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+          load_flag_words<U>(a, f, w, fw);  // (w = 0 where !ok)
 #pragma unroll
           for (int k = 0; k < U; ++k) hk[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
 #pragma unroll
@@ -730,8 +749,7 @@ __device__ __forceinline__ void chunk_wave(const PassArgs &a, const Flags &f, in
     }
     if (!f.gather_all && !f.systolic) {
       uint32_t fw[U];
-#pragma unroll
-      for (int k = 0; k < U; ++k) fw[k] = mod_word(f.prev_bits, w[k], f.sl);  // (w = 0 where !ok)
+      load_flag_words<U>(a, f, w, fw);  // (w = 0 where !ok)
 #pragma unroll
       for (int k = 0; k < U; ++k) ok[k] = ok[k] && mod_in_word(fw[k], w[k], f.sl);
     }
@@ -1034,7 +1052,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   const DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kBlockThreads / kWave];
-  __shared__ int32_t s_cnt[kBlockThreads / kWave];
+  __shared__ int32_t s_cnt[kBlockThreads / kWave], s_mark[kBlockThreads / kWave];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t t = st->t;
   const uint32_t *cb = (t & 1) ? a.bits0 : a.bits1;
@@ -1056,6 +1074,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
     bc += __popc(wv[k]);
   }
   const bool dirty = valid && (force || any != 0u);
+  // the summary byte of the wavefront's 2^kSumShift nodes (after init or resume every
+  // group counts as marked)
+  static_assert(kPerWave << 6 == 1 << kSumShift, "one summary byte per reduction wavefront");
+  const bool marked = __ballot(dirty) != 0ull;
+  if (lane == 0 && b0 < a.n_blocks) a.mod_sum[b0 / kPerWave] = marked ? 1 : 0;
   double bs = (S == 1 && valid && !dirty) ? a.blocksum[b] : 0.0;
   // the dirty blocks of the wavefront, 4 at a time: each block's 64 S estimates are read 64
   // per step; lane l always holds row seed l mod S, so a butterfly over the offsets S..32
@@ -1116,11 +1139,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_reduce_blocks(PassArgs a, int
   if (lane == 0) {
     s_sum[wave] = ws;
     s_cnt[wave] = wc;
+    s_mark[wave] = marked && b0 < a.n_blocks ? 1 : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     a.wgsum[blockIdx.x] = (s_sum[0] + s_sum[1]) + (s_sum[2] + s_sum[3]);
-    a.wgcnt[blockIdx.x] = (int64_t)s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    // changed counters (below 2^36) and, from bit kMarkedShift, the marked summary bytes
+    a.wgcnt[blockIdx.x] = (int64_t)s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3] +
+                          ((int64_t)(s_mark[0] + s_mark[1] + s_mark[2] + s_mark[3]) << kMarkedShift);
   }
 }
 
@@ -1292,13 +1318,16 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   DevState *st = a.st;
   if (st->halted) return;
   __shared__ double s_sum[kTopThreads];
-  __shared__ int64_t s_i[7][kTopThreads];
+  __shared__ int64_t s_i[8][kTopThreads];
   const int tid = threadIdx.x;
   double s = 0.0;
   int64_t c = 0, sc = 0, ga = 0, wr = 0, rd = 0, lo = 0, ne = 0;
+  int64_t mk = 0;
   for (int32_t i = tid; i < a.n_reduce_wgs; i += kTopThreads) {
     s += a.wgsum[i];
-    c += a.wgcnt[i];
+    const int64_t x = a.wgcnt[i];
+    c += x & ((1ll << kMarkedShift) - 1);
+    mk += x >> kMarkedShift;
   }
   if (tid < kStatSlots) {
     int64_t *sl = a.stat_slots + tid * kStatFields;
@@ -1320,17 +1349,20 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   s_i[4][tid] = rd;
   s_i[5][tid] = lo;
   s_i[6][tid] = ne;
+  s_i[7][tid] = mk;
   __syncthreads();
   for (int off = kTopThreads / 2; off > 0; off >>= 1) {
     if (tid < off) {
       s_sum[tid] += s_sum[tid + off];
-      for (int k = 0; k < 7; ++k) s_i[k][tid] += s_i[k][tid + off];
+      for (int k = 0; k < 8; ++k) s_i[k][tid] += s_i[k][tid + off];
     }
     __syncthreads();
   }
   if (tid == 0) {
     const double total = s_sum[0];
     const int32_t t = st->t;
+    // the summary serves the next pass when at most 1 / kSumDiv of its bytes are set
+    st->use_sum = (mode != kReduceInit && s_i[7][0] * kSumDiv <= a.n_sum) ? 1 : 0;
     if (mode == kReduceInit) {
       if (t < a.nt_cap) a.nt[t] = total;
     } else {
@@ -1927,6 +1959,7 @@ __global__ void k_state_reset(DevState *st, int32_t t, int32_t frontier, int32_t
   st->sys_div = sys_div;
   st->sys_acc = 0ull;
   st->sys_units = 0;
+  st->use_sum = 0;
 }
 
 // keys[v] = (chunks of v) << 32 | (v needs a combine step); keys[n] = 0.
