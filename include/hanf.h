@@ -331,8 +331,9 @@ int hanf_read_pass_log(hanf_ctx *ctx, hanf_pass_t *out, int32_t cap, int32_t *le
 
 /* Device bytes a context needs for a graph of n nodes and `arcs` arcs at 2^log2m registers:
  * two register arrays (the counters and the update buffer, Section 3.2; 5m/8 bytes per
- * counter with HANF_FP_PACKED5 in `flags`), modified flags and estimate sums, plus, by the
- * bits of `flags` (HANF_FP_*): the graph copy (HANF_FP_COPY_GRAPH), the transposed graph
+ * counter with HANF_FP_PACKED5 in `flags`), modified flags and their summary (a byte per
+ * 1024 nodes), estimate sums, plus, by the bits of `flags` (HANF_FP_*): the graph copy
+ * (HANF_FP_COPY_GRAPH), the transposed graph
  * with the systolic signal buffers and the lists of signalled successors (HANF_FP_TRANSPOSE;
  * systolic passes from a forward scan need the same buffers less the transposed graph) and
  * the reordered graph (HANF_FP_ORDER). Pure host function; the memory figure of Section 3.4
