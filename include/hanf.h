@@ -200,6 +200,9 @@ typedef struct {
                             4 MiB (one XCD's L2) holds, halved: 16384 at 128-byte rows.
                             Counted by instrumented kernels only (option 104, or staging),
                             else -1 */
+  int32_t flag_summary;  /* 1 if the pass read the modified-flag summary (a byte per 1024
+                            nodes) before successors' flag words: a frontier pass after one
+                            that modified counters in at most an eighth of those groups */
 } hanf_pass_t;
 
 /* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t to order work

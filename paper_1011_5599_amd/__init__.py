@@ -77,7 +77,8 @@ class hanf_pass_t(ctypes.Structure):
                 ("union_ms", ctypes.c_float), ("finalize_ms", ctypes.c_float),
                 ("reduce_ms", ctypes.c_float), ("gather_all", ctypes.c_int32),
                 ("systolic", ctypes.c_int32), ("arcs_signalled", ctypes.c_int64),
-                ("signal_ms", ctypes.c_float), ("arcs_local", ctypes.c_int64), ("arcs_near", ctypes.c_int64)]
+                ("signal_ms", ctypes.c_float), ("arcs_local", ctypes.c_int64), ("arcs_near", ctypes.c_int64),
+                ("flag_summary", ctypes.c_int32)]
 
 
 class HanfError(RuntimeError):

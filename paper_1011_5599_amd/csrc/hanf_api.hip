@@ -1760,6 +1760,7 @@ int hanf_iterate(hanf_ctx *c, int32_t max_steps, int32_t *steps_done, int64_t *c
         r.arcs_signalled = recs[i].signalled;
         r.arcs_local = recs[i].local;
         r.arcs_near = (c->args.count_near || c->args.stage) ? recs[i].near : -1;
+        r.flag_summary = (int32_t)recs[i].summary;
         if (c->timing) {
           hipEvent_t *e = &ev[(size_t)i * kPassEvents];
           (void)hipEventElapsedTime(&r.signal_ms, e[0], e[1]);

@@ -58,6 +58,7 @@ struct PassLog {  // per executed pass, filled on the device
   int64_t local;  // successor counters maximised in from a light tile's rows staged in LDS
   int64_t near;   // successor counters maximised in whose id is within near_window of the node's
                   //   (counted only by the instrumented kernels: count_near or stage)
+  int64_t summary;  // 1 if the pass read the flag summary before flag words
 };
 
 struct Chunk {   // a run of at most `chunk_arcs` arcs of one node, handled by one wavefront

@@ -1361,14 +1361,18 @@ __global__ __launch_bounds__(kTopThreads) void k_reduce_top(PassArgs a, int32_t 
   if (tid == 0) {
     const double total = s_sum[0];
     const int32_t t = st->t;
-    // the summary serves the next pass when at most 1 / kSumDiv of its bytes are set
+    // whether this pass read the flag summary (as make_flags decided), and whether the next
+    // one will: when at most 1 / kSumDiv of its bytes are set
+    const bool dense = st->first_pass || !st->frontier || st->dense_next;
+    const int64_t used_sum = (st->use_sum && !dense && !st->systolic) ? 1 : 0;
     st->use_sum = (mode != kReduceInit && s_i[7][0] * kSumDiv <= a.n_sum) ? 1 : 0;
     if (mode == kReduceInit) {
       if (t < a.nt_cap) a.nt[t] = total;
     } else {
       const int32_t p = st->passes;
       PassLog rec;
-      rec.gather_all = (st->first_pass || !st->frontier || st->dense_next) ? 1 : 0;
+      rec.gather_all = dense ? 1 : 0;
+      rec.summary = used_sum;
       rec.changed = s_i[0][0];
       rec.scanned = s_i[1][0];
       rec.gathered = s_i[2][0];

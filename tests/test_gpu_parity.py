@@ -104,6 +104,8 @@ def step_parity(rp, ci, b, seed, check_every=1, transpose=None, **opts):
                 assert log["arcs_near"] == int(np.count_nonzero(gathered)), (t, log)
             elif not (opts.get("stage") or opts.get("count_near")):
                 assert log["arcs_near"] == -1, (t, log)
+            if log["flag_summary"]:  # read only by frontier passes
+                assert not log["gather_all"] and not log["systolic"], (t, log)
             assert log["gather_all"] == (t == 0 or not opts.get("frontier", 1)
                                          or (opts.get("dense_switch", 4) > 0
                                              and prev_changed >= max(1, n // opts.get("dense_switch", 4))))
@@ -255,6 +257,25 @@ def test_systolic_symmetric_self_transpose(b):
     step_parity(rp, ci, b, 7, transpose="self")
     step_parity(rp, ci, b, 8, transpose="self", dense_switch=0, systolic=1)
     step_parity(rp, ci, b, 9, transpose="declared", systolic=2)
+
+
+@pytest.mark.parametrize("name,b", [("web", 6), ("rmat", 4), ("web15", 8)])
+def test_flag_summary_passes(name, b):
+    """Frontier passes after one that modified counters in few groups of 1024 nodes read the
+    flag summary first; those runs still equal the oracle's at every t (registers, the
+    gathered-arc counts, N_hat), and the summary is used in at least one pass."""
+    graphs = {"web": lambda: graphgen.web(1 << 16, seed=61, keep_kind=True),
+              "rmat": lambda: graphgen.rmat(15, 1 << 19, seed=62),
+              "web15": lambda: graphgen.web(1 << 15, host_mean=300.0, seed=63, keep_kind=True)}
+    rp, ci = graphs[name]()
+    step_parity(rp, ci, b, 13)
+    with hanf.HyperANF(0) as h:
+        h.load(rp, ci).init(b, 13)
+        h.run()
+        log = h.pass_log()
+    used = [t for t, r in enumerate(log) if r["flag_summary"]]
+    _flush(f"[summary] {name}: passes {len(log)}, summary read in passes {used}")
+    assert used, [(r["gather_all"], r["changed"]) for r in log]
 
 
 def test_transpose_errors():
