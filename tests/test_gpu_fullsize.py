@@ -203,6 +203,8 @@ def test_row_lanes_beyond_one_launch():
         del regs
         _one_register_counters(h, n, b, seed, "row lanes: resumed")
         assert len(h.run()) == 1
+    import torch
+    torch.cuda.empty_cache()  # (the 64 GiB register copies stay out of later tests' way)
 
 
 @pytest.mark.timeout(600)
@@ -215,6 +217,8 @@ def test_node_limit():
         h.load(np.zeros(n + 1, np.int32), np.zeros(0, np.int32)).init(b, seed)
         assert len(h.run()) == 1
         _one_register_counters(h, n, b, seed, "node limit")
+    import torch
+    torch.cuda.empty_cache()
 
 
 def test_schedule_beyond_one_launch_is_refused():
